@@ -1,0 +1,40 @@
+"""Writes the stored oracle results under tests/golden/.
+
+Calls only the CPU oracle (``oracle/``) on inputs from the seeded generator;
+nothing here touches the HIP library.  Usage:
+
+    python tests/golden/make_golden.py 1      # config 1: sn-K and four-centre K (seconds)
+    python tests/golden/make_golden.py 2      # config 2: full sn-K (about an hour on 8 cores)
+"""
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+from oracle import oracle as O  # noqa: E402
+from paper_2303_14280_amd import synth  # noqa: E402
+
+
+def fingerprint(s):
+    return np.array([s.npts, s.nbf, s.grid_w.sum(), np.abs(s.grid_xyz).sum(), np.trace(s.P),
+                     np.abs(s.P).sum(), s.exps.sum(), s.coefs.sum()])
+
+
+def main(cfg: int, nthreads: int = 0):
+    s = synth.make_system(cfg)
+    t = time.time()
+    K, ex_tr, ex_fg = O.snk(s, nthreads=nthreads)
+    dt = time.time() - t
+    out = dict(K=K, ex=np.array([ex_tr, ex_fg]), fingerprint=fingerprint(s), seconds=np.array([dt]))
+    if cfg == 1:
+        out["K_exact"] = O.eri_k(s, nthreads=nthreads)
+    np.savez_compressed(os.path.join(HERE, "oracle_config%d.npz" % cfg), **out)
+    print("config", cfg, "E_x", ex_tr, ex_fg, "seconds", dt)
+
+
+if __name__ == "__main__":
+    main(int(sys.argv[1]), int(sys.argv[2]) if len(sys.argv) > 2 else 0)
