@@ -1,0 +1,156 @@
+"""sn-K exchange build benchmark on one MI355X.
+
+A step is one full build K[P] (collocation, F GEMM, 3c-CP A.F digestion, K GEMM,
+symmetrisation and E_x) for the 30-atom water cluster (config 2: 290 Cartesian
+s/p/d functions, 75x302 grid per atom = 679,500 points, FP64, no screening) with
+P and K resident in HBM.  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps 5] [--warmup 2] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "sn-K build time + shell-pair·gridpoint ints/s; mixed+learned vs FP64 at 1e-6 Eh"
+CLASSES = ("ss", "ps", "pp", "ds", "dp", "dd")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(system, target_s: float = 15.0):
+    """The CPU oracle timed on a bounded sample of the same workload (every k-th grid point)."""
+    import numpy as np
+    from oracle import oracle as O
+    nthreads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
+    npair = system.nshell * (system.nshell + 1) // 2
+    probe = system.subset_points(np.arange(0, system.npts, max(1, system.npts // 64)))
+    t = time.perf_counter()
+    O.snk(probe, nthreads=nthreads)
+    dt = max(time.perf_counter() - t, 1e-3)
+    rate = npair * probe.npts / dt
+    n = int(min(system.npts, max(probe.npts, rate * target_s / npair)))
+    stride = max(1, system.npts // n)
+    sample = system.subset_points(np.arange(0, system.npts, stride))
+    t = time.perf_counter()
+    O.snk(sample, nthreads=nthreads)
+    dt = time.perf_counter() - t
+    return {"value": npair * sample.npts / dt, "unit": "shell-pair·gridpoints/s", "cores": nthreads,
+            "kind": "oracle",
+            "sample": "every %d-th grid point of the same workload (%d of %d points, %d shell pairs), %.1f s"
+                      % (stride, sample.npts, system.npts, npair, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (the grid-batch "
+              "sharding is described in DESIGN.md); rerun with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2303_14280_amd import flops, snk, synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    log("generating config %d" % args.config)
+    s = synth.make_system(args.config)
+    stream = torch.cuda.Stream(device=dev)          # default priority
+    torch.cuda.set_stream(stream)
+    ctx = snk.Context(s, flags=snk.SNK_DEVICE_PTRS, stream=stream.cuda_stream, device=0)
+    P = torch.tensor(s.P, dtype=torch.float64, device=dev)
+    K = torch.empty_like(P)
+    torch.cuda.synchronize()
+    log("nbf %d npts %d batches %d" % (ctx.nbf, s.npts, ctx.nbatches))
+
+    for i in range(args.warmup):
+        ctx.build_device(P.data_ptr(), K.data_ptr())
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for i in range(args.steps):
+        ctx.build_device(P.data_ptr(), K.data_ptr())
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_gpu = e0.elapsed_time(e1) / args.steps
+    ms_wall = 1000.0 * wall / args.steps
+    ms = max(ms_gpu, ms_wall)
+    log("timed %d steps: %.3f ms/step (events %.3f, wall %.3f)" % (args.steps, ms, ms_gpu, ms_wall))
+
+    # per-phase and per-kernel times from the library's HIP events (separate, untimed builds)
+    reps = 3
+    acc = None
+    for i in range(reps):
+        st = ctx.build_device(P.data_ptr(), K.data_ptr(), stats=True)
+        if acc is None:
+            acc = {k: (np.array(v, float) if isinstance(v, list) else float(v)) for k, v in st.items()}
+        else:
+            for k, v in st.items():
+                acc[k] = acc[k] + (np.array(v, float) if isinstance(v, list) else float(v))
+    st = {k: v / reps for k, v in acc.items()}
+    pair_points = np.array(st["pair_points"])
+    prim_points = np.array(st["prim_pair_points"])
+    t_cls = np.array(st["t_afg_class_ms"])
+    ints = float(pair_points.sum())
+    cls_flops = [flops.class_flops(c, pair_points[c], prim_points[c]) for c in range(6)]
+    dom = int(np.argmax(t_cls))
+    achieved = cls_flops[dom] / (t_cls[dom] * 1e-3) / 1e12
+    afg_total = sum(cls_flops) / (st["t_afg_ms"] * 1e-3) / 1e12
+
+    out = {
+        "metric": METRIC,
+        "value": ints / (ms * 1e-3),
+        "unit": "shell-pair·gridpoints/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "config%d: %d-atom water-like cluster, %d Cartesian s/p/d functions, "
+                               "%d grid points in %d batches of 256, FP64, no screening"
+                               % (args.config, len(s.atom_Z), ctx.nbf, s.npts, ctx.nbatches),
+                   "atoms": int(len(s.atom_Z)), "nbf": ctx.nbf, "grid_points": s.npts,
+                   "shell_pair_points": ints, "precision": "fp64", "screen": "none",
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "alu", "kernel": "afg_kernel<%d,%d> (%s)" % (flops.CLASS_L[dom] + (CLASSES[dom],)),
+                     "achieved": achieved, "peak": flops.PEAK_FP64_VALU_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / flops.PEAK_FP64_VALU_TFLOPS, "traffic": None,
+                     "launch_ms": float(t_cls[dom]), "algorithmic_flops": cls_flops[dom]},
+        "phases_ms": {"collocate": st["t_collocate_ms"], "fgemm": st["t_fgemm_ms"], "afg": st["t_afg_ms"],
+                      "kgemm": st["t_kgemm_ms"], "finish": st["t_finish_ms"]},
+        "afg_classes": {CLASSES[c]: {"ms": float(t_cls[c]), "pair_points": float(pair_points[c]),
+                                     "tflops": (cls_flops[c] / (t_cls[c] * 1e-3) / 1e12) if t_cls[c] > 0 else 0.0}
+                        for c in range(6)},
+        "afg_tflops_all_classes": afg_total,
+        "ex": st["ex"],
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(s)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

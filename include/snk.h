@@ -1,0 +1,173 @@
+/*
+ * snk.h -- C ABI of the seminumerical exact-exchange (sn-K) library for MI355X (gfx950).
+ *
+ * The library builds the exchange matrix of hybrid Kohn-Sham DFT by the sn-K
+ * factorisation of Sec. II.D of Williams-Young et al., "Distributed Memory, GPU
+ * Accelerated Fock Construction for Hybrid, Gaussian Basis Density Functional
+ * Theory" (arXiv 2303.14280):
+ *
+ *   F_{lam i}  = sum_nu P_{lam nu} Phi_{nu i}            Eq. fmat  (Phi: Eq. collocation)
+ *   G_{mu i}   = w_i sum_lam A_{mu lam i} F_{lam i}      Eq. gmat  (A: Eq. 3c_grid)
+ *   Kt_{mu nu} = sum_i G_{mu i} Phi_{nu i}               Eq. usym_k
+ *   K          = (Kt + Kt^T) / 2                         Eq. sn_k
+ *   E_x        = -1/2 tr(P K)
+ *
+ * evaluated per spatial batch of grid points (Sec. II.E) on one GPU.  The 3c-CP
+ * integrals A are never stored: they are produced on the fly by the Obara-Saika
+ * recursions of App. A (Eqs. vrr, hrr) and contracted with F in the same kernel.
+ *
+ * Conventions shared by every entry point
+ *  - Units: bohr and hartree.
+ *  - Basis: contracted Cartesian Gaussian shells, l = 0, 1, 2, 1..SNK_MAX_NPRIM
+ *    primitives each (Sec. II.B, primitive form).  Components are ordered
+ *    lexicographically (x,y,z; xx,xy,xz,yy,yz,zz).  `coefs` already contain the
+ *    normalisation of the axis-aligned component x^l e^{-zeta r^2}; the library
+ *    scales every other component to unit norm.  Basis functions are numbered
+ *    shell by shell in the order given.
+ *  - Matrices (P, K) are nbf x nbf, row-major, FP64.  P must be symmetric.
+ *  - Ownership: the caller owns every pointer it passes.  The library copies what
+ *    it needs during the call and never frees or retains caller memory.
+ *  - Errors: every function returns an snk_status; no C++ exception crosses the
+ *    ABI.  On SNK_E_DEVICE the HIP error text is available from snk_last_error().
+ *  - Threads: a context is not thread-safe; different contexts are independent.
+ */
+#ifndef SNK_H
+#define SNK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SNK_VERSION 1
+#define SNK_MAX_L 2
+#define SNK_MAX_NPRIM 8
+
+typedef enum snk_status {
+    SNK_OK = 0,
+    SNK_E_ARG = 1,          /* null pointer, l > 2, nprim out of range, exponent <= 0, non-finite, weight < 0 */
+    SNK_E_UNSUPPORTED = 2,  /* option not available in this build */
+    SNK_E_NOMEM = 3,        /* device or host allocation failed, or the device budget is too small */
+    SNK_E_DEVICE = 4,       /* HIP runtime error (text in snk_last_error) */
+    SNK_E_ASYM = 5          /* validate mode: |P - P^T| > 1e-12 max|P| */
+} snk_status;
+
+typedef enum snk_precision {
+    SNK_FP64 = 0,           /* every step in FP64 */
+    SNK_MIXED = 1           /* BF16 MFMA GEMMs with FP32 accumulation; integrals and K accumulation FP64 */
+} snk_precision;
+
+typedef enum snk_screen {
+    SNK_SCREEN_NONE = 0,    /* every shell pair at every batch */
+    SNK_SCREEN_BOUND = 1,   /* rigorous block bound (Sec. II.E, sn-LinK-type pair selection) */
+    SNK_SCREEN_LEARNED = 2  /* MLP estimate with the rigorous bound as fallback */
+} snk_screen;
+
+/* opts.flags */
+#define SNK_DEVICE_PTRS 0x1u   /* P and K_out are device pointers; work is ordered on opts.stream */
+#define SNK_VALIDATE    0x2u   /* check P for symmetry and finiteness (host-pointer mode) */
+
+typedef struct snk_basis {
+    int32_t nshell;
+    const double* center;    /* [3*nshell] shell centres (x,y,z), host memory */
+    const int32_t* l;        /* [nshell] angular momentum 0..2 */
+    const int32_t* nprim;    /* [nshell] primitives per shell, 1..SNK_MAX_NPRIM */
+    const int32_t* prim_off; /* [nshell] offset of the shell's first primitive in exps/coefs */
+    const double* exps;      /* primitive exponents, > 0 */
+    const double* coefs;     /* contraction coefficients (normalised, see above) */
+} snk_basis;
+
+typedef struct snk_grid {
+    int64_t npts;                 /* number of quadrature points; 0 gives K = 0 */
+    const double* xyz;            /* [3*npts] points (x,y,z interleaved), host memory */
+    const int32_t* atom_of_point; /* optional [npts]: parent atom, used to form spatial batches */
+} snk_grid;
+
+typedef struct snk_stats {
+    double ex;               /* E_x = -1/2 tr(P K) */
+    double t_total_ms;       /* wall time of the build (host clock, includes copies in host mode) */
+    double t_collocate_ms;   /* GPU time per phase, summed over batch groups (HIP events) */
+    double t_fgemm_ms;
+    double t_screen_ms;
+    double t_afg_ms;         /* the 3c-CP A.F kernels */
+    double t_kgemm_ms;
+    double t_finish_ms;
+    int64_t pair_points[6];      /* shell-pair x grid-point units evaluated per class ss,ps,pp,ds,dp,dd */
+    int64_t pair_points_skipped; /* units dropped by screening */
+    int64_t pair_points_lowprec; /* units evaluated in reduced precision */
+    double skipped_bound;        /* sum of the rigorous energy bounds of the skipped units */
+    int32_t n_batches;
+    int32_t n_groups;
+    int64_t prim_pair_points[6]; /* primitive-pair x grid-point units evaluated per class */
+    double t_afg_class_ms[6];    /* GPU time of the A.F kernel of each class */
+} snk_stats;
+
+typedef struct snk_mlp snk_mlp;
+
+typedef struct snk_opts {
+    int32_t precision;          /* snk_precision */
+    int32_t screen;             /* snk_screen */
+    const snk_mlp* screener;    /* required for SNK_SCREEN_LEARNED */
+    double eps_basis;           /* basis-function screening tolerance eps_B (Eq. basis_screen); 0 = off */
+    double eps_skip_energy;     /* total energy budget for skipped blocks (Eh) */
+    double eps_lowprec_energy;  /* total energy budget for reduced-precision blocks (Eh) */
+    int32_t batch_points;       /* maximum points per batch, 64..256 (default 256) */
+    int32_t deterministic;      /* 1: no floating-point atomics (the default path uses none) */
+    int64_t max_device_bytes;   /* workspace budget for batch groups (0 = automatic) */
+    int32_t device;             /* HIP device ordinal */
+    void* stream;               /* hipStream_t; NULL = the library's own stream */
+    uint32_t flags;             /* SNK_DEVICE_PTRS | SNK_VALIDATE */
+    snk_stats* stats;           /* optional output of sn_k_build */
+} snk_opts;
+
+typedef struct snk_ctx snk_ctx;
+
+/* Fill opts with defaults: FP64, no screening, eps_basis 0, 256-point batches. */
+void snk_opts_default(snk_opts* opts);
+
+/*
+ * One-shot build (Alg. 1 on one GPU): K_out = K[P] for the given basis, grid and
+ * quadrature weights (`weights` [npts] host memory, >= 0).  Equivalent to
+ * snk_ctx_create + snk_ctx_build + snk_ctx_destroy.  K_out is overwritten; both
+ * triangles are written and the result is exactly symmetric.
+ */
+int sn_k_build(const snk_basis* basis, const snk_grid* grid, const double* weights,
+               const double* P, double* K_out, const snk_opts* opts);
+
+/*
+ * Context API for repeated builds on one geometry (SCF reuse, Sec. II.E: the
+ * batches and basis screening depend on the nuclei only).  snk_ctx_create does
+ * the geometry set-up (shell-pair table, spatial batches, basis screening,
+ * device workspace).  snk_ctx_build computes K for a new density; with
+ * SNK_DEVICE_PTRS in the creation options P and K_out are device pointers and the
+ * call is asynchronous on the context's stream, otherwise they are host pointers
+ * and the call returns when K_out is written.  `stats` may be NULL.
+ */
+int snk_ctx_create(const snk_basis* basis, const snk_grid* grid, const double* weights,
+                   const snk_opts* opts, snk_ctx** out);
+int snk_ctx_build(snk_ctx* ctx, const double* P, double* K_out, snk_stats* stats);
+void snk_ctx_destroy(snk_ctx* ctx);
+
+/* Number of basis functions of a context, and its number of spatial batches. */
+int snk_ctx_nbf(const snk_ctx* ctx);
+int snk_ctx_nbatches(const snk_ctx* ctx);
+
+/* Diagnostics. */
+const char* snk_status_string(int status);
+const char* snk_last_error(const snk_ctx* ctx);   /* NULL ctx: last error of a context-free call */
+int snk_version(void);
+
+/*
+ * Boys function on the device (Eq. boys), as used by the integral kernels:
+ * F_m(T[k]) for m = 0..mmax (mmax <= 4) written to F_out[k*(mmax+1) + m].
+ * T and F_out are device pointers, n values; ordered on `stream` (hipStream_t or
+ * NULL for the default stream).  For checking the kernels' special function.
+ */
+int snk_boys_device(const double* T, int64_t n, int mmax, double* F_out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SNK_H */

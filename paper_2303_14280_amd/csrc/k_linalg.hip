@@ -1,0 +1,223 @@
+// Dense linear-algebra steps of the sn-K build on gfx950:
+//  - FP64 GEMM on the matrix cores (v_mfma_f64_16x16x4f64) for F = P_g Phi_g (Eq. fmat)
+//    and Kt_g = G_g Phi_g^T (Eq. usym_k, split over the grid-point dimension);
+//  - deterministic reduction of the split partials into Kt;
+//  - K = (Kt + Kt^T)/2 (Eq. sn_k) and E_x = -1/2 tr(P K) by a fixed two-stage tree;
+//  - fill and gather helpers.
+#include "snk_internal.h"
+
+namespace snk {
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int TM = 64, TN = 64, TK = 16;
+
+// 256 threads = 4 wave64; wave w owns the 32x32 quadrant (w/2, w%2) of the 64x64 tile as
+// 2x2 MFMA 16x16 blocks.  Operand layout of v_mfma_f64_16x16x4f64 (wave64):
+//   A[i][k] in lane i + 16k, B[k][j] in lane j + 16k, D[i][j] in lane j + 16(i/4), element i%4.
+__global__ __launch_bounds__(256) void gemm_f64_kernel(int64_t M, int64_t N, int64_t K, const double* __restrict__ A,
+                                                       int64_t lda, const double* __restrict__ B, int64_t ldb, int bt,
+                                                       double* __restrict__ C, int64_t ldc, int64_t kchunk,
+                                                       int64_t split_stride)
+{
+    __shared__ double As[TK][TM + 1];
+    __shared__ double Bs[TK][TN + 1];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t m0 = (int64_t)blockIdx.y * TM, n0 = (int64_t)blockIdx.x * TN;
+    const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
+    const int64_t kend = min(K, kbeg + kchunk);
+    C += (int64_t)blockIdx.z * split_stride;
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    const int li = lane & 15, lk = lane >> 4;
+
+    d4 acc[2][2];
+    for (int bi = 0; bi < 2; ++bi)
+        for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = d4{0.0, 0.0, 0.0, 0.0};
+
+    const int ai = tid >> 2, ak = (tid & 3) * 4;
+    for (int64_t k0 = kbeg; k0 < kend; k0 += TK) {
+        {
+            const int64_t gm = m0 + ai;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int64_t gk = k0 + ak + u;
+                As[ak + u][ai] = (gm < M && gk < kend) ? A[gm * lda + gk] : 0.0;
+            }
+        }
+        if (!bt) {
+            const int bk = tid >> 4, bj = (tid & 15) * 4;
+            const int64_t gk = k0 + bk;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int64_t gn = n0 + bj + u;
+                Bs[bk][bj + u] = (gk < kend && gn < N) ? B[gk * ldb + gn] : 0.0;
+            }
+        } else {
+            const int bj = tid >> 2, bk = (tid & 3) * 4;
+            const int64_t gn = n0 + bj;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int64_t gk = k0 + bk + u;
+                Bs[bk + u][bj] = (gn < N && gk < kend) ? B[gn * ldb + gk] : 0.0;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < TK; ks += 4) {
+            double a[2], b[2];
+#pragma unroll
+            for (int bi = 0; bi < 2; ++bi) a[bi] = As[ks + lk][wm + bi * 16 + li];
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj) b[bj] = Bs[ks + lk][wn + bj * 16 + li];
+#pragma unroll
+            for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < 2; ++bj)
+                    acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi], b[bj], acc[bi][bj], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t gm = m0 + wm + bi * 16 + 4 * lk + r;
+                const int64_t gn = n0 + wn + bj * 16 + li;
+                if (gm < M && gn < N) C[gm * ldc + gn] = acc[bi][bj][r];
+            }
+}
+
+__global__ __launch_bounds__(256) void reduce_scatter_kernel(const double* __restrict__ part, int nsplit,
+                                                             int64_t stride, int64_t M, int64_t N,
+                                                             const int32_t* __restrict__ rows,
+                                                             const int32_t* __restrict__ cols,
+                                                             double* __restrict__ Kt, int64_t nbf)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= M * N) return;
+    const int64_t m = idx / N, n = idx - m * N;
+    double s = 0.0;
+    for (int z = 0; z < nsplit; ++z) s += part[z * stride + idx];
+    const int64_t r = rows ? rows[m] : m;
+    const int64_t c = cols ? cols[n] : n;
+    Kt[r * nbf + c] += s;
+}
+
+__global__ __launch_bounds__(256) void fill_kernel(double* __restrict__ p, int64_t n, double v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__device__ double block_sum(double v, double* sh)
+{
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    return sh[0];
+}
+
+__global__ __launch_bounds__(256) void finish_kernel(const double* __restrict__ Kt, const double* __restrict__ P,
+                                                     double* __restrict__ K, int64_t nbf, double* __restrict__ partial)
+{
+    __shared__ double sh[256];
+    const int64_t n2 = nbf * nbf;
+    double acc = 0.0;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n2; idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = idx / nbf, j = idx - i * nbf;
+        const double k = 0.5 * (Kt[idx] + Kt[j * nbf + i]);
+        K[idx] = k;
+        acc = fma(P[idx], k, acc);   // tr(PK) = sum_ij P_ij K_ji and K is symmetric
+    }
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(256) void finish_reduce_kernel(const double* __restrict__ partial, int nblk,
+                                                            double* __restrict__ ex)
+{
+    __shared__ double sh[256];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nblk; i += blockDim.x) acc += partial[i];
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) ex[0] = -0.5 * s;
+}
+
+__global__ __launch_bounds__(256) void gather_kernel(const double* __restrict__ P, int64_t nbf,
+                                                     const int32_t* __restrict__ rows, int64_t M,
+                                                     const int32_t* __restrict__ cols, int64_t N,
+                                                     double* __restrict__ out)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= M * N) return;
+    const int64_t m = idx / N, n = idx - m * N;
+    out[idx] = P[(int64_t)rows[m] * nbf + cols[n]];
+}
+
+}  // namespace
+
+hipError_t launch_gemm_f64(int64_t M, int64_t N, int64_t K, const double* A, int64_t lda, const double* B, int64_t ldb,
+                           bool bt, double* C, int64_t ldc, int nsplit, int64_t split_stride, hipStream_t s)
+{
+    if (M <= 0 || N <= 0) return hipSuccess;
+    if (nsplit < 1) nsplit = 1;
+    int64_t kchunk = (K + nsplit - 1) / nsplit;
+    kchunk = ((kchunk + TK - 1) / TK) * TK;
+    if (kchunk <= 0) kchunk = TK;
+    const int64_t nz = (K + kchunk - 1) / kchunk;
+    dim3 grid((unsigned)((N + TN - 1) / TN), (unsigned)((M + TM - 1) / TM), (unsigned)(nz > 0 ? nz : 1)), block(256);
+    hipLaunchKernelGGL(gemm_f64_kernel, grid, block, 0, s, M, N, K, A, lda, B, ldb, bt ? 1 : 0, C, ldc, kchunk,
+                       split_stride);
+    if (nz < nsplit) {
+        // chunks beyond the K range would be left unwritten: clear them
+        for (int64_t z = nz; z < nsplit; ++z) {
+            hipError_t e = launch_fill(C + z * split_stride, M * ldc, 0.0, s);
+            if (e != hipSuccess) return e;
+        }
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_scatter(const double* part, int nsplit, int64_t stride, int64_t M, int64_t N,
+                                 const int32_t* rows, const int32_t* cols, double* Kt, int64_t nbf, hipStream_t s)
+{
+    if (M <= 0 || N <= 0) return hipSuccess;
+    const int64_t n = M * N;
+    hipLaunchKernelGGL(reduce_scatter_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part, nsplit, stride,
+                       M, N, rows, cols, Kt, nbf);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(fill_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_finish(const double* Kt, const double* P, double* K, int64_t nbf, double* partial, int nblk,
+                         double* ex, hipStream_t s)
+{
+    hipLaunchKernelGGL(finish_kernel, dim3(nblk), dim3(256), 0, s, Kt, P, K, nbf, partial);
+    hipLaunchKernelGGL(finish_reduce_kernel, dim3(1), dim3(256), 0, s, partial, nblk, ex);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(const double* P, int64_t nbf, const int32_t* rows, int64_t M, const int32_t* cols, int64_t N,
+                         double* out, hipStream_t s)
+{
+    if (M <= 0 || N <= 0) return hipSuccess;
+    const int64_t n = M * N;
+    hipLaunchKernelGGL(gather_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, P, nbf, rows, M, cols, N, out);
+    return hipGetLastError();
+}
+
+}  // namespace snk

@@ -1,0 +1,810 @@
+// Host runtime of the sn-K library: argument validation, geometry set-up (shell-pair
+// table, spatial grid batches, basis screening, batch groups sized to the device
+// budget), the per-density build loop of Alg. 1 on one GPU, and the C ABI of snk.h.
+#include "snk.h"
+#include "snk_internal.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+using namespace snk;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+const double kPi = 3.14159265358979323846;
+
+int ncart(int l) { return (l + 1) * (l + 2) / 2; }
+
+struct Group {
+    int b0 = 0, b1 = 0;                 // batch range [b0, b1)
+    int64_t ncols = 0;                  // (b1 - b0) * kBatch
+    std::vector<int32_t> coll_shells;   // shells collocated for this group (basis screening, Eq. basis_screen)
+    std::vector<int32_t> coll_rows;     // row of each such shell's first function in Phi_g
+    std::vector<int32_t> coll_fn;       // global function index of every Phi_g row
+    int32_t nB = 0;                     // rows of Phi_g
+    int32_t* d_coll_shells = nullptr;
+    int32_t* d_coll_rows = nullptr;
+    int32_t* d_coll_fn = nullptr;
+    bool all_functions = true;          // Phi_g rows == all basis functions in order
+};
+
+}  // namespace
+
+struct snk_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    snk_opts opts{};
+    std::string err;
+
+    // basis
+    int nshell = 0, nbf = 0;
+    std::vector<int32_t> sl, snp, spo, sfn;
+    std::vector<double> scen, exps, coefs;
+    ShellDev* d_shells = nullptr;
+    double* d_exps = nullptr;
+    double* d_coefs = nullptr;
+
+    // shell pairs
+    std::vector<PairHdr> pairs;
+    std::vector<PrimPair> prims;
+    std::vector<int32_t> pair_a, pair_b;  // A and B shell of each pair
+    PairHdr* d_pairs = nullptr;
+    PrimPair* d_prims = nullptr;
+    PairTask* d_tasks[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    int32_t ntask[6] = {0, 0, 0, 0, 0, 0};
+    int64_t task_prims[6] = {0, 0, 0, 0, 0, 0};   // surviving primitive pairs summed over a class's tasks
+    int64_t n_prim_pairs_total = 0, n_prim_pairs_kept = 0;
+
+    // grid
+    int64_t npts = 0;
+    int nbatch = 0;
+    double *d_px = nullptr, *d_py = nullptr, *d_pz = nullptr, *d_pw = nullptr;
+    std::vector<int32_t> batch_npts;
+
+    // batch groups and workspace
+    std::vector<Group> groups;
+    int64_t max_cols = 0;
+    int32_t max_nB = 0;
+    int nsplit = 1;
+    double *d_Phi = nullptr, *d_F = nullptr, *d_G = nullptr, *d_part = nullptr, *d_Pg = nullptr;
+    double *d_Kt = nullptr, *d_P = nullptr, *d_K = nullptr, *d_partial = nullptr, *d_ex = nullptr;
+    double* d_boys = nullptr;
+    int nfinish = 256;
+
+    hipEvent_t ev[16] = {};
+};
+
+namespace {
+
+#define HIPCHECK(ctx, expr)                                                                       \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess) {                                                                   \
+            set_err(ctx, std::string(#expr) + ": " + hipGetErrorString(e_));                      \
+            return e_ == hipErrorOutOfMemory ? SNK_E_NOMEM : SNK_E_DEVICE;                        \
+        }                                                                                         \
+    } while (0)
+
+void set_err(snk_ctx* ctx, const std::string& m)
+{
+    if (ctx) ctx->err = m;
+    g_last_error = m;
+}
+
+int arg_error(snk_ctx* ctx, const std::string& m)
+{
+    set_err(ctx, m);
+    return SNK_E_ARG;
+}
+
+bool isfin(double x) { return std::isfinite(x); }
+
+// ---------------------------------------------------------------------------------------------
+// Boys table by Gauss-Legendre quadrature of the defining integral (Eq. boys), long double.
+// ---------------------------------------------------------------------------------------------
+void gauss_legendre(int n, std::vector<long double>& x, std::vector<long double>& w)
+{
+    x.assign(n, 0.0L);
+    w.assign(n, 0.0L);
+    const long double pi = 3.141592653589793238462643383279502884L;
+    for (int i = 0; i < (n + 1) / 2; ++i) {
+        long double z = cosl(pi * (i + 0.75L) / (n + 0.5L));
+        long double pp = 0.0L;
+        for (int it = 0; it < 100; ++it) {
+            long double p1 = 1.0L, p2 = 0.0L;
+            for (int k = 1; k <= n; ++k) {
+                long double p3 = p2;
+                p2 = p1;
+                p1 = ((2.0L * k - 1.0L) * z * p2 - (k - 1.0L) * p3) / k;
+            }
+            pp = n * (z * p1 - p2) / (z * z - 1.0L);
+            long double dz = p1 / pp;
+            z -= dz;
+            if (fabsl(dz) < 1e-19L) break;
+        }
+        x[i] = -z;
+        x[n - 1 - i] = z;
+        w[i] = w[n - 1 - i] = 2.0L / ((1.0L - z * z) * pp * pp);
+    }
+}
+
+std::vector<double> make_boys_table()
+{
+    std::vector<long double> gx, gw;
+    gauss_legendre(160, gx, gw);
+    std::vector<double> tab((size_t)kBoysRows * kBoysCols);
+    for (int k = 0; k < kBoysRows; ++k) {
+        const long double T = (long double)k * kBoysStep;
+        for (int m = 0; m < kBoysCols; ++m) {
+            long double s = 0.0L;
+            for (size_t q = 0; q < gx.size(); ++q) {
+                const long double y = 0.5L * (gx[q] + 1.0L);
+                s += gw[q] * powl(y, 2 * m) * expl(-T * y * y);
+            }
+            tab[(size_t)k * kBoysCols + m] = (double)(0.5L * s);
+        }
+    }
+    return tab;
+}
+
+const std::vector<double>& boys_table()
+{
+    static const std::vector<double> t = make_boys_table();
+    return t;
+}
+
+template <typename T>
+int dalloc(snk_ctx* ctx, T** p, size_t n)
+{
+    *p = nullptr;
+    if (n == 0) n = 1;
+    hipError_t e = hipMalloc((void**)p, n * sizeof(T));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        set_err(ctx, std::string("hipMalloc: ") + hipGetErrorString(e));
+        return e == hipErrorOutOfMemory ? SNK_E_NOMEM : SNK_E_DEVICE;
+    }
+    return SNK_OK;
+}
+
+template <typename T>
+int upload(snk_ctx* ctx, T** p, const std::vector<T>& v)
+{
+    int rc = dalloc(ctx, p, v.size());
+    if (rc) return rc;
+    if (!v.empty()) HIPCHECK(ctx, hipMemcpy(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return SNK_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// validation
+// ---------------------------------------------------------------------------------------------
+int validate_basis(snk_ctx* ctx, const snk_basis* b)
+{
+    if (!b) return arg_error(ctx, "basis is NULL");
+    if (b->nshell < 1) return arg_error(ctx, "basis has no shells");
+    if (!b->center || !b->l || !b->nprim || !b->prim_off || !b->exps || !b->coefs)
+        return arg_error(ctx, "basis has a NULL array");
+    for (int s = 0; s < b->nshell; ++s) {
+        if (b->l[s] < 0 || b->l[s] > SNK_MAX_L) return arg_error(ctx, "shell angular momentum outside 0..2");
+        if (b->nprim[s] < 1 || b->nprim[s] > SNK_MAX_NPRIM) return arg_error(ctx, "primitive count outside 1..8");
+        if (b->prim_off[s] < 0) return arg_error(ctx, "negative primitive offset");
+        for (int d = 0; d < 3; ++d)
+            if (!isfin(b->center[3 * s + d])) return arg_error(ctx, "non-finite shell centre");
+        for (int k = 0; k < b->nprim[s]; ++k) {
+            const double e = b->exps[b->prim_off[s] + k], c = b->coefs[b->prim_off[s] + k];
+            if (!isfin(e) || !(e > 0.0)) return arg_error(ctx, "exponent not finite and positive");
+            if (!isfin(c)) return arg_error(ctx, "non-finite contraction coefficient");
+        }
+    }
+    return SNK_OK;
+}
+
+int validate_grid(snk_ctx* ctx, const snk_grid* g, const double* w)
+{
+    if (!g) return arg_error(ctx, "grid is NULL");
+    if (g->npts < 0) return arg_error(ctx, "negative point count");
+    if (g->npts == 0) return SNK_OK;
+    if (!g->xyz || !w) return arg_error(ctx, "grid points or weights are NULL");
+    if (g->npts > (int64_t)1 << 40) return arg_error(ctx, "too many grid points");
+    for (int64_t i = 0; i < 3 * g->npts; ++i)
+        if (!isfin(g->xyz[i])) return arg_error(ctx, "non-finite grid point");
+    for (int64_t i = 0; i < g->npts; ++i)
+        if (!isfin(w[i]) || w[i] < 0.0) return arg_error(ctx, "weight not finite and non-negative");
+    return SNK_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// set-up pieces
+// ---------------------------------------------------------------------------------------------
+
+// Shell-pair table (App. A data): unique pairs oriented l_A >= l_B, primitive pairs whose
+// prefactor is below 1e-30 / max(1,|AB|)^(l_A+l_B) are dropped (their contribution is far
+// below double-precision resolution of any integral of the pair).
+void build_pairs(snk_ctx* c)
+{
+    c->pairs.clear();
+    c->prims.clear();
+    c->pair_a.clear();
+    c->pair_b.clear();
+    for (int s = 0; s < c->nshell; ++s) {
+        for (int t = 0; t <= s; ++t) {
+            int A = s, B = t;
+            if (c->sl[t] > c->sl[s]) std::swap(A, B);
+            const double* RA = &c->scen[3 * A];
+            const double* RB = &c->scen[3 * B];
+            const double AB[3] = {RA[0] - RB[0], RA[1] - RB[1], RA[2] - RB[2]};
+            const double ab2 = AB[0] * AB[0] + AB[1] * AB[1] + AB[2] * AB[2];
+            const int L = c->sl[A] + c->sl[B];
+            const double grow = std::pow(std::max(1.0, std::sqrt(ab2)), L);
+            PairHdr h{};
+            h.prim_begin = (int32_t)c->prims.size();
+            h.fa = c->sfn[A];
+            h.fb = c->sfn[B];
+            h.ABx = AB[0];
+            h.ABy = AB[1];
+            h.ABz = AB[2];
+            for (int i = 0; i < c->snp[A]; ++i) {
+                for (int j = 0; j < c->snp[B]; ++j) {
+                    const double za = c->exps[c->spo[A] + i], zb = c->exps[c->spo[B] + j];
+                    const double ca = c->coefs[c->spo[A] + i], cb = c->coefs[c->spo[B] + j];
+                    const double zp = za + zb;
+                    const double pref = 2.0 * kPi / zp * std::exp(-za * zb / zp * ab2) * ca * cb;
+                    c->n_prim_pairs_total++;
+                    if (std::fabs(pref) * grow < 1e-30) continue;
+                    PrimPair q{};
+                    q.zp = zp;
+                    q.oo2zp = 0.5 / zp;
+                    q.Px = (za * RA[0] + zb * RB[0]) / zp;
+                    q.Py = (za * RA[1] + zb * RB[1]) / zp;
+                    q.Pz = (za * RA[2] + zb * RB[2]) / zp;
+                    q.PAx = q.Px - RA[0];
+                    q.PAy = q.Py - RA[1];
+                    q.PAz = q.Pz - RA[2];
+                    q.pref = pref;
+                    c->prims.push_back(q);
+                    c->n_prim_pairs_kept++;
+                }
+            }
+            h.nprim = (int32_t)c->prims.size() - h.prim_begin;
+            c->pairs.push_back(h);
+            c->pair_a.push_back(A);
+            c->pair_b.push_back(B);
+        }
+    }
+}
+
+int class_of(int la, int lb)  // la >= lb: ss, ps, pp, ds, dp, dd
+{
+    static const int tab[3][3] = {{0, -1, -1}, {1, 2, -1}, {3, 4, 5}};
+    return tab[la][lb];
+}
+const int kClassLA[6] = {0, 1, 1, 2, 2, 2};
+const int kClassLB[6] = {0, 0, 1, 0, 1, 2};
+
+// Spatial batches (Sec. II.E): per parent atom, recursive bisection on the longest
+// bounding-box axis into pieces of kBatch points (one remainder piece per atom).
+void split_points(const double* xyz, std::vector<int64_t>& idx, size_t lo, size_t hi,
+                  std::vector<std::pair<size_t, size_t>>& out, int cap)
+{
+    const size_t n = hi - lo;
+    if (n <= (size_t)cap) {
+        if (n) out.emplace_back(lo, hi);
+        return;
+    }
+    double mn[3] = {1e300, 1e300, 1e300}, mx[3] = {-1e300, -1e300, -1e300};
+    for (size_t k = lo; k < hi; ++k)
+        for (int d = 0; d < 3; ++d) {
+            mn[d] = std::min(mn[d], xyz[3 * idx[k] + d]);
+            mx[d] = std::max(mx[d], xyz[3 * idx[k] + d]);
+        }
+    int ax = 0;
+    for (int d = 1; d < 3; ++d)
+        if (mx[d] - mn[d] > mx[ax] - mn[ax]) ax = d;
+    std::stable_sort(idx.begin() + lo, idx.begin() + hi, [&](int64_t a, int64_t b) {
+        const double va = xyz[3 * a + ax], vb = xyz[3 * b + ax];
+        return va < vb || (va == vb && a < b);
+    });
+    const size_t pieces = (n + cap - 1) / cap;
+    const size_t left = ((pieces + 1) / 2) * (size_t)cap;
+    split_points(xyz, idx, lo, lo + left, out, cap);
+    split_points(xyz, idx, lo + left, hi, out, cap);
+}
+
+int build_grid(snk_ctx* c, const snk_grid* g, const double* w)
+{
+    c->npts = g->npts;
+    const int cap = c->opts.batch_points;
+    std::vector<std::pair<size_t, size_t>> ranges;
+    std::vector<int64_t> idx(g->npts);
+    std::iota(idx.begin(), idx.end(), 0);
+    if (g->npts > 0) {
+        if (g->atom_of_point) {
+            std::stable_sort(idx.begin(), idx.end(),
+                             [&](int64_t a, int64_t b) { return g->atom_of_point[a] < g->atom_of_point[b]; });
+            size_t lo = 0;
+            while (lo < idx.size()) {
+                size_t hi = lo;
+                while (hi < idx.size() && g->atom_of_point[idx[hi]] == g->atom_of_point[idx[lo]]) ++hi;
+                split_points(g->xyz, idx, lo, hi, ranges, cap);
+                lo = hi;
+            }
+        } else {
+            split_points(g->xyz, idx, 0, idx.size(), ranges, cap);
+        }
+    }
+    c->nbatch = (int)ranges.size();
+    const size_t ncol = (size_t)c->nbatch * kBatch;
+    std::vector<double> px(ncol), py(ncol), pz(ncol), pw(ncol, 0.0);
+    c->batch_npts.assign(c->nbatch, 0);
+    for (int b = 0; b < c->nbatch; ++b) {
+        const size_t lo = ranges[b].first, hi = ranges[b].second;
+        c->batch_npts[b] = (int32_t)(hi - lo);
+        for (size_t k = 0; k < (size_t)kBatch; ++k) {
+            const int64_t p = idx[lo + (k < hi - lo ? k : 0)];
+            const size_t col = (size_t)b * kBatch + k;
+            px[col] = g->xyz[3 * p];
+            py[col] = g->xyz[3 * p + 1];
+            pz[col] = g->xyz[3 * p + 2];
+            pw[col] = k < hi - lo ? w[p] : 0.0;   // padding slots carry zero weight
+        }
+    }
+    int rc;
+    if ((rc = upload(c, &c->d_px, px))) return rc;
+    if ((rc = upload(c, &c->d_py, py))) return rc;
+    if ((rc = upload(c, &c->d_pz, pz))) return rc;
+    if ((rc = upload(c, &c->d_pw, pw))) return rc;
+    return SNK_OK;
+}
+
+// Batch groups (Alg. 1: as many batches as fit the device budget at once).
+int build_groups(snk_ctx* c)
+{
+    c->groups.clear();
+    const int64_t per_batch = (int64_t)(c->nbf + 2 * c->nbf) * kBatch * (int64_t)sizeof(double);
+    int64_t budget = c->opts.max_device_bytes;
+    if (budget <= 0) {
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) != hipSuccess) fr = (size_t)8 << 30;
+        budget = (int64_t)(0.45 * (double)fr);
+    }
+    int64_t per_group = std::max<int64_t>(1, budget / per_batch);
+    if (c->nbatch > 0 && per_group < 1) {
+        set_err(c, "device budget smaller than one batch");
+        return SNK_E_NOMEM;
+    }
+    for (int b0 = 0; b0 < c->nbatch; b0 += (int)per_group) {
+        Group gr;
+        gr.b0 = b0;
+        gr.b1 = (int)std::min<int64_t>(c->nbatch, b0 + per_group);
+        gr.ncols = (int64_t)(gr.b1 - gr.b0) * kBatch;
+        for (int s = 0; s < c->nshell; ++s) {
+            gr.coll_shells.push_back(s);
+            gr.coll_rows.push_back(c->sfn[s]);
+        }
+        for (int f = 0; f < c->nbf; ++f) gr.coll_fn.push_back(f);
+        gr.nB = c->nbf;
+        gr.all_functions = true;
+        c->groups.push_back(std::move(gr));
+    }
+    c->max_cols = 0;
+    c->max_nB = 0;
+    for (auto& gr : c->groups) {
+        c->max_cols = std::max(c->max_cols, gr.ncols);
+        c->max_nB = std::max(c->max_nB, gr.nB);
+        int rc;
+        if ((rc = upload(c, &gr.d_coll_shells, gr.coll_shells))) return rc;
+        if ((rc = upload(c, &gr.d_coll_rows, gr.coll_rows))) return rc;
+        if ((rc = upload(c, &gr.d_coll_fn, gr.coll_fn))) return rc;
+    }
+    return SNK_OK;
+}
+
+int build_tasks(snk_ctx* c)
+{
+    std::vector<std::vector<PairTask>> per(6);
+    for (size_t p = 0; p < c->pairs.size(); ++p) {
+        if (c->pairs[p].nprim == 0) continue;   // every primitive pair negligible
+        const int A = c->pair_a[p], B = c->pair_b[p];
+        const int cl = class_of(c->sl[A], c->sl[B]);
+        per[cl].push_back(PairTask{(int32_t)p, c->sfn[A], c->sfn[B], 0});
+        c->task_prims[cl] += c->pairs[p].nprim;
+    }
+    for (int cl = 0; cl < 6; ++cl) {
+        std::stable_sort(per[cl].begin(), per[cl].end(), [](const PairTask& x, const PairTask& y) {
+            return x.arow < y.arow || (x.arow == y.arow && x.brow < y.brow);
+        });
+        c->ntask[cl] = (int32_t)per[cl].size();
+        int rc = upload(c, &c->d_tasks[cl], per[cl]);
+        if (rc) return rc;
+    }
+    return SNK_OK;
+}
+
+void free_ctx(snk_ctx* c)
+{
+    if (!c) return;
+    (void)hipFree(c->d_shells);
+    (void)hipFree(c->d_exps);
+    (void)hipFree(c->d_coefs);
+    (void)hipFree(c->d_pairs);
+    (void)hipFree(c->d_prims);
+    for (int k = 0; k < 6; ++k) (void)hipFree(c->d_tasks[k]);
+    (void)hipFree(c->d_px);
+    (void)hipFree(c->d_py);
+    (void)hipFree(c->d_pz);
+    (void)hipFree(c->d_pw);
+    for (auto& g : c->groups) {
+        (void)hipFree(g.d_coll_shells);
+        (void)hipFree(g.d_coll_rows);
+        (void)hipFree(g.d_coll_fn);
+    }
+    (void)hipFree(c->d_Phi);
+    (void)hipFree(c->d_F);
+    (void)hipFree(c->d_G);
+    (void)hipFree(c->d_part);
+    (void)hipFree(c->d_Pg);
+    (void)hipFree(c->d_Kt);
+    (void)hipFree(c->d_P);
+    (void)hipFree(c->d_K);
+    (void)hipFree(c->d_partial);
+    (void)hipFree(c->d_ex);
+    (void)hipFree(c->d_boys);
+    for (auto& e : c->ev)
+        if (e) (void)hipEventDestroy(e);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+double ev_ms(hipEvent_t a, hipEvent_t b)
+{
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0.0;
+    return (double)ms;
+}
+
+}  // namespace
+
+// =============================================================================================
+// C ABI
+// =============================================================================================
+extern "C" {
+
+void snk_opts_default(snk_opts* o)
+{
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->precision = SNK_FP64;
+    o->screen = SNK_SCREEN_NONE;
+    o->eps_basis = 0.0;
+    o->eps_skip_energy = 5e-7;
+    o->eps_lowprec_energy = 5e-7;
+    o->batch_points = kBatch;
+    o->deterministic = 1;
+}
+
+int snk_version(void) { return SNK_VERSION; }
+
+const char* snk_status_string(int s)
+{
+    switch (s) {
+        case SNK_OK: return "ok";
+        case SNK_E_ARG: return "invalid argument";
+        case SNK_E_UNSUPPORTED: return "unsupported option";
+        case SNK_E_NOMEM: return "out of memory";
+        case SNK_E_DEVICE: return "device error";
+        case SNK_E_ASYM: return "density matrix not symmetric";
+        default: return "unknown status";
+    }
+}
+
+const char* snk_last_error(const snk_ctx* ctx) { return ctx ? ctx->err.c_str() : g_last_error.c_str(); }
+
+int snk_ctx_nbf(const snk_ctx* ctx) { return ctx ? ctx->nbf : 0; }
+int snk_ctx_nbatches(const snk_ctx* ctx) { return ctx ? ctx->nbatch : 0; }
+
+int snk_ctx_create(const snk_basis* basis, const snk_grid* grid, const double* weights, const snk_opts* opts,
+                   snk_ctx** out)
+{
+    if (!out) return arg_error(nullptr, "output context pointer is NULL");
+    *out = nullptr;
+    snk_opts o;
+    snk_opts_default(&o);
+    if (opts) o = *opts;
+    if (o.batch_points == 0) o.batch_points = kBatch;
+    int rc = validate_basis(nullptr, basis);
+    if (rc) return rc;
+    if ((rc = validate_grid(nullptr, grid, weights))) return rc;
+    if (o.precision != SNK_FP64 && o.precision != SNK_MIXED) return arg_error(nullptr, "unknown precision");
+    if (o.screen < SNK_SCREEN_NONE || o.screen > SNK_SCREEN_LEARNED) return arg_error(nullptr, "unknown screen mode");
+    if (o.batch_points < 1 || o.batch_points > kBatch) return arg_error(nullptr, "batch_points outside 1..256");
+    if (!isfin(o.eps_basis) || o.eps_basis < 0.0) return arg_error(nullptr, "eps_basis must be >= 0");
+    if (o.precision != SNK_FP64 || o.screen != SNK_SCREEN_NONE || o.eps_basis != 0.0) {
+        set_err(nullptr, "only the plain FP64 path is available in this build");
+        return SNK_E_UNSUPPORTED;
+    }
+
+    snk_ctx* c = new (std::nothrow) snk_ctx();
+    if (!c) return SNK_E_NOMEM;
+    c->opts = o;
+    c->device = o.device;
+    {
+        hipError_t e = hipSetDevice(c->device);
+        if (e != hipSuccess) {
+            set_err(c, std::string("hipSetDevice: ") + hipGetErrorString(e));
+            g_last_error = c->err;
+            free_ctx(c);
+            return SNK_E_DEVICE;
+        }
+    }
+#define CREATE_CHECK(x)       \
+    do {                      \
+        int rc_ = (x);        \
+        if (rc_) {            \
+            g_last_error = c->err; \
+            free_ctx(c);      \
+            return rc_;       \
+        }                     \
+    } while (0)
+
+    if (o.stream) {
+        c->stream = (hipStream_t)o.stream;
+    } else {
+        hipError_t e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            set_err(c, std::string("hipStreamCreate: ") + hipGetErrorString(e));
+            g_last_error = c->err;
+            free_ctx(c);
+            return SNK_E_DEVICE;
+        }
+        c->own_stream = true;
+    }
+    for (auto& e : c->ev) CREATE_CHECK(hipEventCreate(&e) == hipSuccess ? SNK_OK : SNK_E_DEVICE);
+
+    // basis
+    c->nshell = basis->nshell;
+    c->sl.assign(basis->l, basis->l + c->nshell);
+    c->snp.assign(basis->nprim, basis->nprim + c->nshell);
+    c->spo.resize(c->nshell);
+    c->scen.assign(basis->center, basis->center + 3 * c->nshell);
+    c->sfn.resize(c->nshell);
+    std::vector<ShellDev> sh(c->nshell);
+    int fn = 0;
+    for (int s = 0; s < c->nshell; ++s) {
+        c->sfn[s] = fn;
+        fn += ncart(c->sl[s]);
+        c->spo[s] = (int32_t)c->exps.size();
+        for (int k = 0; k < c->snp[s]; ++k) {
+            c->exps.push_back(basis->exps[basis->prim_off[s] + k]);
+            c->coefs.push_back(basis->coefs[basis->prim_off[s] + k]);
+        }
+        sh[s] = ShellDev{c->scen[3 * s], c->scen[3 * s + 1], c->scen[3 * s + 2], c->sl[s], c->snp[s], c->spo[s], 0};
+    }
+    c->nbf = fn;
+    CREATE_CHECK(upload(c, &c->d_shells, sh));
+    CREATE_CHECK(upload(c, &c->d_exps, c->exps));
+    CREATE_CHECK(upload(c, &c->d_coefs, c->coefs));
+
+    build_pairs(c);
+    CREATE_CHECK(upload(c, &c->d_pairs, c->pairs));
+    CREATE_CHECK(upload(c, &c->d_prims, c->prims));
+    CREATE_CHECK(build_tasks(c));
+    CREATE_CHECK(build_grid(c, grid, weights));
+    CREATE_CHECK(build_groups(c));
+    CREATE_CHECK(upload(c, &c->d_boys, boys_table()));
+
+    // workspace
+    const int64_t nbf = c->nbf;
+    {
+        const int64_t tiles = ((nbf + 63) / 64) * ((c->max_nB + 63) / 64);
+        int ns = (int)std::max<int64_t>(1, (2048 + tiles - 1) / std::max<int64_t>(1, tiles));
+        ns = (int)std::min<int64_t>(ns, std::max<int64_t>(1, c->max_cols / kBatch));
+        c->nsplit = std::max(1, std::min(ns, 256));
+    }
+    CREATE_CHECK(dalloc(c, &c->d_Phi, (size_t)c->max_nB * c->max_cols));
+    CREATE_CHECK(dalloc(c, &c->d_F, (size_t)nbf * c->max_cols));
+    CREATE_CHECK(dalloc(c, &c->d_G, (size_t)nbf * c->max_cols));
+    CREATE_CHECK(dalloc(c, &c->d_part, (size_t)c->nsplit * nbf * c->max_nB));
+    CREATE_CHECK(dalloc(c, &c->d_Pg, (size_t)nbf * c->max_nB));
+    CREATE_CHECK(dalloc(c, &c->d_Kt, (size_t)nbf * nbf));
+    CREATE_CHECK(dalloc(c, &c->d_P, (size_t)nbf * nbf));
+    CREATE_CHECK(dalloc(c, &c->d_K, (size_t)nbf * nbf));
+    CREATE_CHECK(dalloc(c, &c->d_partial, (size_t)c->nfinish));
+    CREATE_CHECK(dalloc(c, &c->d_ex, 1));
+#undef CREATE_CHECK
+    *out = c;
+    return SNK_OK;
+}
+
+void snk_ctx_destroy(snk_ctx* ctx)
+{
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    free_ctx(ctx);
+}
+
+int snk_ctx_build(snk_ctx* c, const double* P, double* K_out, snk_stats* stats)
+{
+    if (!c) return arg_error(nullptr, "context is NULL");
+    if (!P || !K_out) return arg_error(c, "P or K_out is NULL");
+    const bool dev = (c->opts.flags & SNK_DEVICE_PTRS) != 0;
+    const int64_t nbf = c->nbf;
+    const size_t nb2 = (size_t)nbf * nbf;
+    if (!dev) {
+        for (size_t k = 0; k < nb2; ++k)
+            if (!isfin(P[k])) return arg_error(c, "non-finite density matrix element");
+        if (c->opts.flags & SNK_VALIDATE) {
+            double mx = 0.0, asym = 0.0;
+            for (int64_t i = 0; i < nbf; ++i)
+                for (int64_t j = 0; j < nbf; ++j) {
+                    mx = std::max(mx, std::fabs(P[i * nbf + j]));
+                    asym = std::max(asym, std::fabs(P[i * nbf + j] - P[j * nbf + i]));
+                }
+            if (asym > 1e-12 * mx) {
+                set_err(c, "density matrix is not symmetric");
+                return SNK_E_ASYM;
+            }
+        }
+    }
+    const auto t_start = std::chrono::steady_clock::now();
+    HIPCHECK(c, hipSetDevice(c->device));
+    hipStream_t s = c->stream;
+    const double* dP = P;
+    double* dK = K_out;
+    if (!dev) {
+        HIPCHECK(c, hipMemcpyAsync(c->d_P, P, nb2 * sizeof(double), hipMemcpyHostToDevice, s));
+        dP = c->d_P;
+        dK = c->d_K;
+    }
+    double tcol = 0, tf = 0, tafg = 0, tk = 0;
+    double tcls[6] = {0, 0, 0, 0, 0, 0};
+    int64_t pp[6] = {0, 0, 0, 0, 0, 0}, ppp[6] = {0, 0, 0, 0, 0, 0};
+    const bool timed = stats != nullptr;
+
+    HIPCHECK(c, launch_fill(c->d_Kt, (int64_t)nb2, 0.0, s));
+    for (const Group& g : c->groups) {
+        const int64_t ld = g.ncols;
+        const int64_t off = (int64_t)g.b0 * kBatch;
+        if (timed) HIPCHECK(c, hipEventRecord(c->ev[0], s));
+        // Eq. collocation
+        HIPCHECK(c, launch_collocate(c->d_px + off, c->d_py + off, c->d_pz + off, g.ncols, c->d_shells, c->d_exps,
+                                     c->d_coefs, g.d_coll_shells, g.d_coll_rows, (int32_t)g.coll_shells.size(),
+                                     c->d_Phi, ld, s));
+        if (timed) HIPCHECK(c, hipEventRecord(c->ev[1], s));
+        // Eq. fmat: F_g = P[:, B_g] Phi_g
+        const double* Pg = dP;
+        int64_t ldp = nbf;
+        if (!g.all_functions) {
+            HIPCHECK(c, launch_gather(dP, nbf, nullptr, nbf, g.d_coll_fn, g.nB, c->d_Pg, s));
+            Pg = c->d_Pg;
+            ldp = g.nB;
+        }
+        HIPCHECK(c, launch_gemm_f64(nbf, g.ncols, g.nB, Pg, ldp, c->d_Phi, ld, false, c->d_F, ld, 1, 0, s));
+        if (timed) HIPCHECK(c, hipEventRecord(c->ev[2], s));
+        // Eqs. 3c_grid + gmat
+        HIPCHECK(c, launch_fill(c->d_G, nbf * g.ncols, 0.0, s));
+        AfgArgs a{};
+        a.px = c->d_px + off;
+        a.py = c->d_py + off;
+        a.pz = c->d_pz + off;
+        a.pw = c->d_pw + off;
+        a.F = c->d_F;
+        a.G = c->d_G;
+        a.ld = ld;
+        a.pairs = c->d_pairs;
+        a.prims = c->d_prims;
+        a.batch_task_off = nullptr;
+        a.nbatch = g.b1 - g.b0;
+        a.boys_tab = c->d_boys;
+        int64_t gpts = 0;
+        for (int b = g.b0; b < g.b1; ++b) gpts += c->batch_npts[b];
+        for (int cl = 0; cl < 6; ++cl) {
+            if (c->ntask[cl] == 0) continue;
+            a.tasks = c->d_tasks[cl];
+            a.ntask = c->ntask[cl];
+            if (timed) HIPCHECK(c, hipEventRecord(c->ev[8 + cl], s));
+            HIPCHECK(c, launch_afg(kClassLA[cl], kClassLB[cl], a, s));
+            if (timed) HIPCHECK(c, hipEventRecord(c->ev[cl == 5 ? 15 : 9 + cl], s));
+            pp[cl] += (int64_t)c->ntask[cl] * gpts;
+            ppp[cl] += c->task_prims[cl] * gpts;
+        }
+        if (timed) HIPCHECK(c, hipEventRecord(c->ev[3], s));
+        // Eq. usym_k: Kt[:, B_g] += G_g Phi_g^T, split over grid points
+        const int64_t stride = nbf * g.nB;
+        HIPCHECK(c, launch_gemm_f64(nbf, g.nB, g.ncols, c->d_G, ld, c->d_Phi, ld, true, c->d_part, g.nB, c->nsplit,
+                                    stride, s));
+        HIPCHECK(c, launch_reduce_scatter(c->d_part, c->nsplit, stride, nbf, g.nB, nullptr,
+                                          g.all_functions ? nullptr : g.d_coll_fn, c->d_Kt, nbf, s));
+        if (timed) {
+            HIPCHECK(c, hipEventRecord(c->ev[4], s));
+            HIPCHECK(c, hipEventSynchronize(c->ev[4]));
+            tcol += ev_ms(c->ev[0], c->ev[1]);
+            tf += ev_ms(c->ev[1], c->ev[2]);
+            tafg += ev_ms(c->ev[2], c->ev[3]);
+            for (int cl = 0; cl < 6; ++cl) {
+                if (c->ntask[cl] == 0) continue;
+                tcls[cl] += ev_ms(c->ev[8 + cl], c->ev[cl == 5 ? 15 : 9 + cl]);
+            }
+            tk += ev_ms(c->ev[3], c->ev[4]);
+        }
+    }
+    // Eq. sn_k and E_x
+    if (timed) HIPCHECK(c, hipEventRecord(c->ev[5], s));
+    HIPCHECK(c, launch_finish(c->d_Kt, dP, dK, nbf, c->d_partial, c->nfinish, c->d_ex, s));
+    if (timed) HIPCHECK(c, hipEventRecord(c->ev[6], s));
+    double ex = 0.0;
+    if (!dev) {
+        HIPCHECK(c, hipMemcpyAsync(K_out, dK, nb2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    }
+    if (!dev || timed) {
+        HIPCHECK(c, hipMemcpyAsync(&ex, c->d_ex, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHECK(c, hipStreamSynchronize(s));
+    }
+    if (stats) {
+        std::memset(stats, 0, sizeof(*stats));
+        stats->ex = ex;
+        stats->t_total_ms =
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+        stats->t_collocate_ms = tcol;
+        stats->t_fgemm_ms = tf;
+        stats->t_afg_ms = tafg;
+        stats->t_kgemm_ms = tk;
+        stats->t_finish_ms = ev_ms(c->ev[5], c->ev[6]);
+        for (int k = 0; k < 6; ++k) {
+            stats->pair_points[k] = pp[k];
+            stats->prim_pair_points[k] = ppp[k];
+            stats->t_afg_class_ms[k] = tcls[k];
+        }
+        stats->n_batches = c->nbatch;
+        stats->n_groups = (int32_t)c->groups.size();
+    }
+    return SNK_OK;
+}
+
+int sn_k_build(const snk_basis* basis, const snk_grid* grid, const double* weights, const double* P, double* K_out,
+               const snk_opts* opts)
+{
+    snk_ctx* c = nullptr;
+    int rc = snk_ctx_create(basis, grid, weights, opts, &c);
+    if (rc) return rc;
+    rc = snk_ctx_build(c, P, K_out, opts ? opts->stats : nullptr);
+    if (rc) g_last_error = c->err;
+    snk_ctx_destroy(c);
+    return rc;
+}
+
+int snk_boys_device(const double* T, int64_t n, int mmax, double* F_out, void* stream)
+{
+    if (n < 0 || mmax < 0 || mmax > 2 * SNK_MAX_L) return arg_error(nullptr, "bad Boys request");
+    if (n == 0) return SNK_OK;
+    if (!T || !F_out) return arg_error(nullptr, "NULL pointer");
+    static double* d_tab = nullptr;
+    static int tab_dev = -1;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return SNK_E_DEVICE;
+    if (!d_tab || tab_dev != dev) {
+        const auto& t = boys_table();
+        if (hipMalloc((void**)&d_tab, t.size() * sizeof(double)) != hipSuccess) return SNK_E_NOMEM;
+        if (hipMemcpy(d_tab, t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+            return SNK_E_DEVICE;
+        tab_dev = dev;
+    }
+    hipError_t e = launch_boys_eval(T, n, mmax, F_out, d_tab, (hipStream_t)stream);
+    if (e != hipSuccess) {
+        g_last_error = hipGetErrorString(e);
+        return SNK_E_DEVICE;
+    }
+    return SNK_OK;
+}
+
+}  // extern "C"

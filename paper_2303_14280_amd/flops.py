@@ -1,0 +1,81 @@
+"""Algorithmic work model of the 3c-CP digestion step (App. A, Eqs. vrr, hrr, gmat).
+
+Counts the floating-point operations the recursions need as written, walking
+them term by term (add/sub/mul = 1, fused multiply-add = 2):
+
+per primitive pair and grid point
+  - P - r_i and T = zeta_p |P - r_i|^2                                  9
+  - Boys function F_0..F_L, charged at its asymptotic branch            4 + 2L
+    (F_0 = c rsqrt(T), h = r^2/2, F_m = F_{m-1} (2m-1) h)
+  - base case Theta^n_0 = pref F_n                                      L + 1
+  - each VRR term: PA_q Theta^n - PC_q Theta^{n+1}                      3
+    plus, when a_q > 0, a_q/(2 zeta_p) (Theta^n_{a-1} - Theta^{n+1}_{a-1})  4 more
+  - contraction of Theta^0 over primitives (one add per target)
+per shell pair and grid point
+  - each HRR term                                                        2
+  - digestion G_a += A F_b and G_b += A^T F_a                           4 n_a n_b
+  - weights and component norms on the updates                          2 (n_a + n_b)
+
+The model is the unit of the reported FLOP rates; the kernels execute more
+instructions than this (table-driven Boys branch, address arithmetic).
+"""
+from __future__ import annotations
+
+from functools import lru_cache
+from typing import Tuple
+
+
+def ncart(l: int) -> int:
+    return (l + 1) * (l + 2) // 2
+
+
+def comps(l: int):
+    out = []
+    for x in range(l, -1, -1):
+        for y in range(l - x, -1, -1):
+            out.append((x, y, l - x - y))
+    return out
+
+
+def _dir(c) -> int:
+    return 0 if c[0] > 0 else (1 if c[1] > 0 else 2)
+
+
+@lru_cache(maxsize=None)
+def per_prim_pair(la: int, lb: int) -> int:
+    L = la + lb
+    f = 9 + (4 + 2 * L) + (L + 1)
+    for l in range(1, L + 1):
+        for c in comps(l):
+            q = _dir(c)
+            am = c[q] - 1
+            for _n in range(0, L - l + 1):
+                f += 3 + (4 if am > 0 else 0)
+    f += sum(ncart(l) for l in range(la, L + 1))
+    return f
+
+
+@lru_cache(maxsize=None)
+def per_shell_pair(la: int, lb: int) -> int:
+    f = 0
+    for lbp in range(1, lb + 1):
+        for _cb in comps(lbp):
+            for lap in range(la, la + lb - lbp + 1):
+                f += 2 * ncart(lap)
+    na, nb = ncart(la), ncart(lb)
+    return f + 4 * na * nb + 2 * (na + nb)
+
+
+CLASS_L: Tuple[Tuple[int, int], ...] = ((0, 0), (1, 0), (1, 1), (2, 0), (2, 1), (2, 2))
+
+
+def class_flops(cls: int, pair_points: int, prim_pair_points: int) -> float:
+    la, lb = CLASS_L[cls]
+    return float(prim_pair_points) * per_prim_pair(la, lb) + float(pair_points) * per_shell_pair(la, lb)
+
+
+# MI355X (gfx950) peaks used for roofline fractions
+PEAK_FP64_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12   # 78.6: 256 CU x 4 SIMD x 16 lanes x FMA x 2.4 GHz
+PEAK_FP64_MFMA_TFLOPS = 78.6
+PEAK_BF16_MFMA_TFLOPS = 2500.0
+PEAK_HBM_GBS = 8000.0
