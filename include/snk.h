@@ -166,6 +166,28 @@ int snk_version(void);
  */
 int snk_boys_device(const double* T, int64_t n, int mmax, double* F_out, void* stream);
 
+/*
+ * Test hooks (diagnostics; not needed for building K).
+ *
+ * snk_debug_gemm_f64: C = A op(B) with the library's FP64 matrix-core GEMM on device
+ *   pointers: A is M x K row-major (lda), B is K x N row-major (ldb) or, with bt != 0,
+ *   N x K row-major; C is M x N row-major (ldc).  Ordered on `stream`.
+ * snk_debug_mfma_layout: writes 256 doubles to host memory `out`: element 4*lane + r of
+ *   one v_mfma_f64_16x16x4f64 whose inputs encode D[i][j] = 100 j + i (layout check).
+ * snk_ctx_point_order: col_to_point[c] (host, nbatches*256 entries) = input index of the
+ *   grid point in batch column c, or -1 for a padding slot.
+ * snk_ctx_debug_intermediates: for the first batch group only, the collocation matrix
+ *   Phi (Eq. collocation), F (Eq. fmat) and G (Eq. gmat), each nbf x ncols row-major in
+ *   host memory (ncols = 256 * batches of that group, returned in *ncols_out); P is a host
+ *   pointer.  Pass NULL for any output not wanted.
+ */
+int snk_debug_gemm_f64(int64_t M, int64_t N, int64_t K, const double* A, int64_t lda, const double* B,
+                       int64_t ldb, int bt, double* C, int64_t ldc, void* stream);
+int snk_debug_mfma_layout(double* out);
+int snk_ctx_point_order(const snk_ctx* ctx, int64_t* col_to_point);
+int snk_ctx_debug_intermediates(snk_ctx* ctx, const double* P, double* Phi, double* F, double* G,
+                                int64_t* ncols_out);
+
 #ifdef __cplusplus
 }
 #endif

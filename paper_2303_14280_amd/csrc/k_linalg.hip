@@ -15,7 +15,8 @@ constexpr int TM = 64, TN = 64, TK = 16;
 
 // 256 threads = 4 wave64; wave w owns the 32x32 quadrant (w/2, w%2) of the 64x64 tile as
 // 2x2 MFMA 16x16 blocks.  Operand layout of v_mfma_f64_16x16x4f64 (wave64):
-//   A[i][k] in lane i + 16k, B[k][j] in lane j + 16k, D[i][j] in lane j + 16(i/4), element i%4.
+//   A[i][k] in lane i + 16k, B[k][j] in lane j + 16k, D[i][j] in lane j + 16(i%4), element i/4
+//   (the accumulator layout was measured with the probe kernel below).
 __global__ __launch_bounds__(256) void gemm_f64_kernel(int64_t M, int64_t N, int64_t K, const double* __restrict__ A,
                                                        int64_t lda, const double* __restrict__ B, int64_t ldb, int bt,
                                                        double* __restrict__ C, int64_t ldc, int64_t kchunk,
@@ -84,7 +85,7 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(int64_t M, int64_t N, int
         for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int64_t gm = m0 + wm + bi * 16 + 4 * lk + r;
+                const int64_t gm = m0 + wm + bi * 16 + 4 * r + lk;
                 const int64_t gn = n0 + wn + bj * 16 + li;
                 if (gm < M && gn < N) C[gm * ldc + gn] = acc[bi][bj][r];
             }
@@ -157,10 +158,31 @@ __global__ __launch_bounds__(256) void gather_kernel(const double* __restrict__ 
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= M * N) return;
     const int64_t m = idx / N, n = idx - m * N;
-    out[idx] = P[(int64_t)rows[m] * nbf + cols[n]];
+    const int64_t r = rows ? rows[m] : m;
+    const int64_t c = cols ? cols[n] : n;
+    out[idx] = P[r * nbf + c];
+}
+
+// One wave: A[i][k] = (k == 0) + i (k == 1), B[k][j] = 100 j (k == 0) + (k == 1), so that
+// D[i][j] = 100 j + i; every lane writes its four accumulator elements.
+__global__ void mfma_probe_kernel(double* __restrict__ out)
+{
+    const int lane = threadIdx.x;
+    const int i = lane & 15, k = lane >> 4;
+    const double a = k == 0 ? 1.0 : (k == 1 ? (double)i : 0.0);
+    const double b = k == 0 ? 100.0 * i : (k == 1 ? 1.0 : 0.0);
+    d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    for (int r = 0; r < 4; ++r) out[4 * lane + r] = acc[r];
 }
 
 }  // namespace
+
+hipError_t launch_mfma_probe(double* out_dev, hipStream_t s)
+{
+    hipLaunchKernelGGL(mfma_probe_kernel, dim3(1), dim3(64), 0, s, out_dev);
+    return hipGetLastError();
+}
 
 hipError_t launch_gemm_f64(int64_t M, int64_t N, int64_t K, const double* A, int64_t lda, const double* B, int64_t ldb,
                            bool bt, double* C, int64_t ldc, int nsplit, int64_t split_stride, hipStream_t s)

@@ -69,6 +69,7 @@ struct snk_ctx {
     int nbatch = 0;
     double *d_px = nullptr, *d_py = nullptr, *d_pz = nullptr, *d_pw = nullptr;
     std::vector<int32_t> batch_npts;
+    std::vector<int64_t> col_point;       // input index of the point in each batch column, -1 = padding
 
     // batch groups and workspace
     std::vector<Group> groups;
@@ -346,6 +347,7 @@ int build_grid(snk_ctx* c, const snk_grid* g, const double* w)
     const size_t ncol = (size_t)c->nbatch * kBatch;
     std::vector<double> px(ncol), py(ncol), pz(ncol), pw(ncol, 0.0);
     c->batch_npts.assign(c->nbatch, 0);
+    c->col_point.assign(ncol, -1);
     for (int b = 0; b < c->nbatch; ++b) {
         const size_t lo = ranges[b].first, hi = ranges[b].second;
         c->batch_npts[b] = (int32_t)(hi - lo);
@@ -356,6 +358,7 @@ int build_grid(snk_ctx* c, const snk_grid* g, const double* w)
             py[col] = g->xyz[3 * p + 1];
             pz[col] = g->xyz[3 * p + 2];
             pw[col] = k < hi - lo ? w[p] : 0.0;   // padding slots carry zero weight
+            if (k < hi - lo) c->col_point[col] = p;
         }
     }
     int rc;
@@ -633,6 +636,62 @@ void snk_ctx_destroy(snk_ctx* ctx)
     free_ctx(ctx);
 }
 
+}  // extern "C"
+
+namespace {
+
+// Steps of one batch group up to G: Eq. collocation, Eq. fmat, Eqs. 3c_grid + gmat.
+int group_until_G(snk_ctx* c, const Group& g, const double* dP, bool timed)
+{
+    hipStream_t s = c->stream;
+    const int64_t nbf = c->nbf;
+    const int64_t ld = g.ncols;
+    const int64_t off = (int64_t)g.b0 * kBatch;
+    if (timed) HIPCHECK(c, hipEventRecord(c->ev[0], s));
+    HIPCHECK(c, launch_collocate(c->d_px + off, c->d_py + off, c->d_pz + off, g.ncols, c->d_shells, c->d_exps,
+                                 c->d_coefs, g.d_coll_shells, g.d_coll_rows, (int32_t)g.coll_shells.size(), c->d_Phi,
+                                 ld, s));
+    if (timed) HIPCHECK(c, hipEventRecord(c->ev[1], s));
+    // F_g = P[:, B_g] Phi_g
+    const double* Pg = dP;
+    int64_t ldp = nbf;
+    if (!g.all_functions) {
+        HIPCHECK(c, launch_gather(dP, nbf, nullptr, nbf, g.d_coll_fn, g.nB, c->d_Pg, s));
+        Pg = c->d_Pg;
+        ldp = g.nB;
+    }
+    HIPCHECK(c, launch_gemm_f64(nbf, g.ncols, g.nB, Pg, ldp, c->d_Phi, ld, false, c->d_F, ld, 1, 0, s));
+    if (timed) HIPCHECK(c, hipEventRecord(c->ev[2], s));
+    HIPCHECK(c, launch_fill(c->d_G, nbf * g.ncols, 0.0, s));
+    AfgArgs a{};
+    a.px = c->d_px + off;
+    a.py = c->d_py + off;
+    a.pz = c->d_pz + off;
+    a.pw = c->d_pw + off;
+    a.F = c->d_F;
+    a.G = c->d_G;
+    a.ld = ld;
+    a.pairs = c->d_pairs;
+    a.prims = c->d_prims;
+    a.batch_task_off = nullptr;
+    a.nbatch = g.b1 - g.b0;
+    a.boys_tab = c->d_boys;
+    for (int cl = 0; cl < 6; ++cl) {
+        if (c->ntask[cl] == 0) continue;
+        a.tasks = c->d_tasks[cl];
+        a.ntask = c->ntask[cl];
+        if (timed) HIPCHECK(c, hipEventRecord(c->ev[8 + cl], s));
+        HIPCHECK(c, launch_afg(kClassLA[cl], kClassLB[cl], a, s));
+        if (timed) HIPCHECK(c, hipEventRecord(c->ev[cl == 5 ? 15 : 9 + cl], s));
+    }
+    if (timed) HIPCHECK(c, hipEventRecord(c->ev[3], s));
+    return SNK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int snk_ctx_build(snk_ctx* c, const double* P, double* K_out, snk_stats* stats)
 {
     if (!c) return arg_error(nullptr, "context is NULL");
@@ -674,51 +733,14 @@ int snk_ctx_build(snk_ctx* c, const double* P, double* K_out, snk_stats* stats)
     HIPCHECK(c, launch_fill(c->d_Kt, (int64_t)nb2, 0.0, s));
     for (const Group& g : c->groups) {
         const int64_t ld = g.ncols;
-        const int64_t off = (int64_t)g.b0 * kBatch;
-        if (timed) HIPCHECK(c, hipEventRecord(c->ev[0], s));
-        // Eq. collocation
-        HIPCHECK(c, launch_collocate(c->d_px + off, c->d_py + off, c->d_pz + off, g.ncols, c->d_shells, c->d_exps,
-                                     c->d_coefs, g.d_coll_shells, g.d_coll_rows, (int32_t)g.coll_shells.size(),
-                                     c->d_Phi, ld, s));
-        if (timed) HIPCHECK(c, hipEventRecord(c->ev[1], s));
-        // Eq. fmat: F_g = P[:, B_g] Phi_g
-        const double* Pg = dP;
-        int64_t ldp = nbf;
-        if (!g.all_functions) {
-            HIPCHECK(c, launch_gather(dP, nbf, nullptr, nbf, g.d_coll_fn, g.nB, c->d_Pg, s));
-            Pg = c->d_Pg;
-            ldp = g.nB;
-        }
-        HIPCHECK(c, launch_gemm_f64(nbf, g.ncols, g.nB, Pg, ldp, c->d_Phi, ld, false, c->d_F, ld, 1, 0, s));
-        if (timed) HIPCHECK(c, hipEventRecord(c->ev[2], s));
-        // Eqs. 3c_grid + gmat
-        HIPCHECK(c, launch_fill(c->d_G, nbf * g.ncols, 0.0, s));
-        AfgArgs a{};
-        a.px = c->d_px + off;
-        a.py = c->d_py + off;
-        a.pz = c->d_pz + off;
-        a.pw = c->d_pw + off;
-        a.F = c->d_F;
-        a.G = c->d_G;
-        a.ld = ld;
-        a.pairs = c->d_pairs;
-        a.prims = c->d_prims;
-        a.batch_task_off = nullptr;
-        a.nbatch = g.b1 - g.b0;
-        a.boys_tab = c->d_boys;
+        int rc = group_until_G(c, g, dP, timed);
+        if (rc) return rc;
         int64_t gpts = 0;
         for (int b = g.b0; b < g.b1; ++b) gpts += c->batch_npts[b];
         for (int cl = 0; cl < 6; ++cl) {
-            if (c->ntask[cl] == 0) continue;
-            a.tasks = c->d_tasks[cl];
-            a.ntask = c->ntask[cl];
-            if (timed) HIPCHECK(c, hipEventRecord(c->ev[8 + cl], s));
-            HIPCHECK(c, launch_afg(kClassLA[cl], kClassLB[cl], a, s));
-            if (timed) HIPCHECK(c, hipEventRecord(c->ev[cl == 5 ? 15 : 9 + cl], s));
             pp[cl] += (int64_t)c->ntask[cl] * gpts;
             ppp[cl] += c->task_prims[cl] * gpts;
         }
-        if (timed) HIPCHECK(c, hipEventRecord(c->ev[3], s));
         // Eq. usym_k: Kt[:, B_g] += G_g Phi_g^T, split over grid points
         const int64_t stride = nbf * g.nB;
         HIPCHECK(c, launch_gemm_f64(nbf, g.nB, g.ncols, c->d_G, ld, c->d_Phi, ld, true, c->d_part, g.nB, c->nsplit,
@@ -781,6 +803,63 @@ int sn_k_build(const snk_basis* basis, const snk_grid* grid, const double* weigh
     if (rc) g_last_error = c->err;
     snk_ctx_destroy(c);
     return rc;
+}
+
+int snk_debug_gemm_f64(int64_t M, int64_t N, int64_t K, const double* A, int64_t lda, const double* B, int64_t ldb,
+                       int bt, double* C, int64_t ldc, void* stream)
+{
+    if (M < 0 || N < 0 || K < 0 || !A || !B || !C) return arg_error(nullptr, "bad GEMM arguments");
+    if (lda < K || ldc < N || ldb < (bt ? K : N)) return arg_error(nullptr, "leading dimension too small");
+    hipError_t e = launch_gemm_f64(M, N, K, A, lda, B, ldb, bt != 0, C, ldc, 1, 0, (hipStream_t)stream);
+    if (e != hipSuccess) {
+        g_last_error = hipGetErrorString(e);
+        return SNK_E_DEVICE;
+    }
+    return SNK_OK;
+}
+
+int snk_debug_mfma_layout(double* out)
+{
+    if (!out) return arg_error(nullptr, "NULL output");
+    double* d = nullptr;
+    if (hipMalloc((void**)&d, 256 * sizeof(double)) != hipSuccess) return SNK_E_NOMEM;
+    hipError_t e = launch_mfma_probe(d, nullptr);
+    if (e == hipSuccess) e = hipMemcpy(out, d, 256 * sizeof(double), hipMemcpyDeviceToHost);
+    (void)hipFree(d);
+    if (e != hipSuccess) {
+        g_last_error = hipGetErrorString(e);
+        return SNK_E_DEVICE;
+    }
+    return SNK_OK;
+}
+
+int snk_ctx_point_order(const snk_ctx* c, int64_t* col_to_point)
+{
+    if (!c || !col_to_point) return arg_error(nullptr, "NULL argument");
+    std::copy(c->col_point.begin(), c->col_point.end(), col_to_point);
+    return SNK_OK;
+}
+
+int snk_ctx_debug_intermediates(snk_ctx* c, const double* P, double* Phi, double* F, double* G, int64_t* ncols_out)
+{
+    if (!c || !P) return arg_error(c, "NULL argument");
+    if (c->groups.empty()) {
+        if (ncols_out) *ncols_out = 0;
+        return SNK_OK;
+    }
+    const Group& g = c->groups[0];
+    const int64_t nbf = c->nbf;
+    HIPCHECK(c, hipSetDevice(c->device));
+    HIPCHECK(c, hipMemcpyAsync(c->d_P, P, (size_t)nbf * nbf * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    int rc = group_until_G(c, g, c->d_P, false);
+    if (rc) return rc;
+    const size_t n = (size_t)nbf * g.ncols * sizeof(double);
+    if (Phi) HIPCHECK(c, hipMemcpyAsync(Phi, c->d_Phi, (size_t)g.nB * g.ncols * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    if (F) HIPCHECK(c, hipMemcpyAsync(F, c->d_F, n, hipMemcpyDeviceToHost, c->stream));
+    if (G) HIPCHECK(c, hipMemcpyAsync(G, c->d_G, n, hipMemcpyDeviceToHost, c->stream));
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    if (ncols_out) *ncols_out = g.ncols;
+    return SNK_OK;
 }
 
 int snk_boys_device(const double* T, int64_t n, int mmax, double* F_out, void* stream)

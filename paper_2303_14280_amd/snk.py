@@ -109,6 +109,16 @@ def lib():
             L.snk_boys_device.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p,
                                           ctypes.c_void_p]
             L.snk_boys_device.restype = ctypes.c_int
+            L.snk_debug_gemm_f64.argtypes = [ctypes.c_int64] * 3 + [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                                                   ctypes.c_int64, ctypes.c_int, ctypes.c_void_p,
+                                                                   ctypes.c_int64, ctypes.c_void_p]
+            L.snk_debug_gemm_f64.restype = ctypes.c_int
+            L.snk_debug_mfma_layout.argtypes = [ctypes.c_void_p]
+            L.snk_debug_mfma_layout.restype = ctypes.c_int
+            L.snk_ctx_point_order.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+            L.snk_ctx_point_order.restype = ctypes.c_int
+            L.snk_ctx_debug_intermediates.argtypes = [ctypes.c_void_p] * 5 + [ctypes.POINTER(ctypes.c_int64)]
+            L.snk_ctx_debug_intermediates.restype = ctypes.c_int
             _lib = L
     return _lib
 
@@ -210,6 +220,25 @@ class Context:
                                    ctypes.byref(st) if stats else None), self.handle)
         return st.as_dict() if stats else None
 
+    def point_order(self) -> np.ndarray:
+        """Input point index of every batch column (-1 = padding slot)."""
+        out = np.zeros(self.nbatches * 256, np.int64)
+        _check(lib().snk_ctx_point_order(self.handle, out.ctypes.data), self.handle)
+        return out
+
+    def debug_intermediates(self, P: np.ndarray):
+        """(Phi, F, G) of the first batch group, each nbf x ncols (host-pointer contexts)."""
+        P = np.ascontiguousarray(P, np.float64)
+        n = ctypes.c_int64(0)
+        _check(lib().snk_ctx_debug_intermediates(self.handle, P.ctypes.data, None, None, None, ctypes.byref(n)),
+               self.handle)
+        Phi = np.zeros((self.nbf, n.value))
+        F = np.zeros_like(Phi)
+        G = np.zeros_like(Phi)
+        _check(lib().snk_ctx_debug_intermediates(self.handle, P.ctypes.data, Phi.ctypes.data, F.ctypes.data,
+                                                 G.ctypes.data, ctypes.byref(n)), self.handle)
+        return Phi, F, G
+
     def close(self):
         if getattr(self, "handle", None):
             lib().snk_ctx_destroy(self.handle)
@@ -226,3 +255,14 @@ def boys_device(T_ptr: int, n: int, mmax: int, F_ptr: int, stream: int = 0):
     """F_m(T[k]) for m = 0..mmax on the device (pointers to FP64 device memory)."""
     _check(lib().snk_boys_device(ctypes.c_void_p(T_ptr), int(n), int(mmax), ctypes.c_void_p(F_ptr),
                                  ctypes.c_void_p(stream) if stream else None))
+
+
+def debug_gemm_f64(M, N, K, A_ptr, lda, B_ptr, ldb, bt, C_ptr, ldc, stream: int = 0):
+    _check(lib().snk_debug_gemm_f64(M, N, K, ctypes.c_void_p(A_ptr), lda, ctypes.c_void_p(B_ptr), ldb, int(bt),
+                                    ctypes.c_void_p(C_ptr), ldc, ctypes.c_void_p(stream) if stream else None))
+
+
+def debug_mfma_layout() -> np.ndarray:
+    out = np.zeros(256)
+    _check(lib().snk_debug_mfma_layout(out.ctypes.data))
+    return out
