@@ -27,7 +27,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(system, target_s: float = 15.0):
+def cpu_baseline(system, target_s: float = 20.0):
     """The CPU oracle timed on a bounded sample of the same workload (every k-th grid point)."""
     import numpy as np
     from oracle import oracle as O
@@ -50,6 +50,27 @@ def cpu_baseline(system, target_s: float = 15.0):
                       % (stride, sample.npts, system.npts, npair, dt)}
 
 
+def afg_source_sha() -> str:
+    import hashlib
+    d = os.path.join(ROOT, "paper_2303_14280_amd", "csrc")
+    src = b"".join(open(os.path.join(d, f), "rb").read() for f in ("k_afg.hip", "snk_internal.h"))
+    return hashlib.sha256(src).hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 summaries, or None when the
+    kernel source has changed since the counters were taken."""
+    import glob
+    import re
+    sha = afg_source_sha()
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        for line in open(path):
+            m = re.match(r"traffic: kernel=(\S+) sha=(\w+) read_bytes=(\S+) write_bytes=(\S+)", line.strip())
+            if m and m.group(1) == kernel and m.group(2) == sha:
+                return float(m.group(3)) + float(m.group(4)), os.path.basename(path)
+    return None, None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -57,7 +78,19 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        n = args.calibrate_copy * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log("copied %d MiB" % args.calibrate_copy)
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (the grid-batch "
               "sharding is described in DESIGN.md); rerun with --gpus 1", file=sys.stderr)
@@ -113,6 +146,8 @@ def main():
     cls_flops = [flops.class_flops(c, pair_points[c], prim_points[c]) for c in range(6)]
     dom = int(np.argmax(t_cls))
     achieved = cls_flops[dom] / (t_cls[dom] * 1e-3) / 1e12
+    dom_name = "afg_kernel<%d,%d>" % flops.CLASS_L[dom]
+    traffic, traffic_src = measured_traffic(dom_name)
     afg_total = sum(cls_flops) / (st["t_afg_ms"] * 1e-3) / 1e12
 
     out = {
@@ -136,7 +171,9 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "kernel": "afg_kernel<%d,%d> (%s)" % (flops.CLASS_L[dom] + (CLASSES[dom],)),
                      "achieved": achieved, "peak": flops.PEAK_FP64_VALU_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / flops.PEAK_FP64_VALU_TFLOPS, "traffic": None,
+                     "frac": achieved / flops.PEAK_FP64_VALU_TFLOPS, "traffic": traffic,
+                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                     "traffic_source": traffic_src,
                      "launch_ms": float(t_cls[dom]), "algorithmic_flops": cls_flops[dom]},
         "phases_ms": {"collocate": st["t_collocate_ms"], "fgemm": st["t_fgemm_ms"], "afg": st["t_afg_ms"],
                       "kgemm": st["t_kgemm_ms"], "finish": st["t_finish_ms"]},

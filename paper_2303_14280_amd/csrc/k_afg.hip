@@ -9,11 +9,13 @@
 //
 // Work mapping (gfx950): one workgroup = one 256-point batch = four wave64; a
 // lane owns one grid point, so every G update is lane-private (no atomics and a
-// fixed summation order).  All lanes of a wave walk the same shell-pair list:
-// pair and primitive data are wave-uniform (scalar loads), F/G rows are read and
-// written as 512-byte coalesced vectors.  Consecutive pairs that share shell A
-// keep F_A and the G_A accumulator in registers.  One kernel instantiation per
-// (l_A, l_B) class with l_A >= l_B, fully unrolled at compile time.
+// fixed summation order).  All lanes of a wave walk the same work list, so pair
+// and primitive data are wave-uniform and come through scalar loads (restrict
+// kernel arguments); F/G rows move as 512-byte coalesced vectors.  A run keeps
+// the F rows and G accumulators of a tile of A shells in registers while it
+// sweeps the B shells, so each F_B load and G_B update serves the whole tile.
+// One kernel instantiation per (l_A, l_B) class with l_A >= l_B, fully unrolled
+// at compile time.
 #include "snk_internal.h"
 
 #include <type_traits>
@@ -154,97 +156,144 @@ __device__ __forceinline__ void hrr(const double (&acc)[LA + LB + 1][16], const 
     });
 }
 
+// Contracted 3c-CP block A_ab(C) of one shell pair at the lane's point C:
+// Eq. vrr per primitive pair, contraction over primitives, then Eq. hrr.
 template <int LA, int LB>
-__global__ __launch_bounds__(256) void afg_kernel(AfgArgs a)
+__device__ __forceinline__ void pair_block(const PrimPair* __restrict__ pp0, int nprim, const double (&AB)[3],
+                                           double cx, double cy, double cz, const double* __restrict__ tab,
+                                           double (&Ab)[ncart(LA)][ncart(LB)])
 {
     constexpr int L = LA + LB;
+    double acc[L + 1][16];
+    sfor<LA, L + 1>([&](auto lc) {
+        sfor<0, ncart(CV(lc))>([&](auto cc) { acc[CV(lc)][CV(cc)] = 0.0; });
+    });
+    // software pipeline: the next primitive pair's record is requested before the
+    // current one is evaluated, so its scalar-load latency overlaps the arithmetic
+    PrimPair nxt = pp0[0];
+    for (int k = 0; k < nprim; ++k) {
+        const PrimPair pp = nxt;
+        if (k + 1 < nprim) nxt = pp0[k + 1];
+        const double PC[3] = {pp.Px - cx, pp.Py - cy, pp.Pz - cz};
+        const double PA[3] = {pp.PAx, pp.PAy, pp.PAz};
+        const double T = pp.zp * (PC[0] * PC[0] + PC[1] * PC[1] + PC[2] * PC[2]);
+        double Fm[L + 1];
+        boys<L>(T, tab, Fm);
+        double th[L + 1][L + 1][16];
+        sfor<0, L + 1>([&](auto nc) { th[CV(nc)][0][0] = pp.pref * Fm[CV(nc)]; });
+        vrr<L>(th, PA, PC, pp.oo2zp);
+        sfor<LA, L + 1>([&](auto lc) {
+            sfor<0, ncart(CV(lc))>([&](auto cc) { acc[CV(lc)][CV(cc)] += th[0][CV(lc)][CV(cc)]; });
+        });
+    }
+    hrr<LA, LB>(acc, AB, Ab);
+}
+
+template <int LA, int LB, int TA>
+__global__ __launch_bounds__(256) void afg_kernel(const double* __restrict__ px, const double* __restrict__ py,
+                                                  const double* __restrict__ pz, const double* __restrict__ pw,
+                                                  const double* __restrict__ F, double* __restrict__ G, int64_t ld,
+                                                  const PrimPair* __restrict__ prims,
+                                                  const int32_t* __restrict__ runs,
+                                                  const int32_t* __restrict__ btasks,
+                                                  const double* __restrict__ btask_ab,
+                                                  const int32_t* __restrict__ batch_run_off, int32_t nrun,
+                                                  const double* __restrict__ gtab)
+{
     constexpr int NA = ncart(LA), NB = ncart(LB);
+    constexpr int RS = 2 + TA;        // run record stride
+    constexpr int BS = 2 + 2 * TA;    // B-task record stride
     __shared__ double tab[kBoysRows * kBoysCols];
-    for (int i = threadIdx.x; i < kBoysRows * kBoysCols; i += blockDim.x) tab[i] = a.boys_tab[i];
+    for (int i = threadIdx.x; i < kBoysRows * kBoysCols; i += blockDim.x) tab[i] = gtab[i];
     __syncthreads();
 
     const int batch = blockIdx.x;
     const int64_t col = (int64_t)batch * kBatch + threadIdx.x;
-    const double cx = a.px[col], cy = a.py[col], cz = a.pz[col], w = a.pw[col];
-    const int64_t ld = a.ld;
-    const double* __restrict__ F = a.F;
-    double* __restrict__ G = a.G;
+    const double cx = px[col], cy = py[col], cz = pz[col], w = pw[col];
 
-    int t0 = 0, t1 = a.ntask;
-    if (a.batch_task_off) {
-        t0 = a.batch_task_off[batch];
-        t1 = a.batch_task_off[batch + 1];
+    int r0 = 0, r1 = nrun;
+    if (batch_run_off) {
+        r0 = batch_run_off[batch];
+        r1 = batch_run_off[batch + 1];
     }
-
-    int cur = -1;
-    double Fa[NA], Ga[NA];
-    sfor<0, NA>([&](auto ic) { Fa[CV(ic)] = 0.0; Ga[CV(ic)] = 0.0; });
-
-    for (int t = t0; t < t1; ++t) {
-        const PairTask task = a.tasks[t];
-        const PairHdr h = a.pairs[task.pair];
-        if (task.arow != cur) {
-            if (cur >= 0) {
-                sfor<0, NA>([&](auto ic) {
-                    constexpr int i = CV(ic);
-                    G[(int64_t)(cur + i) * ld + col] += (w * cnorm(LA, i)) * Ga[i];
-                });
-            }
-            cur = task.arow;
+    for (int r = r0; r < r1; ++r) {
+        const int32_t* run = runs + (int64_t)r * RS;
+        const int b0 = run[0], b1 = run[1];
+        int arow[TA];
+        double Fa[TA][NA], Ga[TA][NA];
+        sfor<0, TA>([&](auto kc) {
+            constexpr int k = CV(kc);
+            arow[k] = run[2 + k];
             sfor<0, NA>([&](auto ic) {
                 constexpr int i = CV(ic);
-                Fa[i] = cnorm(LA, i) * F[(int64_t)(cur + i) * ld + col];
-                Ga[i] = 0.0;
+                Fa[k][i] = arow[k] >= 0 ? cnorm(LA, i) * F[(int64_t)(arow[k] + i) * ld + col] : 0.0;
+                Ga[k][i] = 0.0;
             });
-        }
-        double Fb[NB];
-        sfor<0, NB>([&](auto jc) {
-            constexpr int j = CV(jc);
-            Fb[j] = cnorm(LB, j) * F[(int64_t)(task.brow + j) * ld + col];
         });
-
-        // contracted Theta^0_a for l_A <= |a| <= l_A + l_B
-        double acc[L + 1][16];
-        sfor<LA, L + 1>([&](auto lc) {
-            sfor<0, ncart(CV(lc))>([&](auto cc) { acc[CV(lc)][CV(cc)] = 0.0; });
-        });
-        for (int k = 0; k < h.nprim; ++k) {
-            const PrimPair pp = a.prims[h.prim_begin + k];
-            const double PC[3] = {pp.Px - cx, pp.Py - cy, pp.Pz - cz};
-            const double PA[3] = {pp.PAx, pp.PAy, pp.PAz};
-            const double T = pp.zp * (PC[0] * PC[0] + PC[1] * PC[1] + PC[2] * PC[2]);
-            double Fm[L + 1];
-            boys<L>(T, tab, Fm);
-            double th[L + 1][L + 1][16];
-            sfor<0, L + 1>([&](auto nc) { th[CV(nc)][0][0] = pp.pref * Fm[CV(nc)]; });
-            vrr<L>(th, PA, PC, pp.oo2zp);
-            sfor<LA, L + 1>([&](auto lc) {
-                sfor<0, ncart(CV(lc))>([&](auto cc) { acc[CV(lc)][CV(cc)] += th[0][CV(lc)][CV(cc)]; });
+        // the F_B / G_B rows of the next B task are fetched one task ahead
+        int nrow = 0;
+        double Fn[NB], Gn[NB];
+        auto fetch = [&](int bt) {
+            nrow = btasks[(int64_t)bt * BS];
+            sfor<0, NB>([&](auto jc) {
+                const int64_t o = (int64_t)(nrow + CV(jc)) * ld + col;
+                Fn[CV(jc)] = F[o];
+                Gn[CV(jc)] = G[o];
             });
-        }
-        const double AB[3] = {h.ABx, h.ABy, h.ABz};
-        double Ab[NA][NB];
-        hrr<LA, LB>(acc, AB, Ab);
-
-        sfor<0, NA>([&](auto ic) {
-            constexpr int i = CV(ic);
-            double s = Ga[i];
-            sfor<0, NB>([&](auto jc) { s = fma(Ab[i][CV(jc)], Fb[CV(jc)], s); });
-            Ga[i] = s;
-        });
-        if (task.arow != task.brow) {
+        };
+        if (b0 < b1) fetch(b0);
+        for (int bt = b0; bt < b1; ++bt) {
+            const int32_t* cur = btasks + (int64_t)bt * BS;
+            const int brow = nrow;
+            double Fb[NB], Gold[NB], Gb[NB];
             sfor<0, NB>([&](auto jc) {
                 constexpr int j = CV(jc);
-                double s = 0.0;
-                sfor<0, NA>([&](auto ic) { s = fma(Ab[CV(ic)][j], Fa[CV(ic)], s); });
-                G[(int64_t)(task.brow + j) * ld + col] += (w * cnorm(LB, j)) * s;
+                Fb[j] = cnorm(LB, j) * Fn[j];
+                Gold[j] = Gn[j];
+                Gb[j] = 0.0;
             });
+            if (bt + 1 < b1) fetch(bt + 1);
+            const int mask = cur[1];
+            bool transposed = false;
+            sfor<0, TA>([&](auto kc) {
+                constexpr int k = CV(kc);
+                if (mask & (1 << k)) {
+                    const double* ab = btask_ab + ((int64_t)bt * TA + k) * 3;
+                    const double AB[3] = {ab[0], ab[1], ab[2]};
+                    double Ab[NA][NB];
+                    pair_block<LA, LB>(prims + cur[2 + 2 * k], cur[3 + 2 * k], AB, cx, cy, cz, tab, Ab);
+                    sfor<0, NA>([&](auto ic) {
+                        constexpr int i = CV(ic);
+                        double acc = Ga[k][i];
+                        sfor<0, NB>([&](auto jc) { acc = fma(Ab[i][CV(jc)], Fb[CV(jc)], acc); });
+                        Ga[k][i] = acc;
+                    });
+                    if (arow[k] != brow) {   // A != B: the transposed block feeds G_B
+                        transposed = true;
+                        sfor<0, NB>([&](auto jc) {
+                            constexpr int j = CV(jc);
+                            double acc = Gb[j];
+                            sfor<0, NA>([&](auto ic) { acc = fma(Ab[CV(ic)][j], Fa[k][CV(ic)], acc); });
+                            Gb[j] = acc;
+                        });
+                    }
+                }
+            });
+            if (transposed) {
+                sfor<0, NB>([&](auto jc) {
+                    constexpr int j = CV(jc);
+                    G[(int64_t)(brow + j) * ld + col] = fma(w * cnorm(LB, j), Gb[j], Gold[j]);
+                });
+            }
         }
-    }
-    if (cur >= 0) {
-        sfor<0, NA>([&](auto ic) {
-            constexpr int i = CV(ic);
-            G[(int64_t)(cur + i) * ld + col] += (w * cnorm(LA, i)) * Ga[i];
+        sfor<0, TA>([&](auto kc) {
+            constexpr int k = CV(kc);
+            if (arow[k] >= 0) {
+                sfor<0, NA>([&](auto ic) {
+                    constexpr int i = CV(ic);
+                    G[(int64_t)(arow[k] + i) * ld + col] += (w * cnorm(LA, i)) * Ga[k][i];
+                });
+            }
         });
     }
 }
@@ -269,15 +318,19 @@ hipError_t launch_afg(int la, int lb, const AfgArgs& a, hipStream_t s)
 {
     if (a.nbatch <= 0) return hipSuccess;
     dim3 grid(a.nbatch), block(kBatch);
+#define SNK_AFG(LA, LB, TA)                                                                                    \
+    hipLaunchKernelGGL((afg_kernel<LA, LB, TA>), grid, block, 0, s, a.px, a.py, a.pz, a.pw, a.F, a.G, a.ld, \
+                       a.prims, a.runs, a.btasks, a.btask_ab, a.batch_run_off, a.nrun, a.boys_tab)
     switch (la * 3 + lb) {
-        case 0: hipLaunchKernelGGL((afg_kernel<0, 0>), grid, block, 0, s, a); break;
-        case 3: hipLaunchKernelGGL((afg_kernel<1, 0>), grid, block, 0, s, a); break;
-        case 4: hipLaunchKernelGGL((afg_kernel<1, 1>), grid, block, 0, s, a); break;
-        case 6: hipLaunchKernelGGL((afg_kernel<2, 0>), grid, block, 0, s, a); break;
-        case 7: hipLaunchKernelGGL((afg_kernel<2, 1>), grid, block, 0, s, a); break;
-        case 8: hipLaunchKernelGGL((afg_kernel<2, 2>), grid, block, 0, s, a); break;
+        case 0: SNK_AFG(0, 0, kTileA[0]); break;
+        case 3: SNK_AFG(1, 0, kTileA[1]); break;
+        case 4: SNK_AFG(1, 1, kTileA[2]); break;
+        case 6: SNK_AFG(2, 0, kTileA[3]); break;
+        case 7: SNK_AFG(2, 1, kTileA[4]); break;
+        case 8: SNK_AFG(2, 2, kTileA[5]); break;
         default: return hipErrorInvalidValue;
     }
+#undef SNK_AFG
     return hipGetLastError();
 }
 

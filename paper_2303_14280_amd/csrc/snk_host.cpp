@@ -59,9 +59,12 @@ struct snk_ctx {
     std::vector<int32_t> pair_a, pair_b;  // A and B shell of each pair
     PairHdr* d_pairs = nullptr;
     PrimPair* d_prims = nullptr;
-    PairTask* d_tasks[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-    int32_t ntask[6] = {0, 0, 0, 0, 0, 0};
-    int64_t task_prims[6] = {0, 0, 0, 0, 0, 0};   // surviving primitive pairs summed over a class's tasks
+    int32_t* d_runs[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    int32_t* d_btasks[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    double* d_btask_ab[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    int32_t nrun[6] = {0, 0, 0, 0, 0, 0};
+    int64_t ntask[6] = {0, 0, 0, 0, 0, 0};        // shell pairs of a class evaluated at every batch
+    int64_t task_prims[6] = {0, 0, 0, 0, 0, 0};   // surviving primitive pairs summed over those pairs
     int64_t n_prim_pairs_total = 0, n_prim_pairs_kept = 0;
 
     // grid
@@ -412,23 +415,66 @@ int build_groups(snk_ctx* c)
     return SNK_OK;
 }
 
-int build_tasks(snk_ctx* c)
+int64_t pair_index(int s, int t)   // unique pair of shells s, t (stored for s >= t)
 {
-    std::vector<std::vector<PairTask>> per(6);
-    for (size_t p = 0; p < c->pairs.size(); ++p) {
-        if (c->pairs[p].nprim == 0) continue;   // every primitive pair negligible
-        const int A = c->pair_a[p], B = c->pair_b[p];
-        const int cl = class_of(c->sl[A], c->sl[B]);
-        per[cl].push_back(PairTask{(int32_t)p, c->sfn[A], c->sfn[B], 0});
-        c->task_prims[cl] += c->pairs[p].nprim;
-    }
+    if (s < t) std::swap(s, t);
+    return (int64_t)s * (s + 1) / 2 + t;
+}
+
+// Runs and B tasks of every class for the unscreened build: tiles of kTileA[class]
+// consecutive A shells, each sweeping all B shells (B <= A in shell order when l_A = l_B).
+int build_runs(snk_ctx* c)
+{
     for (int cl = 0; cl < 6; ++cl) {
-        std::stable_sort(per[cl].begin(), per[cl].end(), [](const PairTask& x, const PairTask& y) {
-            return x.arow < y.arow || (x.arow == y.arow && x.brow < y.brow);
-        });
-        c->ntask[cl] = (int32_t)per[cl].size();
-        int rc = upload(c, &c->d_tasks[cl], per[cl]);
+        const int LA = kClassLA[cl], LB = kClassLB[cl], TA = kTileA[cl], RS = 2 + TA, BS = 2 + 2 * TA;
+        std::vector<int> SA, SB;
+        for (int sh = 0; sh < c->nshell; ++sh) {
+            if (c->sl[sh] == LA) SA.push_back(sh);
+            if (c->sl[sh] == LB) SB.push_back(sh);
+        }
+        std::vector<int32_t> runs, bt;
+        std::vector<double> bab;
+        int64_t ntask = 0, nprim = 0;
+        for (size_t t0 = 0; t0 < SA.size(); t0 += TA) {
+            std::vector<int32_t> rec(RS, -1);
+            rec[0] = (int32_t)(bt.size() / BS);
+            for (int k = 0; k < TA; ++k)
+                if (t0 + k < SA.size()) rec[2 + k] = c->sfn[SA[t0 + k]];
+            for (int b : SB) {
+                std::vector<int32_t> brec(BS, 0);
+                std::vector<double> ab(3 * TA, 0.0);
+                brec[0] = c->sfn[b];
+                int mask = 0;
+                for (int k = 0; k < TA && t0 + k < SA.size(); ++k) {
+                    const int a = SA[t0 + k];
+                    if (LA == LB && a < b) continue;
+                    const int64_t p = pair_index(a, b);
+                    const PairHdr& h = c->pairs[p];
+                    if (h.nprim == 0) continue;   // every primitive pair negligible
+                    mask |= 1 << k;
+                    brec[2 + 2 * k] = h.prim_begin;
+                    brec[3 + 2 * k] = h.nprim;
+                    ab[3 * k] = h.ABx;
+                    ab[3 * k + 1] = h.ABy;
+                    ab[3 * k + 2] = h.ABz;
+                    ntask += 1;
+                    nprim += h.nprim;
+                }
+                if (!mask) continue;
+                brec[1] = mask;
+                bt.insert(bt.end(), brec.begin(), brec.end());
+                bab.insert(bab.end(), ab.begin(), ab.end());
+            }
+            rec[1] = (int32_t)(bt.size() / BS);
+            if (rec[1] > rec[0]) runs.insert(runs.end(), rec.begin(), rec.end());
+        }
+        c->nrun[cl] = (int32_t)(runs.size() / RS);
+        c->ntask[cl] = ntask;
+        c->task_prims[cl] = nprim;
+        int rc = upload(c, &c->d_runs[cl], runs);
         if (rc) return rc;
+        if ((rc = upload(c, &c->d_btasks[cl], bt))) return rc;
+        if ((rc = upload(c, &c->d_btask_ab[cl], bab))) return rc;
     }
     return SNK_OK;
 }
@@ -441,7 +487,11 @@ void free_ctx(snk_ctx* c)
     (void)hipFree(c->d_coefs);
     (void)hipFree(c->d_pairs);
     (void)hipFree(c->d_prims);
-    for (int k = 0; k < 6; ++k) (void)hipFree(c->d_tasks[k]);
+    for (int k = 0; k < 6; ++k) {
+        (void)hipFree(c->d_runs[k]);
+        (void)hipFree(c->d_btasks[k]);
+        (void)hipFree(c->d_btask_ab[k]);
+    }
     (void)hipFree(c->d_px);
     (void)hipFree(c->d_py);
     (void)hipFree(c->d_pz);
@@ -600,7 +650,7 @@ int snk_ctx_create(const snk_basis* basis, const snk_grid* grid, const double* w
     build_pairs(c);
     CREATE_CHECK(upload(c, &c->d_pairs, c->pairs));
     CREATE_CHECK(upload(c, &c->d_prims, c->prims));
-    CREATE_CHECK(build_tasks(c));
+    CREATE_CHECK(build_runs(c));
     CREATE_CHECK(build_grid(c, grid, weights));
     CREATE_CHECK(build_groups(c));
     CREATE_CHECK(upload(c, &c->d_boys, boys_table()));
@@ -673,13 +723,15 @@ int group_until_G(snk_ctx* c, const Group& g, const double* dP, bool timed)
     a.ld = ld;
     a.pairs = c->d_pairs;
     a.prims = c->d_prims;
-    a.batch_task_off = nullptr;
+    a.batch_run_off = nullptr;
     a.nbatch = g.b1 - g.b0;
     a.boys_tab = c->d_boys;
     for (int cl = 0; cl < 6; ++cl) {
-        if (c->ntask[cl] == 0) continue;
-        a.tasks = c->d_tasks[cl];
-        a.ntask = c->ntask[cl];
+        if (c->nrun[cl] == 0) continue;
+        a.runs = c->d_runs[cl];
+        a.btasks = c->d_btasks[cl];
+        a.btask_ab = c->d_btask_ab[cl];
+        a.nrun = c->nrun[cl];
         if (timed) HIPCHECK(c, hipEventRecord(c->ev[8 + cl], s));
         HIPCHECK(c, launch_afg(kClassLA[cl], kClassLB[cl], a, s));
         if (timed) HIPCHECK(c, hipEventRecord(c->ev[cl == 5 ? 15 : 9 + cl], s));
@@ -738,7 +790,7 @@ int snk_ctx_build(snk_ctx* c, const double* P, double* K_out, snk_stats* stats)
         int64_t gpts = 0;
         for (int b = g.b0; b < g.b1; ++b) gpts += c->batch_npts[b];
         for (int cl = 0; cl < 6; ++cl) {
-            pp[cl] += (int64_t)c->ntask[cl] * gpts;
+            pp[cl] += c->ntask[cl] * gpts;
             ppp[cl] += c->task_prims[cl] * gpts;
         }
         // Eq. usym_k: Kt[:, B_g] += G_g Phi_g^T, split over grid points
@@ -754,7 +806,7 @@ int snk_ctx_build(snk_ctx* c, const double* P, double* K_out, snk_stats* stats)
             tf += ev_ms(c->ev[1], c->ev[2]);
             tafg += ev_ms(c->ev[2], c->ev[3]);
             for (int cl = 0; cl < 6; ++cl) {
-                if (c->ntask[cl] == 0) continue;
+                if (c->nrun[cl] == 0) continue;
                 tcls[cl] += ev_ms(c->ev[8 + cl], c->ev[cl == 5 ? 15 : 9 + cl]);
             }
             tk += ev_ms(c->ev[3], c->ev[4]);

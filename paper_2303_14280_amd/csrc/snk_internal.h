@@ -28,28 +28,33 @@ struct PairHdr {
     double pad;
 };
 
-// Centre-independent data of one primitive pair (Obara-Saika, App. A).
+// Centre-independent data of one primitive pair (Obara-Saika, App. A).  The fields an
+// s-s pair needs come first so that one 64-byte scalar load covers them.
 struct PrimPair {
-    double zp;           // zeta_a + zeta_b
-    double oo2zp;        // 1 / (2 zeta_p)
     double Px, Py, Pz;   // R_p
-    double PAx, PAy, PAz;// R_p - R_A
+    double zp;           // zeta_a + zeta_b
     double pref;         // (2 pi / zeta_p) exp(-zeta_a zeta_b |AB|^2 / zeta_p) c_a c_b
+    double PAx, PAy, PAz;// R_p - R_A
+    double oo2zp;        // 1 / (2 zeta_p)
     double pad;
-};
-
-// A unit of A.F work: one shell pair, with the rows of its two shells in F/G.
-struct PairTask {
-    int32_t pair;
-    int32_t arow;        // row of the first function of shell A in the group's F and G
-    int32_t brow;
-    int32_t pad;
 };
 
 struct ShellDev {
     double x, y, z;
     int32_t l, nprim, prim_off, pad;
 };
+
+// A.F work of one (l_A, l_B) class is organised in runs.  A run fixes a tile of up
+// to kTileA[class] A shells whose F rows and G accumulators stay in registers; it
+// lists B tasks, each a B shell with the pairs (a_k, B) of the tile to evaluate.
+// Runs and B tasks are int32 records, with the pair geometry beside them:
+//   run:   [b_begin, b_end, arow_0 .. arow_{TA-1}]                 (arow = -1: empty slot)
+//   btask: [brow, mask, prim_begin_0, nprim_0, .., prim_begin_{TA-1}, nprim_{TA-1}]
+//          (bit k of mask: pair (a_k, B) present; its primitive pairs are
+//           prims[prim_begin_k .. prim_begin_k + nprim_k))
+//   btask_ab: [btask][k][3] doubles, R_A - R_B of pair k
+constexpr int kMaxTile = 8;
+constexpr int kTileA[6] = {4, 2, 2, 1, 1, 1};   // ss, ps, pp, ds, dp, dd
 
 struct AfgArgs {
     const double* px;
@@ -61,9 +66,11 @@ struct AfgArgs {
     int64_t ld;
     const PairHdr* pairs;
     const PrimPair* prims;
-    const PairTask* tasks;  // tasks of one class
-    const int32_t* batch_task_off;  // [nbatch+1] per-batch task ranges, or nullptr: all tasks for all batches
-    int32_t ntask;
+    const int32_t* runs;            // run records of one class
+    const int32_t* btasks;          // B-task records of that class
+    const double* btask_ab;         // R_A - R_B per B task and tile slot
+    const int32_t* batch_run_off;   // [nbatch+1] per-batch run ranges, or nullptr: all runs for all batches
+    int32_t nrun;
     int32_t nbatch;
     const double* boys_tab;
 };

@@ -386,16 +386,17 @@ def overlap_matrix(sys: System, shells: Optional[np.ndarray] = None) -> np.ndarr
 
 
 def _orthonormal_orbitals(S: np.ndarray, n_occ: int, rng: np.random.Generator) -> np.ndarray:
-    """C with C^T S C = I: canonical orthogonalisation X = U s^{-1/2} (s > 1e-8), C = X Q,
-    Q from the QR factorisation of a seeded Gaussian matrix."""
-    s, U = np.linalg.eigh(S)
-    keep = s > 1e-8
-    X = U[:, keep] / np.sqrt(s[keep])
-    m = X.shape[1]
-    if n_occ > m:
-        raise ValueError("not enough linearly independent functions")
-    Q, _ = np.linalg.qr(rng.normal(size=(m, n_occ)))
-    return X @ Q
+    """C with C^T S C = I: seeded Gaussian coefficients C0, then C = C0 L^{-T} with
+    L L^T = C0^T S C0 (Cholesky of a small, well-conditioned matrix).  Unlike an
+    eigendecomposition of S, this is a smooth function of the inputs, so the same
+    seed gives the same density on every machine to rounding."""
+    nb = S.shape[0]
+    if n_occ > nb:
+        raise ValueError("more occupied orbitals than basis functions")
+    C0 = rng.normal(size=(nb, n_occ))
+    M = C0.T @ S @ C0
+    L = np.linalg.cholesky(0.5 * (M + M.T))
+    return np.linalg.solve(L, C0.T).T
 
 
 def make_density(sys_wo_P: System, n_occ: int, kind: str, seed: Sequence[int]) -> np.ndarray:
@@ -404,7 +405,8 @@ def make_density(sys_wo_P: System, n_occ: int, kind: str, seed: Sequence[int]) -
     if kind == "delocalised":
         S = overlap_matrix(sys_wo_P)
         C = _orthonormal_orbitals(S, n_occ, rng)
-        return 2.0 * C @ C.T
+        Q = C @ C.T
+        return Q + Q.T          # 2 C C^T, exactly symmetric
     if kind != "local":
         raise ValueError(kind)
     # molecule-local: ceil(electrons/2) orbitals per molecule on its own functions
@@ -420,7 +422,8 @@ def make_density(sys_wo_P: System, n_occ: int, kind: str, seed: Sequence[int]) -
         k = (n_el + 1) // 2
         S = overlap_matrix(sys_wo_P, shells)
         C = _orthonormal_orbitals(S, k, rng)
-        P[np.ix_(idx, idx)] += 2.0 * C @ C.T
+        Q = C @ C.T
+        P[np.ix_(idx, idx)] += Q + Q.T
         total += k
     if total != n_occ:
         raise AssertionError((total, n_occ))

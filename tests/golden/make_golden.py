@@ -29,7 +29,8 @@ def main(cfg: int, nthreads: int = 0):
     t = time.time()
     K, ex_tr, ex_fg = O.snk(s, nthreads=nthreads)
     dt = time.time() - t
-    out = dict(K=K, ex=np.array([ex_tr, ex_fg]), fingerprint=fingerprint(s), seconds=np.array([dt]))
+    # the density is stored with the result: tests use it rather than regenerating it
+    out = dict(K=K, ex=np.array([ex_tr, ex_fg]), P=s.P, fingerprint=fingerprint(s), seconds=np.array([dt]))
     if cfg == 1:
         out["K_exact"] = O.eri_k(s, nthreads=nthreads)
     np.savez_compressed(os.path.join(HERE, "oracle_config%d.npz" % cfg), **out)
