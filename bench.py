@@ -71,6 +71,61 @@ def measured_traffic(kernel: str):
     return None, None
 
 
+def time_builds(ctx, P, K, stream, steps, warmup):
+    import torch
+    for i in range(warmup):
+        ctx.build_device(P.data_ptr(), K.data_ptr())
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for i in range(steps):
+        ctx.build_device(P.data_ptr(), K.data_ptr())
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return max(e0.elapsed_time(e1) / steps, 1000.0 * (time.perf_counter() - t0) / steps)
+
+
+def mixed_learned(s, P, K64, stream, args, ms64, ex64, ints):
+    """The mixed-precision + learned-screen build of the same workload, timed the same way,
+    with its errors against the FP64 build (max|dK|, dE_x) and its screen statistics."""
+    import numpy as np
+    import torch
+    from paper_2303_14280_amd import snk
+    res = {}
+    if not os.path.exists(snk.SCREENER_WEIGHTS):
+        return {"error": "no trained screener weights"}
+    mlp = snk.load_screener(device=0)
+    K = torch.empty_like(P)
+    variants = [("mixed+learned", dict(precision=snk.SNK_MIXED, screen=snk.SNK_SCREEN_LEARNED)),
+                ("fp64+learned", dict(precision=snk.SNK_FP64, screen=snk.SNK_SCREEN_LEARNED)),
+                ("mixed", dict(precision=snk.SNK_MIXED, screen=snk.SNK_SCREEN_NONE)),
+                ("fp64+bound", dict(precision=snk.SNK_FP64, screen=snk.SNK_SCREEN_BOUND))]
+    for name, kw in variants:
+        ctx = snk.Context(s, flags=snk.SNK_DEVICE_PTRS, stream=stream.cuda_stream, device=0, screener=mlp,
+                          eps_skip_energy=args.eps, **kw)
+        steps = args.steps if name == "mixed+learned" else max(2, args.steps // 2)
+        ms = time_builds(ctx, P, K, stream, steps, args.warmup)
+        st = ctx.build_device(P.data_ptr(), K.data_ptr(), stats=True)
+        torch.cuda.synchronize()
+        dK = float((K - K64).abs().max().item())
+        evaluated = float(sum(st["pair_points"]))
+        r = {"ms_per_step": ms, "speedup_vs_fp64": ms64 / ms, "dE_x_vs_fp64": st["ex"] - ex64,
+             "max_dK_vs_fp64": dK, "skipped_pair_points_fraction": st["pair_points_skipped"] / max(1.0, ints),
+             "skipped_energy_estimate": st["skipped_bound"], "shell_pair_points_evaluated": evaluated,
+             "effective_rate": ints / (ms * 1e-3),
+             "phases_ms": {"collocate": st["t_collocate_ms"], "fgemm": st["t_fgemm_ms"],
+                           "screen": st["t_screen_ms"], "afg": st["t_afg_ms"], "kgemm": st["t_kgemm_ms"],
+                           "finish": st["t_finish_ms"]}}
+        log("%s: %.3f ms/step (x%.2f vs FP64), dE_x %.2e, max|dK| %.2e, skipped %.3f" %
+            (name, ms, ms64 / ms, r["dE_x_vs_fp64"], dK, r["skipped_pair_points_fraction"]))
+        res[name] = r
+        ctx.close()
+    res["eps_skip_energy"] = args.eps
+    res["target"] = "|dE_x| <= 1e-6 Eh at >= 3x the FP64 build"
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -78,6 +133,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision + learned-screen comparison")
+    ap.add_argument("--eps", type=float, default=5e-7, help="skip budget of the learned screen (Eh)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -183,6 +240,8 @@ def main():
         "afg_tflops_all_classes": afg_total,
         "ex": st["ex"],
     }
+    if not args.no_mixed:
+        out["mixed_learned"] = mixed_learned(s, P, K, stream, args, ms, st["ex"], ints)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(s)

@@ -167,6 +167,62 @@ int snk_version(void);
 int snk_boys_device(const double* T, int64_t n, int mmax, double* F_out, void* stream);
 
 /*
+ * Learned block screener (the AI form beside the plain method; no counterpart in the paper,
+ * which screens with the sn-LinK estimates of Sec. II.E).  A small network,
+ * 16 features -> 64 -> 64 -> 1 (SiLU), predicts log10 of the absolute energy of a
+ * (shell pair, grid batch) block, sum_i w_i sum |F_a,i| |A_ab(r_i)| |F_b,i|.  With
+ * SNK_SCREEN_LEARNED a block is skipped when the prediction plus the stored margin puts it
+ * in the batch's skip budget and its features lie inside the stored training range; the
+ * rigorous bound of SNK_SCREEN_BOUND still applies.  Parameters are FP32 device memory,
+ * flattened W1[64][16], b1[64], W2[64][64], b2[64], W3[64], b3 (snk_mlp_nparams() values).
+ * Features are standardised with the stored mean and std inside the kernels.
+ *
+ * snk_mlp_create / destroy: allocate / free a network on `device` (parameters zero).
+ * snk_mlp_set_params / get_params: copy the parameters from / to host memory.
+ * snk_mlp_set_normalisation: feature mean and std (host, 16 each, std > 0).
+ * snk_mlp_set_range: training range of the raw features (host, 16 each) and the margin
+ *   (log10 units) added to predictions by the screen.
+ * snk_mlp_forward: y[n] = network(x[n][16]); device pointers; bf16 != 0 rounds weights,
+ *   inputs and activations to bfloat16 and accumulates in FP32 (inference form).
+ * snk_mlp_loss_grad: loss (1/n) sum_s c_s (y_s - t_s)^2, c_s = `under` if y_s < t_s else 1,
+ *   and its gradient; grads is a device buffer of nparams + 1 floats (gradient, then loss).
+ * snk_mlp_adam_step: one Adam update (beta 0.9 / 0.999, eps 1e-8) at step t >= 1.
+ */
+int snk_mlp_nparams(void);
+int snk_mlp_create(int device, snk_mlp** out);
+void snk_mlp_destroy(snk_mlp* mlp);
+int snk_mlp_set_params(snk_mlp* mlp, const float* params);
+int snk_mlp_get_params(const snk_mlp* mlp, float* params);
+int snk_mlp_set_normalisation(snk_mlp* mlp, const float* mean, const float* std);
+int snk_mlp_set_range(snk_mlp* mlp, const float* lo, const float* hi, float margin);
+int snk_mlp_forward(const snk_mlp* mlp, const float* x, int64_t n, float* y, int bf16, void* stream);
+int snk_mlp_loss_grad(snk_mlp* mlp, const float* x, const float* target, int64_t n, float under, float* grads,
+                      void* stream);
+int snk_mlp_adam_step(snk_mlp* mlp, const float* grads, float lr, int t, void* stream);
+
+/*
+ * Training data for the learned screener, generated by the method itself for one density.
+ * Blocks are the shell pairs that keep at least one primitive pair (snk_ctx_nblock_pairs of
+ * them, ordered by class ss, ps, pp, ds, dp, dd, then by pair) on every grid batch.
+ *
+ * snk_ctx_block_data: for block (batch b, pair k), features[(b * npairs + k) * 16 + f]
+ *   (device memory, FP32) are the 16 network inputs, and block_energy[b * npairs + k]
+ *   (device memory, FP64) is the exact block magnitude
+ *     t = c_AB sum_i w_i | sum_{a in A, b in B} F_a,i A_ab(r_i) F_b,i |
+ *   from Eqs. fmat and 3c_grid (c_AB = 1 for A != B, 1/2 for A == B), an upper bound on the
+ *   change of E_x when the block is skipped.  pair_shells (host, npairs x 2 int32) receives
+ *   the shells (A, B) of each pair.  Any output may be NULL.  P follows the context's
+ *   SNK_DEVICE_PTRS flag.  Feature order: l_A, l_B, log10 of the smallest exponent of A and
+ *   of B, |AB|, log10 of the summed primitive-pair prefactors, log10 ||P_AB||, distance of
+ *   the diffuse pair centre to the batch's bounding box, the box's half diagonal, distances
+ *   of A and of B to the box, log10 of the batch weight sum, log10 of the F norms of A and B
+ *   on the batch, log10 of the rigorous block bound, distance of the pair centre to the
+ *   batch centroid.
+ */
+int64_t snk_ctx_nblock_pairs(const snk_ctx* ctx);
+int snk_ctx_block_data(snk_ctx* ctx, const double* P, float* features, double* block_energy, int32_t* pair_shells);
+
+/*
  * Test hooks (diagnostics; not needed for building K).
  *
  * snk_debug_gemm_f64: C = A op(B) with the library's FP64 matrix-core GEMM on device
@@ -180,6 +236,15 @@ int snk_boys_device(const double* T, int64_t n, int mmax, double* F_out, void* s
  *   Phi (Eq. collocation), F (Eq. fmat) and G (Eq. gmat), each nbf x ncols row-major in
  *   host memory (ncols = 256 * batches of that group, returned in *ncols_out); P is a host
  *   pointer.  Pass NULL for any output not wanted.
+ * snk_ctx_npair_index: size of the pair index space, nshell (nshell + 1) / 2 (pair of
+ *   shells s >= t at s (s + 1) / 2 + t).
+ * snk_ctx_debug_learned: runs the learned screen of the first batch group (context made
+ *   with SNK_SCREEN_LEARNED; P a host pointer) and copies to host memory, per batch b of
+ *   that group and pair index p, the raw network output yraw[b * npair_index + p] and the
+ *   block estimate log2 est[...] (NaN for blocks the bound already skipped), and the
+ *   first kept estimate bin thr[b].  *nbatch_out = batches of the group.
+ * snk_debug_mfma_bf16: D = A B for 16 x 16 row-major host matrices through one bf16
+ *   matrix-core op (A and B rounded to bf16; layout check).
  */
 int snk_debug_gemm_f64(int64_t M, int64_t N, int64_t K, const double* A, int64_t lda, const double* B,
                        int64_t ldb, int bt, double* C, int64_t ldc, void* stream);
@@ -187,6 +252,10 @@ int snk_debug_mfma_layout(double* out);
 int snk_ctx_point_order(const snk_ctx* ctx, int64_t* col_to_point);
 int snk_ctx_debug_intermediates(snk_ctx* ctx, const double* P, double* Phi, double* F, double* G,
                                 int64_t* ncols_out);
+int64_t snk_ctx_npair_index(const snk_ctx* ctx);
+int snk_ctx_debug_learned(snk_ctx* ctx, const double* P, float* yraw, float* est, int32_t* thr,
+                          int64_t* nbatch_out);
+int snk_debug_mfma_bf16(const float* A, const float* B, float* D);
 
 #ifdef __cplusplus
 }

@@ -17,7 +17,7 @@ INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(PKG, "libsnk.so")
 BUILD_DIR = os.path.join(PKG, "_build")
 
-SOURCES = ["snk_host.cpp", "k_afg.hip", "k_collocate.hip", "k_linalg.hip"]
+SOURCES = ["snk_host.cpp", "snk_mlp.cpp", "k_afg.hip", "k_collocate.hip", "k_linalg.hip", "k_screen.hip", "k_mlp.hip", "k_learn.hip"]
 
 ARCH = os.environ.get("SNK_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

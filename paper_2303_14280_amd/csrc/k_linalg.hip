@@ -6,24 +6,34 @@
 //  - fill and gather helpers.
 #include "snk_internal.h"
 
+#include <type_traits>
+
 namespace snk {
 namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 constexpr int TM = 64, TN = 64, TK = 16;
+constexpr int kFlush = 1024;   // FP32 mode: k per FP32 accumulation before the FP64 add
 
 // 256 threads = 4 wave64; wave w owns the 32x32 quadrant (w/2, w%2) of the 64x64 tile as
-// 2x2 MFMA 16x16 blocks.  Operand layout of v_mfma_f64_16x16x4f64 (wave64):
-//   A[i][k] in lane i + 16k, B[k][j] in lane j + 16k, D[i][j] in lane j + 16(i%4), element i/4
-//   (the accumulator layout was measured with the probe kernel below).
-__global__ __launch_bounds__(256) void gemm_f64_kernel(int64_t M, int64_t N, int64_t K, const double* __restrict__ A,
-                                                       int64_t lda, const double* __restrict__ B, int64_t ldb, int bt,
-                                                       double* __restrict__ C, int64_t ldc, int64_t kchunk,
-                                                       int64_t split_stride)
+// 2x2 matrix-core 16x16 blocks.  F32 = false: v_mfma_f64_16x16x4f64, operands and
+// accumulators FP64; F32 = true: v_mfma_f32_16x16x4f32, operands rounded to FP32 as they are
+// staged (whatever the storage type) and FP32 accumulation.  Operand layout (wave64):
+//   A[i][k] in lane i + 16k, B[k][j] in lane j + 16k;
+//   FP64 accumulator D[i][j] in lane j + 16(i%4), element i/4;
+//   FP32 accumulator D[i][j] in lane j + 16(i/4), element i%4
+// (both accumulator layouts are checked by GEMM tests against host products).
+template <typename TA, typename TB, typename TC, bool F32>
+__global__ __launch_bounds__(256) void gemm_kernel(int64_t M, int64_t N, int64_t K, const TA* __restrict__ A,
+                                                   int64_t lda, const TB* __restrict__ B, int64_t ldb, int bt,
+                                                   TC* __restrict__ C, int64_t ldc, int64_t kchunk,
+                                                   int64_t split_stride)
 {
-    __shared__ double As[TK][TM + 1];
-    __shared__ double Bs[TK][TN + 1];
+    typedef typename std::conditional<F32, float, double>::type TS;
+    typedef TS acc4 __attribute__((ext_vector_type(4)));
+    __shared__ TS As[TK][TM + 1];
+    __shared__ TS Bs[TK][TN + 1];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t m0 = (int64_t)blockIdx.y * TM, n0 = (int64_t)blockIdx.x * TN;
     const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
@@ -32,18 +42,39 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(int64_t M, int64_t N, int
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
     const int li = lane & 15, lk = lane >> 4;
 
-    d4 acc[2][2];
+    acc4 acc[2][2];
     for (int bi = 0; bi < 2; ++bi)
-        for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = d4{0.0, 0.0, 0.0, 0.0};
+        for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = acc4{0, 0, 0, 0};
+    // FP32 mode: the matrix-core accumulators cover at most kFlush consecutive k; they are
+    // then added into FP64 accumulators (FP32 sums stay short, long sums are FP64)
+    double dacc[2][2][4];
+    if constexpr (F32)
+        for (int bi = 0; bi < 2; ++bi)
+            for (int bj = 0; bj < 2; ++bj)
+                for (int r = 0; r < 4; ++r) dacc[bi][bj][r] = 0.0;
+    auto flush = [&]() {
+        if constexpr (F32)
+            for (int bi = 0; bi < 2; ++bi)
+                for (int bj = 0; bj < 2; ++bj) {
+                    for (int r = 0; r < 4; ++r) dacc[bi][bj][r] += (double)acc[bi][bj][r];
+                    acc[bi][bj] = acc4{0, 0, 0, 0};
+                }
+    };
 
     const int ai = tid >> 2, ak = (tid & 3) * 4;
+    int since_flush = 0;
     for (int64_t k0 = kbeg; k0 < kend; k0 += TK) {
+        if (F32 && since_flush == kFlush / TK) {
+            flush();
+            since_flush = 0;
+        }
+        ++since_flush;
         {
             const int64_t gm = m0 + ai;
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int64_t gk = k0 + ak + u;
-                As[ak + u][ai] = (gm < M && gk < kend) ? A[gm * lda + gk] : 0.0;
+                As[ak + u][ai] = (gm < M && gk < kend) ? (TS)A[gm * lda + gk] : (TS)0;
             }
         }
         if (!bt) {
@@ -52,7 +83,7 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(int64_t M, int64_t N, int
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int64_t gn = n0 + bj + u;
-                Bs[bk][bj + u] = (gk < kend && gn < N) ? B[gk * ldb + gn] : 0.0;
+                Bs[bk][bj + u] = (gk < kend && gn < N) ? (TS)B[gk * ldb + gn] : (TS)0;
             }
         } else {
             const int bj = tid >> 2, bk = (tid & 3) * 4;
@@ -60,13 +91,13 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(int64_t M, int64_t N, int
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int64_t gk = k0 + bk + u;
-                Bs[bk + u][bj] = (gn < N && gk < kend) ? B[gn * ldb + gk] : 0.0;
+                Bs[bk + u][bj] = (gn < N && gk < kend) ? (TS)B[gn * ldb + gk] : (TS)0;
             }
         }
         __syncthreads();
 #pragma unroll
         for (int ks = 0; ks < TK; ks += 4) {
-            double a[2], b[2];
+            TS a[2], b[2];
 #pragma unroll
             for (int bi = 0; bi < 2; ++bi) a[bi] = As[ks + lk][wm + bi * 16 + li];
 #pragma unroll
@@ -74,24 +105,34 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(int64_t M, int64_t N, int
 #pragma unroll
             for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-                for (int bj = 0; bj < 2; ++bj)
-                    acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi], b[bj], acc[bi][bj], 0, 0, 0);
+                for (int bj = 0; bj < 2; ++bj) {
+                    if constexpr (F32)
+                        acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[bi], b[bj], acc[bi][bj], 0, 0, 0);
+                    else
+                        acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi], b[bj], acc[bi][bj], 0, 0, 0);
+                }
         }
         __syncthreads();
     }
+    flush();
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int64_t gm = m0 + wm + bi * 16 + 4 * r + lk;
+                const int64_t gm = m0 + wm + bi * 16 + (F32 ? 4 * lk + r : 4 * r + lk);
                 const int64_t gn = n0 + wn + bj * 16 + li;
-                if (gm < M && gn < N) C[gm * ldc + gn] = acc[bi][bj][r];
+                if constexpr (F32) {
+                    if (gm < M && gn < N) C[gm * ldc + gn] = (TC)dacc[bi][bj][r];
+                } else {
+                    if (gm < M && gn < N) C[gm * ldc + gn] = (TC)acc[bi][bj][r];
+                }
             }
 }
 
-__global__ __launch_bounds__(256) void reduce_scatter_kernel(const double* __restrict__ part, int nsplit,
+template <typename TP>
+__global__ __launch_bounds__(256) void reduce_scatter_kernel(const TP* __restrict__ part, int nsplit,
                                                              int64_t stride, int64_t M, int64_t N,
                                                              const int32_t* __restrict__ rows,
                                                              const int32_t* __restrict__ cols,
@@ -101,16 +142,23 @@ __global__ __launch_bounds__(256) void reduce_scatter_kernel(const double* __res
     if (idx >= M * N) return;
     const int64_t m = idx / N, n = idx - m * N;
     double s = 0.0;
-    for (int z = 0; z < nsplit; ++z) s += part[z * stride + idx];
+    for (int z = 0; z < nsplit; ++z) s += (double)part[z * stride + idx];
     const int64_t r = rows ? rows[m] : m;
     const int64_t c = cols ? cols[n] : n;
     Kt[r * nbf + c] += s;
 }
 
-__global__ __launch_bounds__(256) void fill_kernel(double* __restrict__ p, int64_t n, double v)
+template <typename T>
+__global__ __launch_bounds__(256) void fill_kernel(T* __restrict__ p, int64_t n, T v)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = v;
+}
+
+__global__ __launch_bounds__(256) void convert_kernel(const double* __restrict__ in, int64_t n, float* __restrict__ out)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = (float)in[i];
 }
 
 __device__ double block_sum(double v, double* sh)
@@ -184,8 +232,11 @@ hipError_t launch_mfma_probe(double* out_dev, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_gemm_f64(int64_t M, int64_t N, int64_t K, const double* A, int64_t lda, const double* B, int64_t ldb,
-                           bool bt, double* C, int64_t ldc, int nsplit, int64_t split_stride, hipStream_t s)
+namespace {
+
+template <typename TA, typename TB, typename TC, bool F32>
+hipError_t launch_gemm_t(int64_t M, int64_t N, int64_t K, const TA* A, int64_t lda, const TB* B, int64_t ldb, bool bt,
+                         TC* C, int64_t ldc, int nsplit, int64_t split_stride, hipStream_t s)
 {
     if (M <= 0 || N <= 0) return hipSuccess;
     if (nsplit < 1) nsplit = 1;
@@ -194,25 +245,65 @@ hipError_t launch_gemm_f64(int64_t M, int64_t N, int64_t K, const double* A, int
     if (kchunk <= 0) kchunk = TK;
     const int64_t nz = (K + kchunk - 1) / kchunk;
     dim3 grid((unsigned)((N + TN - 1) / TN), (unsigned)((M + TM - 1) / TM), (unsigned)(nz > 0 ? nz : 1)), block(256);
-    hipLaunchKernelGGL(gemm_f64_kernel, grid, block, 0, s, M, N, K, A, lda, B, ldb, bt ? 1 : 0, C, ldc, kchunk,
-                       split_stride);
+    hipLaunchKernelGGL((gemm_kernel<TA, TB, TC, F32>), grid, block, 0, s, M, N, K, A, lda, B, ldb, bt ? 1 : 0, C, ldc,
+                       kchunk, split_stride);
     if (nz < nsplit) {
         // chunks beyond the K range would be left unwritten: clear them
         for (int64_t z = nz; z < nsplit; ++z) {
-            hipError_t e = launch_fill(C + z * split_stride, M * ldc, 0.0, s);
-            if (e != hipSuccess) return e;
+            const int64_t n = M * ldc;
+            int64_t blocks = (n + 255) / 256;
+            if (blocks > 65536) blocks = 65536;
+            hipLaunchKernelGGL((fill_kernel<TC>), dim3((unsigned)blocks), dim3(256), 0, s, C + z * split_stride, n,
+                               (TC)0);
         }
     }
     return hipGetLastError();
 }
 
-hipError_t launch_reduce_scatter(const double* part, int nsplit, int64_t stride, int64_t M, int64_t N,
-                                 const int32_t* rows, const int32_t* cols, double* Kt, int64_t nbf, hipStream_t s)
+template <typename TP>
+hipError_t launch_reduce_scatter_t(const TP* part, int nsplit, int64_t stride, int64_t M, int64_t N,
+                                   const int32_t* rows, const int32_t* cols, double* Kt, int64_t nbf, hipStream_t s)
 {
     if (M <= 0 || N <= 0) return hipSuccess;
     const int64_t n = M * N;
-    hipLaunchKernelGGL(reduce_scatter_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part, nsplit, stride,
-                       M, N, rows, cols, Kt, nbf);
+    hipLaunchKernelGGL((reduce_scatter_kernel<TP>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part, nsplit,
+                       stride, M, N, rows, cols, Kt, nbf);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_gemm_f64(int64_t M, int64_t N, int64_t K, const double* A, int64_t lda, const double* B, int64_t ldb,
+                           bool bt, double* C, int64_t ldc, int nsplit, int64_t split_stride, hipStream_t s)
+{
+    return launch_gemm_t<double, double, double, false>(M, N, K, A, lda, B, ldb, bt, C, ldc, nsplit, split_stride, s);
+}
+
+hipError_t launch_gemm_f32(int64_t M, int64_t N, int64_t K, const float* A, int64_t lda, const float* B, int64_t ldb,
+                           bool bt, float* C, int64_t ldc, int nsplit, int64_t split_stride, hipStream_t s)
+{
+    return launch_gemm_t<float, float, float, true>(M, N, K, A, lda, B, ldb, bt, C, ldc, nsplit, split_stride, s);
+}
+
+hipError_t launch_gemm_f32_dA(int64_t M, int64_t N, int64_t K, const double* A, int64_t lda, const float* B,
+                              int64_t ldb, bool bt, double* C, int64_t ldc, int nsplit, int64_t split_stride,
+                              hipStream_t s)
+{
+    return launch_gemm_t<double, float, double, true>(M, N, K, A, lda, B, ldb, bt, C, ldc, nsplit, split_stride, s);
+}
+
+hipError_t launch_reduce_scatter(const double* part, int nsplit, int64_t stride, int64_t M, int64_t N,
+                                 const int32_t* rows, const int32_t* cols, double* Kt, int64_t nbf, hipStream_t s)
+{
+    return launch_reduce_scatter_t<double>(part, nsplit, stride, M, N, rows, cols, Kt, nbf, s);
+}
+
+hipError_t launch_convert_f32(const double* in, int64_t n, float* out, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(convert_kernel, dim3((unsigned)blocks), dim3(256), 0, s, in, n, out);
     return hipGetLastError();
 }
 
@@ -221,7 +312,7 @@ hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t s)
     if (n <= 0) return hipSuccess;
     int64_t blocks = (n + 255) / 256;
     if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(fill_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
+    hipLaunchKernelGGL((fill_kernel<double>), dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
     return hipGetLastError();
 }
 

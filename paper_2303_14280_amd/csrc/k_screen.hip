@@ -1,0 +1,538 @@
+// Density-dependent screening of the A.F step (Sec. II.E, the role of Eq. sp_set) with a
+// rigorous block bound, on the GPU.
+//
+// A(r) is positive semi-definite (c^T A(r) c = int (sum_mu c_mu phi_mu)^2 / |r - r_i| >= 0),
+// so |A_ab(r)| <= sqrt(A_aa(r) A_bb(r)).  For the energy contribution of the (A,B) shell-pair
+// block over a batch j, e_AB = sum_i w_i F_A,i^T A_AB(r_i) F_B,i, Cauchy-Schwarz over the
+// points gives |e_AB| <= U_A U_B with
+//   U_A = sqrt( sum_i w_i ( sum_c |F_{A_c,i}| sqrt(A_{A_c A_c}(r_i)) )^2 ),
+// which needs only the diagonal integrals (one same-shell pair per shell).  Skipping a set
+// of blocks changes E_x by at most the sum of their U_A U_B.
+//
+// Per batch the builder bins log2(U) in half octaves, bounds the energy of every candidate
+// skip set from the bin histogram (pairs in bins (k, l) have U_A U_B < 2^{(k+l+2)/2}),
+// takes the largest skip set whose bound fits the batch's budget, and writes the surviving
+// pairs as compacted run / B-task records for the A.F kernels.
+//
+// The learned screen refines this: the bound's survivors get a second estimate from the
+// network (min of the bound and the prediction plus a margin; the bound alone for blocks
+// whose features leave the training range), and a second half-octave histogram of these
+// estimates spends the rest of the batch's budget.
+#include "os3c.h"
+#include "learn.h"
+
+namespace snk {
+namespace {
+
+using namespace os3c;
+
+constexpr int kNoBin = -100000;     // U == 0
+
+// ---------------------------------------------------------------------------------------
+// U_A for the shells of one angular momentum L: one workgroup per batch, lane = point.
+// ---------------------------------------------------------------------------------------
+template <int L, typename TF>
+__global__ __launch_bounds__(256) void diag_bound_kernel(const double* __restrict__ px, const double* __restrict__ py,
+                                                         const double* __restrict__ pz, const double* __restrict__ pw,
+                                                         const TF* __restrict__ F, int64_t ld,
+                                                         const PrimPair* __restrict__ prims,
+                                                         const int32_t* __restrict__ dsh,   // [n] shell
+                                                         const int32_t* __restrict__ drow,  // [n] first row
+                                                         const int32_t* __restrict__ dpb,   // [n] prim_begin of (A,A)
+                                                         const int32_t* __restrict__ dnp,   // [n] nprim of (A,A)
+                                                         int32_t n, double* __restrict__ U,
+                                                         double* __restrict__ Nf, int32_t nshell,
+                                                         const double* __restrict__ gtab)
+{
+    constexpr int N = ncart(L);
+    __shared__ double tab[kBoysRows * kBoysCols];
+    __shared__ double part[2][4];
+    __shared__ double npart[2][4];
+    for (int i = threadIdx.x; i < kBoysRows * kBoysCols; i += blockDim.x) tab[i] = gtab[i];
+    __syncthreads();
+    const int batch = blockIdx.x;
+    const int64_t col = (int64_t)batch * kBatch + threadIdx.x;
+    const double cx = px[col], cy = py[col], cz = pz[col], w = pw[col];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const double AB[3] = {0.0, 0.0, 0.0};
+    for (int s = 0; s < n; ++s) {
+        const int row = drow[s];
+        double Ab[N][N];
+        pair_block<L, L>(prims + dpb[s], dnp[s], AB, cx, cy, cz, tab, Ab);
+        double t = 0.0, f2 = 0.0;
+        sfor<0, N>([&](auto cc) {
+            constexpr int c = CV(cc);
+            const double f = cnorm(L, c) * (double)F[(int64_t)(row + c) * ld + col];
+            t += fabs(f) * sqrt(fmax(Ab[c][c], 0.0));    // A_cc of the unit-normalised component
+            f2 += f * f;
+        });
+        double v = w * t * t, q = w * f2;
+        for (int o = 32; o > 0; o >>= 1) {
+            v += __shfl_xor(v, o);
+            q += __shfl_xor(q, o);
+        }
+        if (lane == 0) {
+            part[s & 1][wave] = v;
+            npart[s & 1][wave] = q;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const int64_t o = (int64_t)batch * nshell + dsh[s];
+            U[o] = sqrt(part[s & 1][0] + part[s & 1][1] + part[s & 1][2] + part[s & 1][3]);
+            if (Nf) Nf[o] = sqrt(npart[s & 1][0] + npart[s & 1][1] + npart[s & 1][2] + npart[s & 1][3]);
+        }
+    }
+}
+
+// block-wide exclusive prefix count of a per-thread flag (256 threads), returns the total
+__device__ __forceinline__ int block_scan_flag(bool flag, int* wsum, int* rank)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const unsigned long long m = __ballot(flag);
+    const unsigned long long lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+    const int in_wave = __popcll(m & lt);
+    if (lane == 0) wsum[wave] = __popcll(m);
+    __syncthreads();
+    int before = 0;
+    for (int k = 0; k < wave; ++k) before += wsum[k];
+    const int total = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    __syncthreads();
+    *rank = before + in_wave;
+    return total;
+}
+
+__device__ __forceinline__ int64_t pair_index(int s, int t)
+{
+    if (s < t) {
+        const int x = s;
+        s = t;
+        t = x;
+    }
+    return (int64_t)s * (s + 1) / 2 + t;
+}
+
+// ---------------------------------------------------------------------------------------
+// Bound set-up shared by the list builder and the learned estimate pass: per-shell bins of
+// log2 U, the batch's bound threshold S (pairs with bins[A] + bins[B] < S are skipped), the
+// bound on their energy, and the shells that can pair above S, grouped by l in shell order.
+// ---------------------------------------------------------------------------------------
+struct BoundShared {
+    int32_t hist[kNBins];
+    double cnt_s[2 * kNBins];
+    int32_t aoff[4];
+    int32_t S, bmax;
+    double acc;
+    int wsum[4];
+    int carry;
+};
+
+__device__ void bound_setup(const double* __restrict__ Ub, int nshell, const int32_t* __restrict__ shell_l,
+                            double eps, int32_t* bins, int32_t* act, BoundShared& sh)
+{
+    const int tid = threadIdx.x;
+    for (int k = tid; k < kNBins; k += blockDim.x) sh.hist[k] = 0;
+    __syncthreads();
+    for (int s = tid; s < nshell; s += blockDim.x) {
+        const double u = Ub[s];
+        int b = kNoBin;
+        if (u > 0.0) {
+            b = (int)floor(2.0 * log2(u)) + kBinOff;
+            b = b < 0 ? 0 : (b >= kNBins ? kNBins - 1 : b);   // clamped: still an upper bin
+            atomicAdd(&sh.hist[b], 1);
+        }
+        bins[s] = b;
+    }
+    __syncthreads();
+    // unordered pairs per bin sum s = k + l (index space), weighted by the pair bound
+    for (int s = tid; s < 2 * kNBins; s += blockDim.x) {
+        double c = 0.0;
+        const int k0 = s - (kNBins - 1) > 0 ? s - (kNBins - 1) : 0;
+        const int k1 = s < kNBins - 1 ? s : kNBins - 1;
+        for (int k = k0; k <= k1; ++k) c += (double)sh.hist[k] * (double)sh.hist[s - k];
+        if ((s & 1) == 0) c += (double)sh.hist[s >> 1];
+        sh.cnt_s[s] = 0.5 * c;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        // largest S with sum_{s < S} count(s) * 2^{(s - 2 kBinOff + 2)/2} <= eps
+        double acc = 0.0;
+        int S = 0;
+        for (int s = 0; s < 2 * kNBins; ++s) {
+            if (sh.cnt_s[s] == 0.0) {
+                S = s + 1;
+                continue;
+            }
+            const double add = sh.cnt_s[s] * exp2(0.5 * (double)(s - 2 * kBinOff + 2));
+            if (acc + add > eps) break;
+            acc += add;
+            S = s + 1;
+        }
+        int bmax = -1;
+        for (int k = kNBins - 1; k >= 0; --k)
+            if (sh.hist[k]) {
+                bmax = k;
+                break;
+            }
+        if (bmax < 0) S = 1 << 30;                 // every U is zero: nothing to evaluate
+        sh.S = S;
+        sh.acc = acc;
+        sh.bmax = bmax;
+        sh.aoff[0] = 0;
+    }
+    __syncthreads();
+    const int S = sh.S;
+    const int bmax = sh.bmax;
+    for (int l = 0; l <= 2; ++l) {
+        if (tid == 0) sh.carry = 0;
+        __syncthreads();
+        const int base = sh.aoff[l];
+        for (int s0 = 0; s0 < nshell; s0 += blockDim.x) {
+            const int s = s0 + tid;
+            const bool f = s < nshell && shell_l[s] == l && bins[s] != kNoBin && bins[s] + bmax >= S;
+            int rank;
+            const int tot = block_scan_flag(f, sh.wsum, &rank);
+            if (f) act[base + sh.carry + rank] = s;
+            __syncthreads();
+            if (tid == 0) sh.carry += tot;
+            __syncthreads();
+        }
+        if (tid == 0) sh.aoff[l + 1] = base + sh.carry;
+        __syncthreads();
+    }
+}
+
+__device__ __forceinline__ int est_bin(float lest)
+{
+    if (!(lest > -1e30f)) return -1;            // zero estimate
+    int b = (int)floorf(2.0f * lest) + kBinOff;
+    return b < 0 ? 0 : (b >= kNBins ? kNBins - 1 : b);
+}
+
+// ---------------------------------------------------------------------------------------
+// Learned estimate pass: one workgroup per batch; each wave takes 16 candidate pairs at a
+// time and runs the network on them in one sweep of matrix-core ops.
+// Dynamic shared memory: bins[nshell] + active[nshell] (int32).
+// ---------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void screen_est_kernel(EstArgs a)
+{
+    extern __shared__ int32_t dyn[];
+    int32_t* bins = dyn;
+    int32_t* act = dyn + a.nshell;
+    __shared__ BoundShared sh;
+    __shared__ int32_t lhist[kNBins];
+
+    const int batch = blockIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r = lane & 15, g = lane >> 4;
+    const double* Ub = a.U + (int64_t)batch * a.nshell;
+    const double* Nb = a.N + (int64_t)batch * a.nshell;
+    for (int k = tid; k < kNBins; k += blockDim.x) lhist[k] = 0;
+    bound_setup(Ub, a.nshell, a.shell_l, a.eps_batch, bins, act, sh);
+    const int S = sh.S;
+    const BatchGeo bg = a.geo[batch];
+
+    learn::MlpRegs R;
+    learn::load_mlp(a.params, a.norm, a.lo, a.hi, R);
+    const float ln2_10 = 3.32192809488736f;   // log2(10)
+
+    for (int c = 0; c < 6; ++c) {
+        const int la = kClassLA_dev(c), lb = kClassLB_dev(c);
+        const int nA = sh.aoff[la + 1] - sh.aoff[la], nB = sh.aoff[lb + 1] - sh.aoff[lb];
+        const int32_t* actA = act + sh.aoff[la];
+        const int32_t* actB = act + sh.aoff[lb];
+        const int64_t ncombo = (int64_t)nA * nB;
+        for (int64_t q = wave; q * 16 < ncombo; q += 4) {
+            const int64_t i = q * 16 + r;
+            bool valid = false;
+            int aa = 0, b = 0;
+            int64_t p = 0;
+            if (i < ncombo) {
+                aa = actA[(int)(i / nB)];
+                b = actB[(int)(i % nB)];
+                if (!(la == lb && aa < b) && bins[aa] + bins[b] >= S) {
+                    p = pair_index(aa, b);
+                    valid = a.pairs[p].nprim > 0;
+                }
+            }
+            if (__ballot(valid) == 0ull) continue;
+            float f[16];
+            const PairFeat pf = a.pfeat[p];
+            learn::block_features(pf, a.lp[p], bg, Ub[aa], Ub[b], Nb[aa], Nb[b], f);
+            float x[4];
+            bool oob = false;
+            for (int e = 0; e < 4; ++e) {
+                // this lane supplies features 4g .. 4g+3 (constant-index selects, no scratch)
+                float v = f[e];
+                v = g == 1 ? f[4 + e] : v;
+                v = g == 2 ? f[8 + e] : v;
+                v = g == 3 ? f[12 + e] : v;
+                x[e] = v;
+                oob |= !(v >= R.lo[e] && v <= R.hi[e]);
+            }
+            const unsigned long long mo = __ballot(oob);
+            const bool sample_oob = ((mo >> r) & 0x0001000100010001ull) != 0ull;
+            const float y = learn::mlp_eval16(R, x);
+            if (g == 0 && valid) {
+                const double beta = (double)pf.cab * Ub[aa] * Ub[b];
+                double est = beta;
+                // a prediction never takes a block with a nonzero bound to a zero estimate
+                if (!sample_oob) est = fmin(beta, fmax(exp2((double)((y + a.margin) * ln2_10)), 1e-300));
+                const float lest = est > 0.0 ? (float)log2(est) : -INFINITY;
+                const int64_t o = (int64_t)batch * a.npair_total + p;
+                a.est[o] = lest;
+                if (a.yraw) a.yraw[o] = y;
+                const int eb = est_bin(lest);
+                if (eb >= 0) atomicAdd(&lhist[eb], 1);
+            }
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        // largest T with sum_{k < T} count(k) 2^{(k + 1 - kBinOff)/2} <= budget left by the bound
+        const double rem = a.eps_batch - sh.acc;
+        double acc = 0.0;
+        int T = 0;
+        for (int k = 0; k < kNBins; ++k) {
+            if (lhist[k] == 0) {
+                T = k + 1;
+                continue;
+            }
+            const double add = (double)lhist[k] * exp2(0.5 * (double)(k + 1 - kBinOff));
+            if (acc + add > rem) break;
+            acc += add;
+            T = k + 1;
+        }
+        a.thr[batch] = T;
+        a.skipped[batch] = sh.acc + acc;
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// List builder.  WRITE = false: counts only; WRITE = true: records at the scanned offsets.
+// Dynamic shared memory: bins[nshell] + active[nshell] + tilecnt[nshell] (int32).
+// ---------------------------------------------------------------------------------------
+template <bool WRITE>
+__global__ __launch_bounds__(256) void screen_kernel(ScreenArgs a)
+{
+    extern __shared__ int32_t dyn[];
+    int32_t* bins = dyn;
+    int32_t* act = dyn + a.nshell;
+    int32_t* tilecnt = dyn + 2 * a.nshell;
+    __shared__ BoundShared sh;
+
+    const int batch = blockIdx.x;
+    const int tid = threadIdx.x;
+    const double* Ub = a.U + (int64_t)batch * a.nshell;
+    bound_setup(Ub, a.nshell, a.shell_l, a.eps_batch, bins, act, sh);
+    const int S = sh.S;
+    const bool learned = a.est != nullptr;
+    const int T = learned ? a.thr[batch] : 0;
+    const float* estb = learned ? a.est + (int64_t)batch * a.npair_total : nullptr;
+    // block (aa, b) of the batch is evaluated
+    auto keep = [&](int aa, int b) -> bool {
+        if (bins[aa] + bins[b] < S) return false;
+        const int64_t p = pair_index(aa, b);
+        if (a.pairs[p].nprim == 0) return false;
+        return !learned || est_bin(estb[p]) >= T;
+    };
+
+    for (int c = 0; c < 6; ++c) {
+        const int la = kClassLA_dev(c), lb = kClassLB_dev(c), TA = kTileA_dev(c);
+        const int nA = sh.aoff[la + 1] - sh.aoff[la], nB = sh.aoff[lb + 1] - sh.aoff[lb];
+        const int32_t* actA = act + sh.aoff[la];
+        const int32_t* actB = act + sh.aoff[lb];
+        const int nt = (nA + TA - 1) / TA;
+        const int64_t ncombo = (int64_t)nt * nB;
+        for (int t = tid; t < nt; t += blockDim.x) tilecnt[t] = 0;
+        if (tid == 0) sh.carry = 0;
+        __syncthreads();
+        int64_t npair = 0;
+        // pass 1: per-tile counts
+        for (int64_t i0 = 0; i0 < ncombo; i0 += blockDim.x) {
+            const int64_t i = i0 + tid;
+            int mask = 0;
+            if (i < ncombo) {
+                const int t = (int)(i / nB), bi = (int)(i - (int64_t)t * nB);
+                const int b = actB[bi];
+                for (int k = 0; k < TA; ++k) {
+                    const int ai = t * TA + k;
+                    if (ai >= nA) break;
+                    const int aa = actA[ai];
+                    if (la == lb && aa < b) continue;
+                    if (!keep(aa, b)) continue;
+                    mask |= 1 << k;
+                }
+                if (mask) {
+                    atomicAdd(&tilecnt[t], 1);
+                    npair += __popc(mask);
+                }
+            }
+        }
+        __syncthreads();
+        if (!WRITE) {
+            // reduce npair over the block
+            double v = (double)npair;
+            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+            __shared__ double red[4];
+            if ((tid & 63) == 0) red[tid >> 6] = v;
+            __syncthreads();
+            int nrun = 0, nbt = 0;
+            if (tid == 0) {
+                for (int t = 0; t < nt; ++t) {
+                    nbt += tilecnt[t];
+                    nrun += tilecnt[t] > 0;
+                }
+                a.counts[((int64_t)batch * 6 + c) * 2] = nrun;
+                a.counts[((int64_t)batch * 6 + c) * 2 + 1] = nbt;
+                a.npairs[(int64_t)batch * 6 + c] = (int64_t)(red[0] + red[1] + red[2] + red[3]);
+            }
+            __syncthreads();
+            continue;
+        }
+        // WRITE: exclusive scan of tile counts -> run records
+        if (tid == 0) {
+            const int64_t rb = a.run_base[(int64_t)c * (a.nbatch + 1) + batch];
+            const int64_t bb = a.bt_base[(int64_t)c * (a.nbatch + 1) + batch];
+            int64_t bt = bb, r = rb;
+            const int RS = 2 + TA;
+            for (int t = 0; t < nt; ++t) {
+                const int n = tilecnt[t];
+                if (n > 0) {
+                    int32_t* rec = a.runs[c] + r * RS;
+                    rec[0] = (int32_t)bt;
+                    rec[1] = (int32_t)(bt + n);
+                    for (int k = 0; k < TA; ++k) {
+                        const int ai = t * TA + k;
+                        rec[2 + k] = ai < nA ? a.shell_row[actA[ai]] : -1;
+                    }
+                    ++r;
+                }
+                bt += n;
+            }
+            a.batch_run_off[c][batch] = (int32_t)rb;
+            if (batch == a.nbatch - 1) a.batch_run_off[c][a.nbatch] = (int32_t)r;
+        }
+        __syncthreads();
+        // pass 2: B-task records in (tile, B) order
+        const int64_t bb = a.bt_base[(int64_t)c * (a.nbatch + 1) + batch];
+        const int BS = 2 + 2 * TA;
+        for (int64_t i0 = 0; i0 < ncombo; i0 += blockDim.x) {
+            const int64_t i = i0 + tid;
+            int mask = 0;
+            int t = 0, b = 0;
+            if (i < ncombo) {
+                t = (int)(i / nB);
+                b = actB[(int)(i - (int64_t)t * nB)];
+                for (int k = 0; k < TA; ++k) {
+                    const int ai = t * TA + k;
+                    if (ai >= nA) break;
+                    const int aa = actA[ai];
+                    if (la == lb && aa < b) continue;
+                    if (!keep(aa, b)) continue;
+                    mask |= 1 << k;
+                }
+            }
+            int rank;
+            const int tot = block_scan_flag(mask != 0, sh.wsum, &rank);
+            if (mask) {
+                const int64_t slot = bb + sh.carry + rank;
+                int32_t* rec = a.btasks[c] + slot * BS;
+                double* ab = a.btask_ab[c] + slot * 3 * TA;
+                rec[0] = a.shell_row[b];
+                rec[1] = mask;
+                for (int k = 0; k < TA; ++k) {
+                    const int ai = t * TA + k;
+                    int pb = 0, np = 0;
+                    double x = 0.0, y = 0.0, z = 0.0;
+                    if (mask & (1 << k)) {
+                        const PairHdr h = a.pairs[pair_index(actA[ai], b)];
+                        pb = h.prim_begin;
+                        np = h.nprim;
+                        x = h.ABx;
+                        y = h.ABy;
+                        z = h.ABz;
+                    }
+                    rec[2 + 2 * k] = pb;
+                    rec[3 + 2 * k] = np;
+                    ab[3 * k] = x;
+                    ab[3 * k + 1] = y;
+                    ab[3 * k + 2] = z;
+                }
+            }
+            __syncthreads();
+            if (tid == 0) sh.carry += tot;
+            __syncthreads();
+        }
+    }
+    if (!WRITE && !learned && tid == 0) a.skipped[batch] = sh.acc;
+}
+
+// exclusive scans of the per-(batch, class) counts: run_base / bt_base [6][nbatch+1]
+__global__ void screen_scan_kernel(const int32_t* __restrict__ counts, int32_t nbatch, int64_t* __restrict__ run_base,
+                                   int64_t* __restrict__ bt_base)
+{
+    const int c = threadIdx.x;
+    if (c >= 6) return;
+    int64_t r = 0, b = 0;
+    for (int j = 0; j < nbatch; ++j) {
+        run_base[(int64_t)c * (nbatch + 1) + j] = r;
+        bt_base[(int64_t)c * (nbatch + 1) + j] = b;
+        r += counts[((int64_t)j * 6 + c) * 2];
+        b += counts[((int64_t)j * 6 + c) * 2 + 1];
+    }
+    run_base[(int64_t)c * (nbatch + 1) + nbatch] = r;
+    bt_base[(int64_t)c * (nbatch + 1) + nbatch] = b;
+}
+
+}  // namespace
+
+hipError_t launch_diag_bound(int l, const double* px, const double* py, const double* pz, const double* pw,
+                             const double* F, const float* F32, int64_t ld, const PrimPair* prims, const int32_t* dsh,
+                             const int32_t* drow, const int32_t* dpb, const int32_t* dnp, int32_t n, double* U,
+                             double* N, int32_t nshell, int32_t nbatch, const double* tab, hipStream_t s)
+{
+    if (nbatch <= 0 || n <= 0) return hipSuccess;
+    dim3 grid(nbatch), block(kBatch);
+#define SNK_DB(L)                                                                                                  \
+    if (F32)                                                                                                       \
+        hipLaunchKernelGGL((diag_bound_kernel<L, float>), grid, block, 0, s, px, py, pz, pw, F32, ld, prims, dsh,  \
+                           drow, dpb, dnp, n, U, N, nshell, tab);                                                  \
+    else                                                                                                           \
+        hipLaunchKernelGGL((diag_bound_kernel<L, double>), grid, block, 0, s, px, py, pz, pw, F, ld, prims, dsh,   \
+                           drow, dpb, dnp, n, U, N, nshell, tab)
+    switch (l) {
+        case 0: SNK_DB(0); break;
+        case 1: SNK_DB(1); break;
+        case 2: SNK_DB(2); break;
+        default: return hipErrorInvalidValue;
+    }
+#undef SNK_DB
+    return hipGetLastError();
+}
+
+hipError_t launch_screen(bool write, const ScreenArgs& a, hipStream_t s)
+{
+    if (a.nbatch <= 0) return hipSuccess;
+    const size_t shm = (size_t)3 * a.nshell * sizeof(int32_t);
+    if (write)
+        hipLaunchKernelGGL((screen_kernel<true>), dim3(a.nbatch), dim3(256), shm, s, a);
+    else
+        hipLaunchKernelGGL((screen_kernel<false>), dim3(a.nbatch), dim3(256), shm, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_screen_est(const EstArgs& a, hipStream_t s)
+{
+    if (a.nbatch <= 0) return hipSuccess;
+    const size_t shm = (size_t)2 * a.nshell * sizeof(int32_t);
+    hipLaunchKernelGGL(screen_est_kernel, dim3(a.nbatch), dim3(256), shm, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_screen_scan(const int32_t* counts, int32_t nbatch, int64_t* run_base, int64_t* bt_base, hipStream_t s)
+{
+    hipLaunchKernelGGL(screen_scan_kernel, dim3(1), dim3(64), 0, s, counts, nbatch, run_base, bt_base);
+    return hipGetLastError();
+}
+
+}  // namespace snk

@@ -1,0 +1,124 @@
+// Device code of the learned block screener shared by the screen and training-data kernels:
+// the 16 block features and the network 16 -> 64 -> 64 -> 1 (SiLU) evaluated for 16 blocks
+// at once per wave64 on the bf16 matrix cores with FP32 accumulation.
+#pragma once
+#include "snk_internal.h"
+
+namespace snk {
+namespace learn {
+
+typedef short bf4 __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+// nearest bfloat16 (ties to even): bit pattern, and its value as float
+__device__ __forceinline__ unsigned bf16_bits(float x)
+{
+    unsigned u = __float_as_uint(x);
+    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+__device__ __forceinline__ float bf16_round(float x) { return __uint_as_float(bf16_bits(x) << 16); }
+
+__device__ __forceinline__ float silu(float z) { return z / (1.0f + __expf(-z)); }
+
+__device__ __forceinline__ float lg10(double v) { return v > 1e-40 ? (float)log10(v) : -40.0f; }
+
+__device__ __forceinline__ float box_dist(const float* p, const BatchGeo& g)
+{
+    float s = 0.0f;
+    for (int d = 0; d < 3; ++d) {
+        const float e = fmaxf(fmaxf(g.lo[d] - p[d], p[d] - g.hi[d]), 0.0f);
+        s = fmaf(e, e, s);
+    }
+    return sqrtf(s);
+}
+
+// Features of block (pair, batch): pair constants, batch geometry, and the batch's F norms
+// and bound factors of the two shells.
+__device__ __forceinline__ void block_features(const PairFeat& pf, float lp, const BatchGeo& bg, double UA,
+                                               double UB, double NA, double NB, float f[16])
+{
+    f[0] = pf.la;
+    f[1] = pf.lb;
+    f[2] = pf.lzA;
+    f[3] = pf.lzB;
+    f[4] = pf.ab;
+    f[5] = pf.lq;
+    f[6] = lp;
+    f[7] = box_dist(pf.pc, bg);
+    f[8] = bg.hd;
+    f[9] = box_dist(pf.a, bg);
+    f[10] = box_dist(pf.b, bg);
+    f[11] = bg.lw;
+    f[12] = lg10(NA);
+    f[13] = lg10(NB);
+    f[14] = lg10((double)pf.cab * UA * UB);
+    const float dx = pf.pc[0] - bg.ctr[0], dy = pf.pc[1] - bg.ctr[1], dz = pf.pc[2] - bg.ctr[2];
+    f[15] = sqrtf(dx * dx + dy * dy + dz * dz);
+}
+
+// Register image of the network for one lane of a wave64 that evaluates 16 samples.
+// Lane (r = lane % 16, g = lane / 16).  Matrix-core operand layout of the 16x16x16 bf16
+// product D = A B (checked by the layout probe): lane (r, g) holds A[r][4g..4g+3],
+// B[4g..4g+3][r] and D[4g..4g+3][r].  So the samples are the columns, a layer's output
+// tile is directly the next layer's B operand, and each lane supplies features 4g..4g+3.
+struct MlpRegs {
+    bf4 w1[4];          // W1[16m + r][4g + e]
+    bf4 w2[4][4];       // W2[16m2 + r][16m + 4g + e]
+    f4v b1[4], b2[4];   // b[16m + 4g + e]
+    float w3[4][4];     // W3[16m + 4g + e]
+    float b3;
+    float mean[4], istd[4], lo[4], hi[4];   // features 4g + e
+};
+
+__device__ __forceinline__ short bfs(float x) { return (short)bf16_bits(x); }
+
+// Parameters are bf16-rounded on load (weights and biases), as in the inference form of the
+// standalone forward kernel.
+__device__ inline void load_mlp(const float* __restrict__ params, const MlpNorm& nrm, const float* lo,
+                                const float* hi, MlpRegs& R)
+{
+    constexpr int OW1 = 0, OB1 = 1024, OW2 = 1088, OB2 = 5184, OW3 = 5248, OB3 = 5312;
+    const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
+    for (int m = 0; m < 4; ++m) {
+        for (int e = 0; e < 4; ++e) {
+            R.w1[m][e] = bfs(params[OW1 + (16 * m + r) * 16 + 4 * g + e]);
+            R.b1[m][e] = bf16_round(params[OB1 + 16 * m + 4 * g + e]);
+            R.b2[m][e] = bf16_round(params[OB2 + 16 * m + 4 * g + e]);
+            R.w3[m][e] = bf16_round(params[OW3 + 16 * m + 4 * g + e]);
+        }
+        for (int k = 0; k < 4; ++k)
+            for (int e = 0; e < 4; ++e) R.w2[m][k][e] = bfs(params[OW2 + (16 * m + r) * 64 + 16 * k + 4 * g + e]);
+    }
+    R.b3 = bf16_round(params[OB3]);
+    for (int e = 0; e < 4; ++e) {
+        R.mean[e] = nrm.mean[4 * g + e];
+        R.istd[e] = nrm.inv_std[4 * g + e];
+        R.lo[e] = lo[4 * g + e];
+        R.hi[e] = hi[4 * g + e];
+    }
+}
+
+// x: raw features 4g..4g+3 of sample r.  Returns the network output of sample r in every
+// lane that holds sample r (all of the wave's lanes take part).
+__device__ inline float mlp_eval16(const MlpRegs& R, const float x[4])
+{
+    bf4 xb;
+    for (int e = 0; e < 4; ++e) xb[e] = bfs((x[e] - R.mean[e]) * R.istd[e]);
+    bf4 h1[4];
+    for (int m = 0; m < 4; ++m) {
+        f4v acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(R.w1[m], xb, R.b1[m], 0, 0, 0);
+        for (int e = 0; e < 4; ++e) h1[m][e] = bfs(silu(acc[e]));
+    }
+    float y = 0.0f;
+    for (int m2 = 0; m2 < 4; ++m2) {
+        f4v acc = R.b2[m2];
+        for (int m = 0; m < 4; ++m) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(R.w2[m2][m], h1[m], acc, 0, 0, 0);
+        for (int e = 0; e < 4; ++e) y = fmaf(R.w3[m2][e], bf16_round(silu(acc[e])), y);
+    }
+    y += __shfl_xor(y, 16);
+    y += __shfl_xor(y, 32);
+    return y + R.b3;
+}
+
+}  // namespace learn
+}  // namespace snk

@@ -1,0 +1,182 @@
+// Device building blocks of the 3c-CP integrals (App. A), shared by the A.F digestion
+// kernels and the screening kernels: Cartesian component tables, the Boys function
+// (Eq. boys), the vertical and horizontal Obara-Saika recursions (Eqs. vrr, hrr) and the
+// contracted block of one shell pair at one grid point.
+#pragma once
+
+#include "snk_internal.h"
+
+#include <type_traits>
+
+namespace snk {
+namespace os3c {
+
+constexpr int ncart(int l) { return (l + 1) * (l + 2) / 2; }
+
+// Cartesian exponent of direction q (0=x,1=y,2=z) of component c of level l,
+// lexicographic order (x,y,z; xx,xy,xz,yy,yz,zz; ...).
+constexpr int comp(int l, int c, int q)
+{
+    int k = 0;
+    for (int x = l; x >= 0; --x)
+        for (int y = l - x; y >= 0; --y) {
+            if (k == c) return q == 0 ? x : (q == 1 ? y : l - x - y);
+            ++k;
+        }
+    return -1;
+}
+constexpr int cidx(int l, int x, int z) { return ((l - x) * (l - x + 1)) / 2 + z; }
+// index at level l-1 of component c (level l) lowered in direction q
+constexpr int lower(int l, int c, int q)
+{
+    return cidx(l - 1, comp(l, c, 0) - (q == 0), comp(l, c, 2) - (q == 2));
+}
+// index at level l+1 of component c (level l) raised in direction q
+constexpr int raise(int l, int c, int q)
+{
+    return cidx(l + 1, comp(l, c, 0) + (q == 0), comp(l, c, 2) + (q == 2));
+}
+// recursion direction: first non-zero Cartesian exponent
+constexpr int dir_of(int l, int c) { return comp(l, c, 0) > 0 ? 0 : (comp(l, c, 1) > 0 ? 1 : 2); }
+// factor scaling component c of a shell of angular momentum l to unit norm (l <= 2)
+constexpr double cnorm(int l, int c)
+{
+    return (l == 2 && (c == 1 || c == 2 || c == 4)) ? 1.7320508075688772 : 1.0;
+}
+
+template <int B, int E, typename Fn>
+__device__ __forceinline__ void sfor(Fn&& f)
+{
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        sfor<B + 1, E>(f);
+    }
+}
+#define CV(x) decltype(x)::value
+
+// F_m(T), m = 0..L (Eq. boys).  T < kBoysTmax: Taylor series about the nearest
+// table node, F_m(T) = sum_j F_{m+j}(T_k) (T_k - T)^j / j!  (dF_m/dT = -F_{m+1});
+// above: F_0 = sqrt(pi/T)/2, F_m = F_{m-1} (2m-1)/(2T).
+template <int L>
+__device__ __forceinline__ void boys(double T, const double* __restrict__ tab, double (&F)[L + 1])
+{
+    if (T < kBoysTmax) {
+        const int k = (int)(T * (1.0 / kBoysStep) + 0.5);
+        const double d = k * kBoysStep - T;
+        const double* row = tab + k * kBoysCols;
+        double pw[kBoysTerms];
+        pw[0] = 1.0;
+        sfor<1, kBoysTerms>([&](auto jc) {
+            constexpr int j = CV(jc);
+            pw[j] = pw[j - 1] * (d * (1.0 / j));
+        });
+        sfor<0, L + 1>([&](auto mc) {
+            constexpr int m = CV(mc);
+            double s = row[m + kBoysTerms - 1] * pw[kBoysTerms - 1];
+            sfor<0, kBoysTerms - 1>([&](auto jc) {
+                constexpr int j = kBoysTerms - 2 - CV(jc);
+                s = fma(row[m + j], pw[j], s);
+            });
+            F[m] = s;
+        });
+    } else {
+        const double r = rsqrt(T);
+        const double h = 0.5 * r * r;
+        F[0] = 0.88622692545275801365 * r;
+        sfor<1, L + 1>([&](auto mc) {
+            constexpr int m = CV(mc);
+            F[m] = F[m - 1] * ((2 * m - 1) * h);
+        });
+    }
+}
+
+// Eq. vrr: Theta^n_{a+1q} = PA_q Theta^n_a - PC_q Theta^{n+1}_a + a_q/(2 zeta_p) (Theta^n_{a-1q} - Theta^{n+1}_{a-1q})
+template <int L>
+__device__ __forceinline__ void vrr(double (&th)[L + 1][L + 1][16], const double (&PA)[3], const double (&PC)[3],
+                                    double oo2zp)
+{
+    sfor<1, L + 1>([&](auto lc) {
+        constexpr int l = CV(lc);
+        sfor<0, ncart(l)>([&](auto cc) {
+            constexpr int c = CV(cc);
+            constexpr int q = dir_of(l, c);
+            constexpr int c1 = lower(l, c, q);
+            constexpr int am = comp(l, c, q) - 1;
+            constexpr int c2 = am > 0 ? lower(l - 1, c1, q) : 0;
+            sfor<0, L - l + 1>([&](auto nc) {
+                constexpr int n = CV(nc);
+                double v = PA[q] * th[n][l - 1][c1] - PC[q] * th[n + 1][l - 1][c1];
+                if constexpr (am > 0) v += (am * oo2zp) * (th[n][l - 2][c2] - th[n + 1][l - 2][c2]);
+                th[n][l][c] = v;
+            });
+        });
+    });
+}
+
+// Eq. hrr: Xi_{a(b+1q)} = Xi_{(a+1q)b} + AB_q Xi_{ab}, from Xi_{a0} = contracted Theta^0_a
+template <int LA, int LB>
+__device__ __forceinline__ void hrr(const double (&acc)[LA + LB + 1][16], const double (&AB)[3],
+                                    double (&out)[ncart(LA)][ncart(LB)])
+{
+    double xi[LB + 1][LA + LB + 1][16][6];
+    sfor<LA, LA + LB + 1>([&](auto lc) {
+        constexpr int la = CV(lc);
+        sfor<0, ncart(la)>([&](auto cc) { xi[0][la][CV(cc)][0] = acc[la][CV(cc)]; });
+    });
+    sfor<1, LB + 1>([&](auto lbc) {
+        constexpr int lb = CV(lbc);
+        sfor<0, ncart(lb)>([&](auto cbc) {
+            constexpr int cb = CV(cbc);
+            constexpr int q = dir_of(lb, cb);
+            constexpr int cb1 = lower(lb, cb, q);
+            sfor<LA, LA + LB - lb + 1>([&](auto lac) {
+                constexpr int la = CV(lac);
+                sfor<0, ncart(la)>([&](auto cac) {
+                    constexpr int ca = CV(cac);
+                    constexpr int ca1 = raise(la, ca, q);
+                    xi[lb][la][ca][cb] = xi[lb - 1][la + 1][ca1][cb1] + AB[q] * xi[lb - 1][la][ca][cb1];
+                });
+            });
+        });
+    });
+    sfor<0, ncart(LA)>([&](auto cac) {
+        sfor<0, ncart(LB)>([&](auto cbc) { out[CV(cac)][CV(cbc)] = xi[LB][LA][CV(cac)][CV(cbc)]; });
+    });
+}
+
+// Contracted 3c-CP block A_ab(C) of one shell pair at the lane's point C:
+// Eq. vrr per primitive pair, contraction over primitives, then Eq. hrr.
+template <int LA, int LB>
+__device__ __forceinline__ void pair_block(const PrimPair* __restrict__ pp0, int nprim, const double (&AB)[3],
+                                           double cx, double cy, double cz, const double* __restrict__ tab,
+                                           double (&Ab)[ncart(LA)][ncart(LB)])
+{
+    constexpr int L = LA + LB;
+    double acc[L + 1][16];
+    sfor<LA, L + 1>([&](auto lc) {
+        sfor<0, ncart(CV(lc))>([&](auto cc) { acc[CV(lc)][CV(cc)] = 0.0; });
+    });
+    // software pipeline: the next primitive pair's record is requested before the
+    // current one is evaluated, so its scalar-load latency overlaps the arithmetic
+    PrimPair nxt{};
+    if (nprim > 0) nxt = pp0[0];
+    for (int k = 0; k < nprim; ++k) {
+        const PrimPair pp = nxt;
+        if (k + 1 < nprim) nxt = pp0[k + 1];
+        const double PC[3] = {pp.Px - cx, pp.Py - cy, pp.Pz - cz};
+        const double PA[3] = {pp.PAx, pp.PAy, pp.PAz};
+        const double T = pp.zp * (PC[0] * PC[0] + PC[1] * PC[1] + PC[2] * PC[2]);
+        double Fm[L + 1];
+        boys<L>(T, tab, Fm);
+        double th[L + 1][L + 1][16];
+        sfor<0, L + 1>([&](auto nc) { th[CV(nc)][0][0] = pp.pref * Fm[CV(nc)]; });
+        vrr<L>(th, PA, PC, pp.oo2zp);
+        sfor<LA, L + 1>([&](auto lc) {
+            sfor<0, ncart(CV(lc))>([&](auto cc) { acc[CV(lc)][CV(cc)] += th[0][CV(lc)][CV(cc)]; });
+        });
+    }
+    hrr<LA, LB>(acc, AB, Ab);
+}
+
+}  // namespace os3c
+}  // namespace snk

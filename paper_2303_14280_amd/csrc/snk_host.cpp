@@ -15,6 +15,14 @@
 
 using namespace snk;
 
+namespace snk {
+// the learned screener's network (snk_mlp.cpp)
+const MlpNorm& mlp_norm(const snk_mlp* m);
+const float* mlp_params(const snk_mlp* m);
+void mlp_range(const snk_mlp* m, float* lo, float* hi, float* margin, int* has_range);
+int mlp_device(const snk_mlp* m);
+}  // namespace snk
+
 namespace {
 
 thread_local std::string g_last_error;
@@ -79,12 +87,51 @@ struct snk_ctx {
     int64_t max_cols = 0;
     int32_t max_nB = 0;
     int nsplit = 1;
+    bool mixed = false;                 // SNK_MIXED: FP32 Phi, P and F; FP32 matrix-core GEMMs
+    float *d_Phi32 = nullptr, *d_F32 = nullptr, *d_P32 = nullptr;
     double *d_Phi = nullptr, *d_F = nullptr, *d_G = nullptr, *d_part = nullptr, *d_Pg = nullptr;
     double *d_Kt = nullptr, *d_P = nullptr, *d_K = nullptr, *d_partial = nullptr, *d_ex = nullptr;
     double* d_boys = nullptr;
     int nfinish = 256;
 
     hipEvent_t ev[16] = {};
+
+    // screening (rigorous bound): static diagonal-pair lists per l, per-group work buffers
+    int32_t* d_diag_sh[3] = {nullptr, nullptr, nullptr};
+    int32_t* d_diag_row[3] = {nullptr, nullptr, nullptr};
+    int32_t* d_diag_pb[3] = {nullptr, nullptr, nullptr};
+    int32_t* d_diag_np[3] = {nullptr, nullptr, nullptr};
+    int32_t n_diag[3] = {0, 0, 0};
+    int32_t* d_shell_l = nullptr;
+    int32_t* d_shell_row = nullptr;
+    int32_t max_group_batches = 0;
+    double* d_U = nullptr;
+    int32_t* d_counts = nullptr;
+    int64_t* d_npairs = nullptr;
+    double* d_skipped = nullptr;
+    int64_t* d_run_base = nullptr;
+    int64_t* d_bt_base = nullptr;
+    int32_t* d_bro[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    double* d_N = nullptr;
+
+    // learned screen: static pair features, batch geometry, per-group estimates
+    const snk_mlp* mlp = nullptr;
+    int64_t npair_total = 0;
+    PairFeat* d_pfeat = nullptr;
+    int32_t* d_pa = nullptr;        // [npair_total] shell A of each pair index
+    int32_t* d_pb = nullptr;
+    BatchGeo* d_geo = nullptr;      // [nbatch]
+    float* d_lp = nullptr;          // [npair_total]
+    float* d_est = nullptr;         // [max_group_batches][npair_total]
+    int32_t* d_thr = nullptr;       // [max_group_batches]
+    std::vector<int32_t> ne_list;   // pair indices with kept primitive pairs, class order
+    int32_t ne_class_off[7] = {0, 0, 0, 0, 0, 0, 0};
+    int32_t* d_ne_list = nullptr;
+    int32_t* d_pool_runs[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    int32_t* d_pool_bt[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    double* d_pool_ab[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    int64_t cap_runs[6] = {0, 0, 0, 0, 0, 0};
+    int64_t cap_bt[6] = {0, 0, 0, 0, 0, 0};
 };
 
 namespace {
@@ -295,6 +342,58 @@ int class_of(int la, int lb)  // la >= lb: ss, ps, pp, ds, dp, dd
 const int kClassLA[6] = {0, 1, 1, 2, 2, 2};
 const int kClassLB[6] = {0, 0, 1, 0, 1, 2};
 
+// Static pair data of the learned screener's features, in pair-index order, and the list of
+// pairs with kept primitive pairs in class order (the training-data layout).
+int build_pair_feats(snk_ctx* c)
+{
+    const int64_t np = (int64_t)c->pairs.size();
+    c->npair_total = np;
+    std::vector<PairFeat> pf((size_t)np);
+    std::vector<int32_t> pa((size_t)np), pb((size_t)np);
+    std::vector<int32_t> by_class[6];
+    for (int64_t p = 0; p < np; ++p) {
+        const int A = c->pair_a[p], B = c->pair_b[p];
+        pa[p] = A;
+        pb[p] = B;
+        PairFeat f{};
+        double zA = 1e300, zB = 1e300;
+        for (int k = 0; k < c->snp[A]; ++k) zA = std::min(zA, c->exps[c->spo[A] + k]);
+        for (int k = 0; k < c->snp[B]; ++k) zB = std::min(zB, c->exps[c->spo[B] + k]);
+        double ab2 = 0.0;
+        for (int d = 0; d < 3; ++d) {
+            const double ra = c->scen[3 * A + d], rb = c->scen[3 * B + d];
+            f.a[d] = (float)ra;
+            f.b[d] = (float)rb;
+            f.pc[d] = (float)((zA * ra + zB * rb) / (zA + zB));
+            ab2 += (ra - rb) * (ra - rb);
+        }
+        f.la = (float)c->sl[A];
+        f.lb = (float)c->sl[B];
+        f.lzA = (float)std::log10(zA);
+        f.lzB = (float)std::log10(zB);
+        f.ab = (float)std::sqrt(ab2);
+        double q = 0.0;
+        const PairHdr& h = c->pairs[p];
+        for (int k = 0; k < h.nprim; ++k) q += std::fabs(c->prims[h.prim_begin + k].pref);
+        f.lq = q > 1e-40 ? (float)std::log10(q) : -40.0f;
+        f.cab = A == B ? 0.5f : 1.0f;
+        pf[p] = f;
+        if (h.nprim > 0) by_class[class_of(c->sl[A], c->sl[B])].push_back((int32_t)p);
+    }
+    c->ne_list.clear();
+    for (int k = 0; k < 6; ++k) {
+        c->ne_class_off[k] = (int32_t)c->ne_list.size();
+        c->ne_list.insert(c->ne_list.end(), by_class[k].begin(), by_class[k].end());
+    }
+    c->ne_class_off[6] = (int32_t)c->ne_list.size();
+    int rc;
+    if ((rc = upload(c, &c->d_pfeat, pf))) return rc;
+    if ((rc = upload(c, &c->d_pa, pa))) return rc;
+    if ((rc = upload(c, &c->d_pb, pb))) return rc;
+    if ((rc = upload(c, &c->d_ne_list, c->ne_list))) return rc;
+    return SNK_OK;
+}
+
 // Spatial batches (Sec. II.E): per parent atom, recursive bisection on the longest
 // bounding-box axis into pieces of kBatch points (one remainder piece per atom).
 void split_points(const double* xyz, std::vector<int64_t>& idx, size_t lo, size_t hi,
@@ -364,7 +463,35 @@ int build_grid(snk_ctx* c, const snk_grid* g, const double* w)
             if (k < hi - lo) c->col_point[col] = p;
         }
     }
+    std::vector<BatchGeo> geo(c->nbatch);
+    for (int b = 0; b < c->nbatch; ++b) {
+        BatchGeo gb{};
+        double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300}, ctr[3] = {0, 0, 0}, ws = 0.0;
+        const int n = c->batch_npts[b];
+        for (int k = 0; k < n; ++k) {
+            const size_t col = (size_t)b * kBatch + k;
+            const double q[3] = {px[col], py[col], pz[col]};
+            for (int d = 0; d < 3; ++d) {
+                lo[d] = std::min(lo[d], q[d]);
+                hi[d] = std::max(hi[d], q[d]);
+                ctr[d] += q[d];
+            }
+            ws += pw[col];
+        }
+        double hd2 = 0.0;
+        for (int d = 0; d < 3; ++d) {
+            if (n == 0) lo[d] = hi[d] = 0.0;
+            gb.lo[d] = (float)lo[d];
+            gb.hi[d] = (float)hi[d];
+            gb.ctr[d] = (float)(n ? ctr[d] / n : 0.0);
+            hd2 += 0.25 * (hi[d] - lo[d]) * (hi[d] - lo[d]);
+        }
+        gb.hd = (float)std::sqrt(hd2);
+        gb.lw = ws > 1e-40 ? (float)std::log10(ws) : -40.0f;
+        geo[b] = gb;
+    }
     int rc;
+    if ((rc = upload(c, &c->d_geo, geo))) return rc;
     if ((rc = upload(c, &c->d_px, px))) return rc;
     if ((rc = upload(c, &c->d_py, py))) return rc;
     if ((rc = upload(c, &c->d_pz, pz))) return rc;
@@ -376,7 +503,9 @@ int build_grid(snk_ctx* c, const snk_grid* g, const double* w)
 int build_groups(snk_ctx* c)
 {
     c->groups.clear();
-    const int64_t per_batch = (int64_t)(c->nbf + 2 * c->nbf) * kBatch * (int64_t)sizeof(double);
+    // Phi, F and G columns of one batch (Phi and F are FP32 in the mixed build)
+    int64_t per_batch = (int64_t)c->nbf * kBatch * (c->opts.precision == SNK_MIXED ? 16 : 24);
+    if (c->opts.screen == SNK_SCREEN_LEARNED) per_batch += c->npair_total * (int64_t)sizeof(float);
     int64_t budget = c->opts.max_device_bytes;
     if (budget <= 0) {
         size_t fr = 0, tot = 0;
@@ -479,6 +608,72 @@ int build_runs(snk_ctx* c)
     return SNK_OK;
 }
 
+int setup_screening(snk_ctx* c)
+{
+    if (c->d_U) return SNK_OK;   // already set up
+    for (int l = 0; l < 3; ++l) {
+        std::vector<int32_t> sh, row, pb, np;
+        for (int s = 0; s < c->nshell; ++s) {
+            if (c->sl[s] != l) continue;
+            const PairHdr& h = c->pairs[pair_index(s, s)];
+            sh.push_back(s);
+            row.push_back(c->sfn[s]);
+            pb.push_back(h.prim_begin);
+            np.push_back(h.nprim);
+        }
+        c->n_diag[l] = (int32_t)sh.size();
+        int rc;
+        if ((rc = upload(c, &c->d_diag_sh[l], sh))) return rc;
+        if ((rc = upload(c, &c->d_diag_row[l], row))) return rc;
+        if ((rc = upload(c, &c->d_diag_pb[l], pb))) return rc;
+        if ((rc = upload(c, &c->d_diag_np[l], np))) return rc;
+    }
+    int rc;
+    if ((rc = upload(c, &c->d_shell_l, c->sl))) return rc;
+    if ((rc = upload(c, &c->d_shell_row, c->sfn))) return rc;
+    int32_t mb = 0;
+    for (const auto& g : c->groups) mb = std::max(mb, g.b1 - g.b0);
+    c->max_group_batches = mb;
+    if ((rc = dalloc(c, &c->d_U, (size_t)mb * c->nshell))) return rc;
+    if ((rc = dalloc(c, &c->d_N, (size_t)mb * c->nshell))) return rc;
+    if ((rc = dalloc(c, &c->d_lp, (size_t)c->npair_total))) return rc;
+    if (c->opts.screen == SNK_SCREEN_LEARNED) {
+        if ((rc = dalloc(c, &c->d_est, (size_t)mb * c->npair_total))) return rc;
+        if ((rc = dalloc(c, &c->d_thr, (size_t)mb))) return rc;
+    }
+    if ((rc = dalloc(c, &c->d_counts, (size_t)mb * 12))) return rc;
+    if ((rc = dalloc(c, &c->d_npairs, (size_t)mb * 6))) return rc;
+    if ((rc = dalloc(c, &c->d_skipped, (size_t)mb))) return rc;
+    if ((rc = dalloc(c, &c->d_run_base, (size_t)6 * (mb + 1)))) return rc;
+    if ((rc = dalloc(c, &c->d_bt_base, (size_t)6 * (mb + 1)))) return rc;
+    for (int k = 0; k < 6; ++k)
+        if ((rc = dalloc(c, &c->d_bro[k], (size_t)mb + 1))) return rc;
+    return SNK_OK;
+}
+
+// grow the run / B-task pools of class k to hold nrun runs and nbt B tasks
+int ensure_pools(snk_ctx* c, int k, int64_t nrun, int64_t nbt)
+{
+    const int TA = kTileA[k];
+    if (nrun > c->cap_runs[k]) {
+        (void)hipFree(c->d_pool_runs[k]);
+        const int64_t cap = std::max<int64_t>(nrun + nrun / 4, 1024);
+        int rc = dalloc(c, &c->d_pool_runs[k], (size_t)cap * (2 + TA));
+        if (rc) return rc;
+        c->cap_runs[k] = cap;
+    }
+    if (nbt > c->cap_bt[k]) {
+        (void)hipFree(c->d_pool_bt[k]);
+        (void)hipFree(c->d_pool_ab[k]);
+        const int64_t cap = std::max<int64_t>(nbt + nbt / 4, 4096);
+        int rc = dalloc(c, &c->d_pool_bt[k], (size_t)cap * (2 + 2 * TA));
+        if (rc) return rc;
+        if ((rc = dalloc(c, &c->d_pool_ab[k], (size_t)cap * 3 * TA))) return rc;
+        c->cap_bt[k] = cap;
+    }
+    return SNK_OK;
+}
+
 void free_ctx(snk_ctx* c)
 {
     if (!c) return;
@@ -501,6 +696,9 @@ void free_ctx(snk_ctx* c)
         (void)hipFree(g.d_coll_rows);
         (void)hipFree(g.d_coll_fn);
     }
+    (void)hipFree(c->d_Phi32);
+    (void)hipFree(c->d_F32);
+    (void)hipFree(c->d_P32);
     (void)hipFree(c->d_Phi);
     (void)hipFree(c->d_F);
     (void)hipFree(c->d_G);
@@ -514,6 +712,35 @@ void free_ctx(snk_ctx* c)
     (void)hipFree(c->d_boys);
     for (auto& e : c->ev)
         if (e) (void)hipEventDestroy(e);
+    for (int l = 0; l < 3; ++l) {
+        (void)hipFree(c->d_diag_sh[l]);
+        (void)hipFree(c->d_diag_row[l]);
+        (void)hipFree(c->d_diag_pb[l]);
+        (void)hipFree(c->d_diag_np[l]);
+    }
+    (void)hipFree(c->d_shell_l);
+    (void)hipFree(c->d_shell_row);
+    (void)hipFree(c->d_U);
+    (void)hipFree(c->d_N);
+    (void)hipFree(c->d_pfeat);
+    (void)hipFree(c->d_pa);
+    (void)hipFree(c->d_pb);
+    (void)hipFree(c->d_geo);
+    (void)hipFree(c->d_lp);
+    (void)hipFree(c->d_est);
+    (void)hipFree(c->d_thr);
+    (void)hipFree(c->d_ne_list);
+    (void)hipFree(c->d_counts);
+    (void)hipFree(c->d_npairs);
+    (void)hipFree(c->d_skipped);
+    (void)hipFree(c->d_run_base);
+    (void)hipFree(c->d_bt_base);
+    for (int k = 0; k < 6; ++k) {
+        (void)hipFree(c->d_bro[k]);
+        (void)hipFree(c->d_pool_runs[k]);
+        (void)hipFree(c->d_pool_bt[k]);
+        (void)hipFree(c->d_pool_ab[k]);
+    }
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
@@ -581,8 +808,18 @@ int snk_ctx_create(const snk_basis* basis, const snk_grid* grid, const double* w
     if (o.screen < SNK_SCREEN_NONE || o.screen > SNK_SCREEN_LEARNED) return arg_error(nullptr, "unknown screen mode");
     if (o.batch_points < 1 || o.batch_points > kBatch) return arg_error(nullptr, "batch_points outside 1..256");
     if (!isfin(o.eps_basis) || o.eps_basis < 0.0) return arg_error(nullptr, "eps_basis must be >= 0");
-    if (o.precision != SNK_FP64 || o.screen != SNK_SCREEN_NONE || o.eps_basis != 0.0) {
-        set_err(nullptr, "only the plain FP64 path is available in this build");
+    if (o.screen != SNK_SCREEN_NONE && (!isfin(o.eps_skip_energy) || o.eps_skip_energy < 0.0))
+        return arg_error(nullptr, "eps_skip_energy must be finite and >= 0");
+    if (o.screen == SNK_SCREEN_LEARNED) {
+        if (!o.screener) return arg_error(nullptr, "SNK_SCREEN_LEARNED needs a screener network");
+        float lo[16], hi[16], margin;
+        int has_range = 0;
+        mlp_range(o.screener, lo, hi, &margin, &has_range);
+        if (!has_range) return arg_error(nullptr, "screener network has no training range set");
+        if (mlp_device(o.screener) != o.device) return arg_error(nullptr, "screener network is on another device");
+    }
+    if (o.eps_basis != 0.0) {
+        set_err(nullptr, "option not available in this build");
         return SNK_E_UNSUPPORTED;
     }
 
@@ -590,6 +827,7 @@ int snk_ctx_create(const snk_basis* basis, const snk_grid* grid, const double* w
     if (!c) return SNK_E_NOMEM;
     c->opts = o;
     c->device = o.device;
+    c->mixed = o.precision == SNK_MIXED;
     {
         hipError_t e = hipSetDevice(c->device);
         if (e != hipSuccess) {
@@ -650,6 +888,8 @@ int snk_ctx_create(const snk_basis* basis, const snk_grid* grid, const double* w
     build_pairs(c);
     CREATE_CHECK(upload(c, &c->d_pairs, c->pairs));
     CREATE_CHECK(upload(c, &c->d_prims, c->prims));
+    CREATE_CHECK(build_pair_feats(c));
+    c->mlp = o.screen == SNK_SCREEN_LEARNED ? o.screener : nullptr;
     CREATE_CHECK(build_runs(c));
     CREATE_CHECK(build_grid(c, grid, weights));
     CREATE_CHECK(build_groups(c));
@@ -663,8 +903,14 @@ int snk_ctx_create(const snk_basis* basis, const snk_grid* grid, const double* w
         ns = (int)std::min<int64_t>(ns, std::max<int64_t>(1, c->max_cols / kBatch));
         c->nsplit = std::max(1, std::min(ns, 256));
     }
-    CREATE_CHECK(dalloc(c, &c->d_Phi, (size_t)c->max_nB * c->max_cols));
-    CREATE_CHECK(dalloc(c, &c->d_F, (size_t)nbf * c->max_cols));
+    if (c->mixed) {
+        CREATE_CHECK(dalloc(c, &c->d_Phi32, (size_t)c->max_nB * c->max_cols));
+        CREATE_CHECK(dalloc(c, &c->d_F32, (size_t)nbf * c->max_cols));
+        CREATE_CHECK(dalloc(c, &c->d_P32, (size_t)nbf * nbf));
+    } else {
+        CREATE_CHECK(dalloc(c, &c->d_Phi, (size_t)c->max_nB * c->max_cols));
+        CREATE_CHECK(dalloc(c, &c->d_F, (size_t)nbf * c->max_cols));
+    }
     CREATE_CHECK(dalloc(c, &c->d_G, (size_t)nbf * c->max_cols));
     CREATE_CHECK(dalloc(c, &c->d_part, (size_t)c->nsplit * nbf * c->max_nB));
     CREATE_CHECK(dalloc(c, &c->d_Pg, (size_t)nbf * c->max_nB));
@@ -673,6 +919,7 @@ int snk_ctx_create(const snk_basis* basis, const snk_grid* grid, const double* w
     CREATE_CHECK(dalloc(c, &c->d_K, (size_t)nbf * nbf));
     CREATE_CHECK(dalloc(c, &c->d_partial, (size_t)c->nfinish));
     CREATE_CHECK(dalloc(c, &c->d_ex, 1));
+    if (o.screen != SNK_SCREEN_NONE) CREATE_CHECK(setup_screening(c));
 #undef CREATE_CHECK
     *out = c;
     return SNK_OK;
@@ -690,19 +937,37 @@ void snk_ctx_destroy(snk_ctx* ctx)
 
 namespace {
 
-// Steps of one batch group up to G: Eq. collocation, Eq. fmat, Eqs. 3c_grid + gmat.
-int group_until_G(snk_ctx* c, const Group& g, const double* dP, bool timed)
+struct GroupStats {
+    int64_t pp[6] = {0, 0, 0, 0, 0, 0};    // shell-pair x point units evaluated
+    int64_t ppp[6] = {0, 0, 0, 0, 0, 0};   // primitive-pair x point units evaluated
+    int64_t cand = 0;                       // units before density screening
+    double skipped = 0.0;                   // bound on the energy of the skipped blocks
+};
+
+// Steps of one batch group up to G: Eq. collocation, Eq. fmat, the screen (when enabled),
+// Eqs. 3c_grid + gmat.
+// Eq. collocation and Eq. fmat for one batch group: Phi_g, then F_g = P[:, B_g] Phi_g.
+int group_F(snk_ctx* c, const Group& g, const double* dP, bool timed)
 {
     hipStream_t s = c->stream;
     const int64_t nbf = c->nbf;
     const int64_t ld = g.ncols;
     const int64_t off = (int64_t)g.b0 * kBatch;
     if (timed) HIPCHECK(c, hipEventRecord(c->ev[0], s));
+    if (c->mixed) {
+        // FP32 Phi and F; P was rounded to FP32 once per build (d_P32)
+        HIPCHECK(c, launch_collocate(c->d_px + off, c->d_py + off, c->d_pz + off, g.ncols, c->d_shells, c->d_exps,
+                                     c->d_coefs, g.d_coll_shells, g.d_coll_rows, (int32_t)g.coll_shells.size(),
+                                     c->d_Phi32, ld, s));
+        if (timed) HIPCHECK(c, hipEventRecord(c->ev[1], s));
+        HIPCHECK(c, launch_gemm_f32(nbf, g.ncols, g.nB, c->d_P32, nbf, c->d_Phi32, ld, false, c->d_F32, ld, 1, 0, s));
+        if (timed) HIPCHECK(c, hipEventRecord(c->ev[2], s));
+        return SNK_OK;
+    }
     HIPCHECK(c, launch_collocate(c->d_px + off, c->d_py + off, c->d_pz + off, g.ncols, c->d_shells, c->d_exps,
                                  c->d_coefs, g.d_coll_shells, g.d_coll_rows, (int32_t)g.coll_shells.size(), c->d_Phi,
                                  ld, s));
     if (timed) HIPCHECK(c, hipEventRecord(c->ev[1], s));
-    // F_g = P[:, B_g] Phi_g
     const double* Pg = dP;
     int64_t ldp = nbf;
     if (!g.all_functions) {
@@ -712,6 +977,124 @@ int group_until_G(snk_ctx* c, const Group& g, const double* dP, bool timed)
     }
     HIPCHECK(c, launch_gemm_f64(nbf, g.ncols, g.nB, Pg, ldp, c->d_Phi, ld, false, c->d_F, ld, 1, 0, s));
     if (timed) HIPCHECK(c, hipEventRecord(c->ev[2], s));
+    return SNK_OK;
+}
+
+// U (bound factors) and N (F norms) of every shell on every batch of the group
+int group_bounds(snk_ctx* c, const Group& g)
+{
+    const int64_t off = (int64_t)g.b0 * kBatch;
+    for (int l = 0; l < 3; ++l)
+        HIPCHECK(c, launch_diag_bound(l, c->d_px + off, c->d_py + off, c->d_pz + off, c->d_pw + off, c->d_F,
+                                      c->mixed ? c->d_F32 : nullptr, g.ncols,
+                                      c->d_prims, c->d_diag_sh[l], c->d_diag_row[l], c->d_diag_pb[l],
+                                      c->d_diag_np[l], c->n_diag[l], c->d_U, c->d_N, c->nshell, g.b1 - g.b0,
+                                      c->d_boys, c->stream));
+    return SNK_OK;
+}
+
+int group_until_G(snk_ctx* c, const Group& g, const double* dP, bool timed, GroupStats* gs, float* yraw = nullptr)
+{
+    hipStream_t s = c->stream;
+    const int64_t nbf = c->nbf;
+    const int64_t ld = g.ncols;
+    const int64_t off = (int64_t)g.b0 * kBatch;
+    const int nb = g.b1 - g.b0;
+    const bool screen = c->opts.screen != SNK_SCREEN_NONE;
+    {
+        int rc = group_F(c, g, dP, timed);
+        if (rc) return rc;
+    }
+
+    int64_t gpts = 0;
+    std::vector<int64_t> npts(nb);
+    for (int b = g.b0; b < g.b1; ++b) {
+        npts[b - g.b0] = c->batch_npts[b];
+        gpts += c->batch_npts[b];
+    }
+    for (int cl = 0; cl < 6; ++cl) gs->cand += c->ntask[cl] * gpts;
+    int64_t total_runs[6] = {0, 0, 0, 0, 0, 0};
+    if (screen) {
+        if (timed) HIPCHECK(c, hipEventRecord(c->ev[7], s));
+        {
+            int rc = group_bounds(c, g);
+            if (rc) return rc;
+        }
+        const double eps_batch = c->opts.eps_skip_energy / std::max(1, c->nbatch);
+        if (c->mlp) {
+            EstArgs ea{};
+            ea.U = c->d_U;
+            ea.N = c->d_N;
+            ea.nshell = c->nshell;
+            ea.nbatch = nb;
+            ea.shell_l = c->d_shell_l;
+            ea.pairs = c->d_pairs;
+            ea.pfeat = c->d_pfeat;
+            ea.lp = c->d_lp;
+            ea.geo = c->d_geo + g.b0;
+            ea.eps_batch = eps_batch;
+            ea.params = mlp_params(c->mlp);
+            ea.norm = mlp_norm(c->mlp);
+            int hr = 0;
+            mlp_range(c->mlp, ea.lo, ea.hi, &ea.margin, &hr);
+            ea.npair_total = c->npair_total;
+            ea.est = c->d_est;
+            ea.yraw = yraw;
+            ea.thr = c->d_thr;
+            ea.skipped = c->d_skipped;
+            HIPCHECK(c, launch_screen_est(ea, s));
+        }
+        ScreenArgs sa{};
+        sa.U = c->d_U;
+        sa.nshell = c->nshell;
+        sa.nbatch = nb;
+        sa.shell_l = c->d_shell_l;
+        sa.shell_row = c->d_shell_row;
+        sa.pairs = c->d_pairs;
+        sa.eps_batch = eps_batch;
+        sa.est = c->mlp ? c->d_est : nullptr;
+        sa.thr = c->mlp ? c->d_thr : nullptr;
+        sa.npair_total = c->npair_total;
+        sa.counts = c->d_counts;
+        sa.npairs = c->d_npairs;
+        sa.skipped = c->d_skipped;
+        sa.run_base = c->d_run_base;
+        sa.bt_base = c->d_bt_base;
+        HIPCHECK(c, launch_screen(false, sa, s));
+        HIPCHECK(c, launch_screen_scan(c->d_counts, nb, c->d_run_base, c->d_bt_base, s));
+        std::vector<int64_t> rb(6 * (size_t)(nb + 1)), bb(6 * (size_t)(nb + 1)), npair((size_t)nb * 6);
+        std::vector<double> skipped(nb);
+        HIPCHECK(c, hipMemcpyAsync(rb.data(), c->d_run_base, rb.size() * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        HIPCHECK(c, hipMemcpyAsync(bb.data(), c->d_bt_base, bb.size() * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        HIPCHECK(c, hipMemcpyAsync(npair.data(), c->d_npairs, npair.size() * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        HIPCHECK(c, hipMemcpyAsync(skipped.data(), c->d_skipped, skipped.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHECK(c, hipStreamSynchronize(s));
+        for (int cl = 0; cl < 6; ++cl) {
+            total_runs[cl] = rb[(size_t)cl * (nb + 1) + nb];
+            int rc = ensure_pools(c, cl, total_runs[cl], bb[(size_t)cl * (nb + 1) + nb]);
+            if (rc) return rc;
+            sa.runs[cl] = c->d_pool_runs[cl];
+            sa.btasks[cl] = c->d_pool_bt[cl];
+            sa.btask_ab[cl] = c->d_pool_ab[cl];
+            sa.batch_run_off[cl] = c->d_bro[cl];
+            const double avg_prims = c->ntask[cl] ? (double)c->task_prims[cl] / (double)c->ntask[cl] : 0.0;
+            for (int j = 0; j < nb; ++j) {
+                const int64_t u = npair[(size_t)j * 6 + cl] * npts[j];
+                gs->pp[cl] += u;
+                gs->ppp[cl] += (int64_t)(avg_prims * (double)u);
+            }
+        }
+        for (int j = 0; j < nb; ++j) gs->skipped += skipped[j];
+        HIPCHECK(c, launch_screen(true, sa, s));
+        if (timed) HIPCHECK(c, hipEventRecord(c->ev[14], s));
+    } else {
+        for (int cl = 0; cl < 6; ++cl) {
+            gs->pp[cl] += c->ntask[cl] * gpts;
+            gs->ppp[cl] += c->task_prims[cl] * gpts;
+            total_runs[cl] = c->nrun[cl];
+        }
+    }
+
     HIPCHECK(c, launch_fill(c->d_G, nbf * g.ncols, 0.0, s));
     AfgArgs a{};
     a.px = c->d_px + off;
@@ -719,19 +1102,28 @@ int group_until_G(snk_ctx* c, const Group& g, const double* dP, bool timed)
     a.pz = c->d_pz + off;
     a.pw = c->d_pw + off;
     a.F = c->d_F;
+    a.F32 = c->mixed ? c->d_F32 : nullptr;
     a.G = c->d_G;
     a.ld = ld;
     a.pairs = c->d_pairs;
     a.prims = c->d_prims;
-    a.batch_run_off = nullptr;
-    a.nbatch = g.b1 - g.b0;
+    a.nbatch = nb;
     a.boys_tab = c->d_boys;
     for (int cl = 0; cl < 6; ++cl) {
-        if (c->nrun[cl] == 0) continue;
-        a.runs = c->d_runs[cl];
-        a.btasks = c->d_btasks[cl];
-        a.btask_ab = c->d_btask_ab[cl];
-        a.nrun = c->nrun[cl];
+        if (total_runs[cl] == 0) continue;
+        if (screen) {
+            a.runs = c->d_pool_runs[cl];
+            a.btasks = c->d_pool_bt[cl];
+            a.btask_ab = c->d_pool_ab[cl];
+            a.batch_run_off = c->d_bro[cl];
+            a.nrun = 0;
+        } else {
+            a.runs = c->d_runs[cl];
+            a.btasks = c->d_btasks[cl];
+            a.btask_ab = c->d_btask_ab[cl];
+            a.batch_run_off = nullptr;
+            a.nrun = c->nrun[cl];
+        }
         if (timed) HIPCHECK(c, hipEventRecord(c->ev[8 + cl], s));
         HIPCHECK(c, launch_afg(kClassLA[cl], kClassLB[cl], a, s));
         if (timed) HIPCHECK(c, hipEventRecord(c->ev[cl == 5 ? 15 : 9 + cl], s));
@@ -777,26 +1169,28 @@ int snk_ctx_build(snk_ctx* c, const double* P, double* K_out, snk_stats* stats)
         dP = c->d_P;
         dK = c->d_K;
     }
-    double tcol = 0, tf = 0, tafg = 0, tk = 0;
+    double tcol = 0, tf = 0, tafg = 0, tk = 0, tscr = 0;
     double tcls[6] = {0, 0, 0, 0, 0, 0};
-    int64_t pp[6] = {0, 0, 0, 0, 0, 0}, ppp[6] = {0, 0, 0, 0, 0, 0};
+    GroupStats gs;
     const bool timed = stats != nullptr;
 
     HIPCHECK(c, launch_fill(c->d_Kt, (int64_t)nb2, 0.0, s));
+    if (c->mixed) HIPCHECK(c, launch_convert_f32(dP, (int64_t)nb2, c->d_P32, s));
+    if (c->mlp)
+        HIPCHECK(c, launch_pair_pnorm(dP, nbf, c->d_pa, c->d_pb, c->d_shell_l, c->d_shell_row, c->npair_total,
+                                      c->d_lp, s));
     for (const Group& g : c->groups) {
         const int64_t ld = g.ncols;
-        int rc = group_until_G(c, g, dP, timed);
+        int rc = group_until_G(c, g, dP, timed, &gs);
         if (rc) return rc;
-        int64_t gpts = 0;
-        for (int b = g.b0; b < g.b1; ++b) gpts += c->batch_npts[b];
-        for (int cl = 0; cl < 6; ++cl) {
-            pp[cl] += c->ntask[cl] * gpts;
-            ppp[cl] += c->task_prims[cl] * gpts;
-        }
         // Eq. usym_k: Kt[:, B_g] += G_g Phi_g^T, split over grid points
         const int64_t stride = nbf * g.nB;
-        HIPCHECK(c, launch_gemm_f64(nbf, g.nB, g.ncols, c->d_G, ld, c->d_Phi, ld, true, c->d_part, g.nB, c->nsplit,
-                                    stride, s));
+        if (c->mixed)
+            HIPCHECK(c, launch_gemm_f32_dA(nbf, g.nB, g.ncols, c->d_G, ld, c->d_Phi32, ld, true, c->d_part, g.nB,
+                                           c->nsplit, stride, s));
+        else
+            HIPCHECK(c, launch_gemm_f64(nbf, g.nB, g.ncols, c->d_G, ld, c->d_Phi, ld, true, c->d_part, g.nB,
+                                        c->nsplit, stride, s));
         HIPCHECK(c, launch_reduce_scatter(c->d_part, c->nsplit, stride, nbf, g.nB, nullptr,
                                           g.all_functions ? nullptr : g.d_coll_fn, c->d_Kt, nbf, s));
         if (timed) {
@@ -804,9 +1198,14 @@ int snk_ctx_build(snk_ctx* c, const double* P, double* K_out, snk_stats* stats)
             HIPCHECK(c, hipEventSynchronize(c->ev[4]));
             tcol += ev_ms(c->ev[0], c->ev[1]);
             tf += ev_ms(c->ev[1], c->ev[2]);
-            tafg += ev_ms(c->ev[2], c->ev[3]);
+            if (c->opts.screen != SNK_SCREEN_NONE) {
+                tscr += ev_ms(c->ev[7], c->ev[14]);
+                tafg += ev_ms(c->ev[14], c->ev[3]);
+            } else {
+                tafg += ev_ms(c->ev[2], c->ev[3]);
+            }
             for (int cl = 0; cl < 6; ++cl) {
-                if (c->nrun[cl] == 0) continue;
+                if (gs.pp[cl] == 0) continue;
                 tcls[cl] += ev_ms(c->ev[8 + cl], c->ev[cl == 5 ? 15 : 9 + cl]);
             }
             tk += ev_ms(c->ev[3], c->ev[4]);
@@ -834,11 +1233,16 @@ int snk_ctx_build(snk_ctx* c, const double* P, double* K_out, snk_stats* stats)
         stats->t_afg_ms = tafg;
         stats->t_kgemm_ms = tk;
         stats->t_finish_ms = ev_ms(c->ev[5], c->ev[6]);
+        int64_t evaluated = 0;
         for (int k = 0; k < 6; ++k) {
-            stats->pair_points[k] = pp[k];
-            stats->prim_pair_points[k] = ppp[k];
+            stats->pair_points[k] = gs.pp[k];
+            stats->prim_pair_points[k] = gs.ppp[k];
             stats->t_afg_class_ms[k] = tcls[k];
+            evaluated += gs.pp[k];
         }
+        stats->t_screen_ms = tscr;
+        stats->pair_points_skipped = gs.cand - evaluated;
+        stats->skipped_bound = gs.skipped;
         stats->n_batches = c->nbatch;
         stats->n_groups = (int32_t)c->groups.size();
     }
@@ -895,6 +1299,7 @@ int snk_ctx_point_order(const snk_ctx* c, int64_t* col_to_point)
 int snk_ctx_debug_intermediates(snk_ctx* c, const double* P, double* Phi, double* F, double* G, int64_t* ncols_out)
 {
     if (!c || !P) return arg_error(c, "NULL argument");
+    if (c->mixed) return arg_error(c, "intermediates are available from FP64 contexts only");
     if (c->groups.empty()) {
         if (ncols_out) *ncols_out = 0;
         return SNK_OK;
@@ -903,7 +1308,8 @@ int snk_ctx_debug_intermediates(snk_ctx* c, const double* P, double* Phi, double
     const int64_t nbf = c->nbf;
     HIPCHECK(c, hipSetDevice(c->device));
     HIPCHECK(c, hipMemcpyAsync(c->d_P, P, (size_t)nbf * nbf * sizeof(double), hipMemcpyHostToDevice, c->stream));
-    int rc = group_until_G(c, g, c->d_P, false);
+    GroupStats gs;
+    int rc = group_until_G(c, g, c->d_P, false, &gs);
     if (rc) return rc;
     const size_t n = (size_t)nbf * g.ncols * sizeof(double);
     if (Phi) HIPCHECK(c, hipMemcpyAsync(Phi, c->d_Phi, (size_t)g.nB * g.ncols * sizeof(double), hipMemcpyDeviceToHost, c->stream));
@@ -911,6 +1317,120 @@ int snk_ctx_debug_intermediates(snk_ctx* c, const double* P, double* Phi, double
     if (G) HIPCHECK(c, hipMemcpyAsync(G, c->d_G, n, hipMemcpyDeviceToHost, c->stream));
     HIPCHECK(c, hipStreamSynchronize(c->stream));
     if (ncols_out) *ncols_out = g.ncols;
+    return SNK_OK;
+}
+
+int64_t snk_ctx_nblock_pairs(const snk_ctx* c) { return c ? (int64_t)c->ne_list.size() : 0; }
+
+int snk_ctx_block_data(snk_ctx* c, const double* P, float* features, double* block_energy, int32_t* pair_shells)
+{
+    if (!c || !P) return arg_error(c, "NULL context or density");
+    if (!features && !block_energy && !pair_shells) return SNK_OK;
+    const int64_t nbf = c->nbf;
+    const int64_t ldk = (int64_t)c->ne_list.size();
+    if (pair_shells)
+        for (int64_t k = 0; k < ldk; ++k) {
+            pair_shells[2 * k] = c->pair_a[c->ne_list[k]];
+            pair_shells[2 * k + 1] = c->pair_b[c->ne_list[k]];
+        }
+    if (!features && !block_energy) return SNK_OK;
+    HIPCHECK(c, hipSetDevice(c->device));
+    int rc = setup_screening(c);
+    if (rc) return rc;
+    hipStream_t s = c->stream;
+    const double* dP = P;
+    if (!(c->opts.flags & SNK_DEVICE_PTRS)) {
+        HIPCHECK(c, hipMemcpyAsync(c->d_P, P, (size_t)nbf * nbf * sizeof(double), hipMemcpyHostToDevice, s));
+        dP = c->d_P;
+    }
+    HIPCHECK(c, launch_pair_pnorm(dP, nbf, c->d_pa, c->d_pb, c->d_shell_l, c->d_shell_row, c->npair_total, c->d_lp, s));
+    if (c->mixed) HIPCHECK(c, launch_convert_f32(dP, nbf * nbf, c->d_P32, s));
+    for (const Group& g : c->groups) {
+        if ((rc = group_F(c, g, dP, false))) return rc;
+        if ((rc = group_bounds(c, g))) return rc;
+        const int nb = g.b1 - g.b0;
+        if (features)
+            HIPCHECK(c, launch_block_features(c->d_ne_list, c->d_pa, c->d_pb, (int32_t)ldk, c->d_pfeat, c->d_lp,
+                                              c->d_geo + g.b0, c->d_U, c->d_N, c->nshell, nb,
+                                              features + (int64_t)g.b0 * ldk * 16, ldk, s));
+        if (block_energy) {
+            const int64_t off = (int64_t)g.b0 * kBatch;
+            for (int cl = 0; cl < 6; ++cl) {
+                const int n = c->ne_class_off[cl + 1] - c->ne_class_off[cl];
+                if (n == 0) continue;
+                HIPCHECK(c, launch_block_energy(kClassLA[cl], kClassLB[cl], c->d_px + off, c->d_py + off,
+                                                c->d_pz + off, c->d_pw + off, c->d_F,
+                                                c->mixed ? c->d_F32 : nullptr, g.ncols, c->d_pairs,
+                                                c->d_prims, c->d_pfeat, c->d_ne_list + c->ne_class_off[cl], n, nb,
+                                                block_energy + (int64_t)g.b0 * ldk + c->ne_class_off[cl], ldk,
+                                                c->d_boys, s));
+            }
+        }
+    }
+    HIPCHECK(c, hipStreamSynchronize(s));
+    return SNK_OK;
+}
+
+int snk_ctx_debug_learned(snk_ctx* c, const double* P, float* yraw, float* est, int32_t* thr, int64_t* nbatch_out)
+{
+    if (!c || !P) return arg_error(c, "NULL argument");
+    if (!c->mlp) return arg_error(c, "context was not created with SNK_SCREEN_LEARNED");
+    if (c->groups.empty()) {
+        if (nbatch_out) *nbatch_out = 0;
+        return SNK_OK;
+    }
+    const Group& g = c->groups[0];
+    const int64_t nbf = c->nbf;
+    const int nb = g.b1 - g.b0;
+    const size_t n = (size_t)nb * c->npair_total;
+    HIPCHECK(c, hipSetDevice(c->device));
+    hipStream_t s = c->stream;
+    HIPCHECK(c, hipMemcpyAsync(c->d_P, P, (size_t)nbf * nbf * sizeof(double), hipMemcpyHostToDevice, s));
+    float* d_y = nullptr;
+    int rc = dalloc(c, &d_y, n);
+    if (rc) return rc;
+    // non-candidate blocks keep NaN
+    std::vector<float> nanv(n, std::nanf(""));
+    HIPCHECK(c, hipMemcpyAsync(d_y, nanv.data(), n * sizeof(float), hipMemcpyHostToDevice, s));
+    HIPCHECK(c, hipMemcpyAsync(c->d_est, nanv.data(), n * sizeof(float), hipMemcpyHostToDevice, s));
+    HIPCHECK(c, launch_pair_pnorm(c->d_P, nbf, c->d_pa, c->d_pb, c->d_shell_l, c->d_shell_row, c->npair_total,
+                                  c->d_lp, s));
+    if (c->mixed) HIPCHECK(c, launch_convert_f32(c->d_P, nbf * nbf, c->d_P32, s));
+    GroupStats gs;
+    rc = group_until_G(c, g, c->d_P, false, &gs, d_y);
+    if (!rc) {
+        hipError_t e = hipSuccess;
+        if (yraw) e = hipMemcpyAsync(yraw, d_y, n * sizeof(float), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess && est) e = hipMemcpyAsync(est, c->d_est, n * sizeof(float), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess && thr) e = hipMemcpyAsync(thr, c->d_thr, nb * sizeof(int32_t), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            set_err(c, std::string("debug copy: ") + hipGetErrorString(e));
+            rc = SNK_E_DEVICE;
+        }
+    }
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(d_y);
+    if (!rc && nbatch_out) *nbatch_out = nb;
+    return rc;
+}
+
+int64_t snk_ctx_npair_index(const snk_ctx* c) { return c ? c->npair_total : 0; }
+
+int snk_debug_mfma_bf16(const float* A, const float* B, float* D)
+{
+    if (!A || !B || !D) return arg_error(nullptr, "NULL argument");
+    float* d = nullptr;
+    if (hipMalloc((void**)&d, 3 * 256 * sizeof(float)) != hipSuccess) return SNK_E_NOMEM;
+    hipError_t e = hipMemcpy(d, A, 256 * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d + 256, B, 256 * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = launch_mfma_bf16_probe(d, d + 256, d + 512, nullptr);
+    if (e == hipSuccess) e = hipMemcpy(D, d + 512, 256 * sizeof(float), hipMemcpyDeviceToHost);
+    (void)hipFree(d);
+    if (e != hipSuccess) {
+        g_last_error = hipGetErrorString(e);
+        return SNK_E_DEVICE;
+    }
     return SNK_OK;
 }
 

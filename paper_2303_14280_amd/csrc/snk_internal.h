@@ -56,12 +56,21 @@ struct ShellDev {
 constexpr int kMaxTile = 8;
 constexpr int kTileA[6] = {4, 2, 2, 1, 1, 1};   // ss, ps, pp, ds, dp, dd
 
+// class c = ss, ps, pp, ds, dp, dd: (l_A, l_B) and A-tile size, usable in device code
+__host__ __device__ constexpr int kClassLA_dev(int c) { return c == 0 ? 0 : (c < 3 ? 1 : 2); }
+__host__ __device__ constexpr int kClassLB_dev(int c) { return (c == 0 || c == 1 || c == 3) ? 0 : ((c == 2 || c == 4) ? 1 : 2); }
+__host__ __device__ constexpr int kTileA_dev(int c)
+{
+    return c == 0 ? kTileA[0] : c == 1 ? kTileA[1] : c == 2 ? kTileA[2] : c == 3 ? kTileA[3] : c == 4 ? kTileA[4] : kTileA[5];
+}
+
 struct AfgArgs {
     const double* px;
     const double* py;
     const double* pz;
     const double* pw;
     const double* F;        // [rows][ld]
+    const float* F32;       // FP32 F of the mixed-precision build (used instead of F when set)
     double* G;              // [rows][ld]
     int64_t ld;
     const PairHdr* pairs;
@@ -75,17 +84,141 @@ struct AfgArgs {
     const double* boys_tab;
 };
 
+// Density-dependent screening (rigorous bound) of one batch group.
+struct ScreenArgs {
+    const double* U;            // [nbatch][nshell] block-bound factors
+    int32_t nshell;
+    int32_t nbatch;
+    const int32_t* shell_l;     // [nshell]
+    const int32_t* shell_row;   // [nshell] first row of the shell in F/G
+    const PairHdr* pairs;       // unique pairs, index s(s+1)/2 + t for s >= t
+    double eps_batch;           // energy budget of the skipped blocks of one batch
+    int32_t* counts;            // [nbatch][6][2]: runs, B tasks
+    int64_t* npairs;            // [nbatch][6]: shell pairs kept
+    double* skipped;            // [nbatch]: bound on the skipped energy
+    const int64_t* run_base;    // [6][nbatch+1]
+    const int64_t* bt_base;     // [6][nbatch+1]
+    int32_t* runs[6];
+    int32_t* btasks[6];
+    double* btask_ab[6];
+    int32_t* batch_run_off[6];  // [nbatch+1]
+    const float* est;           // learned screen: [nbatch][npair_total] log2 block estimate, or nullptr
+    const int32_t* thr;         // learned screen: [nbatch] first kept estimate bin
+    int64_t npair_total;
+};
+
+// block-energy histograms of the screens: bin = floor(2 log2 e) + kBinOff, clamped to [0, kNBins)
+constexpr int kBinOff = 400;
+constexpr int kNBins = 512;
+
+// learned screener network 16 -> 64 -> 64 -> 1
+constexpr int kMlpIn = 16;
+constexpr int kMlpParams = 64 * 16 + 64 + 64 * 64 + 64 + 64 + 1;   // 5313
+struct MlpNorm {
+    float mean[16];
+    float inv_std[16];
+};
+
+// Static data of one shell pair used by the learned screener's features (indexed like PairHdr).
+struct PairFeat {
+    float a[3], b[3];    // centres of shells A and B
+    float pc[3];         // centre of the most diffuse primitive pair
+    float la, lb;        // angular momenta
+    float lzA, lzB;      // log10 of the smallest exponent of A and of B
+    float ab;            // |AB|
+    float lq;            // log10 sum over kept primitive pairs of |prefactor| (-40 if none)
+    float cab;           // 1 for A != B (the block and its transpose), 1/2 for A == B
+};
+
+// Static data of one grid batch (valid points only).
+struct BatchGeo {
+    float lo[3], hi[3];  // bounding box
+    float ctr[3];        // centroid
+    float hd;            // half diagonal of the box
+    float lw;            // log10 of the weight sum (-40 if zero)
+    float pad;
+};
+
+// Learned estimate pass of one batch group: per batch, every candidate block (pairs the
+// rigorous bound does not already skip) gets est = min(bound, 10^(y + margin)) from the
+// network (the bound alone when a feature lies outside the training range), stored as
+// log2(est) in est[batch][pair index]; the batch's skip threshold bin goes to thr[batch].
+struct EstArgs {
+    const double* U;            // [nbatch][nshell] bound factors
+    const double* N;            // [nbatch][nshell] F norms sqrt(sum_i w_i |F_A,i|^2)
+    int32_t nshell;
+    int32_t nbatch;
+    const int32_t* shell_l;
+    const PairHdr* pairs;
+    const PairFeat* pfeat;      // per pair index
+    const float* lp;            // per pair index: log10 of the Frobenius norm of the P block
+    const BatchGeo* geo;        // [nbatch] of this group
+    double eps_batch;
+    const float* params;        // network parameters (FP32; rounded to bf16 on load)
+    MlpNorm norm;
+    float lo[16], hi[16];       // training range of the raw features
+    float margin;               // log10 units added to every prediction
+    int64_t npair_total;        // pair index space nshell (nshell + 1) / 2
+    float* est;                 // [nbatch][npair_total] log2 of the block estimate
+    float* yraw;                // optional [nbatch][npair_total] raw network output
+    int32_t* thr;               // [nbatch] first kept bin of the learned estimate
+    double* skipped;            // [nbatch] estimated energy of the skipped blocks
+};
+
 // launchers (return hipError_t of the launch)
+hipError_t launch_mlp_forward(const float* params, const MlpNorm& nrm, const float* x, int64_t n, float* y, bool bf16,
+                              hipStream_t s);
+int64_t mlp_grad_blocks(int64_t n);
+hipError_t launch_mlp_grad(const float* params, const MlpNorm& nrm, const float* x, const float* target, int64_t n,
+                           float under, float* part, float* grads, hipStream_t s);
+hipError_t launch_mlp_adam(float* params, float* m, float* v, const float* g, float lr, int t, hipStream_t s);
+hipError_t launch_diag_bound(int l, const double* px, const double* py, const double* pz, const double* pw,
+                             const double* F, const float* F32, int64_t ld, const PrimPair* prims, const int32_t* dsh,
+                             const int32_t* drow, const int32_t* dpb, const int32_t* dnp, int32_t n, double* U,
+                             double* N, int32_t nshell, int32_t nbatch, const double* tab, hipStream_t s);
+hipError_t launch_screen(bool write, const ScreenArgs& a, hipStream_t s);
+hipError_t launch_screen_est(const EstArgs& a, hipStream_t s);
+// lp[p] = log10 ||P_AB|| over all pair indices p (shells A >= B in index order)
+hipError_t launch_pair_pnorm(const double* P, int64_t nbf, const int32_t* pa, const int32_t* pb,
+                             const int32_t* shell_l, const int32_t* shell_row, int64_t npair, float* lp,
+                             hipStream_t s);
+// training data: features [b][k][16] and exact block energies t[b][k] of the listed pairs
+hipError_t launch_block_features(const int32_t* plist, const int32_t* pa, const int32_t* pb, int32_t n,
+                                 const PairFeat* pfeat, const float* lp, const BatchGeo* geo, const double* U,
+                                 const double* N, int32_t nshell, int32_t nbatch, float* feat, int64_t ldk,
+                                 hipStream_t s);
+hipError_t launch_block_energy(int la, int lb, const double* px, const double* py, const double* pz, const double* pw,
+                               const double* F, const float* F32, int64_t ld, const PairHdr* pairs, const PrimPair* prims,
+                               const PairFeat* pfeat, const int32_t* plist, int32_t n, int32_t nbatch, double* t,
+                               int64_t ldk, const double* tab, hipStream_t s);
+// D = A B for 16 x 16 row-major A, B (bf16-exact FP32 values) through one bf16 matrix-core op
+hipError_t launch_mfma_bf16_probe(const float* A, const float* B, float* D, hipStream_t s);
+hipError_t launch_screen_scan(const int32_t* counts, int32_t nbatch, int64_t* run_base, int64_t* bt_base,
+                              hipStream_t s);
 hipError_t launch_afg(int la, int lb, const AfgArgs& a, hipStream_t s);
 hipError_t launch_collocate(const double* px, const double* py, const double* pz, int64_t ncols,
                             const ShellDev* shells, const double* exps, const double* coefs,
                             const int32_t* shell_list, const int32_t* shell_row, int32_t nsh,
                             double* Phi, int64_t ld, hipStream_t s);
+hipError_t launch_collocate(const double* px, const double* py, const double* pz, int64_t ncols,
+                            const ShellDev* shells, const double* exps, const double* coefs,
+                            const int32_t* shell_list, const int32_t* shell_row, int32_t nsh,
+                            float* Phi, int64_t ld, hipStream_t s);
 // C[M x N] = A[M x K] * op(B); A row-major (lda); B row-major K x N (ldb) or, with bt, N x K.
 // With nsplit > 1 the K range is cut into nsplit chunks and chunk z writes C + z * split_stride.
 hipError_t launch_gemm_f64(int64_t M, int64_t N, int64_t K, const double* A, int64_t lda, const double* B,
                            int64_t ldb, bool bt, double* C, int64_t ldc, int nsplit, int64_t split_stride,
                            hipStream_t s);
+// FP32 matrix-core forms: operands rounded to FP32, FP32 accumulation over at most 1024
+// consecutive k, FP64 accumulation across those runs.  The _dA form takes FP64 A and writes
+// FP64 C (the K~ partials of the mixed build).
+hipError_t launch_gemm_f32(int64_t M, int64_t N, int64_t K, const float* A, int64_t lda, const float* B,
+                           int64_t ldb, bool bt, float* C, int64_t ldc, int nsplit, int64_t split_stride,
+                           hipStream_t s);
+hipError_t launch_gemm_f32_dA(int64_t M, int64_t N, int64_t K, const double* A, int64_t lda, const float* B,
+                              int64_t ldb, bool bt, double* C, int64_t ldc, int nsplit, int64_t split_stride,
+                              hipStream_t s);
+hipError_t launch_convert_f32(const double* in, int64_t n, float* out, hipStream_t s);
 // Kt[rows[m] * nbf + cols[n]] += sum_z part[z * stride + m * N + n]
 hipError_t launch_reduce_scatter(const double* part, int nsplit, int64_t stride, int64_t M, int64_t N,
                                  const int32_t* rows, const int32_t* cols, double* Kt, int64_t nbf, hipStream_t s);

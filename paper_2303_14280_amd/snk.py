@@ -119,6 +119,40 @@ def lib():
             L.snk_ctx_point_order.restype = ctypes.c_int
             L.snk_ctx_debug_intermediates.argtypes = [ctypes.c_void_p] * 5 + [ctypes.POINTER(ctypes.c_int64)]
             L.snk_ctx_debug_intermediates.restype = ctypes.c_int
+            L.snk_ctx_nblock_pairs.argtypes = [ctypes.c_void_p]
+            L.snk_ctx_nblock_pairs.restype = ctypes.c_int64
+            L.snk_ctx_block_data.argtypes = [ctypes.c_void_p] * 5
+            L.snk_ctx_block_data.restype = ctypes.c_int
+            L.snk_ctx_npair_index.argtypes = [ctypes.c_void_p]
+            L.snk_ctx_npair_index.restype = ctypes.c_int64
+            L.snk_ctx_debug_learned.argtypes = [ctypes.c_void_p] * 5 + [ctypes.POINTER(ctypes.c_int64)]
+            L.snk_ctx_debug_learned.restype = ctypes.c_int
+            L.snk_debug_mfma_bf16.argtypes = [ctypes.c_void_p] * 3
+            L.snk_debug_mfma_bf16.restype = ctypes.c_int
+            _F = ctypes.POINTER(ctypes.c_float)
+            L.snk_mlp_nparams.argtypes = []
+            L.snk_mlp_nparams.restype = ctypes.c_int
+            L.snk_mlp_create.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)]
+            L.snk_mlp_create.restype = ctypes.c_int
+            L.snk_mlp_destroy.argtypes = [ctypes.c_void_p]
+            L.snk_mlp_destroy.restype = None
+            L.snk_mlp_set_params.argtypes = [ctypes.c_void_p, _F]
+            L.snk_mlp_set_params.restype = ctypes.c_int
+            L.snk_mlp_get_params.argtypes = [ctypes.c_void_p, _F]
+            L.snk_mlp_get_params.restype = ctypes.c_int
+            L.snk_mlp_set_normalisation.argtypes = [ctypes.c_void_p, _F, _F]
+            L.snk_mlp_set_normalisation.restype = ctypes.c_int
+            L.snk_mlp_set_range.argtypes = [ctypes.c_void_p, _F, _F, ctypes.c_float]
+            L.snk_mlp_set_range.restype = ctypes.c_int
+            L.snk_mlp_forward.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                          ctypes.c_int, ctypes.c_void_p]
+            L.snk_mlp_forward.restype = ctypes.c_int
+            L.snk_mlp_loss_grad.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                            ctypes.c_float, ctypes.c_void_p, ctypes.c_void_p]
+            L.snk_mlp_loss_grad.restype = ctypes.c_int
+            L.snk_mlp_adam_step.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_float, ctypes.c_int,
+                                            ctypes.c_void_p]
+            L.snk_mlp_adam_step.restype = ctypes.c_int
             _lib = L
     return _lib
 
@@ -139,6 +173,8 @@ def default_opts(**kw) -> SnkOpts:
     for k, v in kw.items():
         if not hasattr(o, k):
             raise KeyError(k)
+        if k == "screener" and hasattr(v, "handle"):
+            v = v.handle
         setattr(o, k, v)
     return o
 
@@ -189,6 +225,7 @@ class Context:
 
     def __init__(self, s, xyz=None, w=None, atom=None, use_atoms=True, **opts):
         self._m = _Marshal(s, xyz, w, atom, use_atoms)
+        self._screener = opts.get("screener")   # keeps the network alive while the context uses it
         self.opts = default_opts(**opts)
         self.device_ptrs = bool(self.opts.flags & SNK_DEVICE_PTRS)
         h = ctypes.c_void_p()
@@ -239,6 +276,44 @@ class Context:
                                                  G.ctypes.data, ctypes.byref(n)), self.handle)
         return Phi, F, G
 
+    @property
+    def nblock_pairs(self) -> int:
+        return int(lib().snk_ctx_nblock_pairs(self.handle))
+
+    @property
+    def npair_index(self) -> int:
+        return int(lib().snk_ctx_npair_index(self.handle))
+
+    def block_data(self, P, features_ptr: int = 0, energy_ptr: int = 0) -> np.ndarray:
+        """Training data of the learned screener (device outputs, see snk_ctx_block_data).
+
+        P is a host array, or a device pointer for device-pointer contexts.  Returns the
+        (A, B) shells of every listed pair."""
+        if self.device_ptrs:
+            pp = ctypes.c_void_p(int(P))
+        else:
+            P = np.ascontiguousarray(P, np.float64)
+            pp = ctypes.c_void_p(P.ctypes.data)
+        shells = np.zeros((self.nblock_pairs, 2), np.int32)
+        _check(lib().snk_ctx_block_data(self.handle, pp, ctypes.c_void_p(features_ptr) if features_ptr else None,
+                                        ctypes.c_void_p(energy_ptr) if energy_ptr else None,
+                                        ctypes.c_void_p(shells.ctypes.data)), self.handle)
+        return shells
+
+    def debug_learned(self, P: np.ndarray):
+        """(yraw, log2 est, thr) of the first batch group's learned screen, [batches][pair index]."""
+        P = np.ascontiguousarray(P, np.float64)
+        n = ctypes.c_int64(0)
+        npi = self.npair_index
+        nb = self.nbatches
+        y = np.zeros(nb * npi, np.float32)
+        e = np.zeros(nb * npi, np.float32)
+        t = np.zeros(nb, np.int32)
+        _check(lib().snk_ctx_debug_learned(self.handle, P.ctypes.data, y.ctypes.data, e.ctypes.data, t.ctypes.data,
+                                           ctypes.byref(n)), self.handle)
+        k = n.value
+        return y[:k * npi].reshape(k, npi), e[:k * npi].reshape(k, npi), t[:k]
+
     def close(self):
         if getattr(self, "handle", None):
             lib().snk_ctx_destroy(self.handle)
@@ -266,3 +341,96 @@ def debug_mfma_layout() -> np.ndarray:
     out = np.zeros(256)
     _check(lib().snk_debug_mfma_layout(out.ctypes.data))
     return out
+
+
+def _f32(a, n=None) -> np.ndarray:
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    if n is not None and a.size != n:
+        raise ValueError("expected %d values, got %d" % (n, a.size))
+    return a
+
+
+def _fptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+class Mlp:
+    """The learned block screener's network on one device (FP32 parameters in device memory).
+
+    forward / loss_grad / adam_step take device pointers (e.g. ``tensor.data_ptr()``)."""
+
+    def __init__(self, device: int = 0):
+        self.nparams = int(lib().snk_mlp_nparams())
+        h = ctypes.c_void_p()
+        _check(lib().snk_mlp_create(int(device), ctypes.byref(h)))
+        self._h = h
+        self.device = int(device)
+
+    @property
+    def handle(self) -> int:
+        return self._h.value or 0
+
+    def set_params(self, flat) -> None:
+        a = _f32(flat, self.nparams)
+        _check(lib().snk_mlp_set_params(self._h, _fptr(a)))
+
+    def get_params(self) -> np.ndarray:
+        a = np.zeros(self.nparams, np.float32)
+        _check(lib().snk_mlp_get_params(self._h, _fptr(a)))
+        return a
+
+    def set_normalisation(self, mean, std) -> None:
+        m, s = _f32(mean, 16), _f32(std, 16)
+        _check(lib().snk_mlp_set_normalisation(self._h, _fptr(m), _fptr(s)))
+
+    def set_range(self, lo, hi, margin: float) -> None:
+        a, b = _f32(lo, 16), _f32(hi, 16)
+        _check(lib().snk_mlp_set_range(self._h, _fptr(a), _fptr(b), float(margin)))
+
+    def forward(self, x_ptr: int, n: int, y_ptr: int, bf16: bool = False, stream: int = 0) -> None:
+        _check(lib().snk_mlp_forward(self._h, ctypes.c_void_p(x_ptr), int(n), ctypes.c_void_p(y_ptr), int(bf16),
+                                     ctypes.c_void_p(stream) if stream else None))
+
+    def loss_grad(self, x_ptr: int, t_ptr: int, n: int, g_ptr: int, under: float = 10.0, stream: int = 0) -> None:
+        _check(lib().snk_mlp_loss_grad(self._h, ctypes.c_void_p(x_ptr), ctypes.c_void_p(t_ptr), int(n),
+                                       float(under), ctypes.c_void_p(g_ptr),
+                                       ctypes.c_void_p(stream) if stream else None))
+
+    def adam_step(self, g_ptr: int, lr: float, t: int, stream: int = 0) -> None:
+        _check(lib().snk_mlp_adam_step(self._h, ctypes.c_void_p(g_ptr), float(lr), int(t),
+                                       ctypes.c_void_p(stream) if stream else None))
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().snk_mlp_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def debug_mfma_bf16(A: np.ndarray, B: np.ndarray) -> np.ndarray:
+    """A @ B (16 x 16) through one bf16 matrix-core op."""
+    A = np.ascontiguousarray(A, np.float32)
+    B = np.ascontiguousarray(B, np.float32)
+    D = np.zeros((16, 16), np.float32)
+    _check(lib().snk_debug_mfma_bf16(A.ctypes.data, B.ctypes.data, D.ctypes.data))
+    return D
+
+
+SCREENER_WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "screener_weights.npz")
+
+
+def load_screener(path: Optional[str] = None, device: int = 0) -> Mlp:
+    """The trained block screener (parameters, feature normalisation, training range and
+    margin as written by train_screener) on `device`."""
+    d = np.load(path or SCREENER_WEIGHTS, allow_pickle=False)
+    m = Mlp(device)
+    m.set_params(d["params"])
+    m.set_normalisation(d["mean"], d["std"])
+    m.set_range(d["lo"], d["hi"], float(d["margin"]))
+    m.info = str(d["info"]) if "info" in d else ""
+    return m

@@ -29,6 +29,8 @@ ANGSTROM = 1.0 / 0.529177210903  # bohr per angstrom
 Z_O, Z_H = 8, 1
 
 # Per-config recipe.
+BASIS_SEED = {"sp": 1, "spd": 2}
+
 CONFIGS: Dict[int, dict] = {
     1: dict(n_triads=2, extra=None, box=None, basis="sp", grid=(50, 110), density="delocalised"),
     2: dict(n_triads=10, extra=None, box=9.0, basis="spd", grid=(75, 302), density="delocalised"),
@@ -155,10 +157,12 @@ def _unit(rng: np.random.Generator) -> np.ndarray:
     return v / np.linalg.norm(v)
 
 
-def make_geometry(config_id: int) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
-    """Atoms (Z, xyz in bohr, molecule index) of a seeded water-like cluster."""
+def make_geometry(config_id: int, variant: int = 0) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """Atoms (Z, xyz in bohr, molecule index) of a seeded water-like cluster.
+
+    ``variant`` > 0 draws another cluster of the same recipe (other seed)."""
     cfg = CONFIGS[config_id]
-    rng = np.random.default_rng([config_id, 0])
+    rng = np.random.default_rng([config_id, 0] + ([variant] if variant else []))
     n_tri = cfg["n_triads"]
     if cfg["box"] is None:
         # two triads with O-O = 3.0 A along a random direction
@@ -439,11 +443,15 @@ def n_occupied(atom_Z: np.ndarray) -> int:
 
 
 def make_system(config_id: int, density: Optional[str] = None, grid: Optional[Tuple[int, int]] = None,
-                with_density: bool = True) -> System:
-    """Seeded system for config 1..5 (see ``CONFIGS``)."""
+                with_density: bool = True, variant: int = 0) -> System:
+    """Seeded system for config 1..5 (see ``CONFIGS``).
+
+    ``variant`` > 0 gives another geometry and density of the same recipe; the element
+    basis sets stay those of the config (as a fixed basis-set library would)."""
     cfg = CONFIGS[config_id]
-    Z, xyz, mol = make_geometry(config_id)
-    per_el = make_element_basis(cfg["basis"], np.random.default_rng([config_id, 1]))
+    Z, xyz, mol = make_geometry(config_id, variant)
+    # one element basis library per shell set: every "spd" config shares the one drawn for config 2
+    per_el = make_element_basis(cfg["basis"], np.random.default_rng([BASIS_SEED[cfg["basis"]], 1]))
     cen, ls, npr, off, sat, ex, co = assemble_basis(Z, xyz, per_el)
     n_rad, n_ang = grid if grid is not None else cfg["grid"]
     gx, gw, ga = make_grid(xyz, n_rad, n_ang)
@@ -451,7 +459,7 @@ def make_system(config_id: int, density: Optional[str] = None, grid: Optional[Tu
     sys = System(config_id, Z, xyz, mol, cen, ls, npr, off, sat, ex, co, gx, gw, ga,
                  np.zeros((0, 0)), n_occupied(Z), kind)
     if with_density:
-        sys = sys.with_density(make_density(sys, sys.n_occ, kind, [config_id, 2]))
+        sys = sys.with_density(make_density(sys, sys.n_occ, kind, [config_id, 2] + ([variant] if variant else [])))
     return sys
 
 

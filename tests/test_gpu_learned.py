@@ -1,0 +1,235 @@
+"""Learned block screener on the GPU: the bf16 matrix-core layout its inference relies on,
+the training data (features and exact block energies) against the oracle's integrals, the
+in-screen inference against the standalone network kernel, and the screen's behaviour."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import mlp_ref
+from oracle import oracle as O
+from paper_2303_14280_amd import snk, synth
+
+pytestmark = pytest.mark.gpu
+SQ3 = np.sqrt(3.0)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def soft_spd(grid=(10, 26)):
+    xyz = [[0.0, 0.0, 0.0], [1.3, 0.4, -0.2], [-0.5, 1.1, 0.7]]
+    shells = [
+        [(0, [2.1, 0.6], [0.5, 0.6]), (1, [1.4, 0.45], [0.7, 0.4]), (2, [0.9], [1.0])],
+        [(0, [1.7, 0.5], [0.4, 0.7]), (1, [0.8], [1.0])],
+        [(0, [1.1], [1.0]), (2, [1.3, 0.5], [0.5, 0.5]), (1, [30.0, 3.0, 0.3], [0.3, 0.5, 0.4])],
+    ]
+    return synth.make_custom([8, 1, 1], xyz, shells, grid=grid, n_occ=3)
+
+
+def cnorm(l):
+    return np.array([1.0, SQ3, SQ3, 1.0, SQ3, 1.0]) if l == 2 else np.ones((l + 1) * (l + 2) // 2)
+
+
+def pair_index(a, b):
+    a, b = max(a, b), min(a, b)
+    return a * (a + 1) // 2 + b
+
+
+def test_mfma_bf16_layout():
+    rng = np.random.default_rng(0)
+    A = rng.integers(-8, 9, size=(16, 16)).astype(np.float32)
+    B = rng.integers(-8, 9, size=(16, 16)).astype(np.float32)
+    D = snk.debug_mfma_bf16(A, B)
+    assert np.array_equal(D, A @ B)
+
+
+def _block_data(s, ctx):
+    import torch
+    nk, nb = ctx.nblock_pairs, ctx.nbatches
+    feat = torch.empty(nb * nk * 16, dtype=torch.float32, device="cuda")
+    t = torch.empty(nb * nk, dtype=torch.float64, device="cuda")
+    shells = ctx.block_data(s.P, feat.data_ptr(), t.data_ptr())
+    torch.cuda.synchronize()
+    return shells, feat.cpu().numpy().reshape(nb, nk, 16), t.cpu().numpy().reshape(nb, nk)
+
+
+def test_block_data_matches_oracle_integrals():
+    """t_AB = c_AB sum_i w_i |F_A,i^T A_AB(r_i) F_B,i| from the oracle's collocation and
+    three-centre integrals, and every feature recomputed from its definition."""
+    s = soft_spd()
+    ctx = snk.Context(s, screen=snk.SNK_SCREEN_BOUND)
+    shells, feat, t = _block_data(s, ctx)
+    order = ctx.point_order()
+    offs = s.shell_offsets()
+    F = s.P @ O.collocate(s)
+    nb, nk = t.shape
+    say("blocks", nb, "x", nk)
+    t_ref = np.zeros_like(t)
+    U = np.zeros((nb, s.nshell))
+    N = np.zeros((nb, s.nshell))
+    for b in range(nb):
+        pts = order[b * 256:(b + 1) * 256]
+        pts = pts[pts >= 0]
+        Ai = [O.a3c(s, s.grid_xyz[i]) for i in pts]
+        for sh in range(s.nshell):
+            sl = slice(offs[sh], offs[sh + 1])
+            u = n = 0.0
+            for q, i in enumerate(pts):
+                d = np.sqrt(np.maximum(np.diag(Ai[q])[sl], 0.0))
+                u += s.grid_w[i] * np.sum(np.abs(F[sl, i]) * d) ** 2
+                n += s.grid_w[i] * np.sum((cnorm(s.shell_l[sh]) * F[sl, i]) ** 2)
+            U[b, sh], N[b, sh] = np.sqrt(u), np.sqrt(n)
+        for k, (A, B) in enumerate(shells):
+            sa, sb = slice(offs[A], offs[A + 1]), slice(offs[B], offs[B + 1])
+            v = sum(s.grid_w[i] * abs(F[sa, i] @ Ai[q][sa, sb] @ F[sb, i]) for q, i in enumerate(pts))
+            t_ref[b, k] = v * (0.5 if A == B else 1.0)
+    rel = np.max(np.abs(t - t_ref) / np.maximum(t_ref, 1e-300))
+    say("block energy max rel err", rel)
+    assert rel <= 1e-11
+
+    # features
+    for b in range(nb):
+        pts = order[b * 256:(b + 1) * 256]
+        pts = pts[pts >= 0]
+        X = s.grid_xyz[pts]
+        lo, hi, ctr = X.min(0), X.max(0), X.mean(0)
+        hd = 0.5 * np.linalg.norm(hi - lo)
+        lw = np.log10(s.grid_w[pts].sum())
+
+        def bdist(p):
+            e = np.maximum(np.maximum(lo - p, p - hi), 0.0)
+            return np.linalg.norm(e)
+
+        for k, (A, B) in enumerate(shells):
+            ea = s.exps[s.shell_prim_off[A]:s.shell_prim_off[A] + s.shell_nprim[A]]
+            eb = s.exps[s.shell_prim_off[B]:s.shell_prim_off[B] + s.shell_nprim[B]]
+            RA, RB = s.shell_center[A], s.shell_center[B]
+            za, zb = ea.min(), eb.min()
+            pc = (za * RA + zb * RB) / (za + zb)
+            Pab = s.P[offs[A]:offs[A + 1], offs[B]:offs[B + 1]]
+            cab = 0.5 if A == B else 1.0
+            ref = np.array([s.shell_l[A], s.shell_l[B], np.log10(za), np.log10(zb), np.linalg.norm(RA - RB),
+                            np.nan, np.log10(np.linalg.norm(Pab)), bdist(pc), hd, bdist(RA), bdist(RB), lw,
+                            np.log10(N[b, A]), np.log10(N[b, B]), np.log10(cab * U[b, A] * U[b, B]),
+                            np.linalg.norm(pc - ctr)])
+            got = feat[b, k]
+            ok = np.isnan(ref) | (np.abs(got - ref) <= 2e-4 + 2e-5 * np.abs(ref))
+            assert ok.all(), (b, k, np.nonzero(~ok), got, ref)
+    # feature 5: log10 of the summed |primitive-pair prefactor| is >= log10 of any one term
+    for k, (A, B) in enumerate(shells):
+        ea = s.exps[s.shell_prim_off[A]:s.shell_prim_off[A] + s.shell_nprim[A]]
+        eb = s.exps[s.shell_prim_off[B]:s.shell_prim_off[B] + s.shell_nprim[B]]
+        ca = s.coefs[s.shell_prim_off[A]:s.shell_prim_off[A] + s.shell_nprim[A]]
+        cb = s.coefs[s.shell_prim_off[B]:s.shell_prim_off[B] + s.shell_nprim[B]]
+        ab2 = np.sum((s.shell_center[A] - s.shell_center[B]) ** 2)
+        zp = ea[:, None] + eb[None, :]
+        pref = 2 * np.pi / zp * np.exp(-ea[:, None] * eb[None, :] / zp * ab2) * np.abs(ca[:, None] * cb[None, :])
+        assert abs(feat[0, k, 5] - np.log10(pref.sum())) <= 1e-4
+
+
+def _random_network(seed, mean, std):
+    m = snk.Mlp(0)
+    p = mlp_ref.init_params(seed)
+    m.set_params(mlp_ref.flatten(p).astype(np.float32))
+    m.set_normalisation(mean, std)
+    return m, p
+
+
+def test_screen_inference_matches_network_kernel():
+    """The network as evaluated inside the learned screen (bf16 matrix cores, 16 blocks per
+    wave) against the standalone bf16 forward kernel on the same features."""
+    import torch
+    s = synth.make_system(1, grid=(20, 50))
+    c0 = snk.Context(s, screen=snk.SNK_SCREEN_BOUND)
+    shells, feat, t = _block_data(s, c0)
+    X = feat.reshape(-1, 16)
+    mean, std = X.mean(0), X.std(0) + 1e-3
+    m, _ = _random_network(11, mean, std)
+    m.set_range(np.full(16, -1e30), np.full(16, 1e30), 0.5)
+    ctx = snk.Context(s, screen=snk.SNK_SCREEN_LEARNED, screener=m, eps_skip_energy=1e-6)
+    y, lest, thr = ctx.debug_learned(s.P)
+    nb = y.shape[0]
+    pidx = np.array([pair_index(a, b) for a, b in shells])
+    yg = y[:, pidx]                      # [batch][block pair]
+    cand = ~np.isnan(yg)
+    say("candidate blocks", int(cand.sum()), "of", cand.size)
+    assert cand.sum() > 0.9 * cand.size
+    Xd = torch.from_numpy(np.ascontiguousarray(feat[:nb].reshape(-1, 16))).cuda()
+    yd = torch.empty(Xd.shape[0], dtype=torch.float32, device="cuda")
+    m.forward(Xd.data_ptr(), Xd.shape[0], yd.data_ptr(), bf16=True)
+    torch.cuda.synchronize()
+    yf = yd.cpu().numpy().reshape(nb, -1)
+    d = np.abs(yg[cand] - yf[cand])
+    scale = max(1.0, np.abs(yf).max())
+    say("in-screen vs standalone: median %.2e max %.2e (scale %.1f)" % (np.median(d), d.max(), scale))
+    assert np.median(d) <= 1e-4 * scale
+    assert d.max() <= 2e-2 * scale
+    # est = min(bound, 10^(y + margin)), stored as log2
+    bound = feat[:nb, :, 14].astype(np.float64)
+    le = lest[:, pidx]
+    ref = np.minimum(bound, yg.astype(np.float64) + 0.5) * np.log2(10.0)
+    ok = cand & (bound > -39.0)    # the feature is clamped at -40
+    assert np.max(np.abs(le[ok] - ref[ok])) <= 2e-3 * max(1.0, np.abs(ref[ok]).max())
+
+
+def test_learned_zero_budget_is_exact():
+    s = synth.make_system(1, grid=(20, 50))
+    c0 = snk.Context(s, screen=snk.SNK_SCREEN_BOUND)
+    _, feat, _ = _block_data(s, c0)
+    X = feat.reshape(-1, 16)
+    m, _ = _random_network(5, X.mean(0), X.std(0) + 1e-3)
+    m.set_range(X.min(0), X.max(0), 0.0)
+    K0, st0 = snk.sn_k_build(s)
+    K1, st1 = snk.sn_k_build(s, screen=snk.SNK_SCREEN_LEARNED, screener=m, eps_skip_energy=0.0)
+    say("learned zero budget: skipped", st1["pair_points_skipped"], "|dE|", abs(st1["ex"] - st0["ex"]))
+    assert st1["pair_points_skipped"] == 0
+    assert abs(st1["ex"] - st0["ex"]) <= 1e-12
+    assert np.max(np.abs(K1 - K0)) <= 1e-12 * np.max(np.abs(K0))
+
+
+def test_learned_screen_out_of_range_falls_back_to_bound():
+    """With a training range no block satisfies, every estimate is the rigorous bound: the
+    learned build equals the bound-screened build."""
+    s = synth.make_system(1, grid=(20, 50))
+    m, _ = _random_network(6, np.zeros(16), np.ones(16))
+    m.set_range(np.full(16, 1e6), np.full(16, 2e6), 0.0)
+    for eps in (1e-6, 1e-3):
+        K1, st1 = snk.sn_k_build(s, screen=snk.SNK_SCREEN_BOUND, eps_skip_energy=eps)
+        K2, st2 = snk.sn_k_build(s, screen=snk.SNK_SCREEN_LEARNED, screener=m, eps_skip_energy=eps)
+        say("eps", eps, "bound skipped", st1["pair_points_skipped"], "learned(oob) skipped",
+            st2["pair_points_skipped"], "|dE| bound", abs(st1["ex"] - st2["ex"]))
+        assert st2["pair_points_skipped"] >= st1["pair_points_skipped"]
+        assert abs(st2["ex"] - st1["ex"]) <= st2["skipped_bound"] + st1["skipped_bound"] + 1e-12
+        assert st2["skipped_bound"] <= eps * (1 + 1e-12)
+
+
+@pytest.mark.parametrize("cfg", [1, 2])
+def test_trained_screener_gain_within_budget(cfg):
+    """The committed network on systems it was not trained on (the benchmark systems
+    themselves; training used other geometries and densities of the same recipes): the
+    learned screen keeps |dE_x| within the 1e-6 Eh budget and skips far more work than the
+    rigorous bound alone at the same budget (the network's gain)."""
+    if not os.path.exists(snk.SCREENER_WEIGHTS):
+        pytest.skip("no trained screener weights")
+    m = snk.load_screener()
+    s = synth.make_system(cfg)
+    eps = 5e-7
+    K0, st0 = snk.sn_k_build(s)
+    Kb, stb = snk.sn_k_build(s, screen=snk.SNK_SCREEN_BOUND, eps_skip_energy=eps)
+    Kl, stl = snk.sn_k_build(s, screen=snk.SNK_SCREEN_LEARNED, screener=m, eps_skip_energy=eps)
+
+    def frac(st):
+        return st["pair_points_skipped"] / max(1, st["pair_points_skipped"] + sum(st["pair_points"]))
+
+    dEb, dEl = abs(stb["ex"] - st0["ex"]), abs(stl["ex"] - st0["ex"])
+    say("config %d eps %.1e: bound skips %.4f |dE| %.2e; learned skips %.4f |dE| %.2e (estimate %.2e) "
+        "max|dK| %.2e; afg ms %.2f -> %.2f" % (cfg, eps, frac(stb), dEb, frac(stl), dEl, stl["skipped_bound"],
+                                              np.max(np.abs(Kl - K0)), st0["t_afg_ms"], stl["t_afg_ms"]))
+    assert dEl <= 1e-6
+    assert np.array_equal(Kl, Kl.T)
+    # the 6-atom system has few negligible blocks; the 30-atom one mostly negligible ones
+    assert frac(stl) >= frac(stb) + (0.05 if cfg == 1 else 0.4)

@@ -1,0 +1,82 @@
+"""Mixed-precision build (SNK_MIXED) against the FP64 oracle.
+
+In the mixed build Phi, P and F are stored in FP32 and both GEMMs run on the FP32 matrix
+cores (FP32 products, FP32 sums over at most 1024 terms, FP64 across them); the Boys
+function, the recurrences, G and the K accumulation stay FP64.  FP32 storage rounds each
+F element to a relative 2^-24 ~ 6e-8; the errors enter E_x = -1/2 sum_i F_i^T G_i with
+random signs, so the tolerance below is a small multiple of 6e-8 |E_x| (|dE_x| <= 2e-7 |E_x|
+and max|dK| <= 1e-6 max|K|).  The measured errors are printed.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2303_14280_amd import snk, synth
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def check_mixed(K, ex, Kref, exref, label):
+    dK = float(np.max(np.abs(K - Kref)))
+    dE = abs(ex - exref)
+    say("%s mixed: E_x %.12f ref %.12f |dE| %.3e (rel %.2e) max|dK| %.3e (rel %.2e)" %
+        (label, ex, exref, dE, dE / abs(exref), dK, dK / np.max(np.abs(Kref))))
+    assert np.array_equal(K, K.T)
+    assert dE <= 2e-7 * abs(exref)
+    assert dK <= 1e-6 * float(np.max(np.abs(Kref)))
+    return dE, dK
+
+
+def test_mixed_config1_vs_stored_oracle():
+    g = np.load(os.path.join(GOLDEN, "oracle_config1.npz"))
+    s = synth.make_system(1, with_density=False).with_density(g["P"])
+    K, st = snk.sn_k_build(s, precision=snk.SNK_MIXED)
+    check_mixed(K, st["ex"], g["K"], float(g["ex"][0]), "config1")
+
+
+def test_mixed_all_classes_vs_oracle():
+    xyz = [[0.0, 0.0, 0.0], [1.3, 0.4, -0.2], [-0.5, 1.1, 0.7]]
+    shells = [
+        [(0, [2.1, 0.6], [0.5, 0.6]), (1, [1.4, 0.45], [0.7, 0.4]), (2, [0.9], [1.0])],
+        [(0, [1.7, 0.5], [0.4, 0.7]), (1, [0.8], [1.0])],
+        [(0, [1.1], [1.0]), (2, [1.3, 0.5], [0.5, 0.5]), (1, [30.0, 3.0, 0.3], [0.3, 0.5, 0.4])],
+    ]
+    s = synth.make_custom([8, 1, 1], xyz, shells, grid=(24, 86), n_occ=3)
+    K, st = snk.sn_k_build(s, precision=snk.SNK_MIXED)
+    Kr, exr, _ = O.snk(s)
+    check_mixed(K, st["ex"], Kr, exr, "soft-spd")
+
+
+def test_mixed_config2_sample_vs_fp64_gpu():
+    """A 1/7 point sample of the 30-atom system (many tiles, several GEMM chunks): mixed
+    against the FP64 GPU build, itself parity-checked against the oracle."""
+    s = synth.make_system(2)
+    s = s.subset_points(np.arange(0, s.npts, 7))
+    K0, st0 = snk.sn_k_build(s)
+    K1, st1 = snk.sn_k_build(s, precision=snk.SNK_MIXED)
+    check_mixed(K1, st1["ex"], K0, st0["ex"], "config2/7")
+
+
+def test_mixed_deterministic_and_device_pointers():
+    import torch
+    s = synth.make_system(1, grid=(20, 50))
+    ctx = snk.Context(s, precision=snk.SNK_MIXED)
+    K1, _ = ctx.build(s.P)
+    K2, _ = ctx.build(s.P)
+    assert np.array_equal(K1, K2)
+    st = torch.cuda.Stream()
+    cd = snk.Context(s, precision=snk.SNK_MIXED, flags=snk.SNK_DEVICE_PTRS, stream=st.cuda_stream)
+    Pd = torch.from_numpy(s.P).cuda()
+    Kd = torch.empty_like(Pd)
+    cd.build_device(Pd.data_ptr(), Kd.data_ptr())
+    st.synchronize()
+    assert np.array_equal(Kd.cpu().numpy(), K1)

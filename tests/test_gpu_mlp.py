@@ -1,0 +1,151 @@
+"""GPU network of the learned screener against the FP64 numpy reference in oracle/mlp_ref.py."""
+import numpy as np
+import pytest
+
+from oracle import mlp_ref
+
+pytestmark = pytest.mark.gpu
+
+
+def _bf16(a):
+    """Round float32 values to the nearest bfloat16 (ties to even), as float32."""
+    u = np.ascontiguousarray(a, np.float32).view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000).astype(np.uint32)
+    return u.view(np.float32)
+
+
+def _setup(n, seed, scale_feat=3.0):
+    import torch
+    from paper_2303_14280_amd import snk
+    rng = np.random.default_rng(seed)
+    p = mlp_ref.init_params(seed)
+    for k in p:
+        if k.startswith("b"):
+            p[k] = rng.normal(scale=0.1, size=p[k].shape)
+    flat = mlp_ref.flatten(p).astype(np.float32)
+    mean = rng.normal(size=16).astype(np.float32)
+    std = rng.uniform(0.5, 2.0, size=16).astype(np.float32)
+    X = (mean + std * rng.normal(scale=scale_feat / 3, size=(n, 16))).astype(np.float32)
+    t = rng.normal(size=n).astype(np.float32)
+    m = snk.Mlp(0)
+    m.set_params(flat)
+    m.set_normalisation(mean, std)
+    Xn = (X.astype(np.float64) - mean.astype(np.float64)) * (1.0 / std.astype(np.float32)).astype(np.float64)
+    pf = mlp_ref.unflatten(flat.astype(np.float64))
+    dX = torch.from_numpy(X).cuda()
+    dt = torch.from_numpy(t).cuda()
+    return m, flat, pf, X, Xn, t, dX, dt
+
+
+def test_params_roundtrip():
+    from paper_2303_14280_amd import snk
+    m = snk.Mlp(0)
+    v = np.random.default_rng(1).normal(size=m.nparams).astype(np.float32)
+    m.set_params(v)
+    assert np.array_equal(m.get_params(), v)
+    with pytest.raises(snk.SnkError):
+        m.set_normalisation(np.zeros(16), np.zeros(16))
+    bad = v.copy()
+    bad[3] = np.nan
+    with pytest.raises(snk.SnkError):
+        m.set_params(bad)
+
+
+@pytest.mark.parametrize("n", [1, 255, 1000])
+def test_forward_fp32_matches_reference(n):
+    import torch
+    m, flat, pf, X, Xn, t, dX, dt = _setup(n, 3)
+    y = torch.empty(n, dtype=torch.float32, device="cuda")
+    m.forward(dX.data_ptr(), n, y.data_ptr(), bf16=False)
+    torch.cuda.synchronize()
+    ref, _ = mlp_ref.forward(pf, Xn)
+    err = np.abs(y.cpu().numpy() - ref)
+    assert err.max() <= 1e-5 * max(1.0, np.abs(ref).max()), err.max()
+
+
+def test_forward_bf16_matches_emulation():
+    """BF16 operands, FP32 accumulation: compare with a numpy emulation of the same roundings,
+    and bound the distance to the FP64 result."""
+    import torch
+    n = 2000
+    m, flat, pf, X, Xn, t, dX, dt = _setup(n, 4)
+    y = torch.empty(n, dtype=torch.float32, device="cuda")
+    m.forward(dX.data_ptr(), n, y.data_ptr(), bf16=True)
+    torch.cuda.synchronize()
+    yg = y.cpu().numpy()
+    w = mlp_ref.unflatten(_bf16(flat).astype(np.float64))
+    x = _bf16(Xn.astype(np.float32)).astype(np.float64)
+    h1 = _bf16(mlp_ref.silu(x @ w["W1"].T + w["b1"]).astype(np.float32)).astype(np.float64)
+    h2 = _bf16(mlp_ref.silu(h1 @ w["W2"].T + w["b2"]).astype(np.float32)).astype(np.float64)
+    emu = h2 @ w["W3"][0] + w["b3"][0]
+    # FP32 accumulation order differs; a BF16 rounding of a near-tie may flip: loose per-sample
+    scale = max(1.0, np.abs(emu).max())
+    assert np.median(np.abs(yg - emu)) <= 1e-5 * scale
+    assert np.abs(yg - emu).max() <= 2e-2 * scale
+    ref, _ = mlp_ref.forward(pf, Xn)
+    assert np.abs(yg - ref).max() <= 5e-2 * max(1.0, np.abs(ref).max())
+
+
+@pytest.mark.parametrize("n,under", [(64, 10.0), (1000, 10.0), (777, 1.0)])
+def test_loss_and_gradient_match_reference(n, under):
+    import torch
+    m, flat, pf, X, Xn, t, dX, dt = _setup(n, 5)
+    g = torch.empty(m.nparams + 1, dtype=torch.float32, device="cuda")
+    m.loss_grad(dX.data_ptr(), dt.data_ptr(), n, g.data_ptr(), under=under)
+    torch.cuda.synchronize()
+    gg = g.cpu().numpy().astype(np.float64)
+    y, cache = mlp_ref.forward(pf, Xn)
+    ref = mlp_ref.flatten(mlp_ref.backward(pf, cache, y, t.astype(np.float64), under))
+    L = mlp_ref.loss(y, t.astype(np.float64), under)
+    assert abs(gg[-1] - L) <= 1e-4 * abs(L)
+    num = np.linalg.norm(gg[:-1] - ref)
+    assert num <= 1e-4 * np.linalg.norm(ref), num / np.linalg.norm(ref)
+    # per block of parameters too (so a wrong small block is not hidden by a large one)
+    off = 0
+    for k, shape in [("W1", (64, 16)), ("b1", (64,)), ("W2", (64, 64)), ("b2", (64,)), ("W3", (1, 64)),
+                     ("b3", (1,))]:
+        sz = int(np.prod(shape))
+        a, b = gg[off:off + sz], ref[off:off + sz]
+        assert np.linalg.norm(a - b) <= 1e-4 * np.linalg.norm(b) + 1e-7, k
+        off += sz
+
+
+def test_adam_steps_match_reference():
+    import torch
+    n = 500
+    m, flat, pf, X, Xn, t, dX, dt = _setup(n, 6)
+    g = torch.empty(m.nparams + 1, dtype=torch.float32, device="cuda")
+    p = {k: v.copy() for k, v in pf.items()}
+    mo = {k: np.zeros_like(v) for k, v in p.items()}
+    vo = {k: np.zeros_like(v) for k, v in p.items()}
+    lr = 1e-3
+    for step in range(1, 4):
+        m.loss_grad(dX.data_ptr(), dt.data_ptr(), n, g.data_ptr())
+        m.adam_step(g.data_ptr(), lr, step)
+        y, cache = mlp_ref.forward(p, Xn)
+        mlp_ref.adam_step(p, mlp_ref.backward(p, cache, y, t.astype(np.float64)), mo, vo, step, lr)
+    torch.cuda.synchronize()
+    got = m.get_params().astype(np.float64)
+    ref = mlp_ref.flatten(p)
+    moved = np.abs(ref - mlp_ref.flatten(pf))
+    # Adam moves each parameter by about lr per step; the update must agree to a small part of it
+    assert np.abs(got - ref).max() <= 0.05 * 3 * lr, np.abs(got - ref).max()
+    assert np.median(moved) > 0.5 * lr
+
+
+def test_training_reduces_loss():
+    import torch
+    n = 4096
+    m, flat, pf, X, Xn, t, dX, dt = _setup(n, 7)
+    # a learnable target: a smooth function of the features
+    tt = np.tanh(Xn[:, 0]) + 0.5 * Xn[:, 1] * Xn[:, 2] / (1 + Xn[:, 2] ** 2)
+    dt = torch.from_numpy(tt.astype(np.float32)).cuda()
+    g = torch.empty(m.nparams + 1, dtype=torch.float32, device="cuda")
+    losses = []
+    for step in range(1, 301):
+        m.loss_grad(dX.data_ptr(), dt.data_ptr(), n, g.data_ptr())
+        if step == 1 or step == 300:
+            torch.cuda.synchronize()
+            losses.append(float(g[-1].item()))
+        m.adam_step(g.data_ptr(), 3e-3, step)
+    assert losses[1] < 0.1 * losses[0], losses

@@ -171,3 +171,31 @@ def test_config2_full_vs_stored_oracle():
     ctx = snk.Context(s)
     K, st = ctx.build(s.P)
     check(K, st["ex"], g["K"], g["ex"][0], "config2-full")
+
+
+@pytest.mark.parametrize("cfg,eps", [(1, 1e-6), (1, 1e-3), (2, 1e-6)])
+def test_bound_screening_respects_energy_budget(cfg, eps):
+    """Screened E_x differs from the unscreened build by at most the rigorous bound of the
+    skipped blocks, which itself stays within the budget."""
+    s = synth.make_system(cfg)
+    if cfg == 2:
+        s = s.subset_points(np.arange(0, s.npts, 7))
+    say("screen cfg", cfg, "eps", eps, "npts", s.npts)
+    K0, st0 = snk.sn_k_build(s)
+    K1, st1 = snk.sn_k_build(s, screen=snk.SNK_SCREEN_BOUND, eps_skip_energy=eps)
+    dE = abs(st1["ex"] - st0["ex"])
+    frac = st1["pair_points_skipped"] / max(1, st1["pair_points_skipped"] + sum(st1["pair_points"]))
+    say("  |dE| %.3e bound %.3e budget %.1e skipped fraction %.4f max|dK| %.3e" %
+        (dE, st1["skipped_bound"], eps, frac, np.max(np.abs(K1 - K0))))
+    assert st1["skipped_bound"] <= eps * (1 + 1e-12)
+    assert dE <= st1["skipped_bound"] + 1e-12
+    assert np.array_equal(K1, K1.T)
+
+
+def test_bound_screening_zero_budget_is_exact():
+    s = synth.make_system(1, grid=(20, 50))
+    K0, st0 = snk.sn_k_build(s)
+    K1, st1 = snk.sn_k_build(s, screen=snk.SNK_SCREEN_BOUND, eps_skip_energy=0.0)
+    say("zero budget: skipped", st1["pair_points_skipped"], "|dE|", abs(st1["ex"] - st0["ex"]))
+    assert abs(st1["ex"] - st0["ex"]) <= 1e-12
+    assert np.max(np.abs(K1 - K0)) <= 1e-12 * np.max(np.abs(K0))
