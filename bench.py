@@ -97,13 +97,17 @@ def mixed_learned(s, P, K64, stream, args, ms64, ex64, ints):
         return {"error": "no trained screener weights"}
     mlp = snk.load_screener(device=0)
     K = torch.empty_like(P)
-    variants = [("mixed+learned", dict(precision=snk.SNK_MIXED, screen=snk.SNK_SCREEN_LEARNED)),
-                ("fp64+learned", dict(precision=snk.SNK_FP64, screen=snk.SNK_SCREEN_LEARNED)),
-                ("mixed", dict(precision=snk.SNK_MIXED, screen=snk.SNK_SCREEN_NONE)),
-                ("fp64+bound", dict(precision=snk.SNK_FP64, screen=snk.SNK_SCREEN_BOUND))]
+    D, R = snk.SNK_DEVICE_PTRS, snk.SNK_DEVICE_PTRS | snk.SNK_ROCBLAS
+    variants = [("mixed+learned", dict(precision=snk.SNK_MIXED, screen=snk.SNK_SCREEN_LEARNED, flags=R)),
+                ("mixed+learned+fp32gemm", dict(precision=snk.SNK_MIXED, screen=snk.SNK_SCREEN_LEARNED,
+                                                flags=D | snk.SNK_FP32_GEMM)),
+                ("fp64+learned", dict(precision=snk.SNK_FP64, screen=snk.SNK_SCREEN_LEARNED, flags=R)),
+                ("fp64 native GEMM", dict(precision=snk.SNK_FP64, screen=snk.SNK_SCREEN_NONE, flags=D)),
+                ("fp32gemm", dict(precision=snk.SNK_MIXED, screen=snk.SNK_SCREEN_NONE, flags=D | snk.SNK_FP32_GEMM)),
+                ("fp64+bound", dict(precision=snk.SNK_FP64, screen=snk.SNK_SCREEN_BOUND, flags=R))]
     for name, kw in variants:
-        ctx = snk.Context(s, flags=snk.SNK_DEVICE_PTRS, stream=stream.cuda_stream, device=0, screener=mlp,
-                          eps_skip_energy=args.eps, **kw)
+        ctx = snk.Context(s, stream=stream.cuda_stream, device=0, screener=mlp, eps_skip_energy=args.eps,
+                          eps_lowprec_energy=args.eps, **kw)
         steps = args.steps if name == "mixed+learned" else max(2, args.steps // 2)
         ms = time_builds(ctx, P, K, stream, steps, args.warmup)
         st = ctx.build_device(P.data_ptr(), K.data_ptr(), stats=True)
@@ -112,16 +116,21 @@ def mixed_learned(s, P, K64, stream, args, ms64, ex64, ints):
         evaluated = float(sum(st["pair_points"]))
         r = {"ms_per_step": ms, "speedup_vs_fp64": ms64 / ms, "dE_x_vs_fp64": st["ex"] - ex64,
              "max_dK_vs_fp64": dK, "skipped_pair_points_fraction": st["pair_points_skipped"] / max(1.0, ints),
+             "fp32_pair_points_fraction": st["pair_points_lowprec"] / max(1.0, ints),
              "skipped_energy_estimate": st["skipped_bound"], "shell_pair_points_evaluated": evaluated,
              "effective_rate": ints / (ms * 1e-3),
              "phases_ms": {"collocate": st["t_collocate_ms"], "fgemm": st["t_fgemm_ms"],
                            "screen": st["t_screen_ms"], "afg": st["t_afg_ms"], "kgemm": st["t_kgemm_ms"],
-                           "finish": st["t_finish_ms"]}}
-        log("%s: %.3f ms/step (x%.2f vs FP64), dE_x %.2e, max|dK| %.2e, skipped %.3f" %
-            (name, ms, ms64 / ms, r["dE_x_vs_fp64"], dK, r["skipped_pair_points_fraction"]))
+                           "finish": st["t_finish_ms"]},
+             "afg_class_ms": dict(zip(CLASSES, st["t_afg_class_ms"])),
+             "afg_class_pair_points": dict(zip(CLASSES, st["pair_points"]))}
+        log("%s: %.3f ms/step (x%.2f vs FP64), dE_x %.2e, max|dK| %.2e, skipped %.3f, FP32 %.3f" %
+            (name, ms, ms64 / ms, r["dE_x_vs_fp64"], dK, r["skipped_pair_points_fraction"],
+             r["fp32_pair_points_fraction"]))
         res[name] = r
         ctx.close()
     res["eps_skip_energy"] = args.eps
+    res["eps_lowprec_energy"] = args.eps
     res["target"] = "|dE_x| <= 1e-6 Eh at >= 3x the FP64 build"
     return res
 
@@ -163,7 +172,8 @@ def main():
     s = synth.make_system(args.config)
     stream = torch.cuda.Stream(device=dev)          # default priority
     torch.cuda.set_stream(stream)
-    ctx = snk.Context(s, flags=snk.SNK_DEVICE_PTRS, stream=stream.cuda_stream, device=0)
+    # FP64 reference build: the library's A.F kernels, the dense GEMMs through rocBLAS dgemm
+    ctx = snk.Context(s, flags=snk.SNK_DEVICE_PTRS | snk.SNK_ROCBLAS, stream=stream.cuda_stream, device=0)
     P = torch.tensor(s.P, dtype=torch.float64, device=dev)
     K = torch.empty_like(P)
     torch.cuda.synchronize()
@@ -221,7 +231,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "config%d: %d-atom water-like cluster, %d Cartesian s/p/d functions, "
-                               "%d grid points in %d batches of 256, FP64, no screening"
+                               "%d grid points in %d batches of 256, FP64 (dense GEMMs via rocBLAS), no screening"
                                % (args.config, len(s.atom_Z), ctx.nbf, s.npts, ctx.nbatches),
                    "atoms": int(len(s.atom_Z)), "nbf": ctx.nbf, "grid_points": s.npts,
                    "shell_pair_points": ints, "precision": "fp64", "screen": "none",

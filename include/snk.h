@@ -55,7 +55,10 @@ typedef enum snk_status {
 
 typedef enum snk_precision {
     SNK_FP64 = 0,           /* every step in FP64 */
-    SNK_MIXED = 1           /* BF16 MFMA GEMMs with FP32 accumulation; integrals and K accumulation FP64 */
+    SNK_MIXED = 1           /* with a screen: blocks whose estimated energies sum to at most
+                               eps_lowprec_energy / 1e-5 per build run their Boys function,
+                               recurrences and A.F contraction in FP32 (G, K and the rest FP64);
+                               with SNK_FP32_GEMM also FP32 Phi/P/F and FP32 matrix-core GEMMs */
 } snk_precision;
 
 typedef enum snk_screen {
@@ -67,6 +70,12 @@ typedef enum snk_screen {
 /* opts.flags */
 #define SNK_DEVICE_PTRS 0x1u   /* P and K_out are device pointers; work is ordered on opts.stream */
 #define SNK_VALIDATE    0x2u   /* check P for symmetry and finiteness (host-pointer mode) */
+#define SNK_ROCBLAS     0x4u   /* FP64 build: run the two dense GEMMs (Eqs. fmat, usym_k) through
+                                  rocBLAS dgemm (atomics off, deterministic) instead of the
+                                  library's own FP64 matrix-core kernel */
+#define SNK_FP32_GEMM   0x8u   /* SNK_MIXED: also store Phi, P and F in FP32 and run both dense GEMMs
+                                  on the FP32 matrix cores (FP32 sums over <= 1024 terms, FP64
+                                  across them); without it the mixed build's GEMMs stay FP64 */
 
 typedef struct snk_basis {
     int32_t nshell;
@@ -111,13 +120,13 @@ typedef struct snk_opts {
     const snk_mlp* screener;    /* required for SNK_SCREEN_LEARNED */
     double eps_basis;           /* basis-function screening tolerance eps_B (Eq. basis_screen); 0 = off */
     double eps_skip_energy;     /* total energy budget for skipped blocks (Eh) */
-    double eps_lowprec_energy;  /* total energy budget for reduced-precision blocks (Eh) */
+    double eps_lowprec_energy;  /* SNK_MIXED: error budget of the FP32 blocks (Eh), see SNK_MIXED */
     int32_t batch_points;       /* maximum points per batch, 64..256 (default 256) */
     int32_t deterministic;      /* 1: no floating-point atomics (the default path uses none) */
     int64_t max_device_bytes;   /* workspace budget for batch groups (0 = automatic) */
     int32_t device;             /* HIP device ordinal */
     void* stream;               /* hipStream_t; NULL = the library's own stream */
-    uint32_t flags;             /* SNK_DEVICE_PTRS | SNK_VALIDATE */
+    uint32_t flags;             /* SNK_DEVICE_PTRS | SNK_VALIDATE | SNK_ROCBLAS | SNK_FP32_GEMM */
     snk_stats* stats;           /* optional output of sn_k_build */
 } snk_opts;
 

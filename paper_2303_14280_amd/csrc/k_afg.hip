@@ -15,8 +15,10 @@
 // the F rows and G accumulators of a tile of A shells in registers while it
 // sweeps the B shells, so each F_B load and G_B update serves the whole tile.
 // One kernel instantiation per (l_A, l_B) class with l_A >= l_B, fully unrolled
-// at compile time, and per storage type of F (FP64, or FP32 for the mixed-precision
-// build; the integrals and the contraction are FP64 either way).
+// at compile time, per storage type of F (FP64, or FP32), and per arithmetic type: FP64,
+// or FP32 for the blocks the screen marks as small enough for reduced precision (Boys
+// function, recurrences and the contraction in FP32; G itself is always accumulated in
+// FP64).
 #include "os3c.h"
 
 namespace snk {
@@ -24,11 +26,11 @@ namespace {
 
 using namespace os3c;
 
-template <int LA, int LB, int TA, typename TF>
+template <int LA, int LB, int TA, typename TF, typename R>
 __global__ __launch_bounds__(256) void afg_kernel(const double* __restrict__ px, const double* __restrict__ py,
                                                   const double* __restrict__ pz, const double* __restrict__ pw,
                                                   const TF* __restrict__ F, double* __restrict__ G, int64_t ld,
-                                                  const PrimPair* __restrict__ prims,
+                                                  const typename PrimOf<R>::type* __restrict__ prims,
                                                   const int32_t* __restrict__ runs,
                                                   const int32_t* __restrict__ btasks,
                                                   const double* __restrict__ btask_ab,
@@ -38,13 +40,14 @@ __global__ __launch_bounds__(256) void afg_kernel(const double* __restrict__ px,
     constexpr int NA = ncart(LA), NB = ncart(LB);
     constexpr int RS = 2 + TA;        // run record stride
     constexpr int BS = 2 + 2 * TA;    // B-task record stride
-    __shared__ double tab[kBoysRows * kBoysCols];
-    for (int i = threadIdx.x; i < kBoysRows * kBoysCols; i += blockDim.x) tab[i] = gtab[i];
+    __shared__ R tab[kBoysRows * kBoysCols];
+    for (int i = threadIdx.x; i < kBoysRows * kBoysCols; i += blockDim.x) tab[i] = (R)gtab[i];
     __syncthreads();
 
     const int batch = blockIdx.x;
     const int64_t col = (int64_t)batch * kBatch + threadIdx.x;
-    const double cx = px[col], cy = py[col], cz = pz[col], w = pw[col];
+    const R cx = (R)px[col], cy = (R)py[col], cz = (R)pz[col];
+    const double w = pw[col];
 
     int r0 = 0, r1 = nrun;
     if (batch_run_off) {
@@ -55,14 +58,14 @@ __global__ __launch_bounds__(256) void afg_kernel(const double* __restrict__ px,
         const int32_t* run = runs + (int64_t)r * RS;
         const int b0 = run[0], b1 = run[1];
         int arow[TA];
-        double Fa[TA][NA], Ga[TA][NA];
+        R Fa[TA][NA], Ga[TA][NA];
         sfor<0, TA>([&](auto kc) {
             constexpr int k = CV(kc);
             arow[k] = run[2 + k];
             sfor<0, NA>([&](auto ic) {
                 constexpr int i = CV(ic);
-                Fa[k][i] = arow[k] >= 0 ? cnorm(LA, i) * (double)F[(int64_t)(arow[k] + i) * ld + col] : 0.0;
-                Ga[k][i] = 0.0;
+                Fa[k][i] = arow[k] >= 0 ? (R)(cnorm(LA, i) * (double)F[(int64_t)(arow[k] + i) * ld + col]) : (R)0;
+                Ga[k][i] = (R)0;
             });
         });
         // the F_B / G_B rows of the next B task are fetched one task ahead
@@ -80,12 +83,13 @@ __global__ __launch_bounds__(256) void afg_kernel(const double* __restrict__ px,
         for (int bt = b0; bt < b1; ++bt) {
             const int32_t* cur = btasks + (int64_t)bt * BS;
             const int brow = nrow;
-            double Fb[NB], Gold[NB], Gb[NB];
+            R Fb[NB], Gb[NB];
+            double Gold[NB];
             sfor<0, NB>([&](auto jc) {
                 constexpr int j = CV(jc);
-                Fb[j] = cnorm(LB, j) * Fn[j];
+                Fb[j] = (R)(cnorm(LB, j) * Fn[j]);
                 Gold[j] = Gn[j];
-                Gb[j] = 0.0;
+                Gb[j] = (R)0;
             });
             if (bt + 1 < b1) fetch(bt + 1);
             const int mask = cur[1];
@@ -94,12 +98,12 @@ __global__ __launch_bounds__(256) void afg_kernel(const double* __restrict__ px,
                 constexpr int k = CV(kc);
                 if (mask & (1 << k)) {
                     const double* ab = btask_ab + ((int64_t)bt * TA + k) * 3;
-                    const double AB[3] = {ab[0], ab[1], ab[2]};
-                    double Ab[NA][NB];
-                    pair_block<LA, LB>(prims + cur[2 + 2 * k], cur[3 + 2 * k], AB, cx, cy, cz, tab, Ab);
+                    const R AB[3] = {(R)ab[0], (R)ab[1], (R)ab[2]};
+                    R Ab[NA][NB];
+                    pair_block<LA, LB, R>(prims + cur[2 + 2 * k], cur[3 + 2 * k], AB, cx, cy, cz, tab, Ab);
                     sfor<0, NA>([&](auto ic) {
                         constexpr int i = CV(ic);
-                        double acc = Ga[k][i];
+                        R acc = Ga[k][i];
                         sfor<0, NB>([&](auto jc) { acc = fma(Ab[i][CV(jc)], Fb[CV(jc)], acc); });
                         Ga[k][i] = acc;
                     });
@@ -107,7 +111,7 @@ __global__ __launch_bounds__(256) void afg_kernel(const double* __restrict__ px,
                         transposed = true;
                         sfor<0, NB>([&](auto jc) {
                             constexpr int j = CV(jc);
-                            double acc = Gb[j];
+                            R acc = Gb[j];
                             sfor<0, NA>([&](auto ic) { acc = fma(Ab[CV(ic)][j], Fa[k][CV(ic)], acc); });
                             Gb[j] = acc;
                         });
@@ -117,7 +121,7 @@ __global__ __launch_bounds__(256) void afg_kernel(const double* __restrict__ px,
             if (transposed) {
                 sfor<0, NB>([&](auto jc) {
                     constexpr int j = CV(jc);
-                    G[(int64_t)(brow + j) * ld + col] = fma(w * cnorm(LB, j), Gb[j], Gold[j]);
+                    G[(int64_t)(brow + j) * ld + col] = fma(w * cnorm(LB, j), (double)Gb[j], Gold[j]);
                 });
             }
         }
@@ -126,7 +130,7 @@ __global__ __launch_bounds__(256) void afg_kernel(const double* __restrict__ px,
             if (arow[k] >= 0) {
                 sfor<0, NA>([&](auto ic) {
                     constexpr int i = CV(ic);
-                    G[(int64_t)(arow[k] + i) * ld + col] += (w * cnorm(LA, i)) * Ga[k][i];
+                    G[(int64_t)(arow[k] + i) * ld + col] += (w * cnorm(LA, i)) * (double)Ga[k][i];
                 });
             }
         });
@@ -143,7 +147,7 @@ __global__ __launch_bounds__(256) void boys_eval_kernel(const double* __restrict
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
     double f[MMAX + 1];
-    boys<MMAX>(T[k], tab, f);
+    boys<MMAX, double>(T[k], tab, f);
     sfor<0, MMAX + 1>([&](auto mc) { F[k * (MMAX + 1) + CV(mc)] = f[CV(mc)]; });
 }
 
@@ -153,23 +157,32 @@ hipError_t launch_afg(int la, int lb, const AfgArgs& a, hipStream_t s)
 {
     if (a.nbatch <= 0) return hipSuccess;
     dim3 grid(a.nbatch), block(kBatch);
-#define SNK_AFG(LA, LB, TA)                                                                                     \
-    if (a.F32)                                                                                                   \
-        hipLaunchKernelGGL((afg_kernel<LA, LB, TA, float>), grid, block, 0, s, a.px, a.py, a.pz, a.pw, a.F32, a.G, \
-                           a.ld, a.prims, a.runs, a.btasks, a.btask_ab, a.batch_run_off, a.nrun, a.boys_tab);     \
-    else                                                                                                         \
-        hipLaunchKernelGGL((afg_kernel<LA, LB, TA, double>), grid, block, 0, s, a.px, a.py, a.pz, a.pw, a.F, a.G,  \
-                           a.ld, a.prims, a.runs, a.btasks, a.btask_ab, a.batch_run_off, a.nrun, a.boys_tab)
+#define SNK_AFG_T(LA, LB, TA, TF, R, FP, PR)                                                                  \
+    hipLaunchKernelGGL((afg_kernel<LA, LB, TA, TF, R>), grid, block, 0, s, a.px, a.py, a.pz, a.pw, FP, a.G, a.ld, \
+                       PR, a.runs, a.btasks, a.btask_ab, a.batch_run_off, a.nrun, a.boys_tab)
+#define SNK_AFG(LA, LB, TA, TA32)                                                                       \
+    if (a.lowp) {                                                                                       \
+        if (a.F32)                                                                                      \
+            SNK_AFG_T(LA, LB, TA32, float, float, a.F32, a.prims32);                                    \
+        else                                                                                            \
+            SNK_AFG_T(LA, LB, TA32, double, float, a.F, a.prims32);                                     \
+    } else {                                                                                            \
+        if (a.F32)                                                                                      \
+            SNK_AFG_T(LA, LB, TA, float, double, a.F32, a.prims);                                       \
+        else                                                                                            \
+            SNK_AFG_T(LA, LB, TA, double, double, a.F, a.prims);                                        \
+    }
     switch (la * 3 + lb) {
-        case 0: SNK_AFG(0, 0, kTileA[0]); break;
-        case 3: SNK_AFG(1, 0, kTileA[1]); break;
-        case 4: SNK_AFG(1, 1, kTileA[2]); break;
-        case 6: SNK_AFG(2, 0, kTileA[3]); break;
-        case 7: SNK_AFG(2, 1, kTileA[4]); break;
-        case 8: SNK_AFG(2, 2, kTileA[5]); break;
+        case 0: SNK_AFG(0, 0, kTileA[0], kTileA32[0]); break;
+        case 3: SNK_AFG(1, 0, kTileA[1], kTileA32[1]); break;
+        case 4: SNK_AFG(1, 1, kTileA[2], kTileA32[2]); break;
+        case 6: SNK_AFG(2, 0, kTileA[3], kTileA32[3]); break;
+        case 7: SNK_AFG(2, 1, kTileA[4], kTileA32[4]); break;
+        case 8: SNK_AFG(2, 2, kTileA[5], kTileA32[5]); break;
         default: return hipErrorInvalidValue;
     }
 #undef SNK_AFG
+#undef SNK_AFG_T
     return hipGetLastError();
 }
 

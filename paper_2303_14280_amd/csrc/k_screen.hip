@@ -27,6 +27,7 @@ namespace {
 using namespace os3c;
 
 constexpr int kNoBin = -100000;     // U == 0
+constexpr int kGroup = 32;          // diagonal-bound shells per barrier
 
 // ---------------------------------------------------------------------------------------
 // U_A for the shells of one angular momentum L: one workgroup per batch, lane = point.
@@ -41,13 +42,13 @@ __global__ __launch_bounds__(256) void diag_bound_kernel(const double* __restric
                                                          const int32_t* __restrict__ dpb,   // [n] prim_begin of (A,A)
                                                          const int32_t* __restrict__ dnp,   // [n] nprim of (A,A)
                                                          int32_t n, double* __restrict__ U,
-                                                         double* __restrict__ Nf, int32_t nshell,
+                                                         float2* __restrict__ lun, int32_t nshell,
                                                          const double* __restrict__ gtab)
 {
     constexpr int N = ncart(L);
     __shared__ double tab[kBoysRows * kBoysCols];
-    __shared__ double part[2][4];
-    __shared__ double npart[2][4];
+    __shared__ double part[kGroup][4];
+    __shared__ double npart[kGroup][4];
     for (int i = threadIdx.x; i < kBoysRows * kBoysCols; i += blockDim.x) tab[i] = gtab[i];
     __syncthreads();
     const int batch = blockIdx.x;
@@ -55,32 +56,41 @@ __global__ __launch_bounds__(256) void diag_bound_kernel(const double* __restric
     const double cx = px[col], cy = py[col], cz = pz[col], w = pw[col];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const double AB[3] = {0.0, 0.0, 0.0};
-    for (int s = 0; s < n; ++s) {
-        const int row = drow[s];
-        double Ab[N][N];
-        pair_block<L, L>(prims + dpb[s], dnp[s], AB, cx, cy, cz, tab, Ab);
-        double t = 0.0, f2 = 0.0;
-        sfor<0, N>([&](auto cc) {
-            constexpr int c = CV(cc);
-            const double f = cnorm(L, c) * (double)F[(int64_t)(row + c) * ld + col];
-            t += fabs(f) * sqrt(fmax(Ab[c][c], 0.0));    // A_cc of the unit-normalised component
-            f2 += f * f;
-        });
-        double v = w * t * t, q = w * f2;
-        for (int o = 32; o > 0; o >>= 1) {
-            v += __shfl_xor(v, o);
-            q += __shfl_xor(q, o);
-        }
-        if (lane == 0) {
-            part[s & 1][wave] = v;
-            npart[s & 1][wave] = q;
+    // shells in groups of kGroup: per-wave partial sums in LDS, one barrier pair per group
+    for (int s0 = 0; s0 < n; s0 += kGroup) {
+        const int s1 = min(n, s0 + kGroup);
+        for (int s = s0; s < s1; ++s) {
+            const int row = drow[s];
+            double Ab[N][N];
+            pair_block<L, L, double>(prims + dpb[s], dnp[s], AB, cx, cy, cz, tab, Ab);
+            double t = 0.0, f2 = 0.0;
+            sfor<0, N>([&](auto cc) {
+                constexpr int c = CV(cc);
+                const double f = cnorm(L, c) * (double)F[(int64_t)(row + c) * ld + col];
+                t += fabs(f) * sqrt(fmax(Ab[c][c], 0.0));    // A_cc of the unit-normalised component
+                f2 += f * f;
+            });
+            double v = w * t * t, q = w * f2;
+            for (int o = 32; o > 0; o >>= 1) {
+                v += __shfl_xor(v, o);
+                q += __shfl_xor(q, o);
+            }
+            if (lane == 0) {
+                part[s - s0][wave] = v;
+                npart[s - s0][wave] = q;
+            }
         }
         __syncthreads();
-        if (threadIdx.x == 0) {
-            const int64_t o = (int64_t)batch * nshell + dsh[s];
-            U[o] = sqrt(part[s & 1][0] + part[s & 1][1] + part[s & 1][2] + part[s & 1][3]);
-            if (Nf) Nf[o] = sqrt(npart[s & 1][0] + npart[s & 1][1] + npart[s & 1][2] + npart[s & 1][3]);
+        if ((int)threadIdx.x < s1 - s0) {
+            const int k = threadIdx.x;
+            const int64_t o = (int64_t)batch * nshell + dsh[s0 + k];
+            const double u = sqrt(part[k][0] + part[k][1] + part[k][2] + part[k][3]);
+            U[o] = u;
+            if (lun)
+                lun[o] = make_float2(learn::lg10(u),
+                                     learn::lg10(sqrt(npart[k][0] + npart[k][1] + npart[k][2] + npart[k][3])));
         }
+        __syncthreads();
     }
 }
 
@@ -120,14 +130,14 @@ struct BoundShared {
     int32_t hist[kNBins];
     double cnt_s[2 * kNBins];
     int32_t aoff[4];
-    int32_t S, bmax;
+    int32_t S, S2, bmax;
     double acc;
     int wsum[4];
     int carry;
 };
 
 __device__ void bound_setup(const double* __restrict__ Ub, int nshell, const int32_t* __restrict__ shell_l,
-                            double eps, int32_t* bins, int32_t* act, BoundShared& sh)
+                            double eps, double eps_low, int32_t* bins, int32_t* act, BoundShared& sh)
 {
     const int tid = threadIdx.x;
     for (int k = tid; k < kNBins; k += blockDim.x) sh.hist[k] = 0;
@@ -173,8 +183,18 @@ __device__ void bound_setup(const double* __restrict__ Ub, int nshell, const int
                 bmax = k;
                 break;
             }
-        if (bmax < 0) S = 1 << 30;                 // every U is zero: nothing to evaluate
+        // bound pairs S .. S2-1 may go to FP32 within eps_low
+        int S2 = S;
+        double low = 0.0;
+        for (int s = S; s < 2 * kNBins; ++s) {
+            const double add = sh.cnt_s[s] * exp2(0.5 * (double)(s - 2 * kBinOff + 2));
+            if (low + add > eps_low) break;
+            low += add;
+            S2 = s + 1;
+        }
+        if (bmax < 0) S = S2 = 1 << 30;            // every U is zero: nothing to evaluate
         sh.S = S;
+        sh.S2 = S2;
         sh.acc = acc;
         sh.bmax = bmax;
         sh.aoff[0] = 0;
@@ -213,7 +233,7 @@ __device__ __forceinline__ int est_bin(float lest)
 // time and runs the network on them in one sweep of matrix-core ops.
 // Dynamic shared memory: bins[nshell] + active[nshell] (int32).
 // ---------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void screen_est_kernel(EstArgs a)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void screen_est_kernel(EstArgs a)
 {
     extern __shared__ int32_t dyn[];
     int32_t* bins = dyn;
@@ -225,65 +245,110 @@ __global__ __launch_bounds__(256) void screen_est_kernel(EstArgs a)
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r = lane & 15, g = lane >> 4;
     const double* Ub = a.U + (int64_t)batch * a.nshell;
-    const double* Nb = a.N + (int64_t)batch * a.nshell;
+    const float2* Lb = a.lun + (int64_t)batch * a.nshell;
     for (int k = tid; k < kNBins; k += blockDim.x) lhist[k] = 0;
-    bound_setup(Ub, a.nshell, a.shell_l, a.eps_batch, bins, act, sh);
+    bound_setup(Ub, a.nshell, a.shell_l, a.eps_batch, 0.0, bins, act, sh);
     const int S = sh.S;
     const BatchGeo bg = a.geo[batch];
 
+    __shared__ __align__(16) short w2s[64 * learn::kW2Ld];
     learn::MlpRegs R;
-    learn::load_mlp(a.params, a.norm, a.lo, a.hi, R);
-    const float ln2_10 = 3.32192809488736f;   // log2(10)
+    learn::load_mlp(a.params, a.norm, a.lo, a.hi, R, w2s);
+    const float log2_10 = 3.32192809488736f;
+    const float mlog2 = a.margin * log2_10;
 
-    for (int c = 0; c < 6; ++c) {
-        const int la = kClassLA_dev(c), lb = kClassLB_dev(c);
-        const int nA = sh.aoff[la + 1] - sh.aoff[la], nB = sh.aoff[lb + 1] - sh.aoff[lb];
-        const int32_t* actA = act + sh.aoff[la];
-        const int32_t* actB = act + sh.aoff[lb];
-        const int64_t ncombo = (int64_t)nA * nB;
-        for (int64_t q = wave; q * 16 < ncombo; q += 4) {
-            const int64_t i = q * 16 + r;
-            bool valid = false;
-            int aa = 0, b = 0;
-            int64_t p = 0;
-            if (i < ncombo) {
-                aa = actA[(int)(i / nB)];
-                b = actB[(int)(i % nB)];
-                if (!(la == lb && aa < b) && bins[aa] + bins[b] >= S) {
-                    p = pair_index(aa, b);
-                    valid = a.pairs[p].nprim > 0;
-                }
+    // one combo index space over the six classes; same-l classes enumerate the triangle
+    // ai >= bi only (the active lists ascend in shell index)
+    __shared__ int64_t coff[7];
+    if (tid == 0) {
+        int64_t acc = 0;
+        for (int c = 0; c < 6; ++c) {
+            const int la = kClassLA_dev(c), lb = kClassLB_dev(c);
+            const int64_t nA = sh.aoff[la + 1] - sh.aoff[la], nB = sh.aoff[lb + 1] - sh.aoff[lb];
+            coff[c] = acc;
+            acc += la == lb ? nA * (nA + 1) / 2 : nA * nB;
+        }
+        coff[6] = acc;
+    }
+    __syncthreads();
+    const int64_t total = coff[6];
+
+    // candidate data of combo i, loaded one chunk ahead of its use
+    struct Cand {
+        bool valid;
+        int aa, b;
+        int64_t p;
+        PairFeat pf;
+        float lp;
+        float2 ua, ub;
+    };
+    auto fetch = [&](int64_t i, Cand& d) {
+        d.valid = false;
+        d.aa = 0;
+        d.b = 0;
+        d.p = 0;
+        if (i < total) {
+            int c = 0;
+            while (c < 5 && i >= coff[c + 1]) ++c;
+            const int la = kClassLA_dev(c), lb = kClassLB_dev(c);
+            const int64_t j = i - coff[c];
+            int ai, bi;
+            if (la == lb) {
+                ai = (int)((sqrtf(8.0f * (float)j + 1.0f) - 1.0f) * 0.5f);
+                while ((int64_t)ai * (ai + 1) / 2 > j) --ai;
+                while ((int64_t)(ai + 1) * (ai + 2) / 2 <= j) ++ai;
+                bi = (int)(j - (int64_t)ai * (ai + 1) / 2);
+            } else {
+                const int nB = sh.aoff[lb + 1] - sh.aoff[lb];
+                ai = (int)(j / nB);
+                bi = (int)(j - (int64_t)ai * nB);
             }
-            if (__ballot(valid) == 0ull) continue;
-            float f[16];
-            const PairFeat pf = a.pfeat[p];
-            learn::block_features(pf, a.lp[p], bg, Ub[aa], Ub[b], Nb[aa], Nb[b], f);
-            float x[4];
-            bool oob = false;
-            for (int e = 0; e < 4; ++e) {
-                // this lane supplies features 4g .. 4g+3 (constant-index selects, no scratch)
-                float v = f[e];
-                v = g == 1 ? f[4 + e] : v;
-                v = g == 2 ? f[8 + e] : v;
-                v = g == 3 ? f[12 + e] : v;
-                x[e] = v;
-                oob |= !(v >= R.lo[e] && v <= R.hi[e]);
+            d.aa = act[sh.aoff[la] + ai];
+            d.b = act[sh.aoff[lb] + bi];
+            if (bins[d.aa] + bins[d.b] >= S) {
+                d.p = pair_index(d.aa, d.b);
+                d.valid = true;
             }
-            const unsigned long long mo = __ballot(oob);
-            const bool sample_oob = ((mo >> r) & 0x0001000100010001ull) != 0ull;
-            const float y = learn::mlp_eval16(R, x);
-            if (g == 0 && valid) {
-                const double beta = (double)pf.cab * Ub[aa] * Ub[b];
-                double est = beta;
-                // a prediction never takes a block with a nonzero bound to a zero estimate
-                if (!sample_oob) est = fmin(beta, fmax(exp2((double)((y + a.margin) * ln2_10)), 1e-300));
-                const float lest = est > 0.0 ? (float)log2(est) : -INFINITY;
-                const int64_t o = (int64_t)batch * a.npair_total + p;
-                a.est[o] = lest;
-                if (a.yraw) a.yraw[o] = y;
-                const int eb = est_bin(lest);
-                if (eb >= 0) atomicAdd(&lhist[eb], 1);
-            }
+        }
+        // loads for every lane (in-bounds defaults for lanes without a candidate)
+        d.valid = d.valid && a.pairs[d.p].nprim > 0;
+        d.pf = a.pfeat[d.p];
+        d.lp = a.lp[d.p];
+        d.ua = Lb[d.aa];
+        d.ub = Lb[d.b];
+    };
+
+    Cand cur, nxt;
+    int64_t q = wave;
+    fetch(q * 16 + r, nxt);
+    for (; q * 16 < total; q += 4) {
+        cur = nxt;
+        fetch((q + 4) * 16 + r, nxt);
+        if (__ballot(cur.valid) == 0ull) continue;
+        float f[16];
+        learn::block_features(cur.pf, cur.lp, bg, cur.ua.x, cur.ub.x, cur.ua.y, cur.ub.y, f);
+        float x[4];
+        bool oob = false;
+        for (int e = 0; e < 4; ++e) {
+            // this lane supplies features 4g .. 4g+3 (constant-index selects, no scratch)
+            float v = f[e];
+            v = g == 1 ? f[4 + e] : v;
+            v = g == 2 ? f[8 + e] : v;
+            v = g == 3 ? f[12 + e] : v;
+            x[e] = v;
+            oob |= !(v >= R.lo[e] && v <= R.hi[e]);
+        }
+        const unsigned long long mo = __ballot(oob);
+        const bool sample_oob = ((mo >> r) & 0x0001000100010001ull) != 0ull;
+        const float y = learn::mlp_eval16(R, w2s, x);
+        if (g == 0 && cur.valid) {
+            // log2 of the bound c_AB U_A U_B (an over-estimate where a factor was clamped)
+            const float lbeta = (learn::log_cab(cur.pf) + cur.ua.x + cur.ub.x) * log2_10;
+            const float lest = sample_oob ? lbeta : fminf(lbeta, fmaf(y, log2_10, mlog2));
+            const int64_t o = (int64_t)batch * a.npair_total + cur.p;
+            a.est[o] = lest;
+            if (a.yraw) a.yraw[o] = y;
+            atomicAdd(&lhist[est_bin(lest)], 1);
         }
     }
     __syncthreads();
@@ -302,7 +367,17 @@ __global__ __launch_bounds__(256) void screen_est_kernel(EstArgs a)
             acc += add;
             T = k + 1;
         }
+        // then the FP32 set: bins T .. T2-1 whose estimates sum to at most eps_low
+        int T2 = T;
+        double low = 0.0;
+        for (int k = T; k < kNBins; ++k) {
+            const double add = (double)lhist[k] * exp2(0.5 * (double)(k + 1 - kBinOff));
+            if (low + add > a.eps_low) break;
+            low += add;
+            T2 = k + 1;
+        }
         a.thr[batch] = T;
+        a.thr2[batch] = T2;
         a.skipped[batch] = sh.acc + acc;
     }
 }
@@ -323,21 +398,33 @@ __global__ __launch_bounds__(256) void screen_kernel(ScreenArgs a)
     const int batch = blockIdx.x;
     const int tid = threadIdx.x;
     const double* Ub = a.U + (int64_t)batch * a.nshell;
-    bound_setup(Ub, a.nshell, a.shell_l, a.eps_batch, bins, act, sh);
-    const int S = sh.S;
     const bool learned = a.est != nullptr;
+    bound_setup(Ub, a.nshell, a.shell_l, a.eps_batch, learned ? 0.0 : a.eps_low, bins, act, sh);
+    const int S = sh.S, S2 = sh.S2;
     const int T = learned ? a.thr[batch] : 0;
+    const int T2 = learned ? a.thr2[batch] : 0;
     const float* estb = learned ? a.est + (int64_t)batch * a.npair_total : nullptr;
-    // block (aa, b) of the batch is evaluated
+    // block (aa, b) of the batch is evaluated in list category cat (0: FP64 or all, 1: FP32)
+    int cat = 0;
     auto keep = [&](int aa, int b) -> bool {
         if (bins[aa] + bins[b] < S) return false;
         const int64_t p = pair_index(aa, b);
         if (a.pairs[p].nprim == 0) return false;
-        return !learned || est_bin(estb[p]) >= T;
+        bool high = true;
+        if (learned) {
+            const int eb = est_bin(estb[p]);
+            if (eb < T) return false;
+            high = eb >= T2;
+        } else {
+            high = bins[aa] + bins[b] >= S2;
+        }
+        return a.nlist == 6 || (cat == 0) == high;
     };
 
-    for (int c = 0; c < 6; ++c) {
-        const int la = kClassLA_dev(c), lb = kClassLB_dev(c), TA = kTileA_dev(c);
+    for (int c = 0; c < a.nlist; ++c) {
+        cat = c / 6;
+        const int cl = c % 6;
+        const int la = kClassLA_dev(cl), lb = kClassLB_dev(cl), TA = kListTile(c);
         const int nA = sh.aoff[la + 1] - sh.aoff[la], nB = sh.aoff[lb + 1] - sh.aoff[lb];
         const int32_t* actA = act + sh.aoff[la];
         const int32_t* actB = act + sh.aoff[lb];
@@ -382,9 +469,9 @@ __global__ __launch_bounds__(256) void screen_kernel(ScreenArgs a)
                     nbt += tilecnt[t];
                     nrun += tilecnt[t] > 0;
                 }
-                a.counts[((int64_t)batch * 6 + c) * 2] = nrun;
-                a.counts[((int64_t)batch * 6 + c) * 2 + 1] = nbt;
-                a.npairs[(int64_t)batch * 6 + c] = (int64_t)(red[0] + red[1] + red[2] + red[3]);
+                a.counts[((int64_t)batch * a.nlist + c) * 2] = nrun;
+                a.counts[((int64_t)batch * a.nlist + c) * 2 + 1] = nbt;
+                a.npairs[(int64_t)batch * a.nlist + c] = (int64_t)(red[0] + red[1] + red[2] + red[3]);
             }
             __syncthreads();
             continue;
@@ -467,21 +554,46 @@ __global__ __launch_bounds__(256) void screen_kernel(ScreenArgs a)
     if (!WRITE && !learned && tid == 0) a.skipped[batch] = sh.acc;
 }
 
-// exclusive scans of the per-(batch, class) counts: run_base / bt_base [6][nbatch+1]
-__global__ void screen_scan_kernel(const int32_t* __restrict__ counts, int32_t nbatch, int64_t* __restrict__ run_base,
-                                   int64_t* __restrict__ bt_base)
+// exclusive scans of the per-(batch, class) counts: run_base / bt_base [6][nbatch+1].
+// One workgroup per class; thread t scans a contiguous segment of batches, the segment
+// totals are scanned in LDS (fixed order, integer sums).
+__global__ __launch_bounds__(256) void screen_scan_kernel(const int32_t* __restrict__ counts, int32_t nbatch,
+                                                          int32_t nlist, int64_t* __restrict__ run_base,
+                                                          int64_t* __restrict__ bt_base)
 {
-    const int c = threadIdx.x;
-    if (c >= 6) return;
+    __shared__ int64_t sr[256], sb[256];
+    const int c = blockIdx.x, t = threadIdx.x;
+    const int seg = (nbatch + 255) / 256;
+    const int j0 = min(nbatch, t * seg), j1 = min(nbatch, j0 + seg);
     int64_t r = 0, b = 0;
-    for (int j = 0; j < nbatch; ++j) {
+    for (int j = j0; j < j1; ++j) {
+        r += counts[((int64_t)j * nlist + c) * 2];
+        b += counts[((int64_t)j * nlist + c) * 2 + 1];
+    }
+    sr[t] = r;
+    sb[t] = b;
+    __syncthreads();
+    if (t == 0) {
+        int64_t ar = 0, ab = 0;
+        for (int k = 0; k < 256; ++k) {
+            const int64_t xr = sr[k], xb = sb[k];
+            sr[k] = ar;
+            sb[k] = ab;
+            ar += xr;
+            ab += xb;
+        }
+        run_base[(int64_t)c * (nbatch + 1) + nbatch] = ar;
+        bt_base[(int64_t)c * (nbatch + 1) + nbatch] = ab;
+    }
+    __syncthreads();
+    r = sr[t];
+    b = sb[t];
+    for (int j = j0; j < j1; ++j) {
         run_base[(int64_t)c * (nbatch + 1) + j] = r;
         bt_base[(int64_t)c * (nbatch + 1) + j] = b;
-        r += counts[((int64_t)j * 6 + c) * 2];
-        b += counts[((int64_t)j * 6 + c) * 2 + 1];
+        r += counts[((int64_t)j * nlist + c) * 2];
+        b += counts[((int64_t)j * nlist + c) * 2 + 1];
     }
-    run_base[(int64_t)c * (nbatch + 1) + nbatch] = r;
-    bt_base[(int64_t)c * (nbatch + 1) + nbatch] = b;
 }
 
 }  // namespace
@@ -489,7 +601,7 @@ __global__ void screen_scan_kernel(const int32_t* __restrict__ counts, int32_t n
 hipError_t launch_diag_bound(int l, const double* px, const double* py, const double* pz, const double* pw,
                              const double* F, const float* F32, int64_t ld, const PrimPair* prims, const int32_t* dsh,
                              const int32_t* drow, const int32_t* dpb, const int32_t* dnp, int32_t n, double* U,
-                             double* N, int32_t nshell, int32_t nbatch, const double* tab, hipStream_t s)
+                             float2* N, int32_t nshell, int32_t nbatch, const double* tab, hipStream_t s)
 {
     if (nbatch <= 0 || n <= 0) return hipSuccess;
     dim3 grid(nbatch), block(kBatch);
@@ -529,9 +641,10 @@ hipError_t launch_screen_est(const EstArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_screen_scan(const int32_t* counts, int32_t nbatch, int64_t* run_base, int64_t* bt_base, hipStream_t s)
+hipError_t launch_screen_scan(const int32_t* counts, int32_t nbatch, int32_t nlist, int64_t* run_base,
+                              int64_t* bt_base, hipStream_t s)
 {
-    hipLaunchKernelGGL(screen_scan_kernel, dim3(1), dim3(64), 0, s, counts, nbatch, run_base, bt_base);
+    hipLaunchKernelGGL(screen_scan_kernel, dim3(nlist), dim3(256), 0, s, counts, nbatch, nlist, run_base, bt_base);
     return hipGetLastError();
 }
 

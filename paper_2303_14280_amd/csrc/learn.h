@@ -10,32 +10,34 @@ namespace learn {
 typedef short bf4 __attribute__((ext_vector_type(4)));
 typedef float f4v __attribute__((ext_vector_type(4)));
 
-// nearest bfloat16 (ties to even): bit pattern, and its value as float
+// nearest bfloat16 (ties to even; one hardware conversion on gfx950): bit pattern, and its
+// value as float
 __device__ __forceinline__ unsigned bf16_bits(float x)
 {
-    unsigned u = __float_as_uint(x);
-    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+    return (unsigned)(unsigned short)__builtin_bit_cast(short, (__bf16)x);
 }
 __device__ __forceinline__ float bf16_round(float x) { return __uint_as_float(bf16_bits(x) << 16); }
 
-__device__ __forceinline__ float silu(float z) { return z / (1.0f + __expf(-z)); }
+__device__ __forceinline__ float silu(float z) { return z * __frcp_rn(1.0f + __expf(-z)); }
 
 __device__ __forceinline__ float lg10(double v) { return v > 1e-40 ? (float)log10(v) : -40.0f; }
 
-__device__ __forceinline__ float box_dist(const float* p, const BatchGeo& g)
+// log10 c_AB: 0 for A != B, log10(1/2) for A == B
+__device__ __forceinline__ float log_cab(const PairFeat& pf) { return pf.cab < 1.0f ? -0.30102999566f : 0.0f; }
+
+__device__ __forceinline__ float box_dist(float x, float y, float z, const BatchGeo& g)
 {
-    float s = 0.0f;
-    for (int d = 0; d < 3; ++d) {
-        const float e = fmaxf(fmaxf(g.lo[d] - p[d], p[d] - g.hi[d]), 0.0f);
-        s = fmaf(e, e, s);
-    }
-    return sqrtf(s);
+    const float ex = fmaxf(fmaxf(g.lo[0] - x, x - g.hi[0]), 0.0f);
+    const float ey = fmaxf(fmaxf(g.lo[1] - y, y - g.hi[1]), 0.0f);
+    const float ez = fmaxf(fmaxf(g.lo[2] - z, z - g.hi[2]), 0.0f);
+    return sqrtf(fmaf(ex, ex, fmaf(ey, ey, ez * ez)));
 }
 
 // Features of block (pair, batch): pair constants, batch geometry, and the batch's F norms
-// and bound factors of the two shells.
-__device__ __forceinline__ void block_features(const PairFeat& pf, float lp, const BatchGeo& bg, double UA,
-                                               double UB, double NA, double NB, float f[16])
+// and bound factors of the two shells, given as log10 (lU = log10 U, lN = log10 N, each
+// clamped below at -40).
+__device__ __forceinline__ void block_features(const PairFeat& pf, float lp, const BatchGeo& bg, float lUA,
+                                               float lUB, float lNA, float lNB, float f[16])
 {
     f[0] = pf.la;
     f[1] = pf.lb;
@@ -44,14 +46,14 @@ __device__ __forceinline__ void block_features(const PairFeat& pf, float lp, con
     f[4] = pf.ab;
     f[5] = pf.lq;
     f[6] = lp;
-    f[7] = box_dist(pf.pc, bg);
+    f[7] = box_dist(pf.pc[0], pf.pc[1], pf.pc[2], bg);
     f[8] = bg.hd;
-    f[9] = box_dist(pf.a, bg);
-    f[10] = box_dist(pf.b, bg);
+    f[9] = box_dist(pf.a[0], pf.a[1], pf.a[2], bg);
+    f[10] = box_dist(pf.b[0], pf.b[1], pf.b[2], bg);
     f[11] = bg.lw;
-    f[12] = lg10(NA);
-    f[13] = lg10(NB);
-    f[14] = lg10((double)pf.cab * UA * UB);
+    f[12] = lNA;
+    f[13] = lNB;
+    f[14] = fmaxf(log_cab(pf) + lUA + lUB, -40.0f);
     const float dx = pf.pc[0] - bg.ctr[0], dy = pf.pc[1] - bg.ctr[1], dz = pf.pc[2] - bg.ctr[2];
     f[15] = sqrtf(dx * dx + dy * dy + dz * dz);
 }
@@ -61,9 +63,10 @@ __device__ __forceinline__ void block_features(const PairFeat& pf, float lp, con
 // product D = A B (checked by the layout probe): lane (r, g) holds A[r][4g..4g+3],
 // B[4g..4g+3][r] and D[4g..4g+3][r].  So the samples are the columns, a layer's output
 // tile is directly the next layer's B operand, and each lane supplies features 4g..4g+3.
+constexpr int kW2Ld = 68;   // LDS row stride (bf16 elements) of W2: 136 B spreads the rows over the banks
+
 struct MlpRegs {
     bf4 w1[4];          // W1[16m + r][4g + e]
-    bf4 w2[4][4];       // W2[16m2 + r][16m + 4g + e]
     f4v b1[4], b2[4];   // b[16m + 4g + e]
     float w3[4][4];     // W3[16m + 4g + e]
     float b3;
@@ -73,11 +76,13 @@ struct MlpRegs {
 __device__ __forceinline__ short bfs(float x) { return (short)bf16_bits(x); }
 
 // Parameters are bf16-rounded on load (weights and biases), as in the inference form of the
-// standalone forward kernel.
+// standalone forward kernel.  W2 goes to LDS (w2s, 64 rows of kW2Ld; the whole workgroup
+// stores it, the caller synchronises before the first use), the rest to registers.
 __device__ inline void load_mlp(const float* __restrict__ params, const MlpNorm& nrm, const float* lo,
-                                const float* hi, MlpRegs& R)
+                                const float* hi, MlpRegs& R, short* w2s)
 {
-    constexpr int OW1 = 0, OB1 = 1024, OW2 = 1088, OB2 = 5184, OW3 = 5248, OB3 = 5312;
+    for (int i = threadIdx.x; i < 64 * 64; i += blockDim.x) w2s[(i >> 6) * kW2Ld + (i & 63)] = bfs(params[1088 + i]);
+    constexpr int OW1 = 0, OB1 = 1024, OB2 = 5184, OW3 = 5248, OB3 = 5312;   // W2 at 1088
     const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
     for (int m = 0; m < 4; ++m) {
         for (int e = 0; e < 4; ++e) {
@@ -86,8 +91,6 @@ __device__ inline void load_mlp(const float* __restrict__ params, const MlpNorm&
             R.b2[m][e] = bf16_round(params[OB2 + 16 * m + 4 * g + e]);
             R.w3[m][e] = bf16_round(params[OW3 + 16 * m + 4 * g + e]);
         }
-        for (int k = 0; k < 4; ++k)
-            for (int e = 0; e < 4; ++e) R.w2[m][k][e] = bfs(params[OW2 + (16 * m + r) * 64 + 16 * k + 4 * g + e]);
     }
     R.b3 = bf16_round(params[OB3]);
     for (int e = 0; e < 4; ++e) {
@@ -100,8 +103,9 @@ __device__ inline void load_mlp(const float* __restrict__ params, const MlpNorm&
 
 // x: raw features 4g..4g+3 of sample r.  Returns the network output of sample r in every
 // lane that holds sample r (all of the wave's lanes take part).
-__device__ inline float mlp_eval16(const MlpRegs& R, const float x[4])
+__device__ inline float mlp_eval16(const MlpRegs& R, const short* w2s, const float x[4])
 {
+    const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
     bf4 xb;
     for (int e = 0; e < 4; ++e) xb[e] = bfs((x[e] - R.mean[e]) * R.istd[e]);
     bf4 h1[4];
@@ -112,7 +116,10 @@ __device__ inline float mlp_eval16(const MlpRegs& R, const float x[4])
     float y = 0.0f;
     for (int m2 = 0; m2 < 4; ++m2) {
         f4v acc = R.b2[m2];
-        for (int m = 0; m < 4; ++m) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(R.w2[m2][m], h1[m], acc, 0, 0, 0);
+        for (int m = 0; m < 4; ++m) {
+            const bf4 w = *reinterpret_cast<const bf4*>(w2s + (16 * m2 + r) * kW2Ld + 16 * m + 4 * g);
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w, h1[m], acc, 0, 0, 0);
+        }
         for (int e = 0; e < 4; ++e) y = fmaf(R.w3[m2][e], bf16_round(silu(acc[e])), y);
     }
     y += __shfl_xor(y, 16);

@@ -56,44 +56,49 @@ __device__ __forceinline__ void sfor(Fn&& f)
 
 // F_m(T), m = 0..L (Eq. boys).  T < kBoysTmax: Taylor series about the nearest
 // table node, F_m(T) = sum_j F_{m+j}(T_k) (T_k - T)^j / j!  (dF_m/dT = -F_{m+1});
-// above: F_0 = sqrt(pi/T)/2, F_m = F_{m-1} (2m-1)/(2T).
-template <int L>
-__device__ __forceinline__ void boys(double T, const double* __restrict__ tab, double (&F)[L + 1])
+// above: F_0 = sqrt(pi/T)/2, F_m = F_{m-1} (2m-1)/(2T).  R = double uses kBoysTerms
+// terms; R = float (reduced-precision blocks) uses 7, whose truncation error
+// (1/8)^7 / 7! ~ 1e-10 is far below FP32 rounding.
+template <typename R>
+constexpr int boys_terms() { return std::is_same<R, double>::value ? kBoysTerms : 7; }
+
+template <int L, typename R>
+__device__ __forceinline__ void boys(R T, const R* __restrict__ tab, R (&F)[L + 1])
 {
-    if (T < kBoysTmax) {
-        const int k = (int)(T * (1.0 / kBoysStep) + 0.5);
-        const double d = k * kBoysStep - T;
-        const double* row = tab + k * kBoysCols;
-        double pw[kBoysTerms];
-        pw[0] = 1.0;
-        sfor<1, kBoysTerms>([&](auto jc) {
+    constexpr int NT = boys_terms<R>();
+    if (T < (R)kBoysTmax) {
+        const int k = (int)(T * (R)(1.0 / kBoysStep) + (R)0.5);
+        const R d = (R)k * (R)kBoysStep - T;
+        const R* row = tab + k * kBoysCols;
+        R pw[NT];
+        pw[0] = (R)1;
+        sfor<1, NT>([&](auto jc) {
             constexpr int j = CV(jc);
-            pw[j] = pw[j - 1] * (d * (1.0 / j));
+            pw[j] = pw[j - 1] * (d * (R)(1.0 / j));
         });
         sfor<0, L + 1>([&](auto mc) {
             constexpr int m = CV(mc);
-            double s = row[m + kBoysTerms - 1] * pw[kBoysTerms - 1];
-            sfor<0, kBoysTerms - 1>([&](auto jc) {
-                constexpr int j = kBoysTerms - 2 - CV(jc);
+            R s = row[m + NT - 1] * pw[NT - 1];
+            sfor<0, NT - 1>([&](auto jc) {
+                constexpr int j = NT - 2 - CV(jc);
                 s = fma(row[m + j], pw[j], s);
             });
             F[m] = s;
         });
     } else {
-        const double r = rsqrt(T);
-        const double h = 0.5 * r * r;
-        F[0] = 0.88622692545275801365 * r;
+        const R r = rsqrt(T);
+        const R h = (R)0.5 * r * r;
+        F[0] = (R)0.88622692545275801365 * r;
         sfor<1, L + 1>([&](auto mc) {
             constexpr int m = CV(mc);
-            F[m] = F[m - 1] * ((2 * m - 1) * h);
+            F[m] = F[m - 1] * ((R)(2 * m - 1) * h);
         });
     }
 }
 
 // Eq. vrr: Theta^n_{a+1q} = PA_q Theta^n_a - PC_q Theta^{n+1}_a + a_q/(2 zeta_p) (Theta^n_{a-1q} - Theta^{n+1}_{a-1q})
-template <int L>
-__device__ __forceinline__ void vrr(double (&th)[L + 1][L + 1][16], const double (&PA)[3], const double (&PC)[3],
-                                    double oo2zp)
+template <int L, typename R>
+__device__ __forceinline__ void vrr(R (&th)[L + 1][L + 1][16], const R (&PA)[3], const R (&PC)[3], R oo2zp)
 {
     sfor<1, L + 1>([&](auto lc) {
         constexpr int l = CV(lc);
@@ -105,8 +110,8 @@ __device__ __forceinline__ void vrr(double (&th)[L + 1][L + 1][16], const double
             constexpr int c2 = am > 0 ? lower(l - 1, c1, q) : 0;
             sfor<0, L - l + 1>([&](auto nc) {
                 constexpr int n = CV(nc);
-                double v = PA[q] * th[n][l - 1][c1] - PC[q] * th[n + 1][l - 1][c1];
-                if constexpr (am > 0) v += (am * oo2zp) * (th[n][l - 2][c2] - th[n + 1][l - 2][c2]);
+                R v = PA[q] * th[n][l - 1][c1] - PC[q] * th[n + 1][l - 1][c1];
+                if constexpr (am > 0) v += ((R)am * oo2zp) * (th[n][l - 2][c2] - th[n + 1][l - 2][c2]);
                 th[n][l][c] = v;
             });
         });
@@ -114,11 +119,10 @@ __device__ __forceinline__ void vrr(double (&th)[L + 1][L + 1][16], const double
 }
 
 // Eq. hrr: Xi_{a(b+1q)} = Xi_{(a+1q)b} + AB_q Xi_{ab}, from Xi_{a0} = contracted Theta^0_a
-template <int LA, int LB>
-__device__ __forceinline__ void hrr(const double (&acc)[LA + LB + 1][16], const double (&AB)[3],
-                                    double (&out)[ncart(LA)][ncart(LB)])
+template <int LA, int LB, typename R>
+__device__ __forceinline__ void hrr(const R (&acc)[LA + LB + 1][16], const R (&AB)[3], R (&out)[ncart(LA)][ncart(LB)])
 {
-    double xi[LB + 1][LA + LB + 1][16][6];
+    R xi[LB + 1][LA + LB + 1][16][6];
     sfor<LA, LA + LB + 1>([&](auto lc) {
         constexpr int la = CV(lc);
         sfor<0, ncart(la)>([&](auto cc) { xi[0][la][CV(cc)][0] = acc[la][CV(cc)]; });
@@ -144,38 +148,54 @@ __device__ __forceinline__ void hrr(const double (&acc)[LA + LB + 1][16], const 
     });
 }
 
+// primitive-pair record of the arithmetic type
+template <typename R>
+struct PrimOf;
+template <>
+struct PrimOf<double> {
+    typedef PrimPair type;
+};
+template <>
+struct PrimOf<float> {
+    typedef PrimPair32 type;
+};
+
 // Contracted 3c-CP block A_ab(C) of one shell pair at the lane's point C:
 // Eq. vrr per primitive pair, contraction over primitives, then Eq. hrr.
-template <int LA, int LB>
-__device__ __forceinline__ void pair_block(const PrimPair* __restrict__ pp0, int nprim, const double (&AB)[3],
-                                           double cx, double cy, double cz, const double* __restrict__ tab,
-                                           double (&Ab)[ncart(LA)][ncart(LB)])
+template <int LA, int LB, typename R>
+__device__ __forceinline__ void pair_block(const typename PrimOf<R>::type* __restrict__ pp0, int nprim,
+                                           const R (&AB)[3], R cx, R cy, R cz, const R* __restrict__ tab,
+                                           R (&Ab)[ncart(LA)][ncart(LB)])
 {
+    typedef typename PrimOf<R>::type PP;
     constexpr int L = LA + LB;
-    double acc[L + 1][16];
+    R acc[L + 1][16];
     sfor<LA, L + 1>([&](auto lc) {
-        sfor<0, ncart(CV(lc))>([&](auto cc) { acc[CV(lc)][CV(cc)] = 0.0; });
+        sfor<0, ncart(CV(lc))>([&](auto cc) { acc[CV(lc)][CV(cc)] = (R)0; });
     });
-    // software pipeline: the next primitive pair's record is requested before the
-    // current one is evaluated, so its scalar-load latency overlaps the arithmetic
-    PrimPair nxt{};
-    if (nprim > 0) nxt = pp0[0];
-    for (int k = 0; k < nprim; ++k) {
-        const PrimPair pp = nxt;
-        if (k + 1 < nprim) nxt = pp0[k + 1];
-        const double PC[3] = {pp.Px - cx, pp.Py - cy, pp.Pz - cz};
-        const double PA[3] = {pp.PAx, pp.PAy, pp.PAz};
-        const double T = pp.zp * (PC[0] * PC[0] + PC[1] * PC[1] + PC[2] * PC[2]);
-        double Fm[L + 1];
-        boys<L>(T, tab, Fm);
-        double th[L + 1][L + 1][16];
+    auto prim = [&](const PP& pp) {
+        const R PC[3] = {pp.Px - cx, pp.Py - cy, pp.Pz - cz};
+        const R PA[3] = {pp.PAx, pp.PAy, pp.PAz};
+        const R T = pp.zp * (PC[0] * PC[0] + PC[1] * PC[1] + PC[2] * PC[2]);
+        R Fm[L + 1];
+        boys<L, R>(T, tab, Fm);
+        R th[L + 1][L + 1][16];
         sfor<0, L + 1>([&](auto nc) { th[CV(nc)][0][0] = pp.pref * Fm[CV(nc)]; });
-        vrr<L>(th, PA, PC, pp.oo2zp);
+        vrr<L, R>(th, PA, PC, pp.oo2zp);
         sfor<LA, L + 1>([&](auto lc) {
             sfor<0, ncart(CV(lc))>([&](auto cc) { acc[CV(lc)][CV(cc)] += th[0][CV(lc)][CV(cc)]; });
         });
+    };
+    // software pipeline: the next primitive pair's record is requested before the
+    // current one is evaluated, so its scalar-load latency overlaps the arithmetic
+    PP nxt{};
+    if (nprim > 0) nxt = pp0[0];
+    for (int k = 0; k < nprim; ++k) {
+        const PP pp = nxt;
+        if (k + 1 < nprim) nxt = pp0[k + 1];
+        prim(pp);
     }
-    hrr<LA, LB>(acc, AB, Ab);
+    hrr<LA, LB, R>(acc, AB, Ab);
 }
 
 }  // namespace os3c

@@ -4,6 +4,8 @@
 #include "snk.h"
 #include "snk_internal.h"
 
+#include <rocblas/rocblas.h>
+
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -87,7 +89,8 @@ struct snk_ctx {
     int64_t max_cols = 0;
     int32_t max_nB = 0;
     int nsplit = 1;
-    bool mixed = false;                 // SNK_MIXED: FP32 Phi, P and F; FP32 matrix-core GEMMs
+    bool mixed = false;                 // SNK_MIXED + SNK_FP32_GEMM: FP32 Phi, P and F; FP32 matrix-core GEMMs
+    rocblas_handle blas = nullptr;      // SNK_ROCBLAS (FP64 builds)
     float *d_Phi32 = nullptr, *d_F32 = nullptr, *d_P32 = nullptr;
     double *d_Phi = nullptr, *d_F = nullptr, *d_G = nullptr, *d_part = nullptr, *d_Pg = nullptr;
     double *d_Kt = nullptr, *d_P = nullptr, *d_K = nullptr, *d_partial = nullptr, *d_ex = nullptr;
@@ -111,8 +114,11 @@ struct snk_ctx {
     double* d_skipped = nullptr;
     int64_t* d_run_base = nullptr;
     int64_t* d_bt_base = nullptr;
-    int32_t* d_bro[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-    double* d_N = nullptr;
+    int nlist = 6;                  // screened lists: 6 (FP64), or 12 (FP64 + FP32 per class)
+    int32_t* d_bro[12] = {};
+    int32_t* d_thr2 = nullptr;
+    PrimPair32* d_prims32 = nullptr;
+    float2* d_lun = nullptr;        // [max_group_batches][nshell] log10 U, log10 F norm
 
     // learned screen: static pair features, batch geometry, per-group estimates
     const snk_mlp* mlp = nullptr;
@@ -127,11 +133,11 @@ struct snk_ctx {
     std::vector<int32_t> ne_list;   // pair indices with kept primitive pairs, class order
     int32_t ne_class_off[7] = {0, 0, 0, 0, 0, 0, 0};
     int32_t* d_ne_list = nullptr;
-    int32_t* d_pool_runs[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-    int32_t* d_pool_bt[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-    double* d_pool_ab[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-    int64_t cap_runs[6] = {0, 0, 0, 0, 0, 0};
-    int64_t cap_bt[6] = {0, 0, 0, 0, 0, 0};
+    int32_t* d_pool_runs[12] = {};
+    int32_t* d_pool_bt[12] = {};
+    double* d_pool_ab[12] = {};
+    int64_t cap_runs[12] = {};
+    int64_t cap_bt[12] = {};
 };
 
 namespace {
@@ -504,7 +510,8 @@ int build_groups(snk_ctx* c)
 {
     c->groups.clear();
     // Phi, F and G columns of one batch (Phi and F are FP32 in the mixed build)
-    int64_t per_batch = (int64_t)c->nbf * kBatch * (c->opts.precision == SNK_MIXED ? 16 : 24);
+    const bool f32 = c->opts.precision == SNK_MIXED && (c->opts.flags & SNK_FP32_GEMM);
+    int64_t per_batch = (int64_t)c->nbf * kBatch * (f32 ? 16 : 24);
     if (c->opts.screen == SNK_SCREEN_LEARNED) per_batch += c->npair_total * (int64_t)sizeof(float);
     int64_t budget = c->opts.max_device_bytes;
     if (budget <= 0) {
@@ -635,18 +642,19 @@ int setup_screening(snk_ctx* c)
     for (const auto& g : c->groups) mb = std::max(mb, g.b1 - g.b0);
     c->max_group_batches = mb;
     if ((rc = dalloc(c, &c->d_U, (size_t)mb * c->nshell))) return rc;
-    if ((rc = dalloc(c, &c->d_N, (size_t)mb * c->nshell))) return rc;
+    if ((rc = dalloc(c, &c->d_lun, (size_t)mb * c->nshell))) return rc;
     if ((rc = dalloc(c, &c->d_lp, (size_t)c->npair_total))) return rc;
     if (c->opts.screen == SNK_SCREEN_LEARNED) {
         if ((rc = dalloc(c, &c->d_est, (size_t)mb * c->npair_total))) return rc;
         if ((rc = dalloc(c, &c->d_thr, (size_t)mb))) return rc;
+        if ((rc = dalloc(c, &c->d_thr2, (size_t)mb))) return rc;
     }
-    if ((rc = dalloc(c, &c->d_counts, (size_t)mb * 12))) return rc;
-    if ((rc = dalloc(c, &c->d_npairs, (size_t)mb * 6))) return rc;
+    if ((rc = dalloc(c, &c->d_counts, (size_t)mb * 2 * c->nlist))) return rc;
+    if ((rc = dalloc(c, &c->d_npairs, (size_t)mb * c->nlist))) return rc;
     if ((rc = dalloc(c, &c->d_skipped, (size_t)mb))) return rc;
-    if ((rc = dalloc(c, &c->d_run_base, (size_t)6 * (mb + 1)))) return rc;
-    if ((rc = dalloc(c, &c->d_bt_base, (size_t)6 * (mb + 1)))) return rc;
-    for (int k = 0; k < 6; ++k)
+    if ((rc = dalloc(c, &c->d_run_base, (size_t)c->nlist * (mb + 1)))) return rc;
+    if ((rc = dalloc(c, &c->d_bt_base, (size_t)c->nlist * (mb + 1)))) return rc;
+    for (int k = 0; k < c->nlist; ++k)
         if ((rc = dalloc(c, &c->d_bro[k], (size_t)mb + 1))) return rc;
     return SNK_OK;
 }
@@ -654,7 +662,7 @@ int setup_screening(snk_ctx* c)
 // grow the run / B-task pools of class k to hold nrun runs and nbt B tasks
 int ensure_pools(snk_ctx* c, int k, int64_t nrun, int64_t nbt)
 {
-    const int TA = kTileA[k];
+    const int TA = kListTile(k);
     if (nrun > c->cap_runs[k]) {
         (void)hipFree(c->d_pool_runs[k]);
         const int64_t cap = std::max<int64_t>(nrun + nrun / 4, 1024);
@@ -721,7 +729,7 @@ void free_ctx(snk_ctx* c)
     (void)hipFree(c->d_shell_l);
     (void)hipFree(c->d_shell_row);
     (void)hipFree(c->d_U);
-    (void)hipFree(c->d_N);
+    (void)hipFree(c->d_lun);
     (void)hipFree(c->d_pfeat);
     (void)hipFree(c->d_pa);
     (void)hipFree(c->d_pb);
@@ -729,18 +737,21 @@ void free_ctx(snk_ctx* c)
     (void)hipFree(c->d_lp);
     (void)hipFree(c->d_est);
     (void)hipFree(c->d_thr);
+    (void)hipFree(c->d_thr2);
+    (void)hipFree(c->d_prims32);
     (void)hipFree(c->d_ne_list);
     (void)hipFree(c->d_counts);
     (void)hipFree(c->d_npairs);
     (void)hipFree(c->d_skipped);
     (void)hipFree(c->d_run_base);
     (void)hipFree(c->d_bt_base);
-    for (int k = 0; k < 6; ++k) {
+    for (int k = 0; k < 12; ++k) {
         (void)hipFree(c->d_bro[k]);
         (void)hipFree(c->d_pool_runs[k]);
         (void)hipFree(c->d_pool_bt[k]);
         (void)hipFree(c->d_pool_ab[k]);
     }
+    if (c->blas) (void)rocblas_destroy_handle(c->blas);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
@@ -810,6 +821,8 @@ int snk_ctx_create(const snk_basis* basis, const snk_grid* grid, const double* w
     if (!isfin(o.eps_basis) || o.eps_basis < 0.0) return arg_error(nullptr, "eps_basis must be >= 0");
     if (o.screen != SNK_SCREEN_NONE && (!isfin(o.eps_skip_energy) || o.eps_skip_energy < 0.0))
         return arg_error(nullptr, "eps_skip_energy must be finite and >= 0");
+    if (o.flags & ~(uint32_t)(SNK_DEVICE_PTRS | SNK_VALIDATE | SNK_ROCBLAS | SNK_FP32_GEMM))
+        return arg_error(nullptr, "unknown flag");
     if (o.screen == SNK_SCREEN_LEARNED) {
         if (!o.screener) return arg_error(nullptr, "SNK_SCREEN_LEARNED needs a screener network");
         float lo[16], hi[16], margin;
@@ -827,7 +840,7 @@ int snk_ctx_create(const snk_basis* basis, const snk_grid* grid, const double* w
     if (!c) return SNK_E_NOMEM;
     c->opts = o;
     c->device = o.device;
-    c->mixed = o.precision == SNK_MIXED;
+    c->mixed = o.precision == SNK_MIXED && (o.flags & SNK_FP32_GEMM);
     {
         hipError_t e = hipSetDevice(c->device);
         if (e != hipSuccess) {
@@ -888,6 +901,17 @@ int snk_ctx_create(const snk_basis* basis, const snk_grid* grid, const double* w
     build_pairs(c);
     CREATE_CHECK(upload(c, &c->d_pairs, c->pairs));
     CREATE_CHECK(upload(c, &c->d_prims, c->prims));
+    // the mixed build evaluates the screen's small blocks in FP32
+    c->nlist = (o.precision == SNK_MIXED && o.screen != SNK_SCREEN_NONE) ? 12 : 6;
+    if (c->nlist == 12) {
+        std::vector<PrimPair32> p32(c->prims.size());
+        for (size_t k = 0; k < c->prims.size(); ++k) {
+            const PrimPair& q = c->prims[k];
+            p32[k] = PrimPair32{(float)q.Px, (float)q.Py, (float)q.Pz, (float)q.zp, (float)q.pref,
+                                (float)q.PAx, (float)q.PAy, (float)q.PAz, (float)q.oo2zp, 0.0f};
+        }
+        CREATE_CHECK(upload(c, &c->d_prims32, p32));
+    }
     CREATE_CHECK(build_pair_feats(c));
     c->mlp = o.screen == SNK_SCREEN_LEARNED ? o.screener : nullptr;
     CREATE_CHECK(build_runs(c));
@@ -920,6 +944,16 @@ int snk_ctx_create(const snk_basis* basis, const snk_grid* grid, const double* w
     CREATE_CHECK(dalloc(c, &c->d_partial, (size_t)c->nfinish));
     CREATE_CHECK(dalloc(c, &c->d_ex, 1));
     if (o.screen != SNK_SCREEN_NONE) CREATE_CHECK(setup_screening(c));
+    if ((o.flags & SNK_ROCBLAS) && !c->mixed && c->max_cols <= INT32_MAX && (int64_t)c->nbf <= INT32_MAX) {
+        if (rocblas_create_handle(&c->blas) != rocblas_status_success ||
+            rocblas_set_stream(c->blas, c->stream) != rocblas_status_success ||
+            rocblas_set_atomics_mode(c->blas, rocblas_atomics_not_allowed) != rocblas_status_success) {
+            set_err(c, "rocBLAS handle set-up failed");
+            g_last_error = c->err;
+            free_ctx(c);
+            return SNK_E_DEVICE;
+        }
+    }
 #undef CREATE_CHECK
     *out = c;
     return SNK_OK;
@@ -941,6 +975,7 @@ struct GroupStats {
     int64_t pp[6] = {0, 0, 0, 0, 0, 0};    // shell-pair x point units evaluated
     int64_t ppp[6] = {0, 0, 0, 0, 0, 0};   // primitive-pair x point units evaluated
     int64_t cand = 0;                       // units before density screening
+    int64_t low = 0;                        // units evaluated in FP32
     double skipped = 0.0;                   // bound on the energy of the skipped blocks
 };
 
@@ -975,7 +1010,18 @@ int group_F(snk_ctx* c, const Group& g, const double* dP, bool timed)
         Pg = c->d_Pg;
         ldp = g.nB;
     }
-    HIPCHECK(c, launch_gemm_f64(nbf, g.ncols, g.nB, Pg, ldp, c->d_Phi, ld, false, c->d_F, ld, 1, 0, s));
+    if (c->blas) {
+        // column-major view: F^T (ncols x nbf) = Phi^T (ncols x nB) P_g^T (nB x nbf)
+        const double one = 1.0, zero = 0.0;
+        if (rocblas_dgemm(c->blas, rocblas_operation_none, rocblas_operation_none, (rocblas_int)g.ncols,
+                          (rocblas_int)nbf, (rocblas_int)g.nB, &one, c->d_Phi, (rocblas_int)ld, Pg,
+                          (rocblas_int)ldp, &zero, c->d_F, (rocblas_int)ld) != rocblas_status_success) {
+            set_err(c, "rocblas_dgemm (F) failed");
+            return SNK_E_DEVICE;
+        }
+    } else {
+        HIPCHECK(c, launch_gemm_f64(nbf, g.ncols, g.nB, Pg, ldp, c->d_Phi, ld, false, c->d_F, ld, 1, 0, s));
+    }
     if (timed) HIPCHECK(c, hipEventRecord(c->ev[2], s));
     return SNK_OK;
 }
@@ -988,7 +1034,7 @@ int group_bounds(snk_ctx* c, const Group& g)
         HIPCHECK(c, launch_diag_bound(l, c->d_px + off, c->d_py + off, c->d_pz + off, c->d_pw + off, c->d_F,
                                       c->mixed ? c->d_F32 : nullptr, g.ncols,
                                       c->d_prims, c->d_diag_sh[l], c->d_diag_row[l], c->d_diag_pb[l],
-                                      c->d_diag_np[l], c->n_diag[l], c->d_U, c->d_N, c->nshell, g.b1 - g.b0,
+                                      c->d_diag_np[l], c->n_diag[l], c->d_U, c->d_lun, c->nshell, g.b1 - g.b0,
                                       c->d_boys, c->stream));
     return SNK_OK;
 }
@@ -1013,7 +1059,7 @@ int group_until_G(snk_ctx* c, const Group& g, const double* dP, bool timed, Grou
         gpts += c->batch_npts[b];
     }
     for (int cl = 0; cl < 6; ++cl) gs->cand += c->ntask[cl] * gpts;
-    int64_t total_runs[6] = {0, 0, 0, 0, 0, 0};
+    int64_t total_runs[12] = {};
     if (screen) {
         if (timed) HIPCHECK(c, hipEventRecord(c->ev[7], s));
         {
@@ -1021,10 +1067,13 @@ int group_until_G(snk_ctx* c, const Group& g, const double* dP, bool timed, Grou
             if (rc) return rc;
         }
         const double eps_batch = c->opts.eps_skip_energy / std::max(1, c->nbatch);
+        // FP32 blocks: estimates summing to at most eps_lowprec / kLowRelErr per build
+        const double eps_low =
+            c->nlist == 12 ? c->opts.eps_lowprec_energy / kLowRelErr / std::max(1, c->nbatch) : 0.0;
         if (c->mlp) {
             EstArgs ea{};
             ea.U = c->d_U;
-            ea.N = c->d_N;
+            ea.lun = c->d_lun;
             ea.nshell = c->nshell;
             ea.nbatch = nb;
             ea.shell_l = c->d_shell_l;
@@ -1041,6 +1090,8 @@ int group_until_G(snk_ctx* c, const Group& g, const double* dP, bool timed, Grou
             ea.est = c->d_est;
             ea.yraw = yraw;
             ea.thr = c->d_thr;
+            ea.eps_low = eps_low;
+            ea.thr2 = c->d_thr2;
             ea.skipped = c->d_skipped;
             HIPCHECK(c, launch_screen_est(ea, s));
         }
@@ -1052,8 +1103,11 @@ int group_until_G(snk_ctx* c, const Group& g, const double* dP, bool timed, Grou
         sa.shell_row = c->d_shell_row;
         sa.pairs = c->d_pairs;
         sa.eps_batch = eps_batch;
+        sa.eps_low = eps_low;
+        sa.nlist = c->nlist;
         sa.est = c->mlp ? c->d_est : nullptr;
         sa.thr = c->mlp ? c->d_thr : nullptr;
+        sa.thr2 = c->mlp ? c->d_thr2 : nullptr;
         sa.npair_total = c->npair_total;
         sa.counts = c->d_counts;
         sa.npairs = c->d_npairs;
@@ -1061,27 +1115,30 @@ int group_until_G(snk_ctx* c, const Group& g, const double* dP, bool timed, Grou
         sa.run_base = c->d_run_base;
         sa.bt_base = c->d_bt_base;
         HIPCHECK(c, launch_screen(false, sa, s));
-        HIPCHECK(c, launch_screen_scan(c->d_counts, nb, c->d_run_base, c->d_bt_base, s));
-        std::vector<int64_t> rb(6 * (size_t)(nb + 1)), bb(6 * (size_t)(nb + 1)), npair((size_t)nb * 6);
+        const int NL = c->nlist;
+        HIPCHECK(c, launch_screen_scan(c->d_counts, nb, NL, c->d_run_base, c->d_bt_base, s));
+        std::vector<int64_t> rb(NL * (size_t)(nb + 1)), bb(NL * (size_t)(nb + 1)), npair((size_t)nb * NL);
         std::vector<double> skipped(nb);
         HIPCHECK(c, hipMemcpyAsync(rb.data(), c->d_run_base, rb.size() * sizeof(int64_t), hipMemcpyDeviceToHost, s));
         HIPCHECK(c, hipMemcpyAsync(bb.data(), c->d_bt_base, bb.size() * sizeof(int64_t), hipMemcpyDeviceToHost, s));
         HIPCHECK(c, hipMemcpyAsync(npair.data(), c->d_npairs, npair.size() * sizeof(int64_t), hipMemcpyDeviceToHost, s));
         HIPCHECK(c, hipMemcpyAsync(skipped.data(), c->d_skipped, skipped.size() * sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHECK(c, hipStreamSynchronize(s));
-        for (int cl = 0; cl < 6; ++cl) {
-            total_runs[cl] = rb[(size_t)cl * (nb + 1) + nb];
-            int rc = ensure_pools(c, cl, total_runs[cl], bb[(size_t)cl * (nb + 1) + nb]);
+        for (int k = 0; k < NL; ++k) {
+            const int cl = k % 6;
+            total_runs[k] = rb[(size_t)k * (nb + 1) + nb];
+            int rc = ensure_pools(c, k, total_runs[k], bb[(size_t)k * (nb + 1) + nb]);
             if (rc) return rc;
-            sa.runs[cl] = c->d_pool_runs[cl];
-            sa.btasks[cl] = c->d_pool_bt[cl];
-            sa.btask_ab[cl] = c->d_pool_ab[cl];
-            sa.batch_run_off[cl] = c->d_bro[cl];
+            sa.runs[k] = c->d_pool_runs[k];
+            sa.btasks[k] = c->d_pool_bt[k];
+            sa.btask_ab[k] = c->d_pool_ab[k];
+            sa.batch_run_off[k] = c->d_bro[k];
             const double avg_prims = c->ntask[cl] ? (double)c->task_prims[cl] / (double)c->ntask[cl] : 0.0;
             for (int j = 0; j < nb; ++j) {
-                const int64_t u = npair[(size_t)j * 6 + cl] * npts[j];
+                const int64_t u = npair[(size_t)j * NL + k] * npts[j];
                 gs->pp[cl] += u;
                 gs->ppp[cl] += (int64_t)(avg_prims * (double)u);
+                if (k >= 6) gs->low += u;
             }
         }
         for (int j = 0; j < nb; ++j) gs->skipped += skipped[j];
@@ -1107,25 +1164,30 @@ int group_until_G(snk_ctx* c, const Group& g, const double* dP, bool timed, Grou
     a.ld = ld;
     a.pairs = c->d_pairs;
     a.prims = c->d_prims;
+    a.prims32 = c->d_prims32;
     a.nbatch = nb;
     a.boys_tab = c->d_boys;
     for (int cl = 0; cl < 6; ++cl) {
-        if (total_runs[cl] == 0) continue;
-        if (screen) {
-            a.runs = c->d_pool_runs[cl];
-            a.btasks = c->d_pool_bt[cl];
-            a.btask_ab = c->d_pool_ab[cl];
-            a.batch_run_off = c->d_bro[cl];
-            a.nrun = 0;
-        } else {
-            a.runs = c->d_runs[cl];
-            a.btasks = c->d_btasks[cl];
-            a.btask_ab = c->d_btask_ab[cl];
-            a.batch_run_off = nullptr;
-            a.nrun = c->nrun[cl];
-        }
         if (timed) HIPCHECK(c, hipEventRecord(c->ev[8 + cl], s));
-        HIPCHECK(c, launch_afg(kClassLA[cl], kClassLB[cl], a, s));
+        // the class's FP64 list, then (mixed build) its FP32 list
+        for (int k = cl; k < (screen ? c->nlist : 6); k += 6) {
+            if (total_runs[k] == 0) continue;
+            if (screen) {
+                a.runs = c->d_pool_runs[k];
+                a.btasks = c->d_pool_bt[k];
+                a.btask_ab = c->d_pool_ab[k];
+                a.batch_run_off = c->d_bro[k];
+                a.nrun = 0;
+            } else {
+                a.runs = c->d_runs[cl];
+                a.btasks = c->d_btasks[cl];
+                a.btask_ab = c->d_btask_ab[cl];
+                a.batch_run_off = nullptr;
+                a.nrun = c->nrun[cl];
+            }
+            a.lowp = k >= 6;
+            HIPCHECK(c, launch_afg(kClassLA[cl], kClassLB[cl], a, s));
+        }
         if (timed) HIPCHECK(c, hipEventRecord(c->ev[cl == 5 ? 15 : 9 + cl], s));
     }
     if (timed) HIPCHECK(c, hipEventRecord(c->ev[3], s));
@@ -1185,14 +1247,41 @@ int snk_ctx_build(snk_ctx* c, const double* P, double* K_out, snk_stats* stats)
         if (rc) return rc;
         // Eq. usym_k: Kt[:, B_g] += G_g Phi_g^T, split over grid points
         const int64_t stride = nbf * g.nB;
-        if (c->mixed)
-            HIPCHECK(c, launch_gemm_f32_dA(nbf, g.nB, g.ncols, c->d_G, ld, c->d_Phi32, ld, true, c->d_part, g.nB,
-                                           c->nsplit, stride, s));
-        else
-            HIPCHECK(c, launch_gemm_f64(nbf, g.nB, g.ncols, c->d_G, ld, c->d_Phi, ld, true, c->d_part, g.nB,
-                                        c->nsplit, stride, s));
-        HIPCHECK(c, launch_reduce_scatter(c->d_part, c->nsplit, stride, nbf, g.nB, nullptr,
-                                          g.all_functions ? nullptr : g.d_coll_fn, c->d_Kt, nbf, s));
+        if (c->blas) {
+            // split over whole batches of points; column-major view of chunk z:
+            // part_z^T (nB x nbf) = Phi_z (nB x kchunk) G_z^T (kchunk x nbf), i.e. part_z = G_z Phi_z^T
+            const int nb = g.b1 - g.b0;
+            const int bpc = (nb + c->nsplit - 1) / c->nsplit;
+            const int64_t kchunk = (int64_t)bpc * kBatch;
+            const int nfull = nb / bpc, rem = nb - nfull * bpc;
+            const double one = 1.0, zero = 0.0;
+            rocblas_status st = rocblas_status_success;
+            if (nfull > 0)
+                st = rocblas_dgemm_strided_batched(c->blas, rocblas_operation_transpose, rocblas_operation_none,
+                                                   (rocblas_int)g.nB, (rocblas_int)nbf, (rocblas_int)kchunk, &one,
+                                                   c->d_Phi, (rocblas_int)ld, kchunk, c->d_G, (rocblas_int)ld, kchunk,
+                                                   &zero, c->d_part, (rocblas_int)g.nB, stride, nfull);
+            if (st == rocblas_status_success && rem > 0)
+                st = rocblas_dgemm(c->blas, rocblas_operation_transpose, rocblas_operation_none, (rocblas_int)g.nB,
+                                   (rocblas_int)nbf, (rocblas_int)(rem * kBatch), &one, c->d_Phi + nfull * kchunk,
+                                   (rocblas_int)ld, c->d_G + nfull * kchunk, (rocblas_int)ld, &zero,
+                                   c->d_part + nfull * stride, (rocblas_int)g.nB);
+            if (st != rocblas_status_success) {
+                set_err(c, "rocblas_dgemm (K) failed");
+                return SNK_E_DEVICE;
+            }
+            HIPCHECK(c, launch_reduce_scatter(c->d_part, nfull + (rem > 0), stride, nbf, g.nB, nullptr,
+                                              g.all_functions ? nullptr : g.d_coll_fn, c->d_Kt, nbf, s));
+        } else {
+            if (c->mixed)
+                HIPCHECK(c, launch_gemm_f32_dA(nbf, g.nB, g.ncols, c->d_G, ld, c->d_Phi32, ld, true, c->d_part,
+                                               g.nB, c->nsplit, stride, s));
+            else
+                HIPCHECK(c, launch_gemm_f64(nbf, g.nB, g.ncols, c->d_G, ld, c->d_Phi, ld, true, c->d_part, g.nB,
+                                            c->nsplit, stride, s));
+            HIPCHECK(c, launch_reduce_scatter(c->d_part, c->nsplit, stride, nbf, g.nB, nullptr,
+                                              g.all_functions ? nullptr : g.d_coll_fn, c->d_Kt, nbf, s));
+        }
         if (timed) {
             HIPCHECK(c, hipEventRecord(c->ev[4], s));
             HIPCHECK(c, hipEventSynchronize(c->ev[4]));
@@ -1242,6 +1331,7 @@ int snk_ctx_build(snk_ctx* c, const double* P, double* K_out, snk_stats* stats)
         }
         stats->t_screen_ms = tscr;
         stats->pair_points_skipped = gs.cand - evaluated;
+        stats->pair_points_lowprec = gs.low;
         stats->skipped_bound = gs.skipped;
         stats->n_batches = c->nbatch;
         stats->n_groups = (int32_t)c->groups.size();
@@ -1351,7 +1441,7 @@ int snk_ctx_block_data(snk_ctx* c, const double* P, float* features, double* blo
         const int nb = g.b1 - g.b0;
         if (features)
             HIPCHECK(c, launch_block_features(c->d_ne_list, c->d_pa, c->d_pb, (int32_t)ldk, c->d_pfeat, c->d_lp,
-                                              c->d_geo + g.b0, c->d_U, c->d_N, c->nshell, nb,
+                                              c->d_geo + g.b0, c->d_lun, c->nshell, nb,
                                               features + (int64_t)g.b0 * ldk * 16, ldk, s));
         if (block_energy) {
             const int64_t off = (int64_t)g.b0 * kBatch;

@@ -39,6 +39,11 @@ struct PrimPair {
     double pad;
 };
 
+// FP32 copy of a primitive pair for the reduced-precision A.F blocks (same index).
+struct PrimPair32 {
+    float Px, Py, Pz, zp, pref, PAx, PAy, PAz, oo2zp, pad;
+};
+
 struct ShellDev {
     double x, y, z;
     int32_t l, nprim, prim_off, pad;
@@ -55,6 +60,9 @@ struct ShellDev {
 //   btask_ab: [btask][k][3] doubles, R_A - R_B of pair k
 constexpr int kMaxTile = 8;
 constexpr int kTileA[6] = {4, 2, 2, 1, 1, 1};   // ss, ps, pp, ds, dp, dd
+// A tiles of the FP32 lists (list 6 + class): FP32 registers are half as wide, so twice the
+// tile fits, and each F_B load / G_B update then serves twice the pairs
+constexpr int kTileA32[6] = {8, 4, 4, 2, 2, 1};
 
 // class c = ss, ps, pp, ds, dp, dd: (l_A, l_B) and A-tile size, usable in device code
 __host__ __device__ constexpr int kClassLA_dev(int c) { return c == 0 ? 0 : (c < 3 ? 1 : 2); }
@@ -62,6 +70,13 @@ __host__ __device__ constexpr int kClassLB_dev(int c) { return (c == 0 || c == 1
 __host__ __device__ constexpr int kTileA_dev(int c)
 {
     return c == 0 ? kTileA[0] : c == 1 ? kTileA[1] : c == 2 ? kTileA[2] : c == 3 ? kTileA[3] : c == 4 ? kTileA[4] : kTileA[5];
+}
+// tile of screened list k (0-5 FP64 classes, 6-11 FP32 classes)
+__host__ __device__ constexpr int kListTile(int k)
+{
+    return k < 6 ? kTileA_dev(k)
+                 : (k == 6 ? kTileA32[0] : k == 7 ? kTileA32[1] : k == 8 ? kTileA32[2] : k == 9 ? kTileA32[3]
+                                                              : k == 10 ? kTileA32[4] : kTileA32[5]);
 }
 
 struct AfgArgs {
@@ -75,6 +90,8 @@ struct AfgArgs {
     int64_t ld;
     const PairHdr* pairs;
     const PrimPair* prims;
+    const PrimPair32* prims32;      // FP32 copy of prims
+    bool lowp;                      // evaluate in FP32 (reduced-precision blocks)
     const int32_t* runs;            // run records of one class
     const int32_t* btasks;          // B-task records of that class
     const double* btask_ab;         // R_A - R_B per B task and tile slot
@@ -93,19 +110,27 @@ struct ScreenArgs {
     const int32_t* shell_row;   // [nshell] first row of the shell in F/G
     const PairHdr* pairs;       // unique pairs, index s(s+1)/2 + t for s >= t
     double eps_batch;           // energy budget of the skipped blocks of one batch
-    int32_t* counts;            // [nbatch][6][2]: runs, B tasks
-    int64_t* npairs;            // [nbatch][6]: shell pairs kept
+    double eps_low;             // estimate budget of the reduced-precision blocks of one batch
+    int32_t nlist;              // 6: one list per class; 12: lists 0-5 FP64, lists 6-11 FP32 (same classes)
+    int32_t* counts;            // [nbatch][nlist][2]: runs, B tasks
+    int64_t* npairs;            // [nbatch][nlist]: shell pairs kept
     double* skipped;            // [nbatch]: bound on the skipped energy
-    const int64_t* run_base;    // [6][nbatch+1]
-    const int64_t* bt_base;     // [6][nbatch+1]
-    int32_t* runs[6];
-    int32_t* btasks[6];
-    double* btask_ab[6];
-    int32_t* batch_run_off[6];  // [nbatch+1]
+    const int64_t* run_base;    // [nlist][nbatch+1]
+    const int64_t* bt_base;     // [nlist][nbatch+1]
+    int32_t* runs[12];
+    int32_t* btasks[12];
+    double* btask_ab[12];
+    int32_t* batch_run_off[12]; // [nbatch+1]
     const float* est;           // learned screen: [nbatch][npair_total] log2 block estimate, or nullptr
     const int32_t* thr;         // learned screen: [nbatch] first kept estimate bin
+    const int32_t* thr2;        // learned screen: [nbatch] first FP64 estimate bin (bins thr..thr2-1 are FP32)
     int64_t npair_total;
 };
+
+// Relative error allowed for in an FP32-evaluated block of the mixed build: the FP32 set's
+// summed estimates times kLowRelErr stay within eps_lowprec_energy.  FP32 rounds at 2^-24;
+// the recurrences and the contraction lose up to a few digits more on cancellation.
+constexpr double kLowRelErr = 1e-5;
 
 // block-energy histograms of the screens: bin = floor(2 log2 e) + kBinOff, clamped to [0, kNBins)
 constexpr int kBinOff = 400;
@@ -145,7 +170,7 @@ struct BatchGeo {
 // log2(est) in est[batch][pair index]; the batch's skip threshold bin goes to thr[batch].
 struct EstArgs {
     const double* U;            // [nbatch][nshell] bound factors
-    const double* N;            // [nbatch][nshell] F norms sqrt(sum_i w_i |F_A,i|^2)
+    const float2* lun;          // [nbatch][nshell] log10 U and log10 of the F norm (clamped at -40)
     int32_t nshell;
     int32_t nbatch;
     const int32_t* shell_l;
@@ -162,6 +187,8 @@ struct EstArgs {
     float* est;                 // [nbatch][npair_total] log2 of the block estimate
     float* yraw;                // optional [nbatch][npair_total] raw network output
     int32_t* thr;               // [nbatch] first kept bin of the learned estimate
+    double eps_low;             // estimate budget of the reduced-precision blocks of one batch (0: none)
+    int32_t* thr2;              // [nbatch] first FP64 bin (bins thr .. thr2-1 go to FP32)
     double* skipped;            // [nbatch] estimated energy of the skipped blocks
 };
 
@@ -175,7 +202,7 @@ hipError_t launch_mlp_adam(float* params, float* m, float* v, const float* g, fl
 hipError_t launch_diag_bound(int l, const double* px, const double* py, const double* pz, const double* pw,
                              const double* F, const float* F32, int64_t ld, const PrimPair* prims, const int32_t* dsh,
                              const int32_t* drow, const int32_t* dpb, const int32_t* dnp, int32_t n, double* U,
-                             double* N, int32_t nshell, int32_t nbatch, const double* tab, hipStream_t s);
+                             float2* lun, int32_t nshell, int32_t nbatch, const double* tab, hipStream_t s);
 hipError_t launch_screen(bool write, const ScreenArgs& a, hipStream_t s);
 hipError_t launch_screen_est(const EstArgs& a, hipStream_t s);
 // lp[p] = log10 ||P_AB|| over all pair indices p (shells A >= B in index order)
@@ -184,17 +211,16 @@ hipError_t launch_pair_pnorm(const double* P, int64_t nbf, const int32_t* pa, co
                              hipStream_t s);
 // training data: features [b][k][16] and exact block energies t[b][k] of the listed pairs
 hipError_t launch_block_features(const int32_t* plist, const int32_t* pa, const int32_t* pb, int32_t n,
-                                 const PairFeat* pfeat, const float* lp, const BatchGeo* geo, const double* U,
-                                 const double* N, int32_t nshell, int32_t nbatch, float* feat, int64_t ldk,
-                                 hipStream_t s);
+                                 const PairFeat* pfeat, const float* lp, const BatchGeo* geo, const float2* lun,
+                                 int32_t nshell, int32_t nbatch, float* feat, int64_t ldk, hipStream_t s);
 hipError_t launch_block_energy(int la, int lb, const double* px, const double* py, const double* pz, const double* pw,
                                const double* F, const float* F32, int64_t ld, const PairHdr* pairs, const PrimPair* prims,
                                const PairFeat* pfeat, const int32_t* plist, int32_t n, int32_t nbatch, double* t,
                                int64_t ldk, const double* tab, hipStream_t s);
 // D = A B for 16 x 16 row-major A, B (bf16-exact FP32 values) through one bf16 matrix-core op
 hipError_t launch_mfma_bf16_probe(const float* A, const float* B, float* D, hipStream_t s);
-hipError_t launch_screen_scan(const int32_t* counts, int32_t nbatch, int64_t* run_base, int64_t* bt_base,
-                              hipStream_t s);
+hipError_t launch_screen_scan(const int32_t* counts, int32_t nbatch, int32_t nlist, int64_t* run_base,
+                              int64_t* bt_base, hipStream_t s);
 hipError_t launch_afg(int la, int lb, const AfgArgs& a, hipStream_t s);
 hipError_t launch_collocate(const double* px, const double* py, const double* pz, int64_t ncols,
                             const ShellDev* shells, const double* exps, const double* coefs,

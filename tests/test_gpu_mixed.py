@@ -1,6 +1,6 @@
-"""Mixed-precision build (SNK_MIXED) against the FP64 oracle.
+"""Mixed-precision builds against the FP64 oracle and the FP64 GPU build.
 
-In the mixed build Phi, P and F are stored in FP32 and both GEMMs run on the FP32 matrix
+With SNK_MIXED | SNK_FP32_GEMM, Phi, P and F are stored in FP32 and both GEMMs run on the FP32 matrix
 cores (FP32 products, FP32 sums over at most 1024 terms, FP64 across them); the Boys
 function, the recurrences, G and the K accumulation stay FP64.  FP32 storage rounds each
 F element to a relative 2^-24 ~ 6e-8; the errors enter E_x = -1/2 sum_i F_i^T G_i with
@@ -39,7 +39,7 @@ def check_mixed(K, ex, Kref, exref, label):
 def test_mixed_config1_vs_stored_oracle():
     g = np.load(os.path.join(GOLDEN, "oracle_config1.npz"))
     s = synth.make_system(1, with_density=False).with_density(g["P"])
-    K, st = snk.sn_k_build(s, precision=snk.SNK_MIXED)
+    K, st = snk.sn_k_build(s, precision=snk.SNK_MIXED, flags=snk.SNK_FP32_GEMM)
     check_mixed(K, st["ex"], g["K"], float(g["ex"][0]), "config1")
 
 
@@ -51,7 +51,7 @@ def test_mixed_all_classes_vs_oracle():
         [(0, [1.1], [1.0]), (2, [1.3, 0.5], [0.5, 0.5]), (1, [30.0, 3.0, 0.3], [0.3, 0.5, 0.4])],
     ]
     s = synth.make_custom([8, 1, 1], xyz, shells, grid=(24, 86), n_occ=3)
-    K, st = snk.sn_k_build(s, precision=snk.SNK_MIXED)
+    K, st = snk.sn_k_build(s, precision=snk.SNK_MIXED, flags=snk.SNK_FP32_GEMM)
     Kr, exr, _ = O.snk(s)
     check_mixed(K, st["ex"], Kr, exr, "soft-spd")
 
@@ -62,21 +62,65 @@ def test_mixed_config2_sample_vs_fp64_gpu():
     s = synth.make_system(2)
     s = s.subset_points(np.arange(0, s.npts, 7))
     K0, st0 = snk.sn_k_build(s)
-    K1, st1 = snk.sn_k_build(s, precision=snk.SNK_MIXED)
+    K1, st1 = snk.sn_k_build(s, precision=snk.SNK_MIXED, flags=snk.SNK_FP32_GEMM)
     check_mixed(K1, st1["ex"], K0, st0["ex"], "config2/7")
 
 
 def test_mixed_deterministic_and_device_pointers():
     import torch
     s = synth.make_system(1, grid=(20, 50))
-    ctx = snk.Context(s, precision=snk.SNK_MIXED)
+    ctx = snk.Context(s, precision=snk.SNK_MIXED, flags=snk.SNK_FP32_GEMM)
     K1, _ = ctx.build(s.P)
     K2, _ = ctx.build(s.P)
     assert np.array_equal(K1, K2)
     st = torch.cuda.Stream()
-    cd = snk.Context(s, precision=snk.SNK_MIXED, flags=snk.SNK_DEVICE_PTRS, stream=st.cuda_stream)
+    cd = snk.Context(s, precision=snk.SNK_MIXED, flags=snk.SNK_DEVICE_PTRS | snk.SNK_FP32_GEMM,
+                     stream=st.cuda_stream)
     Pd = torch.from_numpy(s.P).cuda()
     Kd = torch.empty_like(Pd)
     cd.build_device(Pd.data_ptr(), Kd.data_ptr())
     st.synchronize()
     assert np.array_equal(Kd.cpu().numpy(), K1)
+
+
+def _frac_low(st):
+    return st["pair_points_lowprec"] / max(1, sum(st["pair_points"]))
+
+
+@pytest.mark.parametrize("cfg", [1, 2])
+def test_fp32_blocks_everywhere(cfg):
+    """Every block through the FP32 A.F kernels (bound screen, no skipping, unlimited FP32
+    budget): the accuracy of FP32 integrals against the FP64 build.  Relative errors near
+    the FP32 rounding level; the measured values set the FP32 budget constant."""
+    s = synth.make_system(cfg)
+    if cfg == 2:
+        s = s.subset_points(np.arange(0, s.npts, 7))
+    K0, st0 = snk.sn_k_build(s)
+    K1, st1 = snk.sn_k_build(s, precision=snk.SNK_MIXED, screen=snk.SNK_SCREEN_BOUND, eps_skip_energy=0.0,
+                             eps_lowprec_energy=1e30)
+    dE = abs(st1["ex"] - st0["ex"])
+    dK = np.max(np.abs(K1 - K0))
+    say("config %d all-FP32 A.F: FP32 fraction %.3f |dE| %.3e (rel %.2e) max|dK| %.3e (rel %.2e)" %
+        (cfg, _frac_low(st1), dE, dE / abs(st0["ex"]), dK, dK / np.max(np.abs(K0))))
+    assert _frac_low(st1) > 0.99
+    assert np.array_equal(K1, K1.T)
+    assert dE <= 1e-5 * abs(st0["ex"])
+
+
+@pytest.mark.parametrize("cfg", [1, 2])
+def test_mixed_learned_within_budget(cfg):
+    """The mixed build with the learned screen at the default budgets (5e-7 Eh skipped,
+    5e-7 Eh from FP32 blocks): |dE_x| <= 1e-6 Eh against the FP64 build."""
+    if not os.path.exists(snk.SCREENER_WEIGHTS):
+        pytest.skip("no trained screener weights")
+    m = snk.load_screener()
+    s = synth.make_system(cfg)
+    K0, st0 = snk.sn_k_build(s)
+    K1, st1 = snk.sn_k_build(s, precision=snk.SNK_MIXED, screen=snk.SNK_SCREEN_LEARNED, screener=m)
+    dE = abs(st1["ex"] - st0["ex"])
+    skipped = st1["pair_points_skipped"] / max(1, st1["pair_points_skipped"] + sum(st1["pair_points"]))
+    say("config %d mixed+learned: skipped %.3f, FP32 %.3f of evaluated, |dE| %.3e max|dK| %.3e, afg %.2f ms "
+        "(FP64 %.2f)" % (cfg, skipped, _frac_low(st1), dE, np.max(np.abs(K1 - K0)), st1["t_afg_ms"],
+                         st0["t_afg_ms"]))
+    assert dE <= 1e-6
+    assert np.array_equal(K1, K1.T)

@@ -199,3 +199,20 @@ def test_bound_screening_zero_budget_is_exact():
     say("zero budget: skipped", st1["pair_points_skipped"], "|dE|", abs(st1["ex"] - st0["ex"]))
     assert abs(st1["ex"] - st0["ex"]) <= 1e-12
     assert np.max(np.abs(K1 - K0)) <= 1e-12 * np.max(np.abs(K0))
+
+
+def test_rocblas_gemm_path_matches_oracle():
+    """The FP64 build with the dense GEMMs through rocBLAS (SNK_ROCBLAS) against the oracle."""
+    s, g = stored_system(1)
+    K, st = snk.sn_k_build(s, flags=snk.SNK_ROCBLAS)
+    check(K, st["ex"], g["K"], g["ex"][0], "config1 rocBLAS")
+    s2 = synth.make_system(2)
+    s2 = s2.subset_points(np.arange(0, s2.npts, 11))
+    K0, st0 = snk.sn_k_build(s2)
+    K1, st1 = snk.sn_k_build(s2, flags=snk.SNK_ROCBLAS)
+    say("config2/11 rocBLAS vs native: |dE| %.2e max|dK| %.2e" % (abs(st1["ex"] - st0["ex"]),
+                                                                   np.max(np.abs(K1 - K0))))
+    assert abs(st1["ex"] - st0["ex"]) <= 1e-10
+    assert np.max(np.abs(K1 - K0)) <= 1e-11 * np.max(np.abs(K0))
+    K2, _ = snk.sn_k_build(s2, flags=snk.SNK_ROCBLAS)
+    assert np.array_equal(K1, K2)
