@@ -53,7 +53,7 @@ def cpu_baseline(system, target_s: float = 20.0):
 def afg_source_sha() -> str:
     import hashlib
     d = os.path.join(ROOT, "paper_2303_14280_amd", "csrc")
-    src = b"".join(open(os.path.join(d, f), "rb").read() for f in ("k_afg.hip", "snk_internal.h"))
+    src = b"".join(open(os.path.join(d, f), "rb").read() for f in ("k_afg.hip", "os3c.h", "snk_internal.h"))
     return hashlib.sha256(src).hexdigest()[:16]
 
 

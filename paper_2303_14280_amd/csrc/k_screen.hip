@@ -257,23 +257,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void s
     const float log2_10 = 3.32192809488736f;
     const float mlog2 = a.margin * log2_10;
 
-    // one combo index space over the six classes; same-l classes enumerate the triangle
-    // ai >= bi only (the active lists ascend in shell index)
-    __shared__ int64_t coff[7];
-    if (tid == 0) {
-        int64_t acc = 0;
-        for (int c = 0; c < 6; ++c) {
-            const int la = kClassLA_dev(c), lb = kClassLB_dev(c);
-            const int64_t nA = sh.aoff[la + 1] - sh.aoff[la], nB = sh.aoff[lb + 1] - sh.aoff[lb];
-            coff[c] = acc;
-            acc += la == lb ? nA * (nA + 1) / 2 : nA * nB;
-        }
-        coff[6] = acc;
-    }
-    __syncthreads();
-    const int64_t total = coff[6];
-
-    // candidate data of combo i, loaded one chunk ahead of its use
+    // candidates: the static list of pairs with kept primitive pairs (class order), read as
+    // consecutive records; pairs the bound already skips on this batch are dropped
     struct Cand {
         bool valid;
         int aa, b;
@@ -282,38 +267,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void s
         float lp;
         float2 ua, ub;
     };
+    const int64_t total = a.nne;
     auto fetch = [&](int64_t i, Cand& d) {
-        d.valid = false;
-        d.aa = 0;
-        d.b = 0;
-        d.p = 0;
-        if (i < total) {
-            int c = 0;
-            while (c < 5 && i >= coff[c + 1]) ++c;
-            const int la = kClassLA_dev(c), lb = kClassLB_dev(c);
-            const int64_t j = i - coff[c];
-            int ai, bi;
-            if (la == lb) {
-                ai = (int)((sqrtf(8.0f * (float)j + 1.0f) - 1.0f) * 0.5f);
-                while ((int64_t)ai * (ai + 1) / 2 > j) --ai;
-                while ((int64_t)(ai + 1) * (ai + 2) / 2 <= j) ++ai;
-                bi = (int)(j - (int64_t)ai * (ai + 1) / 2);
-            } else {
-                const int nB = sh.aoff[lb + 1] - sh.aoff[lb];
-                ai = (int)(j / nB);
-                bi = (int)(j - (int64_t)ai * nB);
-            }
-            d.aa = act[sh.aoff[la] + ai];
-            d.b = act[sh.aoff[lb] + bi];
-            if (bins[d.aa] + bins[d.b] >= S) {
-                d.p = pair_index(d.aa, d.b);
-                d.valid = true;
-            }
-        }
-        // loads for every lane (in-bounds defaults for lanes without a candidate)
-        d.valid = d.valid && a.pairs[d.p].nprim > 0;
-        d.pf = a.pfeat[d.p];
-        d.lp = a.lp[d.p];
+        const int64_t k = i < total ? i : 0;
+        const int2 ab = a.ne_ab[k];
+        d.aa = ab.x;
+        d.b = ab.y;
+        d.p = a.ne_p[k];
+        d.valid = i < total && bins[d.aa] != kNoBin && bins[d.b] != kNoBin && bins[d.aa] + bins[d.b] >= S;
+        d.pf = a.ne_feat[k];
+        d.lp = a.ne_lp[k];
         d.ua = Lb[d.aa];
         d.ub = Lb[d.b];
     };

@@ -133,6 +133,8 @@ struct snk_ctx {
     std::vector<int32_t> ne_list;   // pair indices with kept primitive pairs, class order
     int32_t ne_class_off[7] = {0, 0, 0, 0, 0, 0, 0};
     int32_t* d_ne_list = nullptr;
+    int2* d_ne_ab = nullptr;
+    PairFeat* d_ne_feat = nullptr;
     int32_t* d_pool_runs[12] = {};
     int32_t* d_pool_bt[12] = {};
     double* d_pool_ab[12] = {};
@@ -397,6 +399,14 @@ int build_pair_feats(snk_ctx* c)
     if ((rc = upload(c, &c->d_pa, pa))) return rc;
     if ((rc = upload(c, &c->d_pb, pb))) return rc;
     if ((rc = upload(c, &c->d_ne_list, c->ne_list))) return rc;
+    std::vector<int2> ne_ab(c->ne_list.size());
+    std::vector<PairFeat> ne_feat(c->ne_list.size());
+    for (size_t k = 0; k < c->ne_list.size(); ++k) {
+        ne_ab[k] = make_int2(pa[c->ne_list[k]], pb[c->ne_list[k]]);
+        ne_feat[k] = pf[c->ne_list[k]];
+    }
+    if ((rc = upload(c, &c->d_ne_ab, ne_ab))) return rc;
+    if ((rc = upload(c, &c->d_ne_feat, ne_feat))) return rc;
     return SNK_OK;
 }
 
@@ -643,7 +653,7 @@ int setup_screening(snk_ctx* c)
     c->max_group_batches = mb;
     if ((rc = dalloc(c, &c->d_U, (size_t)mb * c->nshell))) return rc;
     if ((rc = dalloc(c, &c->d_lun, (size_t)mb * c->nshell))) return rc;
-    if ((rc = dalloc(c, &c->d_lp, (size_t)c->npair_total))) return rc;
+    if ((rc = dalloc(c, &c->d_lp, c->ne_list.size()))) return rc;
     if (c->opts.screen == SNK_SCREEN_LEARNED) {
         if ((rc = dalloc(c, &c->d_est, (size_t)mb * c->npair_total))) return rc;
         if ((rc = dalloc(c, &c->d_thr, (size_t)mb))) return rc;
@@ -740,6 +750,8 @@ void free_ctx(snk_ctx* c)
     (void)hipFree(c->d_thr2);
     (void)hipFree(c->d_prims32);
     (void)hipFree(c->d_ne_list);
+    (void)hipFree(c->d_ne_ab);
+    (void)hipFree(c->d_ne_feat);
     (void)hipFree(c->d_counts);
     (void)hipFree(c->d_npairs);
     (void)hipFree(c->d_skipped);
@@ -1077,9 +1089,11 @@ int group_until_G(snk_ctx* c, const Group& g, const double* dP, bool timed, Grou
             ea.nshell = c->nshell;
             ea.nbatch = nb;
             ea.shell_l = c->d_shell_l;
-            ea.pairs = c->d_pairs;
-            ea.pfeat = c->d_pfeat;
-            ea.lp = c->d_lp;
+            ea.nne = (int64_t)c->ne_list.size();
+            ea.ne_p = c->d_ne_list;
+            ea.ne_ab = c->d_ne_ab;
+            ea.ne_feat = c->d_ne_feat;
+            ea.ne_lp = c->d_lp;
             ea.geo = c->d_geo + g.b0;
             ea.eps_batch = eps_batch;
             ea.params = mlp_params(c->mlp);
@@ -1239,8 +1253,8 @@ int snk_ctx_build(snk_ctx* c, const double* P, double* K_out, snk_stats* stats)
     HIPCHECK(c, launch_fill(c->d_Kt, (int64_t)nb2, 0.0, s));
     if (c->mixed) HIPCHECK(c, launch_convert_f32(dP, (int64_t)nb2, c->d_P32, s));
     if (c->mlp)
-        HIPCHECK(c, launch_pair_pnorm(dP, nbf, c->d_pa, c->d_pb, c->d_shell_l, c->d_shell_row, c->npair_total,
-                                      c->d_lp, s));
+        HIPCHECK(c, launch_pair_pnorm(dP, nbf, c->d_ne_list, c->d_pa, c->d_pb, c->d_shell_l, c->d_shell_row,
+                                      (int64_t)c->ne_list.size(), c->d_lp, s));
     for (const Group& g : c->groups) {
         const int64_t ld = g.ncols;
         int rc = group_until_G(c, g, dP, timed, &gs);
@@ -1433,7 +1447,8 @@ int snk_ctx_block_data(snk_ctx* c, const double* P, float* features, double* blo
         HIPCHECK(c, hipMemcpyAsync(c->d_P, P, (size_t)nbf * nbf * sizeof(double), hipMemcpyHostToDevice, s));
         dP = c->d_P;
     }
-    HIPCHECK(c, launch_pair_pnorm(dP, nbf, c->d_pa, c->d_pb, c->d_shell_l, c->d_shell_row, c->npair_total, c->d_lp, s));
+    HIPCHECK(c, launch_pair_pnorm(dP, nbf, c->d_ne_list, c->d_pa, c->d_pb, c->d_shell_l, c->d_shell_row,
+                                  (int64_t)c->ne_list.size(), c->d_lp, s));
     if (c->mixed) HIPCHECK(c, launch_convert_f32(dP, nbf * nbf, c->d_P32, s));
     for (const Group& g : c->groups) {
         if ((rc = group_F(c, g, dP, false))) return rc;
@@ -1483,8 +1498,8 @@ int snk_ctx_debug_learned(snk_ctx* c, const double* P, float* yraw, float* est, 
     std::vector<float> nanv(n, std::nanf(""));
     HIPCHECK(c, hipMemcpyAsync(d_y, nanv.data(), n * sizeof(float), hipMemcpyHostToDevice, s));
     HIPCHECK(c, hipMemcpyAsync(c->d_est, nanv.data(), n * sizeof(float), hipMemcpyHostToDevice, s));
-    HIPCHECK(c, launch_pair_pnorm(c->d_P, nbf, c->d_pa, c->d_pb, c->d_shell_l, c->d_shell_row, c->npair_total,
-                                  c->d_lp, s));
+    HIPCHECK(c, launch_pair_pnorm(c->d_P, nbf, c->d_ne_list, c->d_pa, c->d_pb, c->d_shell_l, c->d_shell_row,
+                                  (int64_t)c->ne_list.size(), c->d_lp, s));
     if (c->mixed) HIPCHECK(c, launch_convert_f32(c->d_P, nbf * nbf, c->d_P32, s));
     GroupStats gs;
     rc = group_until_G(c, g, c->d_P, false, &gs, d_y);

@@ -174,9 +174,11 @@ struct EstArgs {
     int32_t nshell;
     int32_t nbatch;
     const int32_t* shell_l;
-    const PairHdr* pairs;
-    const PairFeat* pfeat;      // per pair index
-    const float* lp;            // per pair index: log10 of the Frobenius norm of the P block
+    int64_t nne;                // pairs with kept primitive pairs, in class order:
+    const int32_t* ne_p;        //   [nne] pair index
+    const int2* ne_ab;          //   [nne] shells (A, B)
+    const PairFeat* ne_feat;    //   [nne] static features
+    const float* ne_lp;         //   [nne] log10 of the Frobenius norm of the P block
     const BatchGeo* geo;        // [nbatch] of this group
     double eps_batch;
     const float* params;        // network parameters (FP32; rounded to bf16 on load)
@@ -205,10 +207,10 @@ hipError_t launch_diag_bound(int l, const double* px, const double* py, const do
                              float2* lun, int32_t nshell, int32_t nbatch, const double* tab, hipStream_t s);
 hipError_t launch_screen(bool write, const ScreenArgs& a, hipStream_t s);
 hipError_t launch_screen_est(const EstArgs& a, hipStream_t s);
-// lp[p] = log10 ||P_AB|| over all pair indices p (shells A >= B in index order)
-hipError_t launch_pair_pnorm(const double* P, int64_t nbf, const int32_t* pa, const int32_t* pb,
-                             const int32_t* shell_l, const int32_t* shell_row, int64_t npair, float* lp,
-                             hipStream_t s);
+// lp[k] = log10 ||P_AB|| of the listed pairs plist[k] (pa/pb: shells of each pair index)
+hipError_t launch_pair_pnorm(const double* P, int64_t nbf, const int32_t* plist, const int32_t* pa,
+                             const int32_t* pb, const int32_t* shell_l, const int32_t* shell_row, int64_t n,
+                             float* lp, hipStream_t s);
 // training data: features [b][k][16] and exact block energies t[b][k] of the listed pairs
 hipError_t launch_block_features(const int32_t* plist, const int32_t* pa, const int32_t* pb, int32_t n,
                                  const PairFeat* pfeat, const float* lp, const BatchGeo* geo, const float2* lun,
