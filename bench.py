@@ -135,6 +135,45 @@ def mixed_learned(s, P, K64, stream, args, ms64, ex64, ints):
     return res
 
 
+def local_density_comparison(s, stream, args):
+    """The same geometry and grid with a molecule-local density (each water's five occupied
+    orbitals on its own functions, P block-diagonal by molecule): FP64 build against the
+    mixed + learned build, both timed like the headline build."""
+    import torch
+    from paper_2303_14280_amd import snk, synth
+    if not os.path.exists(snk.SCREENER_WEIGHTS):
+        return {"error": "no trained screener weights"}
+    sl = s.with_density(synth.make_density(s, s.n_occ, "local", [args.config, 2]))
+    P = torch.tensor(sl.P, dtype=torch.float64, device="cuda")
+    mlp = snk.load_screener(device=0)
+    R = snk.SNK_DEVICE_PTRS | snk.SNK_ROCBLAS
+    res = {"density": "molecule-local (block-diagonal by molecule)"}
+    K64 = torch.empty_like(P)
+    ctx = snk.Context(sl, flags=R, stream=stream.cuda_stream, device=0)
+    ms64 = time_builds(ctx, P, K64, stream, args.steps, args.warmup)
+    st64 = ctx.build_device(P.data_ptr(), K64.data_ptr(), stats=True)
+    ctx.close()
+    res["fp64"] = {"ms_per_step": ms64, "ex": st64["ex"]}
+    K = torch.empty_like(P)
+    ctx = snk.Context(sl, flags=R, stream=stream.cuda_stream, device=0, screener=mlp, precision=snk.SNK_MIXED,
+                      screen=snk.SNK_SCREEN_LEARNED, eps_skip_energy=args.eps, eps_lowprec_energy=args.eps)
+    ms = time_builds(ctx, P, K, stream, args.steps, args.warmup)
+    st = ctx.build_device(P.data_ptr(), K.data_ptr(), stats=True)
+    torch.cuda.synchronize()
+    ctx.close()
+    ints = float(sum(st["pair_points"]) + st["pair_points_skipped"])
+    res["mixed+learned"] = {
+        "ms_per_step": ms, "speedup_vs_fp64": ms64 / ms, "dE_x_vs_fp64": st["ex"] - st64["ex"],
+        "max_dK_vs_fp64": float((K - K64).abs().max().item()),
+        "skipped_pair_points_fraction": st["pair_points_skipped"] / max(1.0, ints),
+        "fp32_pair_points_fraction": st["pair_points_lowprec"] / max(1.0, ints),
+        "phases_ms": {"collocate": st["t_collocate_ms"], "fgemm": st["t_fgemm_ms"], "screen": st["t_screen_ms"],
+                      "afg": st["t_afg_ms"], "kgemm": st["t_kgemm_ms"], "finish": st["t_finish_ms"]}}
+    log("local density: FP64 %.3f ms, mixed+learned %.3f ms (x%.2f), dE_x %.2e" %
+        (ms64, ms, ms64 / ms, res["mixed+learned"]["dE_x_vs_fp64"]))
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -143,7 +182,8 @@ def main():
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision + learned-screen comparison")
-    ap.add_argument("--eps", type=float, default=5e-7, help="skip budget of the learned screen (Eh)")
+    ap.add_argument("--eps", type=float, default=5e-6,
+                    help="estimate budget (Eh) of the learned screen's skipped blocks and of the FP32 blocks")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -252,6 +292,7 @@ def main():
     }
     if not args.no_mixed:
         out["mixed_learned"] = mixed_learned(s, P, K, stream, args, ms, st["ex"], ints)
+        out["local_density"] = local_density_comparison(s, stream, args)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(s)

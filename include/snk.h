@@ -252,8 +252,9 @@ int snk_ctx_block_data(snk_ctx* ctx, const double* P, float* features, double* b
  *   that group and pair index p, the raw network output yraw[b * npair_index + p] and the
  *   block estimate log2 est[...] (NaN for blocks the bound already skipped), and the
  *   first kept estimate bin thr[b].  *nbatch_out = batches of the group.
- * snk_debug_mfma_bf16: D = A B for 16 x 16 row-major host matrices through one bf16
- *   matrix-core op (A and B rounded to bf16; layout check).
+ * snk_debug_mfma_bf16: D = A B (16 x 16 row-major host D) through one bf16 matrix-core op,
+ *   A and B rounded to bf16: with k32 = 0, A and B are 16 x 16 (16x16x16 op); with k32 != 0,
+ *   A is 16 x 32 and B 32 x 16 (16x16x32 op).  Layout check.
  */
 int snk_debug_gemm_f64(int64_t M, int64_t N, int64_t K, const double* A, int64_t lda, const double* B,
                        int64_t ldb, int bt, double* C, int64_t ldc, void* stream);
@@ -264,7 +265,7 @@ int snk_ctx_debug_intermediates(snk_ctx* ctx, const double* P, double* Phi, doub
 int64_t snk_ctx_npair_index(const snk_ctx* ctx);
 int snk_ctx_debug_learned(snk_ctx* ctx, const double* P, float* yraw, float* est, int32_t* thr,
                           int64_t* nbatch_out);
-int snk_debug_mfma_bf16(const float* A, const float* B, float* D);
+int snk_debug_mfma_bf16(const float* A, const float* B, float* D, int k32);
 
 #ifdef __cplusplus
 }

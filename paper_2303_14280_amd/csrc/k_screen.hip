@@ -6,8 +6,9 @@
 // block over a batch j, e_AB = sum_i w_i F_A,i^T A_AB(r_i) F_B,i, Cauchy-Schwarz over the
 // points gives |e_AB| <= U_A U_B with
 //   U_A = sqrt( sum_i w_i ( sum_c |F_{A_c,i}| sqrt(A_{A_c A_c}(r_i)) )^2 ),
-// which needs only the diagonal integrals (one same-shell pair per shell).  Skipping a set
-// of blocks changes E_x by at most the sum of their U_A U_B.
+// which needs only the diagonal integrals (one same-shell pair per shell, evaluated in FP32
+// with a 1% safety factor on U).  Skipping a set of blocks changes E_x by at most the sum of
+// their U_A U_B.
 //
 // Per batch the builder bins log2(U) in half octaves, bounds the energy of every candidate
 // skip set from the bin histogram (pairs in bins (k, l) have U_A U_B < 2^{(k+l+2)/2}),
@@ -28,6 +29,9 @@ using namespace os3c;
 
 constexpr int kNoBin = -100000;     // U == 0
 constexpr int kGroup = 32;          // diagonal-bound shells per barrier
+// The diagonal integrals are evaluated in FP32 (relative error ~1e-6 for these positive
+// quantities); U is scaled by this factor so that it stays an upper bound.
+constexpr double kBoundSafety = 1.01;
 
 // ---------------------------------------------------------------------------------------
 // U_A for the shells of one angular momentum L: one workgroup per batch, lane = point.
@@ -36,7 +40,7 @@ template <int L, typename TF>
 __global__ __launch_bounds__(256) void diag_bound_kernel(const double* __restrict__ px, const double* __restrict__ py,
                                                          const double* __restrict__ pz, const double* __restrict__ pw,
                                                          const TF* __restrict__ F, int64_t ld,
-                                                         const PrimPair* __restrict__ prims,
+                                                         const PrimPair32* __restrict__ prims,
                                                          const int32_t* __restrict__ dsh,   // [n] shell
                                                          const int32_t* __restrict__ drow,  // [n] first row
                                                          const int32_t* __restrict__ dpb,   // [n] prim_begin of (A,A)
@@ -46,28 +50,30 @@ __global__ __launch_bounds__(256) void diag_bound_kernel(const double* __restric
                                                          const double* __restrict__ gtab)
 {
     constexpr int N = ncart(L);
-    __shared__ double tab[kBoysRows * kBoysCols];
+    __shared__ float tab[kBoysRows * kBoysCols];
     __shared__ double part[kGroup][4];
     __shared__ double npart[kGroup][4];
-    for (int i = threadIdx.x; i < kBoysRows * kBoysCols; i += blockDim.x) tab[i] = gtab[i];
+    for (int i = threadIdx.x; i < kBoysRows * kBoysCols; i += blockDim.x) tab[i] = (float)gtab[i];
     __syncthreads();
     const int batch = blockIdx.x;
     const int64_t col = (int64_t)batch * kBatch + threadIdx.x;
-    const double cx = px[col], cy = py[col], cz = pz[col], w = pw[col];
+    const float cx = (float)px[col], cy = (float)py[col], cz = (float)pz[col];
+    const double w = pw[col];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const double AB[3] = {0.0, 0.0, 0.0};
+    const float AB[3] = {0.0f, 0.0f, 0.0f};
     // shells in groups of kGroup: per-wave partial sums in LDS, one barrier pair per group
     for (int s0 = 0; s0 < n; s0 += kGroup) {
         const int s1 = min(n, s0 + kGroup);
         for (int s = s0; s < s1; ++s) {
             const int row = drow[s];
-            double Ab[N][N];
-            pair_block<L, L, double>(prims + dpb[s], dnp[s], AB, cx, cy, cz, tab, Ab);
+            float Ab[N][N];
+            pair_block<L, L, float>(prims + dpb[s], dnp[s], AB, cx, cy, cz, tab, Ab);
             double t = 0.0, f2 = 0.0;
             sfor<0, N>([&](auto cc) {
                 constexpr int c = CV(cc);
                 const double f = cnorm(L, c) * (double)F[(int64_t)(row + c) * ld + col];
-                t += fabs(f) * sqrt(fmax(Ab[c][c], 0.0));    // A_cc of the unit-normalised component
+                // A_cc of the unit-normalised component (FP32; the result is scaled up by kBoundSafety)
+                t += fabs(f) * (double)sqrtf(fmaxf(Ab[c][c], 0.0f));
                 f2 += f * f;
             });
             double v = w * t * t, q = w * f2;
@@ -84,7 +90,7 @@ __global__ __launch_bounds__(256) void diag_bound_kernel(const double* __restric
         if ((int)threadIdx.x < s1 - s0) {
             const int k = threadIdx.x;
             const int64_t o = (int64_t)batch * nshell + dsh[s0 + k];
-            const double u = sqrt(part[k][0] + part[k][1] + part[k][2] + part[k][3]);
+            const double u = kBoundSafety * sqrt(part[k][0] + part[k][1] + part[k][2] + part[k][3]);
             U[o] = u;
             if (lun)
                 lun[o] = make_float2(learn::lg10(u),
@@ -562,7 +568,7 @@ __global__ __launch_bounds__(256) void screen_scan_kernel(const int32_t* __restr
 }  // namespace
 
 hipError_t launch_diag_bound(int l, const double* px, const double* py, const double* pz, const double* pw,
-                             const double* F, const float* F32, int64_t ld, const PrimPair* prims, const int32_t* dsh,
+                             const double* F, const float* F32, int64_t ld, const PrimPair32* prims, const int32_t* dsh,
                              const int32_t* drow, const int32_t* dpb, const int32_t* dnp, int32_t n, double* U,
                              float2* N, int32_t nshell, int32_t nbatch, const double* tab, hipStream_t s)
 {

@@ -9,6 +9,7 @@ namespace learn {
 
 typedef short bf4 __attribute__((ext_vector_type(4)));
 typedef float f4v __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
 // nearest bfloat16 (ties to even; one hardware conversion on gfx950): bit pattern, and its
 // value as float
@@ -60,7 +61,7 @@ __device__ __forceinline__ void block_features(const PairFeat& pf, float lp, con
 
 // Register image of the network for one lane of a wave64 that evaluates 16 samples.
 // Lane (r = lane % 16, g = lane / 16).  Matrix-core operand layout of the 16x16x16 bf16
-// product D = A B (checked by the layout probe): lane (r, g) holds A[r][4g..4g+3],
+// product D = A B (checked by the layout probes): lane (r, g) holds A[r][4g..4g+3],
 // B[4g..4g+3][r] and D[4g..4g+3][r].  So the samples are the columns, a layer's output
 // tile is directly the next layer's B operand, and each lane supplies features 4g..4g+3.
 constexpr int kW2Ld = 68;   // LDS row stride (bf16 elements) of W2: 136 B spreads the rows over the banks

@@ -625,9 +625,26 @@ int build_runs(snk_ctx* c)
     return SNK_OK;
 }
 
+// FP32 copy of the primitive-pair records (same index)
+int ensure_prims32(snk_ctx* c)
+{
+    if (c->d_prims32) return SNK_OK;
+    std::vector<PrimPair32> p32(c->prims.size());
+    for (size_t k = 0; k < c->prims.size(); ++k) {
+        const PrimPair& q = c->prims[k];
+        p32[k] = PrimPair32{(float)q.Px, (float)q.Py, (float)q.Pz, (float)q.zp, (float)q.pref,
+                            (float)q.PAx, (float)q.PAy, (float)q.PAz, (float)q.oo2zp, 0.0f};
+    }
+    return upload(c, &c->d_prims32, p32);
+}
+
 int setup_screening(snk_ctx* c)
 {
     if (c->d_U) return SNK_OK;   // already set up
+    {
+        int rc = ensure_prims32(c);
+        if (rc) return rc;
+    }
     for (int l = 0; l < 3; ++l) {
         std::vector<int32_t> sh, row, pb, np;
         for (int s = 0; s < c->nshell; ++s) {
@@ -915,15 +932,8 @@ int snk_ctx_create(const snk_basis* basis, const snk_grid* grid, const double* w
     CREATE_CHECK(upload(c, &c->d_prims, c->prims));
     // the mixed build evaluates the screen's small blocks in FP32
     c->nlist = (o.precision == SNK_MIXED && o.screen != SNK_SCREEN_NONE) ? 12 : 6;
-    if (c->nlist == 12) {
-        std::vector<PrimPair32> p32(c->prims.size());
-        for (size_t k = 0; k < c->prims.size(); ++k) {
-            const PrimPair& q = c->prims[k];
-            p32[k] = PrimPair32{(float)q.Px, (float)q.Py, (float)q.Pz, (float)q.zp, (float)q.pref,
-                                (float)q.PAx, (float)q.PAy, (float)q.PAz, (float)q.oo2zp, 0.0f};
-        }
-        CREATE_CHECK(upload(c, &c->d_prims32, p32));
-    }
+    // FP32 records: the mixed build's FP32 blocks and the screen's diagonal bounds
+    if (c->nlist == 12 || o.screen != SNK_SCREEN_NONE) CREATE_CHECK(ensure_prims32(c));
     CREATE_CHECK(build_pair_feats(c));
     c->mlp = o.screen == SNK_SCREEN_LEARNED ? o.screener : nullptr;
     CREATE_CHECK(build_runs(c));
@@ -1045,7 +1055,7 @@ int group_bounds(snk_ctx* c, const Group& g)
     for (int l = 0; l < 3; ++l)
         HIPCHECK(c, launch_diag_bound(l, c->d_px + off, c->d_py + off, c->d_pz + off, c->d_pw + off, c->d_F,
                                       c->mixed ? c->d_F32 : nullptr, g.ncols,
-                                      c->d_prims, c->d_diag_sh[l], c->d_diag_row[l], c->d_diag_pb[l],
+                                      c->d_prims32, c->d_diag_sh[l], c->d_diag_row[l], c->d_diag_pb[l],
                                       c->d_diag_np[l], c->n_diag[l], c->d_U, c->d_lun, c->nshell, g.b1 - g.b0,
                                       c->d_boys, c->stream));
     return SNK_OK;
@@ -1522,15 +1532,18 @@ int snk_ctx_debug_learned(snk_ctx* c, const double* P, float* yraw, float* est, 
 
 int64_t snk_ctx_npair_index(const snk_ctx* c) { return c ? c->npair_total : 0; }
 
-int snk_debug_mfma_bf16(const float* A, const float* B, float* D)
+int snk_debug_mfma_bf16(const float* A, const float* B, float* D, int k32)
 {
     if (!A || !B || !D) return arg_error(nullptr, "NULL argument");
+    const int na = k32 ? 512 : 256;
     float* d = nullptr;
-    if (hipMalloc((void**)&d, 3 * 256 * sizeof(float)) != hipSuccess) return SNK_E_NOMEM;
-    hipError_t e = hipMemcpy(d, A, 256 * sizeof(float), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(d + 256, B, 256 * sizeof(float), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = launch_mfma_bf16_probe(d, d + 256, d + 512, nullptr);
-    if (e == hipSuccess) e = hipMemcpy(D, d + 512, 256 * sizeof(float), hipMemcpyDeviceToHost);
+    if (hipMalloc((void**)&d, (2 * na + 256) * sizeof(float)) != hipSuccess) return SNK_E_NOMEM;
+    hipError_t e = hipMemcpy(d, A, na * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d + na, B, na * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = k32 ? launch_mfma_bf16_k32_probe(d, d + na, d + 2 * na, nullptr)
+                : launch_mfma_bf16_probe(d, d + na, d + 2 * na, nullptr);
+    if (e == hipSuccess) e = hipMemcpy(D, d + 2 * na, 256 * sizeof(float), hipMemcpyDeviceToHost);
     (void)hipFree(d);
     if (e != hipSuccess) {
         g_last_error = hipGetErrorString(e);

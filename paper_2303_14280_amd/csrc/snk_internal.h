@@ -202,7 +202,7 @@ hipError_t launch_mlp_grad(const float* params, const MlpNorm& nrm, const float*
                            float under, float* part, float* grads, hipStream_t s);
 hipError_t launch_mlp_adam(float* params, float* m, float* v, const float* g, float lr, int t, hipStream_t s);
 hipError_t launch_diag_bound(int l, const double* px, const double* py, const double* pz, const double* pw,
-                             const double* F, const float* F32, int64_t ld, const PrimPair* prims, const int32_t* dsh,
+                             const double* F, const float* F32, int64_t ld, const PrimPair32* prims, const int32_t* dsh,
                              const int32_t* drow, const int32_t* dpb, const int32_t* dnp, int32_t n, double* U,
                              float2* lun, int32_t nshell, int32_t nbatch, const double* tab, hipStream_t s);
 hipError_t launch_screen(bool write, const ScreenArgs& a, hipStream_t s);
@@ -221,6 +221,8 @@ hipError_t launch_block_energy(int la, int lb, const double* px, const double* p
                                int64_t ldk, const double* tab, hipStream_t s);
 // D = A B for 16 x 16 row-major A, B (bf16-exact FP32 values) through one bf16 matrix-core op
 hipError_t launch_mfma_bf16_probe(const float* A, const float* B, float* D, hipStream_t s);
+// D = A B for 16 x 32 A and 32 x 16 B (row-major, bf16-exact) through one 16x16x32 bf16 op
+hipError_t launch_mfma_bf16_k32_probe(const float* A, const float* B, float* D, hipStream_t s);
 hipError_t launch_screen_scan(const int32_t* counts, int32_t nbatch, int32_t nlist, int64_t* run_base,
                               int64_t* bt_base, hipStream_t s);
 hipError_t launch_afg(int la, int lb, const AfgArgs& a, hipStream_t s);

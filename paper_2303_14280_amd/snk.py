@@ -129,7 +129,7 @@ def lib():
             L.snk_ctx_npair_index.restype = ctypes.c_int64
             L.snk_ctx_debug_learned.argtypes = [ctypes.c_void_p] * 5 + [ctypes.POINTER(ctypes.c_int64)]
             L.snk_ctx_debug_learned.restype = ctypes.c_int
-            L.snk_debug_mfma_bf16.argtypes = [ctypes.c_void_p] * 3
+            L.snk_debug_mfma_bf16.argtypes = [ctypes.c_void_p] * 3 + [ctypes.c_int]
             L.snk_debug_mfma_bf16.restype = ctypes.c_int
             _F = ctypes.POINTER(ctypes.c_float)
             L.snk_mlp_nparams.argtypes = []
@@ -415,11 +415,14 @@ class Mlp:
 
 
 def debug_mfma_bf16(A: np.ndarray, B: np.ndarray) -> np.ndarray:
-    """A @ B (16 x 16) through one bf16 matrix-core op."""
+    """A @ B through one bf16 matrix-core op: 16x16 @ 16x16, or 16x32 @ 32x16."""
     A = np.ascontiguousarray(A, np.float32)
     B = np.ascontiguousarray(B, np.float32)
+    k32 = A.shape == (16, 32)
+    if not ((A.shape == (16, 16) and B.shape == (16, 16)) or (k32 and B.shape == (32, 16))):
+        raise ValueError("shapes must be 16x16 @ 16x16 or 16x32 @ 32x16")
     D = np.zeros((16, 16), np.float32)
-    _check(lib().snk_debug_mfma_bf16(A.ctypes.data, B.ctypes.data, D.ctypes.data))
+    _check(lib().snk_debug_mfma_bf16(A.ctypes.data, B.ctypes.data, D.ctypes.data, int(k32)))
     return D
 
 
