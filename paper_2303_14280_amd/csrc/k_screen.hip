@@ -257,14 +257,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void s
     const int S = sh.S;
     const BatchGeo bg = a.geo[batch];
 
-    __shared__ __align__(16) short w2s[64 * learn::kW2Ld];
+    __shared__ __align__(16) learn::MlpShared msh;
     learn::MlpRegs R;
-    learn::load_mlp(a.params, a.norm, a.lo, a.hi, R, w2s);
+    learn::load_mlp(a.params, a.norm, a.lo, a.hi, R, msh);
     const float log2_10 = 3.32192809488736f;
     const float mlog2 = a.margin * log2_10;
 
-    // candidates: the static list of pairs with kept primitive pairs (class order), read as
-    // consecutive records; pairs the bound already skips on this batch are dropped
+    // Candidates, enumerated one of two ways (uniform per batch): the static list of pairs
+    // with kept primitive pairs (class order, consecutive records) when most pairs are
+    // active, or the combinations of the shells the bound leaves active (same-l classes over
+    // the triangle ai >= bi; the active lists ascend in shell index) when few are.  Pairs
+    // the bound already skips on this batch are dropped either way.
     struct Cand {
         bool valid;
         int aa, b;
@@ -273,14 +276,60 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void s
         float lp;
         float2 ua, ub;
     };
-    const int64_t total = a.nne;
+    __shared__ int64_t coff[7];
+    __shared__ int use_list;
+    if (tid == 0) {
+        int64_t acc = 0;
+        for (int c = 0; c < 6; ++c) {
+            const int la = kClassLA_dev(c), lb = kClassLB_dev(c);
+            const int64_t nA = sh.aoff[la + 1] - sh.aoff[la], nB = sh.aoff[lb + 1] - sh.aoff[lb];
+            coff[c] = acc;
+            acc += la == lb ? nA * (nA + 1) / 2 : nA * nB;
+        }
+        coff[6] = acc;
+        use_list = 2 * acc >= a.nne;
+    }
+    __syncthreads();
+    const bool list = use_list != 0;
+    const int64_t total = list ? a.nne : coff[6];
     auto fetch = [&](int64_t i, Cand& d) {
-        const int64_t k = i < total ? i : 0;
-        const int2 ab = a.ne_ab[k];
-        d.aa = ab.x;
-        d.b = ab.y;
-        d.p = a.ne_p[k];
-        d.valid = i < total && bins[d.aa] != kNoBin && bins[d.b] != kNoBin && bins[d.aa] + bins[d.b] >= S;
+        int64_t k = 0;
+        bool ok = i < total;
+        if (list) {
+            k = ok ? i : 0;
+            const int2 ab = a.ne_ab[k];
+            d.aa = ab.x;
+            d.b = ab.y;
+            d.p = a.ne_p[k];
+        } else {
+            d.aa = 0;
+            d.b = 0;
+            d.p = 0;
+            if (ok) {
+                int c = 0;
+                while (c < 5 && i >= coff[c + 1]) ++c;
+                const int la = kClassLA_dev(c), lb = kClassLB_dev(c);
+                const int64_t j = i - coff[c];
+                int ai, bi;
+                if (la == lb) {
+                    ai = (int)((sqrtf(8.0f * (float)j + 1.0f) - 1.0f) * 0.5f);
+                    while ((int64_t)ai * (ai + 1) / 2 > j) --ai;
+                    while ((int64_t)(ai + 1) * (ai + 2) / 2 <= j) ++ai;
+                    bi = (int)(j - (int64_t)ai * (ai + 1) / 2);
+                } else {
+                    const int nB = sh.aoff[lb + 1] - sh.aoff[lb];
+                    ai = (int)(j / nB);
+                    bi = (int)(j - (int64_t)ai * nB);
+                }
+                d.aa = act[sh.aoff[la] + ai];
+                d.b = act[sh.aoff[lb] + bi];
+                d.p = pair_index(d.aa, d.b);
+                const int32_t pos = a.ne_pos[d.p];
+                ok = pos >= 0;
+                k = ok ? pos : 0;
+            }
+        }
+        d.valid = ok && bins[d.aa] != kNoBin && bins[d.b] != kNoBin && bins[d.aa] + bins[d.b] >= S;
         d.pf = a.ne_feat[k];
         d.lp = a.ne_lp[k];
         d.ua = Lb[d.aa];
@@ -305,11 +354,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void s
             v = g == 2 ? f[8 + e] : v;
             v = g == 3 ? f[12 + e] : v;
             x[e] = v;
-            oob |= !(v >= R.lo[e] && v <= R.hi[e]);
+            oob |= !(v >= msh.lo[4 * g + e] && v <= msh.hi[4 * g + e]);
         }
         const unsigned long long mo = __ballot(oob);
         const bool sample_oob = ((mo >> r) & 0x0001000100010001ull) != 0ull;
-        const float y = learn::mlp_eval16(R, w2s, x);
+        const float y = learn::mlp_eval16(R, msh, x);
         if (g == 0 && cur.valid) {
             // log2 of the bound c_AB U_A U_B (an over-estimate where a factor was clamped)
             const float lbeta = (learn::log_cab(cur.pf) + cur.ua.x + cur.ub.x) * log2_10;

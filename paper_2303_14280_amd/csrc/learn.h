@@ -68,60 +68,66 @@ constexpr int kW2Ld = 68;   // LDS row stride (bf16 elements) of W2: 136 B sprea
 
 struct MlpRegs {
     bf4 w1[4];          // W1[16m + r][4g + e]
-    f4v b1[4], b2[4];   // b[16m + 4g + e]
-    float w3[4][4];     // W3[16m + 4g + e]
     float b3;
-    float mean[4], istd[4], lo[4], hi[4];   // features 4g + e
+};
+
+// The rest of the network in LDS, shared by the workgroup's waves: W2 as bf16 rows of kW2Ld
+// elements; biases, W3 (bf16-rounded values) and the feature normalisation and range.
+struct MlpShared {
+    short w2[64 * kW2Ld];
+    float b1[64], b2[64], w3[64];
+    float mean[16], istd[16], lo[16], hi[16];
 };
 
 __device__ __forceinline__ short bfs(float x) { return (short)bf16_bits(x); }
 
 // Parameters are bf16-rounded on load (weights and biases), as in the inference form of the
-// standalone forward kernel.  W2 goes to LDS (w2s, 64 rows of kW2Ld; the whole workgroup
-// stores it, the caller synchronises before the first use), the rest to registers.
+// standalone forward kernel.  The whole workgroup fills S; the caller synchronises before
+// the first use.
 __device__ inline void load_mlp(const float* __restrict__ params, const MlpNorm& nrm, const float* lo,
-                                const float* hi, MlpRegs& R, short* w2s)
+                                const float* hi, MlpRegs& R, MlpShared& S)
 {
-    for (int i = threadIdx.x; i < 64 * 64; i += blockDim.x) w2s[(i >> 6) * kW2Ld + (i & 63)] = bfs(params[1088 + i]);
-    constexpr int OW1 = 0, OB1 = 1024, OB2 = 5184, OW3 = 5248, OB3 = 5312;   // W2 at 1088
+    constexpr int OW1 = 0, OB1 = 1024, OW2 = 1088, OB2 = 5184, OW3 = 5248, OB3 = 5312;
+    for (int i = threadIdx.x; i < 64 * 64; i += blockDim.x) S.w2[(i >> 6) * kW2Ld + (i & 63)] = bfs(params[OW2 + i]);
+    for (int i = threadIdx.x; i < 64; i += blockDim.x) {
+        S.b1[i] = bf16_round(params[OB1 + i]);
+        S.b2[i] = bf16_round(params[OB2 + i]);
+        S.w3[i] = bf16_round(params[OW3 + i]);
+    }
+    for (int i = threadIdx.x; i < 16; i += blockDim.x) {
+        S.mean[i] = nrm.mean[i];
+        S.istd[i] = nrm.inv_std[i];
+        S.lo[i] = lo[i];
+        S.hi[i] = hi[i];
+    }
     const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
-    for (int m = 0; m < 4; ++m) {
-        for (int e = 0; e < 4; ++e) {
-            R.w1[m][e] = bfs(params[OW1 + (16 * m + r) * 16 + 4 * g + e]);
-            R.b1[m][e] = bf16_round(params[OB1 + 16 * m + 4 * g + e]);
-            R.b2[m][e] = bf16_round(params[OB2 + 16 * m + 4 * g + e]);
-            R.w3[m][e] = bf16_round(params[OW3 + 16 * m + 4 * g + e]);
-        }
-    }
+    for (int m = 0; m < 4; ++m)
+        for (int e = 0; e < 4; ++e) R.w1[m][e] = bfs(params[OW1 + (16 * m + r) * 16 + 4 * g + e]);
     R.b3 = bf16_round(params[OB3]);
-    for (int e = 0; e < 4; ++e) {
-        R.mean[e] = nrm.mean[4 * g + e];
-        R.istd[e] = nrm.inv_std[4 * g + e];
-        R.lo[e] = lo[4 * g + e];
-        R.hi[e] = hi[4 * g + e];
-    }
 }
 
 // x: raw features 4g..4g+3 of sample r.  Returns the network output of sample r in every
 // lane that holds sample r (all of the wave's lanes take part).
-__device__ inline float mlp_eval16(const MlpRegs& R, const short* w2s, const float x[4])
+__device__ inline float mlp_eval16(const MlpRegs& R, const MlpShared& S, const float x[4])
 {
     const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
     bf4 xb;
-    for (int e = 0; e < 4; ++e) xb[e] = bfs((x[e] - R.mean[e]) * R.istd[e]);
+    for (int e = 0; e < 4; ++e) xb[e] = bfs((x[e] - S.mean[4 * g + e]) * S.istd[4 * g + e]);
     bf4 h1[4];
     for (int m = 0; m < 4; ++m) {
-        f4v acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(R.w1[m], xb, R.b1[m], 0, 0, 0);
+        const f4v b1 = *reinterpret_cast<const f4v*>(S.b1 + 16 * m + 4 * g);
+        f4v acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(R.w1[m], xb, b1, 0, 0, 0);
         for (int e = 0; e < 4; ++e) h1[m][e] = bfs(silu(acc[e]));
     }
     float y = 0.0f;
     for (int m2 = 0; m2 < 4; ++m2) {
-        f4v acc = R.b2[m2];
+        f4v acc = *reinterpret_cast<const f4v*>(S.b2 + 16 * m2 + 4 * g);
         for (int m = 0; m < 4; ++m) {
-            const bf4 w = *reinterpret_cast<const bf4*>(w2s + (16 * m2 + r) * kW2Ld + 16 * m + 4 * g);
+            const bf4 w = *reinterpret_cast<const bf4*>(S.w2 + (16 * m2 + r) * kW2Ld + 16 * m + 4 * g);
             acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w, h1[m], acc, 0, 0, 0);
         }
-        for (int e = 0; e < 4; ++e) y = fmaf(R.w3[m2][e], bf16_round(silu(acc[e])), y);
+        const f4v w3 = *reinterpret_cast<const f4v*>(S.w3 + 16 * m2 + 4 * g);
+        for (int e = 0; e < 4; ++e) y = fmaf(w3[e], bf16_round(silu(acc[e])), y);
     }
     y += __shfl_xor(y, 16);
     y += __shfl_xor(y, 32);

@@ -134,6 +134,7 @@ struct snk_ctx {
     int32_t ne_class_off[7] = {0, 0, 0, 0, 0, 0, 0};
     int32_t* d_ne_list = nullptr;
     int2* d_ne_ab = nullptr;
+    int32_t* d_ne_pos = nullptr;
     PairFeat* d_ne_feat = nullptr;
     int32_t* d_pool_runs[12] = {};
     int32_t* d_pool_bt[12] = {};
@@ -406,6 +407,9 @@ int build_pair_feats(snk_ctx* c)
         ne_feat[k] = pf[c->ne_list[k]];
     }
     if ((rc = upload(c, &c->d_ne_ab, ne_ab))) return rc;
+    std::vector<int32_t> ne_pos((size_t)np, -1);
+    for (size_t k = 0; k < c->ne_list.size(); ++k) ne_pos[c->ne_list[k]] = (int32_t)k;
+    if ((rc = upload(c, &c->d_ne_pos, ne_pos))) return rc;
     if ((rc = upload(c, &c->d_ne_feat, ne_feat))) return rc;
     return SNK_OK;
 }
@@ -768,6 +772,7 @@ void free_ctx(snk_ctx* c)
     (void)hipFree(c->d_prims32);
     (void)hipFree(c->d_ne_list);
     (void)hipFree(c->d_ne_ab);
+    (void)hipFree(c->d_ne_pos);
     (void)hipFree(c->d_ne_feat);
     (void)hipFree(c->d_counts);
     (void)hipFree(c->d_npairs);
@@ -1104,6 +1109,7 @@ int group_until_G(snk_ctx* c, const Group& g, const double* dP, bool timed, Grou
             ea.ne_ab = c->d_ne_ab;
             ea.ne_feat = c->d_ne_feat;
             ea.ne_lp = c->d_lp;
+            ea.ne_pos = c->d_ne_pos;
             ea.geo = c->d_geo + g.b0;
             ea.eps_batch = eps_batch;
             ea.params = mlp_params(c->mlp);

@@ -179,6 +179,7 @@ struct EstArgs {
     const int2* ne_ab;          //   [nne] shells (A, B)
     const PairFeat* ne_feat;    //   [nne] static features
     const float* ne_lp;         //   [nne] log10 of the Frobenius norm of the P block
+    const int32_t* ne_pos;      // [npair_total] position of a pair index in that list, -1 if absent
     const BatchGeo* geo;        // [nbatch] of this group
     double eps_batch;
     const float* params;        // network parameters (FP32; rounded to bf16 on load)
