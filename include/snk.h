@@ -118,7 +118,12 @@ typedef struct snk_opts {
     int32_t precision;          /* snk_precision */
     int32_t screen;             /* snk_screen */
     const snk_mlp* screener;    /* required for SNK_SCREEN_LEARNED */
-    double eps_basis;           /* basis-function screening tolerance eps_B (Eq. basis_screen); 0 = off */
+    double eps_basis;           /* basis-function screening tolerance eps_B (Eq. basis_screen); 0 = off.
+                                   > 0: batches are ordered spatially into tiles of at most 128;
+                                   tile t collocates only the functions B_t whose sphere of
+                                   radius r_cut (beyond which |phi| < eps_basis) reaches the box
+                                   of the tile's points; F_t = P[:, B_t] Phi_t and only the
+                                   columns B_t of K~ receive G_t Phi_t^T (Sec. II.E) */
     double eps_skip_energy;     /* total energy budget for skipped blocks (Eh) */
     double eps_lowprec_energy;  /* SNK_MIXED: error budget of the FP32 blocks (Eh), see SNK_MIXED */
     int32_t batch_points;       /* maximum points per batch, 64..256 (default 256) */
@@ -161,6 +166,24 @@ void snk_ctx_destroy(snk_ctx* ctx);
 /* Number of basis functions of a context, and its number of spatial batches. */
 int snk_ctx_nbf(const snk_ctx* ctx);
 int snk_ctx_nbatches(const snk_ctx* ctx);
+
+/*
+ * Batch groups and tiles.  A group (Alg. 1: the batches processed together) holds the columns
+ * of one F_g and G_g; the screen and the A.F kernels run over a whole group.  A tile is a run
+ * of consecutive batches of a group that shares one set B_t of collocated functions
+ * (Eq. basis_screen); collocation and both GEMMs run per tile.  Without basis screening each
+ * group is one tile with all N_b functions; with eps_basis > 0 tiles hold up to 128
+ * spatially ordered batches.
+ * snk_ctx_ngroups / snk_ctx_ntiles: their numbers.  snk_ctx_tile_info: for tile k, its
+ * group, its batches [b0[k], b1[k]) in the context's batch order (see snk_ctx_point_order)
+ * and nB[k] = |B_t|; host arrays of snk_ctx_ntiles entries, any may be NULL.
+ * snk_ctx_tile_functions: the global indices of the tile's functions, ascending, into host
+ * fn[nB[k]]; SNK_E_ARG for a bad index.
+ */
+int snk_ctx_ngroups(const snk_ctx* ctx);
+int snk_ctx_ntiles(const snk_ctx* ctx);
+int snk_ctx_tile_info(const snk_ctx* ctx, int32_t* group, int32_t* b0, int32_t* b1, int32_t* nB);
+int snk_ctx_tile_functions(const snk_ctx* ctx, int32_t tile, int32_t* fn);
 
 /* Diagnostics. */
 const char* snk_status_string(int status);
@@ -243,8 +266,9 @@ int snk_ctx_block_data(snk_ctx* ctx, const double* P, float* features, double* b
  *   grid point in batch column c, or -1 for a padding slot.
  * snk_ctx_debug_intermediates: for the first batch group only, the collocation matrix
  *   Phi (Eq. collocation), F (Eq. fmat) and G (Eq. gmat), each nbf x ncols row-major in
- *   host memory (ncols = 256 * batches of that group, returned in *ncols_out); P is a host
- *   pointer.  Pass NULL for any output not wanted.
+ *   host memory (ncols = 256 * batches of that group, returned in *ncols_out); elements of
+ *   Phi outside their tile's B_t are zero; P is a host pointer.  Pass NULL for any output not
+ *   wanted.
  * snk_ctx_npair_index: size of the pair index space, nshell (nshell + 1) / 2 (pair of
  *   shells s >= t at s (s + 1) / 2 + t).
  * snk_ctx_debug_learned: runs the learned screen of the first batch group (context made

@@ -155,6 +155,17 @@ __global__ __launch_bounds__(256) void fill_kernel(T* __restrict__ p, int64_t n,
         p[i] = v;
 }
 
+// p[r * ld + c] = v for r < rows, c < cols
+template <typename T>
+__global__ __launch_bounds__(256) void fill2d_kernel(T* __restrict__ p, int64_t rows, int64_t cols, int64_t ld, T v)
+{
+    const int64_t n = rows * cols;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = i / cols;
+        p[r * ld + (i - r * cols)] = v;
+    }
+}
+
 __global__ __launch_bounds__(256) void convert_kernel(const double* __restrict__ in, int64_t n, float* __restrict__ out)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -198,17 +209,18 @@ __global__ __launch_bounds__(256) void finish_reduce_kernel(const double* __rest
     if (threadIdx.x == 0) ex[0] = -0.5 * s;
 }
 
+template <typename TO>
 __global__ __launch_bounds__(256) void gather_kernel(const double* __restrict__ P, int64_t nbf,
                                                      const int32_t* __restrict__ rows, int64_t M,
                                                      const int32_t* __restrict__ cols, int64_t N,
-                                                     double* __restrict__ out)
+                                                     TO* __restrict__ out)
 {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= M * N) return;
     const int64_t m = idx / N, n = idx - m * N;
     const int64_t r = rows ? rows[m] : m;
     const int64_t c = cols ? cols[n] : n;
-    out[idx] = P[r * nbf + c];
+    out[idx] = (TO)P[r * nbf + c];
 }
 
 // One wave: A[i][k] = (k == 0) + i (k == 1), B[k][j] = 100 j (k == 0) + (k == 1), so that
@@ -316,6 +328,35 @@ hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t s)
     return hipGetLastError();
 }
 
+template <typename T>
+static hipError_t launch_fill2d_t(T* p, int64_t rows, int64_t cols, int64_t ld, T v, hipStream_t s)
+{
+    if (rows <= 0 || cols <= 0) return hipSuccess;
+    int64_t blocks = (rows * cols + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL((fill2d_kernel<T>), dim3((unsigned)blocks), dim3(256), 0, s, p, rows, cols, ld, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill2d(double* p, int64_t rows, int64_t cols, int64_t ld, double v, hipStream_t s)
+{
+    return launch_fill2d_t<double>(p, rows, cols, ld, v, s);
+}
+
+hipError_t launch_fill2d(float* p, int64_t rows, int64_t cols, int64_t ld, float v, hipStream_t s)
+{
+    return launch_fill2d_t<float>(p, rows, cols, ld, v, s);
+}
+
+hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL((fill_kernel<float>), dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
 hipError_t launch_finish(const double* Kt, const double* P, double* K, int64_t nbf, double* partial, int nblk,
                          double* ex, hipStream_t s)
 {
@@ -324,13 +365,27 @@ hipError_t launch_finish(const double* Kt, const double* P, double* K, int64_t n
     return hipGetLastError();
 }
 
-hipError_t launch_gather(const double* P, int64_t nbf, const int32_t* rows, int64_t M, const int32_t* cols, int64_t N,
-                         double* out, hipStream_t s)
+template <typename TO>
+static hipError_t launch_gather_t(const double* P, int64_t nbf, const int32_t* rows, int64_t M, const int32_t* cols,
+                                  int64_t N, TO* out, hipStream_t s)
 {
     if (M <= 0 || N <= 0) return hipSuccess;
     const int64_t n = M * N;
-    hipLaunchKernelGGL(gather_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, P, nbf, rows, M, cols, N, out);
+    hipLaunchKernelGGL((gather_kernel<TO>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, P, nbf, rows, M, cols,
+                       N, out);
     return hipGetLastError();
+}
+
+hipError_t launch_gather(const double* P, int64_t nbf, const int32_t* rows, int64_t M, const int32_t* cols, int64_t N,
+                         double* out, hipStream_t s)
+{
+    return launch_gather_t<double>(P, nbf, rows, M, cols, N, out, s);
+}
+
+hipError_t launch_gather(const double* P, int64_t nbf, const int32_t* rows, int64_t M, const int32_t* cols, int64_t N,
+                         float* out, hipStream_t s)
+{
+    return launch_gather_t<float>(P, nbf, rows, M, cols, N, out, s);
 }
 
 }  // namespace snk

@@ -33,17 +33,30 @@ const double kPi = 3.14159265358979323846;
 
 int ncart(int l) { return (l + 1) * (l + 2) / 2; }
 
-struct Group {
+// A run of consecutive batches of a group that shares one set of collocated functions B_t
+// (basis screening, Eq. basis_screen).  Without basis screening one tile spans its group and
+// holds every function.  Collocation and both GEMMs run per tile; the screen and the A.F
+// kernels run over the whole group.
+struct Tile {
     int b0 = 0, b1 = 0;                 // batch range [b0, b1)
-    int64_t ncols = 0;                  // (b1 - b0) * kBatch
-    std::vector<int32_t> coll_shells;   // shells collocated for this group (basis screening, Eq. basis_screen)
-    std::vector<int32_t> coll_rows;     // row of each such shell's first function in Phi_g
-    std::vector<int32_t> coll_fn;       // global function index of every Phi_g row
-    int32_t nB = 0;                     // rows of Phi_g
+    int64_t col0 = 0;                   // first column of the tile in the group's F and G
+    int64_t ncols = 0;                  // (b1 - b0) * kBatch; also the row stride of Phi_t
+    int64_t phi_off = 0;                // offset of Phi_t (nB x ncols) in the Phi buffer
+    std::vector<int32_t> coll_shells;   // shells collocated for this tile
+    std::vector<int32_t> coll_rows;     // row of each such shell's first function in Phi_t
+    std::vector<int32_t> coll_fn;       // global function index of every Phi_t row
+    int32_t nB = 0;                     // rows of Phi_t
     int32_t* d_coll_shells = nullptr;
     int32_t* d_coll_rows = nullptr;
     int32_t* d_coll_fn = nullptr;
-    bool all_functions = true;          // Phi_g rows == all basis functions in order
+    bool all_functions = true;          // Phi_t rows == all basis functions in order
+};
+
+struct Group {
+    int b0 = 0, b1 = 0;                 // batch range [b0, b1)
+    int64_t ncols = 0;                  // (b1 - b0) * kBatch: columns of F_g and G_g
+    std::vector<Tile> tiles;
+    int64_t phi_elems = 0;              // sum of nB * ncols over the tiles
 };
 
 }  // namespace
@@ -59,6 +72,7 @@ struct snk_ctx {
     int nshell = 0, nbf = 0;
     std::vector<int32_t> sl, snp, spo, sfn;
     std::vector<double> scen, exps, coefs;
+    std::vector<double> rcut;             // basis screening radius of each shell (eps_basis > 0)
     ShellDev* d_shells = nullptr;
     double* d_exps = nullptr;
     double* d_coefs = nullptr;
@@ -82,16 +96,19 @@ struct snk_ctx {
     int nbatch = 0;
     double *d_px = nullptr, *d_py = nullptr, *d_pz = nullptr, *d_pw = nullptr;
     std::vector<int32_t> batch_npts;
+    std::vector<double> batch_box;        // [nbatch][6]: lower and upper corner of the batch's points
     std::vector<int64_t> col_point;       // input index of the point in each batch column, -1 = padding
 
     // batch groups and workspace
     std::vector<Group> groups;
     int64_t max_cols = 0;
-    int32_t max_nB = 0;
+    int64_t max_tile_cols = 0;
+    int64_t max_phi = 0;                // Phi buffer elements (largest group)
+    int32_t max_nB = 0;                 // largest tile function set
     int nsplit = 1;
     bool mixed = false;                 // SNK_MIXED + SNK_FP32_GEMM: FP32 Phi, P and F; FP32 matrix-core GEMMs
     rocblas_handle blas = nullptr;      // SNK_ROCBLAS (FP64 builds)
-    float *d_Phi32 = nullptr, *d_F32 = nullptr, *d_P32 = nullptr;
+    float *d_Phi32 = nullptr, *d_F32 = nullptr, *d_P32 = nullptr, *d_Pg32 = nullptr;
     double *d_Phi = nullptr, *d_F = nullptr, *d_G = nullptr, *d_part = nullptr, *d_Pg = nullptr;
     double *d_Kt = nullptr, *d_P = nullptr, *d_K = nullptr, *d_partial = nullptr, *d_ex = nullptr;
     double* d_boys = nullptr;
@@ -443,6 +460,46 @@ void split_points(const double* xyz, std::vector<int64_t>& idx, size_t lo, size_
     split_points(xyz, idx, lo + left, hi, out, cap);
 }
 
+// Batches per tile when basis functions are screened: a tile's functions are those whose
+// sphere reaches the tile's box, so tiles are spatially compact and small enough for the box
+// to exclude distant functions, and large enough (32768 columns) for full-rate GEMMs.
+constexpr int kBasisTileBatches = 128;
+
+// Radius beyond which every Cartesian function of a shell is below eps in magnitude, for the
+// sphere test of Eq. basis_screen; -1 when the shell stays below eps everywhere.  Each
+// unit-normalised component is bounded by r^l times the radial part (|x^a y^b z^c| <= r^l,
+// and sqrt(3) |xy| <= sqrt(3) r^2 / 2 < r^2 for the mixed d components), so
+// b(r) = r^l sum_k |c_k| exp(-zeta_k r^2) bounds the shell, and b never exceeds
+// sum_k |c_k| max_r r^l exp(-zeta_k r^2) = sum_k |c_k| (l / (2 e zeta_k))^(l/2).  Every term
+// of b decreases beyond r0 = sqrt(l / (2 zeta_min)); the radius is the crossing b(r) = eps
+// above r0, or r0 itself when b(r0) < eps already.
+double shell_rcut(int l, const double* e, const double* cf, int np, double eps)
+{
+    double zmin = e[0], peak = 0.0;
+    for (int k = 1; k < np; ++k) zmin = std::min(zmin, e[k]);
+    for (int k = 0; k < np; ++k)
+        peak += std::fabs(cf[k]) * (l > 0 ? std::pow(l / (2.0 * M_E * e[k]), 0.5 * l) : 1.0);
+    if (peak < eps) return -1.0;
+    auto b = [&](double r) {
+        double v = 0.0;
+        for (int k = 0; k < np; ++k) v += std::fabs(cf[k]) * std::exp(-e[k] * r * r);
+        return v * std::pow(r, l);
+    };
+    const double r0 = l > 0 ? std::sqrt(l / (2.0 * zmin)) : 0.0;
+    if (b(r0) < eps) return r0;
+    double lo = r0, hi = std::max(2.0 * r0, 1.0);
+    while (b(hi) >= eps) {
+        lo = hi;
+        hi *= 2.0;
+    }
+    for (int it = 0; it < 200 && hi - lo > 1e-12 * hi; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (b(mid) >= eps) lo = mid;
+        else hi = mid;
+    }
+    return hi;
+}
+
 int build_grid(snk_ctx* c, const snk_grid* g, const double* w)
 {
     c->npts = g->npts;
@@ -465,6 +522,26 @@ int build_grid(snk_ctx* c, const snk_grid* g, const double* w)
             split_points(g->xyz, idx, 0, idx.size(), ranges, cap);
         }
     }
+    if (c->opts.eps_basis > 0.0 && ranges.size() > (size_t)kBasisTileBatches) {
+        // order the batches by recursive bisection of their centroids, so that runs of
+        // kBasisTileBatches consecutive batches (the tiles) are spatially compact
+        std::vector<double> cen(3 * ranges.size(), 0.0);
+        for (size_t b = 0; b < ranges.size(); ++b) {
+            for (size_t k = ranges[b].first; k < ranges[b].second; ++k)
+                for (int d = 0; d < 3; ++d) cen[3 * b + d] += g->xyz[3 * idx[k] + d];
+            for (int d = 0; d < 3; ++d) cen[3 * b + d] /= (double)(ranges[b].second - ranges[b].first);
+        }
+        std::vector<int64_t> order(ranges.size());
+        std::iota(order.begin(), order.end(), 0);
+        std::vector<std::pair<size_t, size_t>> chunks, leaves;
+        split_points(cen.data(), order, 0, order.size(), chunks, kBasisTileBatches);
+        // and within each tile-sized chunk down to single batches, so that shorter runs
+        // (smaller groups under a tight device budget) are compact as well
+        for (const auto& ch : chunks) split_points(cen.data(), order, ch.first, ch.second, leaves, 1);
+        std::vector<std::pair<size_t, size_t>> sorted(ranges.size());
+        for (size_t b = 0; b < order.size(); ++b) sorted[b] = ranges[order[b]];
+        ranges.swap(sorted);
+    }
     c->nbatch = (int)ranges.size();
     const size_t ncol = (size_t)c->nbatch * kBatch;
     std::vector<double> px(ncol), py(ncol), pz(ncol), pw(ncol, 0.0);
@@ -484,6 +561,7 @@ int build_grid(snk_ctx* c, const snk_grid* g, const double* w)
         }
     }
     std::vector<BatchGeo> geo(c->nbatch);
+    c->batch_box.assign((size_t)c->nbatch * 6, 0.0);
     for (int b = 0; b < c->nbatch; ++b) {
         BatchGeo gb{};
         double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300}, ctr[3] = {0, 0, 0}, ws = 0.0;
@@ -503,6 +581,8 @@ int build_grid(snk_ctx* c, const snk_grid* g, const double* w)
             if (n == 0) lo[d] = hi[d] = 0.0;
             gb.lo[d] = (float)lo[d];
             gb.hi[d] = (float)hi[d];
+            c->batch_box[6 * (size_t)b + d] = lo[d];
+            c->batch_box[6 * (size_t)b + 3 + d] = hi[d];
             gb.ctr[d] = (float)(n ? ctr[d] / n : 0.0);
             hd2 += 0.25 * (hi[d] - lo[d]) * (hi[d] - lo[d]);
         }
@@ -523,9 +603,10 @@ int build_grid(snk_ctx* c, const snk_grid* g, const double* w)
 int build_groups(snk_ctx* c)
 {
     c->groups.clear();
-    // Phi, F and G columns of one batch (Phi and F are FP32 in the mixed build)
-    const bool f32 = c->opts.precision == SNK_MIXED && (c->opts.flags & SNK_FP32_GEMM);
-    int64_t per_batch = (int64_t)c->nbf * kBatch * (f32 ? 16 : 24);
+    // Phi, F and G columns of one batch, sized for FP64 storage in both precisions (the
+    // mixed build stores Phi and F in FP32 and uses less), so that the groups, and with them
+    // the basis-screened sets B_g, are the same for both
+    int64_t per_batch = (int64_t)c->nbf * kBatch * 24;
     if (c->opts.screen == SNK_SCREEN_LEARNED) per_batch += c->npair_total * (int64_t)sizeof(float);
     int64_t budget = c->opts.max_device_bytes;
     if (budget <= 0) {
@@ -538,29 +619,69 @@ int build_groups(snk_ctx* c)
         set_err(c, "device budget smaller than one batch");
         return SNK_E_NOMEM;
     }
+    const bool bscreen = c->opts.eps_basis > 0.0;
+    // with basis screening, groups are whole numbers of spatially ordered tiles
+    if (bscreen && per_group > kBasisTileBatches) per_group -= per_group % kBasisTileBatches;
+    const int64_t tile_batches = bscreen ? std::min<int64_t>(per_group, kBasisTileBatches) : per_group;
     for (int b0 = 0; b0 < c->nbatch; b0 += (int)per_group) {
         Group gr;
         gr.b0 = b0;
         gr.b1 = (int)std::min<int64_t>(c->nbatch, b0 + per_group);
         gr.ncols = (int64_t)(gr.b1 - gr.b0) * kBatch;
-        for (int s = 0; s < c->nshell; ++s) {
-            gr.coll_shells.push_back(s);
-            gr.coll_rows.push_back(c->sfn[s]);
+        for (int t0 = gr.b0; t0 < gr.b1; t0 += (int)tile_batches) {
+            Tile t;
+            t.b0 = t0;
+            t.b1 = (int)std::min<int64_t>(gr.b1, t0 + tile_batches);
+            t.col0 = (int64_t)(t0 - gr.b0) * kBatch;
+            t.ncols = (int64_t)(t.b1 - t.b0) * kBatch;
+            t.phi_off = gr.phi_elems;
+            // B_t (Eq. basis_screen at tile level): the shells whose sphere of radius rcut
+            // reaches the box of the tile's points; a superset of the union of its batches' B_j
+            double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+            if (bscreen)
+                for (int b = t.b0; b < t.b1; ++b)
+                    for (int d = 0; d < 3; ++d) {
+                        lo[d] = std::min(lo[d], c->batch_box[6 * (size_t)b + d]);
+                        hi[d] = std::max(hi[d], c->batch_box[6 * (size_t)b + 3 + d]);
+                    }
+            int32_t row = 0;
+            for (int s = 0; s < c->nshell; ++s) {
+                if (bscreen) {
+                    double d2 = 0.0;
+                    for (int d = 0; d < 3; ++d) {
+                        const double x = c->scen[3 * s + d];
+                        const double e = std::max(std::max(lo[d] - x, x - hi[d]), 0.0);
+                        d2 += e * e;
+                    }
+                    if (c->rcut[s] < 0.0 || d2 > c->rcut[s] * c->rcut[s]) continue;
+                }
+                t.coll_shells.push_back(s);
+                t.coll_rows.push_back(row);
+                for (int k = 0; k < ncart(c->sl[s]); ++k) t.coll_fn.push_back(c->sfn[s] + k);
+                row += ncart(c->sl[s]);
+            }
+            t.nB = row;
+            t.all_functions = row == c->nbf;
+            gr.phi_elems += (int64_t)t.nB * t.ncols;
+            gr.tiles.push_back(std::move(t));
         }
-        for (int f = 0; f < c->nbf; ++f) gr.coll_fn.push_back(f);
-        gr.nB = c->nbf;
-        gr.all_functions = true;
         c->groups.push_back(std::move(gr));
     }
     c->max_cols = 0;
+    c->max_tile_cols = 0;
+    c->max_phi = 0;
     c->max_nB = 0;
     for (auto& gr : c->groups) {
         c->max_cols = std::max(c->max_cols, gr.ncols);
-        c->max_nB = std::max(c->max_nB, gr.nB);
-        int rc;
-        if ((rc = upload(c, &gr.d_coll_shells, gr.coll_shells))) return rc;
-        if ((rc = upload(c, &gr.d_coll_rows, gr.coll_rows))) return rc;
-        if ((rc = upload(c, &gr.d_coll_fn, gr.coll_fn))) return rc;
+        c->max_phi = std::max(c->max_phi, gr.phi_elems);
+        for (auto& t : gr.tiles) {
+            c->max_tile_cols = std::max(c->max_tile_cols, t.ncols);
+            c->max_nB = std::max(c->max_nB, t.nB);
+            int rc;
+            if ((rc = upload(c, &t.d_coll_shells, t.coll_shells))) return rc;
+            if ((rc = upload(c, &t.d_coll_rows, t.coll_rows))) return rc;
+            if ((rc = upload(c, &t.d_coll_fn, t.coll_fn))) return rc;
+        }
     }
     return SNK_OK;
 }
@@ -730,14 +851,16 @@ void free_ctx(snk_ctx* c)
     (void)hipFree(c->d_py);
     (void)hipFree(c->d_pz);
     (void)hipFree(c->d_pw);
-    for (auto& g : c->groups) {
-        (void)hipFree(g.d_coll_shells);
-        (void)hipFree(g.d_coll_rows);
-        (void)hipFree(g.d_coll_fn);
-    }
+    for (auto& g : c->groups)
+        for (auto& t : g.tiles) {
+            (void)hipFree(t.d_coll_shells);
+            (void)hipFree(t.d_coll_rows);
+            (void)hipFree(t.d_coll_fn);
+        }
     (void)hipFree(c->d_Phi32);
     (void)hipFree(c->d_F32);
     (void)hipFree(c->d_P32);
+    (void)hipFree(c->d_Pg32);
     (void)hipFree(c->d_Phi);
     (void)hipFree(c->d_F);
     (void)hipFree(c->d_G);
@@ -865,10 +988,6 @@ int snk_ctx_create(const snk_basis* basis, const snk_grid* grid, const double* w
         if (!has_range) return arg_error(nullptr, "screener network has no training range set");
         if (mlp_device(o.screener) != o.device) return arg_error(nullptr, "screener network is on another device");
     }
-    if (o.eps_basis != 0.0) {
-        set_err(nullptr, "option not available in this build");
-        return SNK_E_UNSUPPORTED;
-    }
 
     snk_ctx* c = new (std::nothrow) snk_ctx();
     if (!c) return SNK_E_NOMEM;
@@ -928,6 +1047,11 @@ int snk_ctx_create(const snk_basis* basis, const snk_grid* grid, const double* w
         sh[s] = ShellDev{c->scen[3 * s], c->scen[3 * s + 1], c->scen[3 * s + 2], c->sl[s], c->snp[s], c->spo[s], 0};
     }
     c->nbf = fn;
+    if (o.eps_basis > 0.0) {
+        c->rcut.resize(c->nshell);
+        for (int s = 0; s < c->nshell; ++s)
+            c->rcut[s] = shell_rcut(c->sl[s], &c->exps[c->spo[s]], &c->coefs[c->spo[s]], c->snp[s], o.eps_basis);
+    }
     CREATE_CHECK(upload(c, &c->d_shells, sh));
     CREATE_CHECK(upload(c, &c->d_exps, c->exps));
     CREATE_CHECK(upload(c, &c->d_coefs, c->coefs));
@@ -951,15 +1075,19 @@ int snk_ctx_create(const snk_basis* basis, const snk_grid* grid, const double* w
     {
         const int64_t tiles = ((nbf + 63) / 64) * ((c->max_nB + 63) / 64);
         int ns = (int)std::max<int64_t>(1, (2048 + tiles - 1) / std::max<int64_t>(1, tiles));
-        ns = (int)std::min<int64_t>(ns, std::max<int64_t>(1, c->max_cols / kBatch));
+        ns = (int)std::min<int64_t>(ns, std::max<int64_t>(1, c->max_tile_cols / kBatch));
         c->nsplit = std::max(1, std::min(ns, 256));
     }
     if (c->mixed) {
-        CREATE_CHECK(dalloc(c, &c->d_Phi32, (size_t)c->max_nB * c->max_cols));
+        CREATE_CHECK(dalloc(c, &c->d_Phi32, (size_t)std::max<int64_t>(1, c->max_phi)));
         CREATE_CHECK(dalloc(c, &c->d_F32, (size_t)nbf * c->max_cols));
         CREATE_CHECK(dalloc(c, &c->d_P32, (size_t)nbf * nbf));
+        bool gather = false;
+        for (const auto& g : c->groups)
+            for (const auto& t : g.tiles) gather |= !t.all_functions;
+        if (gather) CREATE_CHECK(dalloc(c, &c->d_Pg32, (size_t)nbf * c->max_nB));
     } else {
-        CREATE_CHECK(dalloc(c, &c->d_Phi, (size_t)c->max_nB * c->max_cols));
+        CREATE_CHECK(dalloc(c, &c->d_Phi, (size_t)std::max<int64_t>(1, c->max_phi)));
         CREATE_CHECK(dalloc(c, &c->d_F, (size_t)nbf * c->max_cols));
     }
     CREATE_CHECK(dalloc(c, &c->d_G, (size_t)nbf * c->max_cols));
@@ -1014,42 +1142,115 @@ int group_F(snk_ctx* c, const Group& g, const double* dP, bool timed)
     hipStream_t s = c->stream;
     const int64_t nbf = c->nbf;
     const int64_t ld = g.ncols;
-    const int64_t off = (int64_t)g.b0 * kBatch;
     if (timed) HIPCHECK(c, hipEventRecord(c->ev[0], s));
-    if (c->mixed) {
-        // FP32 Phi and F; P was rounded to FP32 once per build (d_P32)
-        HIPCHECK(c, launch_collocate(c->d_px + off, c->d_py + off, c->d_pz + off, g.ncols, c->d_shells, c->d_exps,
-                                     c->d_coefs, g.d_coll_shells, g.d_coll_rows, (int32_t)g.coll_shells.size(),
-                                     c->d_Phi32, ld, s));
-        if (timed) HIPCHECK(c, hipEventRecord(c->ev[1], s));
-        HIPCHECK(c, launch_gemm_f32(nbf, g.ncols, g.nB, c->d_P32, nbf, c->d_Phi32, ld, false, c->d_F32, ld, 1, 0, s));
-        if (timed) HIPCHECK(c, hipEventRecord(c->ev[2], s));
-        return SNK_OK;
+    // Eq. collocation for every tile: Phi_t (nB x ncols_t, row stride ncols_t)
+    for (const Tile& t : g.tiles) {
+        const int64_t off = (int64_t)t.b0 * kBatch;
+        if (c->mixed)
+            HIPCHECK(c, launch_collocate(c->d_px + off, c->d_py + off, c->d_pz + off, t.ncols, c->d_shells, c->d_exps,
+                                         c->d_coefs, t.d_coll_shells, t.d_coll_rows, (int32_t)t.coll_shells.size(),
+                                         c->d_Phi32 + t.phi_off, t.ncols, s));
+        else
+            HIPCHECK(c, launch_collocate(c->d_px + off, c->d_py + off, c->d_pz + off, t.ncols, c->d_shells, c->d_exps,
+                                         c->d_coefs, t.d_coll_shells, t.d_coll_rows, (int32_t)t.coll_shells.size(),
+                                         c->d_Phi + t.phi_off, t.ncols, s));
     }
-    HIPCHECK(c, launch_collocate(c->d_px + off, c->d_py + off, c->d_pz + off, g.ncols, c->d_shells, c->d_exps,
-                                 c->d_coefs, g.d_coll_shells, g.d_coll_rows, (int32_t)g.coll_shells.size(), c->d_Phi,
-                                 ld, s));
     if (timed) HIPCHECK(c, hipEventRecord(c->ev[1], s));
-    const double* Pg = dP;
-    int64_t ldp = nbf;
-    if (!g.all_functions) {
-        HIPCHECK(c, launch_gather(dP, nbf, nullptr, nbf, g.d_coll_fn, g.nB, c->d_Pg, s));
-        Pg = c->d_Pg;
-        ldp = g.nB;
-    }
-    if (c->blas) {
-        // column-major view: F^T (ncols x nbf) = Phi^T (ncols x nB) P_g^T (nB x nbf)
-        const double one = 1.0, zero = 0.0;
-        if (rocblas_dgemm(c->blas, rocblas_operation_none, rocblas_operation_none, (rocblas_int)g.ncols,
-                          (rocblas_int)nbf, (rocblas_int)g.nB, &one, c->d_Phi, (rocblas_int)ld, Pg,
-                          (rocblas_int)ldp, &zero, c->d_F, (rocblas_int)ld) != rocblas_status_success) {
-            set_err(c, "rocblas_dgemm (F) failed");
-            return SNK_E_DEVICE;
+    // Eq. fmat per tile: F[:, tile columns] = P[:, B_t] Phi_t
+    for (const Tile& t : g.tiles) {
+        if (t.nB == 0) {
+            // no function reaches the tile's points
+            if (c->mixed) HIPCHECK(c, launch_fill2d(c->d_F32 + t.col0, nbf, t.ncols, ld, 0.0f, s));
+            else HIPCHECK(c, launch_fill2d(c->d_F + t.col0, nbf, t.ncols, ld, 0.0, s));
+            continue;
         }
-    } else {
-        HIPCHECK(c, launch_gemm_f64(nbf, g.ncols, g.nB, Pg, ldp, c->d_Phi, ld, false, c->d_F, ld, 1, 0, s));
+        if (c->mixed) {
+            // FP32 Phi and F; P was rounded to FP32 once per build (d_P32), or is gathered to
+            // FP32 columns B_t
+            const float* Pg = c->d_P32;
+            int64_t ldp = nbf;
+            if (!t.all_functions) {
+                HIPCHECK(c, launch_gather(dP, nbf, nullptr, nbf, t.d_coll_fn, t.nB, c->d_Pg32, s));
+                Pg = c->d_Pg32;
+                ldp = t.nB;
+            }
+            HIPCHECK(c, launch_gemm_f32(nbf, t.ncols, t.nB, Pg, ldp, c->d_Phi32 + t.phi_off, t.ncols, false,
+                                        c->d_F32 + t.col0, ld, 1, 0, s));
+            continue;
+        }
+        const double* Pg = dP;
+        int64_t ldp = nbf;
+        if (!t.all_functions) {
+            HIPCHECK(c, launch_gather(dP, nbf, nullptr, nbf, t.d_coll_fn, t.nB, c->d_Pg, s));
+            Pg = c->d_Pg;
+            ldp = t.nB;
+        }
+        if (c->blas) {
+            // column-major view: F^T (ncols_t x nbf) = Phi_t^T (ncols_t x nB) P_t^T (nB x nbf)
+            const double one = 1.0, zero = 0.0;
+            if (rocblas_dgemm(c->blas, rocblas_operation_none, rocblas_operation_none, (rocblas_int)t.ncols,
+                              (rocblas_int)nbf, (rocblas_int)t.nB, &one, c->d_Phi + t.phi_off, (rocblas_int)t.ncols,
+                              Pg, (rocblas_int)ldp, &zero, c->d_F + t.col0, (rocblas_int)ld) != rocblas_status_success) {
+                set_err(c, "rocblas_dgemm (F) failed");
+                return SNK_E_DEVICE;
+            }
+        } else {
+            HIPCHECK(c, launch_gemm_f64(nbf, t.ncols, t.nB, Pg, ldp, c->d_Phi + t.phi_off, t.ncols, false,
+                                        c->d_F + t.col0, ld, 1, 0, s));
+        }
     }
     if (timed) HIPCHECK(c, hipEventRecord(c->ev[2], s));
+    return SNK_OK;
+}
+
+// Eq. usym_k for one group: Kt[:, B_t] += G[:, tile columns] Phi_t^T for every tile, split
+// over grid points and reduced in a fixed order
+int group_K(snk_ctx* c, const Group& g)
+{
+    hipStream_t s = c->stream;
+    const int64_t nbf = c->nbf;
+    const int64_t ld = g.ncols;
+    for (const Tile& t : g.tiles) {
+        if (t.nB == 0) continue;   // nothing collocated: G Phi_t^T is empty
+        const int64_t stride = nbf * t.nB;
+        const int32_t* cols = t.all_functions ? nullptr : t.d_coll_fn;
+        if (c->blas) {
+            // split over whole batches of points; column-major view of chunk z:
+            // part_z^T (nB x nbf) = Phi_z (nB x kchunk) G_z^T (kchunk x nbf), i.e. part_z = G_z Phi_z^T
+            const double* Phi = c->d_Phi + t.phi_off;
+            const double* G = c->d_G + t.col0;
+            const int nb = t.b1 - t.b0;
+            const int bpc = (nb + c->nsplit - 1) / c->nsplit;
+            const int64_t kchunk = (int64_t)bpc * kBatch;
+            const int nfull = nb / bpc, rem = nb - nfull * bpc;
+            const double one = 1.0, zero = 0.0;
+            rocblas_status st = rocblas_status_success;
+            if (nfull > 0)
+                st = rocblas_dgemm_strided_batched(c->blas, rocblas_operation_transpose, rocblas_operation_none,
+                                                   (rocblas_int)t.nB, (rocblas_int)nbf, (rocblas_int)kchunk, &one, Phi,
+                                                   (rocblas_int)t.ncols, kchunk, G, (rocblas_int)ld, kchunk, &zero,
+                                                   c->d_part, (rocblas_int)t.nB, stride, nfull);
+            if (st == rocblas_status_success && rem > 0)
+                st = rocblas_dgemm(c->blas, rocblas_operation_transpose, rocblas_operation_none, (rocblas_int)t.nB,
+                                   (rocblas_int)nbf, (rocblas_int)(rem * kBatch), &one, Phi + nfull * kchunk,
+                                   (rocblas_int)t.ncols, G + nfull * kchunk, (rocblas_int)ld, &zero,
+                                   c->d_part + nfull * stride, (rocblas_int)t.nB);
+            if (st != rocblas_status_success) {
+                set_err(c, "rocblas_dgemm (K) failed");
+                return SNK_E_DEVICE;
+            }
+            HIPCHECK(c, launch_reduce_scatter(c->d_part, nfull + (rem > 0), stride, nbf, t.nB, nullptr, cols, c->d_Kt,
+                                              nbf, s));
+        } else {
+            if (c->mixed)
+                HIPCHECK(c, launch_gemm_f32_dA(nbf, t.nB, t.ncols, c->d_G + t.col0, ld, c->d_Phi32 + t.phi_off,
+                                               t.ncols, true, c->d_part, t.nB, c->nsplit, stride, s));
+            else
+                HIPCHECK(c, launch_gemm_f64(nbf, t.nB, t.ncols, c->d_G + t.col0, ld, c->d_Phi + t.phi_off, t.ncols,
+                                            true, c->d_part, t.nB, c->nsplit, stride, s));
+            HIPCHECK(c, launch_reduce_scatter(c->d_part, c->nsplit, stride, nbf, t.nB, nullptr, cols, c->d_Kt, nbf, s));
+        }
+    }
     return SNK_OK;
 }
 
@@ -1272,46 +1473,9 @@ int snk_ctx_build(snk_ctx* c, const double* P, double* K_out, snk_stats* stats)
         HIPCHECK(c, launch_pair_pnorm(dP, nbf, c->d_ne_list, c->d_pa, c->d_pb, c->d_shell_l, c->d_shell_row,
                                       (int64_t)c->ne_list.size(), c->d_lp, s));
     for (const Group& g : c->groups) {
-        const int64_t ld = g.ncols;
         int rc = group_until_G(c, g, dP, timed, &gs);
         if (rc) return rc;
-        // Eq. usym_k: Kt[:, B_g] += G_g Phi_g^T, split over grid points
-        const int64_t stride = nbf * g.nB;
-        if (c->blas) {
-            // split over whole batches of points; column-major view of chunk z:
-            // part_z^T (nB x nbf) = Phi_z (nB x kchunk) G_z^T (kchunk x nbf), i.e. part_z = G_z Phi_z^T
-            const int nb = g.b1 - g.b0;
-            const int bpc = (nb + c->nsplit - 1) / c->nsplit;
-            const int64_t kchunk = (int64_t)bpc * kBatch;
-            const int nfull = nb / bpc, rem = nb - nfull * bpc;
-            const double one = 1.0, zero = 0.0;
-            rocblas_status st = rocblas_status_success;
-            if (nfull > 0)
-                st = rocblas_dgemm_strided_batched(c->blas, rocblas_operation_transpose, rocblas_operation_none,
-                                                   (rocblas_int)g.nB, (rocblas_int)nbf, (rocblas_int)kchunk, &one,
-                                                   c->d_Phi, (rocblas_int)ld, kchunk, c->d_G, (rocblas_int)ld, kchunk,
-                                                   &zero, c->d_part, (rocblas_int)g.nB, stride, nfull);
-            if (st == rocblas_status_success && rem > 0)
-                st = rocblas_dgemm(c->blas, rocblas_operation_transpose, rocblas_operation_none, (rocblas_int)g.nB,
-                                   (rocblas_int)nbf, (rocblas_int)(rem * kBatch), &one, c->d_Phi + nfull * kchunk,
-                                   (rocblas_int)ld, c->d_G + nfull * kchunk, (rocblas_int)ld, &zero,
-                                   c->d_part + nfull * stride, (rocblas_int)g.nB);
-            if (st != rocblas_status_success) {
-                set_err(c, "rocblas_dgemm (K) failed");
-                return SNK_E_DEVICE;
-            }
-            HIPCHECK(c, launch_reduce_scatter(c->d_part, nfull + (rem > 0), stride, nbf, g.nB, nullptr,
-                                              g.all_functions ? nullptr : g.d_coll_fn, c->d_Kt, nbf, s));
-        } else {
-            if (c->mixed)
-                HIPCHECK(c, launch_gemm_f32_dA(nbf, g.nB, g.ncols, c->d_G, ld, c->d_Phi32, ld, true, c->d_part,
-                                               g.nB, c->nsplit, stride, s));
-            else
-                HIPCHECK(c, launch_gemm_f64(nbf, g.nB, g.ncols, c->d_G, ld, c->d_Phi, ld, true, c->d_part, g.nB,
-                                            c->nsplit, stride, s));
-            HIPCHECK(c, launch_reduce_scatter(c->d_part, c->nsplit, stride, nbf, g.nB, nullptr,
-                                              g.all_functions ? nullptr : g.d_coll_fn, c->d_Kt, nbf, s));
-        }
+        if ((rc = group_K(c, g))) return rc;
         if (timed) {
             HIPCHECK(c, hipEventRecord(c->ev[4], s));
             HIPCHECK(c, hipEventSynchronize(c->ev[4]));
@@ -1432,15 +1596,65 @@ int snk_ctx_debug_intermediates(snk_ctx* c, const double* P, double* Phi, double
     int rc = group_until_G(c, g, c->d_P, false, &gs);
     if (rc) return rc;
     const size_t n = (size_t)nbf * g.ncols * sizeof(double);
-    if (Phi) HIPCHECK(c, hipMemcpyAsync(Phi, c->d_Phi, (size_t)g.nB * g.ncols * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    std::vector<double> phig(Phi ? (size_t)g.phi_elems : 0);
+    if (!phig.empty())
+        HIPCHECK(c, hipMemcpyAsync(phig.data(), c->d_Phi, phig.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     if (F) HIPCHECK(c, hipMemcpyAsync(F, c->d_F, n, hipMemcpyDeviceToHost, c->stream));
     if (G) HIPCHECK(c, hipMemcpyAsync(G, c->d_G, n, hipMemcpyDeviceToHost, c->stream));
     HIPCHECK(c, hipStreamSynchronize(c->stream));
+    if (Phi) {
+        // elements of functions outside a tile's B_t are zero
+        std::fill(Phi, Phi + (size_t)nbf * g.ncols, 0.0);
+        for (const Tile& t : g.tiles)
+            for (int32_t r = 0; r < t.nB; ++r) {
+                const auto src = phig.begin() + t.phi_off + (int64_t)r * t.ncols;
+                std::copy(src, src + t.ncols, Phi + (size_t)t.coll_fn[r] * g.ncols + t.col0);
+            }
+    }
     if (ncols_out) *ncols_out = g.ncols;
     return SNK_OK;
 }
 
 int64_t snk_ctx_nblock_pairs(const snk_ctx* c) { return c ? (int64_t)c->ne_list.size() : 0; }
+
+int snk_ctx_ngroups(const snk_ctx* c) { return c ? (int)c->groups.size() : 0; }
+
+int snk_ctx_ntiles(const snk_ctx* c)
+{
+    int n = 0;
+    if (c)
+        for (const Group& g : c->groups) n += (int)g.tiles.size();
+    return n;
+}
+
+int snk_ctx_tile_info(const snk_ctx* c, int32_t* group, int32_t* b0, int32_t* b1, int32_t* nB)
+{
+    if (!c) return arg_error(nullptr, "context is NULL");
+    size_t k = 0;
+    for (size_t gi = 0; gi < c->groups.size(); ++gi)
+        for (const Tile& t : c->groups[gi].tiles) {
+            if (group) group[k] = (int32_t)gi;
+            if (b0) b0[k] = t.b0;
+            if (b1) b1[k] = t.b1;
+            if (nB) nB[k] = t.nB;
+            ++k;
+        }
+    return SNK_OK;
+}
+
+int snk_ctx_tile_functions(const snk_ctx* c, int32_t tile, int32_t* fn)
+{
+    if (!c || !fn) return arg_error(nullptr, "NULL argument");
+    int32_t k = 0;
+    if (tile >= 0)
+        for (const Group& g : c->groups)
+            for (const Tile& t : g.tiles)
+                if (k++ == tile) {
+                    std::copy(t.coll_fn.begin(), t.coll_fn.end(), fn);
+                    return SNK_OK;
+                }
+    return arg_error(nullptr, "tile index out of range");
+}
 
 int snk_ctx_block_data(snk_ctx* c, const double* P, float* features, double* block_energy, int32_t* pair_shells)
 {

@@ -254,13 +254,19 @@ hipError_t launch_convert_f32(const double* in, int64_t n, float* out, hipStream
 hipError_t launch_reduce_scatter(const double* part, int nsplit, int64_t stride, int64_t M, int64_t N,
                                  const int32_t* rows, const int32_t* cols, double* Kt, int64_t nbf, hipStream_t s);
 hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t s);
+hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t s);
+// p[r * ld + c] = v for r < rows, c < cols
+hipError_t launch_fill2d(double* p, int64_t rows, int64_t cols, int64_t ld, double v, hipStream_t s);
+hipError_t launch_fill2d(float* p, int64_t rows, int64_t cols, int64_t ld, float v, hipStream_t s);
 hipError_t launch_mfma_probe(double* out_dev, hipStream_t s);
 // K = (Kt + Kt^T)/2 and ex = -1/2 tr(P K) (two-stage deterministic reduction, partial buffer of nblk doubles)
 hipError_t launch_finish(const double* Kt, const double* P, double* K, int64_t nbf, double* partial, int nblk,
                          double* ex, hipStream_t s);
 hipError_t launch_boys_eval(const double* T, int64_t n, int mmax, double* F, const double* tab, hipStream_t s);
-// gather P_g[m][n] = P[rows[m]][cols[n]] (NULL rows/cols: identity)
+// gather P_g[m][n] = P[rows[m]][cols[n]] (NULL rows/cols: identity), stored FP64 or rounded to FP32
 hipError_t launch_gather(const double* P, int64_t nbf, const int32_t* rows, int64_t M, const int32_t* cols,
                          int64_t N, double* out, hipStream_t s);
+hipError_t launch_gather(const double* P, int64_t nbf, const int32_t* rows, int64_t M, const int32_t* cols,
+                         int64_t N, float* out, hipStream_t s);
 
 }  // namespace snk

@@ -102,6 +102,14 @@ def lib():
             L.snk_ctx_nbf.restype = ctypes.c_int
             L.snk_ctx_nbatches.argtypes = [ctypes.c_void_p]
             L.snk_ctx_nbatches.restype = ctypes.c_int
+            L.snk_ctx_ngroups.argtypes = [ctypes.c_void_p]
+            L.snk_ctx_ngroups.restype = ctypes.c_int
+            L.snk_ctx_ntiles.argtypes = [ctypes.c_void_p]
+            L.snk_ctx_ntiles.restype = ctypes.c_int
+            L.snk_ctx_tile_info.argtypes = [ctypes.c_void_p] * 5
+            L.snk_ctx_tile_info.restype = ctypes.c_int
+            L.snk_ctx_tile_functions.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]
+            L.snk_ctx_tile_functions.restype = ctypes.c_int
             L.snk_status_string.argtypes = [ctypes.c_int]
             L.snk_status_string.restype = ctypes.c_char_p
             L.snk_last_error.argtypes = [ctypes.c_void_p]
@@ -258,6 +266,23 @@ class Context:
         _check(lib().snk_ctx_build(self.handle, ctypes.c_void_p(P_ptr), ctypes.c_void_p(K_ptr),
                                    ctypes.byref(st) if stats else None), self.handle)
         return st.as_dict() if stats else None
+
+    @property
+    def ngroups(self) -> int:
+        return int(lib().snk_ctx_ngroups(self.handle))
+
+    def tiles(self):
+        """Tiles: list of (group, b0, b1, functions B_t) with batches [b0, b1) in batch order."""
+        n = lib().snk_ctx_ntiles(self.handle)
+        gr, b0, b1, nB = (np.zeros(n, np.int32) for _ in range(4))
+        _check(lib().snk_ctx_tile_info(self.handle, gr.ctypes.data, b0.ctypes.data, b1.ctypes.data, nB.ctypes.data),
+               self.handle)
+        out = []
+        for k in range(n):
+            fn = np.zeros(max(1, int(nB[k])), np.int32)
+            _check(lib().snk_ctx_tile_functions(self.handle, k, fn.ctypes.data), self.handle)
+            out.append((int(gr[k]), int(b0[k]), int(b1[k]), fn[:int(nB[k])].copy()))
+        return out
 
     def point_order(self) -> np.ndarray:
         """Input point index of every batch column (-1 = padding slot)."""
