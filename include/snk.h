@@ -110,6 +110,9 @@ typedef struct snk_stats {
     int32_t n_groups;
     int64_t prim_pair_points[6]; /* primitive-pair x grid-point units evaluated per class */
     double t_afg_class_ms[6];    /* GPU time of the A.F kernel of each class */
+    double tile_functions;       /* |B_t|, collocated functions per tile (mean weighted by columns) */
+    double tile_frows;           /* rows of F computed per tile (N_b, or |L_t| with eps_basis > 0) */
+    double tile_grows;           /* rows of G in the K GEMM per tile (N_b, or |M_t| with screening and eps_basis > 0) */
 } snk_stats;
 
 typedef struct snk_mlp snk_mlp;

@@ -223,6 +223,52 @@ __global__ __launch_bounds__(256) void gather_kernel(const double* __restrict__ 
     out[idx] = (TO)P[r * nbf + c];
 }
 
+// out[rows[m] * ld + c] = in[m * ncols + c]
+template <typename T>
+__global__ __launch_bounds__(256) void scatter_rows_kernel(const T* __restrict__ in, int64_t M, int64_t ncols,
+                                                           const int32_t* __restrict__ rows, T* __restrict__ out,
+                                                           int64_t ld)
+{
+    const int64_t n = M * ncols;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t m = i / ncols;
+        out[(int64_t)rows[m] * ld + (i - m * ncols)] = in[i];
+    }
+}
+
+// One wave per row: mx[r] = max_c |Phi[r * ncols + c]|
+template <typename T>
+__global__ __launch_bounds__(256) void row_absmax_kernel(const T* __restrict__ Phi, int64_t nrow, int64_t ncols,
+                                                         double* __restrict__ mx)
+{
+    const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (r >= nrow) return;
+    const T* row = Phi + r * ncols;
+    double m = 0.0;
+    for (int64_t c = lane; c < ncols; c += 64) m = fmax(m, fabs((double)row[c]));
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+    if (lane == 0) mx[r] = m;
+}
+
+// One wave per function lam: Ft = sum_k |P[lam][fn[k]]| mx[k] bounds |F_lam,i| on every
+// point of the tile (Eq. fmat with |Phi_nu,i| <= mx); flag[shell_of[lam]] = 1 when Ft >= eps.
+__global__ __launch_bounds__(256) void ftilde_flag_kernel(const double* __restrict__ P, int64_t nbf,
+                                                          const int32_t* __restrict__ fn, int32_t nB,
+                                                          const double* __restrict__ mx, double eps,
+                                                          const int32_t* __restrict__ shell_of,
+                                                          int32_t* __restrict__ flag)
+{
+    const int64_t lam = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (lam >= nbf) return;
+    const double* row = P + lam * nbf;
+    double t = 0.0;
+    for (int k = lane; k < nB; k += 64) t = fma(fabs(row[fn[k]]), mx[k], t);
+    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
+    if (lane == 0 && t >= eps) flag[shell_of[lam]] = 1;
+}
+
 // One wave: A[i][k] = (k == 0) + i (k == 1), B[k][j] = 100 j (k == 0) + (k == 1), so that
 // D[i][j] = 100 j + i; every lane writes its four accumulator elements.
 __global__ void mfma_probe_kernel(double* __restrict__ out)
@@ -348,6 +394,15 @@ hipError_t launch_fill2d(float* p, int64_t rows, int64_t cols, int64_t ld, float
     return launch_fill2d_t<float>(p, rows, cols, ld, v, s);
 }
 
+hipError_t launch_fill(int32_t* p, int64_t n, int32_t v, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL((fill_kernel<int32_t>), dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
@@ -373,6 +428,55 @@ static hipError_t launch_gather_t(const double* P, int64_t nbf, const int32_t* r
     const int64_t n = M * N;
     hipLaunchKernelGGL((gather_kernel<TO>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, P, nbf, rows, M, cols,
                        N, out);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_scatter_rows_t(const T* in, int64_t M, int64_t ncols, const int32_t* rows, T* out, int64_t ld,
+                                       hipStream_t s)
+{
+    if (M <= 0 || ncols <= 0) return hipSuccess;
+    int64_t blocks = (M * ncols + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL((scatter_rows_kernel<T>), dim3((unsigned)blocks), dim3(256), 0, s, in, M, ncols, rows, out, ld);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_rows(const double* in, int64_t M, int64_t ncols, const int32_t* rows, double* out, int64_t ld,
+                               hipStream_t s)
+{
+    return launch_scatter_rows_t<double>(in, M, ncols, rows, out, ld, s);
+}
+
+hipError_t launch_scatter_rows(const float* in, int64_t M, int64_t ncols, const int32_t* rows, float* out, int64_t ld,
+                               hipStream_t s)
+{
+    return launch_scatter_rows_t<float>(in, M, ncols, rows, out, ld, s);
+}
+
+hipError_t launch_row_absmax(const double* Phi, int64_t nrow, int64_t ncols, double* mx, hipStream_t s)
+{
+    if (nrow <= 0) return hipSuccess;
+    hipLaunchKernelGGL((row_absmax_kernel<double>), dim3((unsigned)((nrow + 3) / 4)), dim3(256), 0, s, Phi, nrow, ncols,
+                       mx);
+    return hipGetLastError();
+}
+
+hipError_t launch_row_absmax(const float* Phi, int64_t nrow, int64_t ncols, double* mx, hipStream_t s)
+{
+    if (nrow <= 0) return hipSuccess;
+    hipLaunchKernelGGL((row_absmax_kernel<float>), dim3((unsigned)((nrow + 3) / 4)), dim3(256), 0, s, Phi, nrow, ncols,
+                       mx);
+    return hipGetLastError();
+}
+
+hipError_t launch_ftilde_flag(const double* P, int64_t nbf, const int32_t* fn, int32_t nB, const double* mx, double eps,
+                              const int32_t* shell_of, int32_t* flag, hipStream_t s)
+{
+    if (nbf <= 0) return hipSuccess;
+    if (!P || !fn || !mx || !shell_of || !flag) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(ftilde_flag_kernel, dim3((unsigned)((nbf + 3) / 4)), dim3(256), 0, s, P, nbf, fn, nB, mx, eps,
+                       shell_of, flag);
     return hipGetLastError();
 }
 

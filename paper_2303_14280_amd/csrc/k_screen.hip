@@ -466,6 +466,12 @@ __global__ __launch_bounds__(256) void screen_kernel(ScreenArgs a)
                     if (la == lb && aa < b) continue;
                     if (!keep(aa, b)) continue;
                     mask |= 1 << k;
+                    if (!WRITE && a.shell_flag) {
+                        // both shells receive G contributions (idempotent flag stores)
+                        int32_t* f = a.shell_flag + (int64_t)(batch / a.tile_batches) * a.nshell;
+                        f[aa] = 1;
+                        f[b] = 1;
+                    }
                 }
                 if (mask) {
                     atomicAdd(&tilecnt[t], 1);
@@ -648,6 +654,50 @@ hipError_t launch_screen(bool write, const ScreenArgs& a, hipStream_t s)
         hipLaunchKernelGGL((screen_kernel<true>), dim3(a.nbatch), dim3(256), shm, s, a);
     else
         hipLaunchKernelGGL((screen_kernel<false>), dim3(a.nbatch), dim3(256), shm, s, a);
+    return hipGetLastError();
+}
+
+// One workgroup per tile: each thread takes a contiguous run of shells, counts the functions
+// of its flagged shells, and after a workgroup exclusive scan writes their row indices.
+__global__ __launch_bounds__(256) void tile_rows_kernel(const int32_t* __restrict__ flag, int32_t nshell,
+                                                        const int32_t* __restrict__ shell_l,
+                                                        const int32_t* __restrict__ shell_row, int32_t nbf,
+                                                        int32_t* __restrict__ rows, int32_t* __restrict__ count)
+{
+    __shared__ int32_t part[256];
+    const int tile = blockIdx.x, tid = threadIdx.x;
+    const int32_t* f = flag + (int64_t)tile * nshell;
+    const int per = (nshell + 255) / 256;
+    const int s0 = min(nshell, tid * per), s1 = min(nshell, s0 + per);
+    int n = 0;
+    for (int sh = s0; sh < s1; ++sh)
+        if (f[sh]) n += (shell_l[sh] + 1) * (shell_l[sh] + 2) / 2;
+    part[tid] = n;
+    __syncthreads();
+    // Hillis-Steele inclusive scan over the 256 partial counts
+    for (int o = 1; o < 256; o <<= 1) {
+        const int v = tid >= o ? part[tid - o] : 0;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    int r = part[tid] - n;
+    int32_t* out = rows + (int64_t)tile * nbf;
+    for (int sh = s0; sh < s1; ++sh) {
+        if (!f[sh]) continue;
+        const int nf = (shell_l[sh] + 1) * (shell_l[sh] + 2) / 2;
+        for (int k = 0; k < nf; ++k) out[r++] = shell_row[sh] + k;
+    }
+    if (tid == 255) count[tile] = part[255];
+}
+
+hipError_t launch_tile_rows(const int32_t* shell_flag, int32_t ntile, int32_t nshell, const int32_t* shell_l,
+                            const int32_t* shell_row, int32_t nbf, int32_t* rows, int32_t* count, hipStream_t s)
+{
+    if (ntile <= 0) return hipSuccess;
+    if (!shell_flag || !shell_l || !shell_row || !rows || !count) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(tile_rows_kernel, dim3(ntile), dim3(256), 0, s, shell_flag, nshell, shell_l, shell_row, nbf,
+                       rows, count);
     return hipGetLastError();
 }
 

@@ -105,7 +105,26 @@ struct snk_ctx {
     int64_t max_tile_cols = 0;
     int64_t max_phi = 0;                // Phi buffer elements (largest group)
     int32_t max_nB = 0;                 // largest tile function set
-    int nsplit = 1;
+    int32_t tile_batches = 1;           // batches per tile (the last tile of a group may be shorter)
+    int32_t max_group_tiles = 0;
+    // K GEMM rows restricted per tile to the functions of kept blocks (screen + basis screening)
+    bool row_restrict = false;
+    int32_t* d_shell_flag = nullptr;    // [max_group_tiles][nshell]
+    int32_t* d_trows = nullptr;         // [max_group_tiles][nbf]
+    int32_t* d_tcount = nullptr;        // [max_group_tiles]
+    double* d_Gc = nullptr;             // [nbf][max_tile_cols]: gathered G rows, or compact F rows, of one tile
+    std::vector<int32_t> tile_rows;     // rows per tile of the current group
+    // F GEMM rows restricted per tile to the functions whose bound |F| >= eps_basis
+    bool frow_restrict = false;
+    int32_t* d_fflag = nullptr;         // [max_group_tiles][nshell]
+    int32_t* d_frows = nullptr;         // [max_group_tiles][nbf]
+    int32_t* d_fcount = nullptr;        // [max_group_tiles]
+    double* d_phimax = nullptr;         // [max_nB]
+    int32_t* d_fn_shell = nullptr;      // [nbf] shell of each function
+    std::vector<int32_t> tile_frows;    // F rows per tile of the current group
+    double acc_fn = 0, acc_frows = 0, acc_grows = 0, acc_cols = 0;   // column-weighted tile sizes
+    int nsplit = 1;                     // K GEMM split over points for full-width tiles
+    int64_t part_elems = 0;             // size of the split partial-sum buffer
     bool mixed = false;                 // SNK_MIXED + SNK_FP32_GEMM: FP32 Phi, P and F; FP32 matrix-core GEMMs
     rocblas_handle blas = nullptr;      // SNK_ROCBLAS (FP64 builds)
     float *d_Phi32 = nullptr, *d_F32 = nullptr, *d_P32 = nullptr, *d_Pg32 = nullptr;
@@ -623,6 +642,7 @@ int build_groups(snk_ctx* c)
     // with basis screening, groups are whole numbers of spatially ordered tiles
     if (bscreen && per_group > kBasisTileBatches) per_group -= per_group % kBasisTileBatches;
     const int64_t tile_batches = bscreen ? std::min<int64_t>(per_group, kBasisTileBatches) : per_group;
+    c->tile_batches = (int32_t)std::max<int64_t>(1, tile_batches);
     for (int b0 = 0; b0 < c->nbatch; b0 += (int)per_group) {
         Group gr;
         gr.b0 = b0;
@@ -671,7 +691,9 @@ int build_groups(snk_ctx* c)
     c->max_tile_cols = 0;
     c->max_phi = 0;
     c->max_nB = 0;
+    c->max_group_tiles = 0;
     for (auto& gr : c->groups) {
+        c->max_group_tiles = std::max(c->max_group_tiles, (int32_t)gr.tiles.size());
         c->max_cols = std::max(c->max_cols, gr.ncols);
         c->max_phi = std::max(c->max_phi, gr.phi_elems);
         for (auto& t : gr.tiles) {
@@ -788,8 +810,6 @@ int setup_screening(snk_ctx* c)
         if ((rc = upload(c, &c->d_diag_np[l], np))) return rc;
     }
     int rc;
-    if ((rc = upload(c, &c->d_shell_l, c->sl))) return rc;
-    if ((rc = upload(c, &c->d_shell_row, c->sfn))) return rc;
     int32_t mb = 0;
     for (const auto& g : c->groups) mb = std::max(mb, g.b1 - g.b0);
     c->max_group_batches = mb;
@@ -861,6 +881,15 @@ void free_ctx(snk_ctx* c)
     (void)hipFree(c->d_F32);
     (void)hipFree(c->d_P32);
     (void)hipFree(c->d_Pg32);
+    (void)hipFree(c->d_shell_flag);
+    (void)hipFree(c->d_trows);
+    (void)hipFree(c->d_tcount);
+    (void)hipFree(c->d_Gc);
+    (void)hipFree(c->d_fflag);
+    (void)hipFree(c->d_frows);
+    (void)hipFree(c->d_fcount);
+    (void)hipFree(c->d_phimax);
+    (void)hipFree(c->d_fn_shell);
     (void)hipFree(c->d_Phi);
     (void)hipFree(c->d_F);
     (void)hipFree(c->d_G);
@@ -1069,6 +1098,9 @@ int snk_ctx_create(const snk_basis* basis, const snk_grid* grid, const double* w
     CREATE_CHECK(build_grid(c, grid, weights));
     CREATE_CHECK(build_groups(c));
     CREATE_CHECK(upload(c, &c->d_boys, boys_table()));
+    // angular momentum and first function of every shell (screens and tile row lists)
+    CREATE_CHECK(upload(c, &c->d_shell_l, c->sl));
+    CREATE_CHECK(upload(c, &c->d_shell_row, c->sfn));
 
     // workspace
     const int64_t nbf = c->nbf;
@@ -1082,7 +1114,7 @@ int snk_ctx_create(const snk_basis* basis, const snk_grid* grid, const double* w
         CREATE_CHECK(dalloc(c, &c->d_Phi32, (size_t)std::max<int64_t>(1, c->max_phi)));
         CREATE_CHECK(dalloc(c, &c->d_F32, (size_t)nbf * c->max_cols));
         CREATE_CHECK(dalloc(c, &c->d_P32, (size_t)nbf * nbf));
-        bool gather = false;
+        bool gather = o.eps_basis > 0.0;
         for (const auto& g : c->groups)
             for (const auto& t : g.tiles) gather |= !t.all_functions;
         if (gather) CREATE_CHECK(dalloc(c, &c->d_Pg32, (size_t)nbf * c->max_nB));
@@ -1091,7 +1123,8 @@ int snk_ctx_create(const snk_basis* basis, const snk_grid* grid, const double* w
         CREATE_CHECK(dalloc(c, &c->d_F, (size_t)nbf * c->max_cols));
     }
     CREATE_CHECK(dalloc(c, &c->d_G, (size_t)nbf * c->max_cols));
-    CREATE_CHECK(dalloc(c, &c->d_part, (size_t)c->nsplit * nbf * c->max_nB));
+    c->part_elems = std::max<int64_t>(1, (int64_t)c->nsplit * nbf * c->max_nB);
+    CREATE_CHECK(dalloc(c, &c->d_part, (size_t)c->part_elems));
     CREATE_CHECK(dalloc(c, &c->d_Pg, (size_t)nbf * c->max_nB));
     CREATE_CHECK(dalloc(c, &c->d_Kt, (size_t)nbf * nbf));
     CREATE_CHECK(dalloc(c, &c->d_P, (size_t)nbf * nbf));
@@ -1099,6 +1132,24 @@ int snk_ctx_create(const snk_basis* basis, const snk_grid* grid, const double* w
     CREATE_CHECK(dalloc(c, &c->d_partial, (size_t)c->nfinish));
     CREATE_CHECK(dalloc(c, &c->d_ex, 1));
     if (o.screen != SNK_SCREEN_NONE) CREATE_CHECK(setup_screening(c));
+    c->row_restrict = o.screen != SNK_SCREEN_NONE && o.eps_basis > 0.0 && !c->groups.empty();
+    c->frow_restrict = o.eps_basis > 0.0 && !c->groups.empty();
+    if (c->row_restrict) {
+        CREATE_CHECK(dalloc(c, &c->d_shell_flag, (size_t)c->max_group_tiles * c->nshell));
+        CREATE_CHECK(dalloc(c, &c->d_trows, (size_t)c->max_group_tiles * nbf));
+        CREATE_CHECK(dalloc(c, &c->d_tcount, (size_t)c->max_group_tiles));
+    }
+    if (c->frow_restrict) {
+        CREATE_CHECK(dalloc(c, &c->d_fflag, (size_t)c->max_group_tiles * c->nshell));
+        CREATE_CHECK(dalloc(c, &c->d_frows, (size_t)c->max_group_tiles * nbf));
+        CREATE_CHECK(dalloc(c, &c->d_fcount, (size_t)c->max_group_tiles));
+        CREATE_CHECK(dalloc(c, &c->d_phimax, (size_t)std::max<int32_t>(1, c->max_nB)));
+        std::vector<int32_t> fs(nbf);
+        for (int sh = 0; sh < c->nshell; ++sh)
+            for (int k = 0; k < ncart(c->sl[sh]); ++k) fs[c->sfn[sh] + k] = sh;
+        CREATE_CHECK(upload(c, &c->d_fn_shell, fs));
+    }
+    if (c->row_restrict || c->frow_restrict) CREATE_CHECK(dalloc(c, &c->d_Gc, (size_t)nbf * c->max_tile_cols));
     if ((o.flags & SNK_ROCBLAS) && !c->mixed && c->max_cols <= INT32_MAX && (int64_t)c->nbf <= INT32_MAX) {
         if (rocblas_create_handle(&c->blas) != rocblas_status_success ||
             rocblas_set_stream(c->blas, c->stream) != rocblas_status_success ||
@@ -1156,12 +1207,67 @@ int group_F(snk_ctx* c, const Group& g, const double* dP, bool timed)
                                          c->d_Phi + t.phi_off, t.ncols, s));
     }
     if (timed) HIPCHECK(c, hipEventRecord(c->ev[1], s));
+    const int ntile = (int)g.tiles.size();
+    if (c->frow_restrict) {
+        // rows L_t of F that can reach eps_basis on the tile: functions whose bound
+        // sum_{nu in B_t} |P_lam,nu| max_i |Phi_nu,i| >= eps_basis, by whole shells
+        HIPCHECK(c, launch_fill(c->d_fflag, (int64_t)ntile * c->nshell, 0, s));
+        for (int ti = 0; ti < ntile; ++ti) {
+            const Tile& t = g.tiles[ti];
+            if (t.nB == 0) continue;
+            if (c->mixed) HIPCHECK(c, launch_row_absmax(c->d_Phi32 + t.phi_off, t.nB, t.ncols, c->d_phimax, s));
+            else HIPCHECK(c, launch_row_absmax(c->d_Phi + t.phi_off, t.nB, t.ncols, c->d_phimax, s));
+            HIPCHECK(c, launch_ftilde_flag(dP, nbf, t.d_coll_fn, t.nB, c->d_phimax, c->opts.eps_basis, c->d_fn_shell,
+                                           c->d_fflag + (int64_t)ti * c->nshell, s));
+        }
+        HIPCHECK(c, launch_tile_rows(c->d_fflag, ntile, c->nshell, c->d_shell_l, c->d_shell_row, c->nbf, c->d_frows,
+                                     c->d_fcount, s));
+        c->tile_frows.assign(ntile, 0);
+        HIPCHECK(c, hipMemcpyAsync(c->tile_frows.data(), c->d_fcount, ntile * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIPCHECK(c, hipStreamSynchronize(s));
+    }
     // Eq. fmat per tile: F[:, tile columns] = P[:, B_t] Phi_t
-    for (const Tile& t : g.tiles) {
-        if (t.nB == 0) {
-            // no function reaches the tile's points
+    for (int ti = 0; ti < ntile; ++ti) {
+        const Tile& t = g.tiles[ti];
+        const int64_t L = c->frow_restrict ? c->tile_frows[ti] : nbf;
+        c->acc_fn += (double)t.nB * t.ncols;
+        c->acc_frows += (double)L * t.ncols;
+        c->acc_cols += (double)t.ncols;
+        if (t.nB == 0 || L == 0) {
+            // no function reaches the tile's points, or no row of F does
             if (c->mixed) HIPCHECK(c, launch_fill2d(c->d_F32 + t.col0, nbf, t.ncols, ld, 0.0f, s));
             else HIPCHECK(c, launch_fill2d(c->d_F + t.col0, nbf, t.ncols, ld, 0.0, s));
+            continue;
+        }
+        if (c->frow_restrict && L < nbf) {
+            // F_c = P[L_t, B_t] Phi_t, then rows L_t of the tile's columns; all other rows are 0
+            const int32_t* rows = c->d_frows + (int64_t)ti * nbf;
+            if (c->mixed) {
+                float* Fc = reinterpret_cast<float*>(c->d_Gc);
+                HIPCHECK(c, launch_gather(dP, nbf, rows, L, t.d_coll_fn, t.nB, c->d_Pg32, s));
+                HIPCHECK(c, launch_gemm_f32(L, t.ncols, t.nB, c->d_Pg32, t.nB, c->d_Phi32 + t.phi_off, t.ncols, false,
+                                            Fc, t.ncols, 1, 0, s));
+                HIPCHECK(c, launch_fill2d(c->d_F32 + t.col0, nbf, t.ncols, ld, 0.0f, s));
+                HIPCHECK(c, launch_scatter_rows(Fc, L, t.ncols, rows, c->d_F32 + t.col0, ld, s));
+                continue;
+            }
+            HIPCHECK(c, launch_gather(dP, nbf, rows, L, t.d_coll_fn, t.nB, c->d_Pg, s));
+            if (c->blas) {
+                // column-major view: F_c^T (ncols_t x L) = Phi_t^T (ncols_t x nB) P_c^T (nB x L)
+                const double one = 1.0, zero = 0.0;
+                if (rocblas_dgemm(c->blas, rocblas_operation_none, rocblas_operation_none, (rocblas_int)t.ncols,
+                                  (rocblas_int)L, (rocblas_int)t.nB, &one, c->d_Phi + t.phi_off, (rocblas_int)t.ncols,
+                                  c->d_Pg, (rocblas_int)t.nB, &zero, c->d_Gc, (rocblas_int)t.ncols) !=
+                    rocblas_status_success) {
+                    set_err(c, "rocblas_dgemm (F) failed");
+                    return SNK_E_DEVICE;
+                }
+            } else {
+                HIPCHECK(c, launch_gemm_f64(L, t.ncols, t.nB, c->d_Pg, t.nB, c->d_Phi + t.phi_off, t.ncols, false,
+                                            c->d_Gc, t.ncols, 1, 0, s));
+            }
+            HIPCHECK(c, launch_fill2d(c->d_F + t.col0, nbf, t.ncols, ld, 0.0, s));
+            HIPCHECK(c, launch_scatter_rows(c->d_Gc, L, t.ncols, rows, c->d_F + t.col0, ld, s));
             continue;
         }
         if (c->mixed) {
@@ -1210,45 +1316,68 @@ int group_K(snk_ctx* c, const Group& g)
     hipStream_t s = c->stream;
     const int64_t nbf = c->nbf;
     const int64_t ld = g.ncols;
-    for (const Tile& t : g.tiles) {
+    const bool restrict_rows = c->row_restrict && c->tile_rows.size() == g.tiles.size();
+    for (size_t ti = 0; ti < g.tiles.size(); ++ti) {
+        const Tile& t = g.tiles[ti];
         if (t.nB == 0) continue;   // nothing collocated: G Phi_t^T is empty
-        const int64_t stride = nbf * t.nB;
+        // rows of G the tile's kept blocks touch (all others are zero on the tile's columns)
+        int64_t M = nbf;
+        const double* Gt = c->d_G + t.col0;
+        int64_t ldg = ld;
+        const int32_t* rows = nullptr;
+        if (restrict_rows) {
+            M = c->tile_rows[ti];
+            c->acc_grows += (double)M * t.ncols;
+            if (M == 0) continue;
+            rows = c->d_trows + (int64_t)ti * nbf;
+            HIPCHECK(c, launch_gather(Gt, ld, rows, M, nullptr, t.ncols, c->d_Gc, s));
+            Gt = c->d_Gc;
+            ldg = t.ncols;
+        }
+        const int64_t stride = M * t.nB;
         const int32_t* cols = t.all_functions ? nullptr : t.d_coll_fn;
+        // split over grid points so that the M x nB product fills the device (about 2048
+        // 64 x 64 output tiles in all), within the partial-sum buffer and whole batches
+        const int64_t otiles = ((M + 63) / 64) * ((t.nB + 63) / 64);
+        int64_t ns = std::max<int64_t>(c->nsplit, (2048 + otiles - 1) / otiles);
+        ns = std::min<int64_t>(ns, c->part_elems / std::max<int64_t>(1, stride));
+        ns = std::max<int64_t>(1, std::min<int64_t>(ns, std::min<int64_t>(256, t.b1 - t.b0)));
+        const int nsplit = (int)ns;
         if (c->blas) {
             // split over whole batches of points; column-major view of chunk z:
-            // part_z^T (nB x nbf) = Phi_z (nB x kchunk) G_z^T (kchunk x nbf), i.e. part_z = G_z Phi_z^T
+            // part_z^T (nB x M) = Phi_z (nB x kchunk) G_z^T (kchunk x M), i.e. part_z = G_z Phi_z^T
             const double* Phi = c->d_Phi + t.phi_off;
-            const double* G = c->d_G + t.col0;
+            const double* G = Gt;
             const int nb = t.b1 - t.b0;
-            const int bpc = (nb + c->nsplit - 1) / c->nsplit;
+            const int bpc = (nb + nsplit - 1) / nsplit;
             const int64_t kchunk = (int64_t)bpc * kBatch;
             const int nfull = nb / bpc, rem = nb - nfull * bpc;
             const double one = 1.0, zero = 0.0;
             rocblas_status st = rocblas_status_success;
             if (nfull > 0)
                 st = rocblas_dgemm_strided_batched(c->blas, rocblas_operation_transpose, rocblas_operation_none,
-                                                   (rocblas_int)t.nB, (rocblas_int)nbf, (rocblas_int)kchunk, &one, Phi,
-                                                   (rocblas_int)t.ncols, kchunk, G, (rocblas_int)ld, kchunk, &zero,
+                                                   (rocblas_int)t.nB, (rocblas_int)M, (rocblas_int)kchunk, &one, Phi,
+                                                   (rocblas_int)t.ncols, kchunk, G, (rocblas_int)ldg, kchunk, &zero,
                                                    c->d_part, (rocblas_int)t.nB, stride, nfull);
             if (st == rocblas_status_success && rem > 0)
                 st = rocblas_dgemm(c->blas, rocblas_operation_transpose, rocblas_operation_none, (rocblas_int)t.nB,
-                                   (rocblas_int)nbf, (rocblas_int)(rem * kBatch), &one, Phi + nfull * kchunk,
-                                   (rocblas_int)t.ncols, G + nfull * kchunk, (rocblas_int)ld, &zero,
+                                   (rocblas_int)M, (rocblas_int)(rem * kBatch), &one, Phi + nfull * kchunk,
+                                   (rocblas_int)t.ncols, G + nfull * kchunk, (rocblas_int)ldg, &zero,
                                    c->d_part + nfull * stride, (rocblas_int)t.nB);
             if (st != rocblas_status_success) {
                 set_err(c, "rocblas_dgemm (K) failed");
                 return SNK_E_DEVICE;
             }
-            HIPCHECK(c, launch_reduce_scatter(c->d_part, nfull + (rem > 0), stride, nbf, t.nB, nullptr, cols, c->d_Kt,
+            HIPCHECK(c, launch_reduce_scatter(c->d_part, nfull + (rem > 0), stride, M, t.nB, rows, cols, c->d_Kt,
                                               nbf, s));
         } else {
             if (c->mixed)
-                HIPCHECK(c, launch_gemm_f32_dA(nbf, t.nB, t.ncols, c->d_G + t.col0, ld, c->d_Phi32 + t.phi_off,
-                                               t.ncols, true, c->d_part, t.nB, c->nsplit, stride, s));
+                HIPCHECK(c, launch_gemm_f32_dA(M, t.nB, t.ncols, Gt, ldg, c->d_Phi32 + t.phi_off, t.ncols, true,
+                                               c->d_part, t.nB, nsplit, stride, s));
             else
-                HIPCHECK(c, launch_gemm_f64(nbf, t.nB, t.ncols, c->d_G + t.col0, ld, c->d_Phi + t.phi_off, t.ncols,
-                                            true, c->d_part, t.nB, c->nsplit, stride, s));
-            HIPCHECK(c, launch_reduce_scatter(c->d_part, c->nsplit, stride, nbf, t.nB, nullptr, cols, c->d_Kt, nbf, s));
+                HIPCHECK(c, launch_gemm_f64(M, t.nB, t.ncols, Gt, ldg, c->d_Phi + t.phi_off, t.ncols, true, c->d_part,
+                                            t.nB, nsplit, stride, s));
+            HIPCHECK(c, launch_reduce_scatter(c->d_part, nsplit, stride, M, t.nB, rows, cols, c->d_Kt, nbf, s));
         }
     }
     return SNK_OK;
@@ -1345,9 +1474,22 @@ int group_until_G(snk_ctx* c, const Group& g, const double* dP, bool timed, Grou
         sa.skipped = c->d_skipped;
         sa.run_base = c->d_run_base;
         sa.bt_base = c->d_bt_base;
+        const int ntile = (int)g.tiles.size();
+        if (c->row_restrict) {
+            HIPCHECK(c, launch_fill(c->d_shell_flag, (int64_t)ntile * c->nshell, 0, s));
+            sa.shell_flag = c->d_shell_flag;
+            sa.tile_batches = c->tile_batches;
+        }
         HIPCHECK(c, launch_screen(false, sa, s));
         const int NL = c->nlist;
         HIPCHECK(c, launch_screen_scan(c->d_counts, nb, NL, c->d_run_base, c->d_bt_base, s));
+        if (c->row_restrict) {
+            HIPCHECK(c, launch_tile_rows(c->d_shell_flag, ntile, c->nshell, c->d_shell_l, c->d_shell_row, c->nbf,
+                                         c->d_trows, c->d_tcount, s));
+            c->tile_rows.assign(ntile, 0);
+            HIPCHECK(c, hipMemcpyAsync(c->tile_rows.data(), c->d_tcount, ntile * sizeof(int32_t),
+                                       hipMemcpyDeviceToHost, s));
+        }
         std::vector<int64_t> rb(NL * (size_t)(nb + 1)), bb(NL * (size_t)(nb + 1)), npair((size_t)nb * NL);
         std::vector<double> skipped(nb);
         HIPCHECK(c, hipMemcpyAsync(rb.data(), c->d_run_base, rb.size() * sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -1463,6 +1605,7 @@ int snk_ctx_build(snk_ctx* c, const double* P, double* K_out, snk_stats* stats)
         dK = c->d_K;
     }
     double tcol = 0, tf = 0, tafg = 0, tk = 0, tscr = 0;
+    c->acc_fn = c->acc_frows = c->acc_grows = c->acc_cols = 0.0;
     double tcls[6] = {0, 0, 0, 0, 0, 0};
     GroupStats gs;
     const bool timed = stats != nullptr;
@@ -1529,6 +1672,10 @@ int snk_ctx_build(snk_ctx* c, const double* P, double* K_out, snk_stats* stats)
         stats->skipped_bound = gs.skipped;
         stats->n_batches = c->nbatch;
         stats->n_groups = (int32_t)c->groups.size();
+        const double cols = std::max(1.0, c->acc_cols);
+        stats->tile_functions = c->acc_fn / cols;
+        stats->tile_frows = c->acc_frows / cols;
+        stats->tile_grows = c->row_restrict ? c->acc_grows / cols : (double)nbf;
     }
     return SNK_OK;
 }

@@ -125,6 +125,8 @@ struct ScreenArgs {
     const int32_t* thr;         // learned screen: [nbatch] first kept estimate bin
     const int32_t* thr2;        // learned screen: [nbatch] first FP64 estimate bin (bins thr..thr2-1 are FP32)
     int64_t npair_total;
+    int32_t* shell_flag;        // [tiles][nshell]: set to 1 for both shells of every kept block (or nullptr)
+    int32_t tile_batches;       // batches per tile (tile of batch b: b / tile_batches)
 };
 
 // Relative error allowed for in an FP32-evaluated block of the mixed build: the FP32 set's
@@ -207,6 +209,10 @@ hipError_t launch_diag_bound(int l, const double* px, const double* py, const do
                              const int32_t* drow, const int32_t* dpb, const int32_t* dnp, int32_t n, double* U,
                              float2* lun, int32_t nshell, int32_t nbatch, const double* tab, hipStream_t s);
 hipError_t launch_screen(bool write, const ScreenArgs& a, hipStream_t s);
+// Rows of G that the kept blocks of each tile can touch: for tile t, rows[t * nbf + m]
+// (m < count[t]) are the functions of the flagged shells in ascending order.
+hipError_t launch_tile_rows(const int32_t* shell_flag, int32_t ntile, int32_t nshell, const int32_t* shell_l,
+                            const int32_t* shell_row, int32_t nbf, int32_t* rows, int32_t* count, hipStream_t s);
 hipError_t launch_screen_est(const EstArgs& a, hipStream_t s);
 // lp[k] = log10 ||P_AB|| of the listed pairs plist[k] (pa/pb: shells of each pair index)
 hipError_t launch_pair_pnorm(const double* P, int64_t nbf, const int32_t* plist, const int32_t* pa,
@@ -255,6 +261,7 @@ hipError_t launch_reduce_scatter(const double* part, int nsplit, int64_t stride,
                                  const int32_t* rows, const int32_t* cols, double* Kt, int64_t nbf, hipStream_t s);
 hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t s);
 hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t s);
+hipError_t launch_fill(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 // p[r * ld + c] = v for r < rows, c < cols
 hipError_t launch_fill2d(double* p, int64_t rows, int64_t cols, int64_t ld, double v, hipStream_t s);
 hipError_t launch_fill2d(float* p, int64_t rows, int64_t cols, int64_t ld, float v, hipStream_t s);
@@ -263,6 +270,17 @@ hipError_t launch_mfma_probe(double* out_dev, hipStream_t s);
 hipError_t launch_finish(const double* Kt, const double* P, double* K, int64_t nbf, double* partial, int nblk,
                          double* ex, hipStream_t s);
 hipError_t launch_boys_eval(const double* T, int64_t n, int mmax, double* F, const double* tab, hipStream_t s);
+// out[rows[m] * ld + c] = in[m * ncols + c] for m < M, c < ncols
+hipError_t launch_scatter_rows(const double* in, int64_t M, int64_t ncols, const int32_t* rows, double* out, int64_t ld,
+                               hipStream_t s);
+hipError_t launch_scatter_rows(const float* in, int64_t M, int64_t ncols, const int32_t* rows, float* out, int64_t ld,
+                               hipStream_t s);
+// mx[r] = max_c |Phi[r * ncols + c]| for r < nrow
+hipError_t launch_row_absmax(const double* Phi, int64_t nrow, int64_t ncols, double* mx, hipStream_t s);
+hipError_t launch_row_absmax(const float* Phi, int64_t nrow, int64_t ncols, double* mx, hipStream_t s);
+// flag[shell_of[lam]] = 1 where sum_k |P[lam][fn[k]]| mx[k] >= eps (bound on |F_lam| over a tile)
+hipError_t launch_ftilde_flag(const double* P, int64_t nbf, const int32_t* fn, int32_t nB, const double* mx, double eps,
+                              const int32_t* shell_of, int32_t* flag, hipStream_t s);
 // gather P_g[m][n] = P[rows[m]][cols[n]] (NULL rows/cols: identity), stored FP64 or rounded to FP32
 hipError_t launch_gather(const double* P, int64_t nbf, const int32_t* rows, int64_t M, const int32_t* cols,
                          int64_t N, double* out, hipStream_t s);

@@ -46,7 +46,8 @@ class SnkStats(ctypes.Structure):
                 ("pair_points", ctypes.c_int64 * 6), ("pair_points_skipped", ctypes.c_int64),
                 ("pair_points_lowprec", ctypes.c_int64), ("skipped_bound", ctypes.c_double),
                 ("n_batches", ctypes.c_int32), ("n_groups", ctypes.c_int32),
-                ("prim_pair_points", ctypes.c_int64 * 6), ("t_afg_class_ms", ctypes.c_double * 6)]
+                ("prim_pair_points", ctypes.c_int64 * 6), ("t_afg_class_ms", ctypes.c_double * 6),
+                ("tile_functions", ctypes.c_double), ("tile_frows", ctypes.c_double), ("tile_grows", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         d = {k: getattr(self, k) for k, _ in self._fields_}

@@ -135,3 +135,24 @@ def test_mixed_and_screens_with_basis_screen():
         (st0["n_groups"], e1, e2, st2["skipped_bound"]))
     assert e1 <= 2e-7 * abs(st0["ex"])
     assert e2 <= st2["skipped_bound"] + 1e-12
+
+
+def test_learned_screen_with_basis_screen():
+    """config 2 with the learned screen (5e-7 Eh skip budget) and eps_basis = 1e-9: the K
+    GEMM of each tile runs over the rows of its kept blocks only; |dE_x| <= 1e-6 Eh against
+    the FP64 build on the same tiles."""
+    if not os.path.exists(snk.SCREENER_WEIGHTS):
+        pytest.skip("no trained screener weights")
+    m = snk.load_screener()
+    s = synth.make_system(2)
+    K0, st0 = snk.sn_k_build(s, eps_basis=1e-9, flags=snk.SNK_ROCBLAS)
+    for flags in (snk.SNK_ROCBLAS, 0):
+        K1, st1 = snk.sn_k_build(s, eps_basis=1e-9, screen=snk.SNK_SCREEN_LEARNED, screener=m, flags=flags)
+        dE = abs(st1["ex"] - st0["ex"])
+        skipped = st1["pair_points_skipped"] / max(1, st1["pair_points_skipped"] + sum(st1["pair_points"]))
+        say("config2 learned + eps_basis 1e-9 (flags %d): skipped %.3f |dE| %.2e max|dK| %.2e, kgemm %.2f ms "
+            "(unscreened %.2f); per tile |B_t| %.1f, F rows %.1f, G rows %.1f" %
+            (flags, skipped, dE, np.max(np.abs(K1 - K0)), st1["t_kgemm_ms"], st0["t_kgemm_ms"],
+             st1["tile_functions"], st1["tile_frows"], st1["tile_grows"]))
+        assert np.array_equal(K1, K1.T)
+        assert dE <= 1e-6
