@@ -236,37 +236,57 @@ __global__ __launch_bounds__(256) void scatter_rows_kernel(const T* __restrict__
     }
 }
 
-// One wave per row: mx[r] = max_c |Phi[r * ncols + c]|
+// p[rows[m] * ld + c] = v for m < M, c < ncols
+__global__ __launch_bounds__(256) void fill_rows_kernel(double* __restrict__ p, int64_t ld,
+                                                        const int32_t* __restrict__ rows, int64_t M, int64_t ncols,
+                                                        double v)
+{
+    const int64_t n = M * ncols;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t m = i / ncols;
+        p[(int64_t)rows[m] * ld + (i - m * ncols)] = v;
+    }
+}
+
+// One wave per row of a group's Phi buffer (the tiles' Phi_t one after the other: nfull rows
+// of ncols_full columns, then the rows of the last tile with ncols_last columns):
+// mx[r] = max_c |Phi_r,c|
 template <typename T>
-__global__ __launch_bounds__(256) void row_absmax_kernel(const T* __restrict__ Phi, int64_t nrow, int64_t ncols,
-                                                         double* __restrict__ mx)
+__global__ __launch_bounds__(256) void row_absmax_kernel(const T* __restrict__ Phi, int64_t nfull, int64_t ncols_full,
+                                                         int64_t nrow, int64_t ncols_last, double* __restrict__ mx)
 {
     const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (r >= nrow) return;
-    const T* row = Phi + r * ncols;
+    const bool full = r < nfull;
+    const int64_t ncols = full ? ncols_full : ncols_last;
+    const T* row = Phi + (full ? r * ncols_full : nfull * ncols_full + (r - nfull) * ncols_last);
     double m = 0.0;
     for (int64_t c = lane; c < ncols; c += 64) m = fmax(m, fabs((double)row[c]));
     for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
     if (lane == 0) mx[r] = m;
 }
 
-// One wave per function lam: Ft = sum_k |P[lam][fn[k]]| mx[k] bounds |F_lam,i| on every
-// point of the tile (Eq. fmat with |Phi_nu,i| <= mx); flag[shell_of[lam]] = 1 when Ft >= eps.
+// One wave per (function lam, tile t): Ft = sum_k |P[lam][fn[k]]| mx[k] over the tile's
+// functions (rows roff[t] .. roff[t+1]-1 of fn and mx) bounds |F_lam,i| on every point of the
+// tile (Eq. fmat with |Phi_nu,i| <= mx); flag[t][shell_of[lam]] = 1 when Ft >= eps.
 __global__ __launch_bounds__(256) void ftilde_flag_kernel(const double* __restrict__ P, int64_t nbf,
-                                                          const int32_t* __restrict__ fn, int32_t nB,
+                                                          const int32_t* __restrict__ fn,
+                                                          const int32_t* __restrict__ roff,
                                                           const double* __restrict__ mx, double eps,
-                                                          const int32_t* __restrict__ shell_of,
+                                                          const int32_t* __restrict__ shell_of, int32_t nshell,
                                                           int32_t* __restrict__ flag)
 {
     const int64_t lam = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int t = blockIdx.y;
     const int lane = threadIdx.x & 63;
     if (lam >= nbf) return;
     const double* row = P + lam * nbf;
-    double t = 0.0;
-    for (int k = lane; k < nB; k += 64) t = fma(fabs(row[fn[k]]), mx[k], t);
-    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
-    if (lane == 0 && t >= eps) flag[shell_of[lam]] = 1;
+    const int k0 = roff[t], k1 = roff[t + 1];
+    double v = 0.0;
+    for (int k = k0 + lane; k < k1; k += 64) v = fma(fabs(row[fn[k]]), mx[k], v);
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if (lane == 0 && v >= eps) flag[(int64_t)t * nshell + shell_of[lam]] = 1;
 }
 
 // One wave: A[i][k] = (k == 0) + i (k == 1), B[k][j] = 100 j (k == 0) + (k == 1), so that
@@ -454,29 +474,48 @@ hipError_t launch_scatter_rows(const float* in, int64_t M, int64_t ncols, const 
     return launch_scatter_rows_t<float>(in, M, ncols, rows, out, ld, s);
 }
 
-hipError_t launch_row_absmax(const double* Phi, int64_t nrow, int64_t ncols, double* mx, hipStream_t s)
+hipError_t launch_fill_rows(double* p, int64_t ld, const int32_t* rows, int64_t M, int64_t ncols, double v,
+                            hipStream_t s)
 {
-    if (nrow <= 0) return hipSuccess;
-    hipLaunchKernelGGL((row_absmax_kernel<double>), dim3((unsigned)((nrow + 3) / 4)), dim3(256), 0, s, Phi, nrow, ncols,
-                       mx);
+    if (M <= 0 || ncols <= 0) return hipSuccess;
+    if (!p || !rows) return hipErrorInvalidValue;
+    int64_t blocks = (M * ncols + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(fill_rows_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, ld, rows, M, ncols, v);
     return hipGetLastError();
 }
 
-hipError_t launch_row_absmax(const float* Phi, int64_t nrow, int64_t ncols, double* mx, hipStream_t s)
+template <typename T>
+static hipError_t launch_row_absmax_t(const T* Phi, int64_t nfull, int64_t ncols_full, int64_t nrow, int64_t ncols_last,
+                                      double* mx, hipStream_t s)
 {
     if (nrow <= 0) return hipSuccess;
-    hipLaunchKernelGGL((row_absmax_kernel<float>), dim3((unsigned)((nrow + 3) / 4)), dim3(256), 0, s, Phi, nrow, ncols,
-                       mx);
+    if (!Phi || !mx || nfull > nrow) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((row_absmax_kernel<T>), dim3((unsigned)((nrow + 3) / 4)), dim3(256), 0, s, Phi, nfull,
+                       ncols_full, nrow, ncols_last, mx);
     return hipGetLastError();
 }
 
-hipError_t launch_ftilde_flag(const double* P, int64_t nbf, const int32_t* fn, int32_t nB, const double* mx, double eps,
-                              const int32_t* shell_of, int32_t* flag, hipStream_t s)
+hipError_t launch_row_absmax(const double* Phi, int64_t nfull, int64_t ncols_full, int64_t nrow, int64_t ncols_last,
+                             double* mx, hipStream_t s)
 {
-    if (nbf <= 0) return hipSuccess;
-    if (!P || !fn || !mx || !shell_of || !flag) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(ftilde_flag_kernel, dim3((unsigned)((nbf + 3) / 4)), dim3(256), 0, s, P, nbf, fn, nB, mx, eps,
-                       shell_of, flag);
+    return launch_row_absmax_t<double>(Phi, nfull, ncols_full, nrow, ncols_last, mx, s);
+}
+
+hipError_t launch_row_absmax(const float* Phi, int64_t nfull, int64_t ncols_full, int64_t nrow, int64_t ncols_last,
+                             double* mx, hipStream_t s)
+{
+    return launch_row_absmax_t<float>(Phi, nfull, ncols_full, nrow, ncols_last, mx, s);
+}
+
+hipError_t launch_ftilde_flag(const double* P, int64_t nbf, const int32_t* fn, const int32_t* roff, int32_t ntile,
+                              const double* mx, double eps, const int32_t* shell_of, int32_t nshell, int32_t* flag,
+                              hipStream_t s)
+{
+    if (nbf <= 0 || ntile <= 0) return hipSuccess;
+    if (!P || !fn || !roff || !mx || !shell_of || !flag) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(ftilde_flag_kernel, dim3((unsigned)((nbf + 3) / 4), (unsigned)ntile), dim3(256), 0, s, P, nbf,
+                       fn, roff, mx, eps, shell_of, nshell, flag);
     return hipGetLastError();
 }
 

@@ -35,6 +35,8 @@ constexpr double kBoundSafety = 1.01;
 
 // ---------------------------------------------------------------------------------------
 // U_A for the shells of one angular momentum L: one workgroup per batch, lane = point.
+// With a tile shell flag array, shells whose F rows the tile did not compute (flag 0, F = 0
+// there) get U = 0 and N = 0 without evaluating their integrals.
 // ---------------------------------------------------------------------------------------
 template <int L, typename TF>
 __global__ __launch_bounds__(256) void diag_bound_kernel(const double* __restrict__ px, const double* __restrict__ py,
@@ -47,7 +49,8 @@ __global__ __launch_bounds__(256) void diag_bound_kernel(const double* __restric
                                                          const int32_t* __restrict__ dnp,   // [n] nprim of (A,A)
                                                          int32_t n, double* __restrict__ U,
                                                          float2* __restrict__ lun, int32_t nshell,
-                                                         const double* __restrict__ gtab)
+                                                         const double* __restrict__ gtab,
+                                                         const int32_t* __restrict__ tflag, int32_t tile_batches)
 {
     constexpr int N = ncart(L);
     __shared__ float tab[kBoysRows * kBoysCols];
@@ -61,10 +64,18 @@ __global__ __launch_bounds__(256) void diag_bound_kernel(const double* __restric
     const double w = pw[col];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const float AB[3] = {0.0f, 0.0f, 0.0f};
+    const int32_t* fl = tflag ? tflag + (int64_t)(batch / tile_batches) * nshell : nullptr;
     // shells in groups of kGroup: per-wave partial sums in LDS, one barrier pair per group
     for (int s0 = 0; s0 < n; s0 += kGroup) {
         const int s1 = min(n, s0 + kGroup);
         for (int s = s0; s < s1; ++s) {
+            if (fl && !fl[dsh[s]]) {   // uniform over the workgroup
+                if (lane == 0) {
+                    part[s - s0][wave] = 0.0;
+                    npart[s - s0][wave] = 0.0;
+                }
+                continue;
+            }
             const int row = drow[s];
             float Ab[N][N];
             pair_block<L, L, float>(prims + dpb[s], dnp[s], AB, cx, cy, cz, tab, Ab);
@@ -625,17 +636,19 @@ __global__ __launch_bounds__(256) void screen_scan_kernel(const int32_t* __restr
 hipError_t launch_diag_bound(int l, const double* px, const double* py, const double* pz, const double* pw,
                              const double* F, const float* F32, int64_t ld, const PrimPair32* prims, const int32_t* dsh,
                              const int32_t* drow, const int32_t* dpb, const int32_t* dnp, int32_t n, double* U,
-                             float2* N, int32_t nshell, int32_t nbatch, const double* tab, hipStream_t s)
+                             float2* N, int32_t nshell, int32_t nbatch, const double* tab, const int32_t* tflag,
+                             int32_t tile_batches, hipStream_t s)
 {
+    if (tflag && tile_batches < 1) return hipErrorInvalidValue;
     if (nbatch <= 0 || n <= 0) return hipSuccess;
     dim3 grid(nbatch), block(kBatch);
 #define SNK_DB(L)                                                                                                  \
     if (F32)                                                                                                       \
         hipLaunchKernelGGL((diag_bound_kernel<L, float>), grid, block, 0, s, px, py, pz, pw, F32, ld, prims, dsh,  \
-                           drow, dpb, dnp, n, U, N, nshell, tab);                                                  \
+                           drow, dpb, dnp, n, U, N, nshell, tab, tflag, tile_batches);                             \
     else                                                                                                           \
         hipLaunchKernelGGL((diag_bound_kernel<L, double>), grid, block, 0, s, px, py, pz, pw, F, ld, prims, dsh,   \
-                           drow, dpb, dnp, n, U, N, nshell, tab)
+                           drow, dpb, dnp, n, U, N, nshell, tab, tflag, tile_batches)
     switch (l) {
         case 0: SNK_DB(0); break;
         case 1: SNK_DB(1); break;

@@ -46,6 +46,7 @@ struct Tile {
     std::vector<int32_t> coll_rows;     // row of each such shell's first function in Phi_t
     std::vector<int32_t> coll_fn;       // global function index of every Phi_t row
     int32_t nB = 0;                     // rows of Phi_t
+    int32_t row_off = 0;                // first row of Phi_t among the group's Phi rows
     int32_t* d_coll_shells = nullptr;
     int32_t* d_coll_rows = nullptr;
     int32_t* d_coll_fn = nullptr;
@@ -57,6 +58,9 @@ struct Group {
     int64_t ncols = 0;                  // (b1 - b0) * kBatch: columns of F_g and G_g
     std::vector<Tile> tiles;
     int64_t phi_elems = 0;              // sum of nB * ncols over the tiles
+    int32_t phi_rows = 0;               // sum of nB over the tiles
+    int32_t* d_fn_cat = nullptr;        // the tiles' coll_fn one after the other (eps_basis > 0)
+    int32_t* d_roff = nullptr;          // [ntiles + 1] row_off of each tile, then phi_rows
 };
 
 }  // namespace
@@ -119,9 +123,11 @@ struct snk_ctx {
     int32_t* d_fflag = nullptr;         // [max_group_tiles][nshell]
     int32_t* d_frows = nullptr;         // [max_group_tiles][nbf]
     int32_t* d_fcount = nullptr;        // [max_group_tiles]
-    double* d_phimax = nullptr;         // [max_nB]
+    double* d_mx = nullptr;             // [max_group_rows] max |Phi| of each row of a group's Phi
+    int32_t max_group_rows = 0;
     int32_t* d_fn_shell = nullptr;      // [nbf] shell of each function
     std::vector<int32_t> tile_frows;    // F rows per tile of the current group
+    bool zero_f_rows = false;           // write every zero row of F and G (readers of every row)
     double acc_fn = 0, acc_frows = 0, acc_grows = 0, acc_cols = 0;   // column-weighted tile sizes
     int nsplit = 1;                     // K GEMM split over points for full-width tiles
     int64_t part_elems = 0;             // size of the split partial-sum buffer
@@ -666,8 +672,8 @@ int build_groups(snk_ctx* c)
                     }
             int32_t row = 0;
             for (int s = 0; s < c->nshell; ++s) {
+                double d2 = 0.0;
                 if (bscreen) {
-                    double d2 = 0.0;
                     for (int d = 0; d < 3; ++d) {
                         const double x = c->scen[3 * s + d];
                         const double e = std::max(std::max(lo[d] - x, x - hi[d]), 0.0);
@@ -682,6 +688,8 @@ int build_groups(snk_ctx* c)
             }
             t.nB = row;
             t.all_functions = row == c->nbf;
+            t.row_off = gr.phi_rows;
+            gr.phi_rows += row;
             gr.phi_elems += (int64_t)t.nB * t.ncols;
             gr.tiles.push_back(std::move(t));
         }
@@ -694,6 +702,7 @@ int build_groups(snk_ctx* c)
     c->max_group_tiles = 0;
     for (auto& gr : c->groups) {
         c->max_group_tiles = std::max(c->max_group_tiles, (int32_t)gr.tiles.size());
+        c->max_group_rows = std::max(c->max_group_rows, gr.phi_rows);
         c->max_cols = std::max(c->max_cols, gr.ncols);
         c->max_phi = std::max(c->max_phi, gr.phi_elems);
         for (auto& t : gr.tiles) {
@@ -871,12 +880,15 @@ void free_ctx(snk_ctx* c)
     (void)hipFree(c->d_py);
     (void)hipFree(c->d_pz);
     (void)hipFree(c->d_pw);
-    for (auto& g : c->groups)
+    for (auto& g : c->groups) {
+        (void)hipFree(g.d_fn_cat);
+        (void)hipFree(g.d_roff);
         for (auto& t : g.tiles) {
             (void)hipFree(t.d_coll_shells);
             (void)hipFree(t.d_coll_rows);
             (void)hipFree(t.d_coll_fn);
         }
+    }
     (void)hipFree(c->d_Phi32);
     (void)hipFree(c->d_F32);
     (void)hipFree(c->d_P32);
@@ -888,7 +900,7 @@ void free_ctx(snk_ctx* c)
     (void)hipFree(c->d_fflag);
     (void)hipFree(c->d_frows);
     (void)hipFree(c->d_fcount);
-    (void)hipFree(c->d_phimax);
+    (void)hipFree(c->d_mx);
     (void)hipFree(c->d_fn_shell);
     (void)hipFree(c->d_Phi);
     (void)hipFree(c->d_F);
@@ -1143,7 +1155,18 @@ int snk_ctx_create(const snk_basis* basis, const snk_grid* grid, const double* w
         CREATE_CHECK(dalloc(c, &c->d_fflag, (size_t)c->max_group_tiles * c->nshell));
         CREATE_CHECK(dalloc(c, &c->d_frows, (size_t)c->max_group_tiles * nbf));
         CREATE_CHECK(dalloc(c, &c->d_fcount, (size_t)c->max_group_tiles));
-        CREATE_CHECK(dalloc(c, &c->d_phimax, (size_t)std::max<int32_t>(1, c->max_nB)));
+        CREATE_CHECK(dalloc(c, &c->d_mx, (size_t)std::max<int32_t>(1, c->max_group_rows)));
+        for (auto& g : c->groups) {
+            std::vector<int32_t> cat, roff;
+            for (const auto& t : g.tiles) {
+                roff.push_back((int32_t)cat.size());
+                cat.insert(cat.end(), t.coll_fn.begin(), t.coll_fn.end());
+            }
+            roff.push_back((int32_t)cat.size());
+            if (cat.empty()) cat.push_back(0);
+            CREATE_CHECK(upload(c, &g.d_fn_cat, cat));
+            CREATE_CHECK(upload(c, &g.d_roff, roff));
+        }
         std::vector<int32_t> fs(nbf);
         for (int sh = 0; sh < c->nshell; ++sh)
             for (int k = 0; k < ncart(c->sl[sh]); ++k) fs[c->sfn[sh] + k] = sh;
@@ -1212,14 +1235,15 @@ int group_F(snk_ctx* c, const Group& g, const double* dP, bool timed)
         // rows L_t of F that can reach eps_basis on the tile: functions whose bound
         // sum_{nu in B_t} |P_lam,nu| max_i |Phi_nu,i| >= eps_basis, by whole shells
         HIPCHECK(c, launch_fill(c->d_fflag, (int64_t)ntile * c->nshell, 0, s));
-        for (int ti = 0; ti < ntile; ++ti) {
-            const Tile& t = g.tiles[ti];
-            if (t.nB == 0) continue;
-            if (c->mixed) HIPCHECK(c, launch_row_absmax(c->d_Phi32 + t.phi_off, t.nB, t.ncols, c->d_phimax, s));
-            else HIPCHECK(c, launch_row_absmax(c->d_Phi + t.phi_off, t.nB, t.ncols, c->d_phimax, s));
-            HIPCHECK(c, launch_ftilde_flag(dP, nbf, t.d_coll_fn, t.nB, c->d_phimax, c->opts.eps_basis, c->d_fn_shell,
-                                           c->d_fflag + (int64_t)ti * c->nshell, s));
-        }
+        const Tile& last = g.tiles.back();
+        const int64_t nfull = last.row_off;
+        const int64_t ncols_full = ntile > 1 ? g.tiles[0].ncols : 0;
+        if (c->mixed)
+            HIPCHECK(c, launch_row_absmax(c->d_Phi32, nfull, ncols_full, g.phi_rows, last.ncols, c->d_mx, s));
+        else
+            HIPCHECK(c, launch_row_absmax(c->d_Phi, nfull, ncols_full, g.phi_rows, last.ncols, c->d_mx, s));
+        HIPCHECK(c, launch_ftilde_flag(dP, nbf, g.d_fn_cat, g.d_roff, ntile, c->d_mx, c->opts.eps_basis, c->d_fn_shell,
+                                       c->nshell, c->d_fflag, s));
         HIPCHECK(c, launch_tile_rows(c->d_fflag, ntile, c->nshell, c->d_shell_l, c->d_shell_row, c->nbf, c->d_frows,
                                      c->d_fcount, s));
         c->tile_frows.assign(ntile, 0);
@@ -1240,14 +1264,18 @@ int group_F(snk_ctx* c, const Group& g, const double* dP, bool timed)
             continue;
         }
         if (c->frow_restrict && L < nbf) {
-            // F_c = P[L_t, B_t] Phi_t, then rows L_t of the tile's columns; all other rows are 0
+            // F_c = P[L_t, B_t] Phi_t, then rows L_t of the tile's columns.  The other rows are
+            // zero; they are written only where a reader takes every row (no density screen,
+            // training data, debugging): the screens give those shells U = 0 without reading
+            // them and never list their blocks.
+            const bool zero_rows = c->opts.screen == SNK_SCREEN_NONE || c->zero_f_rows;
             const int32_t* rows = c->d_frows + (int64_t)ti * nbf;
             if (c->mixed) {
                 float* Fc = reinterpret_cast<float*>(c->d_Gc);
                 HIPCHECK(c, launch_gather(dP, nbf, rows, L, t.d_coll_fn, t.nB, c->d_Pg32, s));
                 HIPCHECK(c, launch_gemm_f32(L, t.ncols, t.nB, c->d_Pg32, t.nB, c->d_Phi32 + t.phi_off, t.ncols, false,
                                             Fc, t.ncols, 1, 0, s));
-                HIPCHECK(c, launch_fill2d(c->d_F32 + t.col0, nbf, t.ncols, ld, 0.0f, s));
+                if (zero_rows) HIPCHECK(c, launch_fill2d(c->d_F32 + t.col0, nbf, t.ncols, ld, 0.0f, s));
                 HIPCHECK(c, launch_scatter_rows(Fc, L, t.ncols, rows, c->d_F32 + t.col0, ld, s));
                 continue;
             }
@@ -1266,7 +1294,7 @@ int group_F(snk_ctx* c, const Group& g, const double* dP, bool timed)
                 HIPCHECK(c, launch_gemm_f64(L, t.ncols, t.nB, c->d_Pg, t.nB, c->d_Phi + t.phi_off, t.ncols, false,
                                             c->d_Gc, t.ncols, 1, 0, s));
             }
-            HIPCHECK(c, launch_fill2d(c->d_F + t.col0, nbf, t.ncols, ld, 0.0, s));
+            if (zero_rows) HIPCHECK(c, launch_fill2d(c->d_F + t.col0, nbf, t.ncols, ld, 0.0, s));
             HIPCHECK(c, launch_scatter_rows(c->d_Gc, L, t.ncols, rows, c->d_F + t.col0, ld, s));
             continue;
         }
@@ -1392,7 +1420,8 @@ int group_bounds(snk_ctx* c, const Group& g)
                                       c->mixed ? c->d_F32 : nullptr, g.ncols,
                                       c->d_prims32, c->d_diag_sh[l], c->d_diag_row[l], c->d_diag_pb[l],
                                       c->d_diag_np[l], c->n_diag[l], c->d_U, c->d_lun, c->nshell, g.b1 - g.b0,
-                                      c->d_boys, c->stream));
+                                      c->d_boys, c->frow_restrict ? c->d_fflag : nullptr, c->tile_batches,
+                                      c->stream));
     return SNK_OK;
 }
 
@@ -1525,7 +1554,14 @@ int group_until_G(snk_ctx* c, const Group& g, const double* dP, bool timed, Grou
         }
     }
 
-    HIPCHECK(c, launch_fill(c->d_G, nbf * g.ncols, 0.0, s));
+    if (screen && c->row_restrict && !c->zero_f_rows && c->tile_rows.size() == g.tiles.size()) {
+        // the A.F kernels update only the rows M_t of each tile's kept blocks
+        for (size_t ti = 0; ti < g.tiles.size(); ++ti)
+            HIPCHECK(c, launch_fill_rows(c->d_G + g.tiles[ti].col0, ld, c->d_trows + (int64_t)ti * nbf,
+                                         c->tile_rows[ti], g.tiles[ti].ncols, 0.0, s));
+    } else {
+        HIPCHECK(c, launch_fill(c->d_G, nbf * g.ncols, 0.0, s));
+    }
     AfgArgs a{};
     a.px = c->d_px + off;
     a.py = c->d_py + off;
@@ -1727,9 +1763,17 @@ int snk_ctx_point_order(const snk_ctx* c, int64_t* col_to_point)
     return SNK_OK;
 }
 
+// Sets snk_ctx::zero_f_rows for the lifetime of a call that reads every row of F or G.
+struct ZeroRows {
+    snk_ctx* c;
+    explicit ZeroRows(snk_ctx* x) : c(x) { c->zero_f_rows = true; }
+    ~ZeroRows() { c->zero_f_rows = false; }
+};
+
 int snk_ctx_debug_intermediates(snk_ctx* c, const double* P, double* Phi, double* F, double* G, int64_t* ncols_out)
 {
     if (!c || !P) return arg_error(c, "NULL argument");
+    ZeroRows zr(c);
     if (c->mixed) return arg_error(c, "intermediates are available from FP64 contexts only");
     if (c->groups.empty()) {
         if (ncols_out) *ncols_out = 0;
@@ -1806,6 +1850,7 @@ int snk_ctx_tile_functions(const snk_ctx* c, int32_t tile, int32_t* fn)
 int snk_ctx_block_data(snk_ctx* c, const double* P, float* features, double* block_energy, int32_t* pair_shells)
 {
     if (!c || !P) return arg_error(c, "NULL context or density");
+    ZeroRows zr(c);
     if (!features && !block_energy && !pair_shells) return SNK_OK;
     const int64_t nbf = c->nbf;
     const int64_t ldk = (int64_t)c->ne_list.size();

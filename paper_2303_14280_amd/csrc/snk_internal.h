@@ -207,7 +207,8 @@ hipError_t launch_mlp_adam(float* params, float* m, float* v, const float* g, fl
 hipError_t launch_diag_bound(int l, const double* px, const double* py, const double* pz, const double* pw,
                              const double* F, const float* F32, int64_t ld, const PrimPair32* prims, const int32_t* dsh,
                              const int32_t* drow, const int32_t* dpb, const int32_t* dnp, int32_t n, double* U,
-                             float2* lun, int32_t nshell, int32_t nbatch, const double* tab, hipStream_t s);
+                             float2* lun, int32_t nshell, int32_t nbatch, const double* tab, const int32_t* tflag,
+                             int32_t tile_batches, hipStream_t s);
 hipError_t launch_screen(bool write, const ScreenArgs& a, hipStream_t s);
 // Rows of G that the kept blocks of each tile can touch: for tile t, rows[t * nbf + m]
 // (m < count[t]) are the functions of the flagged shells in ascending order.
@@ -275,12 +276,20 @@ hipError_t launch_scatter_rows(const double* in, int64_t M, int64_t ncols, const
                                hipStream_t s);
 hipError_t launch_scatter_rows(const float* in, int64_t M, int64_t ncols, const int32_t* rows, float* out, int64_t ld,
                                hipStream_t s);
-// mx[r] = max_c |Phi[r * ncols + c]| for r < nrow
-hipError_t launch_row_absmax(const double* Phi, int64_t nrow, int64_t ncols, double* mx, hipStream_t s);
-hipError_t launch_row_absmax(const float* Phi, int64_t nrow, int64_t ncols, double* mx, hipStream_t s);
-// flag[shell_of[lam]] = 1 where sum_k |P[lam][fn[k]]| mx[k] >= eps (bound on |F_lam| over a tile)
-hipError_t launch_ftilde_flag(const double* P, int64_t nbf, const int32_t* fn, int32_t nB, const double* mx, double eps,
-                              const int32_t* shell_of, int32_t* flag, hipStream_t s);
+// p[rows[m] * ld + c] = v for m < M, c < ncols
+hipError_t launch_fill_rows(double* p, int64_t ld, const int32_t* rows, int64_t M, int64_t ncols, double v,
+                            hipStream_t s);
+// Row maxima of a group's Phi buffer: nfull rows of ncols_full columns, then rows nfull..nrow-1
+// of ncols_last columns; mx[r] = max_c |Phi_r,c|
+hipError_t launch_row_absmax(const double* Phi, int64_t nfull, int64_t ncols_full, int64_t nrow, int64_t ncols_last,
+                             double* mx, hipStream_t s);
+hipError_t launch_row_absmax(const float* Phi, int64_t nfull, int64_t ncols_full, int64_t nrow, int64_t ncols_last,
+                             double* mx, hipStream_t s);
+// flag[t * nshell + shell_of[lam]] = 1 where sum_{k in roff[t]..roff[t+1]-1} |P[lam][fn[k]]| mx[k] >= eps
+// (a bound on |F_lam| over tile t), for every function lam and tile t < ntile
+hipError_t launch_ftilde_flag(const double* P, int64_t nbf, const int32_t* fn, const int32_t* roff, int32_t ntile,
+                              const double* mx, double eps, const int32_t* shell_of, int32_t nshell, int32_t* flag,
+                              hipStream_t s);
 // gather P_g[m][n] = P[rows[m]][cols[n]] (NULL rows/cols: identity), stored FP64 or rounded to FP32
 hipError_t launch_gather(const double* P, int64_t nbf, const int32_t* rows, int64_t M, const int32_t* cols,
                          int64_t N, double* out, hipStream_t s);

@@ -156,3 +156,22 @@ def test_learned_screen_with_basis_screen():
              st1["tile_functions"], st1["tile_frows"], st1["tile_grows"]))
         assert np.array_equal(K1, K1.T)
         assert dE <= 1e-6
+
+
+@pytest.mark.parametrize("screen", [snk.SNK_SCREEN_NONE, snk.SNK_SCREEN_BOUND])
+def test_f_rows_bound(screen):
+    """Rows of F restricted per tile: F = P Phi_t on the rows L_t, and every dropped element
+    (rows whose bound sum_nu |P_lam,nu| max|phi_nu| < eps_basis) is below eps_basis.  Phi and
+    F of the first group from the debug hook (full rows, zeros outside B_t and L_t)."""
+    s = synth.make_system(1, grid=(30, 110))
+    eps = 1e-4
+    ctx = snk.Context(s, eps_basis=eps, screen=screen, eps_skip_energy=1e-8, max_device_bytes=group_bytes(s, 4))
+    Phi, F, G = ctx.debug_intermediates(s.P)
+    ref = s.P @ Phi
+    kept = np.any(F != 0.0, axis=1)
+    dropped = ~kept
+    say("screen %d: %d of %d rows of F computed in the first group; max dropped |P Phi| %.2e; max |dF| kept %.2e" %
+        (screen, int(kept.sum()), s.nbf, np.max(np.abs(ref[dropped])) if dropped.any() else 0.0,
+         np.max(np.abs(F[kept] - ref[kept]))))
+    assert np.max(np.abs(F - ref)) <= eps
+    assert np.max(np.abs(F[kept] - ref[kept])) <= 1e-12 * max(1.0, np.max(np.abs(ref)))
