@@ -5,7 +5,11 @@ symmetrisation and E_x) for the 30-atom water cluster (config 2: 290 Cartesian
 s/p/d functions, 75x302 grid per atom = 679,500 points, FP64, no screening) with
 P and K resident in HBM.  Prints one JSON line.
 
-    python bench.py [--gpus 1] [--steps 5] [--warmup 2] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps 5] [--warmup 2] [--no-cpu-baseline] [--large 4,5]
+
+The JSON line also carries the mixed-precision and learned-screen builds of the same
+workload, a molecule-local density on the same geometry, and (--large) the 500- and
+1000-atom clusters with basis and density screening.
 """
 from __future__ import annotations
 
@@ -174,6 +178,57 @@ def local_density_comparison(s, stream, args):
     return res
 
 
+def large_system(config, stream, args):
+    """A large cluster with molecule-local density (500 or 1000 atoms): FP64 with basis
+    screening (eps_basis 1e-9) and the rigorous density screen (5e-7 Eh) against the learned
+    screen in FP64 and in the mixed build, each timed over `args.large_steps` builds after one
+    warm-up, with E_x differences against the first."""
+    import torch
+    from paper_2303_14280_amd import snk, synth
+    if not os.path.exists(snk.SCREENER_WEIGHTS):
+        return {"error": "no trained screener weights"}
+    t = time.perf_counter()
+    s = synth.make_system(config)
+    log("config %d generated in %.1f s" % (config, time.perf_counter() - t))
+    P = torch.tensor(s.P, dtype=torch.float64, device="cuda")
+    mlp = snk.load_screener(device=0)
+    R = snk.SNK_DEVICE_PTRS | snk.SNK_ROCBLAS
+    res = {"workload": "config%d: %d atoms, %d functions, %d grid points, %s density"
+                       % (config, len(s.atom_Z), s.nbf, s.npts, s.density)}
+    variants = [("fp64+bound", dict(screen=snk.SNK_SCREEN_BOUND, eps_skip_energy=5e-7)),
+                ("fp64+learned", dict(screen=snk.SNK_SCREEN_LEARNED, eps_skip_energy=args.eps)),
+                ("mixed+learned", dict(screen=snk.SNK_SCREEN_LEARNED, precision=snk.SNK_MIXED,
+                                       eps_skip_energy=args.eps, eps_lowprec_energy=args.eps))]
+    K0 = None
+    for name, kw in variants:
+        t = time.perf_counter()
+        ctx = snk.Context(s, flags=R, stream=stream.cuda_stream, device=0, screener=mlp, eps_basis=1e-9, **kw)
+        t_create = time.perf_counter() - t
+        K = torch.empty_like(P)
+        ms = time_builds(ctx, P, K, stream, args.large_steps, 1)
+        st = ctx.build_device(P.data_ptr(), K.data_ptr(), stats=True)
+        torch.cuda.synchronize()
+        ctx.close()
+        ints = float(sum(st["pair_points"]) + st["pair_points_skipped"])
+        r = {"ms_per_step": ms, "create_s": t_create, "ex": st["ex"],
+             "skipped_pair_points_fraction": st["pair_points_skipped"] / max(1.0, ints),
+             "fp32_pair_points_fraction": st["pair_points_lowprec"] / max(1.0, ints),
+             "skipped_energy_estimate": st["skipped_bound"], "effective_rate": ints / (ms * 1e-3),
+             "tile_functions": st["tile_functions"], "tile_f_rows": st["tile_frows"], "tile_g_rows": st["tile_grows"],
+             "phases_ms": {"collocate": st["t_collocate_ms"], "fgemm": st["t_fgemm_ms"], "screen": st["t_screen_ms"],
+                           "afg": st["t_afg_ms"], "kgemm": st["t_kgemm_ms"], "finish": st["t_finish_ms"]}}
+        if K0 is None:
+            K0, ms0, ex0 = K, ms, st["ex"]
+            r["unscreened_shell_pair_points"] = ints
+        else:
+            r["speedup_vs_fp64_bound"] = ms0 / ms
+            r["dE_x_vs_fp64_bound"] = st["ex"] - ex0
+            r["max_dK_vs_fp64_bound"] = float((K - K0).abs().max().item())
+        log("config %d %s: %.1f ms/step, E_x %.10f" % (config, name, ms, st["ex"]))
+        res[name] = r
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -184,6 +239,10 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision + learned-screen comparison")
     ap.add_argument("--eps", type=float, default=5e-6,
                     help="estimate budget (Eh) of the learned screen's skipped blocks and of the FP32 blocks")
+    ap.add_argument("--large", default="4,5",
+                    help="comma-separated large configurations (4: 500 atoms, 5: 1000 atoms) to time with basis "
+                         "and density screening, or 'none'")
+    ap.add_argument("--large-steps", type=int, default=3)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -293,6 +352,10 @@ def main():
     if not args.no_mixed:
         out["mixed_learned"] = mixed_learned(s, P, K, stream, args, ms, st["ex"], ints)
         out["local_density"] = local_density_comparison(s, stream, args)
+    if args.large and args.large != "none":
+        out["large_systems"] = {}
+        for c in args.large.split(","):
+            out["large_systems"]["config%d" % int(c)] = large_system(int(c), stream, args)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(s)
