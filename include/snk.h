@@ -122,7 +122,7 @@ typedef struct snk_opts {
     int32_t screen;             /* snk_screen */
     const snk_mlp* screener;    /* required for SNK_SCREEN_LEARNED */
     double eps_basis;           /* basis-function screening tolerance eps_B (Eq. basis_screen); 0 = off.
-                                   > 0: batches are ordered spatially into tiles of at most 128;
+                                   > 0: batches are ordered spatially into tiles of at most 16;
                                    tile t collocates only the functions B_t whose sphere of
                                    radius r_cut (beyond which |phi| < eps_basis) reaches the box
                                    of the tile's points; F_t = P[:, B_t] Phi_t and only the
@@ -175,7 +175,7 @@ int snk_ctx_nbatches(const snk_ctx* ctx);
  * of one F_g and G_g; the screen and the A.F kernels run over a whole group.  A tile is a run
  * of consecutive batches of a group that shares one set B_t of collocated functions
  * (Eq. basis_screen); collocation and both GEMMs run per tile.  Without basis screening each
- * group is one tile with all N_b functions; with eps_basis > 0 tiles hold up to 128
+ * group is one tile with all N_b functions; with eps_basis > 0 tiles hold up to 16
  * spatially ordered batches.
  * snk_ctx_ngroups / snk_ctx_ntiles: their numbers.  snk_ctx_tile_info: for tile k, its
  * group, its batches [b0[k], b1[k]) in the context's batch order (see snk_ctx_point_order)

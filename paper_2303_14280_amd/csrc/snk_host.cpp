@@ -487,8 +487,10 @@ void split_points(const double* xyz, std::vector<int64_t>& idx, size_t lo, size_
 
 // Batches per tile when basis functions are screened: a tile's functions are those whose
 // sphere reaches the tile's box, so tiles are spatially compact and small enough for the box
-// to exclude distant functions, and large enough (32768 columns) for full-rate GEMMs.
-constexpr int kBasisTileBatches = 128;
+// to exclude distant functions.  Smaller tiles shrink B_t, L_t and M_t (the GEMMs scale with
+// their products) but lower the GEMMs' rate; 16 batches (4096 columns) measured best on the
+// 500- and 1000-atom clusters (8: 5% slower, 32: 10%, 128: 50%).
+constexpr int kBasisTileBatches = 16;
 
 // Radius beyond which every Cartesian function of a shell is below eps in magnitude, for the
 // sphere test of Eq. basis_screen; -1 when the shell stays below eps everywhere.  Each

@@ -1,6 +1,6 @@
 """Basis-function screening (Eq. basis_screen) on the GPU.
 
-With eps_basis > 0 the batches are ordered spatially into tiles (runs of at most 128
+With eps_basis > 0 the batches are ordered spatially into tiles (runs of at most 16
 batches inside a batch group) and tile t collocates only the functions B_t whose sphere of
 radius r_cut (beyond which |phi_mu| < eps_basis) reaches the box of the tile's points.
 Checks:
