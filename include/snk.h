@@ -202,6 +202,15 @@ int snk_version(void);
 int snk_boys_device(const double* T, int64_t n, int mmax, double* F_out, void* stream);
 
 /*
+ * Basis screening radius (Eq. basis_screen), host only: the radius beyond which every
+ * Cartesian function of a shell of angular momentum l (contracted over nprim primitives
+ * with exponents exps and coefficients coefs as in snk_basis) is below eps in magnitude;
+ * -1 when the shell stays below eps everywhere.  Returns the radius in *r_out; SNK_E_ARG
+ * for a NULL pointer, l outside 0..2, nprim < 1, a non-positive exponent or eps <= 0.
+ */
+int snk_shell_rcut(int l, const double* exps, const double* coefs, int nprim, double eps, double* r_out);
+
+/*
  * Learned block screener (the AI form beside the plain method; no counterpart in the paper,
  * which screens with the sn-LinK estimates of Sec. II.E).  A small network,
  * 16 features -> 64 -> 64 -> 1 (SiLU), predicts log10 of the absolute energy of a

@@ -1730,6 +1730,16 @@ int sn_k_build(const snk_basis* basis, const snk_grid* grid, const double* weigh
     return rc;
 }
 
+int snk_shell_rcut(int l, const double* exps, const double* coefs, int nprim, double eps, double* r_out)
+{
+    if (!exps || !coefs || !r_out) return arg_error(nullptr, "NULL argument");
+    if (l < 0 || l > kMaxL || nprim < 1 || !isfin(eps) || eps <= 0.0) return arg_error(nullptr, "bad shell or eps");
+    for (int k = 0; k < nprim; ++k)
+        if (!isfin(exps[k]) || exps[k] <= 0.0 || !isfin(coefs[k])) return arg_error(nullptr, "bad exponent or coefficient");
+    *r_out = shell_rcut(l, exps, coefs, nprim, eps);
+    return SNK_OK;
+}
+
 int snk_debug_gemm_f64(int64_t M, int64_t N, int64_t K, const double* A, int64_t lda, const double* B, int64_t ldb,
                        int bt, double* C, int64_t ldc, void* stream)
 {

@@ -105,6 +105,9 @@ def lib():
             L.snk_ctx_nbatches.restype = ctypes.c_int
             L.snk_ctx_ngroups.argtypes = [ctypes.c_void_p]
             L.snk_ctx_ngroups.restype = ctypes.c_int
+            L.snk_shell_rcut.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_double,
+                                         ctypes.POINTER(ctypes.c_double)]
+            L.snk_shell_rcut.restype = ctypes.c_int
             L.snk_ctx_ntiles.argtypes = [ctypes.c_void_p]
             L.snk_ctx_ntiles.restype = ctypes.c_int
             L.snk_ctx_tile_info.argtypes = [ctypes.c_void_p] * 5
@@ -209,6 +212,15 @@ class _Marshal:
                               self.exps.ctypes.data_as(_D), self.coefs.ctypes.data_as(_D))
         self.grid = SnkGrid(int(self.w.shape[0]), self.xyz.ctypes.data_as(_D),
                             self.atom.ctypes.data_as(_I32) if self.atom is not None else None)
+
+
+def shell_rcut(l: int, exps, coefs, eps: float) -> float:
+    """Basis screening radius of one shell (snk_shell_rcut; host only, no GPU needed)."""
+    e = np.ascontiguousarray(exps, np.float64)
+    c = np.ascontiguousarray(coefs, np.float64)
+    r = ctypes.c_double(0.0)
+    _check(lib().snk_shell_rcut(int(l), e.ctypes.data, c.ctypes.data, int(e.shape[0]), float(eps), ctypes.byref(r)))
+    return r.value
 
 
 def nbf_of(s) -> int:
