@@ -127,6 +127,18 @@ struct snk_ctx {
     int32_t max_group_rows = 0;
     int32_t* d_fn_shell = nullptr;      // [nbf] shell of each function
     std::vector<int32_t> tile_frows;    // F rows per tile of the current group
+    // Small per-tile GEMMs run on kLanes streams at once (lane 0 is the context's stream),
+    // each lane with its own gather / product / partial-sum buffers
+    static constexpr int kLanes = 4;
+    int nlanes = 1;
+    hipStream_t lane_stream[kLanes] = {};
+    hipEvent_t lane_ev[kLanes] = {};
+    hipEvent_t lane_red[kLanes] = {};
+    hipEvent_t fork_ev = nullptr;
+    double* lane_Pg[kLanes] = {};
+    double* lane_Gc[kLanes] = {};
+    double* lane_part[kLanes] = {};
+    rocblas_handle lane_blas[kLanes] = {};   // [0] = blas; one handle per lane stream (own workspace)
     bool zero_f_rows = false;           // write every zero row of F and G (readers of every row)
     double acc_fn = 0, acc_frows = 0, acc_grows = 0, acc_cols = 0;   // column-weighted tile sizes
     int nsplit = 1;                     // K GEMM split over points for full-width tiles
@@ -899,6 +911,18 @@ void free_ctx(snk_ctx* c)
     (void)hipFree(c->d_trows);
     (void)hipFree(c->d_tcount);
     (void)hipFree(c->d_Gc);
+    for (int k = 1; k < snk_ctx::kLanes; ++k) {
+        if (c->lane_blas[k]) (void)rocblas_destroy_handle(c->lane_blas[k]);
+        (void)hipFree(c->lane_Pg[k]);
+        (void)hipFree(c->lane_Gc[k]);
+        (void)hipFree(c->lane_part[k]);
+        if (c->lane_stream[k]) (void)hipStreamDestroy(c->lane_stream[k]);
+    }
+    for (int k = 0; k < snk_ctx::kLanes; ++k) {
+        if (c->lane_ev[k]) (void)hipEventDestroy(c->lane_ev[k]);
+        if (c->lane_red[k]) (void)hipEventDestroy(c->lane_red[k]);
+    }
+    if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
     (void)hipFree(c->d_fflag);
     (void)hipFree(c->d_frows);
     (void)hipFree(c->d_fcount);
@@ -1174,7 +1198,28 @@ int snk_ctx_create(const snk_basis* basis, const snk_grid* grid, const double* w
             for (int k = 0; k < ncart(c->sl[sh]); ++k) fs[c->sfn[sh] + k] = sh;
         CREATE_CHECK(upload(c, &c->d_fn_shell, fs));
     }
-    if (c->row_restrict || c->frow_restrict) CREATE_CHECK(dalloc(c, &c->d_Gc, (size_t)nbf * c->max_tile_cols));
+    if (c->row_restrict || c->frow_restrict) {
+        CREATE_CHECK(dalloc(c, &c->d_Gc, (size_t)nbf * c->max_tile_cols));
+        // tiles are small: their GEMMs run on several streams (default priority) at once
+        c->nlanes = snk_ctx::kLanes;
+        c->lane_Pg[0] = c->d_Pg;
+        c->lane_Gc[0] = c->d_Gc;
+        c->lane_part[0] = c->d_part;
+        CREATE_CHECK(hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming) == hipSuccess ? SNK_OK : SNK_E_DEVICE);
+        for (int k = 0; k < c->nlanes; ++k) {
+            CREATE_CHECK(hipEventCreateWithFlags(&c->lane_ev[k], hipEventDisableTiming) == hipSuccess ? SNK_OK
+                                                                                                       : SNK_E_DEVICE);
+            CREATE_CHECK(hipEventCreateWithFlags(&c->lane_red[k], hipEventDisableTiming) == hipSuccess ? SNK_OK
+                                                                                                        : SNK_E_DEVICE);
+            if (k == 0) continue;
+            CREATE_CHECK(hipStreamCreateWithFlags(&c->lane_stream[k], hipStreamNonBlocking) == hipSuccess
+                             ? SNK_OK
+                             : SNK_E_DEVICE);
+            CREATE_CHECK(dalloc(c, &c->lane_Pg[k], (size_t)nbf * std::max<int32_t>(1, c->max_nB)));
+            CREATE_CHECK(dalloc(c, &c->lane_Gc[k], (size_t)nbf * c->max_tile_cols));
+            CREATE_CHECK(dalloc(c, &c->lane_part[k], (size_t)c->part_elems));
+        }
+    }
     if ((o.flags & SNK_ROCBLAS) && !c->mixed && c->max_cols <= INT32_MAX && (int64_t)c->nbf <= INT32_MAX) {
         if (rocblas_create_handle(&c->blas) != rocblas_status_success ||
             rocblas_set_stream(c->blas, c->stream) != rocblas_status_success ||
@@ -1183,6 +1228,16 @@ int snk_ctx_create(const snk_basis* basis, const snk_grid* grid, const double* w
             g_last_error = c->err;
             free_ctx(c);
             return SNK_E_DEVICE;
+        }
+        for (int k = 1; k < c->nlanes; ++k) {
+            if (rocblas_create_handle(&c->lane_blas[k]) != rocblas_status_success ||
+                rocblas_set_stream(c->lane_blas[k], c->lane_stream[k]) != rocblas_status_success ||
+                rocblas_set_atomics_mode(c->lane_blas[k], rocblas_atomics_not_allowed) != rocblas_status_success) {
+                set_err(c, "rocBLAS handle set-up failed");
+                g_last_error = c->err;
+                free_ctx(c);
+                return SNK_E_DEVICE;
+            }
         }
     }
 #undef CREATE_CHECK
@@ -1209,6 +1264,9 @@ struct GroupStats {
     int64_t low = 0;                        // units evaluated in FP32
     double skipped = 0.0;                   // bound on the energy of the skipped blocks
 };
+
+int tile_F(snk_ctx* c, const Group& g, int ti, const double* dP, hipStream_t s, int k);
+int tile_K(snk_ctx* c, const Group& g, int ti, bool restrict_rows, hipStream_t ls, int k);
 
 // Steps of one batch group up to G: Eq. collocation, Eq. fmat, the screen (when enabled),
 // Eqs. 3c_grid + gmat.
@@ -1252,8 +1310,37 @@ int group_F(snk_ctx* c, const Group& g, const double* dP, bool timed)
         HIPCHECK(c, hipMemcpyAsync(c->tile_frows.data(), c->d_fcount, ntile * sizeof(int32_t), hipMemcpyDeviceToHost, s));
         HIPCHECK(c, hipStreamSynchronize(s));
     }
-    // Eq. fmat per tile: F[:, tile columns] = P[:, B_t] Phi_t
-    for (int ti = 0; ti < ntile; ++ti) {
+    // Eq. fmat per tile: F[:, tile columns] = P[:, B_t] Phi_t.  Tiles write disjoint columns,
+    // so their products run on all lanes at once (tile ti on lane ti mod nlanes).
+    const bool par = c->nlanes > 1 && ntile > 1;
+    if (par) {
+        HIPCHECK(c, hipEventRecord(c->fork_ev, s));
+        for (int k = 1; k < c->nlanes; ++k) HIPCHECK(c, hipStreamWaitEvent(c->lane_stream[k], c->fork_ev, 0));
+    }
+    int rc = SNK_OK;
+    for (int ti = 0; ti < ntile && rc == SNK_OK; ++ti) {
+        const int k = par ? ti % c->nlanes : 0;
+        rc = tile_F(c, g, ti, dP, k ? c->lane_stream[k] : s, k);
+    }
+    if (par) {
+        for (int k = 1; k < c->nlanes; ++k) {
+            HIPCHECK(c, hipEventRecord(c->lane_ev[k], c->lane_stream[k]));
+            HIPCHECK(c, hipStreamWaitEvent(s, c->lane_ev[k], 0));
+        }
+    }
+    if (rc) return rc;
+    if (timed) HIPCHECK(c, hipEventRecord(c->ev[2], s));
+    return SNK_OK;
+}
+
+// Eq. fmat for tile ti of group g on stream s with the buffers of lane k (lane 0: the
+// context's own buffers; only the restricted-row path runs on other lanes)
+int tile_F(snk_ctx* c, const Group& g, int ti, const double* dP, hipStream_t s, int k)
+{
+    const int64_t nbf = c->nbf;
+    const int64_t ld = g.ncols;
+    rocblas_handle blas = k ? c->lane_blas[k] : c->blas;   // bound to stream s
+    {
         const Tile& t = g.tiles[ti];
         const int64_t L = c->frow_restrict ? c->tile_frows[ti] : nbf;
         c->acc_fn += (double)t.nB * t.ncols;
@@ -1263,7 +1350,7 @@ int group_F(snk_ctx* c, const Group& g, const double* dP, bool timed)
             // no function reaches the tile's points, or no row of F does
             if (c->mixed) HIPCHECK(c, launch_fill2d(c->d_F32 + t.col0, nbf, t.ncols, ld, 0.0f, s));
             else HIPCHECK(c, launch_fill2d(c->d_F + t.col0, nbf, t.ncols, ld, 0.0, s));
-            continue;
+            return SNK_OK;
         }
         if (c->frow_restrict && L < nbf) {
             // F_c = P[L_t, B_t] Phi_t, then rows L_t of the tile's columns.  The other rows are
@@ -1273,32 +1360,34 @@ int group_F(snk_ctx* c, const Group& g, const double* dP, bool timed)
             const bool zero_rows = c->opts.screen == SNK_SCREEN_NONE || c->zero_f_rows;
             const int32_t* rows = c->d_frows + (int64_t)ti * nbf;
             if (c->mixed) {
-                float* Fc = reinterpret_cast<float*>(c->d_Gc);
-                HIPCHECK(c, launch_gather(dP, nbf, rows, L, t.d_coll_fn, t.nB, c->d_Pg32, s));
-                HIPCHECK(c, launch_gemm_f32(L, t.ncols, t.nB, c->d_Pg32, t.nB, c->d_Phi32 + t.phi_off, t.ncols, false,
+                float* Fc = reinterpret_cast<float*>(c->lane_Gc[k]);
+                float* Pc = reinterpret_cast<float*>(c->lane_Pg[k]);
+                HIPCHECK(c, launch_gather(dP, nbf, rows, L, t.d_coll_fn, t.nB, Pc, s));
+                HIPCHECK(c, launch_gemm_f32(L, t.ncols, t.nB, Pc, t.nB, c->d_Phi32 + t.phi_off, t.ncols, false,
                                             Fc, t.ncols, 1, 0, s));
                 if (zero_rows) HIPCHECK(c, launch_fill2d(c->d_F32 + t.col0, nbf, t.ncols, ld, 0.0f, s));
                 HIPCHECK(c, launch_scatter_rows(Fc, L, t.ncols, rows, c->d_F32 + t.col0, ld, s));
-                continue;
+                return SNK_OK;
             }
-            HIPCHECK(c, launch_gather(dP, nbf, rows, L, t.d_coll_fn, t.nB, c->d_Pg, s));
-            if (c->blas) {
+            double* Pc = c->lane_Pg[k];
+            double* Fc = c->lane_Gc[k];
+            HIPCHECK(c, launch_gather(dP, nbf, rows, L, t.d_coll_fn, t.nB, Pc, s));
+            if (blas) {
                 // column-major view: F_c^T (ncols_t x L) = Phi_t^T (ncols_t x nB) P_c^T (nB x L)
                 const double one = 1.0, zero = 0.0;
-                if (rocblas_dgemm(c->blas, rocblas_operation_none, rocblas_operation_none, (rocblas_int)t.ncols,
+                if (rocblas_dgemm(blas, rocblas_operation_none, rocblas_operation_none, (rocblas_int)t.ncols,
                                   (rocblas_int)L, (rocblas_int)t.nB, &one, c->d_Phi + t.phi_off, (rocblas_int)t.ncols,
-                                  c->d_Pg, (rocblas_int)t.nB, &zero, c->d_Gc, (rocblas_int)t.ncols) !=
-                    rocblas_status_success) {
+                                  Pc, (rocblas_int)t.nB, &zero, Fc, (rocblas_int)t.ncols) != rocblas_status_success) {
                     set_err(c, "rocblas_dgemm (F) failed");
                     return SNK_E_DEVICE;
                 }
             } else {
-                HIPCHECK(c, launch_gemm_f64(L, t.ncols, t.nB, c->d_Pg, t.nB, c->d_Phi + t.phi_off, t.ncols, false,
-                                            c->d_Gc, t.ncols, 1, 0, s));
+                HIPCHECK(c, launch_gemm_f64(L, t.ncols, t.nB, Pc, t.nB, c->d_Phi + t.phi_off, t.ncols, false, Fc,
+                                            t.ncols, 1, 0, s));
             }
             if (zero_rows) HIPCHECK(c, launch_fill2d(c->d_F + t.col0, nbf, t.ncols, ld, 0.0, s));
-            HIPCHECK(c, launch_scatter_rows(c->d_Gc, L, t.ncols, rows, c->d_F + t.col0, ld, s));
-            continue;
+            HIPCHECK(c, launch_scatter_rows(Fc, L, t.ncols, rows, c->d_F + t.col0, ld, s));
+            return SNK_OK;
         }
         if (c->mixed) {
             // FP32 Phi and F; P was rounded to FP32 once per build (d_P32), or is gathered to
@@ -1306,25 +1395,27 @@ int group_F(snk_ctx* c, const Group& g, const double* dP, bool timed)
             const float* Pg = c->d_P32;
             int64_t ldp = nbf;
             if (!t.all_functions) {
-                HIPCHECK(c, launch_gather(dP, nbf, nullptr, nbf, t.d_coll_fn, t.nB, c->d_Pg32, s));
-                Pg = c->d_Pg32;
+                float* Pb = k ? reinterpret_cast<float*>(c->lane_Pg[k]) : c->d_Pg32;
+                HIPCHECK(c, launch_gather(dP, nbf, nullptr, nbf, t.d_coll_fn, t.nB, Pb, s));
+                Pg = Pb;
                 ldp = t.nB;
             }
             HIPCHECK(c, launch_gemm_f32(nbf, t.ncols, t.nB, Pg, ldp, c->d_Phi32 + t.phi_off, t.ncols, false,
                                         c->d_F32 + t.col0, ld, 1, 0, s));
-            continue;
+            return SNK_OK;
         }
         const double* Pg = dP;
         int64_t ldp = nbf;
         if (!t.all_functions) {
-            HIPCHECK(c, launch_gather(dP, nbf, nullptr, nbf, t.d_coll_fn, t.nB, c->d_Pg, s));
-            Pg = c->d_Pg;
+            double* Pb = k ? c->lane_Pg[k] : c->d_Pg;
+            HIPCHECK(c, launch_gather(dP, nbf, nullptr, nbf, t.d_coll_fn, t.nB, Pb, s));
+            Pg = Pb;
             ldp = t.nB;
         }
-        if (c->blas) {
+        if (blas) {
             // column-major view: F^T (ncols_t x nbf) = Phi_t^T (ncols_t x nB) P_t^T (nB x nbf)
             const double one = 1.0, zero = 0.0;
-            if (rocblas_dgemm(c->blas, rocblas_operation_none, rocblas_operation_none, (rocblas_int)t.ncols,
+            if (rocblas_dgemm(blas, rocblas_operation_none, rocblas_operation_none, (rocblas_int)t.ncols,
                               (rocblas_int)nbf, (rocblas_int)t.nB, &one, c->d_Phi + t.phi_off, (rocblas_int)t.ncols,
                               Pg, (rocblas_int)ldp, &zero, c->d_F + t.col0, (rocblas_int)ld) != rocblas_status_success) {
                 set_err(c, "rocblas_dgemm (F) failed");
@@ -1335,7 +1426,6 @@ int group_F(snk_ctx* c, const Group& g, const double* dP, bool timed)
                                         c->d_F + t.col0, ld, 1, 0, s));
         }
     }
-    if (timed) HIPCHECK(c, hipEventRecord(c->ev[2], s));
     return SNK_OK;
 }
 
@@ -1347,9 +1437,40 @@ int group_K(snk_ctx* c, const Group& g)
     const int64_t nbf = c->nbf;
     const int64_t ld = g.ncols;
     const bool restrict_rows = c->row_restrict && c->tile_rows.size() == g.tiles.size();
-    for (size_t ti = 0; ti < g.tiles.size(); ++ti) {
+    // tile products on all lanes at once; the reductions into Kt stay on the context's stream
+    // in tile order (fixed summation order), each after its product, and a lane reuses its
+    // partial-sum buffer only after the reduction that read it
+    const bool par = c->nlanes > 1 && g.tiles.size() > 1;
+    if (par) {
+        HIPCHECK(c, hipEventRecord(c->fork_ev, s));
+        for (int k = 1; k < c->nlanes; ++k) {
+            HIPCHECK(c, hipStreamWaitEvent(c->lane_stream[k], c->fork_ev, 0));
+            HIPCHECK(c, hipEventRecord(c->lane_red[k], s));
+        }
+    }
+    int rc = SNK_OK;
+    for (size_t ti = 0; ti < g.tiles.size() && rc == SNK_OK; ++ti) {
+        const int k = par ? (int)(ti % c->nlanes) : 0;
+        const hipStream_t ls = k ? c->lane_stream[k] : s;
+        if (k) HIPCHECK(c, hipStreamWaitEvent(ls, c->lane_red[k], 0));
+        rc = tile_K(c, g, (int)ti, restrict_rows, ls, k);
+        if (rc == SNK_OK && k) HIPCHECK(c, hipEventRecord(c->lane_red[k], s));
+    }
+    return rc;
+}
+
+// Eq. usym_k for tile ti: the product on stream ls with lane k's buffers, the reduction into Kt
+// on the context's stream after it
+int tile_K(snk_ctx* c, const Group& g, int ti, bool restrict_rows, hipStream_t ls, int k)
+{
+    hipStream_t s = c->stream;
+    const int64_t nbf = c->nbf;
+    const int64_t ld = g.ncols;
+    double* part = k ? c->lane_part[k] : c->d_part;
+    rocblas_handle blas = k ? c->lane_blas[k] : c->blas;   // bound to stream ls
+    {
         const Tile& t = g.tiles[ti];
-        if (t.nB == 0) continue;   // nothing collocated: G Phi_t^T is empty
+        if (t.nB == 0) return SNK_OK;   // nothing collocated: G Phi_t^T is empty
         // rows of G the tile's kept blocks touch (all others are zero on the tile's columns)
         int64_t M = nbf;
         const double* Gt = c->d_G + t.col0;
@@ -1358,10 +1479,11 @@ int group_K(snk_ctx* c, const Group& g)
         if (restrict_rows) {
             M = c->tile_rows[ti];
             c->acc_grows += (double)M * t.ncols;
-            if (M == 0) continue;
+            if (M == 0) return SNK_OK;
             rows = c->d_trows + (int64_t)ti * nbf;
-            HIPCHECK(c, launch_gather(Gt, ld, rows, M, nullptr, t.ncols, c->d_Gc, s));
-            Gt = c->d_Gc;
+            double* Gc = k ? c->lane_Gc[k] : c->d_Gc;
+            HIPCHECK(c, launch_gather(Gt, ld, rows, M, nullptr, t.ncols, Gc, ls));
+            Gt = Gc;
             ldg = t.ncols;
         }
         const int64_t stride = M * t.nB;
@@ -1373,7 +1495,7 @@ int group_K(snk_ctx* c, const Group& g)
         ns = std::min<int64_t>(ns, c->part_elems / std::max<int64_t>(1, stride));
         ns = std::max<int64_t>(1, std::min<int64_t>(ns, std::min<int64_t>(256, t.b1 - t.b0)));
         const int nsplit = (int)ns;
-        if (c->blas) {
+        if (blas) {
             // split over whole batches of points; column-major view of chunk z:
             // part_z^T (nB x M) = Phi_z (nB x kchunk) G_z^T (kchunk x M), i.e. part_z = G_z Phi_z^T
             const double* Phi = c->d_Phi + t.phi_off;
@@ -1385,29 +1507,36 @@ int group_K(snk_ctx* c, const Group& g)
             const double one = 1.0, zero = 0.0;
             rocblas_status st = rocblas_status_success;
             if (nfull > 0)
-                st = rocblas_dgemm_strided_batched(c->blas, rocblas_operation_transpose, rocblas_operation_none,
+                st = rocblas_dgemm_strided_batched(blas, rocblas_operation_transpose, rocblas_operation_none,
                                                    (rocblas_int)t.nB, (rocblas_int)M, (rocblas_int)kchunk, &one, Phi,
                                                    (rocblas_int)t.ncols, kchunk, G, (rocblas_int)ldg, kchunk, &zero,
-                                                   c->d_part, (rocblas_int)t.nB, stride, nfull);
+                                                   part, (rocblas_int)t.nB, stride, nfull);
             if (st == rocblas_status_success && rem > 0)
-                st = rocblas_dgemm(c->blas, rocblas_operation_transpose, rocblas_operation_none, (rocblas_int)t.nB,
+                st = rocblas_dgemm(blas, rocblas_operation_transpose, rocblas_operation_none, (rocblas_int)t.nB,
                                    (rocblas_int)M, (rocblas_int)(rem * kBatch), &one, Phi + nfull * kchunk,
                                    (rocblas_int)t.ncols, G + nfull * kchunk, (rocblas_int)ldg, &zero,
-                                   c->d_part + nfull * stride, (rocblas_int)t.nB);
+                                   part + nfull * stride, (rocblas_int)t.nB);
             if (st != rocblas_status_success) {
                 set_err(c, "rocblas_dgemm (K) failed");
                 return SNK_E_DEVICE;
             }
-            HIPCHECK(c, launch_reduce_scatter(c->d_part, nfull + (rem > 0), stride, M, t.nB, rows, cols, c->d_Kt,
-                                              nbf, s));
+            if (k) {
+                HIPCHECK(c, hipEventRecord(c->lane_ev[k], ls));
+                HIPCHECK(c, hipStreamWaitEvent(s, c->lane_ev[k], 0));
+            }
+            HIPCHECK(c, launch_reduce_scatter(part, nfull + (rem > 0), stride, M, t.nB, rows, cols, c->d_Kt, nbf, s));
         } else {
             if (c->mixed)
-                HIPCHECK(c, launch_gemm_f32_dA(M, t.nB, t.ncols, Gt, ldg, c->d_Phi32 + t.phi_off, t.ncols, true,
-                                               c->d_part, t.nB, nsplit, stride, s));
+                HIPCHECK(c, launch_gemm_f32_dA(M, t.nB, t.ncols, Gt, ldg, c->d_Phi32 + t.phi_off, t.ncols, true, part,
+                                               t.nB, nsplit, stride, ls));
             else
-                HIPCHECK(c, launch_gemm_f64(M, t.nB, t.ncols, Gt, ldg, c->d_Phi + t.phi_off, t.ncols, true, c->d_part,
-                                            t.nB, nsplit, stride, s));
-            HIPCHECK(c, launch_reduce_scatter(c->d_part, nsplit, stride, M, t.nB, rows, cols, c->d_Kt, nbf, s));
+                HIPCHECK(c, launch_gemm_f64(M, t.nB, t.ncols, Gt, ldg, c->d_Phi + t.phi_off, t.ncols, true, part,
+                                            t.nB, nsplit, stride, ls));
+            if (k) {
+                HIPCHECK(c, hipEventRecord(c->lane_ev[k], ls));
+                HIPCHECK(c, hipStreamWaitEvent(s, c->lane_ev[k], 0));
+            }
+            HIPCHECK(c, launch_reduce_scatter(part, nsplit, stride, M, t.nB, rows, cols, c->d_Kt, nbf, s));
         }
     }
     return SNK_OK;

@@ -147,7 +147,10 @@ def test_learned_screen_with_basis_screen():
     s = synth.make_system(2)
     K0, st0 = snk.sn_k_build(s, eps_basis=1e-9, flags=snk.SNK_ROCBLAS)
     for flags in (snk.SNK_ROCBLAS, 0):
-        K1, st1 = snk.sn_k_build(s, eps_basis=1e-9, screen=snk.SNK_SCREEN_LEARNED, screener=m, flags=flags)
+        ctx = snk.Context(s, eps_basis=1e-9, screen=snk.SNK_SCREEN_LEARNED, screener=m, flags=flags)
+        K1, st1 = ctx.build(s.P)
+        K2, _ = ctx.build(s.P)
+        assert np.array_equal(K1, K2)   # tile products run on several streams; reductions stay ordered
         dE = abs(st1["ex"] - st0["ex"])
         skipped = st1["pair_points_skipped"] / max(1, st1["pair_points_skipped"] + sum(st1["pair_points"]))
         say("config2 learned + eps_basis 1e-9 (flags %d): skipped %.3f |dE| %.2e max|dK| %.2e, kgemm %.2f ms "
