@@ -131,6 +131,19 @@ __global__ __launch_bounds__(256) void gemm_kernel(int64_t M, int64_t N, int64_t
             }
 }
 
+// Row-wise element kernels: blockIdx.y strides the rows, the x blocks of 256 threads stride a
+// row's columns (no integer division per element).
+#define SNK_ROWS(m, M) for (int64_t m = blockIdx.y; m < (M); m += gridDim.y)
+#define SNK_COLS(n, N) \
+    for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < (N); n += (int64_t)gridDim.x * blockDim.x)
+
+dim3 rows_grid(int64_t rows, int64_t cols)
+{
+    const int64_t gx = std::min<int64_t>(std::max<int64_t>(1, (cols + 255) / 256), 16);
+    const int64_t gy = std::min<int64_t>(std::max<int64_t>(1, rows), 65535);
+    return dim3((unsigned)gx, (unsigned)gy);
+}
+
 template <typename TP>
 __global__ __launch_bounds__(256) void reduce_scatter_kernel(const TP* __restrict__ part, int nsplit,
                                                              int64_t stride, int64_t M, int64_t N,
@@ -138,14 +151,17 @@ __global__ __launch_bounds__(256) void reduce_scatter_kernel(const TP* __restric
                                                              const int32_t* __restrict__ cols,
                                                              double* __restrict__ Kt, int64_t nbf)
 {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= M * N) return;
-    const int64_t m = idx / N, n = idx - m * N;
-    double s = 0.0;
-    for (int z = 0; z < nsplit; ++z) s += (double)part[z * stride + idx];
-    const int64_t r = rows ? rows[m] : m;
-    const int64_t c = cols ? cols[n] : n;
-    Kt[r * nbf + c] += s;
+    SNK_ROWS(m, M)
+    {
+        double* krow = Kt + (int64_t)(rows ? rows[m] : m) * nbf;
+        SNK_COLS(n, N)
+        {
+            const int64_t idx = m * N + n;
+            double s = 0.0;
+            for (int z = 0; z < nsplit; ++z) s += (double)part[z * stride + idx];
+            krow[cols ? cols[n] : n] += s;
+        }
+    }
 }
 
 template <typename T>
@@ -159,10 +175,9 @@ __global__ __launch_bounds__(256) void fill_kernel(T* __restrict__ p, int64_t n,
 template <typename T>
 __global__ __launch_bounds__(256) void fill2d_kernel(T* __restrict__ p, int64_t rows, int64_t cols, int64_t ld, T v)
 {
-    const int64_t n = rows * cols;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t r = i / cols;
-        p[r * ld + (i - r * cols)] = v;
+    SNK_ROWS(r, rows)
+    {
+        SNK_COLS(c, cols) p[r * ld + c] = v;
     }
 }
 
@@ -215,12 +230,12 @@ __global__ __launch_bounds__(256) void gather_kernel(const double* __restrict__ 
                                                      const int32_t* __restrict__ cols, int64_t N,
                                                      TO* __restrict__ out)
 {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= M * N) return;
-    const int64_t m = idx / N, n = idx - m * N;
-    const int64_t r = rows ? rows[m] : m;
-    const int64_t c = cols ? cols[n] : n;
-    out[idx] = (TO)P[r * nbf + c];
+    SNK_ROWS(m, M)
+    {
+        const double* src = P + (int64_t)(rows ? rows[m] : m) * nbf;
+        TO* dst = out + m * N;
+        SNK_COLS(n, N) dst[n] = (TO)src[cols ? cols[n] : n];
+    }
 }
 
 // out[rows[m] * ld + c] = in[m * ncols + c]
@@ -229,10 +244,11 @@ __global__ __launch_bounds__(256) void scatter_rows_kernel(const T* __restrict__
                                                            const int32_t* __restrict__ rows, T* __restrict__ out,
                                                            int64_t ld)
 {
-    const int64_t n = M * ncols;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t m = i / ncols;
-        out[(int64_t)rows[m] * ld + (i - m * ncols)] = in[i];
+    SNK_ROWS(m, M)
+    {
+        const T* src = in + m * ncols;
+        T* dst = out + (int64_t)rows[m] * ld;
+        SNK_COLS(c, ncols) dst[c] = src[c];
     }
 }
 
@@ -241,10 +257,10 @@ __global__ __launch_bounds__(256) void fill_rows_kernel(double* __restrict__ p, 
                                                         const int32_t* __restrict__ rows, int64_t M, int64_t ncols,
                                                         double v)
 {
-    const int64_t n = M * ncols;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t m = i / ncols;
-        p[(int64_t)rows[m] * ld + (i - m * ncols)] = v;
+    SNK_ROWS(m, M)
+    {
+        double* dst = p + (int64_t)rows[m] * ld;
+        SNK_COLS(c, ncols) dst[c] = v;
     }
 }
 
@@ -343,9 +359,8 @@ hipError_t launch_reduce_scatter_t(const TP* part, int nsplit, int64_t stride, i
                                    const int32_t* rows, const int32_t* cols, double* Kt, int64_t nbf, hipStream_t s)
 {
     if (M <= 0 || N <= 0) return hipSuccess;
-    const int64_t n = M * N;
-    hipLaunchKernelGGL((reduce_scatter_kernel<TP>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part, nsplit,
-                       stride, M, N, rows, cols, Kt, nbf);
+    hipLaunchKernelGGL((reduce_scatter_kernel<TP>), rows_grid(M, N), dim3(256), 0, s, part, nsplit, stride, M, N, rows,
+                       cols, Kt, nbf);
     return hipGetLastError();
 }
 
@@ -398,9 +413,7 @@ template <typename T>
 static hipError_t launch_fill2d_t(T* p, int64_t rows, int64_t cols, int64_t ld, T v, hipStream_t s)
 {
     if (rows <= 0 || cols <= 0) return hipSuccess;
-    int64_t blocks = (rows * cols + 255) / 256;
-    if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL((fill2d_kernel<T>), dim3((unsigned)blocks), dim3(256), 0, s, p, rows, cols, ld, v);
+    hipLaunchKernelGGL((fill2d_kernel<T>), rows_grid(rows, cols), dim3(256), 0, s, p, rows, cols, ld, v);
     return hipGetLastError();
 }
 
@@ -445,9 +458,7 @@ static hipError_t launch_gather_t(const double* P, int64_t nbf, const int32_t* r
                                   int64_t N, TO* out, hipStream_t s)
 {
     if (M <= 0 || N <= 0) return hipSuccess;
-    const int64_t n = M * N;
-    hipLaunchKernelGGL((gather_kernel<TO>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, P, nbf, rows, M, cols,
-                       N, out);
+    hipLaunchKernelGGL((gather_kernel<TO>), rows_grid(M, N), dim3(256), 0, s, P, nbf, rows, M, cols, N, out);
     return hipGetLastError();
 }
 
@@ -456,9 +467,7 @@ static hipError_t launch_scatter_rows_t(const T* in, int64_t M, int64_t ncols, c
                                        hipStream_t s)
 {
     if (M <= 0 || ncols <= 0) return hipSuccess;
-    int64_t blocks = (M * ncols + 255) / 256;
-    if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL((scatter_rows_kernel<T>), dim3((unsigned)blocks), dim3(256), 0, s, in, M, ncols, rows, out, ld);
+    hipLaunchKernelGGL((scatter_rows_kernel<T>), rows_grid(M, ncols), dim3(256), 0, s, in, M, ncols, rows, out, ld);
     return hipGetLastError();
 }
 
@@ -479,9 +488,7 @@ hipError_t launch_fill_rows(double* p, int64_t ld, const int32_t* rows, int64_t 
 {
     if (M <= 0 || ncols <= 0) return hipSuccess;
     if (!p || !rows) return hipErrorInvalidValue;
-    int64_t blocks = (M * ncols + 255) / 256;
-    if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(fill_rows_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, ld, rows, M, ncols, v);
+    hipLaunchKernelGGL(fill_rows_kernel, rows_grid(M, ncols), dim3(256), 0, s, p, ld, rows, M, ncols, v);
     return hipGetLastError();
 }
 
