@@ -230,6 +230,9 @@ int snk_shell_rcut(int l, const double* exps, const double* coefs, int nprim, do
  *   inputs and activations to bfloat16 and accumulates in FP32 (inference form).
  * snk_mlp_loss_grad: loss (1/n) sum_s c_s (y_s - t_s)^2, c_s = `under` if y_s < t_s else 1,
  *   and its gradient; grads is a device buffer of nparams + 1 floats (gradient, then loss).
+ * snk_mlp_backward: the gradient of sum_s dy[s] y[s] with respect to the parameters for a
+ *   given upstream gradient dy[n] (device), into grads (nparams + 1 floats, the last 0): the
+ *   plain backward pass of the FP32 network.
  * snk_mlp_adam_step: one Adam update (beta 0.9 / 0.999, eps 1e-8) at step t >= 1.
  */
 int snk_mlp_nparams(void);
@@ -242,6 +245,7 @@ int snk_mlp_set_range(snk_mlp* mlp, const float* lo, const float* hi, float marg
 int snk_mlp_forward(const snk_mlp* mlp, const float* x, int64_t n, float* y, int bf16, void* stream);
 int snk_mlp_loss_grad(snk_mlp* mlp, const float* x, const float* target, int64_t n, float under, float* grads,
                       void* stream);
+int snk_mlp_backward(snk_mlp* mlp, const float* x, const float* dy, int64_t n, float* grads, void* stream);
 int snk_mlp_adam_step(snk_mlp* mlp, const float* grads, float lr, int t, void* stream);
 
 /*
@@ -265,6 +269,16 @@ int snk_mlp_adam_step(snk_mlp* mlp, const float* grads, float lr, int t, void* s
  */
 int64_t snk_ctx_nblock_pairs(const snk_ctx* ctx);
 int snk_ctx_block_data(snk_ctx* ctx, const double* P, float* features, double* block_energy, int32_t* pair_shells);
+
+/*
+ * snk_collect_block_norms: the training samples of one density in one call: for every block
+ * (batch-major, as above) its 16 features feats[k * 16 + f] and the target log10 t
+ * (target[k], -40 where t <= 1e-40), both FP32 device memory of capacity `cap` blocks.
+ * *n_out receives the number of blocks, nbatches * snk_ctx_nblock_pairs; SNK_E_ARG (nothing
+ * written) when cap is smaller.
+ */
+int snk_collect_block_norms(snk_ctx* ctx, const double* P, float* feats, float* target, int64_t cap,
+                            int64_t* n_out);
 
 /*
  * Test hooks (diagnostics; not needed for building K).

@@ -64,7 +64,8 @@ __global__ __launch_bounds__(256) void mlp_fwd_kernel(const float* __restrict__ 
 constexpr int GS = 64;
 __global__ __launch_bounds__(256) void mlp_grad_kernel(const float* __restrict__ params, MlpNorm nrm,
                                                        const float* __restrict__ x, const float* __restrict__ target,
-                                                       int64_t n, float under, float* __restrict__ part)
+                                                       const float* __restrict__ dyin, int64_t n, float under,
+                                                       float* __restrict__ part)
 {
     __shared__ float w[NP];
     __shared__ float sx[GS][IN];
@@ -102,11 +103,20 @@ __global__ __launch_bounds__(256) void mlp_grad_kernel(const float* __restrict__
             sh2[t][o] = h2;
             y = fmaf(w[OFF_W3 + o], h2, y);
         }
-        const float tg = live ? target[s] : 0.0f;
-        const float c = y < tg ? under : 1.0f;
-        const float dy = live ? 2.0f * c * (y - tg) / (float)n : 0.0f;
+        // loss mode: dy = d loss / d y of the asymmetric squared error; backward mode: dy given
+        float dy = 0.0f, l = 0.0f;
+        if (live) {
+            if (dyin) {
+                dy = dyin[s];
+            } else {
+                const float tg = target[s];
+                const float c = y < tg ? under : 1.0f;
+                dy = 2.0f * c * (y - tg) / (float)n;
+                l = c * (y - tg) * (y - tg) / (float)n;
+            }
+        }
         sdy[t] = dy;
-        sl[t] = live ? c * (y - tg) * (y - tg) / (float)n : 0.0f;
+        sl[t] = l;
         float d2[H];
         for (int o = 0; o < H; ++o) {
             d2[o] = dy * w[OFF_W3 + o] * dsilu(z2[o]);
@@ -190,12 +200,29 @@ hipError_t launch_mlp_forward(const float* params, const MlpNorm& nrm, const flo
 
 int64_t mlp_grad_blocks(int64_t n) { return (n + GS - 1) / GS; }
 
-hipError_t launch_mlp_grad(const float* params, const MlpNorm& nrm, const float* x, const float* target, int64_t n,
-                           float under, float* part, float* grads, hipStream_t s)
+namespace {
+__global__ __launch_bounds__(256) void log10_kernel(const double* __restrict__ in, int64_t n, float* __restrict__ out)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = in[i] > 1e-40 ? (float)log10(in[i]) : -40.0f;
+}
+}  // namespace
+
+hipError_t launch_log10(const double* in, int64_t n, float* out, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 65536);
+    hipLaunchKernelGGL(log10_kernel, dim3((unsigned)blocks), dim3(256), 0, s, in, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_grad(const float* params, const MlpNorm& nrm, const float* x, const float* target,
+                           const float* dy, int64_t n, float under, float* part, float* grads, hipStream_t s)
 {
     const int64_t nblk = mlp_grad_blocks(n);
     if (nblk <= 0) return hipSuccess;
-    hipLaunchKernelGGL(mlp_grad_kernel, dim3((unsigned)nblk), dim3(256), 0, s, params, nrm, x, target, n, under, part);
+    hipLaunchKernelGGL(mlp_grad_kernel, dim3((unsigned)nblk), dim3(256), 0, s, params, nrm, x, target, dy, n, under,
+                       part);
     hipLaunchKernelGGL(mlp_reduce_kernel, dim3((NP + 1 + 255) / 256), dim3(256), 0, s, part, (int)nblk, grads);
     return hipGetLastError();
 }

@@ -2039,6 +2039,30 @@ int snk_ctx_block_data(snk_ctx* c, const double* P, float* features, double* blo
     return SNK_OK;
 }
 
+int snk_collect_block_norms(snk_ctx* c, const double* P, float* feats, float* target, int64_t cap, int64_t* n_out)
+{
+    if (!c || !P || !feats || !target || !n_out) return arg_error(c, "NULL argument");
+    const int64_t n = (int64_t)c->nbatch * (int64_t)c->ne_list.size();
+    *n_out = n;
+    if (cap < n) return arg_error(c, "capacity smaller than the number of blocks");
+    if (n == 0) return SNK_OK;
+    HIPCHECK(c, hipSetDevice(c->device));
+    double* d_t = nullptr;
+    int rc = dalloc(c, &d_t, (size_t)n);
+    if (rc) return rc;
+    rc = snk_ctx_block_data(c, P, feats, d_t, nullptr);
+    if (!rc) {
+        hipError_t e = launch_log10(d_t, n, target, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) {
+            set_err(c, std::string("block norms: ") + hipGetErrorString(e));
+            rc = SNK_E_DEVICE;
+        }
+    }
+    (void)hipFree(d_t);
+    return rc;
+}
+
 int snk_ctx_debug_learned(snk_ctx* c, const double* P, float* yraw, float* est, int32_t* thr, int64_t* nbatch_out)
 {
     if (!c || !P) return arg_error(c, "NULL argument");

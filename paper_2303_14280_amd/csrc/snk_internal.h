@@ -201,8 +201,13 @@ struct EstArgs {
 hipError_t launch_mlp_forward(const float* params, const MlpNorm& nrm, const float* x, int64_t n, float* y, bool bf16,
                               hipStream_t s);
 int64_t mlp_grad_blocks(int64_t n);
-hipError_t launch_mlp_grad(const float* params, const MlpNorm& nrm, const float* x, const float* target, int64_t n,
-                           float under, float* part, float* grads, hipStream_t s);
+// gradients of the loss (dy == nullptr: asymmetric squared error against target) or of
+// sum_s dy[s] y[s] (dy given, target unused) with respect to the parameters; grads[kMlpParams]
+// holds the loss (0 in the second form)
+hipError_t launch_mlp_grad(const float* params, const MlpNorm& nrm, const float* x, const float* target,
+                           const float* dy, int64_t n, float under, float* part, float* grads, hipStream_t s);
+// out[k] = log10(in[k]) for in[k] > 1e-40, else -40
+hipError_t launch_log10(const double* in, int64_t n, float* out, hipStream_t s);
 hipError_t launch_mlp_adam(float* params, float* m, float* v, const float* g, float lr, int t, hipStream_t s);
 hipError_t launch_diag_bound(int l, const double* px, const double* py, const double* pz, const double* pw,
                              const double* F, const float* F32, int64_t ld, const PrimPair32* prims, const int32_t* dsh,

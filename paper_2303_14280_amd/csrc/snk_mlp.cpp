@@ -130,6 +130,34 @@ int snk_mlp_forward(const snk_mlp* m, const float* x, int64_t n, float* y, int b
                : SNK_E_DEVICE;
 }
 
+namespace {
+int ensure_part(snk_mlp* m, int64_t n)
+{
+    const int64_t nblk = mlp_grad_blocks(n);
+    if (nblk > m->part_cap) {
+        (void)hipFree(m->d_part);
+        m->d_part = nullptr;
+        if (hipMalloc((void**)&m->d_part, (size_t)nblk * (kMlpParams + 1) * sizeof(float)) != hipSuccess) {
+            m->part_cap = 0;
+            return SNK_E_NOMEM;
+        }
+        m->part_cap = nblk;
+    }
+    return SNK_OK;
+}
+}  // namespace
+
+int snk_mlp_backward(snk_mlp* m, const float* x, const float* dy, int64_t n, float* grads, void* stream)
+{
+    if (!m || n <= 0 || !x || !dy || !grads) return SNK_E_ARG;
+    const int rc = ensure_part(m, n);
+    if (rc) return rc;
+    return launch_mlp_grad(m->d_params, m->norm, x, nullptr, dy, n, 1.0f, m->d_part, grads, (hipStream_t)stream) ==
+                   hipSuccess
+               ? SNK_OK
+               : SNK_E_DEVICE;
+}
+
 int snk_mlp_loss_grad(snk_mlp* m, const float* x, const float* target, int64_t n, float under, float* grads,
                       void* stream)
 {
@@ -144,7 +172,7 @@ int snk_mlp_loss_grad(snk_mlp* m, const float* x, const float* target, int64_t n
         }
         m->part_cap = nblk;
     }
-    return launch_mlp_grad(m->d_params, m->norm, x, target, n, under, m->d_part, grads, (hipStream_t)stream) ==
+    return launch_mlp_grad(m->d_params, m->norm, x, target, nullptr, n, under, m->d_part, grads, (hipStream_t)stream) ==
                    hipSuccess
                ? SNK_OK
                : SNK_E_DEVICE;

@@ -105,6 +105,11 @@ def lib():
             L.snk_ctx_nbatches.restype = ctypes.c_int
             L.snk_ctx_ngroups.argtypes = [ctypes.c_void_p]
             L.snk_ctx_ngroups.restype = ctypes.c_int
+            L.snk_mlp_backward.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                           ctypes.c_void_p, ctypes.c_void_p]
+            L.snk_mlp_backward.restype = ctypes.c_int
+            L.snk_collect_block_norms.argtypes = [ctypes.c_void_p] * 4 + [ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
+            L.snk_collect_block_norms.restype = ctypes.c_int
             L.snk_shell_rcut.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_double,
                                          ctypes.POINTER(ctypes.c_double)]
             L.snk_shell_rcut.restype = ctypes.c_int
@@ -324,6 +329,18 @@ class Context:
     def npair_index(self) -> int:
         return int(lib().snk_ctx_npair_index(self.handle))
 
+    def collect_block_norms(self, P, feats_ptr: int, target_ptr: int, cap: int) -> int:
+        """Features and log10 targets of every block (snk_collect_block_norms); returns the count."""
+        if self.device_ptrs:
+            pp = ctypes.c_void_p(int(P))
+        else:
+            P = np.ascontiguousarray(P, np.float64)
+            pp = ctypes.c_void_p(P.ctypes.data)
+        n = ctypes.c_int64(0)
+        _check(lib().snk_collect_block_norms(self.handle, pp, ctypes.c_void_p(feats_ptr), ctypes.c_void_p(target_ptr),
+                                             int(cap), ctypes.byref(n)), self.handle)
+        return int(n.value)
+
     def block_data(self, P, features_ptr: int = 0, energy_ptr: int = 0) -> np.ndarray:
         """Training data of the learned screener (device outputs, see snk_ctx_block_data).
 
@@ -435,6 +452,10 @@ class Mlp:
         _check(lib().snk_mlp_loss_grad(self._h, ctypes.c_void_p(x_ptr), ctypes.c_void_p(t_ptr), int(n),
                                        float(under), ctypes.c_void_p(g_ptr),
                                        ctypes.c_void_p(stream) if stream else None))
+
+    def backward(self, x_ptr: int, dy_ptr: int, n: int, g_ptr: int, stream: int = 0) -> None:
+        _check(lib().snk_mlp_backward(self._h, ctypes.c_void_p(x_ptr), ctypes.c_void_p(dy_ptr), int(n),
+                                      ctypes.c_void_p(g_ptr), ctypes.c_void_p(stream) if stream else None))
 
     def adam_step(self, g_ptr: int, lr: float, t: int, stream: int = 0) -> None:
         _check(lib().snk_mlp_adam_step(self._h, ctypes.c_void_p(g_ptr), float(lr), int(t),

@@ -134,6 +134,19 @@ def test_block_data_matches_oracle_integrals():
         pref = 2 * np.pi / zp * np.exp(-ea[:, None] * eb[None, :] / zp * ab2) * np.abs(ca[:, None] * cb[None, :])
         assert abs(feat[0, k, 5] - np.log10(pref.sum())) <= 1e-4
 
+    # the one-call collection gives the same features and log10 of the same block magnitudes
+    import torch
+    n = nb * nk
+    f2 = torch.empty(n * 16, dtype=torch.float32, device="cuda")
+    t2 = torch.empty(n, dtype=torch.float32, device="cuda")
+    with pytest.raises(snk.SnkError):
+        ctx.collect_block_norms(s.P, f2.data_ptr(), t2.data_ptr(), n - 1)
+    assert ctx.collect_block_norms(s.P, f2.data_ptr(), t2.data_ptr(), n) == n
+    torch.cuda.synchronize()
+    assert np.array_equal(f2.cpu().numpy().reshape(nb, nk, 16), feat)
+    ref = np.where(t > 1e-40, np.log10(np.maximum(t, 1e-300)), -40.0).astype(np.float32)
+    assert np.max(np.abs(t2.cpu().numpy().reshape(nb, nk) - ref)) <= 1e-5
+
 
 def _random_network(seed, mean, std):
     m = snk.Mlp(0)

@@ -110,6 +110,26 @@ def test_loss_and_gradient_match_reference(n, under):
         off += sz
 
 
+@pytest.mark.parametrize("n", [64, 1000])
+def test_backward_matches_reference(n):
+    """snk_mlp_backward with a given upstream gradient dy >= 0 against the oracle's backward of
+    the loss with targets t = y - n dy / 2 (for which d loss / d y = dy exactly, y from the
+    FP64 reference forward)."""
+    import torch
+    m, flat, pf, X, Xn, t, dX, dt = _setup(n, 7)
+    y, cache = mlp_ref.forward(pf, Xn)
+    dy = np.random.default_rng(8).uniform(0.0, 1.0, size=n) / n
+    tt = y - n * dy / 2.0
+    ref = mlp_ref.flatten(mlp_ref.backward(pf, cache, y, tt, under=10.0))
+    ddy = torch.from_numpy(dy.astype(np.float32)).cuda()
+    g = torch.empty(m.nparams + 1, dtype=torch.float32, device="cuda")
+    m.backward(dX.data_ptr(), ddy.data_ptr(), n, g.data_ptr())
+    torch.cuda.synchronize()
+    gg = g.cpu().numpy().astype(np.float64)
+    assert gg[-1] == 0.0
+    assert np.linalg.norm(gg[:-1] - ref) <= 1e-4 * np.linalg.norm(ref)
+
+
 def test_adam_steps_match_reference():
     import torch
     n = 500
