@@ -54,6 +54,8 @@ def lib():
             L.orc_a3c.restype = None
             L.orc_snk.argtypes = basis + [ctypes.c_long, _D, _D, _D, _D, _D, ctypes.c_int]
             L.orc_snk.restype = ctypes.c_int
+            L.orc_snk_rows.argtypes = basis + [ctypes.c_long, _D, _D, _D, _I, ctypes.c_int, _D, ctypes.c_int]
+            L.orc_snk_rows.restype = ctypes.c_int
             L.orc_eri_shells.argtypes = basis + [ctypes.c_int] * 4 + [_D]
             L.orc_eri_shells.restype = None
             L.orc_eri_k.argtypes = basis + [_D, _D, ctypes.c_int]
@@ -128,6 +130,28 @@ def snk(s, P=None, xyz=None, w=None, nthreads: int = 0):
     if rc != 0:
         raise MemoryError("oracle sn-K failed")
     return K, float(ex[0]), float(ex[1])
+
+
+def snk_rows(s, rows, P=None, xyz=None, w=None, nthreads: int = 0) -> np.ndarray:
+    """Rows `rows` of the unsymmetrised sn-K matrix Kt = G Phi^T (len(rows) x nbf)."""
+    b = _Basis(s)
+    P = np.ascontiguousarray(s.P if P is None else P, np.float64)
+    xyz = np.ascontiguousarray(s.grid_xyz if xyz is None else xyz, np.float64).reshape(-1, 3)
+    w = np.ascontiguousarray(s.grid_w if w is None else w, np.float64)
+    r = np.ascontiguousarray(rows, np.int32)
+    assert P.shape == (b.nbf, b.nbf) and len(w) == len(xyz) and r.min() >= 0 and r.max() < b.nbf
+    out = np.zeros((len(r), b.nbf))
+    rc = lib().orc_snk_rows(*b.args(), len(w), _dp(xyz), _dp(w), _dp(P), _ip(r), len(r), _dp(out), int(nthreads))
+    if rc != 0:
+        raise MemoryError("oracle sn-K rows failed")
+    return out
+
+
+def k_block(s, rows, **kw) -> np.ndarray:
+    """K[rows][rows] = (Kt + Kt^T)/2 restricted to `rows` (Eq. sn_k), from snk_rows."""
+    Kt = snk_rows(s, rows, **kw)
+    sub = Kt[:, np.asarray(rows)]
+    return 0.5 * (sub + sub.T)
 
 
 def eri_shells(s, sa, sb, sc, sd) -> np.ndarray:

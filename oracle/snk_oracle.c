@@ -515,6 +515,86 @@ int orc_snk(int nshell, const double* center, const int* l, const int* nprim, co
     return 0;
 }
 
+/*
+ * Selected rows of the unsymmetrised sn-K matrix (Eqs. fmat, 3c_grid, gmat, usym_k):
+ *   Kt_rows[r][nu] = sum_i G_{mu_r i} Phi_{nu i},   G_{mu i} = w_i sum_lam A_{mu lam}(r_i) F_{lam i},
+ * for mu_r = rows[r], r < nrows (nrows x nbf, row-major, overwritten).  The same definition as
+ * orc_snk, restricted to the rows asked for, so that matrices too large for the full product
+ * can be sampled: K_{mu nu} = (Kt_{mu nu} + Kt_{nu mu}) / 2 for mu, nu both among the rows.
+ * Points are split into fixed chunks summed pairwise (thread-count independent).
+ */
+int orc_snk_rows(int nshell, const double* center, const int* l, const int* nprim, const int* prim_off,
+                 const double* exps, const double* coefs, long npts, const double* xyz, const double* w,
+                 const double* P, const int* rows, int nrows, double* Kt_rows, int nthreads)
+{
+    const int nbf = orc_nbf(nshell, l);
+    int* off = (int*)malloc(sizeof(int) * (size_t)(nshell + 1));
+    shell_offsets(nshell, l, off);
+    int* shell_of = (int*)malloc(sizeof(int) * (size_t)nbf);
+    for (int sh = 0; sh < nshell; ++sh)
+        for (int k = off[sh]; k < off[sh + 1]; ++k) shell_of[k] = sh;
+    /* the shell pairs (row shell, any shell) */
+    shell_pair* sps = (shell_pair*)malloc(sizeof(shell_pair) * (size_t)nrows * nshell);
+    for (int r = 0; r < nrows; ++r)
+        for (int sb = 0; sb < nshell; ++sb)
+            make_shell_pair(&sps[(size_t)r * nshell + sb], shell_of[rows[r]], sb, center, l, nprim, prim_off, exps,
+                            coefs);
+    const size_t nout = (size_t)nrows * nbf;
+    int nchunk = 64;
+    if (npts < nchunk) nchunk = npts > 0 ? (int)npts : 1;
+    double* part = (double*)calloc((size_t)nchunk * nout, sizeof(double));
+    if (!part) return 1;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+#pragma omp parallel
+    {
+        double* phi = (double*)malloc(sizeof(double) * (size_t)nbf);
+        double* f = (double*)malloc(sizeof(double) * (size_t)nbf);
+        double blk[36];
+#pragma omp for schedule(dynamic, 1)
+        for (int c = 0; c < nchunk; ++c) {
+            const long i0 = npts * c / nchunk, i1 = npts * (c + 1) / nchunk;
+            double* Kt = part + (size_t)c * nout;
+            for (long i = i0; i < i1; ++i) {
+                const double* rp = xyz + 3 * i;
+                collocate_point(nshell, center, l, nprim, prim_off, exps, coefs, rp, phi);
+                for (int lam = 0; lam < nbf; ++lam) {
+                    double s = 0.0;
+                    for (int nu = 0; nu < nbf; ++nu) s += P[(size_t)lam * nbf + nu] * phi[nu];
+                    f[lam] = s;
+                }
+                for (int r = 0; r < nrows; ++r) {
+                    const int mu = rows[r], sa = shell_of[mu], ia = mu - off[sa];
+                    double s = 0.0;
+                    for (int sb = 0; sb < nshell; ++sb) {
+                        const shell_pair* sp = &sps[(size_t)r * nshell + sb];
+                        const int nbb = ncart(sp->lb);
+                        a3c_block(sp, rp, blk);
+                        for (int ib = 0; ib < nbb; ++ib) s += blk[ia * nbb + ib] * f[off[sb] + ib];
+                    }
+                    const double g = w[i] * s;
+                    double* row = Kt + (size_t)r * nbf;
+                    for (int nu = 0; nu < nbf; ++nu) row[nu] += g * phi[nu];
+                }
+            }
+        }
+        free(phi); free(f);
+    }
+    for (int stride = 1; stride < nchunk; stride *= 2)
+        for (int c = 0; c + stride < nchunk; c += 2 * stride) {
+            double* dst = part + (size_t)c * nout;
+            const double* src = part + (size_t)(c + stride) * nout;
+            for (size_t k = 0; k < nout; ++k) dst[k] += src[k];
+        }
+    for (size_t k = 0; k < nout; ++k) Kt_rows[k] = part[k];
+    for (size_t k = 0; k < (size_t)nrows * nshell; ++k) free(sps[k].pp);
+    free(sps); free(part); free(off); free(shell_of);
+    return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* exact exchange from four-centre ERIs (Eq. full_k)                        */
 /* ------------------------------------------------------------------------ */

@@ -1,0 +1,64 @@
+"""Parity at the real shapes of the larger clusters, on sampled outputs.
+
+K is a sum over grid points, so the GPU build over a seeded subset of a configuration's grid
+points (every k-th point: thousands of points, every basis function) is compared exactly
+with the oracle over the same points.  The oracle cannot form the whole N_b x N_b product
+at these sizes; it computes the rows S of the unsymmetrised matrix (orc_snk_rows, pinned
+against the full oracle on small systems), which fix K[S][S] = (Kt + Kt^T)/2 on S x S for a
+seeded set S of functions of every angular momentum.
+
+* eps_basis = 0: the plain definition on both sides, |dK| <= 1e-11 max|K[S][S]| (rounding
+  order only, as in the full parity tests).
+* eps_basis = 1e-9, rocBLAS GEMMs (the launch configuration of the plain FP64 build of the
+  large clusters in bench.py): collocation values below 1e-9 and F rows whose bound is
+  below 1e-9 are dropped; the measured change of K[S][S] is printed and must stay below
+  1e-7 max|K[S][S]|.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2303_14280_amd import snk, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+CASES = [(3, 256), (4, 4096), (5, 8192)]
+
+
+def sample(cfg, stride):
+    s = synth.make_system(cfg)
+    off = int(np.random.default_rng([cfg, 77]).integers(stride))
+    sub = s.subset_points(np.arange(off, s.npts, stride))
+    rng = np.random.default_rng([cfg, 78])
+    offs = s.shell_offsets()
+    rows = []
+    for l in (0, 1, 2):
+        sh = rng.choice(np.nonzero(s.shell_l == l)[0], size=3, replace=False)
+        rows += [int(offs[k] + rng.integers(offs[k + 1] - offs[k])) for k in sh]
+    return sub, np.sort(np.array(rows))
+
+
+@pytest.mark.parametrize("cfg,stride", CASES)
+def test_sampled_block_matches_oracle(cfg, stride):
+    sub, rows = sample(cfg, stride)
+    say("config %d: %d functions, %d of the grid points, rows %s" % (cfg, sub.nbf, sub.npts, rows.tolist()))
+    Kref = O.k_block(sub, rows)
+    scale = float(np.max(np.abs(Kref)))
+    K0, st0 = snk.sn_k_build(sub, flags=snk.SNK_ROCBLAS)
+    d0 = float(np.max(np.abs(K0[np.ix_(rows, rows)] - Kref)))
+    K1, st1 = snk.sn_k_build(sub, flags=snk.SNK_ROCBLAS, eps_basis=1e-9)
+    d1 = float(np.max(np.abs(K1[np.ix_(rows, rows)] - Kref)))
+    say("config %d: max|K[S][S]| %.3e; eps_basis 0: max|dK| %.2e (rel %.1e); eps_basis 1e-9: max|dK| %.2e "
+        "(rel %.1e), tile F rows %.0f of %d" % (cfg, scale, d0, d0 / scale, d1, d1 / scale, st1["tile_frows"],
+                                                 sub.nbf))
+    assert np.array_equal(K0, K0.T) and np.array_equal(K1, K1.T)
+    assert d0 <= 1e-11 * scale
+    assert d1 <= 1e-7 * scale

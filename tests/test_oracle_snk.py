@@ -113,3 +113,25 @@ def test_stored_inputs_fingerprint(cfg):
     s = synth.make_system(cfg)
     assert np.allclose(mg.fingerprint(s), g["fingerprint"], rtol=1e-12, atol=0)
     assert np.max(np.abs(s.P - g["P"])) < 1e-12
+
+
+@pytest.mark.parametrize("which", ["config1", "soft_spd"])
+def test_rows_match_full_oracle(which):
+    """orc_snk_rows (selected rows of the unsymmetrised matrix, for sampling large systems)
+    against the full oracle: K[S][S] from the rows equals the full K on S x S."""
+    if which == "config1":
+        s = synth.make_system(1, grid=(20, 50))
+    else:
+        xyz = [[0.0, 0.0, 0.0], [1.3, 0.4, -0.2], [-0.5, 1.1, 0.7]]
+        shells = [
+            [(0, [2.1, 0.6], [0.5, 0.6]), (1, [1.4, 0.45], [0.7, 0.4]), (2, [0.9], [1.0])],
+            [(0, [1.7, 0.5], [0.4, 0.7]), (1, [0.8], [1.0])],
+            [(0, [1.1], [1.0]), (2, [1.3, 0.5], [0.5, 0.5]), (1, [30.0, 3.0, 0.3], [0.3, 0.5, 0.4])],
+        ]
+        s = synth.make_custom([8, 1, 1], xyz, shells, grid=(16, 50), n_occ=3)
+    K, ex, _ = O.snk(s)
+    rows = np.sort(np.random.default_rng(3).choice(s.nbf, size=min(9, s.nbf), replace=False))
+    Kb = O.k_block(s, rows)
+    assert np.max(np.abs(Kb - K[np.ix_(rows, rows)])) <= 1e-13 * np.max(np.abs(K))
+    Kt = O.snk_rows(s, np.arange(s.nbf))
+    assert np.max(np.abs(0.5 * (Kt + Kt.T) - K)) <= 1e-13 * np.max(np.abs(K))
