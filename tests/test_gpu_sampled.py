@@ -11,8 +11,8 @@ seeded set S of functions of every angular momentum.
   order only, as in the full parity tests).
 * eps_basis = 1e-9, rocBLAS GEMMs (the launch configuration of the plain FP64 build of the
   large clusters in bench.py): collocation values below 1e-9 and F rows whose bound is
-  below 1e-9 are dropped; the measured change of K[S][S] is printed and must stay below
-  1e-7 max|K[S][S]|.
+  below 1e-9 are dropped, so K[S][S] may move by ~1e-9 times O(1) sums of |G| and |Phi|;
+  the test allows 1e-9 max|K[S][S]| (measured: the same ~1e-13 as without screening).
 """
 import sys
 
@@ -61,4 +61,4 @@ def test_sampled_block_matches_oracle(cfg, stride):
                                                  sub.nbf))
     assert np.array_equal(K0, K0.T) and np.array_equal(K1, K1.T)
     assert d0 <= 1e-11 * scale
-    assert d1 <= 1e-7 * scale
+    assert d1 <= 1e-9 * scale
