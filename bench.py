@@ -108,9 +108,13 @@ def mixed_learned(s, P, K64, stream, args, ms64, ex64, ints):
                 ("fp64+learned", dict(precision=snk.SNK_FP64, screen=snk.SNK_SCREEN_LEARNED, flags=R)),
                 ("fp64 native GEMM", dict(precision=snk.SNK_FP64, screen=snk.SNK_SCREEN_NONE, flags=D)),
                 ("fp32gemm", dict(precision=snk.SNK_MIXED, screen=snk.SNK_SCREEN_NONE, flags=D | snk.SNK_FP32_GEMM)),
-                ("fp64+bound", dict(precision=snk.SNK_FP64, screen=snk.SNK_SCREEN_BOUND, flags=R))]
+                ("fp64+bound", dict(precision=snk.SNK_FP64, screen=snk.SNK_SCREEN_BOUND, flags=R)),
+                ("fp64+link (paper, 1e-9)", dict(precision=snk.SNK_FP64, screen=snk.SNK_SCREEN_LINK, flags=R,
+                                                 eps_skip_energy=1e-9))]
     for name, kw in variants:
-        ctx = snk.Context(s, stream=stream.cuda_stream, device=0, screener=mlp, eps_skip_energy=args.eps,
+        kw = dict(kw)
+        eps_skip = kw.pop("eps_skip_energy", args.eps)
+        ctx = snk.Context(s, stream=stream.cuda_stream, device=0, screener=mlp, eps_skip_energy=eps_skip,
                           eps_lowprec_energy=args.eps, **kw)
         steps = args.steps if name == "mixed+learned" else max(2, args.steps // 2)
         ms = time_builds(ctx, P, K, stream, steps, args.warmup)
@@ -198,6 +202,7 @@ def large_system(config, stream, args):
                        % (config, len(s.atom_Z), s.nbf, s.npts, s.density)}
     variants = [("fp64", dict(screen=snk.SNK_SCREEN_NONE)),
                 ("fp64+bound", dict(screen=snk.SNK_SCREEN_BOUND, eps_skip_energy=5e-7)),
+                ("fp64+link (paper, 1e-9)", dict(screen=snk.SNK_SCREEN_LINK, eps_skip_energy=1e-9)),
                 ("fp64+learned", dict(screen=snk.SNK_SCREEN_LEARNED, eps_skip_energy=args.eps)),
                 ("mixed+learned", dict(screen=snk.SNK_SCREEN_LEARNED, precision=snk.SNK_MIXED,
                                        eps_skip_energy=args.eps, eps_lowprec_energy=args.eps))]

@@ -64,7 +64,15 @@ typedef enum snk_precision {
 typedef enum snk_screen {
     SNK_SCREEN_NONE = 0,    /* every shell pair at every batch */
     SNK_SCREEN_BOUND = 1,   /* rigorous block bound (Sec. II.E, sn-LinK-type pair selection) */
-    SNK_SCREEN_LEARNED = 2  /* MLP estimate with the rigorous bound as fallback */
+    SNK_SCREEN_LEARNED = 2, /* MLP estimate with the rigorous bound as fallback */
+    SNK_SCREEN_LINK = 3     /* the paper's pair selection (Eq. sp_set): keep (A,B) on batch j when
+                               Ft_A Ft_B At_AB >= eps or max(Ft_A, Ft_B) phit_j At_AB >= eps,
+                               eps = eps_skip_energy (the paper uses 1e-9); Ft_A = max over the
+                               batch of sqrt(w_i) |F_a,i| (a in A, from F itself), phit_j = max_i
+                               sqrt(w_i) sum_mu |Phi_mu,i|, At_AB = sum over primitive pairs of
+                               |prefactor| max(1, |AB|)^(l_A + l_B) (a global estimate of
+                               max |A_ab|).  Not an energy budget: stats->skipped_bound
+                               reports the rigorous bound on the skipped blocks' energy */
 } snk_screen;
 
 /* opts.flags */
@@ -127,7 +135,8 @@ typedef struct snk_opts {
                                    radius r_cut (beyond which |phi| < eps_basis) reaches the box
                                    of the tile's points; F_t = P[:, B_t] Phi_t and only the
                                    columns B_t of K~ receive G_t Phi_t^T (Sec. II.E) */
-    double eps_skip_energy;     /* total energy budget for skipped blocks (Eh) */
+    double eps_skip_energy;     /* total energy budget for skipped blocks (Eh); SNK_SCREEN_LINK: the
+                                   per-pair thresholds eps_E = eps_K of Eq. sp_set */
     double eps_lowprec_energy;  /* SNK_MIXED: error budget of the FP32 blocks (Eh), see SNK_MIXED */
     int32_t batch_points;       /* maximum points per batch, 64..256 (default 256) */
     int32_t deterministic;      /* 1: no floating-point atomics (the default path uses none) */

@@ -50,12 +50,14 @@ __global__ __launch_bounds__(256) void diag_bound_kernel(const double* __restric
                                                          int32_t n, double* __restrict__ U,
                                                          float2* __restrict__ lun, int32_t nshell,
                                                          const double* __restrict__ gtab,
-                                                         const int32_t* __restrict__ tflag, int32_t tile_batches)
+                                                         const int32_t* __restrict__ tflag, int32_t tile_batches,
+                                                         double* __restrict__ fmax_out)
 {
     constexpr int N = ncart(L);
     __shared__ float tab[kBoysRows * kBoysCols];
     __shared__ double part[kGroup][4];
     __shared__ double npart[kGroup][4];
+    __shared__ double mpart[kGroup][4];
     for (int i = threadIdx.x; i < kBoysRows * kBoysCols; i += blockDim.x) tab[i] = (float)gtab[i];
     __syncthreads();
     const int batch = blockIdx.x;
@@ -73,28 +75,32 @@ __global__ __launch_bounds__(256) void diag_bound_kernel(const double* __restric
                 if (lane == 0) {
                     part[s - s0][wave] = 0.0;
                     npart[s - s0][wave] = 0.0;
+                    mpart[s - s0][wave] = 0.0;
                 }
                 continue;
             }
             const int row = drow[s];
             float Ab[N][N];
             pair_block<L, L, float>(prims + dpb[s], dnp[s], AB, cx, cy, cz, tab, Ab);
-            double t = 0.0, f2 = 0.0;
+            double t = 0.0, f2 = 0.0, fm = 0.0;
             sfor<0, N>([&](auto cc) {
                 constexpr int c = CV(cc);
                 const double f = cnorm(L, c) * (double)F[(int64_t)(row + c) * ld + col];
                 // A_cc of the unit-normalised component (FP32; the result is scaled up by kBoundSafety)
                 t += fabs(f) * (double)sqrtf(fmaxf(Ab[c][c], 0.0f));
                 f2 += f * f;
+                fm = fmax(fm, fabs(f));
             });
-            double v = w * t * t, q = w * f2;
+            double v = w * t * t, q = w * f2, m = sqrt(w) * fm;
             for (int o = 32; o > 0; o >>= 1) {
                 v += __shfl_xor(v, o);
                 q += __shfl_xor(q, o);
+                m = fmax(m, __shfl_xor(m, o));
             }
             if (lane == 0) {
                 part[s - s0][wave] = v;
                 npart[s - s0][wave] = q;
+                mpart[s - s0][wave] = m;
             }
         }
         __syncthreads();
@@ -106,6 +112,7 @@ __global__ __launch_bounds__(256) void diag_bound_kernel(const double* __restric
             if (lun)
                 lun[o] = make_float2(learn::lg10(u),
                                      learn::lg10(sqrt(npart[k][0] + npart[k][1] + npart[k][2] + npart[k][3])));
+            if (fmax_out) fmax_out[o] = fmax(fmax(mpart[k][0], mpart[k][1]), fmax(mpart[k][2], mpart[k][3]));
         }
         __syncthreads();
     }
@@ -435,10 +442,18 @@ __global__ __launch_bounds__(256) void screen_kernel(ScreenArgs a)
     const float* estb = learned ? a.est + (int64_t)batch * a.npair_total : nullptr;
     // block (aa, b) of the batch is evaluated in list category cat (0: FP64 or all, 1: FP32)
     int cat = 0;
+    const double* fm = a.link ? a.fmax + (int64_t)batch * a.nshell : nullptr;
+    const double phit = a.link ? a.phit[batch] : 0.0;
+    // Eq. sp_set: the energy estimate or the exchange-matrix estimate reaches the threshold
+    auto link_keep = [&](int aa, int b, int64_t p) -> bool {
+        const double at = a.atil[p];
+        return fm[aa] * fm[b] * at >= a.link_eps || ::fmax(fm[aa], fm[b]) * phit * at >= a.link_eps;
+    };
     auto keep = [&](int aa, int b) -> bool {
         if (bins[aa] + bins[b] < S) return false;
         const int64_t p = pair_index(aa, b);
         if (a.pairs[p].nprim == 0) return false;
+        if (a.link && !link_keep(aa, b, p)) return false;
         bool high = true;
         if (learned) {
             const int eb = est_bin(estb[p]);
@@ -463,6 +478,7 @@ __global__ __launch_bounds__(256) void screen_kernel(ScreenArgs a)
         if (tid == 0) sh.carry = 0;
         __syncthreads();
         int64_t npair = 0;
+        double lskip = 0.0;   // link mode: bound on the energy of the blocks it drops
         // pass 1: per-tile counts
         for (int64_t i0 = 0; i0 < ncombo; i0 += blockDim.x) {
             const int64_t i = i0 + tid;
@@ -475,7 +491,14 @@ __global__ __launch_bounds__(256) void screen_kernel(ScreenArgs a)
                     if (ai >= nA) break;
                     const int aa = actA[ai];
                     if (la == lb && aa < b) continue;
-                    if (!keep(aa, b)) continue;
+                    if (!keep(aa, b)) {
+                        if (!WRITE && a.link && cat == 0) {
+                            const int64_t p = pair_index(aa, b);
+                            if (a.pairs[p].nprim > 0 && !link_keep(aa, b, p))
+                                lskip += (aa == b ? 0.5 : 1.0) * Ub[aa] * Ub[b];
+                        }
+                        continue;
+                    }
                     mask |= 1 << k;
                     if (!WRITE && a.shell_flag) {
                         // both shells receive G contributions (idempotent flag stores)
@@ -492,12 +515,19 @@ __global__ __launch_bounds__(256) void screen_kernel(ScreenArgs a)
         }
         __syncthreads();
         if (!WRITE) {
-            // reduce npair over the block
-            double v = (double)npair;
-            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-            __shared__ double red[4];
-            if ((tid & 63) == 0) red[tid >> 6] = v;
+            // reduce npair (and the link-skipped bound) over the block
+            double v = (double)npair, ls = lskip;
+            for (int o = 32; o > 0; o >>= 1) {
+                v += __shfl_xor(v, o);
+                ls += __shfl_xor(ls, o);
+            }
+            __shared__ double red[4], lred[4];
+            if ((tid & 63) == 0) {
+                red[tid >> 6] = v;
+                lred[tid >> 6] = ls;
+            }
             __syncthreads();
+            if (a.link && tid == 0) sh.acc += lred[0] + lred[1] + lred[2] + lred[3];
             int nrun = 0, nbt = 0;
             if (tid == 0) {
                 for (int t = 0; t < nt; ++t) {
@@ -637,7 +667,7 @@ hipError_t launch_diag_bound(int l, const double* px, const double* py, const do
                              const double* F, const float* F32, int64_t ld, const PrimPair32* prims, const int32_t* dsh,
                              const int32_t* drow, const int32_t* dpb, const int32_t* dnp, int32_t n, double* U,
                              float2* N, int32_t nshell, int32_t nbatch, const double* tab, const int32_t* tflag,
-                             int32_t tile_batches, hipStream_t s)
+                             int32_t tile_batches, double* fmax, hipStream_t s)
 {
     if (tflag && tile_batches < 1) return hipErrorInvalidValue;
     if (nbatch <= 0 || n <= 0) return hipSuccess;
@@ -645,10 +675,10 @@ hipError_t launch_diag_bound(int l, const double* px, const double* py, const do
 #define SNK_DB(L)                                                                                                  \
     if (F32)                                                                                                       \
         hipLaunchKernelGGL((diag_bound_kernel<L, float>), grid, block, 0, s, px, py, pz, pw, F32, ld, prims, dsh,  \
-                           drow, dpb, dnp, n, U, N, nshell, tab, tflag, tile_batches);                             \
+                           drow, dpb, dnp, n, U, N, nshell, tab, tflag, tile_batches, fmax);                       \
     else                                                                                                           \
         hipLaunchKernelGGL((diag_bound_kernel<L, double>), grid, block, 0, s, px, py, pz, pw, F, ld, prims, dsh,   \
-                           drow, dpb, dnp, n, U, N, nshell, tab, tflag, tile_batches)
+                           drow, dpb, dnp, n, U, N, nshell, tab, tflag, tile_batches, fmax)
     switch (l) {
         case 0: SNK_DB(0); break;
         case 1: SNK_DB(1); break;
@@ -711,6 +741,46 @@ hipError_t launch_tile_rows(const int32_t* shell_flag, int32_t ntile, int32_t ns
     if (!shell_flag || !shell_l || !shell_row || !rows || !count) return hipErrorInvalidValue;
     hipLaunchKernelGGL(tile_rows_kernel, dim3(ntile), dim3(256), 0, s, shell_flag, nshell, shell_l, shell_row, nbf,
                        rows, count);
+    return hipGetLastError();
+}
+
+// One workgroup per batch of a group, lane = point: phit[b] = max_i sqrt(w_i) sum_mu |Phi_mu,i|
+// over the rows of the batch's tile (the paper's phi-tilde of the sn-LinK estimates).
+template <typename T>
+__global__ __launch_bounds__(256) void phisum_kernel(const T* __restrict__ Phi, const int32_t* __restrict__ roff,
+                                                     int32_t ntile, int32_t tile_batches, int64_t ncols_last,
+                                                     const double* __restrict__ pw, double* __restrict__ phit)
+{
+    __shared__ double red[4];
+    const int b = blockIdx.x;
+    const int t = b / tile_batches;
+    const int64_t tile_cols = (int64_t)tile_batches * kBatch;
+    const int64_t ncols = t == ntile - 1 ? ncols_last : tile_cols;
+    const T* base = Phi + (int64_t)roff[t] * tile_cols;   // every tile before t is full
+    const int64_t c = (int64_t)(b - t * tile_batches) * kBatch + threadIdx.x;
+    double v = 0.0;
+    for (int r = roff[t]; r < roff[t + 1]; ++r) v += fabs((double)base[(int64_t)(r - roff[t]) * ncols + c]);
+    v *= sqrt(pw[(int64_t)b * kBatch + threadIdx.x]);
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) phit[b] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+}
+
+hipError_t launch_phisum(const double* Phi, const float* Phi32, const int32_t* roff, int32_t ntile,
+                         int32_t tile_batches, int64_t ncols_last, const double* pw, int32_t nbatch, double* phit,
+                         hipStream_t s)
+{
+    if (nbatch <= 0) return hipSuccess;
+    if ((!Phi && !Phi32) || !roff || !pw || !phit || tile_batches < 1 || ntile < 1 ||
+        (int64_t)ntile * tile_batches < nbatch)
+        return hipErrorInvalidValue;
+    if (Phi32)
+        hipLaunchKernelGGL((phisum_kernel<float>), dim3(nbatch), dim3(kBatch), 0, s, Phi32, roff, ntile, tile_batches,
+                           ncols_last, pw, phit);
+    else
+        hipLaunchKernelGGL((phisum_kernel<double>), dim3(nbatch), dim3(kBatch), 0, s, Phi, roff, ntile, tile_batches,
+                           ncols_last, pw, phit);
     return hipGetLastError();
 }
 

@@ -173,6 +173,10 @@ struct snk_ctx {
     int32_t* d_thr2 = nullptr;
     PrimPair32* d_prims32 = nullptr;
     float2* d_lun = nullptr;        // [max_group_batches][nshell] log10 U, log10 F norm
+    // the paper's pair selection (SNK_SCREEN_LINK)
+    double* d_fmax = nullptr;       // [max_group_batches][nshell] max_i sqrt(w_i) |F_a,i|
+    double* d_phit = nullptr;       // [max_group_batches] max_i sqrt(w_i) sum_mu |Phi_mu,i|
+    double* d_atil = nullptr;       // [npair_total] global estimate of max |A_ab|
 
     // learned screen: static pair features, batch geometry, per-group estimates
     const snk_mlp* mlp = nullptr;
@@ -844,6 +848,22 @@ int setup_screening(snk_ctx* c)
         if ((rc = dalloc(c, &c->d_thr, (size_t)mb))) return rc;
         if ((rc = dalloc(c, &c->d_thr2, (size_t)mb))) return rc;
     }
+    if (c->opts.screen == SNK_SCREEN_LINK) {
+        if ((rc = dalloc(c, &c->d_fmax, (size_t)mb * c->nshell))) return rc;
+        if ((rc = dalloc(c, &c->d_phit, (size_t)mb))) return rc;
+        // At_AB = sum over primitive pairs of |prefactor| max(1, |AB|)^(l_A + l_B)
+        std::vector<double> at(c->npair_total, 0.0);
+        for (int a = 0; a < c->nshell; ++a)
+            for (int b = 0; b <= a; ++b) {
+                const int64_t p = pair_index(a, b);
+                const PairHdr& h = c->pairs[p];
+                const double ab = std::sqrt(h.ABx * h.ABx + h.ABy * h.ABy + h.ABz * h.ABz);
+                double v = 0.0;
+                for (int k = 0; k < h.nprim; ++k) v += std::fabs(c->prims[h.prim_begin + k].pref);
+                at[p] = v * std::pow(std::max(1.0, ab), c->sl[a] + c->sl[b]);
+            }
+        if ((rc = upload(c, &c->d_atil, at))) return rc;
+    }
     if ((rc = dalloc(c, &c->d_counts, (size_t)mb * 2 * c->nlist))) return rc;
     if ((rc = dalloc(c, &c->d_npairs, (size_t)mb * c->nlist))) return rc;
     if ((rc = dalloc(c, &c->d_skipped, (size_t)mb))) return rc;
@@ -951,6 +971,9 @@ void free_ctx(snk_ctx* c)
     (void)hipFree(c->d_shell_row);
     (void)hipFree(c->d_U);
     (void)hipFree(c->d_lun);
+    (void)hipFree(c->d_fmax);
+    (void)hipFree(c->d_phit);
+    (void)hipFree(c->d_atil);
     (void)hipFree(c->d_pfeat);
     (void)hipFree(c->d_pa);
     (void)hipFree(c->d_pb);
@@ -1040,7 +1063,7 @@ int snk_ctx_create(const snk_basis* basis, const snk_grid* grid, const double* w
     if (rc) return rc;
     if ((rc = validate_grid(nullptr, grid, weights))) return rc;
     if (o.precision != SNK_FP64 && o.precision != SNK_MIXED) return arg_error(nullptr, "unknown precision");
-    if (o.screen < SNK_SCREEN_NONE || o.screen > SNK_SCREEN_LEARNED) return arg_error(nullptr, "unknown screen mode");
+    if (o.screen < SNK_SCREEN_NONE || o.screen > SNK_SCREEN_LINK) return arg_error(nullptr, "unknown screen mode");
     if (o.batch_points < 1 || o.batch_points > kBatch) return arg_error(nullptr, "batch_points outside 1..256");
     if (!isfin(o.eps_basis) || o.eps_basis < 0.0) return arg_error(nullptr, "eps_basis must be >= 0");
     if (o.screen != SNK_SCREEN_NONE && (!isfin(o.eps_skip_energy) || o.eps_skip_energy < 0.0))
@@ -1177,22 +1200,23 @@ int snk_ctx_create(const snk_basis* basis, const snk_grid* grid, const double* w
         CREATE_CHECK(dalloc(c, &c->d_trows, (size_t)c->max_group_tiles * nbf));
         CREATE_CHECK(dalloc(c, &c->d_tcount, (size_t)c->max_group_tiles));
     }
+    // per group: the tiles' function lists one after the other and their row offsets
+    for (auto& g : c->groups) {
+        std::vector<int32_t> cat, roff;
+        for (const auto& t : g.tiles) {
+            roff.push_back((int32_t)cat.size());
+            cat.insert(cat.end(), t.coll_fn.begin(), t.coll_fn.end());
+        }
+        roff.push_back((int32_t)cat.size());
+        if (cat.empty()) cat.push_back(0);
+        CREATE_CHECK(upload(c, &g.d_fn_cat, cat));
+        CREATE_CHECK(upload(c, &g.d_roff, roff));
+    }
     if (c->frow_restrict) {
         CREATE_CHECK(dalloc(c, &c->d_fflag, (size_t)c->max_group_tiles * c->nshell));
         CREATE_CHECK(dalloc(c, &c->d_frows, (size_t)c->max_group_tiles * nbf));
         CREATE_CHECK(dalloc(c, &c->d_fcount, (size_t)c->max_group_tiles));
         CREATE_CHECK(dalloc(c, &c->d_mx, (size_t)std::max<int32_t>(1, c->max_group_rows)));
-        for (auto& g : c->groups) {
-            std::vector<int32_t> cat, roff;
-            for (const auto& t : g.tiles) {
-                roff.push_back((int32_t)cat.size());
-                cat.insert(cat.end(), t.coll_fn.begin(), t.coll_fn.end());
-            }
-            roff.push_back((int32_t)cat.size());
-            if (cat.empty()) cat.push_back(0);
-            CREATE_CHECK(upload(c, &g.d_fn_cat, cat));
-            CREATE_CHECK(upload(c, &g.d_roff, roff));
-        }
         std::vector<int32_t> fs(nbf);
         for (int sh = 0; sh < c->nshell; ++sh)
             for (int k = 0; k < ncart(c->sl[sh]); ++k) fs[c->sfn[sh] + k] = sh;
@@ -1552,7 +1576,7 @@ int group_bounds(snk_ctx* c, const Group& g)
                                       c->d_prims32, c->d_diag_sh[l], c->d_diag_row[l], c->d_diag_pb[l],
                                       c->d_diag_np[l], c->n_diag[l], c->d_U, c->d_lun, c->nshell, g.b1 - g.b0,
                                       c->d_boys, c->frow_restrict ? c->d_fflag : nullptr, c->tile_batches,
-                                      c->stream));
+                                      c->d_fmax, c->stream));
     return SNK_OK;
 }
 
@@ -1583,7 +1607,9 @@ int group_until_G(snk_ctx* c, const Group& g, const double* dP, bool timed, Grou
             int rc = group_bounds(c, g);
             if (rc) return rc;
         }
-        const double eps_batch = c->opts.eps_skip_energy / std::max(1, c->nbatch);
+        const bool link = c->opts.screen == SNK_SCREEN_LINK;
+        // the link selection has per-pair thresholds instead of an energy budget
+        const double eps_batch = link ? 0.0 : c->opts.eps_skip_energy / std::max(1, c->nbatch);
         // FP32 blocks: estimates summing to at most eps_lowprec / kLowRelErr per build
         const double eps_low =
             c->nlist == 12 ? c->opts.eps_lowprec_energy / kLowRelErr / std::max(1, c->nbatch) : 0.0;
@@ -1635,6 +1661,15 @@ int group_until_G(snk_ctx* c, const Group& g, const double* dP, bool timed, Grou
         sa.run_base = c->d_run_base;
         sa.bt_base = c->d_bt_base;
         const int ntile = (int)g.tiles.size();
+        if (link) {
+            HIPCHECK(c, launch_phisum(c->mixed ? nullptr : c->d_Phi, c->mixed ? c->d_Phi32 : nullptr, g.d_roff, ntile,
+                                      c->tile_batches, g.tiles.back().ncols, c->d_pw + off, nb, c->d_phit, s));
+            sa.link = 1;
+            sa.link_eps = c->opts.eps_skip_energy;
+            sa.fmax = c->d_fmax;
+            sa.phit = c->d_phit;
+            sa.atil = c->d_atil;
+        }
         if (c->row_restrict) {
             HIPCHECK(c, launch_fill(c->d_shell_flag, (int64_t)ntile * c->nshell, 0, s));
             sa.shell_flag = c->d_shell_flag;

@@ -127,6 +127,12 @@ struct ScreenArgs {
     int64_t npair_total;
     int32_t* shell_flag;        // [tiles][nshell]: set to 1 for both shells of every kept block (or nullptr)
     int32_t tile_batches;       // batches per tile (tile of batch b: b / tile_batches)
+    // pair selection of Eq. sp_set (link != 0): thresholds and the estimates it takes
+    int32_t link;
+    double link_eps;            // eps_E = eps_K
+    const double* fmax;         // [nbatch][nshell] max_i sqrt(w_i) |F_a,i| over the shell's functions
+    const double* phit;         // [nbatch] max_i sqrt(w_i) sum_mu |Phi_mu,i|
+    const double* atil;         // [npair_total] global estimate of max |A_ab| of the pair
 };
 
 // Relative error allowed for in an FP32-evaluated block of the mixed build: the FP32 set's
@@ -213,7 +219,13 @@ hipError_t launch_diag_bound(int l, const double* px, const double* py, const do
                              const double* F, const float* F32, int64_t ld, const PrimPair32* prims, const int32_t* dsh,
                              const int32_t* drow, const int32_t* dpb, const int32_t* dnp, int32_t n, double* U,
                              float2* lun, int32_t nshell, int32_t nbatch, const double* tab, const int32_t* tflag,
-                             int32_t tile_batches, hipStream_t s);
+                             int32_t tile_batches, double* fmax, hipStream_t s);
+// phit[b] = max over the points of batch b of sqrt(w_i) sum_mu |Phi_mu,i| for the batches of one
+// group: batch b lies in tile t = b / tile_batches, whose Phi_t has rows roff[t]..roff[t+1]-1
+// (tiles before the last have tile_batches * 256 columns, the last ncols_last)
+hipError_t launch_phisum(const double* Phi, const float* Phi32, const int32_t* roff, int32_t ntile,
+                         int32_t tile_batches, int64_t ncols_last, const double* pw, int32_t nbatch, double* phit,
+                         hipStream_t s);
 hipError_t launch_screen(bool write, const ScreenArgs& a, hipStream_t s);
 // Rows of G that the kept blocks of each tile can touch: for tile t, rows[t * nbf + m]
 // (m < count[t]) are the functions of the flagged shells in ascending order.

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libsnk.so")
 
 SNK_OK, SNK_E_ARG, SNK_E_UNSUPPORTED, SNK_E_NOMEM, SNK_E_DEVICE, SNK_E_ASYM = range(6)
 SNK_FP64, SNK_MIXED = 0, 1
-SNK_SCREEN_NONE, SNK_SCREEN_BOUND, SNK_SCREEN_LEARNED = 0, 1, 2
+SNK_SCREEN_NONE, SNK_SCREEN_BOUND, SNK_SCREEN_LEARNED, SNK_SCREEN_LINK = 0, 1, 2, 3
 SNK_DEVICE_PTRS = 0x1
 SNK_VALIDATE = 0x2
 SNK_ROCBLAS = 0x4
