@@ -139,6 +139,17 @@ struct snk_ctx {
     double* lane_Gc[kLanes] = {};
     double* lane_part[kLanes] = {};
     rocblas_handle lane_blas[kLanes] = {};   // [0] = blas; one handle per lane stream (own workspace)
+    // Plain FP64 builds (no screen, no basis screening) run consecutive groups on two streams
+    // with two buffer sets, so that one group's GEMMs overlap the other's A.F kernels; the
+    // reductions into K~ stay in group order.
+    bool pipe = false;
+    hipStream_t pstream[2] = {};
+    rocblas_handle pblas[2] = {};
+    hipEvent_t pev_fork = nullptr, pev_k[2] = {}, pev_end[2] = {};
+    double* p_Phi[2] = {};
+    double* p_F[2] = {};
+    double* p_G[2] = {};
+    double* p_part[2] = {};
     bool zero_f_rows = false;           // write every zero row of F and G (readers of every row)
     double acc_fn = 0, acc_frows = 0, acc_grows = 0, acc_cols = 0;   // column-weighted tile sizes
     int nsplit = 1;                     // K GEMM split over points for full-width tiles
@@ -508,6 +519,9 @@ void split_points(const double* xyz, std::vector<int64_t>& idx, size_t lo, size_
 // 500- and 1000-atom clusters (8: 5% slower, 32: 10%, 128: 50%).
 constexpr int kBasisTileBatches = 16;
 
+// Plain FP64 builds of at least twice this many batches run two groups at once.
+constexpr int kPipeMinBatches = 64;
+
 // Radius beyond which every Cartesian function of a shell is below eps in magnitude, for the
 // sphere test of Eq. basis_screen; -1 when the shell stays below eps everywhere.  Each
 // unit-normalised component is bounded by r^l times the radial part (|x^a y^b z^c| <= r^l,
@@ -663,6 +677,9 @@ int build_groups(snk_ctx* c)
         return SNK_E_NOMEM;
     }
     const bool bscreen = c->opts.eps_basis > 0.0;
+    // plain FP64 builds: at least two groups, each half of the budget (two buffer sets)
+    c->pipe = c->opts.screen == SNK_SCREEN_NONE && !bscreen && !c->mixed && c->nbatch >= 2 * kPipeMinBatches;
+    if (c->pipe) per_group = std::min<int64_t>(std::max<int64_t>(1, per_group / 2), (c->nbatch + 1) / 2);
     // with basis screening, groups are whole numbers of spatially ordered tiles
     if (bscreen && per_group > kBasisTileBatches) per_group -= per_group % kBasisTileBatches;
     const int64_t tile_batches = bscreen ? std::min<int64_t>(per_group, kBasisTileBatches) : per_group;
@@ -943,6 +960,18 @@ void free_ctx(snk_ctx* c)
         if (c->lane_red[k]) (void)hipEventDestroy(c->lane_red[k]);
     }
     if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
+    for (int k = 0; k < 2; ++k) {
+        if (c->pblas[k]) (void)rocblas_destroy_handle(c->pblas[k]);
+        if (c->pstream[k]) (void)hipStreamDestroy(c->pstream[k]);
+        if (c->pev_k[k]) (void)hipEventDestroy(c->pev_k[k]);
+        if (c->pev_end[k]) (void)hipEventDestroy(c->pev_end[k]);
+    }
+    if (c->pev_fork) (void)hipEventDestroy(c->pev_fork);
+    // the second buffer set (the first is the context's own)
+    (void)hipFree(c->p_Phi[1]);
+    (void)hipFree(c->p_F[1]);
+    (void)hipFree(c->p_G[1]);
+    (void)hipFree(c->p_part[1]);
     (void)hipFree(c->d_fflag);
     (void)hipFree(c->d_frows);
     (void)hipFree(c->d_fcount);
@@ -1244,6 +1273,25 @@ int snk_ctx_create(const snk_basis* basis, const snk_grid* grid, const double* w
             CREATE_CHECK(dalloc(c, &c->lane_part[k], (size_t)c->part_elems));
         }
     }
+    if (c->pipe) {
+        c->p_Phi[0] = c->d_Phi;
+        c->p_F[0] = c->d_F;
+        c->p_G[0] = c->d_G;
+        c->p_part[0] = c->d_part;
+        CREATE_CHECK(dalloc(c, &c->p_Phi[1], (size_t)std::max<int64_t>(1, c->max_phi)));
+        CREATE_CHECK(dalloc(c, &c->p_F[1], (size_t)nbf * c->max_cols));
+        CREATE_CHECK(dalloc(c, &c->p_G[1], (size_t)nbf * c->max_cols));
+        CREATE_CHECK(dalloc(c, &c->p_part[1], (size_t)c->part_elems));
+        CREATE_CHECK(hipEventCreateWithFlags(&c->pev_fork, hipEventDisableTiming) == hipSuccess ? SNK_OK : SNK_E_DEVICE);
+        for (int k = 0; k < 2; ++k) {
+            CREATE_CHECK(hipStreamCreateWithFlags(&c->pstream[k], hipStreamNonBlocking) == hipSuccess ? SNK_OK
+                                                                                                       : SNK_E_DEVICE);
+            CREATE_CHECK(hipEventCreateWithFlags(&c->pev_k[k], hipEventDisableTiming) == hipSuccess ? SNK_OK
+                                                                                                    : SNK_E_DEVICE);
+            CREATE_CHECK(hipEventCreateWithFlags(&c->pev_end[k], hipEventDisableTiming) == hipSuccess ? SNK_OK
+                                                                                                      : SNK_E_DEVICE);
+        }
+    }
     if ((o.flags & SNK_ROCBLAS) && !c->mixed && c->max_cols <= INT32_MAX && (int64_t)c->nbf <= INT32_MAX) {
         if (rocblas_create_handle(&c->blas) != rocblas_status_success ||
             rocblas_set_stream(c->blas, c->stream) != rocblas_status_success ||
@@ -1252,6 +1300,16 @@ int snk_ctx_create(const snk_basis* basis, const snk_grid* grid, const double* w
             g_last_error = c->err;
             free_ctx(c);
             return SNK_E_DEVICE;
+        }
+        for (int k = 0; k < 2 && c->pipe; ++k) {
+            if (rocblas_create_handle(&c->pblas[k]) != rocblas_status_success ||
+                rocblas_set_stream(c->pblas[k], c->pstream[k]) != rocblas_status_success ||
+                rocblas_set_atomics_mode(c->pblas[k], rocblas_atomics_not_allowed) != rocblas_status_success) {
+                set_err(c, "rocBLAS handle set-up failed");
+                g_last_error = c->err;
+                free_ctx(c);
+                return SNK_E_DEVICE;
+            }
         }
         for (int k = 1; k < c->nlanes; ++k) {
             if (rocblas_create_handle(&c->lane_blas[k]) != rocblas_status_success ||
@@ -1771,6 +1829,41 @@ int group_until_G(snk_ctx* c, const Group& g, const double* dP, bool timed, Grou
 
 }  // namespace
 
+namespace {
+
+// Points the context's stream, rocBLAS handle and group buffers at pipeline set k for the
+// duration of a build, and back to the context's own at restore() or destruction.
+struct PipeSwap {
+    snk_ctx* c;
+    bool on;
+    hipStream_t s0;
+    rocblas_handle b0;
+    PipeSwap(snk_ctx* x, bool active) : c(x), on(active), s0(x->stream), b0(x->blas) {}
+    void use(int k)
+    {
+        c->stream = c->pstream[k];
+        c->blas = b0 ? c->pblas[k] : nullptr;
+        c->d_Phi = c->p_Phi[k];
+        c->d_F = c->p_F[k];
+        c->d_G = c->p_G[k];
+        c->d_part = c->p_part[k];
+    }
+    void restore()
+    {
+        if (!on) return;
+        c->stream = s0;
+        c->blas = b0;
+        c->d_Phi = c->p_Phi[0];
+        c->d_F = c->p_F[0];
+        c->d_G = c->p_G[0];
+        c->d_part = c->p_part[0];
+        on = false;
+    }
+    ~PipeSwap() { restore(); }
+};
+
+}  // namespace
+
 extern "C" {
 
 int snk_ctx_build(snk_ctx* c, const double* P, double* K_out, snk_stats* stats)
@@ -1817,10 +1910,22 @@ int snk_ctx_build(snk_ctx* c, const double* P, double* K_out, snk_stats* stats)
     if (c->mlp)
         HIPCHECK(c, launch_pair_pnorm(dP, nbf, c->d_ne_list, c->d_pa, c->d_pb, c->d_shell_l, c->d_shell_row,
                                       (int64_t)c->ne_list.size(), c->d_lp, s));
-    for (const Group& g : c->groups) {
+    // two groups at once (untimed plain FP64 builds): group gi runs on pipeline stream gi % 2
+    // with buffer set gi % 2; its reductions into Kt wait for those of group gi - 1
+    const bool pipe = c->pipe && c->groups.size() > 1 && !timed;
+    PipeSwap swap(c, pipe);
+    if (pipe) {
+        HIPCHECK(c, hipEventRecord(c->pev_fork, s));
+        for (int k = 0; k < 2; ++k) HIPCHECK(c, hipStreamWaitEvent(c->pstream[k], c->pev_fork, 0));
+    }
+    for (size_t gi = 0; gi < c->groups.size(); ++gi) {
+        const Group& g = c->groups[gi];
+        if (pipe) swap.use((int)(gi & 1));
         int rc = group_until_G(c, g, dP, timed, &gs);
         if (rc) return rc;
+        if (pipe && gi > 0) HIPCHECK(c, hipStreamWaitEvent(c->stream, c->pev_k[(gi - 1) & 1], 0));
         if ((rc = group_K(c, g))) return rc;
+        if (pipe) HIPCHECK(c, hipEventRecord(c->pev_k[gi & 1], c->stream));
         if (timed) {
             HIPCHECK(c, hipEventRecord(c->ev[4], s));
             HIPCHECK(c, hipEventSynchronize(c->ev[4]));
@@ -1837,6 +1942,13 @@ int snk_ctx_build(snk_ctx* c, const double* P, double* K_out, snk_stats* stats)
                 tcls[cl] += ev_ms(c->ev[8 + cl], c->ev[cl == 5 ? 15 : 9 + cl]);
             }
             tk += ev_ms(c->ev[3], c->ev[4]);
+        }
+    }
+    if (pipe) {
+        swap.restore();
+        for (int k = 0; k < 2; ++k) {
+            HIPCHECK(c, hipEventRecord(c->pev_end[k], c->pstream[k]));
+            HIPCHECK(c, hipStreamWaitEvent(s, c->pev_end[k], 0));
         }
     }
     // Eq. sn_k and E_x

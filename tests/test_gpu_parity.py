@@ -216,3 +216,19 @@ def test_rocblas_gemm_path_matches_oracle():
     assert np.max(np.abs(K1 - K0)) <= 1e-11 * np.max(np.abs(K0))
     K2, _ = snk.sn_k_build(s2, flags=snk.SNK_ROCBLAS)
     assert np.array_equal(K1, K2)
+
+
+@pytest.mark.parametrize("flags", [0, snk.SNK_ROCBLAS])
+def test_two_stream_groups_match_sequential(flags):
+    """Plain FP64 builds without statistics run consecutive batch groups on two streams; with
+    statistics they run one after the other.  Same groups, same reduction order: bitwise
+    equal K, and both at the oracle."""
+    g = np.load(os.path.join(GOLDEN, "oracle_config2.npz"))
+    s = synth.make_system(2, with_density=False).with_density(g["P"])
+    ctx = snk.Context(s, flags=flags)
+    K1, st = ctx.build(s.P, stats=True)
+    K2, _ = ctx.build(s.P, stats=False)
+    say("config2 groups %d: pipelined == sequential %s" % (st["n_groups"], np.array_equal(K1, K2)))
+    assert st["n_groups"] >= 2
+    assert np.array_equal(K1, K2)
+    check(K2, st["ex"], g["K"], float(g["ex"][0]), "config2 two-stream")
