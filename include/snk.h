@@ -84,6 +84,14 @@ typedef enum snk_screen {
 #define SNK_FP32_GEMM   0x8u   /* SNK_MIXED: also store Phi, P and F in FP32 and run both dense GEMMs
                                   on the FP32 matrix cores (FP32 sums over <= 1024 terms, FP64
                                   across them); without it the mixed build's GEMMs stay FP64 */
+#define SNK_OVERLAP_GROUPS 0x10u /* plain FP64 builds (no density or basis screen, FP64, at least 128
+                                  batches): split the batches into two groups with their own Phi, F,
+                                  G and partial-sum buffers and run them on two streams, so that one
+                                  group's collocation and GEMMs, and the tail of each of its A.F
+                                  launches, overlap the other's A.F work.  K is bitwise that of
+                                  the sequential order (the reductions into K stay ordered); each
+                                  A.F launch covers half the batches.  Ignored elsewhere; builds
+                                  that return statistics run the two groups one after the other */
 
 typedef struct snk_basis {
     int32_t nshell;
@@ -143,7 +151,8 @@ typedef struct snk_opts {
     int64_t max_device_bytes;   /* workspace budget for batch groups (0 = automatic) */
     int32_t device;             /* HIP device ordinal */
     void* stream;               /* hipStream_t; NULL = the library's own stream */
-    uint32_t flags;             /* SNK_DEVICE_PTRS | SNK_VALIDATE | SNK_ROCBLAS | SNK_FP32_GEMM */
+    uint32_t flags;             /* SNK_DEVICE_PTRS | SNK_VALIDATE | SNK_ROCBLAS | SNK_FP32_GEMM |
+                                   SNK_OVERLAP_GROUPS */
     snk_stats* stats;           /* optional output of sn_k_build */
 } snk_opts;
 

@@ -677,8 +677,9 @@ int build_groups(snk_ctx* c)
         return SNK_E_NOMEM;
     }
     const bool bscreen = c->opts.eps_basis > 0.0;
-    // plain FP64 builds: at least two groups, each half of the budget (two buffer sets)
-    c->pipe = c->opts.screen == SNK_SCREEN_NONE && !bscreen && !c->mixed && c->nbatch >= 2 * kPipeMinBatches;
+    // overlapped plain FP64 builds: at least two groups, each half of the budget (two buffer sets)
+    c->pipe = (c->opts.flags & SNK_OVERLAP_GROUPS) && c->opts.screen == SNK_SCREEN_NONE && !bscreen && !c->mixed &&
+              c->nbatch >= 2 * kPipeMinBatches;
     if (c->pipe) per_group = std::min<int64_t>(std::max<int64_t>(1, per_group / 2), (c->nbatch + 1) / 2);
     // with basis screening, groups are whole numbers of spatially ordered tiles
     if (bscreen && per_group > kBasisTileBatches) per_group -= per_group % kBasisTileBatches;
@@ -1097,7 +1098,7 @@ int snk_ctx_create(const snk_basis* basis, const snk_grid* grid, const double* w
     if (!isfin(o.eps_basis) || o.eps_basis < 0.0) return arg_error(nullptr, "eps_basis must be >= 0");
     if (o.screen != SNK_SCREEN_NONE && (!isfin(o.eps_skip_energy) || o.eps_skip_energy < 0.0))
         return arg_error(nullptr, "eps_skip_energy must be finite and >= 0");
-    if (o.flags & ~(uint32_t)(SNK_DEVICE_PTRS | SNK_VALIDATE | SNK_ROCBLAS | SNK_FP32_GEMM))
+    if (o.flags & ~(uint32_t)(SNK_DEVICE_PTRS | SNK_VALIDATE | SNK_ROCBLAS | SNK_FP32_GEMM | SNK_OVERLAP_GROUPS))
         return arg_error(nullptr, "unknown flag");
     if (o.screen == SNK_SCREEN_LEARNED) {
         if (!o.screener) return arg_error(nullptr, "SNK_SCREEN_LEARNED needs a screener network");

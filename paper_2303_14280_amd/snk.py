@@ -23,6 +23,7 @@ SNK_DEVICE_PTRS = 0x1
 SNK_VALIDATE = 0x2
 SNK_ROCBLAS = 0x4
 SNK_FP32_GEMM = 0x8
+SNK_OVERLAP_GROUPS = 0x10
 CLASSES = ("ss", "ps", "pp", "ds", "dp", "dd")
 CLASS_L = ((0, 0), (1, 0), (1, 1), (2, 0), (2, 1), (2, 2))
 

@@ -220,15 +220,18 @@ def test_rocblas_gemm_path_matches_oracle():
 
 @pytest.mark.parametrize("flags", [0, snk.SNK_ROCBLAS])
 def test_two_stream_groups_match_sequential(flags):
-    """Plain FP64 builds without statistics run consecutive batch groups on two streams; with
-    statistics they run one after the other.  Same groups, same reduction order: bitwise
-    equal K, and both at the oracle."""
+    """With SNK_OVERLAP_GROUPS, plain FP64 builds without statistics run two batch groups on two
+    streams; with statistics they run one after the other.  Same groups, same reduction order:
+    bitwise equal K, and both at the oracle and at the default (one group) build."""
     g = np.load(os.path.join(GOLDEN, "oracle_config2.npz"))
     s = synth.make_system(2, with_density=False).with_density(g["P"])
-    ctx = snk.Context(s, flags=flags)
+    ctx = snk.Context(s, flags=flags | snk.SNK_OVERLAP_GROUPS)
     K1, st = ctx.build(s.P, stats=True)
     K2, _ = ctx.build(s.P, stats=False)
-    say("config2 groups %d: pipelined == sequential %s" % (st["n_groups"], np.array_equal(K1, K2)))
-    assert st["n_groups"] >= 2
+    K0, st0 = snk.sn_k_build(s, flags=flags)
+    say("config2 groups %d (default %d): overlapped == sequential %s; max|dK| vs one group %.2e" %
+        (st["n_groups"], st0["n_groups"], np.array_equal(K1, K2), np.max(np.abs(K2 - K0))))
+    assert st["n_groups"] >= 2 and st0["n_groups"] == 1
     assert np.array_equal(K1, K2)
     check(K2, st["ex"], g["K"], float(g["ex"][0]), "config2 two-stream")
+    assert np.max(np.abs(K2 - K0)) <= 1e-12 * np.max(np.abs(K0))
