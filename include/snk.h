@@ -206,6 +206,31 @@ int snk_ctx_ntiles(const snk_ctx* ctx);
 int snk_ctx_tile_info(const snk_ctx* ctx, int32_t* group, int32_t* b0, int32_t* b1, int32_t* nB);
 int snk_ctx_tile_functions(const snk_ctx* ctx, int32_t tile, int32_t* fn);
 
+/*
+ * Exchange-correlation potential matrix on the context's grid (Sec. II.C), the sibling of
+ * sn-K that shares its collocation (Eq. collocation) and F = P Phi (Eq. fmat):
+ *   rho_i = sum_mu F_mu,i Phi_mu,i,  grad rho_i = 2 sum_mu F_mu,i grad Phi_mu,i   (Eq. den_grid)
+ *   E^rho_i, E^gamma_i = partial derivatives of the functional's energy per unit volume
+ *     eps(rho, gamma = |grad rho|^2) at the point                               (Eq. exc_grid)
+ *   Z_mu,i = w_i / 2 (E^rho_i Phi_mu,i + 4 E^gamma_i grad rho_i . grad Phi_mu,i)   (Eq. zmat)
+ *   V_out = Phi Z^T + Z Phi^T (nbf x nbf, row-major, exactly symmetric)         (Eq. vxc_num)
+ * and *exc_out = E_xc = sum_i w_i eps_i, *nel_out = sum_i w_i rho_i (either may be NULL).
+ * The density is spin-restricted (P as for sn-K, both spins); grid points with
+ * rho < 1e-12 contribute nothing.  P and V_out are host or device pointers as the context's
+ * SNK_DEVICE_PTRS flag says; the call is ordered on the context's stream and returns after
+ * the scalars are in host memory when exc_out or nel_out is given (host-pointer mode:
+ * always synchronous).  Each call may reuse buffers of the context: calls on one context do
+ * not overlap.  All arithmetic FP64; the basis and grid are the context's (density and
+ * basis screening settings do not apply).  SNK_E_ARG for a NULL context, P or V_out or an
+ * unknown functional; SNK_E_NOMEM when the workspace (6 nbf doubles per grid point of a
+ * chunk of batches, chunks sized to max_device_bytes or a quarter of free device memory)
+ * does not fit.
+ */
+#define SNK_XC_SLATER 1   /* Dirac-Slater exchange */
+#define SNK_XC_LDA    2   /* Slater exchange + Perdew-Wang 1992 correlation (zeta = 0) */
+#define SNK_XC_PBE    3   /* Perdew-Burke-Ernzerhof exchange and correlation */
+int snk_vxc_build(snk_ctx* ctx, const double* P, int functional, double* V_out, double* exc_out, double* nel_out);
+
 /* Diagnostics. */
 const char* snk_status_string(int status);
 const char* snk_last_error(const snk_ctx* ctx);   /* NULL ctx: last error of a context-free call */

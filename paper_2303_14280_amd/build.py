@@ -18,11 +18,11 @@ OUT = os.path.join(PKG, "libsnk.so")
 BUILD_DIR = os.path.join(PKG, "_build")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
-SOURCES = ["snk_host.cpp", "snk_mlp.cpp", "k_afg.hip", "k_collocate.hip", "k_linalg.hip", "k_screen.hip", "k_mlp.hip", "k_learn.hip"]
+SOURCES = ["snk_host.cpp", "snk_mlp.cpp", "k_afg.hip", "k_collocate.hip", "k_linalg.hip", "k_screen.hip", "k_mlp.hip", "k_learn.hip", "k_xc.hip"]
 
 ARCH = os.environ.get("SNK_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
-         # packed FP32 instructions are kept out of every code object (see DESIGN.md)
+         # packed FP32 instructions are kept out of every code object
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", INCLUDE, "-I", CSRC, "-Wno-unused-command-line-argument"]
 

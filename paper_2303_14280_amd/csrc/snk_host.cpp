@@ -210,6 +210,18 @@ struct snk_ctx {
     double* d_pool_ab[12] = {};
     int64_t cap_runs[12] = {};
     int64_t cap_bt[12] = {};
+
+    // exchange-correlation potential (snk_vxc_build): workspace made on first use
+    int64_t xc_cols = 0;                // grid columns per chunk (whole batches)
+    double* d_xphi = nullptr;           // [4][nbf][xc_cols] Phi and grad Phi
+    double* d_xF = nullptr;             // [nbf][xc_cols]
+    double* d_xG = nullptr;             // [nbf][xc_cols] G = 2 Z
+    double* d_xe = nullptr;             // [2][xc_cols] w eps, w rho per column
+    double* d_xpart = nullptr;          // [xc_nsplit][nbf][nbf] split partial products
+    double* d_xred = nullptr;           // [512] partial sums
+    double* d_xsum = nullptr;           // [2] E_xc, N_el
+    int32_t* d_iota = nullptr;          // [nbf] identity row / column map
+    int xc_nsplit = 1;
 };
 
 namespace {
@@ -986,6 +998,14 @@ void free_ctx(snk_ctx* c)
     (void)hipFree(c->d_Kt);
     (void)hipFree(c->d_P);
     (void)hipFree(c->d_K);
+    (void)hipFree(c->d_xphi);
+    (void)hipFree(c->d_xF);
+    (void)hipFree(c->d_xG);
+    (void)hipFree(c->d_xe);
+    (void)hipFree(c->d_xpart);
+    (void)hipFree(c->d_xred);
+    (void)hipFree(c->d_xsum);
+    (void)hipFree(c->d_iota);
     (void)hipFree(c->d_partial);
     (void)hipFree(c->d_ex);
     (void)hipFree(c->d_boys);
@@ -1865,7 +1885,119 @@ struct PipeSwap {
 
 }  // namespace
 
+namespace {
+
+// XC workspace: chunks of whole batches sized to the device budget (six nbf-row buffers of
+// FP64 per column), and the split of the Z Phi^T product over grid points that fills the
+// device with nbf x nbf outputs of 64 x 64 tiles.
+int xc_workspace(snk_ctx* c)
+{
+    const int64_t nbf = c->nbf;
+    const int64_t total = (int64_t)c->nbatch * kBatch;
+    const int64_t otiles = ((nbf + 63) / 64) * ((nbf + 63) / 64);
+    c->xc_nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(256, 2048 / std::max<int64_t>(1, otiles)));
+    int64_t budget = c->opts.max_device_bytes;
+    if (budget <= 0) {
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) != hipSuccess) fr = (size_t)8 << 30;
+        budget = (int64_t)(0.25 * (double)fr);
+    }
+    budget -= (int64_t)c->xc_nsplit * nbf * nbf * 8;
+    const int64_t per_col = 6 * nbf * 8 + 16;
+    int64_t cols = budget / per_col;
+    cols = std::min<int64_t>(total, cols - cols % kBatch);
+    if (cols < kBatch) {
+        set_err(c, "device budget smaller than one batch of the XC workspace");
+        return SNK_E_NOMEM;
+    }
+    c->xc_cols = cols;
+    std::vector<int32_t> iota((size_t)nbf);
+    std::iota(iota.begin(), iota.end(), 0);
+    int rc = 0;
+    if ((rc = dalloc(c, &c->d_xphi, (size_t)(4 * nbf * cols))) || (rc = dalloc(c, &c->d_xF, (size_t)(nbf * cols))) ||
+        (rc = dalloc(c, &c->d_xG, (size_t)(nbf * cols))) || (rc = dalloc(c, &c->d_xe, (size_t)(2 * cols))) ||
+        (rc = dalloc(c, &c->d_xpart, (size_t)c->xc_nsplit * nbf * nbf)) || (rc = dalloc(c, &c->d_xred, 512)) ||
+        (rc = upload(c, &c->d_iota, iota)) || (rc = dalloc(c, &c->d_xsum, 2))) {
+        for (double** p : {&c->d_xphi, &c->d_xF, &c->d_xG, &c->d_xe, &c->d_xpart, &c->d_xred, &c->d_xsum}) {
+            (void)hipFree(*p);
+            *p = nullptr;
+        }
+        (void)hipFree(c->d_iota);
+        c->d_iota = nullptr;
+        return rc;
+    }
+    return SNK_OK;
+}
+
+}  // namespace
+
 extern "C" {
+
+int snk_vxc_build(snk_ctx* c, const double* P, int functional, double* V_out, double* exc_out, double* nel_out)
+{
+    if (!c) return arg_error(nullptr, "context is NULL");
+    if (!P || !V_out) return arg_error(c, "P or V_out is NULL");
+    if (functional < SNK_XC_SLATER || functional > SNK_XC_PBE) return arg_error(c, "unknown functional");
+    const bool dev = (c->opts.flags & SNK_DEVICE_PTRS) != 0;
+    const int64_t nbf = c->nbf;
+    const size_t nb2 = (size_t)nbf * nbf;
+    if (!dev)
+        for (size_t k = 0; k < nb2; ++k)
+            if (!isfin(P[k])) return arg_error(c, "non-finite density matrix element");
+    HIPCHECK(c, hipSetDevice(c->device));
+    hipStream_t s = c->stream;
+    const double* dP = P;
+    double* dV = V_out;
+    if (!dev) {
+        HIPCHECK(c, hipMemcpyAsync(c->d_P, P, nb2 * sizeof(double), hipMemcpyHostToDevice, s));
+        dP = c->d_P;
+        dV = c->d_K;
+    }
+    const int64_t total = (int64_t)c->nbatch * kBatch;
+    if (!c->d_xsum) {
+        int rc = total > 0 && nbf > 0 ? xc_workspace(c) : dalloc(c, &c->d_xsum, 2);
+        if (rc) return rc;
+    }
+    HIPCHECK(c, launch_fill(c->d_Kt, (int64_t)nb2, 0.0, s));
+    HIPCHECK(c, launch_fill(c->d_xsum, 2, 0.0, s));
+    for (int64_t col0 = 0; col0 < total && nbf > 0; col0 += c->xc_cols) {
+        const int64_t ncols = std::min<int64_t>(c->xc_cols, total - col0);
+        // Eq. collocation with gradients, Eq. fmat
+        HIPCHECK(c, launch_collocate_grad(c->d_px + col0, c->d_py + col0, c->d_pz + col0, ncols, c->d_shells, c->d_exps,
+                                          c->d_coefs, c->d_shell_row, c->nshell, nbf, c->d_xphi, s));
+        if (c->blas) {
+            const double one = 1.0, zero = 0.0;
+            // column-major view: F^T (ncols x nbf) = Phi^T (ncols x nbf) P^T
+            if (rocblas_dgemm(c->blas, rocblas_operation_none, rocblas_operation_none, (rocblas_int)ncols,
+                              (rocblas_int)nbf, (rocblas_int)nbf, &one, c->d_xphi, (rocblas_int)ncols, dP,
+                              (rocblas_int)nbf, &zero, c->d_xF, (rocblas_int)ncols) != rocblas_status_success) {
+                set_err(c, "rocblas_dgemm (XC F) failed");
+                return SNK_E_DEVICE;
+            }
+        } else {
+            HIPCHECK(c, launch_gemm_f64(nbf, ncols, nbf, dP, nbf, c->d_xphi, ncols, false, c->d_xF, ncols, 1, 0, s));
+        }
+        // Eqs. den_grid, exc_grid, zmat
+        HIPCHECK(c, launch_xc_point(c->d_xphi, c->d_xF, c->d_pw + col0, ncols, nbf, functional, c->d_xG, c->d_xe, s));
+        HIPCHECK(c, launch_xc_sum(c->d_xe, ncols, c->d_xred, c->d_xsum, true, s));
+        // Eq. vxc_num: Kt += G Phi^T over the chunk's points, split over points, fixed-order sum
+        HIPCHECK(c, launch_gemm_f64(nbf, nbf, ncols, c->d_xG, ncols, c->d_xphi, ncols, true, c->d_xpart, nbf,
+                                    c->xc_nsplit, (int64_t)nb2, s));
+        HIPCHECK(c, launch_reduce_scatter(c->d_xpart, c->xc_nsplit, (int64_t)nb2, nbf, nbf, c->d_iota, c->d_iota,
+                                          c->d_Kt, nbf, s));
+    }
+    // V = (Kt + Kt^T) / 2 with G = 2 Z; the finish's trace term is not used here
+    HIPCHECK(c, launch_finish(c->d_Kt, dP, dV, nbf, c->d_partial, c->nfinish, c->d_ex, s));
+    double sums[2] = {0.0, 0.0};
+    if (!dev) HIPCHECK(c, hipMemcpyAsync(V_out, dV, nb2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (!dev || exc_out || nel_out) {
+        HIPCHECK(c, hipMemcpyAsync(sums, c->d_xsum, sizeof(sums), hipMemcpyDeviceToHost, s));
+        HIPCHECK(c, hipStreamSynchronize(s));
+    }
+    if (exc_out) *exc_out = sums[0];
+    if (nel_out) *nel_out = sums[1];
+    return SNK_OK;
+}
 
 int snk_ctx_build(snk_ctx* c, const double* P, double* K_out, snk_stats* stats)
 {

@@ -24,6 +24,7 @@ SNK_VALIDATE = 0x2
 SNK_ROCBLAS = 0x4
 SNK_FP32_GEMM = 0x8
 SNK_OVERLAP_GROUPS = 0x10
+SNK_XC_SLATER, SNK_XC_LDA, SNK_XC_PBE = 1, 2, 3
 CLASSES = ("ss", "ps", "pp", "ds", "dp", "dd")
 CLASS_L = ((0, 0), (1, 0), (1, 1), (2, 0), (2, 1), (2, 2))
 
@@ -114,6 +115,9 @@ def lib():
             L.snk_shell_rcut.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_double,
                                          ctypes.POINTER(ctypes.c_double)]
             L.snk_shell_rcut.restype = ctypes.c_int
+            L.snk_vxc_build.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+            L.snk_vxc_build.restype = ctypes.c_int
             L.snk_ctx_ntiles.argtypes = [ctypes.c_void_p]
             L.snk_ctx_ntiles.restype = ctypes.c_int
             L.snk_ctx_tile_info.argtypes = [ctypes.c_void_p] * 5
@@ -285,6 +289,30 @@ class Context:
         _check(lib().snk_ctx_build(self.handle, ctypes.c_void_p(P_ptr), ctypes.c_void_p(K_ptr),
                                    ctypes.byref(st) if stats else None), self.handle)
         return st.as_dict() if stats else None
+
+    def vxc(self, P: np.ndarray, functional: int = SNK_XC_LDA) -> Tuple[np.ndarray, float, float]:
+        """Host-pointer XC potential (snk_vxc_build): returns (V^xc, E_xc, N_el)."""
+        if self.device_ptrs:
+            raise ValueError("context was created for device pointers; use vxc_device")
+        P = np.ascontiguousarray(P, np.float64)
+        if P.shape != (self.nbf, self.nbf):
+            raise ValueError("P has shape %s, expected %s" % (P.shape, (self.nbf, self.nbf)))
+        V = np.zeros_like(P)
+        exc, nel = ctypes.c_double(0.0), ctypes.c_double(0.0)
+        _check(lib().snk_vxc_build(self.handle, P.ctypes.data, int(functional), V.ctypes.data, ctypes.byref(exc),
+                                   ctypes.byref(nel)), self.handle)
+        return V, exc.value, nel.value
+
+    def vxc_device(self, P_ptr: int, V_ptr: int, functional: int = SNK_XC_LDA, scalars: bool = False):
+        """Device-pointer XC potential on the context's stream; (E_xc, N_el) when scalars is set
+        (then the call waits for them), else None (asynchronous)."""
+        if not self.device_ptrs:
+            raise ValueError("context was created for host pointers")
+        exc, nel = ctypes.c_double(0.0), ctypes.c_double(0.0)
+        _check(lib().snk_vxc_build(self.handle, ctypes.c_void_p(P_ptr), int(functional), ctypes.c_void_p(V_ptr),
+                                   ctypes.byref(exc) if scalars else None, ctypes.byref(nel) if scalars else None),
+               self.handle)
+        return (exc.value, nel.value) if scalars else None
 
     @property
     def ngroups(self) -> int:

@@ -1,0 +1,105 @@
+"""The exchange-correlation potential matrix (Sec. II.C) on the GPU, through the C ABI, against
+the XC oracle (oracle/xc_oracle.py, pinned in test_oracle_xc.py).
+
+Tolerance: every step is FP64; V^xc sums O(10^5) grid points of O(1) terms, so rounding
+order alone moves elements by ~1e-13 of max |V|.  The bar is 1e-11 max |V| element by element
+and 1e-10 (relative to max(1, |E_xc|)) for E_xc and N_el.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import xc_oracle as X
+from paper_2303_14280_amd import snk, synth
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+FUNCTIONALS = [snk.SNK_XC_SLATER, snk.SNK_XC_LDA, snk.SNK_XC_PBE]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def compare(V, exc, nel, s, functional, tag):
+    Vr, er, nr = X.vxc(s, functional)
+    scale = float(np.max(np.abs(Vr)))
+    dV = float(np.max(np.abs(V - Vr)))
+    say("%s functional %d: E_xc %.12f (oracle %.12f), N_el %.10f (oracle %.10f), max|dV| %.2e of %.2e" %
+        (tag, functional, exc, er, nel, nr, dV, scale))
+    assert np.array_equal(V, V.T)
+    assert dV <= 1e-11 * scale
+    assert abs(exc - er) <= 1e-10 * max(1.0, abs(er))
+    assert abs(nel - nr) <= 1e-10 * max(1.0, abs(nr))
+
+
+@pytest.mark.parametrize("functional", FUNCTIONALS)
+def test_config1_matches_oracle(functional):
+    s = synth.make_system(1)
+    ctx = snk.Context(s)
+    V, exc, nel = ctx.vxc(s.P, functional)
+    compare(V, exc, nel, s, functional, "config1")
+
+
+@pytest.mark.parametrize("functional", [snk.SNK_XC_LDA, snk.SNK_XC_PBE])
+def test_config2_subset_matches_oracle(functional):
+    """config 2 (290 functions) on every 7th grid point, through rocBLAS for F."""
+    s = synth.make_system(2)
+    s = s.subset_points(np.arange(3, s.npts, 7))
+    ctx = snk.Context(s, flags=snk.SNK_ROCBLAS)
+    V, exc, nel = ctx.vxc(s.P, functional)
+    compare(V, exc, nel, s, functional, "config2/7")
+
+
+def test_chunks_paths_and_determinism():
+    """A small device budget (several chunks of batches), the library's GEMM and rocBLAS, two
+    calls in a row: same V to rounding, bitwise equal per path and call."""
+    s = synth.make_system(1)
+    # split partial products (256 x nbf^2) plus six FP64 rows per column: ten batches a chunk
+    budget = 256 * 38 * 38 * 8 + (6 * 38 * 8 + 16) * 2560
+    a = snk.Context(s, max_device_bytes=budget)
+    b = snk.Context(s, flags=snk.SNK_ROCBLAS)
+    Va, ea, na = a.vxc(s.P, snk.SNK_XC_PBE)
+    Va2, ea2, _ = a.vxc(s.P, snk.SNK_XC_PBE)
+    Vb, eb, nb = b.vxc(s.P, snk.SNK_XC_PBE)
+    say("chunked (native GEMM) vs one chunk (rocBLAS F): |dE| %.2e max|dV| %.2e" %
+        (abs(ea - eb), np.max(np.abs(Va - Vb))))
+    assert np.array_equal(Va, Va2) and ea == ea2
+    assert np.max(np.abs(Va - Vb)) <= 1e-12 * np.max(np.abs(Vb))
+    assert abs(ea - eb) <= 1e-12 * abs(eb) and abs(na - nb) <= 1e-12 * abs(nb)
+
+
+def test_device_pointers_and_sn_k_on_one_context():
+    """Device-pointer mode on a torch stream, interleaved with sn-K builds on the same context."""
+    import torch
+    s = synth.make_system(1)
+    stream = torch.cuda.Stream()
+    ctx = snk.Context(s, flags=snk.SNK_DEVICE_PTRS, stream=stream.cuda_stream, device=0)
+    P = torch.tensor(s.P, dtype=torch.float64, device="cuda")
+    V = torch.empty_like(P)
+    K = torch.empty_like(P)
+    ctx.build_device(P.data_ptr(), K.data_ptr())
+    exc, nel = ctx.vxc_device(P.data_ptr(), V.data_ptr(), snk.SNK_XC_LDA, scalars=True)
+    ctx.build_device(P.data_ptr(), K.data_ptr())
+    torch.cuda.synchronize()
+    Vh, eh, nh = snk.Context(s).vxc(s.P, snk.SNK_XC_LDA)
+    K0, _ = snk.Context(s).build(s.P)
+    assert np.array_equal(V.cpu().numpy(), Vh) and exc == eh and nel == nh
+    assert np.array_equal(K.cpu().numpy(), K0)
+
+
+def test_empty_and_negligible_density():
+    """A grid far from every basis function: every point is below the density threshold, so V,
+    E_xc and N_el are exactly zero; arguments are checked."""
+    shells = [[(0, [2.0, 0.5], [0.5, 0.5]), (1, [1.0], [1.0])], []]
+    s = synth.make_custom([8, 1], [[0.0, 0.0, 0.0], [0.0, 0.0, 80.0]], shells, grid=None, n_occ=1)
+    pts = np.array([[0.0, 0.0, 80.0 + 0.1 * k] for k in range(300)])
+    s = s.with_grid(pts, np.full(300, 0.01))
+    ctx = snk.Context(s)
+    V, exc, nel = ctx.vxc(s.P, snk.SNK_XC_PBE)
+    assert not np.any(V) and exc == 0.0 and nel == 0.0
+    with pytest.raises(snk.SnkError):
+        ctx.vxc(s.P, 7)
