@@ -8,7 +8,8 @@ P and K resident in HBM.  Prints one JSON line.
     python bench.py [--gpus 1] [--steps 5] [--warmup 2] [--no-cpu-baseline] [--large 4,5]
 
 The JSON line also carries the mixed-precision and learned-screen builds of the same
-workload, a molecule-local density on the same geometry, and (--large) the 500- and
+workload, a molecule-local density on the same geometry, the exchange-correlation potential
+matrix (Slater, LDA, PBE) of the same density and grid, and (--large) the 500- and
 1000-atom clusters with basis and density screening.
 """
 from __future__ import annotations
@@ -145,6 +146,35 @@ def mixed_learned(s, P, K64, stream, args, ms64, ex64, ints):
     return res
 
 
+def xc_potential(s, P, stream, args):
+    """The exchange-correlation potential matrix (Sec. II.C) of the same workload: Slater, LDA
+    and PBE through snk_vxc_build (device pointers, F GEMM through rocBLAS), timed like the sn-K
+    builds, with E_xc and the electron count."""
+    import torch
+    from paper_2303_14280_amd import snk
+    ctx = snk.Context(s, flags=snk.SNK_DEVICE_PTRS | snk.SNK_ROCBLAS, stream=stream.cuda_stream, device=0)
+    V = torch.empty_like(P)
+    res = {"grid_points": s.npts, "nbf": ctx.nbf,
+           "gemm_flops": 4.0 * ctx.nbf * ctx.nbf * ctx.nbatches * 256}
+    for name, fn in (("slater", snk.SNK_XC_SLATER), ("lda", snk.SNK_XC_LDA), ("pbe", snk.SNK_XC_PBE)):
+        for i in range(args.warmup):
+            ctx.vxc_device(P.data_ptr(), V.data_ptr(), fn)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for i in range(args.steps):
+            ctx.vxc_device(P.data_ptr(), V.data_ptr(), fn)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = max(e0.elapsed_time(e1) / args.steps, 1000.0 * (time.perf_counter() - t0) / args.steps)
+        exc, nel = ctx.vxc_device(P.data_ptr(), V.data_ptr(), fn, scalars=True)
+        res[name] = {"ms_per_build": ms, "exc": exc, "nel": nel}
+        log("XC %s: %.3f ms/build, E_xc %.10f, N_el %.8f" % (name, ms, exc, nel))
+    ctx.close()
+    return res
+
+
 def local_density_comparison(s, stream, args):
     """The same geometry and grid with a molecule-local density (each water's five occupied
     orbitals on its own functions, P block-diagonal by molecule): FP64 build against the
@@ -256,6 +286,7 @@ def main():
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision + learned-screen comparison")
+    ap.add_argument("--no-xc", action="store_true", help="skip the exchange-correlation potential timings")
     ap.add_argument("--eps", type=float, default=5e-6,
                     help="estimate budget (Eh) of the learned screen's skipped blocks and of the FP32 blocks")
     ap.add_argument("--large", default="4,5",
@@ -375,6 +406,8 @@ def main():
     if not args.no_mixed:
         out["mixed_learned"] = mixed_learned(s, P, K, stream, args, ms, st["ex"], ints)
         out["local_density"] = local_density_comparison(s, stream, args)
+    if not args.no_xc:
+        out["xc_potential"] = xc_potential(s, P, stream, args)
     if args.large and args.large != "none":
         out["large_systems"] = {}
         for c in args.large.split(","):

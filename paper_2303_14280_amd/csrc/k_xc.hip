@@ -1,7 +1,8 @@
 // Exchange-correlation potential matrix on the grid (Sec. II.C): the kernels between the
 // F GEMM (Eq. fmat) and the Z Phi^T GEMM (Eq. vxc_num).
 //   * collocate_grad_kernel: Phi and its gradient, four row blocks of one buffer
-//     (Phi, d/dx, d/dy, d/dz), function-major like the sn-K collocation;
+//     (Phi, d/dx, d/dy, d/dz), function-major like the sn-K collocation (Phi alone for the
+//     local functionals, which need no gradient: one quarter of the traffic);
 //   * xc_point_kernel: one lane per grid point; rho and grad rho from F and Phi (Eq. den_grid),
 //     the functional and its partial derivatives E^rho, E^gamma (Eq. exc_grid) in closed form,
 //     and the product rows G = 2 Z (Eq. zmat), so that V = (G Phi^T + Phi G^T) / 2 goes
@@ -25,19 +26,24 @@ __device__ __forceinline__ double ipow(double x, int n)
 
 // One Cartesian component (exponents a, b, c; normalisation nc) of a shell with radial part R
 // and (1/r) dR/dr = dR at displacement d: value and gradient at four row blocks.
+template <bool GRAD>
 __device__ __forceinline__ void emit(double* __restrict__ out, int64_t blk, double nc, int a, int b, int c, double dx,
                                      double dy, double dz, double R, double dR)
 {
     const double m = ipow(dx, a) * ipow(dy, b) * ipow(dz, c);
-    const double mx = a ? a * ipow(dx, a - 1) * ipow(dy, b) * ipow(dz, c) : 0.0;
-    const double my = b ? b * ipow(dx, a) * ipow(dy, b - 1) * ipow(dz, c) : 0.0;
-    const double mz = c ? c * ipow(dx, a) * ipow(dy, b) * ipow(dz, c - 1) : 0.0;
     out[0] = nc * m * R;
-    out[blk] = nc * (mx * R + m * dx * dR);
-    out[2 * blk] = nc * (my * R + m * dy * dR);
-    out[3 * blk] = nc * (mz * R + m * dz * dR);
+    if constexpr (GRAD) {
+        const double mx = a ? a * ipow(dx, a - 1) * ipow(dy, b) * ipow(dz, c) : 0.0;
+        const double my = b ? b * ipow(dx, a) * ipow(dy, b - 1) * ipow(dz, c) : 0.0;
+        const double mz = c ? c * ipow(dx, a) * ipow(dy, b) * ipow(dz, c - 1) : 0.0;
+        out[blk] = nc * (mx * R + m * dx * dR);
+        out[2 * blk] = nc * (my * R + m * dy * dR);
+        out[3 * blk] = nc * (mz * R + m * dz * dR);
+    }
 }
 
+// GRAD = false (local functionals): Phi only, the gradient blocks are not touched
+template <bool GRAD>
 __global__ __launch_bounds__(256) void collocate_grad_kernel(const double* __restrict__ px,
                                                              const double* __restrict__ py,
                                                              const double* __restrict__ pz, int64_t ncols,
@@ -66,19 +72,19 @@ __global__ __launch_bounds__(256) void collocate_grad_kernel(const double* __res
         }
         double* out = Phi4 + (int64_t)shell_row[si] * ncols + col;
         if (sh.l == 0) {
-            emit(out, blk, 1.0, 0, 0, 0, dx, dy, dz, R, dR);
+            emit<GRAD>(out, blk, 1.0, 0, 0, 0, dx, dy, dz, R, dR);
         } else if (sh.l == 1) {
-            emit(out, blk, 1.0, 1, 0, 0, dx, dy, dz, R, dR);
-            emit(out + ncols, blk, 1.0, 0, 1, 0, dx, dy, dz, R, dR);
-            emit(out + 2 * ncols, blk, 1.0, 0, 0, 1, dx, dy, dz, R, dR);
+            emit<GRAD>(out, blk, 1.0, 1, 0, 0, dx, dy, dz, R, dR);
+            emit<GRAD>(out + ncols, blk, 1.0, 0, 1, 0, dx, dy, dz, R, dR);
+            emit<GRAD>(out + 2 * ncols, blk, 1.0, 0, 0, 1, dx, dy, dz, R, dR);
         } else {
             const double r3 = 1.7320508075688772;
-            emit(out, blk, 1.0, 2, 0, 0, dx, dy, dz, R, dR);
-            emit(out + ncols, blk, r3, 1, 1, 0, dx, dy, dz, R, dR);
-            emit(out + 2 * ncols, blk, r3, 1, 0, 1, dx, dy, dz, R, dR);
-            emit(out + 3 * ncols, blk, 1.0, 0, 2, 0, dx, dy, dz, R, dR);
-            emit(out + 4 * ncols, blk, r3, 0, 1, 1, dx, dy, dz, R, dR);
-            emit(out + 5 * ncols, blk, 1.0, 0, 0, 2, dx, dy, dz, R, dR);
+            emit<GRAD>(out, blk, 1.0, 2, 0, 0, dx, dy, dz, R, dR);
+            emit<GRAD>(out + ncols, blk, r3, 1, 1, 0, dx, dy, dz, R, dR);
+            emit<GRAD>(out + 2 * ncols, blk, r3, 1, 0, 1, dx, dy, dz, R, dR);
+            emit<GRAD>(out + 3 * ncols, blk, 1.0, 0, 2, 0, dx, dy, dz, R, dR);
+            emit<GRAD>(out + 4 * ncols, blk, r3, 0, 1, 1, dx, dy, dz, R, dR);
+            emit<GRAD>(out + 5 * ncols, blk, 1.0, 0, 0, 2, dx, dy, dz, R, dR);
         }
     }
 }
@@ -170,6 +176,7 @@ __device__ XcVal functional_eval(int fn, double rho, double sigma)
 }
 
 // one lane per column; rows of Phi4 (4 blocks of nbf rows), F and G with leading dimension ld
+template <bool GGA>
 __global__ __launch_bounds__(256) void xc_point_kernel(const double* __restrict__ Phi4,
                                                        const double* __restrict__ F,
                                                        const double* __restrict__ pw, int64_t ncols, int64_t nbf,
@@ -184,9 +191,11 @@ __global__ __launch_bounds__(256) void xc_point_kernel(const double* __restrict_
         const int64_t o = m * ncols;
         const double f = F[o + col];
         rho = fma(f, ph[o], rho);
-        gx = fma(f, ph[blk + o], gx);
-        gy = fma(f, ph[2 * blk + o], gy);
-        gz = fma(f, ph[3 * blk + o], gz);
+        if constexpr (GGA) {
+            gx = fma(f, ph[blk + o], gx);
+            gy = fma(f, ph[2 * blk + o], gy);
+            gz = fma(f, ph[3 * blk + o], gz);
+        }
     }
     gx *= 2.0;
     gy *= 2.0;
@@ -200,7 +209,10 @@ __global__ __launch_bounds__(256) void xc_point_kernel(const double* __restrict_
     const double bx = b * gx, by = b * gy, bz = b * gz;
     for (int64_t m = 0; m < nbf; ++m) {
         const int64_t o = m * ncols;
-        G[o + col] = fma(a, ph[o], fma(bx, ph[blk + o], fma(by, ph[2 * blk + o], bz * ph[3 * blk + o])));
+        if constexpr (GGA)
+            G[o + col] = fma(a, ph[o], fma(bx, ph[blk + o], fma(by, ph[2 * blk + o], bz * ph[3 * blk + o])));
+        else
+            G[o + col] = a * ph[o];
     }
     epart[col] = w * v.e;
     epart[ncols + col] = w * rho;
@@ -258,12 +270,17 @@ __global__ __launch_bounds__(256) void xc_sum_final_kernel(const double* __restr
 
 hipError_t launch_collocate_grad(const double* px, const double* py, const double* pz, int64_t ncols,
                                  const ShellDev* shells, const double* exps, const double* coefs,
-                                 const int32_t* shell_row, int32_t nsh, int64_t nbf, double* Phi4, hipStream_t s)
+                                 const int32_t* shell_row, int32_t nsh, int64_t nbf, bool grad, double* Phi4,
+                                 hipStream_t s)
 {
     if (ncols <= 0 || nsh <= 0) return hipSuccess;
     dim3 grid((unsigned)((ncols + 255) / 256), (unsigned)((nsh + kXcShellsPerBlock - 1) / kXcShellsPerBlock));
-    hipLaunchKernelGGL(collocate_grad_kernel, grid, dim3(256), 0, s, px, py, pz, ncols, shells, exps, coefs,
-                       shell_row, nsh, nbf, Phi4);
+    if (grad)
+        hipLaunchKernelGGL(collocate_grad_kernel<true>, grid, dim3(256), 0, s, px, py, pz, ncols, shells, exps, coefs,
+                           shell_row, nsh, nbf, Phi4);
+    else
+        hipLaunchKernelGGL(collocate_grad_kernel<false>, grid, dim3(256), 0, s, px, py, pz, ncols, shells, exps, coefs,
+                           shell_row, nsh, nbf, Phi4);
     return hipGetLastError();
 }
 
@@ -271,8 +288,11 @@ hipError_t launch_xc_point(const double* Phi4, const double* F, const double* pw
                            double* G, double* epart, hipStream_t s)
 {
     if (ncols <= 0) return hipSuccess;
-    hipLaunchKernelGGL(xc_point_kernel, dim3((unsigned)((ncols + 255) / 256)), dim3(256), 0, s, Phi4, F, pw, ncols,
-                       nbf, fn, G, epart);
+    dim3 grid((unsigned)((ncols + 255) / 256));
+    if (fn == SNK_XC_PBE)
+        hipLaunchKernelGGL(xc_point_kernel<true>, grid, dim3(256), 0, s, Phi4, F, pw, ncols, nbf, fn, G, epart);
+    else
+        hipLaunchKernelGGL(xc_point_kernel<false>, grid, dim3(256), 0, s, Phi4, F, pw, ncols, nbf, fn, G, epart);
     return hipGetLastError();
 }
 

@@ -1964,7 +1964,8 @@ int snk_vxc_build(snk_ctx* c, const double* P, int functional, double* V_out, do
         const int64_t ncols = std::min<int64_t>(c->xc_cols, total - col0);
         // Eq. collocation with gradients, Eq. fmat
         HIPCHECK(c, launch_collocate_grad(c->d_px + col0, c->d_py + col0, c->d_pz + col0, ncols, c->d_shells, c->d_exps,
-                                          c->d_coefs, c->d_shell_row, c->nshell, nbf, c->d_xphi, s));
+                                          c->d_coefs, c->d_shell_row, c->nshell, nbf, functional == SNK_XC_PBE,
+                                          c->d_xphi, s));
         if (c->blas) {
             const double one = 1.0, zero = 0.0;
             // column-major view: F^T (ncols x nbf) = Phi^T (ncols x nbf) P^T
@@ -1981,10 +1982,37 @@ int snk_vxc_build(snk_ctx* c, const double* P, int functional, double* V_out, do
         HIPCHECK(c, launch_xc_point(c->d_xphi, c->d_xF, c->d_pw + col0, ncols, nbf, functional, c->d_xG, c->d_xe, s));
         HIPCHECK(c, launch_xc_sum(c->d_xe, ncols, c->d_xred, c->d_xsum, true, s));
         // Eq. vxc_num: Kt += G Phi^T over the chunk's points, split over points, fixed-order sum
-        HIPCHECK(c, launch_gemm_f64(nbf, nbf, ncols, c->d_xG, ncols, c->d_xphi, ncols, true, c->d_xpart, nbf,
-                                    c->xc_nsplit, (int64_t)nb2, s));
-        HIPCHECK(c, launch_reduce_scatter(c->d_xpart, c->xc_nsplit, (int64_t)nb2, nbf, nbf, c->d_iota, c->d_iota,
-                                          c->d_Kt, nbf, s));
+        if (c->blas) {
+            // split over whole batches; column-major view of chunk z: part_z^T = Phi_z G_z^T
+            const int64_t nb = ncols / kBatch;
+            const int64_t bpc = (nb + c->xc_nsplit - 1) / c->xc_nsplit;
+            const int64_t kchunk = bpc * kBatch;
+            const int64_t nfull = nb / bpc, rem = nb - nfull * bpc;
+            const double one = 1.0, zero = 0.0;
+            rocblas_status st = rocblas_status_success;
+            if (nfull > 0)
+                st = rocblas_dgemm_strided_batched(c->blas, rocblas_operation_transpose, rocblas_operation_none,
+                                                   (rocblas_int)nbf, (rocblas_int)nbf, (rocblas_int)kchunk, &one,
+                                                   c->d_xphi, (rocblas_int)ncols, kchunk, c->d_xG, (rocblas_int)ncols,
+                                                   kchunk, &zero, c->d_xpart, (rocblas_int)nbf, (int64_t)nb2,
+                                                   (rocblas_int)nfull);
+            if (st == rocblas_status_success && rem > 0)
+                st = rocblas_dgemm(c->blas, rocblas_operation_transpose, rocblas_operation_none, (rocblas_int)nbf,
+                                   (rocblas_int)nbf, (rocblas_int)(rem * kBatch), &one, c->d_xphi + nfull * kchunk,
+                                   (rocblas_int)ncols, c->d_xG + nfull * kchunk, (rocblas_int)ncols, &zero,
+                                   c->d_xpart + nfull * (int64_t)nb2, (rocblas_int)nbf);
+            if (st != rocblas_status_success) {
+                set_err(c, "rocblas_dgemm (XC V) failed");
+                return SNK_E_DEVICE;
+            }
+            HIPCHECK(c, launch_reduce_scatter(c->d_xpart, (int)(nfull + (rem > 0)), (int64_t)nb2, nbf, nbf, c->d_iota,
+                                              c->d_iota, c->d_Kt, nbf, s));
+        } else {
+            HIPCHECK(c, launch_gemm_f64(nbf, nbf, ncols, c->d_xG, ncols, c->d_xphi, ncols, true, c->d_xpart, nbf,
+                                        c->xc_nsplit, (int64_t)nb2, s));
+            HIPCHECK(c, launch_reduce_scatter(c->d_xpart, c->xc_nsplit, (int64_t)nb2, nbf, nbf, c->d_iota, c->d_iota,
+                                              c->d_Kt, nbf, s));
+        }
     }
     // V = (Kt + Kt^T) / 2 with G = 2 Z; the finish's trace term is not used here
     HIPCHECK(c, launch_finish(c->d_Kt, dP, dV, nbf, c->d_partial, c->nfinish, c->d_ex, s));

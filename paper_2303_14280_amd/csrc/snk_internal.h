@@ -294,7 +294,8 @@ hipError_t launch_finish(const double* Kt, const double* P, double* K, int64_t n
 // (partial: 512 doubles), added to out when accumulate.
 hipError_t launch_collocate_grad(const double* px, const double* py, const double* pz, int64_t ncols,
                                  const ShellDev* shells, const double* exps, const double* coefs,
-                                 const int32_t* shell_row, int32_t nsh, int64_t nbf, double* Phi4, hipStream_t s);
+                                 const int32_t* shell_row, int32_t nsh, int64_t nbf, bool grad, double* Phi4,
+                                 hipStream_t s);
 hipError_t launch_xc_point(const double* Phi4, const double* F, const double* pw, int64_t ncols, int64_t nbf, int fn,
                            double* G, double* epart, hipStream_t s);
 hipError_t launch_xc_sum(const double* epart, int64_t n, double* partial, double* out, bool accumulate, hipStream_t s);
