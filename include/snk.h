@@ -222,7 +222,7 @@ int snk_ctx_tile_functions(const snk_ctx* ctx, int32_t tile, int32_t* fn);
  * always synchronous).  Each call may reuse buffers of the context: calls on one context do
  * not overlap.  All arithmetic FP64; the basis and grid are the context's (density and
  * basis screening settings do not apply).  SNK_E_ARG for a NULL context, P or V_out or an
- * unknown functional; SNK_E_NOMEM when the workspace (6 nbf doubles per grid point of a
+ * unknown functional; SNK_E_NOMEM when the workspace (3 nbf doubles per grid point of a
  * chunk of batches, chunks sized to max_device_bytes or a quarter of free device memory)
  * does not fit.
  */

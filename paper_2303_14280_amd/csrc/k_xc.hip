@@ -1,12 +1,10 @@
 // Exchange-correlation potential matrix on the grid (Sec. II.C): the kernels between the
 // F GEMM (Eq. fmat) and the Z Phi^T GEMM (Eq. vxc_num).
-//   * collocate_grad_kernel: Phi and its gradient, four row blocks of one buffer
-//     (Phi, d/dx, d/dy, d/dz), function-major like the sn-K collocation (Phi alone for the
-//     local functionals, which need no gradient: one quarter of the traffic);
-//   * xc_point_kernel: one lane per grid point; rho and grad rho from F and Phi (Eq. den_grid),
-//     the functional and its partial derivatives E^rho, E^gamma (Eq. exc_grid) in closed form,
-//     and the product rows G = 2 Z (Eq. zmat), so that V = (G Phi^T + Phi G^T) / 2 goes
-//     through the same symmetrising finish as sn-K;
+//   * xc_collocate_kernel: Phi (function-major like the sn-K collocation) for the two GEMMs;
+//   * xc_point_kernel: one lane per grid point; rho and grad rho from F and the basis values
+//     (Eq. den_grid), recomputed in registers, the functional and its partial derivatives
+//     E^rho, E^gamma (Eq. exc_grid) in closed form, and the product rows G = 2 Z (Eq. zmat),
+//     so that V = (G Phi^T + Phi G^T) / 2 goes through the same symmetrising finish as sn-K;
 //   * xc_sum_kernel: fixed-order two-stage sums of w_i eps_i (E_xc) and w_i rho_i (N_el).
 // All arithmetic is FP64.  Points with rho below kXcRhoMin contribute nothing.
 #include "snk.h"
@@ -16,78 +14,6 @@ namespace snk {
 namespace {
 
 constexpr int kXcShellsPerBlock = 8;
-
-__device__ __forceinline__ double ipow(double x, int n)
-{
-    double r = 1.0;
-    for (int k = 0; k < n; ++k) r *= x;
-    return r;
-}
-
-// One Cartesian component (exponents a, b, c; normalisation nc) of a shell with radial part R
-// and (1/r) dR/dr = dR at displacement d: value and gradient at four row blocks.
-template <bool GRAD>
-__device__ __forceinline__ void emit(double* __restrict__ out, int64_t blk, double nc, int a, int b, int c, double dx,
-                                     double dy, double dz, double R, double dR)
-{
-    const double m = ipow(dx, a) * ipow(dy, b) * ipow(dz, c);
-    out[0] = nc * m * R;
-    if constexpr (GRAD) {
-        const double mx = a ? a * ipow(dx, a - 1) * ipow(dy, b) * ipow(dz, c) : 0.0;
-        const double my = b ? b * ipow(dx, a) * ipow(dy, b - 1) * ipow(dz, c) : 0.0;
-        const double mz = c ? c * ipow(dx, a) * ipow(dy, b) * ipow(dz, c - 1) : 0.0;
-        out[blk] = nc * (mx * R + m * dx * dR);
-        out[2 * blk] = nc * (my * R + m * dy * dR);
-        out[3 * blk] = nc * (mz * R + m * dz * dR);
-    }
-}
-
-// GRAD = false (local functionals): Phi only, the gradient blocks are not touched
-template <bool GRAD>
-__global__ __launch_bounds__(256) void collocate_grad_kernel(const double* __restrict__ px,
-                                                             const double* __restrict__ py,
-                                                             const double* __restrict__ pz, int64_t ncols,
-                                                             const ShellDev* __restrict__ shells,
-                                                             const double* __restrict__ exps,
-                                                             const double* __restrict__ coefs,
-                                                             const int32_t* __restrict__ shell_row, int32_t nsh,
-                                                             int64_t nbf, double* __restrict__ Phi4)
-{
-    const int64_t col = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (col >= ncols) return;
-    const double x = px[col], y = py[col], z = pz[col];
-    const int64_t blk = nbf * ncols;
-    const int s0 = blockIdx.y * kXcShellsPerBlock;
-    const int s1 = min(nsh, s0 + kXcShellsPerBlock);
-    for (int si = s0; si < s1; ++si) {
-        const ShellDev sh = shells[si];
-        const double dx = x - sh.x, dy = y - sh.y, dz = z - sh.z;
-        const double r2 = dx * dx + dy * dy + dz * dz;
-        double R = 0.0, dR = 0.0;
-        for (int k = 0; k < sh.nprim; ++k) {
-            const double ck = coefs[sh.prim_off + k], zk = exps[sh.prim_off + k];
-            const double g = ck * exp(-zk * r2);
-            R += g;
-            dR = fma(-2.0 * zk, g, dR);
-        }
-        double* out = Phi4 + (int64_t)shell_row[si] * ncols + col;
-        if (sh.l == 0) {
-            emit<GRAD>(out, blk, 1.0, 0, 0, 0, dx, dy, dz, R, dR);
-        } else if (sh.l == 1) {
-            emit<GRAD>(out, blk, 1.0, 1, 0, 0, dx, dy, dz, R, dR);
-            emit<GRAD>(out + ncols, blk, 1.0, 0, 1, 0, dx, dy, dz, R, dR);
-            emit<GRAD>(out + 2 * ncols, blk, 1.0, 0, 0, 1, dx, dy, dz, R, dR);
-        } else {
-            const double r3 = 1.7320508075688772;
-            emit<GRAD>(out, blk, 1.0, 2, 0, 0, dx, dy, dz, R, dR);
-            emit<GRAD>(out + ncols, blk, r3, 1, 1, 0, dx, dy, dz, R, dR);
-            emit<GRAD>(out + 2 * ncols, blk, r3, 1, 0, 1, dx, dy, dz, R, dR);
-            emit<GRAD>(out + 3 * ncols, blk, 1.0, 0, 2, 0, dx, dy, dz, R, dR);
-            emit<GRAD>(out + 4 * ncols, blk, r3, 0, 1, 1, dx, dy, dz, R, dR);
-            emit<GRAD>(out + 5 * ncols, blk, 1.0, 0, 0, 2, dx, dy, dz, R, dR);
-        }
-    }
-}
 
 // ---- functionals: energy per volume e(rho, sigma) and its partial derivatives -------------
 
@@ -175,46 +101,128 @@ __device__ XcVal functional_eval(int fn, double rho, double sigma)
     return v;
 }
 
-// one lane per column; rows of Phi4 (4 blocks of nbf rows), F and G with leading dimension ld
+// Values (and for GGA gradients) of the Cartesian components of one shell at displacement d,
+// in lexicographic order; nc = the component normalisations.
 template <bool GGA>
-__global__ __launch_bounds__(256) void xc_point_kernel(const double* __restrict__ Phi4,
-                                                       const double* __restrict__ F,
-                                                       const double* __restrict__ pw, int64_t ncols, int64_t nbf,
-                                                       int fn, double* __restrict__ G, double* __restrict__ epart)
+__device__ __forceinline__ int shell_values(const ShellDev& sh, const double* __restrict__ exps,
+                                            const double* __restrict__ coefs, double dx, double dy, double dz,
+                                            double (&v)[6], double (&gx)[6], double (&gy)[6], double (&gz)[6])
+{
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    double R = 0.0, dR = 0.0;
+    for (int k = 0; k < sh.nprim; ++k) {
+        const double g = coefs[sh.prim_off + k] * exp(-exps[sh.prim_off + k] * r2);
+        R += g;
+        dR = fma(-2.0 * exps[sh.prim_off + k], g, dR);
+    }
+    // monomials m and their derivatives, component by component
+    auto put = [&](int i, double nc, double m, double mx, double my, double mz) {
+        v[i] = nc * m * R;
+        if constexpr (GGA) {
+            gx[i] = nc * (mx * R + m * dx * dR);
+            gy[i] = nc * (my * R + m * dy * dR);
+            gz[i] = nc * (mz * R + m * dz * dR);
+        }
+    };
+    if (sh.l == 0) {
+        put(0, 1.0, 1.0, 0.0, 0.0, 0.0);
+        return 1;
+    }
+    if (sh.l == 1) {
+        put(0, 1.0, dx, 1.0, 0.0, 0.0);
+        put(1, 1.0, dy, 0.0, 1.0, 0.0);
+        put(2, 1.0, dz, 0.0, 0.0, 1.0);
+        return 3;
+    }
+    const double r3 = 1.7320508075688772;
+    put(0, 1.0, dx * dx, 2.0 * dx, 0.0, 0.0);
+    put(1, r3, dx * dy, dy, dx, 0.0);
+    put(2, r3, dx * dz, dz, 0.0, dx);
+    put(3, 1.0, dy * dy, 0.0, 2.0 * dy, 0.0);
+    put(4, r3, dy * dz, 0.0, dz, dy);
+    put(5, 1.0, dz * dz, 0.0, 0.0, 2.0 * dz);
+    return 6;
+}
+
+// Phi of every shell for the two GEMMs (function-major, ld = ncols), from the same
+// component values as the point kernel.
+__global__ __launch_bounds__(256) void xc_collocate_kernel(const double* __restrict__ px,
+                                                           const double* __restrict__ py,
+                                                           const double* __restrict__ pz, int64_t ncols,
+                                                           const ShellDev* __restrict__ shells,
+                                                           const double* __restrict__ exps,
+                                                           const double* __restrict__ coefs,
+                                                           const int32_t* __restrict__ shell_row, int32_t nsh,
+                                                           double* __restrict__ Phi)
 {
     const int64_t col = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (col >= ncols) return;
-    const int64_t blk = nbf * ncols;
-    const double* ph = Phi4 + col;
+    const double x = px[col], y = py[col], z = pz[col];
+    const int s0 = blockIdx.y * kXcShellsPerBlock;
+    const int s1 = min(nsh, s0 + kXcShellsPerBlock);
+    double v[6], unused[6];
+    for (int si = s0; si < s1; ++si) {
+        const ShellDev sh = shells[si];
+        const int n = shell_values<false>(sh, exps, coefs, x - sh.x, y - sh.y, z - sh.z, v, unused, unused, unused);
+        double* out = Phi + (int64_t)shell_row[si] * ncols + col;
+        for (int i = 0; i < n; ++i) out[i * ncols] = v[i];
+    }
+}
+
+// One lane per column.  Phi and its gradient are recomputed from the shell data in both
+// passes instead of being read from memory (a few exponentials per shell against four
+// 8-byte loads per function): the kernel reads only F (nbf rows, ld = ncols) and writes G.
+template <bool GGA>
+__global__ __launch_bounds__(256) void xc_point_kernel(const double* __restrict__ px, const double* __restrict__ py,
+                                                       const double* __restrict__ pz, const double* __restrict__ pw,
+                                                       const ShellDev* __restrict__ shells,
+                                                       const double* __restrict__ exps,
+                                                       const double* __restrict__ coefs, int32_t nsh,
+                                                       const double* __restrict__ F, int64_t ncols, int fn,
+                                                       double* __restrict__ G, double* __restrict__ epart)
+{
+    const int64_t col = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (col >= ncols) return;
+    const double x = px[col], y = py[col], z = pz[col];
+    double v[6], vx[6], vy[6], vz[6];
     double rho = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
-    for (int64_t m = 0; m < nbf; ++m) {
-        const int64_t o = m * ncols;
-        const double f = F[o + col];
-        rho = fma(f, ph[o], rho);
-        if constexpr (GGA) {
-            gx = fma(f, ph[blk + o], gx);
-            gy = fma(f, ph[2 * blk + o], gy);
-            gz = fma(f, ph[3 * blk + o], gz);
+    int64_t row = 0;
+    for (int si = 0; si < nsh; ++si) {
+        const ShellDev sh = shells[si];
+        const int n = shell_values<GGA>(sh, exps, coefs, x - sh.x, y - sh.y, z - sh.z, v, vx, vy, vz);
+        for (int i = 0; i < n; ++i) {
+            const double f = F[(row + i) * ncols + col];
+            rho = fma(f, v[i], rho);
+            if constexpr (GGA) {
+                gx = fma(f, vx[i], gx);
+                gy = fma(f, vy[i], gy);
+                gz = fma(f, vz[i], gz);
+            }
         }
+        row += n;
     }
     gx *= 2.0;
     gy *= 2.0;
     gz *= 2.0;
     const double w = pw[col];
-    XcVal v{0.0, 0.0, 0.0};
-    if (rho >= kXcRhoMin) v = functional_eval(fn, rho, gx * gx + gy * gy + gz * gz);
+    XcVal e{0.0, 0.0, 0.0};
+    if (rho >= kXcRhoMin) e = functional_eval(fn, rho, gx * gx + gy * gy + gz * gz);
     // G = 2 Z = w (E^rho Phi + 4 E^gamma grad rho . grad Phi)
-    const double a = w * v.vr;
-    const double b = 4.0 * w * v.vs;
+    const double a = w * e.vr;
+    const double b = 4.0 * w * e.vs;
     const double bx = b * gx, by = b * gy, bz = b * gz;
-    for (int64_t m = 0; m < nbf; ++m) {
-        const int64_t o = m * ncols;
-        if constexpr (GGA)
-            G[o + col] = fma(a, ph[o], fma(bx, ph[blk + o], fma(by, ph[2 * blk + o], bz * ph[3 * blk + o])));
-        else
-            G[o + col] = a * ph[o];
+    row = 0;
+    for (int si = 0; si < nsh; ++si) {
+        const ShellDev sh = shells[si];
+        const int n = shell_values<GGA>(sh, exps, coefs, x - sh.x, y - sh.y, z - sh.z, v, vx, vy, vz);
+        for (int i = 0; i < n; ++i) {
+            double g = a * v[i];
+            if constexpr (GGA) g = fma(bx, vx[i], fma(by, vy[i], fma(bz, vz[i], g)));
+            G[(row + i) * ncols + col] = g;
+        }
+        row += n;
     }
-    epart[col] = w * v.e;
+    epart[col] = w * e.e;
     epart[ncols + col] = w * rho;
 }
 
@@ -268,31 +276,29 @@ __global__ __launch_bounds__(256) void xc_sum_final_kernel(const double* __restr
 
 }  // namespace
 
-hipError_t launch_collocate_grad(const double* px, const double* py, const double* pz, int64_t ncols,
-                                 const ShellDev* shells, const double* exps, const double* coefs,
-                                 const int32_t* shell_row, int32_t nsh, int64_t nbf, bool grad, double* Phi4,
-                                 hipStream_t s)
+hipError_t launch_xc_collocate(const double* px, const double* py, const double* pz, int64_t ncols,
+                               const ShellDev* shells, const double* exps, const double* coefs,
+                               const int32_t* shell_row, int32_t nsh, double* Phi, hipStream_t s)
 {
     if (ncols <= 0 || nsh <= 0) return hipSuccess;
     dim3 grid((unsigned)((ncols + 255) / 256), (unsigned)((nsh + kXcShellsPerBlock - 1) / kXcShellsPerBlock));
-    if (grad)
-        hipLaunchKernelGGL(collocate_grad_kernel<true>, grid, dim3(256), 0, s, px, py, pz, ncols, shells, exps, coefs,
-                           shell_row, nsh, nbf, Phi4);
-    else
-        hipLaunchKernelGGL(collocate_grad_kernel<false>, grid, dim3(256), 0, s, px, py, pz, ncols, shells, exps, coefs,
-                           shell_row, nsh, nbf, Phi4);
+    hipLaunchKernelGGL(xc_collocate_kernel, grid, dim3(256), 0, s, px, py, pz, ncols, shells, exps, coefs, shell_row,
+                       nsh, Phi);
     return hipGetLastError();
 }
 
-hipError_t launch_xc_point(const double* Phi4, const double* F, const double* pw, int64_t ncols, int64_t nbf, int fn,
-                           double* G, double* epart, hipStream_t s)
+hipError_t launch_xc_point(const double* px, const double* py, const double* pz, const double* pw, int64_t ncols,
+                           const ShellDev* shells, const double* exps, const double* coefs, int32_t nsh,
+                           const double* F, int fn, double* G, double* epart, hipStream_t s)
 {
     if (ncols <= 0) return hipSuccess;
     dim3 grid((unsigned)((ncols + 255) / 256));
     if (fn == SNK_XC_PBE)
-        hipLaunchKernelGGL(xc_point_kernel<true>, grid, dim3(256), 0, s, Phi4, F, pw, ncols, nbf, fn, G, epart);
+        hipLaunchKernelGGL(xc_point_kernel<true>, grid, dim3(256), 0, s, px, py, pz, pw, shells, exps, coefs, nsh, F,
+                           ncols, fn, G, epart);
     else
-        hipLaunchKernelGGL(xc_point_kernel<false>, grid, dim3(256), 0, s, Phi4, F, pw, ncols, nbf, fn, G, epart);
+        hipLaunchKernelGGL(xc_point_kernel<false>, grid, dim3(256), 0, s, px, py, pz, pw, shells, exps, coefs, nsh, F,
+                           ncols, fn, G, epart);
     return hipGetLastError();
 }
 

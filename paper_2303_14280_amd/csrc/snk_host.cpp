@@ -213,7 +213,7 @@ struct snk_ctx {
 
     // exchange-correlation potential (snk_vxc_build): workspace made on first use
     int64_t xc_cols = 0;                // grid columns per chunk (whole batches)
-    double* d_xphi = nullptr;           // [4][nbf][xc_cols] Phi and grad Phi
+    double* d_xphi = nullptr;           // [nbf][xc_cols] Phi
     double* d_xF = nullptr;             // [nbf][xc_cols]
     double* d_xG = nullptr;             // [nbf][xc_cols] G = 2 Z
     double* d_xe = nullptr;             // [2][xc_cols] w eps, w rho per column
@@ -1887,8 +1887,8 @@ struct PipeSwap {
 
 namespace {
 
-// XC workspace: chunks of whole batches sized to the device budget (six nbf-row buffers of
-// FP64 per column), and the split of the Z Phi^T product over grid points that fills the
+// XC workspace: chunks of whole batches sized to the device budget (three nbf-row buffers of
+// FP64 per column: Phi, F, G), and the split of the Z Phi^T product over grid points that fills the
 // device with nbf x nbf outputs of 64 x 64 tiles.
 int xc_workspace(snk_ctx* c)
 {
@@ -1903,7 +1903,7 @@ int xc_workspace(snk_ctx* c)
         budget = (int64_t)(0.25 * (double)fr);
     }
     budget -= (int64_t)c->xc_nsplit * nbf * nbf * 8;
-    const int64_t per_col = 6 * nbf * 8 + 16;
+    const int64_t per_col = 3 * nbf * 8 + 16;
     int64_t cols = budget / per_col;
     cols = std::min<int64_t>(total, cols - cols % kBatch);
     if (cols < kBatch) {
@@ -1914,7 +1914,7 @@ int xc_workspace(snk_ctx* c)
     std::vector<int32_t> iota((size_t)nbf);
     std::iota(iota.begin(), iota.end(), 0);
     int rc = 0;
-    if ((rc = dalloc(c, &c->d_xphi, (size_t)(4 * nbf * cols))) || (rc = dalloc(c, &c->d_xF, (size_t)(nbf * cols))) ||
+    if ((rc = dalloc(c, &c->d_xphi, (size_t)(nbf * cols))) || (rc = dalloc(c, &c->d_xF, (size_t)(nbf * cols))) ||
         (rc = dalloc(c, &c->d_xG, (size_t)(nbf * cols))) || (rc = dalloc(c, &c->d_xe, (size_t)(2 * cols))) ||
         (rc = dalloc(c, &c->d_xpart, (size_t)c->xc_nsplit * nbf * nbf)) || (rc = dalloc(c, &c->d_xred, 512)) ||
         (rc = upload(c, &c->d_iota, iota)) || (rc = dalloc(c, &c->d_xsum, 2))) {
@@ -1962,10 +1962,9 @@ int snk_vxc_build(snk_ctx* c, const double* P, int functional, double* V_out, do
     HIPCHECK(c, launch_fill(c->d_xsum, 2, 0.0, s));
     for (int64_t col0 = 0; col0 < total && nbf > 0; col0 += c->xc_cols) {
         const int64_t ncols = std::min<int64_t>(c->xc_cols, total - col0);
-        // Eq. collocation with gradients, Eq. fmat
-        HIPCHECK(c, launch_collocate_grad(c->d_px + col0, c->d_py + col0, c->d_pz + col0, ncols, c->d_shells, c->d_exps,
-                                          c->d_coefs, c->d_shell_row, c->nshell, nbf, functional == SNK_XC_PBE,
-                                          c->d_xphi, s));
+        // Eqs. collocation, fmat
+        HIPCHECK(c, launch_xc_collocate(c->d_px + col0, c->d_py + col0, c->d_pz + col0, ncols, c->d_shells, c->d_exps,
+                                        c->d_coefs, c->d_shell_row, c->nshell, c->d_xphi, s));
         if (c->blas) {
             const double one = 1.0, zero = 0.0;
             // column-major view: F^T (ncols x nbf) = Phi^T (ncols x nbf) P^T
@@ -1979,7 +1978,8 @@ int snk_vxc_build(snk_ctx* c, const double* P, int functional, double* V_out, do
             HIPCHECK(c, launch_gemm_f64(nbf, ncols, nbf, dP, nbf, c->d_xphi, ncols, false, c->d_xF, ncols, 1, 0, s));
         }
         // Eqs. den_grid, exc_grid, zmat
-        HIPCHECK(c, launch_xc_point(c->d_xphi, c->d_xF, c->d_pw + col0, ncols, nbf, functional, c->d_xG, c->d_xe, s));
+        HIPCHECK(c, launch_xc_point(c->d_px + col0, c->d_py + col0, c->d_pz + col0, c->d_pw + col0, ncols, c->d_shells,
+                                    c->d_exps, c->d_coefs, c->nshell, c->d_xF, functional, c->d_xG, c->d_xe, s));
         HIPCHECK(c, launch_xc_sum(c->d_xe, ncols, c->d_xred, c->d_xsum, true, s));
         // Eq. vxc_num: Kt += G Phi^T over the chunk's points, split over points, fixed-order sum
         if (c->blas) {

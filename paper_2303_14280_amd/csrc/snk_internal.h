@@ -288,16 +288,17 @@ hipError_t launch_mfma_probe(double* out_dev, hipStream_t s);
 // K = (Kt + Kt^T)/2 and ex = -1/2 tr(P K) (two-stage deterministic reduction, partial buffer of nblk doubles)
 hipError_t launch_finish(const double* Kt, const double* P, double* K, int64_t nbf, double* partial, int nblk,
                          double* ex, hipStream_t s);
-// XC potential (Sec. II.C): Phi and grad Phi as four row blocks of nbf rows (ld = ncols);
-// per point rho, grad rho, the functional and G = 2 Z; per point w eps and w rho in
+// XC potential (Sec. II.C): Phi (nbf rows, ld = ncols); per point rho, grad rho, the
+// functional and G = 2 Z from F and the basis values recomputed from the shells; per point
+// w eps and w rho in
 // epart[0..ncols) and epart[ncols..2 ncols); fixed-order sums of those into out[0..1]
 // (partial: 512 doubles), added to out when accumulate.
-hipError_t launch_collocate_grad(const double* px, const double* py, const double* pz, int64_t ncols,
-                                 const ShellDev* shells, const double* exps, const double* coefs,
-                                 const int32_t* shell_row, int32_t nsh, int64_t nbf, bool grad, double* Phi4,
-                                 hipStream_t s);
-hipError_t launch_xc_point(const double* Phi4, const double* F, const double* pw, int64_t ncols, int64_t nbf, int fn,
-                           double* G, double* epart, hipStream_t s);
+hipError_t launch_xc_collocate(const double* px, const double* py, const double* pz, int64_t ncols,
+                               const ShellDev* shells, const double* exps, const double* coefs,
+                               const int32_t* shell_row, int32_t nsh, double* Phi, hipStream_t s);
+hipError_t launch_xc_point(const double* px, const double* py, const double* pz, const double* pw, int64_t ncols,
+                           const ShellDev* shells, const double* exps, const double* coefs, int32_t nsh,
+                           const double* F, int fn, double* G, double* epart, hipStream_t s);
 hipError_t launch_xc_sum(const double* epart, int64_t n, double* partial, double* out, bool accumulate, hipStream_t s);
 hipError_t launch_boys_eval(const double* T, int64_t n, int mmax, double* F, const double* tab, hipStream_t s);
 // out[rows[m] * ld + c] = in[m * ncols + c] for m < M, c < ncols

@@ -58,8 +58,8 @@ def test_chunks_paths_and_determinism():
     """A small device budget (several chunks of batches), the library's GEMM and rocBLAS, two
     calls in a row: same V to rounding, bitwise equal per path and call."""
     s = synth.make_system(1)
-    # split partial products (256 x nbf^2) plus six FP64 rows per column: ten batches a chunk
-    budget = 256 * 38 * 38 * 8 + (6 * 38 * 8 + 16) * 2560
+    # split partial products (256 x nbf^2) plus three FP64 rows per column: ten batches a chunk
+    budget = 256 * 38 * 38 * 8 + (3 * 38 * 8 + 16) * 2560
     a = snk.Context(s, max_device_bytes=budget)
     b = snk.Context(s, flags=snk.SNK_ROCBLAS)
     Va, ea, na = a.vxc(s.P, snk.SNK_XC_PBE)
