@@ -307,8 +307,8 @@ def main():
         log("copied %d MiB" % args.calibrate_copy)
         return
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (the grid-batch "
-              "sharding is described in DESIGN.md); rerun with --gpus 1", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (the build would "
+              "shard by grid batch and all-reduce K); rerun with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

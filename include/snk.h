@@ -47,7 +47,7 @@ extern "C" {
 typedef enum snk_status {
     SNK_OK = 0,
     SNK_E_ARG = 1,          /* null pointer, l > 2, nprim out of range, exponent <= 0, non-finite, weight < 0 */
-    SNK_E_UNSUPPORTED = 2,  /* option not available in this build */
+    SNK_E_UNSUPPORTED = 2,  /* option not available in this library */
     SNK_E_NOMEM = 3,        /* device or host allocation failed, or the device budget is too small */
     SNK_E_DEVICE = 4,       /* HIP runtime error (text in snk_last_error) */
     SNK_E_ASYM = 5          /* validate mode: |P - P^T| > 1e-12 max|P| */

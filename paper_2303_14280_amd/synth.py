@@ -28,7 +28,7 @@ ANGSTROM = 1.0 / 0.529177210903  # bohr per angstrom
 
 Z_O, Z_H = 8, 1
 
-# Per-config recipe.
+# Per-config recipe: atoms, box, basis flavour, grid (radial x angular) and occupied orbitals.
 BASIS_SEED = {"sp": 1, "spd": 2}
 
 CONFIGS: Dict[int, dict] = {
