@@ -171,13 +171,15 @@ __global__ __launch_bounds__(256) void xc_collocate_kernel(const double* __restr
 
 // One lane per column.  Phi and its gradient are recomputed from the shell data in both
 // passes instead of being read from memory (a few exponentials per shell against four
-// 8-byte loads per function): the kernel reads only F (nbf rows, ld = ncols) and writes G.
+// 8-byte loads per function): the kernel reads only F and writes G, whose rows follow the
+// shells of shell_list (NULL: every shell in order), ld = ncols.
 template <bool GGA>
 __global__ __launch_bounds__(256) void xc_point_kernel(const double* __restrict__ px, const double* __restrict__ py,
                                                        const double* __restrict__ pz, const double* __restrict__ pw,
                                                        const ShellDev* __restrict__ shells,
                                                        const double* __restrict__ exps,
                                                        const double* __restrict__ coefs, int32_t nsh,
+                                                       const int32_t* __restrict__ shell_list,
                                                        const double* __restrict__ F, int64_t ncols, int fn,
                                                        double* __restrict__ G, double* __restrict__ epart)
 {
@@ -188,7 +190,7 @@ __global__ __launch_bounds__(256) void xc_point_kernel(const double* __restrict_
     double rho = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
     int64_t row = 0;
     for (int si = 0; si < nsh; ++si) {
-        const ShellDev sh = shells[si];
+        const ShellDev sh = shells[shell_list ? shell_list[si] : si];
         const int n = shell_values<GGA>(sh, exps, coefs, x - sh.x, y - sh.y, z - sh.z, v, vx, vy, vz);
         for (int i = 0; i < n; ++i) {
             const double f = F[(row + i) * ncols + col];
@@ -213,7 +215,7 @@ __global__ __launch_bounds__(256) void xc_point_kernel(const double* __restrict_
     const double bx = b * gx, by = b * gy, bz = b * gz;
     row = 0;
     for (int si = 0; si < nsh; ++si) {
-        const ShellDev sh = shells[si];
+        const ShellDev sh = shells[shell_list ? shell_list[si] : si];
         const int n = shell_values<GGA>(sh, exps, coefs, x - sh.x, y - sh.y, z - sh.z, v, vx, vy, vz);
         for (int i = 0; i < n; ++i) {
             double g = a * v[i];
@@ -289,16 +291,17 @@ hipError_t launch_xc_collocate(const double* px, const double* py, const double*
 
 hipError_t launch_xc_point(const double* px, const double* py, const double* pz, const double* pw, int64_t ncols,
                            const ShellDev* shells, const double* exps, const double* coefs, int32_t nsh,
-                           const double* F, int fn, double* G, double* epart, hipStream_t s)
+                           const int32_t* shell_list, const double* F, int fn, double* G, double* epart,
+                           hipStream_t s)
 {
     if (ncols <= 0) return hipSuccess;
     dim3 grid((unsigned)((ncols + 255) / 256));
     if (fn == SNK_XC_PBE)
-        hipLaunchKernelGGL(xc_point_kernel<true>, grid, dim3(256), 0, s, px, py, pz, pw, shells, exps, coefs, nsh, F,
-                           ncols, fn, G, epart);
+        hipLaunchKernelGGL(xc_point_kernel<true>, grid, dim3(256), 0, s, px, py, pz, pw, shells, exps, coefs, nsh,
+                           shell_list, F, ncols, fn, G, epart);
     else
-        hipLaunchKernelGGL(xc_point_kernel<false>, grid, dim3(256), 0, s, px, py, pz, pw, shells, exps, coefs, nsh, F,
-                           ncols, fn, G, epart);
+        hipLaunchKernelGGL(xc_point_kernel<false>, grid, dim3(256), 0, s, px, py, pz, pw, shells, exps, coefs, nsh,
+                           shell_list, F, ncols, fn, G, epart);
     return hipGetLastError();
 }
 

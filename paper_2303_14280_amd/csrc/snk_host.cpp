@@ -221,6 +221,7 @@ struct snk_ctx {
     double* d_xred = nullptr;           // [512] partial sums
     double* d_xsum = nullptr;           // [2] E_xc, N_el
     int32_t* d_iota = nullptr;          // [nbf] identity row / column map
+    double* d_xP = nullptr;             // [max_nB][max_nB] P[B_t, B_t] (basis-screened form)
     int xc_nsplit = 1;
 };
 
@@ -1006,6 +1007,7 @@ void free_ctx(snk_ctx* c)
     (void)hipFree(c->d_xred);
     (void)hipFree(c->d_xsum);
     (void)hipFree(c->d_iota);
+    (void)hipFree(c->d_xP);
     (void)hipFree(c->d_partial);
     (void)hipFree(c->d_ex);
     (void)hipFree(c->d_boys);
@@ -1929,6 +1931,70 @@ int xc_workspace(snk_ctx* c)
     return SNK_OK;
 }
 
+// Basis-screened XC (eps_basis > 0): one tile at a time, buffers of the largest tile
+// (|B_t| rows of at most 16 batches), the V product split per batch.
+int xc_workspace_tiled(snk_ctx* c)
+{
+    const int64_t rows = std::max<int32_t>(1, c->max_nB), cols = std::max<int64_t>(kBatch, c->max_tile_cols);
+    c->xc_cols = cols;
+    c->xc_nsplit = kBasisTileBatches;
+    int rc = 0;
+    if ((rc = dalloc(c, &c->d_xphi, (size_t)(rows * cols))) || (rc = dalloc(c, &c->d_xF, (size_t)(rows * cols))) ||
+        (rc = dalloc(c, &c->d_xG, (size_t)(rows * cols))) || (rc = dalloc(c, &c->d_xe, (size_t)(2 * cols))) ||
+        (rc = dalloc(c, &c->d_xP, (size_t)(rows * rows))) ||
+        (rc = dalloc(c, &c->d_xpart, (size_t)(c->xc_nsplit * rows * rows))) || (rc = dalloc(c, &c->d_xred, 512)) ||
+        (rc = dalloc(c, &c->d_xsum, 2))) {
+        for (double** p : {&c->d_xphi, &c->d_xF, &c->d_xG, &c->d_xe, &c->d_xP, &c->d_xpart, &c->d_xred, &c->d_xsum}) {
+            (void)hipFree(*p);
+            *p = nullptr;
+        }
+        return rc;
+    }
+    return SNK_OK;
+}
+
+// One tile of the basis-screened XC build: Phi_t over B_t, F_t = P[B_t, B_t] Phi_t, the point
+// kernel over the tile's shells, Kt[B_t, B_t] += G_t Phi_t^T (split per batch, fixed order).
+int xc_tile(snk_ctx* c, const Tile& t, const double* dP, int functional)
+{
+    hipStream_t s = c->stream;
+    const int64_t nbf = c->nbf, nB = t.nB, ncols = t.ncols, off = (int64_t)t.b0 * kBatch;
+    const int32_t nsh = (int32_t)t.coll_shells.size();
+    HIPCHECK(c, launch_collocate(c->d_px + off, c->d_py + off, c->d_pz + off, ncols, c->d_shells, c->d_exps, c->d_coefs,
+                                 t.d_coll_shells, t.d_coll_rows, nsh, c->d_xphi, ncols, s));
+    HIPCHECK(c, launch_gather(dP, nbf, t.d_coll_fn, nB, t.d_coll_fn, nB, c->d_xP, s));
+    const int nb = (int)(ncols / kBatch);
+    if (c->blas) {
+        const double one = 1.0, zero = 0.0;
+        if (rocblas_dgemm(c->blas, rocblas_operation_none, rocblas_operation_none, (rocblas_int)ncols, (rocblas_int)nB,
+                          (rocblas_int)nB, &one, c->d_xphi, (rocblas_int)ncols, c->d_xP, (rocblas_int)nB, &zero,
+                          c->d_xF, (rocblas_int)ncols) != rocblas_status_success) {
+            set_err(c, "rocblas_dgemm (XC F) failed");
+            return SNK_E_DEVICE;
+        }
+    } else {
+        HIPCHECK(c, launch_gemm_f64(nB, ncols, nB, c->d_xP, nB, c->d_xphi, ncols, false, c->d_xF, ncols, 1, 0, s));
+    }
+    HIPCHECK(c, launch_xc_point(c->d_px + off, c->d_py + off, c->d_pz + off, c->d_pw + off, ncols, c->d_shells,
+                                c->d_exps, c->d_coefs, nsh, t.d_coll_shells, c->d_xF, functional, c->d_xG, c->d_xe, s));
+    HIPCHECK(c, launch_xc_sum(c->d_xe, ncols, c->d_xred, c->d_xsum, true, s));
+    if (c->blas) {
+        const double one = 1.0, zero = 0.0;
+        if (rocblas_dgemm_strided_batched(c->blas, rocblas_operation_transpose, rocblas_operation_none, (rocblas_int)nB,
+                                          (rocblas_int)nB, kBatch, &one, c->d_xphi, (rocblas_int)ncols, kBatch,
+                                          c->d_xG, (rocblas_int)ncols, kBatch, &zero, c->d_xpart, (rocblas_int)nB,
+                                          nB * nB, nb) != rocblas_status_success) {
+            set_err(c, "rocblas_dgemm (XC V) failed");
+            return SNK_E_DEVICE;
+        }
+    } else {
+        HIPCHECK(c, launch_gemm_f64(nB, nB, ncols, c->d_xG, ncols, c->d_xphi, ncols, true, c->d_xpart, nB, nb, nB * nB,
+                                    s));
+    }
+    HIPCHECK(c, launch_reduce_scatter(c->d_xpart, nb, nB * nB, nB, nB, t.d_coll_fn, t.d_coll_fn, c->d_Kt, nbf, s));
+    return SNK_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1954,13 +2020,22 @@ int snk_vxc_build(snk_ctx* c, const double* P, int functional, double* V_out, do
         dV = c->d_K;
     }
     const int64_t total = (int64_t)c->nbatch * kBatch;
+    const bool tiled = c->opts.eps_basis > 0.0;
     if (!c->d_xsum) {
-        int rc = total > 0 && nbf > 0 ? xc_workspace(c) : dalloc(c, &c->d_xsum, 2);
+        int rc = total > 0 && nbf > 0 ? (tiled ? xc_workspace_tiled(c) : xc_workspace(c)) : dalloc(c, &c->d_xsum, 2);
         if (rc) return rc;
     }
     HIPCHECK(c, launch_fill(c->d_Kt, (int64_t)nb2, 0.0, s));
     HIPCHECK(c, launch_fill(c->d_xsum, 2, 0.0, s));
-    for (int64_t col0 = 0; col0 < total && nbf > 0; col0 += c->xc_cols) {
+    if (tiled && total > 0) {
+        for (const Group& g : c->groups)
+            for (const Tile& t : g.tiles) {
+                if (t.nB == 0) continue;
+                int rc = xc_tile(c, t, dP, functional);
+                if (rc) return rc;
+            }
+    }
+    for (int64_t col0 = 0; col0 < total && nbf > 0 && !tiled; col0 += c->xc_cols) {
         const int64_t ncols = std::min<int64_t>(c->xc_cols, total - col0);
         // Eqs. collocation, fmat
         HIPCHECK(c, launch_xc_collocate(c->d_px + col0, c->d_py + col0, c->d_pz + col0, ncols, c->d_shells, c->d_exps,
@@ -1979,7 +2054,8 @@ int snk_vxc_build(snk_ctx* c, const double* P, int functional, double* V_out, do
         }
         // Eqs. den_grid, exc_grid, zmat
         HIPCHECK(c, launch_xc_point(c->d_px + col0, c->d_py + col0, c->d_pz + col0, c->d_pw + col0, ncols, c->d_shells,
-                                    c->d_exps, c->d_coefs, c->nshell, c->d_xF, functional, c->d_xG, c->d_xe, s));
+                                    c->d_exps, c->d_coefs, c->nshell, nullptr, c->d_xF, functional, c->d_xG, c->d_xe,
+                                    s));
         HIPCHECK(c, launch_xc_sum(c->d_xe, ncols, c->d_xred, c->d_xsum, true, s));
         // Eq. vxc_num: Kt += G Phi^T over the chunk's points, split over points, fixed-order sum
         if (c->blas) {

@@ -298,7 +298,8 @@ hipError_t launch_xc_collocate(const double* px, const double* py, const double*
                                const int32_t* shell_row, int32_t nsh, double* Phi, hipStream_t s);
 hipError_t launch_xc_point(const double* px, const double* py, const double* pz, const double* pw, int64_t ncols,
                            const ShellDev* shells, const double* exps, const double* coefs, int32_t nsh,
-                           const double* F, int fn, double* G, double* epart, hipStream_t s);
+                           const int32_t* shell_list, const double* F, int fn, double* G, double* epart,
+                           hipStream_t s);
 hipError_t launch_xc_sum(const double* epart, int64_t n, double* partial, double* out, bool accumulate, hipStream_t s);
 hipError_t launch_boys_eval(const double* T, int64_t n, int mmax, double* F, const double* tab, hipStream_t s);
 // out[rows[m] * ld + c] = in[m * ncols + c] for m < M, c < ncols

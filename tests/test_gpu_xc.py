@@ -103,3 +103,38 @@ def test_empty_and_negligible_density():
     assert not np.any(V) and exc == 0.0 and nel == 0.0
     with pytest.raises(snk.SnkError):
         ctx.vxc(s.P, 7)
+
+
+def test_basis_screened_tight_matches_oracle():
+    """eps_basis = 1e-13 (tiles of at most 16 batches, each over its functions B_t; small
+    groups so that tiles drop functions): the dropped basis values are below 1e-13, so V^xc and
+    E_xc keep the unscreened parity bar against the oracle."""
+    s = synth.make_system(1)
+    ctx = snk.Context(s, eps_basis=1e-13, max_device_bytes=6 * s.nbf * 256 * 24)
+    sizes = [fn.size for _, _, _, fn in ctx.tiles()]
+    assert min(sizes) < s.nbf
+    for functional in (snk.SNK_XC_LDA, snk.SNK_XC_PBE):
+        V, exc, nel = ctx.vxc(s.P, functional)
+        compare(V, exc, nel, s, functional, "config1 eps_basis 1e-13 (|B_t| mean %.1f of %d)" %
+                (np.mean(sizes), s.nbf))
+
+
+@pytest.mark.parametrize("cfg,stride", [(3, 256), (4, 4096)])
+def test_basis_screened_sampled_large(cfg, stride):
+    """The 150- and 500-atom clusters at their real basis size, on a seeded subset of their grid
+    points, basis-screened at the paper's tolerance (1e-9), against the unscreened oracle on
+    the same points: |dE_xc| <= 1e-6 Eh and max|dV| <= 1e-6 max|V|."""
+    s = synth.make_system(cfg)
+    off = int(np.random.default_rng([cfg, 91]).integers(stride))
+    s = s.subset_points(np.arange(off, s.npts, stride))
+    ctx = snk.Context(s, eps_basis=1e-9, flags=snk.SNK_ROCBLAS)
+    sizes = [fn.size for _, _, _, fn in ctx.tiles()]
+    V, exc, nel = ctx.vxc(s.P, snk.SNK_XC_PBE)
+    Vr, er, nr = X.vxc(s, X.PBE, chunk=4000)
+    dV = float(np.max(np.abs(V - Vr)))
+    say("config %d / %d points, |B_t| mean %.1f of %d: E_xc %.10f (oracle %.10f) |dE| %.2e, N_el %.8f (oracle %.8f), "
+        "max|dV| %.2e of %.2e" % (cfg, s.npts, np.mean(sizes), s.nbf, exc, er, abs(exc - er), nel, nr, dV,
+                                  np.max(np.abs(Vr))))
+    assert np.array_equal(V, V.T)
+    assert abs(exc - er) <= 1e-6 and abs(nel - nr) <= 1e-6
+    assert dV <= 1e-6 * float(np.max(np.abs(Vr)))
