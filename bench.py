@@ -219,7 +219,7 @@ def large_system(config, stream, args):
     screening (eps_basis 1e-9): the plain FP64 build (no density screen; one timed build, the
     reference for E_x and K), FP64 with the rigorous density screen (5e-7 Eh), and the learned
     screen in FP64 and in the mixed build, each timed over `args.large_steps` builds after one
-    warm-up."""
+    warm-up; then the basis-screened PBE exchange-correlation potential of the same density."""
     import torch
     from paper_2303_14280_amd import snk, synth
     if not os.path.exists(snk.SCREENER_WEIGHTS):
@@ -275,6 +275,21 @@ def large_system(config, stream, args):
                 r["speedup_vs_fp64_bound"] = res["fp64+bound"]["ms_per_step"] / ms
         log("config %d %s: %.1f ms/step, E_x %.10f" % (config, name, ms, st["ex"]))
         res[name] = r
+    if not args.no_xc:
+        # the XC potential of the same density over the same tiles (basis-screened, PBE)
+        ctx = snk.Context(s, flags=R, stream=stream.cuda_stream, device=0, eps_basis=1e-9)
+        V = torch.empty_like(P)
+        ctx.vxc_device(P.data_ptr(), V.data_ptr(), snk.SNK_XC_PBE)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for i in range(args.large_steps):
+            ctx.vxc_device(P.data_ptr(), V.data_ptr(), snk.SNK_XC_PBE)
+        torch.cuda.synchronize()
+        ms = 1000.0 * (time.perf_counter() - t) / args.large_steps
+        exc, nel = ctx.vxc_device(P.data_ptr(), V.data_ptr(), snk.SNK_XC_PBE, scalars=True)
+        ctx.close()
+        res["xc_pbe"] = {"ms_per_build": ms, "exc": exc, "nel": nel}
+        log("config %d XC PBE: %.1f ms/build, E_xc %.10f, N_el %.6f" % (config, ms, exc, nel))
     return res
 
 
