@@ -169,31 +169,38 @@ __global__ __launch_bounds__(256) void xc_collocate_kernel(const double* __restr
     }
 }
 
-// One lane per column.  Phi and its gradient are recomputed from the shell data in both
-// passes instead of being read from memory (a few exponentials per shell against four
-// 8-byte loads per function): the kernel reads only F and writes G, whose rows follow the
-// shells of shell_list (NULL: every shell in order), ld = ncols.
+// One lane per column of a launch over one or more tiles (a chunk of the unscreened build,
+// or every tile of a batch group of the basis-screened build).  The basis values and
+// gradients are recomputed from the shell data in both passes instead of being read from
+// memory (a few exponentials per shell against four 8-byte loads per function): the kernel
+// reads only F and writes G, whose rows follow the tile's shells.
 template <bool GGA>
 __global__ __launch_bounds__(256) void xc_point_kernel(const double* __restrict__ px, const double* __restrict__ py,
                                                        const double* __restrict__ pz, const double* __restrict__ pw,
                                                        const ShellDev* __restrict__ shells,
                                                        const double* __restrict__ exps,
-                                                       const double* __restrict__ coefs, int32_t nsh,
-                                                       const int32_t* __restrict__ shell_list,
+                                                       const double* __restrict__ coefs,
+                                                       const XcTile* __restrict__ tiles,
+                                                       const int32_t* __restrict__ shell_cat, int32_t tile_batches,
                                                        const double* __restrict__ F, int64_t ncols, int fn,
                                                        double* __restrict__ G, double* __restrict__ epart)
 {
     const int64_t col = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (col >= ncols) return;
+    const int tix = (int)(blockIdx.x / (unsigned)tile_batches);
+    const XcTile t = tiles[tix];
+    const int64_t lc = col - (int64_t)tix * tile_batches * kBatch;   // column within the tile
+    const double* Ft = F + t.phi_off + lc;
+    double* Gt = G + t.phi_off + lc;
     const double x = px[col], y = py[col], z = pz[col];
     double v[6], vx[6], vy[6], vz[6];
     double rho = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
     int64_t row = 0;
-    for (int si = 0; si < nsh; ++si) {
-        const ShellDev sh = shells[shell_list ? shell_list[si] : si];
+    for (int si = 0; si < t.nsh; ++si) {
+        const ShellDev sh = shells[shell_cat[t.sh_off + si]];
         const int n = shell_values<GGA>(sh, exps, coefs, x - sh.x, y - sh.y, z - sh.z, v, vx, vy, vz);
         for (int i = 0; i < n; ++i) {
-            const double f = F[(row + i) * ncols + col];
+            const double f = Ft[(row + i) * t.ncols];
             rho = fma(f, v[i], rho);
             if constexpr (GGA) {
                 gx = fma(f, vx[i], gx);
@@ -214,13 +221,13 @@ __global__ __launch_bounds__(256) void xc_point_kernel(const double* __restrict_
     const double b = 4.0 * w * e.vs;
     const double bx = b * gx, by = b * gy, bz = b * gz;
     row = 0;
-    for (int si = 0; si < nsh; ++si) {
-        const ShellDev sh = shells[shell_list ? shell_list[si] : si];
+    for (int si = 0; si < t.nsh; ++si) {
+        const ShellDev sh = shells[shell_cat[t.sh_off + si]];
         const int n = shell_values<GGA>(sh, exps, coefs, x - sh.x, y - sh.y, z - sh.z, v, vx, vy, vz);
         for (int i = 0; i < n; ++i) {
             double g = a * v[i];
             if constexpr (GGA) g = fma(bx, vx[i], fma(by, vy[i], fma(bz, vz[i], g)));
-            G[(row + i) * ncols + col] = g;
+            Gt[(row + i) * t.ncols] = g;
         }
         row += n;
     }
@@ -290,18 +297,19 @@ hipError_t launch_xc_collocate(const double* px, const double* py, const double*
 }
 
 hipError_t launch_xc_point(const double* px, const double* py, const double* pz, const double* pw, int64_t ncols,
-                           const ShellDev* shells, const double* exps, const double* coefs, int32_t nsh,
-                           const int32_t* shell_list, const double* F, int fn, double* G, double* epart,
-                           hipStream_t s)
+                           const ShellDev* shells, const double* exps, const double* coefs, const XcTile* tiles,
+                           const int32_t* shell_cat, int32_t tile_batches, const double* F, int fn, double* G,
+                           double* epart, hipStream_t s)
 {
     if (ncols <= 0) return hipSuccess;
+    if (tile_batches < 1) return hipErrorInvalidValue;
     dim3 grid((unsigned)((ncols + 255) / 256));
     if (fn == SNK_XC_PBE)
-        hipLaunchKernelGGL(xc_point_kernel<true>, grid, dim3(256), 0, s, px, py, pz, pw, shells, exps, coefs, nsh,
-                           shell_list, F, ncols, fn, G, epart);
+        hipLaunchKernelGGL(xc_point_kernel<true>, grid, dim3(256), 0, s, px, py, pz, pw, shells, exps, coefs, tiles,
+                           shell_cat, tile_batches, F, ncols, fn, G, epart);
     else
-        hipLaunchKernelGGL(xc_point_kernel<false>, grid, dim3(256), 0, s, px, py, pz, pw, shells, exps, coefs, nsh,
-                           shell_list, F, ncols, fn, G, epart);
+        hipLaunchKernelGGL(xc_point_kernel<false>, grid, dim3(256), 0, s, px, py, pz, pw, shells, exps, coefs, tiles,
+                           shell_cat, tile_batches, F, ncols, fn, G, epart);
     return hipGetLastError();
 }
 

@@ -222,6 +222,9 @@ struct snk_ctx {
     double* d_xsum = nullptr;           // [2] E_xc, N_el
     int32_t* d_iota = nullptr;          // [nbf] identity row / column map
     double* d_xP = nullptr;             // [max_nB][max_nB] P[B_t, B_t] (basis-screened form)
+    XcTile* d_xtiles = nullptr;         // point-kernel tiles: one per chunk, or every tile of every group
+    int32_t* d_xshells = nullptr;       // their shell lists, concatenated
+    std::vector<int32_t> xc_gt0;        // first tile of each group in d_xtiles (basis-screened form)
     int xc_nsplit = 1;
 };
 
@@ -1008,6 +1011,8 @@ void free_ctx(snk_ctx* c)
     (void)hipFree(c->d_xsum);
     (void)hipFree(c->d_iota);
     (void)hipFree(c->d_xP);
+    (void)hipFree(c->d_xtiles);
+    (void)hipFree(c->d_xshells);
     (void)hipFree(c->d_partial);
     (void)hipFree(c->d_ex);
     (void)hipFree(c->d_boys);
@@ -1915,83 +1920,126 @@ int xc_workspace(snk_ctx* c)
     c->xc_cols = cols;
     std::vector<int32_t> iota((size_t)nbf);
     std::iota(iota.begin(), iota.end(), 0);
+    // one point-kernel tile per chunk: every shell, F and G rows of stride ncols from 0
+    std::vector<XcTile> tiles;
+    for (int64_t col0 = 0; col0 < total; col0 += cols)
+        tiles.push_back(XcTile{0, (int32_t)std::min<int64_t>(cols, total - col0), 0, c->nshell, 0});
+    std::vector<int32_t> shells((size_t)c->nshell);
+    std::iota(shells.begin(), shells.end(), 0);
     int rc = 0;
     if ((rc = dalloc(c, &c->d_xphi, (size_t)(nbf * cols))) || (rc = dalloc(c, &c->d_xF, (size_t)(nbf * cols))) ||
         (rc = dalloc(c, &c->d_xG, (size_t)(nbf * cols))) || (rc = dalloc(c, &c->d_xe, (size_t)(2 * cols))) ||
         (rc = dalloc(c, &c->d_xpart, (size_t)c->xc_nsplit * nbf * nbf)) || (rc = dalloc(c, &c->d_xred, 512)) ||
-        (rc = upload(c, &c->d_iota, iota)) || (rc = dalloc(c, &c->d_xsum, 2))) {
+        (rc = upload(c, &c->d_iota, iota)) || (rc = upload(c, &c->d_xtiles, tiles)) ||
+        (rc = upload(c, &c->d_xshells, shells)) || (rc = dalloc(c, &c->d_xsum, 2))) {
         for (double** p : {&c->d_xphi, &c->d_xF, &c->d_xG, &c->d_xe, &c->d_xpart, &c->d_xred, &c->d_xsum}) {
             (void)hipFree(*p);
             *p = nullptr;
         }
         (void)hipFree(c->d_iota);
+        (void)hipFree(c->d_xtiles);
+        (void)hipFree(c->d_xshells);
         c->d_iota = nullptr;
+        c->d_xtiles = nullptr;
+        c->d_xshells = nullptr;
         return rc;
     }
     return SNK_OK;
 }
 
-// Basis-screened XC (eps_basis > 0): one tile at a time, buffers of the largest tile
-// (|B_t| rows of at most 16 batches), the V product split per batch.
+// Basis-screened XC (eps_basis > 0): one batch group at a time in the sn-K group layout
+// (tile t's Phi_t, F_t and G_t at phi_off, |B_t| rows of stride ncols_t), one point-kernel
+// launch per group, the tile products one after the other.
 int xc_workspace_tiled(snk_ctx* c)
 {
-    const int64_t rows = std::max<int32_t>(1, c->max_nB), cols = std::max<int64_t>(kBatch, c->max_tile_cols);
+    int64_t cols = kBatch;
+    std::vector<XcTile> tiles;
+    std::vector<int32_t> shells;
+    c->xc_gt0.clear();
+    for (const Group& g : c->groups) {
+        cols = std::max<int64_t>(cols, g.ncols);
+        c->xc_gt0.push_back((int32_t)tiles.size());
+        for (const Tile& t : g.tiles) {
+            tiles.push_back(XcTile{t.phi_off, (int32_t)t.ncols, (int32_t)shells.size(), (int32_t)t.coll_shells.size(), 0});
+            shells.insert(shells.end(), t.coll_shells.begin(), t.coll_shells.end());
+        }
+    }
+    const int64_t elems = std::max<int64_t>(1, c->max_phi), rows = std::max<int32_t>(1, c->max_nB);
     c->xc_cols = cols;
     c->xc_nsplit = kBasisTileBatches;
     int rc = 0;
-    if ((rc = dalloc(c, &c->d_xphi, (size_t)(rows * cols))) || (rc = dalloc(c, &c->d_xF, (size_t)(rows * cols))) ||
-        (rc = dalloc(c, &c->d_xG, (size_t)(rows * cols))) || (rc = dalloc(c, &c->d_xe, (size_t)(2 * cols))) ||
+    if ((rc = dalloc(c, &c->d_xphi, (size_t)elems)) || (rc = dalloc(c, &c->d_xF, (size_t)elems)) ||
+        (rc = dalloc(c, &c->d_xG, (size_t)elems)) || (rc = dalloc(c, &c->d_xe, (size_t)(2 * cols))) ||
         (rc = dalloc(c, &c->d_xP, (size_t)(rows * rows))) ||
         (rc = dalloc(c, &c->d_xpart, (size_t)(c->xc_nsplit * rows * rows))) || (rc = dalloc(c, &c->d_xred, 512)) ||
+        (rc = upload(c, &c->d_xtiles, tiles)) || (rc = upload(c, &c->d_xshells, shells)) ||
         (rc = dalloc(c, &c->d_xsum, 2))) {
         for (double** p : {&c->d_xphi, &c->d_xF, &c->d_xG, &c->d_xe, &c->d_xP, &c->d_xpart, &c->d_xred, &c->d_xsum}) {
             (void)hipFree(*p);
             *p = nullptr;
         }
+        (void)hipFree(c->d_xtiles);
+        (void)hipFree(c->d_xshells);
+        c->d_xtiles = nullptr;
+        c->d_xshells = nullptr;
         return rc;
     }
     return SNK_OK;
 }
 
-// One tile of the basis-screened XC build: Phi_t over B_t, F_t = P[B_t, B_t] Phi_t, the point
-// kernel over the tile's shells, Kt[B_t, B_t] += G_t Phi_t^T (split per batch, fixed order).
-int xc_tile(snk_ctx* c, const Tile& t, const double* dP, int functional)
+// One batch group of the basis-screened XC build: Phi_t over B_t and F_t = P[B_t, B_t] Phi_t per
+// tile, the point kernel over all tiles at once, then Kt[B_t, B_t] += G_t Phi_t^T per tile
+// (split per batch, fixed order).
+int xc_group(snk_ctx* c, size_t gi, const double* dP, int functional)
 {
     hipStream_t s = c->stream;
-    const int64_t nbf = c->nbf, nB = t.nB, ncols = t.ncols, off = (int64_t)t.b0 * kBatch;
-    const int32_t nsh = (int32_t)t.coll_shells.size();
-    HIPCHECK(c, launch_collocate(c->d_px + off, c->d_py + off, c->d_pz + off, ncols, c->d_shells, c->d_exps, c->d_coefs,
-                                 t.d_coll_shells, t.d_coll_rows, nsh, c->d_xphi, ncols, s));
-    HIPCHECK(c, launch_gather(dP, nbf, t.d_coll_fn, nB, t.d_coll_fn, nB, c->d_xP, s));
-    const int nb = (int)(ncols / kBatch);
-    if (c->blas) {
-        const double one = 1.0, zero = 0.0;
-        if (rocblas_dgemm(c->blas, rocblas_operation_none, rocblas_operation_none, (rocblas_int)ncols, (rocblas_int)nB,
-                          (rocblas_int)nB, &one, c->d_xphi, (rocblas_int)ncols, c->d_xP, (rocblas_int)nB, &zero,
-                          c->d_xF, (rocblas_int)ncols) != rocblas_status_success) {
-            set_err(c, "rocblas_dgemm (XC F) failed");
-            return SNK_E_DEVICE;
+    const Group& g = c->groups[gi];
+    const int64_t nbf = c->nbf, goff = (int64_t)g.b0 * kBatch;
+    for (const Tile& t : g.tiles) {
+        if (t.nB == 0) continue;
+        const int64_t nB = t.nB, ncols = t.ncols, off = (int64_t)t.b0 * kBatch;
+        double* Phi = c->d_xphi + t.phi_off;
+        double* F = c->d_xF + t.phi_off;
+        HIPCHECK(c, launch_collocate(c->d_px + off, c->d_py + off, c->d_pz + off, ncols, c->d_shells, c->d_exps,
+                                     c->d_coefs, t.d_coll_shells, t.d_coll_rows, (int32_t)t.coll_shells.size(), Phi,
+                                     ncols, s));
+        HIPCHECK(c, launch_gather(dP, nbf, t.d_coll_fn, nB, t.d_coll_fn, nB, c->d_xP, s));
+        if (c->blas) {
+            const double one = 1.0, zero = 0.0;
+            if (rocblas_dgemm(c->blas, rocblas_operation_none, rocblas_operation_none, (rocblas_int)ncols,
+                              (rocblas_int)nB, (rocblas_int)nB, &one, Phi, (rocblas_int)ncols, c->d_xP, (rocblas_int)nB,
+                              &zero, F, (rocblas_int)ncols) != rocblas_status_success) {
+                set_err(c, "rocblas_dgemm (XC F) failed");
+                return SNK_E_DEVICE;
+            }
+        } else {
+            HIPCHECK(c, launch_gemm_f64(nB, ncols, nB, c->d_xP, nB, Phi, ncols, false, F, ncols, 1, 0, s));
         }
-    } else {
-        HIPCHECK(c, launch_gemm_f64(nB, ncols, nB, c->d_xP, nB, c->d_xphi, ncols, false, c->d_xF, ncols, 1, 0, s));
     }
-    HIPCHECK(c, launch_xc_point(c->d_px + off, c->d_py + off, c->d_pz + off, c->d_pw + off, ncols, c->d_shells,
-                                c->d_exps, c->d_coefs, nsh, t.d_coll_shells, c->d_xF, functional, c->d_xG, c->d_xe, s));
-    HIPCHECK(c, launch_xc_sum(c->d_xe, ncols, c->d_xred, c->d_xsum, true, s));
-    if (c->blas) {
-        const double one = 1.0, zero = 0.0;
-        if (rocblas_dgemm_strided_batched(c->blas, rocblas_operation_transpose, rocblas_operation_none, (rocblas_int)nB,
-                                          (rocblas_int)nB, kBatch, &one, c->d_xphi, (rocblas_int)ncols, kBatch,
-                                          c->d_xG, (rocblas_int)ncols, kBatch, &zero, c->d_xpart, (rocblas_int)nB,
-                                          nB * nB, nb) != rocblas_status_success) {
-            set_err(c, "rocblas_dgemm (XC V) failed");
-            return SNK_E_DEVICE;
+    HIPCHECK(c, launch_xc_point(c->d_px + goff, c->d_py + goff, c->d_pz + goff, c->d_pw + goff, g.ncols, c->d_shells,
+                                c->d_exps, c->d_coefs, c->d_xtiles + c->xc_gt0[gi], c->d_xshells, c->tile_batches,
+                                c->d_xF, functional, c->d_xG, c->d_xe, s));
+    HIPCHECK(c, launch_xc_sum(c->d_xe, g.ncols, c->d_xred, c->d_xsum, true, s));
+    for (const Tile& t : g.tiles) {
+        if (t.nB == 0) continue;
+        const int64_t nB = t.nB, ncols = t.ncols;
+        const int nb = (int)(ncols / kBatch);
+        const double* Phi = c->d_xphi + t.phi_off;
+        const double* G = c->d_xG + t.phi_off;
+        if (c->blas) {
+            const double one = 1.0, zero = 0.0;
+            if (rocblas_dgemm_strided_batched(c->blas, rocblas_operation_transpose, rocblas_operation_none,
+                                              (rocblas_int)nB, (rocblas_int)nB, kBatch, &one, Phi, (rocblas_int)ncols,
+                                              kBatch, G, (rocblas_int)ncols, kBatch, &zero, c->d_xpart,
+                                              (rocblas_int)nB, nB * nB, nb) != rocblas_status_success) {
+                set_err(c, "rocblas_dgemm (XC V) failed");
+                return SNK_E_DEVICE;
+            }
+        } else {
+            HIPCHECK(c, launch_gemm_f64(nB, nB, ncols, G, ncols, Phi, ncols, true, c->d_xpart, nB, nb, nB * nB, s));
         }
-    } else {
-        HIPCHECK(c, launch_gemm_f64(nB, nB, ncols, c->d_xG, ncols, c->d_xphi, ncols, true, c->d_xpart, nB, nb, nB * nB,
-                                    s));
+        HIPCHECK(c, launch_reduce_scatter(c->d_xpart, nb, nB * nB, nB, nB, t.d_coll_fn, t.d_coll_fn, c->d_Kt, nbf, s));
     }
-    HIPCHECK(c, launch_reduce_scatter(c->d_xpart, nb, nB * nB, nB, nB, t.d_coll_fn, t.d_coll_fn, c->d_Kt, nbf, s));
     return SNK_OK;
 }
 
@@ -2028,14 +2076,12 @@ int snk_vxc_build(snk_ctx* c, const double* P, int functional, double* V_out, do
     HIPCHECK(c, launch_fill(c->d_Kt, (int64_t)nb2, 0.0, s));
     HIPCHECK(c, launch_fill(c->d_xsum, 2, 0.0, s));
     if (tiled && total > 0) {
-        for (const Group& g : c->groups)
-            for (const Tile& t : g.tiles) {
-                if (t.nB == 0) continue;
-                int rc = xc_tile(c, t, dP, functional);
-                if (rc) return rc;
-            }
+        for (size_t gi = 0; gi < c->groups.size(); ++gi) {
+            int rc = xc_group(c, gi, dP, functional);
+            if (rc) return rc;
+        }
     }
-    for (int64_t col0 = 0; col0 < total && nbf > 0 && !tiled; col0 += c->xc_cols) {
+    for (int64_t col0 = 0, chunk = 0; col0 < total && nbf > 0 && !tiled; col0 += c->xc_cols, ++chunk) {
         const int64_t ncols = std::min<int64_t>(c->xc_cols, total - col0);
         // Eqs. collocation, fmat
         HIPCHECK(c, launch_xc_collocate(c->d_px + col0, c->d_py + col0, c->d_pz + col0, ncols, c->d_shells, c->d_exps,
@@ -2054,8 +2100,8 @@ int snk_vxc_build(snk_ctx* c, const double* P, int functional, double* V_out, do
         }
         // Eqs. den_grid, exc_grid, zmat
         HIPCHECK(c, launch_xc_point(c->d_px + col0, c->d_py + col0, c->d_pz + col0, c->d_pw + col0, ncols, c->d_shells,
-                                    c->d_exps, c->d_coefs, c->nshell, nullptr, c->d_xF, functional, c->d_xG, c->d_xe,
-                                    s));
+                                    c->d_exps, c->d_coefs, c->d_xtiles + chunk, c->d_xshells,
+                                    (int32_t)(ncols / kBatch), c->d_xF, functional, c->d_xG, c->d_xe, s));
         HIPCHECK(c, launch_xc_sum(c->d_xe, ncols, c->d_xred, c->d_xsum, true, s));
         // Eq. vxc_num: Kt += G Phi^T over the chunk's points, split over points, fixed-order sum
         if (c->blas) {

@@ -296,10 +296,17 @@ hipError_t launch_finish(const double* Kt, const double* P, double* K, int64_t n
 hipError_t launch_xc_collocate(const double* px, const double* py, const double* pz, int64_t ncols,
                                const ShellDev* shells, const double* exps, const double* coefs,
                                const int32_t* shell_row, int32_t nsh, double* Phi, hipStream_t s);
+// One tile of an XC launch: its F and G rows start at phi_off (row stride ncols), its shells
+// are shell_cat[sh_off .. sh_off + nsh) in row order.  Tile k covers columns
+// [k * tile_batches * kBatch, ...) of the launch.
+struct XcTile {
+    int64_t phi_off;
+    int32_t ncols, sh_off, nsh, pad;
+};
 hipError_t launch_xc_point(const double* px, const double* py, const double* pz, const double* pw, int64_t ncols,
-                           const ShellDev* shells, const double* exps, const double* coefs, int32_t nsh,
-                           const int32_t* shell_list, const double* F, int fn, double* G, double* epart,
-                           hipStream_t s);
+                           const ShellDev* shells, const double* exps, const double* coefs, const XcTile* tiles,
+                           const int32_t* shell_cat, int32_t tile_batches, const double* F, int fn, double* G,
+                           double* epart, hipStream_t s);
 hipError_t launch_xc_sum(const double* epart, int64_t n, double* partial, double* out, bool accumulate, hipStream_t s);
 hipError_t launch_boys_eval(const double* T, int64_t n, int mmax, double* F, const double* tab, hipStream_t s);
 // out[rows[m] * ld + c] = in[m * ncols + c] for m < M, c < ncols
