@@ -220,11 +220,15 @@ int snk_ctx_tile_functions(const snk_ctx* ctx, int32_t tile, int32_t* fn);
  * SNK_DEVICE_PTRS flag says; the call is ordered on the context's stream and returns after
  * the scalars are in host memory when exc_out or nel_out is given (host-pointer mode:
  * always synchronous).  Each call may reuse buffers of the context: calls on one context do
- * not overlap.  All arithmetic FP64; the basis and grid are the context's (density and
- * basis screening settings do not apply).  SNK_E_ARG for a NULL context, P or V_out or an
- * unknown functional; SNK_E_NOMEM when the workspace (3 nbf doubles per grid point of a
- * chunk of batches, chunks sized to max_device_bytes or a quarter of free device memory)
- * does not fit.
+ * not overlap.  All arithmetic FP64; the basis and grid are the context's (its precision and
+ * density screen do not apply).  With eps_basis > 0 the build runs over the context's
+ * batch groups and tiles: tile t uses only its functions B_t (F_t = P[B_t, B_t] Phi_t,
+ * V[B_t, B_t] += ...), dropping basis values below eps_basis as sn-K does.  SNK_E_ARG for a
+ * NULL context, P or V_out, an unknown functional or (host pointers) a non-finite element of
+ * P; SNK_E_ASYM with SNK_VALIDATE for an asymmetric P (host pointers); SNK_E_NOMEM when the
+ * workspace (3 nbf doubles per grid point of a chunk of batches, chunks sized to
+ * max_device_bytes or a quarter of free device memory; with eps_basis > 0, three buffers of
+ * the largest group's tiles) does not fit.
  */
 #define SNK_XC_SLATER 1   /* Dirac-Slater exchange */
 #define SNK_XC_LDA    2   /* Slater exchange + Perdew-Wang 1992 correlation (zeta = 0) */

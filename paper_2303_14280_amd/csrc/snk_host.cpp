@@ -1894,6 +1894,29 @@ struct PipeSwap {
 
 namespace {
 
+// Host-pointer density matrix: finite elements, and with SNK_VALIDATE symmetric to
+// 1e-12 of its largest element.
+int check_density(snk_ctx* c, const double* P)
+{
+    const int64_t nbf = c->nbf;
+    const size_t nb2 = (size_t)nbf * nbf;
+    for (size_t k = 0; k < nb2; ++k)
+        if (!isfin(P[k])) return arg_error(c, "non-finite density matrix element");
+    if (c->opts.flags & SNK_VALIDATE) {
+        double mx = 0.0, asym = 0.0;
+        for (int64_t i = 0; i < nbf; ++i)
+            for (int64_t j = 0; j < nbf; ++j) {
+                mx = std::max(mx, std::fabs(P[i * nbf + j]));
+                asym = std::max(asym, std::fabs(P[i * nbf + j] - P[j * nbf + i]));
+            }
+        if (asym > 1e-12 * mx) {
+            set_err(c, "density matrix is not symmetric");
+            return SNK_E_ASYM;
+        }
+    }
+    return SNK_OK;
+}
+
 // XC workspace: chunks of whole batches sized to the device budget (three nbf-row buffers of
 // FP64 per column: Phi, F, G), and the split of the Z Phi^T product over grid points that fills the
 // device with nbf x nbf outputs of 64 x 64 tiles.
@@ -2055,9 +2078,10 @@ int snk_vxc_build(snk_ctx* c, const double* P, int functional, double* V_out, do
     const bool dev = (c->opts.flags & SNK_DEVICE_PTRS) != 0;
     const int64_t nbf = c->nbf;
     const size_t nb2 = (size_t)nbf * nbf;
-    if (!dev)
-        for (size_t k = 0; k < nb2; ++k)
-            if (!isfin(P[k])) return arg_error(c, "non-finite density matrix element");
+    if (!dev) {
+        int rc = check_density(c, P);
+        if (rc) return rc;
+    }
     HIPCHECK(c, hipSetDevice(c->device));
     hipStream_t s = c->stream;
     const double* dP = P;
@@ -2157,20 +2181,8 @@ int snk_ctx_build(snk_ctx* c, const double* P, double* K_out, snk_stats* stats)
     const int64_t nbf = c->nbf;
     const size_t nb2 = (size_t)nbf * nbf;
     if (!dev) {
-        for (size_t k = 0; k < nb2; ++k)
-            if (!isfin(P[k])) return arg_error(c, "non-finite density matrix element");
-        if (c->opts.flags & SNK_VALIDATE) {
-            double mx = 0.0, asym = 0.0;
-            for (int64_t i = 0; i < nbf; ++i)
-                for (int64_t j = 0; j < nbf; ++j) {
-                    mx = std::max(mx, std::fabs(P[i * nbf + j]));
-                    asym = std::max(asym, std::fabs(P[i * nbf + j] - P[j * nbf + i]));
-                }
-            if (asym > 1e-12 * mx) {
-                set_err(c, "density matrix is not symmetric");
-                return SNK_E_ASYM;
-            }
-        }
+        int rc = check_density(c, P);
+        if (rc) return rc;
     }
     const auto t_start = std::chrono::steady_clock::now();
     HIPCHECK(c, hipSetDevice(c->device));

@@ -103,6 +103,14 @@ def test_empty_and_negligible_density():
     assert not np.any(V) and exc == 0.0 and nel == 0.0
     with pytest.raises(snk.SnkError):
         ctx.vxc(s.P, 7)
+    bad = s.P.copy()
+    bad[0, 0] = np.nan
+    with pytest.raises(snk.SnkError):
+        ctx.vxc(bad, snk.SNK_XC_LDA)
+    asym = s.P.copy()
+    asym[0, 1] += 1.0
+    with pytest.raises(snk.SnkError):
+        snk.Context(s, flags=snk.SNK_VALIDATE).vxc(asym, snk.SNK_XC_LDA)
 
 
 def test_basis_screened_tight_matches_oracle():
