@@ -26,7 +26,14 @@ namespace {
 
 using namespace os3c;
 
-template <int LA, int LB, int TA, typename TF, typename R>
+// Grid points per lane (NP): a lane evaluates every primitive-pair record for NP points of its
+// batch (workgroups of 256 / NP lanes), so that each scalar record load and loop step serves
+// NP times the vector work.  Two points pay off only for the p-s class of unscreened
+// launches (every batch walks the same full work list); screened launches and the other
+// classes run one point per lane (measured: the extra registers cost more occupancy there).
+constexpr int kPointsPerLanePs = 2;
+
+template <int LA, int LB, int TA, int NP, typename TF, typename R>
 __global__ __launch_bounds__(256) void afg_kernel(const double* __restrict__ px, const double* __restrict__ py,
                                                   const double* __restrict__ pz, const double* __restrict__ pw,
                                                   const TF* __restrict__ F, double* __restrict__ G, int64_t ld,
@@ -40,14 +47,25 @@ __global__ __launch_bounds__(256) void afg_kernel(const double* __restrict__ px,
     constexpr int NA = ncart(LA), NB = ncart(LB);
     constexpr int RS = 2 + TA;        // run record stride
     constexpr int BS = 2 + 2 * TA;    // B-task record stride
-    __shared__ R tab[kBoysRows * kBoysCols];
-    for (int i = threadIdx.x; i < kBoysRows * kBoysCols; i += blockDim.x) tab[i] = (R)gtab[i];
+    constexpr int STRIDE = kBatch / NP;   // lanes per workgroup; lane t owns points t, t + STRIDE, ...
+    // the Boys table columns this class reads (m + j <= l_A + l_B + terms - 1), in LDS
+    constexpr int TC = LA + LB + boys_terms<R>();
+    __shared__ R tab[kBoysRows * TC];
+    for (int i = threadIdx.x; i < kBoysRows * TC; i += blockDim.x) tab[i] = (R)gtab[(i / TC) * kBoysCols + i % TC];
     __syncthreads();
 
     const int batch = blockIdx.x;
-    const int64_t col = (int64_t)batch * kBatch + threadIdx.x;
-    const R cx = (R)px[col], cy = (R)py[col], cz = (R)pz[col];
-    const double w = pw[col];
+    int64_t col[NP];
+    R cx[NP], cy[NP], cz[NP];
+    double w[NP];
+    sfor<0, NP>([&](auto pc) {
+        constexpr int p = CV(pc);
+        col[p] = (int64_t)batch * kBatch + threadIdx.x + p * STRIDE;
+        cx[p] = (R)px[col[p]];
+        cy[p] = (R)py[col[p]];
+        cz[p] = (R)pz[col[p]];
+        w[p] = pw[col[p]];
+    });
 
     int r0 = 0, r1 = nrun;
     if (batch_run_off) {
@@ -58,38 +76,48 @@ __global__ __launch_bounds__(256) void afg_kernel(const double* __restrict__ px,
         const int32_t* run = runs + (int64_t)r * RS;
         const int b0 = run[0], b1 = run[1];
         int arow[TA];
-        R Fa[TA][NA], Ga[TA][NA];
+        R Fa[NP][TA][NA], Ga[NP][TA][NA];
         sfor<0, TA>([&](auto kc) {
             constexpr int k = CV(kc);
             arow[k] = run[2 + k];
-            sfor<0, NA>([&](auto ic) {
-                constexpr int i = CV(ic);
-                Fa[k][i] = arow[k] >= 0 ? (R)(cnorm(LA, i) * (double)F[(int64_t)(arow[k] + i) * ld + col]) : (R)0;
-                Ga[k][i] = (R)0;
+            sfor<0, NP>([&](auto pc) {
+                constexpr int p = CV(pc);
+                sfor<0, NA>([&](auto ic) {
+                    constexpr int i = CV(ic);
+                    Fa[p][k][i] = arow[k] >= 0 ? (R)(cnorm(LA, i) * (double)F[(int64_t)(arow[k] + i) * ld + col[p]])
+                                               : (R)0;
+                    Ga[p][k][i] = (R)0;
+                });
             });
         });
         // the F_B / G_B rows of the next B task are fetched one task ahead
         int nrow = 0;
-        double Fn[NB], Gn[NB];
+        double Fn[NP][NB], Gn[NP][NB];
         auto fetch = [&](int bt) {
             nrow = btasks[(int64_t)bt * BS];
-            sfor<0, NB>([&](auto jc) {
-                const int64_t o = (int64_t)(nrow + CV(jc)) * ld + col;
-                Fn[CV(jc)] = (double)F[o];
-                Gn[CV(jc)] = G[o];
+            sfor<0, NP>([&](auto pc) {
+                constexpr int p = CV(pc);
+                sfor<0, NB>([&](auto jc) {
+                    const int64_t o = (int64_t)(nrow + CV(jc)) * ld + col[p];
+                    Fn[p][CV(jc)] = (double)F[o];
+                    Gn[p][CV(jc)] = G[o];
+                });
             });
         };
         if (b0 < b1) fetch(b0);
         for (int bt = b0; bt < b1; ++bt) {
             const int32_t* cur = btasks + (int64_t)bt * BS;
             const int brow = nrow;
-            R Fb[NB], Gb[NB];
-            double Gold[NB];
-            sfor<0, NB>([&](auto jc) {
-                constexpr int j = CV(jc);
-                Fb[j] = (R)(cnorm(LB, j) * Fn[j]);
-                Gold[j] = Gn[j];
-                Gb[j] = (R)0;
+            R Fb[NP][NB], Gb[NP][NB];
+            double Gold[NP][NB];
+            sfor<0, NP>([&](auto pc) {
+                constexpr int p = CV(pc);
+                sfor<0, NB>([&](auto jc) {
+                    constexpr int j = CV(jc);
+                    Fb[p][j] = (R)(cnorm(LB, j) * Fn[p][j]);
+                    Gold[p][j] = Gn[p][j];
+                    Gb[p][j] = (R)0;
+                });
             });
             if (bt + 1 < b1) fetch(bt + 1);
             const int mask = cur[1];
@@ -99,38 +127,48 @@ __global__ __launch_bounds__(256) void afg_kernel(const double* __restrict__ px,
                 if (mask & (1 << k)) {
                     const double* ab = btask_ab + ((int64_t)bt * TA + k) * 3;
                     const R AB[3] = {(R)ab[0], (R)ab[1], (R)ab[2]};
-                    R Ab[NA][NB];
-                    pair_block<LA, LB, R>(prims + cur[2 + 2 * k], cur[3 + 2 * k], AB, cx, cy, cz, tab, Ab);
-                    sfor<0, NA>([&](auto ic) {
-                        constexpr int i = CV(ic);
-                        R acc = Ga[k][i];
-                        sfor<0, NB>([&](auto jc) { acc = fma(Ab[i][CV(jc)], Fb[CV(jc)], acc); });
-                        Ga[k][i] = acc;
-                    });
-                    if (arow[k] != brow) {   // A != B: the transposed block feeds G_B
-                        transposed = true;
-                        sfor<0, NB>([&](auto jc) {
-                            constexpr int j = CV(jc);
-                            R acc = Gb[j];
-                            sfor<0, NA>([&](auto ic) { acc = fma(Ab[CV(ic)][j], Fa[k][CV(ic)], acc); });
-                            Gb[j] = acc;
+                    R Ab[NP][NA][NB];
+                    pair_block_n<LA, LB, R, NP, TC>(prims + cur[2 + 2 * k], cur[3 + 2 * k], AB, cx, cy, cz, tab, Ab);
+                    const bool offdiag = arow[k] != brow;   // A != B: the transposed block feeds G_B
+                    transposed |= offdiag;
+                    sfor<0, NP>([&](auto pc) {
+                        constexpr int p = CV(pc);
+                        sfor<0, NA>([&](auto ic) {
+                            constexpr int i = CV(ic);
+                            R acc = Ga[p][k][i];
+                            sfor<0, NB>([&](auto jc) { acc = fma(Ab[p][i][CV(jc)], Fb[p][CV(jc)], acc); });
+                            Ga[p][k][i] = acc;
                         });
-                    }
+                        if (offdiag) {
+                            sfor<0, NB>([&](auto jc) {
+                                constexpr int j = CV(jc);
+                                R acc = Gb[p][j];
+                                sfor<0, NA>([&](auto ic) { acc = fma(Ab[p][CV(ic)][j], Fa[p][k][CV(ic)], acc); });
+                                Gb[p][j] = acc;
+                            });
+                        }
+                    });
                 }
             });
             if (transposed) {
-                sfor<0, NB>([&](auto jc) {
-                    constexpr int j = CV(jc);
-                    G[(int64_t)(brow + j) * ld + col] = fma(w * cnorm(LB, j), (double)Gb[j], Gold[j]);
+                sfor<0, NP>([&](auto pc) {
+                    constexpr int p = CV(pc);
+                    sfor<0, NB>([&](auto jc) {
+                        constexpr int j = CV(jc);
+                        G[(int64_t)(brow + j) * ld + col[p]] = fma(w[p] * cnorm(LB, j), (double)Gb[p][j], Gold[p][j]);
+                    });
                 });
             }
         }
         sfor<0, TA>([&](auto kc) {
             constexpr int k = CV(kc);
             if (arow[k] >= 0) {
-                sfor<0, NA>([&](auto ic) {
-                    constexpr int i = CV(ic);
-                    G[(int64_t)(arow[k] + i) * ld + col] += (w * cnorm(LA, i)) * (double)Ga[k][i];
+                sfor<0, NP>([&](auto pc) {
+                    constexpr int p = CV(pc);
+                    sfor<0, NA>([&](auto ic) {
+                        constexpr int i = CV(ic);
+                        G[(int64_t)(arow[k] + i) * ld + col[p]] += (w[p] * cnorm(LA, i)) * (double)Ga[p][k][i];
+                    });
                 });
             }
         });
@@ -156,10 +194,18 @@ __global__ __launch_bounds__(256) void boys_eval_kernel(const double* __restrict
 hipError_t launch_afg(int la, int lb, const AfgArgs& a, hipStream_t s)
 {
     if (a.nbatch <= 0) return hipSuccess;
-    dim3 grid(a.nbatch), block(kBatch);
-#define SNK_AFG_T(LA, LB, TA, TF, R, FP, PR)                                                                  \
-    hipLaunchKernelGGL((afg_kernel<LA, LB, TA, TF, R>), grid, block, 0, s, a.px, a.py, a.pz, a.pw, FP, a.G, a.ld, \
-                       PR, a.runs, a.btasks, a.btask_ab, a.batch_run_off, a.nrun, a.boys_tab)
+    dim3 grid(a.nbatch);
+    const bool two = la == 1 && lb == 0 && a.batch_run_off == nullptr;
+#define SNK_AFG_NP(LA, LB, TA, NP, TF, R, FP, PR)                                                                  \
+    hipLaunchKernelGGL((afg_kernel<LA, LB, TA, NP, TF, R>), grid, dim3(kBatch / NP), 0, s, a.px, a.py, a.pz, a.pw, \
+                       FP, a.G, a.ld, PR, a.runs, a.btasks, a.btask_ab, a.batch_run_off, a.nrun, a.boys_tab)
+#define SNK_AFG_T(LA, LB, TA, TF, R, FP, PR)                                                                       \
+    do {                                                                                                          \
+        if (two)                                                                                                  \
+            SNK_AFG_NP(LA, LB, TA, (LA == 1 && LB == 0 ? kPointsPerLanePs : 1), TF, R, FP, PR);                   \
+        else                                                                                                      \
+            SNK_AFG_NP(LA, LB, TA, 1, TF, R, FP, PR);                                                             \
+    } while (0)
 #define SNK_AFG(LA, LB, TA, TA32)                                                                       \
     if (a.lowp) {                                                                                       \
         if (a.F32)                                                                                      \
@@ -183,6 +229,7 @@ hipError_t launch_afg(int la, int lb, const AfgArgs& a, hipStream_t s)
     }
 #undef SNK_AFG
 #undef SNK_AFG_T
+#undef SNK_AFG_NP
     return hipGetLastError();
 }
 

@@ -62,14 +62,17 @@ __device__ __forceinline__ void sfor(Fn&& f)
 template <typename R>
 constexpr int boys_terms() { return std::is_same<R, double>::value ? kBoysTerms : 7; }
 
-template <int L, typename R>
+// TC: columns per row of the table in memory (the full kBoysCols, or a prefix of at least
+// L + boys_terms<R>() columns)
+template <int L, typename R, int TC = kBoysCols>
 __device__ __forceinline__ void boys(R T, const R* __restrict__ tab, R (&F)[L + 1])
 {
     constexpr int NT = boys_terms<R>();
     if (T < (R)kBoysTmax) {
         const int k = (int)(T * (R)(1.0 / kBoysStep) + (R)0.5);
         const R d = (R)k * (R)kBoysStep - T;
-        const R* row = tab + k * kBoysCols;
+        static_assert(TC >= L + NT && TC <= kBoysCols, "Boys table too narrow");
+        const R* row = tab + k * TC;
         R pw[NT];
         pw[0] = (R)1;
         sfor<1, NT>([&](auto jc) {
@@ -160,30 +163,37 @@ struct PrimOf<float> {
     typedef PrimPair32 type;
 };
 
-// Contracted 3c-CP block A_ab(C) of one shell pair at the lane's point C:
-// Eq. vrr per primitive pair, contraction over primitives, then Eq. hrr.
-template <int LA, int LB, typename R>
-__device__ __forceinline__ void pair_block(const typename PrimOf<R>::type* __restrict__ pp0, int nprim,
-                                           const R (&AB)[3], R cx, R cy, R cz, const R* __restrict__ tab,
-                                           R (&Ab)[ncart(LA)][ncart(LB)])
+// Contracted 3c-CP blocks A_ab(C_p) of one shell pair at the lane's NP points C_p:
+// Eq. vrr per primitive pair and point, contraction over primitives, then Eq. hrr.  Each
+// primitive-pair record is loaded once for all NP points.
+template <int LA, int LB, typename R, int NP, int TC = kBoysCols>
+__device__ __forceinline__ void pair_block_n(const typename PrimOf<R>::type* __restrict__ pp0, int nprim,
+                                             const R (&AB)[3], const R (&cx)[NP], const R (&cy)[NP],
+                                             const R (&cz)[NP], const R* __restrict__ tab,
+                                             R (&Ab)[NP][ncart(LA)][ncart(LB)])
 {
     typedef typename PrimOf<R>::type PP;
     constexpr int L = LA + LB;
-    R acc[L + 1][16];
-    sfor<LA, L + 1>([&](auto lc) {
-        sfor<0, ncart(CV(lc))>([&](auto cc) { acc[CV(lc)][CV(cc)] = (R)0; });
+    R acc[NP][L + 1][16];
+    sfor<0, NP>([&](auto pc) {
+        sfor<LA, L + 1>([&](auto lc) {
+            sfor<0, ncart(CV(lc))>([&](auto cc) { acc[CV(pc)][CV(lc)][CV(cc)] = (R)0; });
+        });
     });
     auto prim = [&](const PP& pp) {
-        const R PC[3] = {pp.Px - cx, pp.Py - cy, pp.Pz - cz};
         const R PA[3] = {pp.PAx, pp.PAy, pp.PAz};
-        const R T = pp.zp * (PC[0] * PC[0] + PC[1] * PC[1] + PC[2] * PC[2]);
-        R Fm[L + 1];
-        boys<L, R>(T, tab, Fm);
-        R th[L + 1][L + 1][16];
-        sfor<0, L + 1>([&](auto nc) { th[CV(nc)][0][0] = pp.pref * Fm[CV(nc)]; });
-        vrr<L, R>(th, PA, PC, pp.oo2zp);
-        sfor<LA, L + 1>([&](auto lc) {
-            sfor<0, ncart(CV(lc))>([&](auto cc) { acc[CV(lc)][CV(cc)] += th[0][CV(lc)][CV(cc)]; });
+        sfor<0, NP>([&](auto pc) {
+            constexpr int p = CV(pc);
+            const R PC[3] = {pp.Px - cx[p], pp.Py - cy[p], pp.Pz - cz[p]};
+            const R T = pp.zp * (PC[0] * PC[0] + PC[1] * PC[1] + PC[2] * PC[2]);
+            R Fm[L + 1];
+            boys<L, R, TC>(T, tab, Fm);
+            R th[L + 1][L + 1][16];
+            sfor<0, L + 1>([&](auto nc) { th[CV(nc)][0][0] = pp.pref * Fm[CV(nc)]; });
+            vrr<L, R>(th, PA, PC, pp.oo2zp);
+            sfor<LA, L + 1>([&](auto lc) {
+                sfor<0, ncart(CV(lc))>([&](auto cc) { acc[p][CV(lc)][CV(cc)] += th[0][CV(lc)][CV(cc)]; });
+            });
         });
     };
     // software pipeline: the next primitive pair's record is requested before the
@@ -195,7 +205,21 @@ __device__ __forceinline__ void pair_block(const typename PrimOf<R>::type* __res
         if (k + 1 < nprim) nxt = pp0[k + 1];
         prim(pp);
     }
-    hrr<LA, LB, R>(acc, AB, Ab);
+    sfor<0, NP>([&](auto pc) { hrr<LA, LB, R>(acc[CV(pc)], AB, Ab[CV(pc)]); });
+}
+
+// One point: A_ab(C) of one shell pair at the lane's point C.
+template <int LA, int LB, typename R>
+__device__ __forceinline__ void pair_block(const typename PrimOf<R>::type* __restrict__ pp0, int nprim,
+                                           const R (&AB)[3], R cx, R cy, R cz, const R* __restrict__ tab,
+                                           R (&Ab)[ncart(LA)][ncart(LB)])
+{
+    const R x[1] = {cx}, y[1] = {cy}, z[1] = {cz};
+    R out[1][ncart(LA)][ncart(LB)];
+    pair_block_n<LA, LB, R, 1>(pp0, nprim, AB, x, y, z, tab, out);
+    sfor<0, ncart(LA)>([&](auto ic) {
+        sfor<0, ncart(LB)>([&](auto jc) { Ab[CV(ic)][CV(jc)] = out[0][CV(ic)][CV(jc)]; });
+    });
 }
 
 }  // namespace os3c
