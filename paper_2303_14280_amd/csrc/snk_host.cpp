@@ -222,6 +222,8 @@ struct snk_ctx {
     double* d_xsum = nullptr;           // [2] E_xc, N_el
     int32_t* d_iota = nullptr;          // [nbf] identity row / column map
     double* d_xP = nullptr;             // [max_nB][max_nB] P[B_t, B_t] (basis-screened form)
+    double* xc_lane_P[kLanes] = {};     // per lane (lane 0: d_xP): P[B_t, B_t] of the lane's tile
+    double* xc_lane_part[kLanes] = {};  // per lane (lane 0: d_xpart): split products of the lane's tile
     XcTile* d_xtiles = nullptr;         // point-kernel tiles: one per chunk, or every tile of every group
     int32_t* d_xshells = nullptr;       // their shell lists, concatenated
     std::vector<int32_t> xc_gt0;        // first tile of each group in d_xtiles (basis-screened form)
@@ -1013,6 +1015,10 @@ void free_ctx(snk_ctx* c)
     (void)hipFree(c->d_xP);
     (void)hipFree(c->d_xtiles);
     (void)hipFree(c->d_xshells);
+    for (int k = 1; k < snk_ctx::kLanes; ++k) {
+        (void)hipFree(c->xc_lane_P[k]);
+        (void)hipFree(c->xc_lane_part[k]);
+    }
     (void)hipFree(c->d_partial);
     (void)hipFree(c->d_ex);
     (void)hipFree(c->d_boys);
@@ -2007,61 +2013,119 @@ int xc_workspace_tiled(snk_ctx* c)
         c->d_xshells = nullptr;
         return rc;
     }
+    c->xc_lane_P[0] = c->d_xP;
+    c->xc_lane_part[0] = c->d_xpart;
+    for (int k = 1; k < c->nlanes; ++k) {
+        if ((rc = dalloc(c, &c->xc_lane_P[k], (size_t)(rows * rows))) ||
+            (rc = dalloc(c, &c->xc_lane_part[k], (size_t)(c->xc_nsplit * rows * rows)))) {
+            // undo everything, so that the next call makes the whole workspace again
+            for (int j = 1; j < c->nlanes; ++j) {
+                (void)hipFree(c->xc_lane_P[j]);
+                (void)hipFree(c->xc_lane_part[j]);
+                c->xc_lane_P[j] = c->xc_lane_part[j] = nullptr;
+            }
+            for (double** p : {&c->d_xphi, &c->d_xF, &c->d_xG, &c->d_xe, &c->d_xP, &c->d_xpart, &c->d_xred, &c->d_xsum}) {
+                (void)hipFree(*p);
+                *p = nullptr;
+            }
+            (void)hipFree(c->d_xtiles);
+            (void)hipFree(c->d_xshells);
+            c->d_xtiles = nullptr;
+            c->d_xshells = nullptr;
+            return rc;
+        }
+    }
     return SNK_OK;
 }
 
 // One batch group of the basis-screened XC build: Phi_t over B_t and F_t = P[B_t, B_t] Phi_t per
 // tile, the point kernel over all tiles at once, then Kt[B_t, B_t] += G_t Phi_t^T per tile
-// (split per batch, fixed order).
+// (split per batch).  The tiles' small products run on all lanes at once (tile ti on lane
+// ti mod nlanes, each lane with its own P_t and partial-sum buffers; Phi_t, F_t and G_t are
+// disjoint parts of the group buffers); the reductions into Kt stay on the context's stream
+// in tile order, and a lane reuses its partial-sum buffer only after the reduction that read it.
 int xc_group(snk_ctx* c, size_t gi, const double* dP, int functional)
 {
     hipStream_t s = c->stream;
     const Group& g = c->groups[gi];
     const int64_t nbf = c->nbf, goff = (int64_t)g.b0 * kBatch;
-    for (const Tile& t : g.tiles) {
+    const bool par = c->nlanes > 1 && g.tiles.size() > 1;
+    auto fork = [&](bool reductions) -> int {
+        HIPCHECK(c, hipEventRecord(c->fork_ev, s));
+        for (int k = 1; k < c->nlanes; ++k) {
+            HIPCHECK(c, hipStreamWaitEvent(c->lane_stream[k], c->fork_ev, 0));
+            if (reductions) HIPCHECK(c, hipEventRecord(c->lane_red[k], s));
+        }
+        return SNK_OK;
+    };
+    int rc = par ? fork(false) : SNK_OK;
+    if (rc) return rc;
+    for (size_t ti = 0; ti < g.tiles.size(); ++ti) {
+        const Tile& t = g.tiles[ti];
         if (t.nB == 0) continue;
+        const int k = par ? (int)(ti % c->nlanes) : 0;
+        const hipStream_t ls = k ? c->lane_stream[k] : s;
+        const rocblas_handle blas = c->blas ? (k ? c->lane_blas[k] : c->blas) : nullptr;
         const int64_t nB = t.nB, ncols = t.ncols, off = (int64_t)t.b0 * kBatch;
         double* Phi = c->d_xphi + t.phi_off;
         double* F = c->d_xF + t.phi_off;
+        double* Pt = c->xc_lane_P[k];
         HIPCHECK(c, launch_collocate(c->d_px + off, c->d_py + off, c->d_pz + off, ncols, c->d_shells, c->d_exps,
                                      c->d_coefs, t.d_coll_shells, t.d_coll_rows, (int32_t)t.coll_shells.size(), Phi,
-                                     ncols, s));
-        HIPCHECK(c, launch_gather(dP, nbf, t.d_coll_fn, nB, t.d_coll_fn, nB, c->d_xP, s));
-        if (c->blas) {
+                                     ncols, ls));
+        HIPCHECK(c, launch_gather(dP, nbf, t.d_coll_fn, nB, t.d_coll_fn, nB, Pt, ls));
+        if (blas) {
             const double one = 1.0, zero = 0.0;
-            if (rocblas_dgemm(c->blas, rocblas_operation_none, rocblas_operation_none, (rocblas_int)ncols,
-                              (rocblas_int)nB, (rocblas_int)nB, &one, Phi, (rocblas_int)ncols, c->d_xP, (rocblas_int)nB,
+            if (rocblas_dgemm(blas, rocblas_operation_none, rocblas_operation_none, (rocblas_int)ncols,
+                              (rocblas_int)nB, (rocblas_int)nB, &one, Phi, (rocblas_int)ncols, Pt, (rocblas_int)nB,
                               &zero, F, (rocblas_int)ncols) != rocblas_status_success) {
                 set_err(c, "rocblas_dgemm (XC F) failed");
                 return SNK_E_DEVICE;
             }
         } else {
-            HIPCHECK(c, launch_gemm_f64(nB, ncols, nB, c->d_xP, nB, Phi, ncols, false, F, ncols, 1, 0, s));
+            HIPCHECK(c, launch_gemm_f64(nB, ncols, nB, Pt, nB, Phi, ncols, false, F, ncols, 1, 0, ls));
         }
     }
+    if (par)
+        for (int k = 1; k < c->nlanes; ++k) {
+            HIPCHECK(c, hipEventRecord(c->lane_ev[k], c->lane_stream[k]));
+            HIPCHECK(c, hipStreamWaitEvent(s, c->lane_ev[k], 0));
+        }
     HIPCHECK(c, launch_xc_point(c->d_px + goff, c->d_py + goff, c->d_pz + goff, c->d_pw + goff, g.ncols, c->d_shells,
                                 c->d_exps, c->d_coefs, c->d_xtiles + c->xc_gt0[gi], c->d_xshells, c->tile_batches,
                                 c->d_xF, functional, c->d_xG, c->d_xe, s));
     HIPCHECK(c, launch_xc_sum(c->d_xe, g.ncols, c->d_xred, c->d_xsum, true, s));
-    for (const Tile& t : g.tiles) {
+    if (par && (rc = fork(true))) return rc;
+    for (size_t ti = 0; ti < g.tiles.size(); ++ti) {
+        const Tile& t = g.tiles[ti];
         if (t.nB == 0) continue;
+        const int k = par ? (int)(ti % c->nlanes) : 0;
+        const hipStream_t ls = k ? c->lane_stream[k] : s;
+        const rocblas_handle blas = c->blas ? (k ? c->lane_blas[k] : c->blas) : nullptr;
         const int64_t nB = t.nB, ncols = t.ncols;
         const int nb = (int)(ncols / kBatch);
         const double* Phi = c->d_xphi + t.phi_off;
         const double* G = c->d_xG + t.phi_off;
-        if (c->blas) {
+        double* part = c->xc_lane_part[k];
+        if (k) HIPCHECK(c, hipStreamWaitEvent(ls, c->lane_red[k], 0));
+        if (blas) {
             const double one = 1.0, zero = 0.0;
-            if (rocblas_dgemm_strided_batched(c->blas, rocblas_operation_transpose, rocblas_operation_none,
+            if (rocblas_dgemm_strided_batched(blas, rocblas_operation_transpose, rocblas_operation_none,
                                               (rocblas_int)nB, (rocblas_int)nB, kBatch, &one, Phi, (rocblas_int)ncols,
-                                              kBatch, G, (rocblas_int)ncols, kBatch, &zero, c->d_xpart,
-                                              (rocblas_int)nB, nB * nB, nb) != rocblas_status_success) {
+                                              kBatch, G, (rocblas_int)ncols, kBatch, &zero, part, (rocblas_int)nB,
+                                              nB * nB, nb) != rocblas_status_success) {
                 set_err(c, "rocblas_dgemm (XC V) failed");
                 return SNK_E_DEVICE;
             }
         } else {
-            HIPCHECK(c, launch_gemm_f64(nB, nB, ncols, G, ncols, Phi, ncols, true, c->d_xpart, nB, nb, nB * nB, s));
+            HIPCHECK(c, launch_gemm_f64(nB, nB, ncols, G, ncols, Phi, ncols, true, part, nB, nb, nB * nB, ls));
         }
-        HIPCHECK(c, launch_reduce_scatter(c->d_xpart, nb, nB * nB, nB, nB, t.d_coll_fn, t.d_coll_fn, c->d_Kt, nbf, s));
+        if (k) {
+            HIPCHECK(c, hipEventRecord(c->lane_ev[k], ls));
+            HIPCHECK(c, hipStreamWaitEvent(s, c->lane_ev[k], 0));
+        }
+        HIPCHECK(c, launch_reduce_scatter(part, nb, nB * nB, nB, nB, t.d_coll_fn, t.d_coll_fn, c->d_Kt, nbf, s));
+        if (k) HIPCHECK(c, hipEventRecord(c->lane_red[k], s));
     }
     return SNK_OK;
 }

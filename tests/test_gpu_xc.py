@@ -123,6 +123,8 @@ def test_basis_screened_tight_matches_oracle():
     assert min(sizes) < s.nbf
     for functional in (snk.SNK_XC_LDA, snk.SNK_XC_PBE):
         V, exc, nel = ctx.vxc(s.P, functional)
+        V2, _, _ = ctx.vxc(s.P, functional)
+        assert np.array_equal(V, V2)
         compare(V, exc, nel, s, functional, "config1 eps_basis 1e-13 (|B_t| mean %.1f of %d)" %
                 (np.mean(sizes), s.nbf))
 
@@ -138,6 +140,8 @@ def test_basis_screened_sampled_large(cfg, stride):
     ctx = snk.Context(s, eps_basis=1e-9, flags=snk.SNK_ROCBLAS)
     sizes = [fn.size for _, _, _, fn in ctx.tiles()]
     V, exc, nel = ctx.vxc(s.P, snk.SNK_XC_PBE)
+    V2, exc2, _ = ctx.vxc(s.P, snk.SNK_XC_PBE)
+    assert np.array_equal(V, V2) and exc == exc2   # tile products on several streams, reductions in order
     Vr, er, nr = X.vxc(s, X.PBE, chunk=4000)
     dV = float(np.max(np.abs(V - Vr)))
     say("config %d / %d points, |B_t| mean %.1f of %d: E_xc %.10f (oracle %.10f) |dE| %.2e, N_el %.8f (oracle %.8f), "
