@@ -150,3 +150,25 @@ def test_basis_screened_sampled_large(cfg, stride):
     assert np.array_equal(V, V.T)
     assert abs(exc - er) <= 1e-6 and abs(nel - nr) <= 1e-6
     assert dV <= 1e-6 * float(np.max(np.abs(Vr)))
+
+
+def test_xc_ignores_sn_k_modes_and_leaves_k_unchanged():
+    """The XC build on contexts made for the other sn-K modes (mixed precision with the learned
+    screen, the paper's pair selection, two overlapped groups) gives the plain context's V^xc,
+    and sn-K builds on the same context before and after an XC call agree bitwise."""
+    s = synth.make_system(2)
+    s = s.subset_points(np.arange(0, s.npts, 5))
+    V0, e0, _ = snk.Context(s).vxc(s.P, snk.SNK_XC_PBE)
+    kws = [dict(screen=snk.SNK_SCREEN_LINK, eps_skip_energy=1e-9),
+           dict(flags=snk.SNK_OVERLAP_GROUPS | snk.SNK_ROCBLAS, max_device_bytes=64 * s.nbf * 256 * 24)]
+    if os.path.exists(snk.SCREENER_WEIGHTS):
+        kws.append(dict(precision=snk.SNK_MIXED, screen=snk.SNK_SCREEN_LEARNED, screener=snk.load_screener()))
+    for kw in kws:
+        ctx = snk.Context(s, **kw)
+        K1, st1 = ctx.build(s.P)
+        V, e, _ = ctx.vxc(s.P, snk.SNK_XC_PBE)
+        K2, st2 = ctx.build(s.P)
+        say("context %s: max|dV| %.2e, |dE_xc| %.2e, K unchanged %s" %
+            (sorted(kw), np.max(np.abs(V - V0)), abs(e - e0), np.array_equal(K1, K2)))
+        assert np.max(np.abs(V - V0)) <= 1e-12 * np.max(np.abs(V0)) and abs(e - e0) <= 1e-11 * abs(e0)
+        assert np.array_equal(K1, K2) and st1["ex"] == st2["ex"]
