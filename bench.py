@@ -146,10 +146,11 @@ def mixed_learned(s, P, K64, stream, args, ms64, ex64, ints):
     return res
 
 
-def xc_potential(s, P, stream, args):
+def xc_potential(s, P, stream, args, ms64):
     """The exchange-correlation potential matrix (Sec. II.C) of the same workload: Slater, LDA
     and PBE through snk_vxc_build (device pointers, F GEMM through rocBLAS), timed like the sn-K
-    builds, with E_xc and the electron count."""
+    builds, with E_xc and the electron count; then K and the PBE V^xc of the same density in one
+    call (snk_ctx_build_kxc, collocation and F shared) against the two builds apart."""
     import torch
     from paper_2303_14280_amd import snk
     ctx = snk.Context(s, flags=snk.SNK_DEVICE_PTRS | snk.SNK_ROCBLAS, stream=stream.cuda_stream, device=0)
@@ -171,6 +172,21 @@ def xc_potential(s, P, stream, args):
         exc, nel = ctx.vxc_device(P.data_ptr(), V.data_ptr(), fn, scalars=True)
         res[name] = {"ms_per_build": ms, "exc": exc, "nel": nel}
         log("XC %s: %.3f ms/build, E_xc %.10f, N_el %.8f" % (name, ms, exc, nel))
+    # K and V^xc (PBE) of the same density in one call, sharing Phi and F
+    K = torch.empty_like(P)
+    for i in range(args.warmup):
+        ctx.build_kxc_device(P.data_ptr(), K.data_ptr(), V.data_ptr(), snk.SNK_XC_PBE)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for i in range(args.steps):
+        ctx.build_kxc_device(P.data_ptr(), K.data_ptr(), V.data_ptr(), snk.SNK_XC_PBE)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = max(e0.elapsed_time(e1) / args.steps, 1000.0 * (time.perf_counter() - t0) / args.steps)
+    res["k_and_pbe_one_pass"] = {"ms_per_build": ms, "separate_ms": ms64 + res["pbe"]["ms_per_build"]}
+    log("K + V^xc (PBE) in one pass: %.3f ms/build (separately %.3f)" % (ms, ms64 + res["pbe"]["ms_per_build"]))
     ctx.close()
     return res
 
@@ -422,7 +438,7 @@ def main():
         out["mixed_learned"] = mixed_learned(s, P, K, stream, args, ms, st["ex"], ints)
         out["local_density"] = local_density_comparison(s, stream, args)
     if not args.no_xc:
-        out["xc_potential"] = xc_potential(s, P, stream, args)
+        out["xc_potential"] = xc_potential(s, P, stream, args, ms)
     if args.large and args.large != "none":
         out["large_systems"] = {}
         for c in args.large.split(","):

@@ -235,6 +235,18 @@ int snk_ctx_tile_functions(const snk_ctx* ctx, int32_t tile, int32_t* fn);
 #define SNK_XC_PBE    3   /* Perdew-Burke-Ernzerhof exchange and correlation */
 int snk_vxc_build(snk_ctx* ctx, const double* P, int functional, double* V_out, double* exc_out, double* nel_out);
 
+/*
+ * snk_ctx_build_kxc: snk_ctx_build and snk_vxc_build of the same density in one call.  For
+ * FP64 contexts without basis screening (eps_basis = 0) and without SNK_OVERLAP_GROUPS the
+ * two share each batch group's collocation Phi and F = P Phi (Eq. fmat; the paper's common
+ * intermediates of the exchange and XC builds): the XC point kernel and V product run on the
+ * group's Phi and F after its K product.  Other contexts run the two builds one after the
+ * other.  Outputs, pointer modes, statistics (those of sn-K; the XC work is outside its phase
+ * timings) and error codes as for the two calls; K_out and V_out must not overlap.
+ */
+int snk_ctx_build_kxc(snk_ctx* ctx, const double* P, double* K_out, int functional, double* V_out, double* exc_out,
+                      double* nel_out, snk_stats* stats);
+
 /* Diagnostics. */
 const char* snk_status_string(int status);
 const char* snk_last_error(const snk_ctx* ctx);   /* NULL ctx: last error of a context-free call */

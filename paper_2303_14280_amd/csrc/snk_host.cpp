@@ -222,6 +222,18 @@ struct snk_ctx {
     double* d_xsum = nullptr;           // [2] E_xc, N_el
     int32_t* d_iota = nullptr;          // [nbf] identity row / column map
     double* d_xP = nullptr;             // [max_nB][max_nB] P[B_t, B_t] (basis-screened form)
+    // sn-K and XC from one pass (snk_ctx_build_kxc): the XC point kernel and V product run on
+    // each group's Phi and F right after its K product
+    int kx_fn = 0;                      // functional while a combined build runs, else 0
+    double* d_kxG = nullptr;            // [nbf][max_cols] G = 2 Z of the group
+    double* d_kxe = nullptr;            // [2][max_cols] w eps, w rho
+    double* d_kxpart = nullptr;         // [kx_nsplit][nbf][nbf]
+    double* d_kxKt = nullptr;           // [nbf][nbf] unsymmetrised V
+    double* d_kxred = nullptr;          // [512]
+    double* d_kxsum = nullptr;          // [3] E_xc, N_el, and the finish's unused trace
+    XcTile* d_kxtiles = nullptr;        // one point-kernel tile per group: every shell, from row 0
+    int32_t* d_kxshells = nullptr;      // identity shell list
+    int kx_nsplit = 1;
     double* xc_lane_P[kLanes] = {};     // per lane (lane 0: d_xP): P[B_t, B_t] of the lane's tile
     double* xc_lane_part[kLanes] = {};  // per lane (lane 0: d_xpart): split products of the lane's tile
     XcTile* d_xtiles = nullptr;         // point-kernel tiles: one per chunk, or every tile of every group
@@ -1015,6 +1027,9 @@ void free_ctx(snk_ctx* c)
     (void)hipFree(c->d_xP);
     (void)hipFree(c->d_xtiles);
     (void)hipFree(c->d_xshells);
+    for (double* p : {c->d_kxG, c->d_kxe, c->d_kxpart, c->d_kxKt, c->d_kxred, c->d_kxsum}) (void)hipFree(p);
+    (void)hipFree(c->d_kxtiles);
+    (void)hipFree(c->d_kxshells);
     for (int k = 1; k < snk_ctx::kLanes; ++k) {
         (void)hipFree(c->xc_lane_P[k]);
         (void)hipFree(c->xc_lane_part[k]);
@@ -2130,6 +2145,87 @@ int xc_group(snk_ctx* c, size_t gi, const double* dP, int functional)
     return SNK_OK;
 }
 
+// Combined build: workspace of the group-sized XC buffers (FP64 contexts without basis
+// screening, one tile per group spanning every function).
+int kx_workspace(snk_ctx* c)
+{
+    const int64_t nbf = c->nbf, cols = std::max<int64_t>(kBatch, c->max_cols);
+    const int64_t otiles = ((nbf + 63) / 64) * ((nbf + 63) / 64);
+    c->kx_nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(256, 2048 / std::max<int64_t>(1, otiles)));
+    std::vector<XcTile> tiles;
+    for (const Group& g : c->groups) tiles.push_back(XcTile{0, (int32_t)g.ncols, 0, c->nshell, 0});
+    std::vector<int32_t> shells((size_t)c->nshell);
+    std::iota(shells.begin(), shells.end(), 0);
+    int rc = 0;
+    if ((rc = dalloc(c, &c->d_kxG, (size_t)(nbf * cols))) || (rc = dalloc(c, &c->d_kxe, (size_t)(2 * cols))) ||
+        (rc = dalloc(c, &c->d_kxpart, (size_t)c->kx_nsplit * nbf * nbf)) ||
+        (rc = dalloc(c, &c->d_kxKt, (size_t)(nbf * nbf))) || (rc = dalloc(c, &c->d_kxred, 512)) ||
+        (rc = upload(c, &c->d_kxtiles, tiles)) || (rc = upload(c, &c->d_kxshells, shells)) ||
+        (rc = dalloc(c, &c->d_kxsum, 3))) {
+        for (double** p : {&c->d_kxG, &c->d_kxe, &c->d_kxpart, &c->d_kxKt, &c->d_kxred, &c->d_kxsum}) {
+            (void)hipFree(*p);
+            *p = nullptr;
+        }
+        (void)hipFree(c->d_kxtiles);
+        (void)hipFree(c->d_kxshells);
+        c->d_kxtiles = nullptr;
+        c->d_kxshells = nullptr;
+        return rc;
+    }
+    if (!c->d_iota) {
+        std::vector<int32_t> iota((size_t)nbf);
+        std::iota(iota.begin(), iota.end(), 0);
+        if ((rc = upload(c, &c->d_iota, iota))) return rc;
+    }
+    return SNK_OK;
+}
+
+// Combined build, group gi: the XC point kernel on the group's Phi and F (Eqs. den_grid,
+// exc_grid, zmat) and Kt_xc += G_xc Phi^T (Eq. vxc_num), on the context's stream after the
+// group's K product, before the next group reuses Phi and F.
+int group_kx(snk_ctx* c, size_t gi)
+{
+    hipStream_t s = c->stream;
+    const Group& g = c->groups[gi];
+    const int64_t nbf = c->nbf, ncols = g.ncols, off = (int64_t)g.b0 * kBatch;
+    const size_t nb2 = (size_t)nbf * nbf;
+    const double* Phi = c->d_Phi + g.tiles[0].phi_off;
+    HIPCHECK(c, launch_xc_point(c->d_px + off, c->d_py + off, c->d_pz + off, c->d_pw + off, ncols, c->d_shells,
+                                c->d_exps, c->d_coefs, c->d_kxtiles + gi, c->d_kxshells, (int32_t)(ncols / kBatch),
+                                c->d_F, c->kx_fn, c->d_kxG, c->d_kxe, s));
+    HIPCHECK(c, launch_xc_sum(c->d_kxe, ncols, c->d_kxred, c->d_kxsum, true, s));
+    if (c->blas) {
+        const int64_t nb = ncols / kBatch;
+        const int64_t bpc = (nb + c->kx_nsplit - 1) / c->kx_nsplit;
+        const int64_t kchunk = bpc * kBatch;
+        const int64_t nfull = nb / bpc, rem = nb - nfull * bpc;
+        const double one = 1.0, zero = 0.0;
+        rocblas_status st = rocblas_status_success;
+        if (nfull > 0)
+            st = rocblas_dgemm_strided_batched(c->blas, rocblas_operation_transpose, rocblas_operation_none,
+                                               (rocblas_int)nbf, (rocblas_int)nbf, (rocblas_int)kchunk, &one, Phi,
+                                               (rocblas_int)ncols, kchunk, c->d_kxG, (rocblas_int)ncols, kchunk, &zero,
+                                               c->d_kxpart, (rocblas_int)nbf, (int64_t)nb2, (rocblas_int)nfull);
+        if (st == rocblas_status_success && rem > 0)
+            st = rocblas_dgemm(c->blas, rocblas_operation_transpose, rocblas_operation_none, (rocblas_int)nbf,
+                               (rocblas_int)nbf, (rocblas_int)(rem * kBatch), &one, Phi + nfull * kchunk,
+                               (rocblas_int)ncols, c->d_kxG + nfull * kchunk, (rocblas_int)ncols, &zero,
+                               c->d_kxpart + nfull * (int64_t)nb2, (rocblas_int)nbf);
+        if (st != rocblas_status_success) {
+            set_err(c, "rocblas_dgemm (XC V) failed");
+            return SNK_E_DEVICE;
+        }
+        HIPCHECK(c, launch_reduce_scatter(c->d_kxpart, (int)(nfull + (rem > 0)), (int64_t)nb2, nbf, nbf, c->d_iota,
+                                          c->d_iota, c->d_kxKt, nbf, s));
+    } else {
+        HIPCHECK(c, launch_gemm_f64(nbf, nbf, ncols, c->d_kxG, ncols, Phi, ncols, true, c->d_kxpart, nbf,
+                                    c->kx_nsplit, (int64_t)nb2, s));
+        HIPCHECK(c, launch_reduce_scatter(c->d_kxpart, c->kx_nsplit, (int64_t)nb2, nbf, nbf, c->d_iota, c->d_iota,
+                                          c->d_kxKt, nbf, s));
+    }
+    return SNK_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -2237,6 +2333,44 @@ int snk_vxc_build(snk_ctx* c, const double* P, int functional, double* V_out, do
     return SNK_OK;
 }
 
+int snk_ctx_build_kxc(snk_ctx* c, const double* P, double* K_out, int functional, double* V_out, double* exc_out,
+                      double* nel_out, snk_stats* stats)
+{
+    if (!c) return arg_error(nullptr, "context is NULL");
+    if (!P || !K_out || !V_out) return arg_error(c, "P, K_out or V_out is NULL");
+    if (functional < SNK_XC_SLATER || functional > SNK_XC_PBE) return arg_error(c, "unknown functional");
+    const bool share = !c->mixed && c->opts.eps_basis <= 0.0 && !c->pipe && c->nbatch > 0 && c->nbf > 0;
+    if (!share) {
+        int rc = snk_ctx_build(c, P, K_out, stats);
+        return rc ? rc : snk_vxc_build(c, P, functional, V_out, exc_out, nel_out);
+    }
+    HIPCHECK(c, hipSetDevice(c->device));
+    if (!c->d_kxsum) {
+        int rc = kx_workspace(c);
+        if (rc) return rc;
+    }
+    const bool dev = (c->opts.flags & SNK_DEVICE_PTRS) != 0;
+    const size_t nb2 = (size_t)c->nbf * c->nbf;
+    c->kx_fn = functional;
+    int rc = snk_ctx_build(c, P, K_out, stats);
+    c->kx_fn = 0;
+    if (rc) return rc;
+    hipStream_t s = c->stream;
+    const double* dP = dev ? P : c->d_P;     // uploaded by the sn-K build in host-pointer mode
+    double* dV = dev ? V_out : c->d_K;
+    // V = (Kt_xc + Kt_xc^T) / 2 with G = 2 Z (Eq. vxc_num); the trace goes to an unused slot
+    HIPCHECK(c, launch_finish(c->d_kxKt, dP, dV, c->nbf, c->d_partial, c->nfinish, c->d_kxsum + 2, s));
+    double sums[2] = {0.0, 0.0};
+    if (!dev) HIPCHECK(c, hipMemcpyAsync(V_out, dV, nb2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (!dev || exc_out || nel_out) {
+        HIPCHECK(c, hipMemcpyAsync(sums, c->d_kxsum, sizeof(sums), hipMemcpyDeviceToHost, s));
+        HIPCHECK(c, hipStreamSynchronize(s));
+    }
+    if (exc_out) *exc_out = sums[0];
+    if (nel_out) *nel_out = sums[1];
+    return SNK_OK;
+}
+
 int snk_ctx_build(snk_ctx* c, const double* P, double* K_out, snk_stats* stats)
 {
     if (!c) return arg_error(nullptr, "context is NULL");
@@ -2265,6 +2399,10 @@ int snk_ctx_build(snk_ctx* c, const double* P, double* K_out, snk_stats* stats)
     const bool timed = stats != nullptr;
 
     HIPCHECK(c, launch_fill(c->d_Kt, (int64_t)nb2, 0.0, s));
+    if (c->kx_fn) {
+        HIPCHECK(c, launch_fill(c->d_kxKt, (int64_t)nb2, 0.0, s));
+        HIPCHECK(c, launch_fill(c->d_kxsum, 3, 0.0, s));
+    }
     if (c->mixed) HIPCHECK(c, launch_convert_f32(dP, (int64_t)nb2, c->d_P32, s));
     if (c->mlp)
         HIPCHECK(c, launch_pair_pnorm(dP, nbf, c->d_ne_list, c->d_pa, c->d_pb, c->d_shell_l, c->d_shell_row,
@@ -2302,6 +2440,8 @@ int snk_ctx_build(snk_ctx* c, const double* P, double* K_out, snk_stats* stats)
             }
             tk += ev_ms(c->ev[3], c->ev[4]);
         }
+        // combined build: the XC potential from this group's Phi and F (outside the sn-K phase timings)
+        if (c->kx_fn && (rc = group_kx(c, gi))) return rc;
     }
     if (pipe) {
         swap.restore();

@@ -118,6 +118,10 @@ def lib():
             L.snk_vxc_build.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
                                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
             L.snk_vxc_build.restype = ctypes.c_int
+            L.snk_ctx_build_kxc.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                            ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                            ctypes.POINTER(ctypes.c_double), ctypes.POINTER(SnkStats)]
+            L.snk_ctx_build_kxc.restype = ctypes.c_int
             L.snk_ctx_ntiles.argtypes = [ctypes.c_void_p]
             L.snk_ctx_ntiles.restype = ctypes.c_int
             L.snk_ctx_tile_info.argtypes = [ctypes.c_void_p] * 5
@@ -302,6 +306,30 @@ class Context:
         _check(lib().snk_vxc_build(self.handle, P.ctypes.data, int(functional), V.ctypes.data, ctypes.byref(exc),
                                    ctypes.byref(nel)), self.handle)
         return V, exc.value, nel.value
+
+    def build_kxc(self, P: np.ndarray, functional: int = SNK_XC_LDA, stats: bool = True):
+        """Host-pointer sn-K and XC build of one density (snk_ctx_build_kxc): returns
+        (K, V^xc, E_xc, N_el, stats)."""
+        if self.device_ptrs:
+            raise ValueError("context was created for device pointers")
+        P = np.ascontiguousarray(P, np.float64)
+        if P.shape != (self.nbf, self.nbf):
+            raise ValueError("P has shape %s, expected %s" % (P.shape, (self.nbf, self.nbf)))
+        K = np.zeros_like(P)
+        V = np.zeros_like(P)
+        exc, nel = ctypes.c_double(0.0), ctypes.c_double(0.0)
+        st = SnkStats()
+        _check(lib().snk_ctx_build_kxc(self.handle, P.ctypes.data, K.ctypes.data, int(functional), V.ctypes.data,
+                                       ctypes.byref(exc), ctypes.byref(nel), ctypes.byref(st) if stats else None),
+               self.handle)
+        return K, V, exc.value, nel.value, st.as_dict()
+
+    def build_kxc_device(self, P_ptr: int, K_ptr: int, V_ptr: int, functional: int = SNK_XC_LDA):
+        """Device-pointer sn-K and XC build on the context's stream (asynchronous)."""
+        if not self.device_ptrs:
+            raise ValueError("context was created for host pointers")
+        _check(lib().snk_ctx_build_kxc(self.handle, ctypes.c_void_p(P_ptr), ctypes.c_void_p(K_ptr), int(functional),
+                                       ctypes.c_void_p(V_ptr), None, None, None), self.handle)
 
     def vxc_device(self, P_ptr: int, V_ptr: int, functional: int = SNK_XC_LDA, scalars: bool = False):
         """Device-pointer XC potential on the context's stream; (E_xc, N_el) when scalars is set

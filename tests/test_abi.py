@@ -88,3 +88,4 @@ def test_null_pointers_rejected():
     assert L.snk_boys_device(None, 10, 2, None, None) == snk.SNK_E_ARG
     assert L.snk_boys_device(None, 10, 7, None, None) == snk.SNK_E_ARG
     assert L.snk_vxc_build(None, None, snk.SNK_XC_LDA, None, None, None) == snk.SNK_E_ARG
+    assert L.snk_ctx_build_kxc(None, None, None, snk.SNK_XC_LDA, None, None, None, None) == snk.SNK_E_ARG

@@ -172,3 +172,27 @@ def test_xc_ignores_sn_k_modes_and_leaves_k_unchanged():
             (sorted(kw), np.max(np.abs(V - V0)), abs(e - e0), np.array_equal(K1, K2)))
         assert np.max(np.abs(V - V0)) <= 1e-12 * np.max(np.abs(V0)) and abs(e - e0) <= 1e-11 * abs(e0)
         assert np.array_equal(K1, K2) and st1["ex"] == st2["ex"]
+
+
+@pytest.mark.parametrize("kw", [dict(), dict(flags=snk.SNK_ROCBLAS), dict(screen=snk.SNK_SCREEN_LINK, eps_skip_energy=1e-9),
+                                dict(eps_basis=1e-9)])
+def test_combined_build_matches_separate_calls(kw):
+    """snk_ctx_build_kxc (Phi and F shared between sn-K and XC where the context allows it) gives
+    the K of snk_ctx_build bitwise and the V^xc of snk_vxc_build to rounding order; V^xc
+    also against the XC oracle."""
+    s = synth.make_system(2)
+    s = s.subset_points(np.arange(1, s.npts, 9))
+    ctx = snk.Context(s, **kw)
+    K0, st0 = ctx.build(s.P)
+    V0, e0, n0 = ctx.vxc(s.P, snk.SNK_XC_PBE)
+    K1, V1, e1, n1, st1 = ctx.build_kxc(s.P, snk.SNK_XC_PBE)
+    K2, V2, e2, _, _ = ctx.build_kxc(s.P, snk.SNK_XC_PBE)
+    say("combined %s: K equal %s, max|dV| %.2e, |dE_xc| %.2e, repeat equal %s" %
+        (sorted(kw), np.array_equal(K0, K1), np.max(np.abs(V1 - V0)), abs(e1 - e0),
+         np.array_equal(V1, V2) and np.array_equal(K1, K2)))
+    assert np.array_equal(K0, K1) and st0["ex"] == st1["ex"]
+    assert np.array_equal(V1, V2) and np.array_equal(K1, K2) and e1 == e2
+    assert np.max(np.abs(V1 - V0)) <= 1e-13 * np.max(np.abs(V0))
+    assert abs(e1 - e0) <= 1e-12 * abs(e0) and abs(n1 - n0) <= 1e-12 * abs(n0)
+    if not kw:
+        compare(V1, e1, n1, s, snk.SNK_XC_PBE, "config2/9 combined")
