@@ -1974,16 +1974,15 @@ int xc_workspace(snk_ctx* c)
     if ((rc = dalloc(c, &c->d_xphi, (size_t)(nbf * cols))) || (rc = dalloc(c, &c->d_xF, (size_t)(nbf * cols))) ||
         (rc = dalloc(c, &c->d_xG, (size_t)(nbf * cols))) || (rc = dalloc(c, &c->d_xe, (size_t)(2 * cols))) ||
         (rc = dalloc(c, &c->d_xpart, (size_t)c->xc_nsplit * nbf * nbf)) || (rc = dalloc(c, &c->d_xred, 512)) ||
-        (rc = upload(c, &c->d_iota, iota)) || (rc = upload(c, &c->d_xtiles, tiles)) ||
+        (!c->d_iota && (rc = upload(c, &c->d_iota, iota))) || (rc = upload(c, &c->d_xtiles, tiles)) ||
         (rc = upload(c, &c->d_xshells, shells)) || (rc = dalloc(c, &c->d_xsum, 2))) {
+        // the identity map stays (the combined build shares it; freed with the context)
         for (double** p : {&c->d_xphi, &c->d_xF, &c->d_xG, &c->d_xe, &c->d_xpart, &c->d_xred, &c->d_xsum}) {
             (void)hipFree(*p);
             *p = nullptr;
         }
-        (void)hipFree(c->d_iota);
         (void)hipFree(c->d_xtiles);
         (void)hipFree(c->d_xshells);
-        c->d_iota = nullptr;
         c->d_xtiles = nullptr;
         c->d_xshells = nullptr;
         return rc;

@@ -196,3 +196,8 @@ def test_combined_build_matches_separate_calls(kw):
     assert abs(e1 - e0) <= 1e-12 * abs(e0) and abs(n1 - n0) <= 1e-12 * abs(n0)
     if not kw:
         compare(V1, e1, n1, s, snk.SNK_XC_PBE, "config2/9 combined")
+        # the other order on a fresh context: combined first, then the XC build alone
+        c2 = snk.Context(s, **kw)
+        K3, V3, e3, _, _ = c2.build_kxc(s.P, snk.SNK_XC_PBE)
+        V4, e4, _ = c2.vxc(s.P, snk.SNK_XC_PBE)
+        assert np.array_equal(K3, K1) and np.array_equal(V3, V1) and np.array_equal(V4, V0) and e4 == e0
