@@ -18,8 +18,11 @@ the geometry, 1 for the basis and 2 for the orbitals.
 """
 from __future__ import annotations
 
+import ctypes
 import dataclasses
 import math
+import os
+import subprocess
 from typing import Dict, List, Optional, Sequence, Tuple
 
 import numpy as np
@@ -290,32 +293,66 @@ def becke_partition(points: np.ndarray, parent: int, atoms: np.ndarray, cand: np
     return Pc[ip] / np.sum(Pc, axis=0)
 
 
-def make_grid(atom_xyz: np.ndarray, n_rad: int, n_ang: int, neighbour_radius: Optional[float] = None,
-              exact_below: int = 64) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
-    """Atom-centred grid: Mura-Knowles x Lebedev per atom with Becke partition weights.
+_SSF_SRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "grid_ssf.c")
+_SSF_LIB = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libgridssf.so")
+_ssf = None
 
-    For more than ``exact_below`` atoms the Becke product runs over the atoms within
-    ``neighbour_radius`` bohr of the parent atom (default 12 bohr)."""
+
+def build_ssf(force: bool = False) -> str:
+    """Compile the Stratmann-weight helper (``grid_ssf.c``) with gcc."""
+    if force or not os.path.exists(_SSF_LIB) or os.path.getmtime(_SSF_LIB) < os.path.getmtime(_SSF_SRC):
+        tmp = _SSF_LIB + ".tmp%d" % os.getpid()
+        subprocess.run(["gcc", "-O3", "-fno-math-errno", "-fopenmp", "-fPIC", "-shared", "-std=gnu11", "-o", tmp, _SSF_SRC, "-lm"],
+                       check=True)
+        os.replace(tmp, _SSF_LIB)
+    return _SSF_LIB
+
+
+def ssf_partition(points: np.ndarray, parent: np.ndarray, atoms: np.ndarray) -> np.ndarray:
+    """Stratmann-Scuseria-Frisch partition factor of each point's parent atom over all atoms
+    (a = 0.64), evaluated exactly: the scheme's cell function is exactly 0 or 1 outside
+    |mu| < a, which bounds the atoms that can contribute (see grid_ssf.c)."""
+    global _ssf
+    if _ssf is None:
+        L = ctypes.CDLL(build_ssf())
+        L.ssf_weights.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_long, ctypes.c_void_p, ctypes.c_void_p,
+                                  ctypes.c_void_p]
+        L.ssf_weights.restype = ctypes.c_int
+        _ssf = L
+    A = np.ascontiguousarray(atoms, np.float64)
+    X = np.ascontiguousarray(points, np.float64)
+    par = np.ascontiguousarray(parent, np.int32)
+    out = np.empty(len(X), np.float64)
+    rc = _ssf.ssf_weights(len(A), A.ctypes.data, len(X), X.ctypes.data, par.ctypes.data, out.ctypes.data)
+    if rc != 0:
+        raise MemoryError("ssf_weights: out of memory")
+    return out
+
+
+def make_grid(atom_xyz: np.ndarray, n_rad: int, n_ang: int, exact_below: int = 64
+              ) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """Atom-centred grid: Mura-Knowles x Lebedev per atom with fuzzy-cell partition weights.
+
+    Up to ``exact_below`` atoms: Becke's partition (3-fold iterated cell function) over all
+    atoms.  Above: the Stratmann-Scuseria-Frisch partition (the paper's choice, Sec. II.C)
+    over all atoms, evaluated exactly with its own cut-offs, so the cell weights of every
+    point add up to one."""
     r, wr = mura_knowles(n_rad)
     u, wa = lebedev(n_ang)
     loc = (r[:, None, None] * u[None, :, :]).reshape(-1, 3)
     wloc = (wr[:, None] * wa[None, :]).reshape(-1)
     n_atom = len(atom_xyz)
-    if neighbour_radius is None:
-        neighbour_radius = 12.0
-    xyz, w, at = [], [], []
-    for a in range(n_atom):
-        pts = atom_xyz[a] + loc
-        if n_atom <= exact_below:
-            cand = np.arange(n_atom)
-        else:
-            dist = np.linalg.norm(atom_xyz - atom_xyz[a], axis=1)
-            cand = np.nonzero(dist <= neighbour_radius)[0]
-        wb = becke_partition(pts, a, atom_xyz, cand) if len(cand) > 1 else np.ones(len(pts))
-        xyz.append(pts)
-        w.append(wloc * wb)
-        at.append(np.full(len(pts), a, np.int32))
-    return np.concatenate(xyz), np.concatenate(w), np.concatenate(at)
+    xyz = np.concatenate([atom_xyz[a] + loc for a in range(n_atom)]) if n_atom else np.zeros((0, 3))
+    at = np.repeat(np.arange(n_atom, dtype=np.int32), len(loc))
+    if n_atom <= 1:
+        wb = np.ones(len(xyz))
+    elif n_atom <= exact_below:
+        wb = np.concatenate([becke_partition(atom_xyz[a] + loc, a, atom_xyz, np.arange(n_atom))
+                             for a in range(n_atom)])
+    else:
+        wb = ssf_partition(xyz, at, atom_xyz)
+    w = np.tile(wloc, n_atom) * wb
+    return xyz, w, at
 
 
 # ----------------------------------------------------------------------------------------------
