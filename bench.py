@@ -102,7 +102,7 @@ def mixed_learned(s, P, K64, stream, args, ms64, ex64, ints):
         return {"error": "no trained screener weights"}
     mlp = snk.load_screener(device=0)
     K = torch.empty_like(P)
-    D, R = snk.SNK_DEVICE_PTRS, snk.SNK_DEVICE_PTRS | snk.SNK_ROCBLAS
+    D, R = snk.SNK_DEVICE_PTRS, snk.SNK_DEVICE_PTRS
     variants = [("mixed+learned", dict(precision=snk.SNK_MIXED, screen=snk.SNK_SCREEN_LEARNED, flags=R)),
                 ("mixed+learned+fp32gemm", dict(precision=snk.SNK_MIXED, screen=snk.SNK_SCREEN_LEARNED,
                                                 flags=D | snk.SNK_FP32_GEMM)),
@@ -153,7 +153,7 @@ def xc_potential(s, P, stream, args, ms64):
     call (snk_ctx_build_kxc, collocation and F shared) against the two builds apart."""
     import torch
     from paper_2303_14280_amd import snk
-    ctx = snk.Context(s, flags=snk.SNK_DEVICE_PTRS | snk.SNK_ROCBLAS, stream=stream.cuda_stream, device=0)
+    ctx = snk.Context(s, flags=snk.SNK_DEVICE_PTRS, stream=stream.cuda_stream, device=0)
     V = torch.empty_like(P)
     res = {"grid_points": s.npts, "nbf": ctx.nbf,
            "gemm_flops": 4.0 * ctx.nbf * ctx.nbf * ctx.nbatches * 256}
@@ -202,7 +202,7 @@ def local_density_comparison(s, stream, args):
     sl = s.with_density(synth.make_density(s, s.n_occ, "local", [args.config, 2]))
     P = torch.tensor(sl.P, dtype=torch.float64, device="cuda")
     mlp = snk.load_screener(device=0)
-    R = snk.SNK_DEVICE_PTRS | snk.SNK_ROCBLAS
+    R = snk.SNK_DEVICE_PTRS
     res = {"density": "molecule-local (block-diagonal by molecule)"}
     K64 = torch.empty_like(P)
     ctx = snk.Context(sl, flags=R, stream=stream.cuda_stream, device=0)
@@ -245,7 +245,7 @@ def large_system(config, stream, args):
     log("config %d generated in %.1f s" % (config, time.perf_counter() - t))
     P = torch.tensor(s.P, dtype=torch.float64, device="cuda")
     mlp = snk.load_screener(device=0)
-    R = snk.SNK_DEVICE_PTRS | snk.SNK_ROCBLAS
+    R = snk.SNK_DEVICE_PTRS
     res = {"workload": "config%d: %d atoms, %d functions, %d grid points, %s density"
                        % (config, len(s.atom_Z), s.nbf, s.npts, s.density)}
     variants = [("fp64", dict(screen=snk.SNK_SCREEN_NONE)),
@@ -353,7 +353,7 @@ def main():
     stream = torch.cuda.Stream(device=dev)          # default priority
     torch.cuda.set_stream(stream)
     # FP64 reference build: the library's A.F kernels, the dense GEMMs through rocBLAS dgemm
-    ctx = snk.Context(s, flags=snk.SNK_DEVICE_PTRS | snk.SNK_ROCBLAS, stream=stream.cuda_stream, device=0)
+    ctx = snk.Context(s, flags=snk.SNK_DEVICE_PTRS, stream=stream.cuda_stream, device=0)
     P = torch.tensor(s.P, dtype=torch.float64, device=dev)
     K = torch.empty_like(P)
     torch.cuda.synchronize()

@@ -78,9 +78,7 @@ typedef enum snk_screen {
 /* opts.flags */
 #define SNK_DEVICE_PTRS 0x1u   /* P and K_out are device pointers; work is ordered on opts.stream */
 #define SNK_VALIDATE    0x2u   /* check P for symmetry and finiteness (host-pointer mode) */
-#define SNK_ROCBLAS     0x4u   /* FP64 build: run the two dense GEMMs (Eqs. fmat, usym_k) through
-                                  rocBLAS dgemm (atomics off, deterministic) instead of the
-                                  library's own FP64 matrix-core kernel */
+/* 0x4u is not a flag (rejected with SNK_E_ARG) */
 #define SNK_FP32_GEMM   0x8u   /* SNK_MIXED: also store Phi, P and F in FP32 and run both dense GEMMs
                                   on the FP32 matrix cores (FP32 sums over <= 1024 terms, FP64
                                   across them); without it the mixed build's GEMMs stay FP64 */
@@ -151,8 +149,7 @@ typedef struct snk_opts {
     int64_t max_device_bytes;   /* workspace budget for batch groups (0 = automatic) */
     int32_t device;             /* HIP device ordinal */
     void* stream;               /* hipStream_t; NULL = the library's own stream */
-    uint32_t flags;             /* SNK_DEVICE_PTRS | SNK_VALIDATE | SNK_ROCBLAS | SNK_FP32_GEMM |
-                                   SNK_OVERLAP_GROUPS */
+    uint32_t flags;             /* SNK_DEVICE_PTRS | SNK_VALIDATE | SNK_FP32_GEMM | SNK_OVERLAP_GROUPS */
     snk_stats* stats;           /* optional output of sn_k_build */
 } snk_opts;
 

@@ -1,9 +1,8 @@
-// Dense linear-algebra steps of the sn-K build on gfx950:
-//  - FP64 GEMM on the matrix cores (v_mfma_f64_16x16x4f64) for F = P_g Phi_g (Eq. fmat)
-//    and Kt_g = G_g Phi_g^T (Eq. usym_k, split over the grid-point dimension);
-//  - deterministic reduction of the split partials into Kt;
+// Dense linear-algebra steps of the sn-K build on gfx950 besides the grouped products
+// (k_ggemm.hip):
 //  - K = (Kt + Kt^T)/2 (Eq. sn_k) and E_x = -1/2 tr(P K) by a fixed two-stage tree;
-//  - fill and gather helpers.
+//  - the bounds that restrict the rows of F per tile (row maxima of Phi, F~ flags);
+//  - fill and conversion helpers, and a probe of the FP64 matrix-core accumulator layout.
 #include "snk_internal.h"
 
 #include <type_traits>
@@ -12,124 +11,6 @@ namespace snk {
 namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
-
-constexpr int TM = 64, TN = 64, TK = 16;
-constexpr int kFlush = 1024;   // FP32 mode: k per FP32 accumulation before the FP64 add
-
-// 256 threads = 4 wave64; wave w owns the 32x32 quadrant (w/2, w%2) of the 64x64 tile as
-// 2x2 matrix-core 16x16 blocks.  F32 = false: v_mfma_f64_16x16x4f64, operands and
-// accumulators FP64; F32 = true: v_mfma_f32_16x16x4f32, operands rounded to FP32 as they are
-// staged (whatever the storage type) and FP32 accumulation.  Operand layout (wave64):
-//   A[i][k] in lane i + 16k, B[k][j] in lane j + 16k;
-//   FP64 accumulator D[i][j] in lane j + 16(i%4), element i/4;
-//   FP32 accumulator D[i][j] in lane j + 16(i/4), element i%4
-// (both accumulator layouts are checked by GEMM tests against host products).
-template <typename TA, typename TB, typename TC, bool F32>
-__global__ __launch_bounds__(256) void gemm_kernel(int64_t M, int64_t N, int64_t K, const TA* __restrict__ A,
-                                                   int64_t lda, const TB* __restrict__ B, int64_t ldb, int bt,
-                                                   TC* __restrict__ C, int64_t ldc, int64_t kchunk,
-                                                   int64_t split_stride)
-{
-    typedef typename std::conditional<F32, float, double>::type TS;
-    typedef TS acc4 __attribute__((ext_vector_type(4)));
-    __shared__ TS As[TK][TM + 1];
-    __shared__ TS Bs[TK][TN + 1];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int64_t m0 = (int64_t)blockIdx.y * TM, n0 = (int64_t)blockIdx.x * TN;
-    const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
-    const int64_t kend = min(K, kbeg + kchunk);
-    C += (int64_t)blockIdx.z * split_stride;
-    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-    const int li = lane & 15, lk = lane >> 4;
-
-    acc4 acc[2][2];
-    for (int bi = 0; bi < 2; ++bi)
-        for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = acc4{0, 0, 0, 0};
-    // FP32 mode: the matrix-core accumulators cover at most kFlush consecutive k; they are
-    // then added into FP64 accumulators (FP32 sums stay short, long sums are FP64)
-    double dacc[2][2][4];
-    if constexpr (F32)
-        for (int bi = 0; bi < 2; ++bi)
-            for (int bj = 0; bj < 2; ++bj)
-                for (int r = 0; r < 4; ++r) dacc[bi][bj][r] = 0.0;
-    auto flush = [&]() {
-        if constexpr (F32)
-            for (int bi = 0; bi < 2; ++bi)
-                for (int bj = 0; bj < 2; ++bj) {
-                    for (int r = 0; r < 4; ++r) dacc[bi][bj][r] += (double)acc[bi][bj][r];
-                    acc[bi][bj] = acc4{0, 0, 0, 0};
-                }
-    };
-
-    const int ai = tid >> 2, ak = (tid & 3) * 4;
-    int since_flush = 0;
-    for (int64_t k0 = kbeg; k0 < kend; k0 += TK) {
-        if (F32 && since_flush == kFlush / TK) {
-            flush();
-            since_flush = 0;
-        }
-        ++since_flush;
-        {
-            const int64_t gm = m0 + ai;
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int64_t gk = k0 + ak + u;
-                As[ak + u][ai] = (gm < M && gk < kend) ? (TS)A[gm * lda + gk] : (TS)0;
-            }
-        }
-        if (!bt) {
-            const int bk = tid >> 4, bj = (tid & 15) * 4;
-            const int64_t gk = k0 + bk;
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int64_t gn = n0 + bj + u;
-                Bs[bk][bj + u] = (gk < kend && gn < N) ? (TS)B[gk * ldb + gn] : (TS)0;
-            }
-        } else {
-            const int bj = tid >> 2, bk = (tid & 3) * 4;
-            const int64_t gn = n0 + bj;
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int64_t gk = k0 + bk + u;
-                Bs[bk + u][bj] = (gn < N && gk < kend) ? (TS)B[gn * ldb + gk] : (TS)0;
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int ks = 0; ks < TK; ks += 4) {
-            TS a[2], b[2];
-#pragma unroll
-            for (int bi = 0; bi < 2; ++bi) a[bi] = As[ks + lk][wm + bi * 16 + li];
-#pragma unroll
-            for (int bj = 0; bj < 2; ++bj) b[bj] = Bs[ks + lk][wn + bj * 16 + li];
-#pragma unroll
-            for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-                for (int bj = 0; bj < 2; ++bj) {
-                    if constexpr (F32)
-                        acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[bi], b[bj], acc[bi][bj], 0, 0, 0);
-                    else
-                        acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi], b[bj], acc[bi][bj], 0, 0, 0);
-                }
-        }
-        __syncthreads();
-    }
-    flush();
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-        for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int64_t gm = m0 + wm + bi * 16 + (F32 ? 4 * lk + r : 4 * r + lk);
-                const int64_t gn = n0 + wn + bj * 16 + li;
-                if constexpr (F32) {
-                    if (gm < M && gn < N) C[gm * ldc + gn] = (TC)dacc[bi][bj][r];
-                } else {
-                    if (gm < M && gn < N) C[gm * ldc + gn] = (TC)acc[bi][bj][r];
-                }
-            }
-}
 
 // Row-wise element kernels: blockIdx.y strides the rows, the x blocks of 256 threads stride a
 // row's columns (no integer division per element).
@@ -142,26 +23,6 @@ dim3 rows_grid(int64_t rows, int64_t cols)
     const int64_t gx = std::min<int64_t>(std::max<int64_t>(1, (cols + 255) / 256), 16);
     const int64_t gy = std::min<int64_t>(std::max<int64_t>(1, rows), 65535);
     return dim3((unsigned)gx, (unsigned)gy);
-}
-
-template <typename TP>
-__global__ __launch_bounds__(256) void reduce_scatter_kernel(const TP* __restrict__ part, int nsplit,
-                                                             int64_t stride, int64_t M, int64_t N,
-                                                             const int32_t* __restrict__ rows,
-                                                             const int32_t* __restrict__ cols,
-                                                             double* __restrict__ Kt, int64_t nbf)
-{
-    SNK_ROWS(m, M)
-    {
-        double* krow = Kt + (int64_t)(rows ? rows[m] : m) * nbf;
-        SNK_COLS(n, N)
-        {
-            const int64_t idx = m * N + n;
-            double s = 0.0;
-            for (int z = 0; z < nsplit; ++z) s += (double)part[z * stride + idx];
-            krow[cols ? cols[n] : n] += s;
-        }
-    }
 }
 
 template <typename T>
@@ -222,34 +83,6 @@ __global__ __launch_bounds__(256) void finish_reduce_kernel(const double* __rest
     for (int i = threadIdx.x; i < nblk; i += blockDim.x) acc += partial[i];
     const double s = block_sum(acc, sh);
     if (threadIdx.x == 0) ex[0] = -0.5 * s;
-}
-
-template <typename TO>
-__global__ __launch_bounds__(256) void gather_kernel(const double* __restrict__ P, int64_t nbf,
-                                                     const int32_t* __restrict__ rows, int64_t M,
-                                                     const int32_t* __restrict__ cols, int64_t N,
-                                                     TO* __restrict__ out)
-{
-    SNK_ROWS(m, M)
-    {
-        const double* src = P + (int64_t)(rows ? rows[m] : m) * nbf;
-        TO* dst = out + m * N;
-        SNK_COLS(n, N) dst[n] = (TO)src[cols ? cols[n] : n];
-    }
-}
-
-// out[rows[m] * ld + c] = in[m * ncols + c]
-template <typename T>
-__global__ __launch_bounds__(256) void scatter_rows_kernel(const T* __restrict__ in, int64_t M, int64_t ncols,
-                                                           const int32_t* __restrict__ rows, T* __restrict__ out,
-                                                           int64_t ld)
-{
-    SNK_ROWS(m, M)
-    {
-        const T* src = in + m * ncols;
-        T* dst = out + (int64_t)rows[m] * ld;
-        SNK_COLS(c, ncols) dst[c] = src[c];
-    }
 }
 
 // p[rows[m] * ld + c] = v for m < M, c < ncols
@@ -326,71 +159,6 @@ hipError_t launch_mfma_probe(double* out_dev, hipStream_t s)
     return hipGetLastError();
 }
 
-namespace {
-
-template <typename TA, typename TB, typename TC, bool F32>
-hipError_t launch_gemm_t(int64_t M, int64_t N, int64_t K, const TA* A, int64_t lda, const TB* B, int64_t ldb, bool bt,
-                         TC* C, int64_t ldc, int nsplit, int64_t split_stride, hipStream_t s)
-{
-    if (M <= 0 || N <= 0) return hipSuccess;
-    if (nsplit < 1) nsplit = 1;
-    int64_t kchunk = (K + nsplit - 1) / nsplit;
-    kchunk = ((kchunk + TK - 1) / TK) * TK;
-    if (kchunk <= 0) kchunk = TK;
-    const int64_t nz = (K + kchunk - 1) / kchunk;
-    dim3 grid((unsigned)((N + TN - 1) / TN), (unsigned)((M + TM - 1) / TM), (unsigned)(nz > 0 ? nz : 1)), block(256);
-    hipLaunchKernelGGL((gemm_kernel<TA, TB, TC, F32>), grid, block, 0, s, M, N, K, A, lda, B, ldb, bt ? 1 : 0, C, ldc,
-                       kchunk, split_stride);
-    if (nz < nsplit) {
-        // chunks beyond the K range would be left unwritten: clear them
-        for (int64_t z = nz; z < nsplit; ++z) {
-            const int64_t n = M * ldc;
-            int64_t blocks = (n + 255) / 256;
-            if (blocks > 65536) blocks = 65536;
-            hipLaunchKernelGGL((fill_kernel<TC>), dim3((unsigned)blocks), dim3(256), 0, s, C + z * split_stride, n,
-                               (TC)0);
-        }
-    }
-    return hipGetLastError();
-}
-
-template <typename TP>
-hipError_t launch_reduce_scatter_t(const TP* part, int nsplit, int64_t stride, int64_t M, int64_t N,
-                                   const int32_t* rows, const int32_t* cols, double* Kt, int64_t nbf, hipStream_t s)
-{
-    if (M <= 0 || N <= 0) return hipSuccess;
-    hipLaunchKernelGGL((reduce_scatter_kernel<TP>), rows_grid(M, N), dim3(256), 0, s, part, nsplit, stride, M, N, rows,
-                       cols, Kt, nbf);
-    return hipGetLastError();
-}
-
-}  // namespace
-
-hipError_t launch_gemm_f64(int64_t M, int64_t N, int64_t K, const double* A, int64_t lda, const double* B, int64_t ldb,
-                           bool bt, double* C, int64_t ldc, int nsplit, int64_t split_stride, hipStream_t s)
-{
-    return launch_gemm_t<double, double, double, false>(M, N, K, A, lda, B, ldb, bt, C, ldc, nsplit, split_stride, s);
-}
-
-hipError_t launch_gemm_f32(int64_t M, int64_t N, int64_t K, const float* A, int64_t lda, const float* B, int64_t ldb,
-                           bool bt, float* C, int64_t ldc, int nsplit, int64_t split_stride, hipStream_t s)
-{
-    return launch_gemm_t<float, float, float, true>(M, N, K, A, lda, B, ldb, bt, C, ldc, nsplit, split_stride, s);
-}
-
-hipError_t launch_gemm_f32_dA(int64_t M, int64_t N, int64_t K, const double* A, int64_t lda, const float* B,
-                              int64_t ldb, bool bt, double* C, int64_t ldc, int nsplit, int64_t split_stride,
-                              hipStream_t s)
-{
-    return launch_gemm_t<double, float, double, true>(M, N, K, A, lda, B, ldb, bt, C, ldc, nsplit, split_stride, s);
-}
-
-hipError_t launch_reduce_scatter(const double* part, int nsplit, int64_t stride, int64_t M, int64_t N,
-                                 const int32_t* rows, const int32_t* cols, double* Kt, int64_t nbf, hipStream_t s)
-{
-    return launch_reduce_scatter_t<double>(part, nsplit, stride, M, N, rows, cols, Kt, nbf, s);
-}
-
 hipError_t launch_convert_f32(const double* in, int64_t n, float* out, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
@@ -453,36 +221,6 @@ hipError_t launch_finish(const double* Kt, const double* P, double* K, int64_t n
     return hipGetLastError();
 }
 
-template <typename TO>
-static hipError_t launch_gather_t(const double* P, int64_t nbf, const int32_t* rows, int64_t M, const int32_t* cols,
-                                  int64_t N, TO* out, hipStream_t s)
-{
-    if (M <= 0 || N <= 0) return hipSuccess;
-    hipLaunchKernelGGL((gather_kernel<TO>), rows_grid(M, N), dim3(256), 0, s, P, nbf, rows, M, cols, N, out);
-    return hipGetLastError();
-}
-
-template <typename T>
-static hipError_t launch_scatter_rows_t(const T* in, int64_t M, int64_t ncols, const int32_t* rows, T* out, int64_t ld,
-                                       hipStream_t s)
-{
-    if (M <= 0 || ncols <= 0) return hipSuccess;
-    hipLaunchKernelGGL((scatter_rows_kernel<T>), rows_grid(M, ncols), dim3(256), 0, s, in, M, ncols, rows, out, ld);
-    return hipGetLastError();
-}
-
-hipError_t launch_scatter_rows(const double* in, int64_t M, int64_t ncols, const int32_t* rows, double* out, int64_t ld,
-                               hipStream_t s)
-{
-    return launch_scatter_rows_t<double>(in, M, ncols, rows, out, ld, s);
-}
-
-hipError_t launch_scatter_rows(const float* in, int64_t M, int64_t ncols, const int32_t* rows, float* out, int64_t ld,
-                               hipStream_t s)
-{
-    return launch_scatter_rows_t<float>(in, M, ncols, rows, out, ld, s);
-}
-
 hipError_t launch_fill_rows(double* p, int64_t ld, const int32_t* rows, int64_t M, int64_t ncols, double v,
                             hipStream_t s)
 {
@@ -524,18 +262,6 @@ hipError_t launch_ftilde_flag(const double* P, int64_t nbf, const int32_t* fn, c
     hipLaunchKernelGGL(ftilde_flag_kernel, dim3((unsigned)((nbf + 3) / 4), (unsigned)ntile), dim3(256), 0, s, P, nbf,
                        fn, roff, mx, eps, shell_of, nshell, flag);
     return hipGetLastError();
-}
-
-hipError_t launch_gather(const double* P, int64_t nbf, const int32_t* rows, int64_t M, const int32_t* cols, int64_t N,
-                         double* out, hipStream_t s)
-{
-    return launch_gather_t<double>(P, nbf, rows, M, cols, N, out, s);
-}
-
-hipError_t launch_gather(const double* P, int64_t nbf, const int32_t* rows, int64_t M, const int32_t* cols, int64_t N,
-                         float* out, hipStream_t s)
-{
-    return launch_gather_t<float>(P, nbf, rows, M, cols, N, out, s);
 }
 
 }  // namespace snk

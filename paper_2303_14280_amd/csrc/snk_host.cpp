@@ -4,7 +4,6 @@
 #include "snk.h"
 #include "snk_internal.h"
 
-#include <rocblas/rocblas.h>
 
 #include <algorithm>
 #include <chrono>
@@ -116,7 +115,7 @@ struct snk_ctx {
     int32_t* d_shell_flag = nullptr;    // [max_group_tiles][nshell]
     int32_t* d_trows = nullptr;         // [max_group_tiles][nbf]
     int32_t* d_tcount = nullptr;        // [max_group_tiles]
-    double* d_Gc = nullptr;             // [nbf][max_tile_cols]: gathered G rows, or compact F rows, of one tile
+    int32_t* d_rinv = nullptr;          // [max_group_tiles][nbf] local row of each function per tile, -1: none
     std::vector<int32_t> tile_rows;     // rows per tile of the current group
     // F GEMM rows restricted per tile to the functions whose bound |F| >= eps_basis
     bool frow_restrict = false;
@@ -127,24 +126,16 @@ struct snk_ctx {
     int32_t max_group_rows = 0;
     int32_t* d_fn_shell = nullptr;      // [nbf] shell of each function
     std::vector<int32_t> tile_frows;    // F rows per tile of the current group
-    // Small per-tile GEMMs run on kLanes streams at once (lane 0 is the context's stream),
-    // each lane with its own gather / product / partial-sum buffers
-    static constexpr int kLanes = 4;
-    int nlanes = 1;
-    hipStream_t lane_stream[kLanes] = {};
-    hipEvent_t lane_ev[kLanes] = {};
-    hipEvent_t lane_red[kLanes] = {};
-    hipEvent_t fork_ev = nullptr;
-    double* lane_Pg[kLanes] = {};
-    double* lane_Gc[kLanes] = {};
-    double* lane_part[kLanes] = {};
-    rocblas_handle lane_blas[kLanes] = {};   // [0] = blas; one handle per lane stream (own workspace)
+    // Grouped products: problem and reduction records of the launches, staged through a host
+    // mirror that is never rewritten before the stream has passed every copy out of it
+    char* d_arena = nullptr;
+    std::vector<char> h_arena;
+    size_t arena_cur = 0;
     // Plain FP64 builds (no screen, no basis screening) run consecutive groups on two streams
     // with two buffer sets, so that one group's GEMMs overlap the other's A.F kernels; the
     // reductions into K~ stay in group order.
     bool pipe = false;
     hipStream_t pstream[2] = {};
-    rocblas_handle pblas[2] = {};
     hipEvent_t pev_fork = nullptr, pev_k[2] = {}, pev_end[2] = {};
     double* p_Phi[2] = {};
     double* p_F[2] = {};
@@ -153,11 +144,10 @@ struct snk_ctx {
     bool zero_f_rows = false;           // write every zero row of F and G (readers of every row)
     double acc_fn = 0, acc_frows = 0, acc_grows = 0, acc_cols = 0;   // column-weighted tile sizes
     int nsplit = 1;                     // K GEMM split over points for full-width tiles
-    int64_t part_elems = 0;             // size of the split partial-sum buffer
+    int64_t part_elems = 0;             // capacity of the split partial-product buffer
     bool mixed = false;                 // SNK_MIXED + SNK_FP32_GEMM: FP32 Phi, P and F; FP32 matrix-core GEMMs
-    rocblas_handle blas = nullptr;      // SNK_ROCBLAS (FP64 builds)
-    float *d_Phi32 = nullptr, *d_F32 = nullptr, *d_P32 = nullptr, *d_Pg32 = nullptr;
-    double *d_Phi = nullptr, *d_F = nullptr, *d_G = nullptr, *d_part = nullptr, *d_Pg = nullptr;
+    float *d_Phi32 = nullptr, *d_F32 = nullptr, *d_P32 = nullptr;
+    double *d_Phi = nullptr, *d_F = nullptr, *d_G = nullptr, *d_part = nullptr;
     double *d_Kt = nullptr, *d_P = nullptr, *d_K = nullptr, *d_partial = nullptr, *d_ex = nullptr;
     double* d_boys = nullptr;
     int nfinish = 256;
@@ -217,25 +207,19 @@ struct snk_ctx {
     double* d_xF = nullptr;             // [nbf][xc_cols]
     double* d_xG = nullptr;             // [nbf][xc_cols] G = 2 Z
     double* d_xe = nullptr;             // [2][xc_cols] w eps, w rho per column
-    double* d_xpart = nullptr;          // [xc_nsplit][nbf][nbf] split partial products
     double* d_xred = nullptr;           // [512] partial sums
     double* d_xsum = nullptr;           // [2] E_xc, N_el
-    int32_t* d_iota = nullptr;          // [nbf] identity row / column map
-    double* d_xP = nullptr;             // [max_nB][max_nB] P[B_t, B_t] (basis-screened form)
     // sn-K and XC from one pass (snk_ctx_build_kxc): the XC point kernel and V product run on
     // each group's Phi and F right after its K product
     int kx_fn = 0;                      // functional while a combined build runs, else 0
     double* d_kxG = nullptr;            // [nbf][max_cols] G = 2 Z of the group
     double* d_kxe = nullptr;            // [2][max_cols] w eps, w rho
-    double* d_kxpart = nullptr;         // [kx_nsplit][nbf][nbf]
     double* d_kxKt = nullptr;           // [nbf][nbf] unsymmetrised V
     double* d_kxred = nullptr;          // [512]
     double* d_kxsum = nullptr;          // [3] E_xc, N_el, and the finish's unused trace
     XcTile* d_kxtiles = nullptr;        // one point-kernel tile per group: every shell, from row 0
     int32_t* d_kxshells = nullptr;      // identity shell list
     int kx_nsplit = 1;
-    double* xc_lane_P[kLanes] = {};     // per lane (lane 0: d_xP): P[B_t, B_t] of the lane's tile
-    double* xc_lane_part[kLanes] = {};  // per lane (lane 0: d_xpart): split products of the lane's tile
     XcTile* d_xtiles = nullptr;         // point-kernel tiles: one per chunk, or every tile of every group
     int32_t* d_xshells = nullptr;       // their shell lists, concatenated
     std::vector<int32_t> xc_gt0;        // first tile of each group in d_xtiles (basis-screened form)
@@ -551,6 +535,9 @@ constexpr int kBasisTileBatches = 16;
 
 // Plain FP64 builds of at least twice this many batches run two groups at once.
 constexpr int kPipeMinBatches = 64;
+// Workgroups a grouped product launch aims for (8 per compute unit): products with few output
+// tiles are split over k until the launch reaches it
+constexpr int64_t kGemmTarget = 2048;
 
 // Radius beyond which every Cartesian function of a shell is below eps in magnitude, for the
 // sphere test of Eq. basis_screen; -1 when the shell stays below eps everywhere.  Each
@@ -974,25 +961,12 @@ void free_ctx(snk_ctx* c)
     (void)hipFree(c->d_Phi32);
     (void)hipFree(c->d_F32);
     (void)hipFree(c->d_P32);
-    (void)hipFree(c->d_Pg32);
     (void)hipFree(c->d_shell_flag);
     (void)hipFree(c->d_trows);
     (void)hipFree(c->d_tcount);
-    (void)hipFree(c->d_Gc);
-    for (int k = 1; k < snk_ctx::kLanes; ++k) {
-        if (c->lane_blas[k]) (void)rocblas_destroy_handle(c->lane_blas[k]);
-        (void)hipFree(c->lane_Pg[k]);
-        (void)hipFree(c->lane_Gc[k]);
-        (void)hipFree(c->lane_part[k]);
-        if (c->lane_stream[k]) (void)hipStreamDestroy(c->lane_stream[k]);
-    }
-    for (int k = 0; k < snk_ctx::kLanes; ++k) {
-        if (c->lane_ev[k]) (void)hipEventDestroy(c->lane_ev[k]);
-        if (c->lane_red[k]) (void)hipEventDestroy(c->lane_red[k]);
-    }
-    if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
+    (void)hipFree(c->d_rinv);
+    (void)hipFree(c->d_arena);
     for (int k = 0; k < 2; ++k) {
-        if (c->pblas[k]) (void)rocblas_destroy_handle(c->pblas[k]);
         if (c->pstream[k]) (void)hipStreamDestroy(c->pstream[k]);
         if (c->pev_k[k]) (void)hipEventDestroy(c->pev_k[k]);
         if (c->pev_end[k]) (void)hipEventDestroy(c->pev_end[k]);
@@ -1012,7 +986,6 @@ void free_ctx(snk_ctx* c)
     (void)hipFree(c->d_F);
     (void)hipFree(c->d_G);
     (void)hipFree(c->d_part);
-    (void)hipFree(c->d_Pg);
     (void)hipFree(c->d_Kt);
     (void)hipFree(c->d_P);
     (void)hipFree(c->d_K);
@@ -1020,20 +993,13 @@ void free_ctx(snk_ctx* c)
     (void)hipFree(c->d_xF);
     (void)hipFree(c->d_xG);
     (void)hipFree(c->d_xe);
-    (void)hipFree(c->d_xpart);
     (void)hipFree(c->d_xred);
     (void)hipFree(c->d_xsum);
-    (void)hipFree(c->d_iota);
-    (void)hipFree(c->d_xP);
     (void)hipFree(c->d_xtiles);
     (void)hipFree(c->d_xshells);
-    for (double* p : {c->d_kxG, c->d_kxe, c->d_kxpart, c->d_kxKt, c->d_kxred, c->d_kxsum}) (void)hipFree(p);
+    for (double* p : {c->d_kxG, c->d_kxe, c->d_kxKt, c->d_kxred, c->d_kxsum}) (void)hipFree(p);
     (void)hipFree(c->d_kxtiles);
     (void)hipFree(c->d_kxshells);
-    for (int k = 1; k < snk_ctx::kLanes; ++k) {
-        (void)hipFree(c->xc_lane_P[k]);
-        (void)hipFree(c->xc_lane_part[k]);
-    }
     (void)hipFree(c->d_partial);
     (void)hipFree(c->d_ex);
     (void)hipFree(c->d_boys);
@@ -1076,7 +1042,6 @@ void free_ctx(snk_ctx* c)
         (void)hipFree(c->d_pool_bt[k]);
         (void)hipFree(c->d_pool_ab[k]);
     }
-    if (c->blas) (void)rocblas_destroy_handle(c->blas);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
@@ -1146,7 +1111,7 @@ int snk_ctx_create(const snk_basis* basis, const snk_grid* grid, const double* w
     if (!isfin(o.eps_basis) || o.eps_basis < 0.0) return arg_error(nullptr, "eps_basis must be >= 0");
     if (o.screen != SNK_SCREEN_NONE && (!isfin(o.eps_skip_energy) || o.eps_skip_energy < 0.0))
         return arg_error(nullptr, "eps_skip_energy must be finite and >= 0");
-    if (o.flags & ~(uint32_t)(SNK_DEVICE_PTRS | SNK_VALIDATE | SNK_ROCBLAS | SNK_FP32_GEMM | SNK_OVERLAP_GROUPS))
+    if (o.flags & ~(uint32_t)(SNK_DEVICE_PTRS | SNK_VALIDATE | SNK_FP32_GEMM | SNK_OVERLAP_GROUPS))
         return arg_error(nullptr, "unknown flag");
     if (o.screen == SNK_SCREEN_LEARNED) {
         if (!o.screener) return arg_error(nullptr, "SNK_SCREEN_LEARNED needs a screener network");
@@ -1245,7 +1210,7 @@ int snk_ctx_create(const snk_basis* basis, const snk_grid* grid, const double* w
     const int64_t nbf = c->nbf;
     {
         const int64_t tiles = ((nbf + 63) / 64) * ((c->max_nB + 63) / 64);
-        int ns = (int)std::max<int64_t>(1, (2048 + tiles - 1) / std::max<int64_t>(1, tiles));
+        int ns = (int)std::max<int64_t>(1, (kGemmTarget + tiles - 1) / std::max<int64_t>(1, tiles));
         ns = (int)std::min<int64_t>(ns, std::max<int64_t>(1, c->max_tile_cols / kBatch));
         c->nsplit = std::max(1, std::min(ns, 256));
     }
@@ -1253,18 +1218,15 @@ int snk_ctx_create(const snk_basis* basis, const snk_grid* grid, const double* w
         CREATE_CHECK(dalloc(c, &c->d_Phi32, (size_t)std::max<int64_t>(1, c->max_phi)));
         CREATE_CHECK(dalloc(c, &c->d_F32, (size_t)nbf * c->max_cols));
         CREATE_CHECK(dalloc(c, &c->d_P32, (size_t)nbf * nbf));
-        bool gather = o.eps_basis > 0.0;
-        for (const auto& g : c->groups)
-            for (const auto& t : g.tiles) gather |= !t.all_functions;
-        if (gather) CREATE_CHECK(dalloc(c, &c->d_Pg32, (size_t)nbf * c->max_nB));
     } else {
         CREATE_CHECK(dalloc(c, &c->d_Phi, (size_t)std::max<int64_t>(1, c->max_phi)));
         CREATE_CHECK(dalloc(c, &c->d_F, (size_t)nbf * c->max_cols));
     }
     CREATE_CHECK(dalloc(c, &c->d_G, (size_t)nbf * c->max_cols));
+    // partial products of the K GEMM: fixed size for full-width tiles (also the overlapped
+    // build's second set); grown on demand when the rows are restricted per tile
     c->part_elems = std::max<int64_t>(1, (int64_t)c->nsplit * nbf * c->max_nB);
     CREATE_CHECK(dalloc(c, &c->d_part, (size_t)c->part_elems));
-    CREATE_CHECK(dalloc(c, &c->d_Pg, (size_t)nbf * c->max_nB));
     CREATE_CHECK(dalloc(c, &c->d_Kt, (size_t)nbf * nbf));
     CREATE_CHECK(dalloc(c, &c->d_P, (size_t)nbf * nbf));
     CREATE_CHECK(dalloc(c, &c->d_K, (size_t)nbf * nbf));
@@ -1300,28 +1262,8 @@ int snk_ctx_create(const snk_basis* basis, const snk_grid* grid, const double* w
             for (int k = 0; k < ncart(c->sl[sh]); ++k) fs[c->sfn[sh] + k] = sh;
         CREATE_CHECK(upload(c, &c->d_fn_shell, fs));
     }
-    if (c->row_restrict || c->frow_restrict) {
-        CREATE_CHECK(dalloc(c, &c->d_Gc, (size_t)nbf * c->max_tile_cols));
-        // tiles are small: their GEMMs run on several streams (default priority) at once
-        c->nlanes = snk_ctx::kLanes;
-        c->lane_Pg[0] = c->d_Pg;
-        c->lane_Gc[0] = c->d_Gc;
-        c->lane_part[0] = c->d_part;
-        CREATE_CHECK(hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming) == hipSuccess ? SNK_OK : SNK_E_DEVICE);
-        for (int k = 0; k < c->nlanes; ++k) {
-            CREATE_CHECK(hipEventCreateWithFlags(&c->lane_ev[k], hipEventDisableTiming) == hipSuccess ? SNK_OK
-                                                                                                       : SNK_E_DEVICE);
-            CREATE_CHECK(hipEventCreateWithFlags(&c->lane_red[k], hipEventDisableTiming) == hipSuccess ? SNK_OK
-                                                                                                        : SNK_E_DEVICE);
-            if (k == 0) continue;
-            CREATE_CHECK(hipStreamCreateWithFlags(&c->lane_stream[k], hipStreamNonBlocking) == hipSuccess
-                             ? SNK_OK
-                             : SNK_E_DEVICE);
-            CREATE_CHECK(dalloc(c, &c->lane_Pg[k], (size_t)nbf * std::max<int32_t>(1, c->max_nB)));
-            CREATE_CHECK(dalloc(c, &c->lane_Gc[k], (size_t)nbf * c->max_tile_cols));
-            CREATE_CHECK(dalloc(c, &c->lane_part[k], (size_t)c->part_elems));
-        }
-    }
+    if (c->row_restrict || c->frow_restrict)
+        CREATE_CHECK(dalloc(c, &c->d_rinv, (size_t)std::max<int32_t>(1, c->max_group_tiles) * nbf));
     if (c->pipe) {
         c->p_Phi[0] = c->d_Phi;
         c->p_F[0] = c->d_F;
@@ -1339,36 +1281,6 @@ int snk_ctx_create(const snk_basis* basis, const snk_grid* grid, const double* w
                                                                                                     : SNK_E_DEVICE);
             CREATE_CHECK(hipEventCreateWithFlags(&c->pev_end[k], hipEventDisableTiming) == hipSuccess ? SNK_OK
                                                                                                       : SNK_E_DEVICE);
-        }
-    }
-    if ((o.flags & SNK_ROCBLAS) && !c->mixed && c->max_cols <= INT32_MAX && (int64_t)c->nbf <= INT32_MAX) {
-        if (rocblas_create_handle(&c->blas) != rocblas_status_success ||
-            rocblas_set_stream(c->blas, c->stream) != rocblas_status_success ||
-            rocblas_set_atomics_mode(c->blas, rocblas_atomics_not_allowed) != rocblas_status_success) {
-            set_err(c, "rocBLAS handle set-up failed");
-            g_last_error = c->err;
-            free_ctx(c);
-            return SNK_E_DEVICE;
-        }
-        for (int k = 0; k < 2 && c->pipe; ++k) {
-            if (rocblas_create_handle(&c->pblas[k]) != rocblas_status_success ||
-                rocblas_set_stream(c->pblas[k], c->pstream[k]) != rocblas_status_success ||
-                rocblas_set_atomics_mode(c->pblas[k], rocblas_atomics_not_allowed) != rocblas_status_success) {
-                set_err(c, "rocBLAS handle set-up failed");
-                g_last_error = c->err;
-                free_ctx(c);
-                return SNK_E_DEVICE;
-            }
-        }
-        for (int k = 1; k < c->nlanes; ++k) {
-            if (rocblas_create_handle(&c->lane_blas[k]) != rocblas_status_success ||
-                rocblas_set_stream(c->lane_blas[k], c->lane_stream[k]) != rocblas_status_success ||
-                rocblas_set_atomics_mode(c->lane_blas[k], rocblas_atomics_not_allowed) != rocblas_status_success) {
-                set_err(c, "rocBLAS handle set-up failed");
-                g_last_error = c->err;
-                free_ctx(c);
-                return SNK_E_DEVICE;
-            }
         }
     }
 #undef CREATE_CHECK
@@ -1396,8 +1308,7 @@ struct GroupStats {
     double skipped = 0.0;                   // bound on the energy of the skipped blocks
 };
 
-int tile_F(snk_ctx* c, const Group& g, int ti, const double* dP, hipStream_t s, int k);
-int tile_K(snk_ctx* c, const Group& g, int ti, bool restrict_rows, hipStream_t ls, int k);
+int group_fgemm(snk_ctx* c, const Group& g, const double* dP);
 
 // Steps of one batch group up to G: Eq. collocation, Eq. fmat, the screen (when enabled),
 // Eqs. 3c_grid + gmat.
@@ -1406,7 +1317,6 @@ int group_F(snk_ctx* c, const Group& g, const double* dP, bool timed)
 {
     hipStream_t s = c->stream;
     const int64_t nbf = c->nbf;
-    const int64_t ld = g.ncols;
     if (timed) HIPCHECK(c, hipEventRecord(c->ev[0], s));
     // Eq. collocation for every tile: Phi_t (nB x ncols_t, row stride ncols_t)
     for (const Tile& t : g.tiles) {
@@ -1441,236 +1351,228 @@ int group_F(snk_ctx* c, const Group& g, const double* dP, bool timed)
         HIPCHECK(c, hipMemcpyAsync(c->tile_frows.data(), c->d_fcount, ntile * sizeof(int32_t), hipMemcpyDeviceToHost, s));
         HIPCHECK(c, hipStreamSynchronize(s));
     }
-    // Eq. fmat per tile: F[:, tile columns] = P[:, B_t] Phi_t.  Tiles write disjoint columns,
-    // so their products run on all lanes at once (tile ti on lane ti mod nlanes).
-    const bool par = c->nlanes > 1 && ntile > 1;
-    if (par) {
-        HIPCHECK(c, hipEventRecord(c->fork_ev, s));
-        for (int k = 1; k < c->nlanes; ++k) HIPCHECK(c, hipStreamWaitEvent(c->lane_stream[k], c->fork_ev, 0));
-    }
-    int rc = SNK_OK;
-    for (int ti = 0; ti < ntile && rc == SNK_OK; ++ti) {
-        const int k = par ? ti % c->nlanes : 0;
-        rc = tile_F(c, g, ti, dP, k ? c->lane_stream[k] : s, k);
-    }
-    if (par) {
-        for (int k = 1; k < c->nlanes; ++k) {
-            HIPCHECK(c, hipEventRecord(c->lane_ev[k], c->lane_stream[k]));
-            HIPCHECK(c, hipStreamWaitEvent(s, c->lane_ev[k], 0));
-        }
-    }
+    // Eq. fmat for every tile in one grouped launch: F[L_t, tile columns] = P[L_t, B_t] Phi_t
+    int rc = group_fgemm(c, g, dP);
     if (rc) return rc;
     if (timed) HIPCHECK(c, hipEventRecord(c->ev[2], s));
     return SNK_OK;
 }
 
-// Eq. fmat for tile ti of group g on stream s with the buffers of lane k (lane 0: the
-// context's own buffers; only the restricted-row path runs on other lanes)
-int tile_F(snk_ctx* c, const Group& g, int ti, const double* dP, hipStream_t s, int k)
+// Copies n records into the device arena and returns their device address.  The host mirror
+// of a record is never rewritten before the stream has passed the copy that reads it: when the
+// arena is full the stream is drained and the arena restarts (larger if needed).
+int push_records(snk_ctx* c, const void* src, size_t bytes, const void** dptr)
+{
+    bytes = (bytes + 255) & ~(size_t)255;
+    if (c->arena_cur + bytes > c->h_arena.size()) {
+        // every stream of the context may still read records: wait for the device
+        HIPCHECK(c, hipDeviceSynchronize());
+        if (bytes > c->h_arena.size()) {
+            const size_t cap = std::max<size_t>(bytes, std::max<size_t>((size_t)1 << 20, 2 * c->h_arena.size()));
+            (void)hipFree(c->d_arena);
+            c->d_arena = nullptr;
+            HIPCHECK(c, hipMalloc((void**)&c->d_arena, cap));
+            c->h_arena.assign(cap, 0);
+        }
+        c->arena_cur = 0;
+    }
+    char* h = c->h_arena.data() + c->arena_cur;
+    std::memcpy(h, src, bytes);   // bytes is rounded up: the source is padded by the callers' vectors
+    HIPCHECK(c, hipMemcpyAsync(c->d_arena + c->arena_cur, h, bytes, hipMemcpyHostToDevice, c->stream));
+    *dptr = c->d_arena + c->arena_cur;
+    c->arena_cur += bytes;
+    return SNK_OK;
+}
+
+template <typename T>
+int push_vector(snk_ctx* c, std::vector<T>& v, const T** dptr)
+{
+    const size_t n = v.size();
+    v.resize(n + (256 + sizeof(T) - 1) / sizeof(T));   // padding read by the rounded copy
+    const void* d = nullptr;
+    const int rc = push_records(c, v.data(), n * sizeof(T), &d);
+    v.resize(n);
+    *dptr = static_cast<const T*>(d);
+    return rc;
+}
+
+enum GemmKind { kGemmF64 = 0, kGemmF32 = 1, kGemmF32dA = 2 };
+
+// One grouped launch of the products in probs (all read B the same way), on the context's stream.
+int run_gemms(snk_ctx* c, std::vector<GemmProb>& probs, GemmKind kind, bool bt)
+{
+    if (probs.empty()) return SNK_OK;
+    int64_t nwg = 0;
+    const int asz = kind == kGemmF32 ? 4 : 8, bsz = kind == kGemmF64 ? 8 : 4;
+    const int tile = ggemm_tile(probs.data(), (int)probs.size());
+    for (auto& p : probs) {
+        ggemm_plan(p, tile, asz, bsz);
+        p.wg0 = nwg;
+        nwg += ggemm_workgroups(p);
+    }
+    const GemmProb* d = nullptr;
+    int rc = push_vector(c, probs, &d);
+    if (rc) return rc;
+    const int n = (int)probs.size();
+    hipError_t e = kind == kGemmF64 ? launch_ggemm_f64(d, n, nwg, tile, bt, c->stream)
+                   : kind == kGemmF32 ? launch_ggemm_f32(d, n, nwg, tile, bt, c->stream)
+                                      : launch_ggemm_f32_dA(d, n, nwg, tile, bt, c->stream);
+    HIPCHECK(c, e);
+    return SNK_OK;
+}
+
+// T[r][ccol(n)] += sum_z part[tile][z][rinv(r)][n] for the tiles in list order (rows of T: nbf)
+int run_reduce(snk_ctx* c, std::vector<RedTile>& tiles, double* T)
+{
+    if (tiles.empty()) return SNK_OK;
+    const RedTile* d = nullptr;
+    int rc = push_vector(c, tiles, &d);
+    if (rc) return rc;
+    HIPCHECK(c, launch_group_reduce(c->d_part, d, (int)tiles.size(), T, c->nbf, c->nbf, c->stream));
+    return SNK_OK;
+}
+
+// The split partial-product buffer holds at least n elements (the stream is drained before
+// a smaller buffer is replaced).
+int ensure_part(snk_ctx* c, int64_t n)
+{
+    if (n <= c->part_elems) return SNK_OK;
+    if (c->pipe) {
+        set_err(c, "partial-product buffer too small for an overlapped build");
+        return SNK_E_DEVICE;
+    }
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    (void)hipFree(c->d_part);
+    c->d_part = nullptr;
+    const int64_t cap = std::max<int64_t>(n, c->part_elems + c->part_elems / 2);
+    int rc = dalloc(c, &c->d_part, (size_t)cap);
+    if (rc) {
+        c->part_elems = 0;
+        return rc;
+    }
+    c->part_elems = cap;
+    return SNK_OK;
+}
+
+// Chunks over k for a set of products with otiles output tiles in all: enough workgroups for
+// the device, chunks of whole batches, at most 256.
+int choose_ksplit(int64_t otiles, int64_t batches)
+{
+    const int64_t ks = (kGemmTarget + std::max<int64_t>(1, otiles) - 1) / std::max<int64_t>(1, otiles);
+    return (int)std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(ks, 256), std::max<int64_t>(1, batches)));
+}
+
+int64_t out_tiles(int64_t M, int64_t N) { return ((M + 63) / 64) * ((N + 63) / 64); }
+
+// Eq. fmat for group g: one grouped launch over its tiles, F[L_t, tile columns] = P[L_t, B_t] Phi_t
+// with the rows L_t and columns B_t of P read in place and the rows written straight into F.
+int group_fgemm(snk_ctx* c, const Group& g, const double* dP)
 {
     const int64_t nbf = c->nbf;
     const int64_t ld = g.ncols;
-    rocblas_handle blas = k ? c->lane_blas[k] : c->blas;   // bound to stream s
-    {
+    // rows outside L_t are zero; they are written only where a reader takes every row (no
+    // density screen, training data, debugging): the screens give those shells U = 0 without
+    // reading them and never list their blocks
+    const bool zero_rows = c->opts.screen == SNK_SCREEN_NONE || c->zero_f_rows;
+    bool need_zero = false;
+    std::vector<GemmProb> probs;
+    for (size_t ti = 0; ti < g.tiles.size(); ++ti) {
         const Tile& t = g.tiles[ti];
         const int64_t L = c->frow_restrict ? c->tile_frows[ti] : nbf;
         c->acc_fn += (double)t.nB * t.ncols;
         c->acc_frows += (double)L * t.ncols;
         c->acc_cols += (double)t.ncols;
-        if (t.nB == 0 || L == 0) {
-            // no function reaches the tile's points, or no row of F does
-            if (c->mixed) HIPCHECK(c, launch_fill2d(c->d_F32 + t.col0, nbf, t.ncols, ld, 0.0f, s));
-            else HIPCHECK(c, launch_fill2d(c->d_F + t.col0, nbf, t.ncols, ld, 0.0, s));
-            return SNK_OK;
-        }
-        if (c->frow_restrict && L < nbf) {
-            // F_c = P[L_t, B_t] Phi_t, then rows L_t of the tile's columns.  The other rows are
-            // zero; they are written only where a reader takes every row (no density screen,
-            // training data, debugging): the screens give those shells U = 0 without reading
-            // them and never list their blocks.
-            const bool zero_rows = c->opts.screen == SNK_SCREEN_NONE || c->zero_f_rows;
-            const int32_t* rows = c->d_frows + (int64_t)ti * nbf;
-            if (c->mixed) {
-                float* Fc = reinterpret_cast<float*>(c->lane_Gc[k]);
-                float* Pc = reinterpret_cast<float*>(c->lane_Pg[k]);
-                HIPCHECK(c, launch_gather(dP, nbf, rows, L, t.d_coll_fn, t.nB, Pc, s));
-                HIPCHECK(c, launch_gemm_f32(L, t.ncols, t.nB, Pc, t.nB, c->d_Phi32 + t.phi_off, t.ncols, false,
-                                            Fc, t.ncols, 1, 0, s));
-                if (zero_rows) HIPCHECK(c, launch_fill2d(c->d_F32 + t.col0, nbf, t.ncols, ld, 0.0f, s));
-                HIPCHECK(c, launch_scatter_rows(Fc, L, t.ncols, rows, c->d_F32 + t.col0, ld, s));
-                return SNK_OK;
-            }
-            double* Pc = c->lane_Pg[k];
-            double* Fc = c->lane_Gc[k];
-            HIPCHECK(c, launch_gather(dP, nbf, rows, L, t.d_coll_fn, t.nB, Pc, s));
-            if (blas) {
-                // column-major view: F_c^T (ncols_t x L) = Phi_t^T (ncols_t x nB) P_c^T (nB x L)
-                const double one = 1.0, zero = 0.0;
-                if (rocblas_dgemm(blas, rocblas_operation_none, rocblas_operation_none, (rocblas_int)t.ncols,
-                                  (rocblas_int)L, (rocblas_int)t.nB, &one, c->d_Phi + t.phi_off, (rocblas_int)t.ncols,
-                                  Pc, (rocblas_int)t.nB, &zero, Fc, (rocblas_int)t.ncols) != rocblas_status_success) {
-                    set_err(c, "rocblas_dgemm (F) failed");
-                    return SNK_E_DEVICE;
-                }
-            } else {
-                HIPCHECK(c, launch_gemm_f64(L, t.ncols, t.nB, Pc, t.nB, c->d_Phi + t.phi_off, t.ncols, false, Fc,
-                                            t.ncols, 1, 0, s));
-            }
-            if (zero_rows) HIPCHECK(c, launch_fill2d(c->d_F + t.col0, nbf, t.ncols, ld, 0.0, s));
-            HIPCHECK(c, launch_scatter_rows(Fc, L, t.ncols, rows, c->d_F + t.col0, ld, s));
-            return SNK_OK;
-        }
-        if (c->mixed) {
-            // FP32 Phi and F; P was rounded to FP32 once per build (d_P32), or is gathered to
-            // FP32 columns B_t
-            const float* Pg = c->d_P32;
-            int64_t ldp = nbf;
-            if (!t.all_functions) {
-                float* Pb = k ? reinterpret_cast<float*>(c->lane_Pg[k]) : c->d_Pg32;
-                HIPCHECK(c, launch_gather(dP, nbf, nullptr, nbf, t.d_coll_fn, t.nB, Pb, s));
-                Pg = Pb;
-                ldp = t.nB;
-            }
-            HIPCHECK(c, launch_gemm_f32(nbf, t.ncols, t.nB, Pg, ldp, c->d_Phi32 + t.phi_off, t.ncols, false,
-                                        c->d_F32 + t.col0, ld, 1, 0, s));
-            return SNK_OK;
-        }
-        const double* Pg = dP;
-        int64_t ldp = nbf;
-        if (!t.all_functions) {
-            double* Pb = k ? c->lane_Pg[k] : c->d_Pg;
-            HIPCHECK(c, launch_gather(dP, nbf, nullptr, nbf, t.d_coll_fn, t.nB, Pb, s));
-            Pg = Pb;
-            ldp = t.nB;
-        }
-        if (blas) {
-            // column-major view: F^T (ncols_t x nbf) = Phi_t^T (ncols_t x nB) P_t^T (nB x nbf)
-            const double one = 1.0, zero = 0.0;
-            if (rocblas_dgemm(blas, rocblas_operation_none, rocblas_operation_none, (rocblas_int)t.ncols,
-                              (rocblas_int)nbf, (rocblas_int)t.nB, &one, c->d_Phi + t.phi_off, (rocblas_int)t.ncols,
-                              Pg, (rocblas_int)ldp, &zero, c->d_F + t.col0, (rocblas_int)ld) != rocblas_status_success) {
-                set_err(c, "rocblas_dgemm (F) failed");
-                return SNK_E_DEVICE;
-            }
-        } else {
-            HIPCHECK(c, launch_gemm_f64(nbf, t.ncols, t.nB, Pg, ldp, c->d_Phi + t.phi_off, t.ncols, false,
-                                        c->d_F + t.col0, ld, 1, 0, s));
-        }
+        if (t.nB == 0 || L == 0 || L < nbf) need_zero |= zero_rows;
+        if (t.nB == 0 || L == 0) continue;
+        GemmProb p{};
+        p.A = c->mixed ? (const void*)c->d_P32 : (const void*)dP;
+        p.lda = nbf;
+        p.arow = L < nbf ? c->d_frows + (int64_t)ti * nbf : nullptr;
+        p.acol = t.all_functions ? nullptr : t.d_coll_fn;
+        p.B = c->mixed ? (const void*)(c->d_Phi32 + t.phi_off) : (const void*)(c->d_Phi + t.phi_off);
+        p.ldb = t.ncols;
+        p.C = c->mixed ? (void*)(c->d_F32 + t.col0) : (void*)(c->d_F + t.col0);
+        p.crow = p.arow;
+        p.ldc = ld;
+        p.M = (int32_t)L;
+        p.N = (int32_t)t.ncols;
+        p.K = t.nB;
+        p.ksplit = 1;
+        probs.push_back(p);
     }
-    return SNK_OK;
+    if (need_zero) {
+        if (c->mixed) HIPCHECK(c, launch_fill(c->d_F32, nbf * ld, 0.0f, c->stream));
+        else HIPCHECK(c, launch_fill(c->d_F, nbf * ld, 0.0, c->stream));
+    }
+    return run_gemms(c, probs, c->mixed ? kGemmF32 : kGemmF64, false);
 }
 
-// Eq. usym_k for one group: Kt[:, B_t] += G[:, tile columns] Phi_t^T for every tile, split
-// over grid points and reduced in a fixed order
+// Eq. usym_k for group g: Kt[M_t, B_t] += G[M_t, tile columns] Phi_t^T for every tile in one
+// grouped launch (split over points where the tiles are few), then one fixed-order reduction
+// of all tiles into Kt.  M_t: the rows of the tile's kept blocks (screen with basis screening;
+// every other row of G is zero on the tile), else every row.
 int group_K(snk_ctx* c, const Group& g)
 {
-    hipStream_t s = c->stream;
     const int64_t nbf = c->nbf;
     const int64_t ld = g.ncols;
     const bool restrict_rows = c->row_restrict && c->tile_rows.size() == g.tiles.size();
-    // tile products on all lanes at once; the reductions into Kt stay on the context's stream
-    // in tile order (fixed summation order), each after its product, and a lane reuses its
-    // partial-sum buffer only after the reduction that read it
-    const bool par = c->nlanes > 1 && g.tiles.size() > 1;
-    if (par) {
-        HIPCHECK(c, hipEventRecord(c->fork_ev, s));
-        for (int k = 1; k < c->nlanes; ++k) {
-            HIPCHECK(c, hipStreamWaitEvent(c->lane_stream[k], c->fork_ev, 0));
-            HIPCHECK(c, hipEventRecord(c->lane_red[k], s));
-        }
-    }
-    int rc = SNK_OK;
-    for (size_t ti = 0; ti < g.tiles.size() && rc == SNK_OK; ++ti) {
-        const int k = par ? (int)(ti % c->nlanes) : 0;
-        const hipStream_t ls = k ? c->lane_stream[k] : s;
-        if (k) HIPCHECK(c, hipStreamWaitEvent(ls, c->lane_red[k], 0));
-        rc = tile_K(c, g, (int)ti, restrict_rows, ls, k);
-        if (rc == SNK_OK && k) HIPCHECK(c, hipEventRecord(c->lane_red[k], s));
-    }
-    return rc;
-}
-
-// Eq. usym_k for tile ti: the product on stream ls with lane k's buffers, the reduction into Kt
-// on the context's stream after it
-int tile_K(snk_ctx* c, const Group& g, int ti, bool restrict_rows, hipStream_t ls, int k)
-{
-    hipStream_t s = c->stream;
-    const int64_t nbf = c->nbf;
-    const int64_t ld = g.ncols;
-    double* part = k ? c->lane_part[k] : c->d_part;
-    rocblas_handle blas = k ? c->lane_blas[k] : c->blas;   // bound to stream ls
-    {
+    const int ntile = (int)g.tiles.size();
+    int64_t otiles = 0;
+    int32_t max_rows = 0;
+    for (int ti = 0; ti < ntile; ++ti) {
         const Tile& t = g.tiles[ti];
-        if (t.nB == 0) return SNK_OK;   // nothing collocated: G Phi_t^T is empty
-        // rows of G the tile's kept blocks touch (all others are zero on the tile's columns)
-        int64_t M = nbf;
-        const double* Gt = c->d_G + t.col0;
-        int64_t ldg = ld;
-        const int32_t* rows = nullptr;
-        if (restrict_rows) {
-            M = c->tile_rows[ti];
-            c->acc_grows += (double)M * t.ncols;
-            if (M == 0) return SNK_OK;
-            rows = c->d_trows + (int64_t)ti * nbf;
-            double* Gc = k ? c->lane_Gc[k] : c->d_Gc;
-            HIPCHECK(c, launch_gather(Gt, ld, rows, M, nullptr, t.ncols, Gc, ls));
-            Gt = Gc;
-            ldg = t.ncols;
-        }
-        const int64_t stride = M * t.nB;
-        const int32_t* cols = t.all_functions ? nullptr : t.d_coll_fn;
-        // split over grid points so that the M x nB product fills the device (about 2048
-        // 64 x 64 output tiles in all), within the partial-sum buffer and whole batches
-        const int64_t otiles = ((M + 63) / 64) * ((t.nB + 63) / 64);
-        int64_t ns = std::max<int64_t>(c->nsplit, (2048 + otiles - 1) / otiles);
-        ns = std::min<int64_t>(ns, c->part_elems / std::max<int64_t>(1, stride));
-        ns = std::max<int64_t>(1, std::min<int64_t>(ns, std::min<int64_t>(256, t.b1 - t.b0)));
-        const int nsplit = (int)ns;
-        if (blas) {
-            // split over whole batches of points; column-major view of chunk z:
-            // part_z^T (nB x M) = Phi_z (nB x kchunk) G_z^T (kchunk x M), i.e. part_z = G_z Phi_z^T
-            const double* Phi = c->d_Phi + t.phi_off;
-            const double* G = Gt;
-            const int nb = t.b1 - t.b0;
-            const int bpc = (nb + nsplit - 1) / nsplit;
-            const int64_t kchunk = (int64_t)bpc * kBatch;
-            const int nfull = nb / bpc, rem = nb - nfull * bpc;
-            const double one = 1.0, zero = 0.0;
-            rocblas_status st = rocblas_status_success;
-            if (nfull > 0)
-                st = rocblas_dgemm_strided_batched(blas, rocblas_operation_transpose, rocblas_operation_none,
-                                                   (rocblas_int)t.nB, (rocblas_int)M, (rocblas_int)kchunk, &one, Phi,
-                                                   (rocblas_int)t.ncols, kchunk, G, (rocblas_int)ldg, kchunk, &zero,
-                                                   part, (rocblas_int)t.nB, stride, nfull);
-            if (st == rocblas_status_success && rem > 0)
-                st = rocblas_dgemm(blas, rocblas_operation_transpose, rocblas_operation_none, (rocblas_int)t.nB,
-                                   (rocblas_int)M, (rocblas_int)(rem * kBatch), &one, Phi + nfull * kchunk,
-                                   (rocblas_int)t.ncols, G + nfull * kchunk, (rocblas_int)ldg, &zero,
-                                   part + nfull * stride, (rocblas_int)t.nB);
-            if (st != rocblas_status_success) {
-                set_err(c, "rocblas_dgemm (K) failed");
-                return SNK_E_DEVICE;
-            }
-            if (k) {
-                HIPCHECK(c, hipEventRecord(c->lane_ev[k], ls));
-                HIPCHECK(c, hipStreamWaitEvent(s, c->lane_ev[k], 0));
-            }
-            HIPCHECK(c, launch_reduce_scatter(part, nfull + (rem > 0), stride, M, t.nB, rows, cols, c->d_Kt, nbf, s));
-        } else {
-            if (c->mixed)
-                HIPCHECK(c, launch_gemm_f32_dA(M, t.nB, t.ncols, Gt, ldg, c->d_Phi32 + t.phi_off, t.ncols, true, part,
-                                               t.nB, nsplit, stride, ls));
-            else
-                HIPCHECK(c, launch_gemm_f64(M, t.nB, t.ncols, Gt, ldg, c->d_Phi + t.phi_off, t.ncols, true, part,
-                                            t.nB, nsplit, stride, ls));
-            if (k) {
-                HIPCHECK(c, hipEventRecord(c->lane_ev[k], ls));
-                HIPCHECK(c, hipStreamWaitEvent(s, c->lane_ev[k], 0));
-            }
-            HIPCHECK(c, launch_reduce_scatter(part, nsplit, stride, M, t.nB, rows, cols, c->d_Kt, nbf, s));
-        }
+        const int64_t M = restrict_rows ? c->tile_rows[ti] : nbf;
+        if (restrict_rows) c->acc_grows += (double)M * t.ncols;
+        max_rows = std::max<int32_t>(max_rows, (int32_t)M);
+        if (t.nB > 0 && M > 0) otiles += out_tiles(M, t.nB);
     }
-    return SNK_OK;
+    if (otiles == 0) return SNK_OK;
+    int64_t need = 0;
+    std::vector<int> ks(ntile, 1);
+    for (int ti = 0; ti < ntile; ++ti) {
+        const Tile& t = g.tiles[ti];
+        const int64_t M = restrict_rows ? c->tile_rows[ti] : nbf;
+        if (t.nB == 0 || M == 0) continue;
+        ks[ti] = c->pipe ? c->nsplit : choose_ksplit(otiles, t.b1 - t.b0);
+        need += (int64_t)ks[ti] * M * t.nB;
+    }
+    int rc = ensure_part(c, need);
+    if (rc) return rc;
+    if (restrict_rows)
+        HIPCHECK(c, launch_rinv(c->d_trows, nbf, nullptr, c->d_tcount, ntile, nbf, max_rows, c->d_rinv, c->stream));
+    std::vector<GemmProb> probs;
+    std::vector<RedTile> red;
+    int64_t poff = 0;
+    for (int ti = 0; ti < ntile; ++ti) {
+        const Tile& t = g.tiles[ti];
+        const int64_t M = restrict_rows ? c->tile_rows[ti] : nbf;
+        if (t.nB == 0 || M == 0) continue;
+        GemmProb p{};
+        p.A = c->d_G + t.col0;
+        p.lda = ld;
+        p.arow = restrict_rows ? c->d_trows + (int64_t)ti * nbf : nullptr;
+        p.B = c->mixed ? (const void*)(c->d_Phi32 + t.phi_off) : (const void*)(c->d_Phi + t.phi_off);
+        p.ldb = t.ncols;
+        p.C = c->d_part + poff;
+        p.ldc = t.nB;
+        p.cstride = M * t.nB;
+        p.M = (int32_t)M;
+        p.N = t.nB;
+        p.K = (int32_t)t.ncols;
+        p.ksplit = ks[ti];
+        probs.push_back(p);
+        RedTile r{};
+        r.poff = poff;
+        r.M = (int32_t)M;
+        r.N = t.nB;
+        r.ksplit = ks[ti];
+        r.rinv = restrict_rows ? c->d_rinv + (int64_t)ti * nbf : nullptr;
+        r.ccol = t.all_functions ? nullptr : t.d_coll_fn;
+        red.push_back(r);
+        poff += (int64_t)ks[ti] * M * t.nB;
+    }
+    if ((rc = run_gemms(c, probs, c->mixed ? kGemmF32dA : kGemmF64, true))) return rc;
+    return run_reduce(c, red, c->d_Kt);
 }
 
 // U (bound factors) and N (F norms) of every shell on every batch of the group
@@ -1880,18 +1782,16 @@ int group_until_G(snk_ctx* c, const Group& g, const double* dP, bool timed, Grou
 
 namespace {
 
-// Points the context's stream, rocBLAS handle and group buffers at pipeline set k for the
+// Points the context's stream and group buffers at pipeline set k for the
 // duration of a build, and back to the context's own at restore() or destruction.
 struct PipeSwap {
     snk_ctx* c;
     bool on;
     hipStream_t s0;
-    rocblas_handle b0;
-    PipeSwap(snk_ctx* x, bool active) : c(x), on(active), s0(x->stream), b0(x->blas) {}
+    PipeSwap(snk_ctx* x, bool active) : c(x), on(active), s0(x->stream) {}
     void use(int k)
     {
         c->stream = c->pstream[k];
-        c->blas = b0 ? c->pblas[k] : nullptr;
         c->d_Phi = c->p_Phi[k];
         c->d_F = c->p_F[k];
         c->d_G = c->p_G[k];
@@ -1901,7 +1801,6 @@ struct PipeSwap {
     {
         if (!on) return;
         c->stream = s0;
-        c->blas = b0;
         c->d_Phi = c->p_Phi[0];
         c->d_F = c->p_F[0];
         c->d_G = c->p_G[0];
@@ -1945,14 +1844,15 @@ int xc_workspace(snk_ctx* c)
 {
     const int64_t nbf = c->nbf;
     const int64_t total = (int64_t)c->nbatch * kBatch;
-    const int64_t otiles = ((nbf + 63) / 64) * ((nbf + 63) / 64);
-    c->xc_nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(256, 2048 / std::max<int64_t>(1, otiles)));
     int64_t budget = c->opts.max_device_bytes;
     if (budget <= 0) {
         size_t fr = 0, tot = 0;
         if (hipMemGetInfo(&fr, &tot) != hipSuccess) fr = (size_t)8 << 30;
         budget = (int64_t)(0.25 * (double)fr);
     }
+    // split partial products of the V product: at most half the budget
+    c->xc_nsplit = (int)std::max<int64_t>(
+        1, std::min<int64_t>(choose_ksplit(out_tiles(nbf, nbf), 256), budget / 2 / std::max<int64_t>(1, nbf * nbf * 8)));
     budget -= (int64_t)c->xc_nsplit * nbf * nbf * 8;
     const int64_t per_col = 3 * nbf * 8 + 16;
     int64_t cols = budget / per_col;
@@ -1962,8 +1862,6 @@ int xc_workspace(snk_ctx* c)
         return SNK_E_NOMEM;
     }
     c->xc_cols = cols;
-    std::vector<int32_t> iota((size_t)nbf);
-    std::iota(iota.begin(), iota.end(), 0);
     // one point-kernel tile per chunk: every shell, F and G rows of stride ncols from 0
     std::vector<XcTile> tiles;
     for (int64_t col0 = 0; col0 < total; col0 += cols)
@@ -1973,11 +1871,9 @@ int xc_workspace(snk_ctx* c)
     int rc = 0;
     if ((rc = dalloc(c, &c->d_xphi, (size_t)(nbf * cols))) || (rc = dalloc(c, &c->d_xF, (size_t)(nbf * cols))) ||
         (rc = dalloc(c, &c->d_xG, (size_t)(nbf * cols))) || (rc = dalloc(c, &c->d_xe, (size_t)(2 * cols))) ||
-        (rc = dalloc(c, &c->d_xpart, (size_t)c->xc_nsplit * nbf * nbf)) || (rc = dalloc(c, &c->d_xred, 512)) ||
-        (!c->d_iota && (rc = upload(c, &c->d_iota, iota))) || (rc = upload(c, &c->d_xtiles, tiles)) ||
+        (rc = dalloc(c, &c->d_xred, 512)) || (rc = upload(c, &c->d_xtiles, tiles)) ||
         (rc = upload(c, &c->d_xshells, shells)) || (rc = dalloc(c, &c->d_xsum, 2))) {
-        // the identity map stays (the combined build shares it; freed with the context)
-        for (double** p : {&c->d_xphi, &c->d_xF, &c->d_xG, &c->d_xe, &c->d_xpart, &c->d_xred, &c->d_xsum}) {
+        for (double** p : {&c->d_xphi, &c->d_xF, &c->d_xG, &c->d_xe, &c->d_xred, &c->d_xsum}) {
             (void)hipFree(*p);
             *p = nullptr;
         }
@@ -2007,17 +1903,15 @@ int xc_workspace_tiled(snk_ctx* c)
             shells.insert(shells.end(), t.coll_shells.begin(), t.coll_shells.end());
         }
     }
-    const int64_t elems = std::max<int64_t>(1, c->max_phi), rows = std::max<int32_t>(1, c->max_nB);
+    const int64_t elems = std::max<int64_t>(1, c->max_phi);
     c->xc_cols = cols;
     c->xc_nsplit = kBasisTileBatches;
     int rc = 0;
     if ((rc = dalloc(c, &c->d_xphi, (size_t)elems)) || (rc = dalloc(c, &c->d_xF, (size_t)elems)) ||
         (rc = dalloc(c, &c->d_xG, (size_t)elems)) || (rc = dalloc(c, &c->d_xe, (size_t)(2 * cols))) ||
-        (rc = dalloc(c, &c->d_xP, (size_t)(rows * rows))) ||
-        (rc = dalloc(c, &c->d_xpart, (size_t)(c->xc_nsplit * rows * rows))) || (rc = dalloc(c, &c->d_xred, 512)) ||
-        (rc = upload(c, &c->d_xtiles, tiles)) || (rc = upload(c, &c->d_xshells, shells)) ||
-        (rc = dalloc(c, &c->d_xsum, 2))) {
-        for (double** p : {&c->d_xphi, &c->d_xF, &c->d_xG, &c->d_xe, &c->d_xP, &c->d_xpart, &c->d_xred, &c->d_xsum}) {
+        (rc = dalloc(c, &c->d_xred, 512)) || (rc = upload(c, &c->d_xtiles, tiles)) ||
+        (rc = upload(c, &c->d_xshells, shells)) || (rc = dalloc(c, &c->d_xsum, 2))) {
+        for (double** p : {&c->d_xphi, &c->d_xF, &c->d_xG, &c->d_xe, &c->d_xred, &c->d_xsum}) {
             (void)hipFree(*p);
             *p = nullptr;
         }
@@ -2027,121 +1921,80 @@ int xc_workspace_tiled(snk_ctx* c)
         c->d_xshells = nullptr;
         return rc;
     }
-    c->xc_lane_P[0] = c->d_xP;
-    c->xc_lane_part[0] = c->d_xpart;
-    for (int k = 1; k < c->nlanes; ++k) {
-        if ((rc = dalloc(c, &c->xc_lane_P[k], (size_t)(rows * rows))) ||
-            (rc = dalloc(c, &c->xc_lane_part[k], (size_t)(c->xc_nsplit * rows * rows)))) {
-            // undo everything, so that the next call makes the whole workspace again
-            for (int j = 1; j < c->nlanes; ++j) {
-                (void)hipFree(c->xc_lane_P[j]);
-                (void)hipFree(c->xc_lane_part[j]);
-                c->xc_lane_P[j] = c->xc_lane_part[j] = nullptr;
-            }
-            for (double** p : {&c->d_xphi, &c->d_xF, &c->d_xG, &c->d_xe, &c->d_xP, &c->d_xpart, &c->d_xred, &c->d_xsum}) {
-                (void)hipFree(*p);
-                *p = nullptr;
-            }
-            (void)hipFree(c->d_xtiles);
-            (void)hipFree(c->d_xshells);
-            c->d_xtiles = nullptr;
-            c->d_xshells = nullptr;
-            return rc;
-        }
-    }
     return SNK_OK;
 }
 
-// One batch group of the basis-screened XC build: Phi_t over B_t and F_t = P[B_t, B_t] Phi_t per
-// tile, the point kernel over all tiles at once, then Kt[B_t, B_t] += G_t Phi_t^T per tile
-// (split per batch).  The tiles' small products run on all lanes at once (tile ti on lane
-// ti mod nlanes, each lane with its own P_t and partial-sum buffers; Phi_t, F_t and G_t are
-// disjoint parts of the group buffers); the reductions into Kt stay on the context's stream
-// in tile order, and a lane reuses its partial-sum buffer only after the reduction that read it.
+// One batch group of the basis-screened XC build: Phi_t over B_t per tile, F_t = P[B_t, B_t] Phi_t
+// for every tile in one grouped launch (P read in place), the point kernel over all tiles at
+// once, then Kt[B_t, B_t] += G_t Phi_t^T for every tile in one grouped launch (split per
+// batch) and one fixed-order reduction of all tiles into Kt.
 int xc_group(snk_ctx* c, size_t gi, const double* dP, int functional)
 {
     hipStream_t s = c->stream;
     const Group& g = c->groups[gi];
     const int64_t nbf = c->nbf, goff = (int64_t)g.b0 * kBatch;
-    const bool par = c->nlanes > 1 && g.tiles.size() > 1;
-    auto fork = [&](bool reductions) -> int {
-        HIPCHECK(c, hipEventRecord(c->fork_ev, s));
-        for (int k = 1; k < c->nlanes; ++k) {
-            HIPCHECK(c, hipStreamWaitEvent(c->lane_stream[k], c->fork_ev, 0));
-            if (reductions) HIPCHECK(c, hipEventRecord(c->lane_red[k], s));
-        }
-        return SNK_OK;
-    };
-    int rc = par ? fork(false) : SNK_OK;
+    const int ntile = (int)g.tiles.size();
+    std::vector<GemmProb> fp, vp;
+    std::vector<RedTile> red;
+    int64_t need = 0;
+    for (const Tile& t : g.tiles) need += (int64_t)(t.b1 - t.b0) * t.nB * t.nB;
+    int rc = ensure_part(c, need);
     if (rc) return rc;
-    for (size_t ti = 0; ti < g.tiles.size(); ++ti) {
+    int64_t poff = 0;
+    int32_t max_nb = 0;
+    for (int ti = 0; ti < ntile; ++ti) {
         const Tile& t = g.tiles[ti];
         if (t.nB == 0) continue;
-        const int k = par ? (int)(ti % c->nlanes) : 0;
-        const hipStream_t ls = k ? c->lane_stream[k] : s;
-        const rocblas_handle blas = c->blas ? (k ? c->lane_blas[k] : c->blas) : nullptr;
-        const int64_t nB = t.nB, ncols = t.ncols, off = (int64_t)t.b0 * kBatch;
-        double* Phi = c->d_xphi + t.phi_off;
-        double* F = c->d_xF + t.phi_off;
-        double* Pt = c->xc_lane_P[k];
+        max_nb = std::max(max_nb, t.nB);
+        const int64_t ncols = t.ncols, off = (int64_t)t.b0 * kBatch;
         HIPCHECK(c, launch_collocate(c->d_px + off, c->d_py + off, c->d_pz + off, ncols, c->d_shells, c->d_exps,
-                                     c->d_coefs, t.d_coll_shells, t.d_coll_rows, (int32_t)t.coll_shells.size(), Phi,
-                                     ncols, ls));
-        HIPCHECK(c, launch_gather(dP, nbf, t.d_coll_fn, nB, t.d_coll_fn, nB, Pt, ls));
-        if (blas) {
-            const double one = 1.0, zero = 0.0;
-            if (rocblas_dgemm(blas, rocblas_operation_none, rocblas_operation_none, (rocblas_int)ncols,
-                              (rocblas_int)nB, (rocblas_int)nB, &one, Phi, (rocblas_int)ncols, Pt, (rocblas_int)nB,
-                              &zero, F, (rocblas_int)ncols) != rocblas_status_success) {
-                set_err(c, "rocblas_dgemm (XC F) failed");
-                return SNK_E_DEVICE;
-            }
-        } else {
-            HIPCHECK(c, launch_gemm_f64(nB, ncols, nB, Pt, nB, Phi, ncols, false, F, ncols, 1, 0, ls));
-        }
+                                     c->d_coefs, t.d_coll_shells, t.d_coll_rows, (int32_t)t.coll_shells.size(),
+                                     c->d_xphi + t.phi_off, ncols, s));
+        GemmProb p{};
+        p.A = dP;
+        p.lda = nbf;
+        p.arow = t.d_coll_fn;
+        p.acol = t.d_coll_fn;
+        p.B = c->d_xphi + t.phi_off;
+        p.ldb = ncols;
+        p.C = c->d_xF + t.phi_off;
+        p.ldc = ncols;
+        p.M = t.nB;
+        p.N = (int32_t)ncols;
+        p.K = t.nB;
+        p.ksplit = 1;
+        fp.push_back(p);
+        GemmProb v{};
+        v.A = c->d_xG + t.phi_off;
+        v.lda = ncols;
+        v.B = c->d_xphi + t.phi_off;
+        v.ldb = ncols;
+        v.C = c->d_part + poff;
+        v.ldc = t.nB;
+        v.cstride = (int64_t)t.nB * t.nB;
+        v.M = t.nB;
+        v.N = t.nB;
+        v.K = (int32_t)ncols;
+        v.ksplit = t.b1 - t.b0;
+        vp.push_back(v);
+        RedTile r{};
+        r.poff = poff;
+        r.M = t.nB;
+        r.N = t.nB;
+        r.ksplit = v.ksplit;
+        r.rinv = c->d_rinv + (int64_t)ti * nbf;
+        r.ccol = t.d_coll_fn;
+        red.push_back(r);
+        poff += (int64_t)v.ksplit * t.nB * t.nB;
     }
-    if (par)
-        for (int k = 1; k < c->nlanes; ++k) {
-            HIPCHECK(c, hipEventRecord(c->lane_ev[k], c->lane_stream[k]));
-            HIPCHECK(c, hipStreamWaitEvent(s, c->lane_ev[k], 0));
-        }
+    if ((rc = run_gemms(c, fp, kGemmF64, false))) return rc;
     HIPCHECK(c, launch_xc_point(c->d_px + goff, c->d_py + goff, c->d_pz + goff, c->d_pw + goff, g.ncols, c->d_shells,
                                 c->d_exps, c->d_coefs, c->d_xtiles + c->xc_gt0[gi], c->d_xshells, c->tile_batches,
                                 c->d_xF, functional, c->d_xG, c->d_xe, s));
     HIPCHECK(c, launch_xc_sum(c->d_xe, g.ncols, c->d_xred, c->d_xsum, true, s));
-    if (par && (rc = fork(true))) return rc;
-    for (size_t ti = 0; ti < g.tiles.size(); ++ti) {
-        const Tile& t = g.tiles[ti];
-        if (t.nB == 0) continue;
-        const int k = par ? (int)(ti % c->nlanes) : 0;
-        const hipStream_t ls = k ? c->lane_stream[k] : s;
-        const rocblas_handle blas = c->blas ? (k ? c->lane_blas[k] : c->blas) : nullptr;
-        const int64_t nB = t.nB, ncols = t.ncols;
-        const int nb = (int)(ncols / kBatch);
-        const double* Phi = c->d_xphi + t.phi_off;
-        const double* G = c->d_xG + t.phi_off;
-        double* part = c->xc_lane_part[k];
-        if (k) HIPCHECK(c, hipStreamWaitEvent(ls, c->lane_red[k], 0));
-        if (blas) {
-            const double one = 1.0, zero = 0.0;
-            if (rocblas_dgemm_strided_batched(blas, rocblas_operation_transpose, rocblas_operation_none,
-                                              (rocblas_int)nB, (rocblas_int)nB, kBatch, &one, Phi, (rocblas_int)ncols,
-                                              kBatch, G, (rocblas_int)ncols, kBatch, &zero, part, (rocblas_int)nB,
-                                              nB * nB, nb) != rocblas_status_success) {
-                set_err(c, "rocblas_dgemm (XC V) failed");
-                return SNK_E_DEVICE;
-            }
-        } else {
-            HIPCHECK(c, launch_gemm_f64(nB, nB, ncols, G, ncols, Phi, ncols, true, part, nB, nb, nB * nB, ls));
-        }
-        if (k) {
-            HIPCHECK(c, hipEventRecord(c->lane_ev[k], ls));
-            HIPCHECK(c, hipStreamWaitEvent(s, c->lane_ev[k], 0));
-        }
-        HIPCHECK(c, launch_reduce_scatter(part, nb, nB * nB, nB, nB, t.d_coll_fn, t.d_coll_fn, c->d_Kt, nbf, s));
-        if (k) HIPCHECK(c, hipEventRecord(c->lane_red[k], s));
-    }
-    return SNK_OK;
+    if ((rc = run_gemms(c, vp, kGemmF64, true))) return rc;
+    HIPCHECK(c, launch_rinv(g.d_fn_cat, 0, g.d_roff, nullptr, ntile, nbf, max_nb, c->d_rinv, s));
+    return run_reduce(c, red, c->d_Kt);
 }
 
 // Combined build: workspace of the group-sized XC buffers (FP64 contexts without basis
@@ -2149,19 +2002,17 @@ int xc_group(snk_ctx* c, size_t gi, const double* dP, int functional)
 int kx_workspace(snk_ctx* c)
 {
     const int64_t nbf = c->nbf, cols = std::max<int64_t>(kBatch, c->max_cols);
-    const int64_t otiles = ((nbf + 63) / 64) * ((nbf + 63) / 64);
-    c->kx_nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(256, 2048 / std::max<int64_t>(1, otiles)));
+    c->kx_nsplit = choose_ksplit(out_tiles(nbf, nbf), 256);
     std::vector<XcTile> tiles;
     for (const Group& g : c->groups) tiles.push_back(XcTile{0, (int32_t)g.ncols, 0, c->nshell, 0});
     std::vector<int32_t> shells((size_t)c->nshell);
     std::iota(shells.begin(), shells.end(), 0);
     int rc = 0;
     if ((rc = dalloc(c, &c->d_kxG, (size_t)(nbf * cols))) || (rc = dalloc(c, &c->d_kxe, (size_t)(2 * cols))) ||
-        (rc = dalloc(c, &c->d_kxpart, (size_t)c->kx_nsplit * nbf * nbf)) ||
         (rc = dalloc(c, &c->d_kxKt, (size_t)(nbf * nbf))) || (rc = dalloc(c, &c->d_kxred, 512)) ||
         (rc = upload(c, &c->d_kxtiles, tiles)) || (rc = upload(c, &c->d_kxshells, shells)) ||
         (rc = dalloc(c, &c->d_kxsum, 3))) {
-        for (double** p : {&c->d_kxG, &c->d_kxe, &c->d_kxpart, &c->d_kxKt, &c->d_kxred, &c->d_kxsum}) {
+        for (double** p : {&c->d_kxG, &c->d_kxe, &c->d_kxKt, &c->d_kxred, &c->d_kxsum}) {
             (void)hipFree(*p);
             *p = nullptr;
         }
@@ -2171,12 +2022,38 @@ int kx_workspace(snk_ctx* c)
         c->d_kxshells = nullptr;
         return rc;
     }
-    if (!c->d_iota) {
-        std::vector<int32_t> iota((size_t)nbf);
-        std::iota(iota.begin(), iota.end(), 0);
-        if ((rc = upload(c, &c->d_iota, iota))) return rc;
-    }
     return SNK_OK;
+}
+
+// Eq. vxc_num over ncols points of every function: T += G Phi^T (G and Phi nbf x ncols), split
+// over ksplit chunks of points and reduced in a fixed order
+int xc_vproduct(snk_ctx* c, const double* G, const double* Phi, int64_t ncols, int ksplit, double* T)
+{
+    const int64_t nbf = c->nbf;
+    ksplit = std::max(1, ksplit);
+    int rc = ensure_part(c, (int64_t)ksplit * nbf * nbf);
+    if (rc) return rc;
+    std::vector<GemmProb> vp(1);
+    GemmProb& v = vp[0];
+    v = GemmProb{};
+    v.A = G;
+    v.lda = ncols;
+    v.B = Phi;
+    v.ldb = ncols;
+    v.C = c->d_part;
+    v.ldc = nbf;
+    v.cstride = nbf * nbf;
+    v.M = (int32_t)nbf;
+    v.N = (int32_t)nbf;
+    v.K = (int32_t)ncols;
+    v.ksplit = ksplit;
+    if ((rc = run_gemms(c, vp, kGemmF64, true))) return rc;
+    std::vector<RedTile> red(1);
+    red[0] = RedTile{};
+    red[0].M = (int32_t)nbf;
+    red[0].N = (int32_t)nbf;
+    red[0].ksplit = ksplit;
+    return run_reduce(c, red, T);
 }
 
 // Combined build, group gi: the XC point kernel on the group's Phi and F (Eqs. den_grid,
@@ -2187,42 +2064,12 @@ int group_kx(snk_ctx* c, size_t gi)
     hipStream_t s = c->stream;
     const Group& g = c->groups[gi];
     const int64_t nbf = c->nbf, ncols = g.ncols, off = (int64_t)g.b0 * kBatch;
-    const size_t nb2 = (size_t)nbf * nbf;
     const double* Phi = c->d_Phi + g.tiles[0].phi_off;
     HIPCHECK(c, launch_xc_point(c->d_px + off, c->d_py + off, c->d_pz + off, c->d_pw + off, ncols, c->d_shells,
                                 c->d_exps, c->d_coefs, c->d_kxtiles + gi, c->d_kxshells, (int32_t)(ncols / kBatch),
                                 c->d_F, c->kx_fn, c->d_kxG, c->d_kxe, s));
     HIPCHECK(c, launch_xc_sum(c->d_kxe, ncols, c->d_kxred, c->d_kxsum, true, s));
-    if (c->blas) {
-        const int64_t nb = ncols / kBatch;
-        const int64_t bpc = (nb + c->kx_nsplit - 1) / c->kx_nsplit;
-        const int64_t kchunk = bpc * kBatch;
-        const int64_t nfull = nb / bpc, rem = nb - nfull * bpc;
-        const double one = 1.0, zero = 0.0;
-        rocblas_status st = rocblas_status_success;
-        if (nfull > 0)
-            st = rocblas_dgemm_strided_batched(c->blas, rocblas_operation_transpose, rocblas_operation_none,
-                                               (rocblas_int)nbf, (rocblas_int)nbf, (rocblas_int)kchunk, &one, Phi,
-                                               (rocblas_int)ncols, kchunk, c->d_kxG, (rocblas_int)ncols, kchunk, &zero,
-                                               c->d_kxpart, (rocblas_int)nbf, (int64_t)nb2, (rocblas_int)nfull);
-        if (st == rocblas_status_success && rem > 0)
-            st = rocblas_dgemm(c->blas, rocblas_operation_transpose, rocblas_operation_none, (rocblas_int)nbf,
-                               (rocblas_int)nbf, (rocblas_int)(rem * kBatch), &one, Phi + nfull * kchunk,
-                               (rocblas_int)ncols, c->d_kxG + nfull * kchunk, (rocblas_int)ncols, &zero,
-                               c->d_kxpart + nfull * (int64_t)nb2, (rocblas_int)nbf);
-        if (st != rocblas_status_success) {
-            set_err(c, "rocblas_dgemm (XC V) failed");
-            return SNK_E_DEVICE;
-        }
-        HIPCHECK(c, launch_reduce_scatter(c->d_kxpart, (int)(nfull + (rem > 0)), (int64_t)nb2, nbf, nbf, c->d_iota,
-                                          c->d_iota, c->d_kxKt, nbf, s));
-    } else {
-        HIPCHECK(c, launch_gemm_f64(nbf, nbf, ncols, c->d_kxG, ncols, Phi, ncols, true, c->d_kxpart, nbf,
-                                    c->kx_nsplit, (int64_t)nb2, s));
-        HIPCHECK(c, launch_reduce_scatter(c->d_kxpart, c->kx_nsplit, (int64_t)nb2, nbf, nbf, c->d_iota, c->d_iota,
-                                          c->d_kxKt, nbf, s));
-    }
-    return SNK_OK;
+    return xc_vproduct(c, c->d_kxG, Phi, ncols, std::min<int>(c->kx_nsplit, (int)(ncols / kBatch)), c->d_kxKt);
 }
 
 }  // namespace
@@ -2269,17 +2116,21 @@ int snk_vxc_build(snk_ctx* c, const double* P, int functional, double* V_out, do
         // Eqs. collocation, fmat
         HIPCHECK(c, launch_xc_collocate(c->d_px + col0, c->d_py + col0, c->d_pz + col0, ncols, c->d_shells, c->d_exps,
                                         c->d_coefs, c->d_shell_row, c->nshell, c->d_xphi, s));
-        if (c->blas) {
-            const double one = 1.0, zero = 0.0;
-            // column-major view: F^T (ncols x nbf) = Phi^T (ncols x nbf) P^T
-            if (rocblas_dgemm(c->blas, rocblas_operation_none, rocblas_operation_none, (rocblas_int)ncols,
-                              (rocblas_int)nbf, (rocblas_int)nbf, &one, c->d_xphi, (rocblas_int)ncols, dP,
-                              (rocblas_int)nbf, &zero, c->d_xF, (rocblas_int)ncols) != rocblas_status_success) {
-                set_err(c, "rocblas_dgemm (XC F) failed");
-                return SNK_E_DEVICE;
-            }
-        } else {
-            HIPCHECK(c, launch_gemm_f64(nbf, ncols, nbf, dP, nbf, c->d_xphi, ncols, false, c->d_xF, ncols, 1, 0, s));
+        {
+            std::vector<GemmProb> fp(1);
+            fp[0] = GemmProb{};
+            fp[0].A = dP;
+            fp[0].lda = nbf;
+            fp[0].B = c->d_xphi;
+            fp[0].ldb = ncols;
+            fp[0].C = c->d_xF;
+            fp[0].ldc = ncols;
+            fp[0].M = (int32_t)nbf;
+            fp[0].N = (int32_t)ncols;
+            fp[0].K = (int32_t)nbf;
+            fp[0].ksplit = 1;
+            int rc = run_gemms(c, fp, kGemmF64, false);
+            if (rc) return rc;
         }
         // Eqs. den_grid, exc_grid, zmat
         HIPCHECK(c, launch_xc_point(c->d_px + col0, c->d_py + col0, c->d_pz + col0, c->d_pw + col0, ncols, c->d_shells,
@@ -2287,37 +2138,8 @@ int snk_vxc_build(snk_ctx* c, const double* P, int functional, double* V_out, do
                                     (int32_t)(ncols / kBatch), c->d_xF, functional, c->d_xG, c->d_xe, s));
         HIPCHECK(c, launch_xc_sum(c->d_xe, ncols, c->d_xred, c->d_xsum, true, s));
         // Eq. vxc_num: Kt += G Phi^T over the chunk's points, split over points, fixed-order sum
-        if (c->blas) {
-            // split over whole batches; column-major view of chunk z: part_z^T = Phi_z G_z^T
-            const int64_t nb = ncols / kBatch;
-            const int64_t bpc = (nb + c->xc_nsplit - 1) / c->xc_nsplit;
-            const int64_t kchunk = bpc * kBatch;
-            const int64_t nfull = nb / bpc, rem = nb - nfull * bpc;
-            const double one = 1.0, zero = 0.0;
-            rocblas_status st = rocblas_status_success;
-            if (nfull > 0)
-                st = rocblas_dgemm_strided_batched(c->blas, rocblas_operation_transpose, rocblas_operation_none,
-                                                   (rocblas_int)nbf, (rocblas_int)nbf, (rocblas_int)kchunk, &one,
-                                                   c->d_xphi, (rocblas_int)ncols, kchunk, c->d_xG, (rocblas_int)ncols,
-                                                   kchunk, &zero, c->d_xpart, (rocblas_int)nbf, (int64_t)nb2,
-                                                   (rocblas_int)nfull);
-            if (st == rocblas_status_success && rem > 0)
-                st = rocblas_dgemm(c->blas, rocblas_operation_transpose, rocblas_operation_none, (rocblas_int)nbf,
-                                   (rocblas_int)nbf, (rocblas_int)(rem * kBatch), &one, c->d_xphi + nfull * kchunk,
-                                   (rocblas_int)ncols, c->d_xG + nfull * kchunk, (rocblas_int)ncols, &zero,
-                                   c->d_xpart + nfull * (int64_t)nb2, (rocblas_int)nbf);
-            if (st != rocblas_status_success) {
-                set_err(c, "rocblas_dgemm (XC V) failed");
-                return SNK_E_DEVICE;
-            }
-            HIPCHECK(c, launch_reduce_scatter(c->d_xpart, (int)(nfull + (rem > 0)), (int64_t)nb2, nbf, nbf, c->d_iota,
-                                              c->d_iota, c->d_Kt, nbf, s));
-        } else {
-            HIPCHECK(c, launch_gemm_f64(nbf, nbf, ncols, c->d_xG, ncols, c->d_xphi, ncols, true, c->d_xpart, nbf,
-                                        c->xc_nsplit, (int64_t)nb2, s));
-            HIPCHECK(c, launch_reduce_scatter(c->d_xpart, c->xc_nsplit, (int64_t)nb2, nbf, nbf, c->d_iota, c->d_iota,
-                                              c->d_Kt, nbf, s));
-        }
+        int rc = xc_vproduct(c, c->d_xG, c->d_xphi, ncols, std::min<int>(c->xc_nsplit, (int)(ncols / kBatch)), c->d_Kt);
+        if (rc) return rc;
     }
     // V = (Kt + Kt^T) / 2 with G = 2 Z; the finish's trace term is not used here
     HIPCHECK(c, launch_finish(c->d_Kt, dP, dV, nbf, c->d_partial, c->nfinish, c->d_ex, s));
@@ -2519,7 +2341,27 @@ int snk_debug_gemm_f64(int64_t M, int64_t N, int64_t K, const double* A, int64_t
 {
     if (M < 0 || N < 0 || K < 0 || !A || !B || !C) return arg_error(nullptr, "bad GEMM arguments");
     if (lda < K || ldc < N || ldb < (bt ? K : N)) return arg_error(nullptr, "leading dimension too small");
-    hipError_t e = launch_gemm_f64(M, N, K, A, lda, B, ldb, bt != 0, C, ldc, 1, 0, (hipStream_t)stream);
+    if (M > INT32_MAX || N > INT32_MAX || K > INT32_MAX) return arg_error(nullptr, "GEMM too large");
+    GemmProb p{};
+    p.A = A;
+    p.lda = lda;
+    p.B = B;
+    p.ldb = ldb;
+    p.C = C;
+    p.ldc = ldc;
+    p.M = (int32_t)M;
+    p.N = (int32_t)N;
+    p.K = (int32_t)K;
+    p.ksplit = 1;
+    const int tile = ggemm_tile(&p, 1);
+    ggemm_plan(p, tile, 8, 8);
+    GemmProb* d = nullptr;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipMalloc((void**)&d, sizeof(GemmProb));
+    if (e == hipSuccess) e = hipMemcpyAsync(d, &p, sizeof(GemmProb), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_ggemm_f64(d, 1, ggemm_workgroups(p), tile, bt != 0, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(d);
     if (e != hipSuccess) {
         g_last_error = hipGetErrorString(e);
         return SNK_E_DEVICE;

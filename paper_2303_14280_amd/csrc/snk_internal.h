@@ -260,24 +260,56 @@ hipError_t launch_collocate(const double* px, const double* py, const double* pz
                             const ShellDev* shells, const double* exps, const double* coefs,
                             const int32_t* shell_list, const int32_t* shell_row, int32_t nsh,
                             float* Phi, int64_t ld, hipStream_t s);
-// C[M x N] = A[M x K] * op(B); A row-major (lda); B row-major K x N (ldb) or, with bt, N x K.
-// With nsplit > 1 the K range is cut into nsplit chunks and chunk z writes C + z * split_stride.
-hipError_t launch_gemm_f64(int64_t M, int64_t N, int64_t K, const double* A, int64_t lda, const double* B,
-                           int64_t ldb, bool bt, double* C, int64_t ldc, int nsplit, int64_t split_stride,
-                           hipStream_t s);
-// FP32 matrix-core forms: operands rounded to FP32, FP32 accumulation over at most 1024
-// consecutive k, FP64 accumulation across those runs.  The _dA form takes FP64 A and writes
-// FP64 C (the K~ partials of the mixed build).
-hipError_t launch_gemm_f32(int64_t M, int64_t N, int64_t K, const float* A, int64_t lda, const float* B,
-                           int64_t ldb, bool bt, float* C, int64_t ldc, int nsplit, int64_t split_stride,
-                           hipStream_t s);
-hipError_t launch_gemm_f32_dA(int64_t M, int64_t N, int64_t K, const double* A, int64_t lda, const float* B,
-                              int64_t ldb, bool bt, double* C, int64_t ldc, int nsplit, int64_t split_stride,
-                              hipStream_t s);
+// Grouped products (k_ggemm.hip).  One problem: for i < M, j < N and chunk z of k,
+//   C[z * cstride + crow(i) * ldc + j] = sum_k A[arow(i) * lda + acol(k)] B(k, j)
+// with arow, acol, crow the identity where null, B(k, j) = B[k * ldb + j] (row-major) or
+// B[j * ldb + k] (bt); the k range [0, K) is cut into ksplit chunks of kchunk.  The host
+// fills the operands, sizes and ksplit; ggemm_plan sets kchunk, tm, tn and vec, and wg0 is the
+// problem's first workgroup in the launch (sum of ggemm_workgroups of the problems before it).
+struct GemmProb {
+    const void* A;
+    const int32_t* arow;
+    const int32_t* acol;
+    int64_t lda;
+    const void* B;
+    int64_t ldb;
+    void* C;
+    const int32_t* crow;
+    int64_t ldc;
+    int64_t cstride;
+    int64_t wg0;
+    int32_t M, N, K, ksplit, kchunk, tm, tn;
+    int32_t vec;   // bit 0: A rows 16-byte aligned, bit 1: B rows (set by ggemm_plan)
+};
+// One tile of a grouped reduction: T[r][ccol(n)] += sum_z part[poff + z M N + rinv(r) N + n]
+// for every row r with rinv(r) >= 0 (rinv null: r < M), in list order.
+struct RedTile {
+    int64_t poff;
+    int32_t M, N, ksplit, pad;
+    const int32_t* rinv;
+    const int32_t* ccol;
+};
+// Output tile (64 or 128) for a launch of these problems (M, N, K and ksplit filled in): 64 for
+// short k per workgroup, else 128 unless 64 saves most of the padded work
+int ggemm_tile(const GemmProb* probs, int nprob);
+// asize, bsize: bytes per element of A and B
+void ggemm_plan(GemmProb& p, int tile, int asize, int bsize);
+int64_t ggemm_workgroups(const GemmProb& p);
+// probs: device array of nprob problems planned for the tile size, nwg workgroups in all;
+// FP64 matrix cores
+hipError_t launch_ggemm_f64(const GemmProb* probs, int nprob, int64_t nwg, int tile, bool bt, hipStream_t s);
+// FP32 matrix-core forms: operands rounded to FP32, FP32 sums over at most 1024 consecutive k
+// added into FP64 sums; f32: FP32 A, B, C; f32_dA: FP64 A, FP32 B, FP64 C
+hipError_t launch_ggemm_f32(const GemmProb* probs, int nprob, int64_t nwg, int tile, bool bt, hipStream_t s);
+hipError_t launch_ggemm_f32_dA(const GemmProb* probs, int nprob, int64_t nwg, int tile, bool bt, hipStream_t s);
+// T (nrow rows of stride ldt) += the tiles' chunk sums, one workgroup per row, tiles in order
+hipError_t launch_group_reduce(const double* part, const RedTile* tiles, int ntile, double* T, int64_t ldt,
+                               int64_t nrow, hipStream_t s);
+// rinv[t][r] = position of r in tile t's row list (lists[roff[t] .. roff[t+1]) when roff is
+// given, else lists[t * stride .. t * stride + counts[t])), -1 for rows not listed
+hipError_t launch_rinv(const int32_t* lists, int64_t stride, const int32_t* roff, const int32_t* counts, int ntile,
+                       int64_t nbf, int64_t max_count, int32_t* rinv, hipStream_t s);
 hipError_t launch_convert_f32(const double* in, int64_t n, float* out, hipStream_t s);
-// Kt[rows[m] * nbf + cols[n]] += sum_z part[z * stride + m * N + n]
-hipError_t launch_reduce_scatter(const double* part, int nsplit, int64_t stride, int64_t M, int64_t N,
-                                 const int32_t* rows, const int32_t* cols, double* Kt, int64_t nbf, hipStream_t s);
 hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t s);
 hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t s);
 hipError_t launch_fill(int32_t* p, int64_t n, int32_t v, hipStream_t s);
@@ -309,11 +341,6 @@ hipError_t launch_xc_point(const double* px, const double* py, const double* pz,
                            double* epart, hipStream_t s);
 hipError_t launch_xc_sum(const double* epart, int64_t n, double* partial, double* out, bool accumulate, hipStream_t s);
 hipError_t launch_boys_eval(const double* T, int64_t n, int mmax, double* F, const double* tab, hipStream_t s);
-// out[rows[m] * ld + c] = in[m * ncols + c] for m < M, c < ncols
-hipError_t launch_scatter_rows(const double* in, int64_t M, int64_t ncols, const int32_t* rows, double* out, int64_t ld,
-                               hipStream_t s);
-hipError_t launch_scatter_rows(const float* in, int64_t M, int64_t ncols, const int32_t* rows, float* out, int64_t ld,
-                               hipStream_t s);
 // p[rows[m] * ld + c] = v for m < M, c < ncols
 hipError_t launch_fill_rows(double* p, int64_t ld, const int32_t* rows, int64_t M, int64_t ncols, double v,
                             hipStream_t s);
@@ -328,10 +355,5 @@ hipError_t launch_row_absmax(const float* Phi, int64_t nfull, int64_t ncols_full
 hipError_t launch_ftilde_flag(const double* P, int64_t nbf, const int32_t* fn, const int32_t* roff, int32_t ntile,
                               const double* mx, double eps, const int32_t* shell_of, int32_t nshell, int32_t* flag,
                               hipStream_t s);
-// gather P_g[m][n] = P[rows[m]][cols[n]] (NULL rows/cols: identity), stored FP64 or rounded to FP32
-hipError_t launch_gather(const double* P, int64_t nbf, const int32_t* rows, int64_t M, const int32_t* cols,
-                         int64_t N, double* out, hipStream_t s);
-hipError_t launch_gather(const double* P, int64_t nbf, const int32_t* rows, int64_t M, const int32_t* cols,
-                         int64_t N, float* out, hipStream_t s);
 
 }  // namespace snk

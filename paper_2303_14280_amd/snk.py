@@ -21,7 +21,6 @@ SNK_FP64, SNK_MIXED = 0, 1
 SNK_SCREEN_NONE, SNK_SCREEN_BOUND, SNK_SCREEN_LEARNED, SNK_SCREEN_LINK = 0, 1, 2, 3
 SNK_DEVICE_PTRS = 0x1
 SNK_VALIDATE = 0x2
-SNK_ROCBLAS = 0x4
 SNK_FP32_GEMM = 0x8
 SNK_OVERLAP_GROUPS = 0x10
 SNK_XC_SLATER, SNK_XC_LDA, SNK_XC_PBE = 1, 2, 3

@@ -9,7 +9,7 @@ Checks:
   * at eps_basis = 1e-13 the dropped collocation values are below 1e-13, so K and E_x keep
     the FP64 parity bar against the unscreened oracle while most groups drop functions;
   * at the paper's operating tolerance (1e-9) |dE_x| stays below 1e-6 Eh;
-  * the rocBLAS and native GEMM paths, the mixed build and the screens agree on the same
+  * the FP64 build, the mixed build and the screens agree on the same
     B_t, including tiles that collocate nothing, and with several tiles per group.
 """
 import os
@@ -61,18 +61,17 @@ def test_basis_sets_contain_significant_functions(eps):
         assert np.min(sizes) < s.nbf
 
 
-@pytest.mark.parametrize("blas", [False, True])
-def test_tight_basis_screen_keeps_fp64_parity(blas):
+def test_tight_basis_screen_keeps_fp64_parity():
     g = np.load(os.path.join(GOLDEN, "oracle_config1.npz"))
     s = synth.make_system(1, with_density=False).with_density(g["P"])
-    flags = snk.SNK_ROCBLAS if blas else 0
+    flags = 0
     ctx = snk.Context(s, eps_basis=1e-13, max_device_bytes=group_bytes(s, 6), flags=flags)
     sizes = [fn.size for _, _, _, fn in ctx.tiles()]
     K, st = ctx.build(s.P)
     dE = abs(st["ex"] - float(g["ex"][0]))
     dK = float(np.max(np.abs(K - g["K"])))
     say("config1 eps_basis 1e-13 (%s): %d tiles, |B_t| mean %.1f of %d; |dE| %.2e max|dK| %.2e" %
-        ("rocBLAS" if blas else "native", len(sizes), np.mean(sizes), s.nbf, dE, dK))
+        ("native", len(sizes), np.mean(sizes), s.nbf, dE, dK))
     assert min(sizes) < s.nbf
     assert np.array_equal(K, K.T)
     assert dE <= 1e-10
@@ -82,7 +81,7 @@ def test_tight_basis_screen_keeps_fp64_parity(blas):
 def test_paper_basis_tolerance_config2():
     g = np.load(os.path.join(GOLDEN, "oracle_config2.npz"))
     s = synth.make_system(2, with_density=False).with_density(g["P"])
-    ctx = snk.Context(s, eps_basis=1e-9, flags=snk.SNK_ROCBLAS)
+    ctx = snk.Context(s, eps_basis=1e-9)
     sizes = [fn.size for _, _, _, fn in ctx.tiles()]
     K, st = ctx.build(s.P)
     dE = abs(st["ex"] - float(g["ex"][0]))
@@ -97,15 +96,14 @@ def test_paper_basis_tolerance_config2():
 def test_paths_agree_with_empty_groups():
     """Two grid centres 30 bohr apart, all basis functions (compact, exponents >= 1) on the
     first: at eps_basis = 1e-6 the groups around the second centre, and the outer groups of
-    the first, collocate nothing.  Native FP64 GEMMs, rocBLAS and the mixed FP32-GEMM build
-    agree, and a tolerance above every function's peak gives K = 0 exactly."""
+    the first, collocate nothing.  Two FP64 contexts and the mixed FP32-GEMM build agree, and a tolerance above every function's peak gives K = 0 exactly."""
     shells = [[(0, [3.0, 1.0], [0.5, 0.5]), (1, [2.0], [1.0]), (2, [1.5], [1.0])], []]
     s = synth.make_custom([8, 1], [[0.0, 0.0, 0.0], [0.0, 0.0, 30.0]], shells, grid=(20, 50), n_occ=2)
     kw = dict(eps_basis=1e-6, max_device_bytes=group_bytes(s, 1))
     ctx = snk.Context(s, **kw)
     sizes = np.array([fn.size for _, _, _, fn in ctx.tiles()])
     K0, st0 = ctx.build(s.P)
-    K1, st1 = snk.Context(s, flags=snk.SNK_ROCBLAS, **kw).build(s.P)
+    K1, st1 = snk.Context(s, **kw).build(s.P)
     K2, st2 = snk.Context(s, precision=snk.SNK_MIXED, flags=snk.SNK_FP32_GEMM, **kw).build(s.P)
     Kr, exr, _ = O.snk(s)
     say("eps_basis 1e-6: %d tiles, %d empty, |B_t| max %d of %d; E_x %.12f / %.12f / %.12f, oracle %.12f" %
@@ -145,8 +143,8 @@ def test_learned_screen_with_basis_screen():
         pytest.skip("no trained screener weights")
     m = snk.load_screener()
     s = synth.make_system(2)
-    K0, st0 = snk.sn_k_build(s, eps_basis=1e-9, flags=snk.SNK_ROCBLAS)
-    for flags in (snk.SNK_ROCBLAS, 0):
+    K0, st0 = snk.sn_k_build(s, eps_basis=1e-9)
+    for flags in (0,):
         ctx = snk.Context(s, eps_basis=1e-9, screen=snk.SNK_SCREEN_LEARNED, screener=m, flags=flags)
         K1, st1 = ctx.build(s.P)
         K2, _ = ctx.build(s.P)

@@ -30,10 +30,13 @@ def test_mfma_f64_layout():
 
 
 @pytest.mark.parametrize("bt", [False, True])
-def test_gemm_f64_vs_numpy(bt):
+@pytest.mark.parametrize("shape", [(100, 130, 77), (300, 517, 333), (1, 1, 1), (129, 257, 16)])
+def test_gemm_f64_vs_numpy(bt, shape):
+    """The grouped matrix-core product on one problem: ragged edges of the 128 x 128 output
+    tiles and of the 16-wide k steps, several tiles in both directions."""
     import torch
     rng = np.random.default_rng(1)
-    M, N, K = 100, 130, 77
+    M, N, K = shape
     A = rng.normal(size=(M, K))
     B = rng.normal(size=(N, K)) if bt else rng.normal(size=(K, N))
     ref = A @ (B.T if bt else B)
@@ -41,7 +44,7 @@ def test_gemm_f64_vs_numpy(bt):
     Bd = torch.tensor(B, device="cuda")
     Cd = torch.full((M, N), float("nan"), dtype=torch.float64, device="cuda")
     torch.cuda.synchronize()
-    say("gemm bt", bt)
+    say("gemm bt", bt, "shape", shape)
     snk.debug_gemm_f64(M, N, K, Ad.data_ptr(), K, Bd.data_ptr(), K if bt else N, bt, Cd.data_ptr(), N)
     torch.cuda.synchronize()
     C = Cd.cpu().numpy()

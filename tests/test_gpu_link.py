@@ -35,7 +35,7 @@ def skipped_fraction(st):
 def test_link_against_oracle(cfg, eps):
     g = np.load(os.path.join(GOLDEN, "oracle_config%d.npz" % cfg))
     s = synth.make_system(cfg, with_density=False).with_density(g["P"])
-    K, st = snk.sn_k_build(s, screen=snk.SNK_SCREEN_LINK, eps_skip_energy=eps, flags=snk.SNK_ROCBLAS)
+    K, st = snk.sn_k_build(s, screen=snk.SNK_SCREEN_LINK, eps_skip_energy=eps)
     dE = abs(st["ex"] - float(g["ex"][0]))
     say("config %d link eps %.0e: skipped %.4f, |dE| %.2e, reported bound %.2e, max|dK| %.2e, afg %.2f ms" %
         (cfg, eps, skipped_fraction(st), dE, st["skipped_bound"], np.max(np.abs(K - g["K"])), st["t_afg_ms"]))

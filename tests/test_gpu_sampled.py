@@ -9,8 +9,8 @@ seeded set S of functions of every angular momentum.
 
 * eps_basis = 0: the plain definition on both sides, |dK| <= 1e-11 max|K[S][S]| (rounding
   order only, as in the full parity tests).
-* eps_basis = 1e-9, rocBLAS GEMMs (the launch configuration of the plain FP64 build of the
-  large clusters in bench.py): collocation values below 1e-9 and F rows whose bound is
+* eps_basis = 1e-9 (the launch configuration of the plain FP64 build of the large clusters
+  in bench.py): collocation values below 1e-9 and F rows whose bound is
   below 1e-9 are dropped, so K[S][S] may move by ~1e-9 times O(1) sums of |G| and |Phi|;
   the test allows 1e-9 max|K[S][S]| (measured: the same ~1e-13 as without screening).
 """
@@ -52,9 +52,9 @@ def test_sampled_block_matches_oracle(cfg, stride):
     say("config %d: %d functions, %d of the grid points, rows %s" % (cfg, sub.nbf, sub.npts, rows.tolist()))
     Kref = O.k_block(sub, rows)
     scale = float(np.max(np.abs(Kref)))
-    K0, st0 = snk.sn_k_build(sub, flags=snk.SNK_ROCBLAS)
+    K0, st0 = snk.sn_k_build(sub)
     d0 = float(np.max(np.abs(K0[np.ix_(rows, rows)] - Kref)))
-    K1, st1 = snk.sn_k_build(sub, flags=snk.SNK_ROCBLAS, eps_basis=1e-9)
+    K1, st1 = snk.sn_k_build(sub, eps_basis=1e-9)
     d1 = float(np.max(np.abs(K1[np.ix_(rows, rows)] - Kref)))
     say("config %d: max|K[S][S]| %.3e; eps_basis 0: max|dK| %.2e (rel %.1e); eps_basis 1e-9: max|dK| %.2e "
         "(rel %.1e), tile F rows %.0f of %d" % (cfg, scale, d0, d0 / scale, d1, d1 / scale, st1["tile_frows"],

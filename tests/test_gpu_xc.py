@@ -46,26 +46,26 @@ def test_config1_matches_oracle(functional):
 
 @pytest.mark.parametrize("functional", [snk.SNK_XC_LDA, snk.SNK_XC_PBE])
 def test_config2_subset_matches_oracle(functional):
-    """config 2 (290 functions) on every 7th grid point, through rocBLAS for F."""
+    """config 2 (290 functions) on every 7th grid point."""
     s = synth.make_system(2)
     s = s.subset_points(np.arange(3, s.npts, 7))
-    ctx = snk.Context(s, flags=snk.SNK_ROCBLAS)
+    ctx = snk.Context(s)
     V, exc, nel = ctx.vxc(s.P, functional)
     compare(V, exc, nel, s, functional, "config2/7")
 
 
 def test_chunks_paths_and_determinism():
-    """A small device budget (several chunks of batches), the library's GEMM and rocBLAS, two
-    calls in a row: same V to rounding, bitwise equal per path and call."""
+    """A small device budget (several chunks of batches) and one chunk, two calls in a row: same V
+    to rounding, bitwise equal per call."""
     s = synth.make_system(1)
     # split partial products (256 x nbf^2) plus three FP64 rows per column: ten batches a chunk
     budget = 256 * 38 * 38 * 8 + (3 * 38 * 8 + 16) * 2560
     a = snk.Context(s, max_device_bytes=budget)
-    b = snk.Context(s, flags=snk.SNK_ROCBLAS)
+    b = snk.Context(s)
     Va, ea, na = a.vxc(s.P, snk.SNK_XC_PBE)
     Va2, ea2, _ = a.vxc(s.P, snk.SNK_XC_PBE)
     Vb, eb, nb = b.vxc(s.P, snk.SNK_XC_PBE)
-    say("chunked (native GEMM) vs one chunk (rocBLAS F): |dE| %.2e max|dV| %.2e" %
+    say("chunked vs one chunk: |dE| %.2e max|dV| %.2e" %
         (abs(ea - eb), np.max(np.abs(Va - Vb))))
     assert np.array_equal(Va, Va2) and ea == ea2
     assert np.max(np.abs(Va - Vb)) <= 1e-12 * np.max(np.abs(Vb))
@@ -137,7 +137,7 @@ def test_basis_screened_sampled_large(cfg, stride):
     s = synth.make_system(cfg)
     off = int(np.random.default_rng([cfg, 91]).integers(stride))
     s = s.subset_points(np.arange(off, s.npts, stride))
-    ctx = snk.Context(s, eps_basis=1e-9, flags=snk.SNK_ROCBLAS)
+    ctx = snk.Context(s, eps_basis=1e-9)
     sizes = [fn.size for _, _, _, fn in ctx.tiles()]
     V, exc, nel = ctx.vxc(s.P, snk.SNK_XC_PBE)
     V2, exc2, _ = ctx.vxc(s.P, snk.SNK_XC_PBE)
@@ -160,7 +160,7 @@ def test_xc_ignores_sn_k_modes_and_leaves_k_unchanged():
     s = s.subset_points(np.arange(0, s.npts, 5))
     V0, e0, _ = snk.Context(s).vxc(s.P, snk.SNK_XC_PBE)
     kws = [dict(screen=snk.SNK_SCREEN_LINK, eps_skip_energy=1e-9),
-           dict(flags=snk.SNK_OVERLAP_GROUPS | snk.SNK_ROCBLAS, max_device_bytes=64 * s.nbf * 256 * 24)]
+           dict(flags=snk.SNK_OVERLAP_GROUPS, max_device_bytes=64 * s.nbf * 256 * 24)]
     if os.path.exists(snk.SCREENER_WEIGHTS):
         kws.append(dict(precision=snk.SNK_MIXED, screen=snk.SNK_SCREEN_LEARNED, screener=snk.load_screener()))
     for kw in kws:
@@ -174,7 +174,7 @@ def test_xc_ignores_sn_k_modes_and_leaves_k_unchanged():
         assert np.array_equal(K1, K2) and st1["ex"] == st2["ex"]
 
 
-@pytest.mark.parametrize("kw", [dict(), dict(flags=snk.SNK_ROCBLAS), dict(screen=snk.SNK_SCREEN_LINK, eps_skip_energy=1e-9),
+@pytest.mark.parametrize("kw", [dict(), dict(screen=snk.SNK_SCREEN_LINK, eps_skip_energy=1e-9),
                                 dict(eps_basis=1e-9)])
 def test_combined_build_matches_separate_calls(kw):
     """snk_ctx_build_kxc (Phi and F shared between sn-K and XC where the context allows it) gives
