@@ -55,10 +55,18 @@ typedef enum snk_status {
 
 typedef enum snk_precision {
     SNK_FP64 = 0,           /* every step in FP64 */
-    SNK_MIXED = 1           /* with a screen: blocks whose estimated energies sum to at most
-                               eps_lowprec_energy / 1e-5 per build run their Boys function,
-                               recurrences and A.F contraction in FP32 (G, K and the rest FP64);
-                               with SNK_FP32_GEMM also FP32 Phi/P/F and FP32 matrix-core GEMMs */
+    SNK_MIXED = 1           /* with a screen and eps_basis > 0: per tile, the functions whose
+                               largest |phi| over the tile's points is below 1e-3 enter both
+                               dense products (Eqs. fmat, usym_k) through the FP32 matrix cores
+                               (their P columns and Phi rows rounded to FP32, FP32 sums of at
+                               most 1024 terms added to the FP64 products of the other
+                               functions); stats->lowprec_bound is a rigorous bound on the
+                               energy this moves.  Boys function, recurrences, A.F, G and K stay
+                               FP64.  With a screen and eps_basis = 0: blocks whose estimated
+                               energies sum to at most eps_lowprec_energy / 1e-5 per build run
+                               their Boys function, recurrences and A.F contraction in FP32.
+                               With SNK_FP32_GEMM: FP32 Phi/P/F and FP32 matrix-core GEMMs for
+                               every function (the uniform form, outside the 1e-6 Eh budget) */
 } snk_precision;
 
 typedef enum snk_screen {
@@ -127,6 +135,13 @@ typedef struct snk_stats {
     double tile_functions;       /* |B_t|, collocated functions per tile (mean weighted by columns) */
     double tile_frows;           /* rows of F computed per tile (N_b, or |L_t| with eps_basis > 0) */
     double tile_grows;           /* rows of G in the K GEMM per tile (N_b, or |M_t| with screening and eps_basis > 0) */
+    double gemm_flops_fp64;      /* flops of the two dense products (Eqs. fmat, usym_k) on the FP64 matrix cores */
+    double gemm_flops_fp32;      /* ... and on the FP32 matrix cores (SNK_MIXED) */
+    double lowprec_bound;        /* SNK_MIXED with basis and density screening: rigorous bound on |dE_x|
+                                    from the FP32 dense products (see SNK_MIXED); 0 otherwise */
+    double t_gemm_ms[4];         /* GPU time (HIP events) of the grouped dense-product launches: F on
+                                    the FP64 / FP32 matrix cores, K~ on the FP64 / FP32 matrix cores */
+    int64_t gemm_launches[4];    /* ... and the number of such timed launch sequences (one per group) */
 } snk_stats;
 
 typedef struct snk_mlp snk_mlp;
@@ -250,14 +265,6 @@ const char* snk_last_error(const snk_ctx* ctx);   /* NULL ctx: last error of a c
 int snk_version(void);
 
 /*
- * Boys function on the device (Eq. boys), as used by the integral kernels:
- * F_m(T[k]) for m = 0..mmax (mmax <= 4) written to F_out[k*(mmax+1) + m].
- * T and F_out are device pointers, n values; ordered on `stream` (hipStream_t or
- * NULL for the default stream).  For checking the kernels' special function.
- */
-int snk_boys_device(const double* T, int64_t n, int mmax, double* F_out, void* stream);
-
-/*
  * Basis screening radius (Eq. basis_screen), host only: the radius beyond which every
  * Cartesian function of a shell of angular momentum l (contracted over nprim primitives
  * with exponents exps and coefficients coefs as in snk_basis) is below eps in magnitude;
@@ -290,6 +297,7 @@ int snk_shell_rcut(int l, const double* exps, const double* coefs, int nprim, do
  *   given upstream gradient dy[n] (device), into grads (nparams + 1 floats, the last 0): the
  *   plain backward pass of the FP32 network.
  * snk_mlp_adam_step: one Adam update (beta 0.9 / 0.999, eps 1e-8) at step t >= 1.
+
  */
 int snk_mlp_nparams(void);
 int snk_mlp_create(int device, snk_mlp** out);
@@ -336,42 +344,7 @@ int snk_ctx_block_data(snk_ctx* ctx, const double* P, float* features, double* b
 int snk_collect_block_norms(snk_ctx* ctx, const double* P, float* feats, float* target, int64_t cap,
                             int64_t* n_out);
 
-/*
- * Test hooks (diagnostics; not needed for building K).
- *
- * snk_debug_gemm_f64: C = A op(B) with the library's FP64 matrix-core GEMM on device
- *   pointers: A is M x K row-major (lda), B is K x N row-major (ldb) or, with bt != 0,
- *   N x K row-major; C is M x N row-major (ldc).  Ordered on `stream`.
- * snk_debug_mfma_layout: writes 256 doubles to host memory `out`: element 4*lane + r of
- *   one v_mfma_f64_16x16x4f64 whose inputs encode D[i][j] = 100 j + i (layout check).
- * snk_ctx_point_order: col_to_point[c] (host, nbatches*256 entries) = input index of the
- *   grid point in batch column c, or -1 for a padding slot.
- * snk_ctx_debug_intermediates: for the first batch group only, the collocation matrix
- *   Phi (Eq. collocation), F (Eq. fmat) and G (Eq. gmat), each nbf x ncols row-major in
- *   host memory (ncols = 256 * batches of that group, returned in *ncols_out); elements of
- *   Phi outside their tile's B_t are zero; P is a host pointer.  Pass NULL for any output not
- *   wanted.
- * snk_ctx_npair_index: size of the pair index space, nshell (nshell + 1) / 2 (pair of
- *   shells s >= t at s (s + 1) / 2 + t).
- * snk_ctx_debug_learned: runs the learned screen of the first batch group (context made
- *   with SNK_SCREEN_LEARNED; P a host pointer) and copies to host memory, per batch b of
- *   that group and pair index p, the raw network output yraw[b * npair_index + p] and the
- *   block estimate log2 est[...] (NaN for blocks the bound already skipped), and the
- *   first kept estimate bin thr[b].  *nbatch_out = batches of the group.
- * snk_debug_mfma_bf16: D = A B (16 x 16 row-major host D) through one bf16 matrix-core op,
- *   A and B rounded to bf16: with k32 = 0, A and B are 16 x 16 (16x16x16 op); with k32 != 0,
- *   A is 16 x 32 and B 32 x 16 (16x16x32 op).  Layout check.
- */
-int snk_debug_gemm_f64(int64_t M, int64_t N, int64_t K, const double* A, int64_t lda, const double* B,
-                       int64_t ldb, int bt, double* C, int64_t ldc, void* stream);
-int snk_debug_mfma_layout(double* out);
-int snk_ctx_point_order(const snk_ctx* ctx, int64_t* col_to_point);
-int snk_ctx_debug_intermediates(snk_ctx* ctx, const double* P, double* Phi, double* F, double* G,
-                                int64_t* ncols_out);
-int64_t snk_ctx_npair_index(const snk_ctx* ctx);
-int snk_ctx_debug_learned(snk_ctx* ctx, const double* P, float* yraw, float* est, int32_t* thr,
-                          int64_t* nbatch_out);
-int snk_debug_mfma_bf16(const float* A, const float* B, float* D, int k32);
+/* Test hooks (diagnostics, not needed to build K) are declared in snk_testing.h. */
 
 #ifdef __cplusplus
 }

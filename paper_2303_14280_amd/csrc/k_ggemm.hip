@@ -14,8 +14,9 @@
 // of its problems), k in steps of 16 staged through double-buffered LDS with the next step's
 // global loads in flight during the current step's matrix-core work.  FP64 mode:
 // v_mfma_f64_16x16x4f64, FP64 operands and sums.  FP32 mode: operands rounded to FP32 as they
-// are staged, v_mfma_f32_16x16x4f32 with FP32 sums over at most kFlushK consecutive k, added
-// into FP64 sums.
+// are staged, v_mfma_f32_16x16x4f32 with FP32 sums over the workgroup's k chunk; the host keeps
+// those chunks at most kFp32MaxK long and adds chunks in FP64 (split products) or FP64
+// accumulation into C.
 //
 // A deterministic scatter-add of the chunk products into a row-major FP64 target goes with
 // it: one workgroup per target row walks the tiles in list order.
@@ -25,7 +26,6 @@ namespace snk {
 namespace {
 
 constexpr int GBK = 16, GPAD = 4;
-constexpr int kFlushK = 1024;
 
 template <int MODE>
 struct GTraits;
@@ -71,67 +71,66 @@ __device__ inline void loadv(GP<const T> p, TS* out)
     }
 }
 
-// WB x WB blocks of 16 x 16 per wave, 2 x 2 waves: BM = BN = 32 WB outputs per workgroup
-template <typename TA, typename TB, typename TC, int MODE, bool BT, int WB>
-__global__ __launch_bounds__(256) void ggemm_kernel(const GemmProb* __restrict__ probs, int nprob, int64_t nwg)
+// One operand pair of a product as the main loop reads it: A(i, k) = A[arow(i) lda + acol(k)]
+// (k contiguous), B(k, j) = B[bmap(k) ldb + j] or, transposed, B[bmap(j) ldb + k].
+template <typename TA, typename TB>
+struct Operands {
+    GP<const TA> A;
+    const int32_t* arow;
+    const int32_t* acol;
+    int64_t lda;
+    GP<const TB> B;
+    const int32_t* bmap;
+    int64_t ldb;
+    bool avec, bvec;
+};
+
+// Double-buffered LDS staging of BM x GBK (A, k-major) and GBK x BN (B) operand tiles.
+template <typename TS, int WB>
+struct Stage {
+    TS A[2][GBK][32 * WB + GPAD];
+    TS B[2][GBK][32 * WB + GPAD];
+};
+
+template <typename TS>
+__device__ inline void mfma_step(TS a, TS b, typename GTraits<sizeof(TS) == 4 ? 1 : 0>::acc4& acc)
 {
-    typedef typename GTraits<MODE>::TS TS;
-    typedef typename GTraits<MODE>::acc4 acc4;
+    if constexpr (sizeof(TS) == 4) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+    else acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+}
+
+// The k loop of one workgroup over [kbeg, kend) for outputs [m0, m0 + BM) x [n0, n0 + BN)
+// (rows < M, columns < N): operands staged to TS (FP64 or FP32) in LDS, matrix-core products
+// accumulated into acc (the wave's WB x WB blocks).  Every load address is clamped into the
+// operand (k to kend - 1, columns to N - 1) and out-of-range elements are staged as zeros;
+// runs that lie inside and start on 16-byte aligned rows are read as vectors.
+template <typename TS, typename TA, typename TB, bool BT, int WB>
+__device__ inline void mainloop(Stage<TS, WB>& L, const Operands<TA, TB>& op, int64_t M, int64_t N, int64_t m0,
+                                int64_t n0, int64_t kbeg, int64_t kend,
+                                typename GTraits<sizeof(TS) == 4 ? 1 : 0>::acc4 (&acc)[WB][WB])
+{
     constexpr int BM = 32 * WB, BN = 32 * WB;
     constexpr int E = BM * GBK / 256;   // operand elements each thread stages per k step
     constexpr int TPR = GBK / E;        // threads per k-contiguous run of 16
-    __shared__ TS As[2][GBK][BM + GPAD];
-    __shared__ TS Bs[2][GBK][BN + GPAD];
-
-    // The hardware deals consecutive workgroups out to the 8 XCDs in turn; workgroup w takes
-    // logical tile (w % 8) * per + w / 8, so each XCD works through one contiguous range of
-    // tiles (tiles that share operands share that XCD's L2).
-    const int64_t per = gridDim.x >> 3;   // gridDim.x is a multiple of 8
-    const int64_t w = blockIdx.x;
-    const int64_t logical = (w & 7) * per + (w >> 3);
-    if (logical >= nwg) return;
-    int lo = 0, hi = nprob - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (probs[mid].wg0 <= logical) lo = mid;
-        else hi = mid - 1;
-    }
-    const GemmProb pr = probs[lo];
-    const int local = (int)(logical - pr.wg0);   // < tm tn ksplit, far below 2^31
-    const int tmn = pr.tm * pr.tn;
-    const int z = local / tmn;
-    const int rmn = local - z * tmn;
-    const int tn_i = rmn / pr.tm;
-    const int tm_i = rmn - tn_i * pr.tm;
-    const int64_t m0 = (int64_t)tm_i * BM, n0 = (int64_t)tn_i * BN;
-    const int64_t kbeg = (int64_t)z * pr.kchunk;
-    const int64_t kend = kbeg + pr.kchunk < pr.K ? kbeg + pr.kchunk : pr.K;
     const int nk = kend > kbeg ? (int)((kend - kbeg + GBK - 1) / GBK) : 0;
-
-    const GP<const TA> A = glb(static_cast<const TA*>(pr.A));
-    const GP<const TB> B = glb(static_cast<const TB*>(pr.B));
-    const GP<const int32_t> acol = glb(pr.acol);
-    const bool avec = (pr.vec & 1) != 0, bvec = (pr.vec & 2) != 0;
+    const GP<const int32_t> acol = glb(op.acol);
+    const GP<const int32_t> bmap = glb(op.bmap);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = (wave >> 1) * (BM / 2), wn = (wave & 1) * (BN / 2);
     const int li = lane & 15, lk = lane >> 4;
 
-    // global -> register staging: A row tid / TPR, k run (tid % TPR) * E; rows past M read
-    // row M - 1 and stage zeros
+    // A row tid / TPR, k run (tid % TPR) * E; rows past M read row M - 1 and stage zeros
     const int ai = tid / TPR, ak = (tid % TPR) * E;
     const int64_t gma = m0 + ai;
-    const bool a_ok = gma < pr.M;
-    const int64_t arow_i = a_ok ? gma : pr.M - 1;
-    const GP<const TA> arow_ptr = A + (int64_t)(pr.arow ? glb(pr.arow)[arow_i] : arow_i) * pr.lda;
+    const bool a_ok = gma < M;
+    const int64_t arow_i = a_ok ? gma : M - 1;
+    const GP<const TA> arow_ptr = op.A + (int64_t)(op.arow ? glb(op.arow)[arow_i] : arow_i) * op.lda;
     // B: row-major -> k = tid / (BN / E), columns (tid % (BN / E)) * E; transposed -> column
     // tid / TPR, k run (tid % TPR) * E
     const int bk = BT ? (tid % TPR) * E : tid / (BN / E);
     const int bj = BT ? tid / TPR : (tid % (BN / E)) * E;
     TS va[E], vb[E];
 
-    // Every load address is clamped into the operand (k to kend - 1, columns to N - 1) and
-    // out-of-range elements are staged as zeros; runs that lie inside and start on 16-byte
-    // aligned rows are read as vectors.
     auto load = [&](int64_t k0) {
         const int64_t ka = k0 + ak;
         if (acol) {
@@ -143,7 +142,7 @@ __global__ __launch_bounds__(256) void ggemm_kernel(const GemmProb* __restrict__
                 const TS v = (TS)arow_ptr[col[u]];
                 va[u] = (a_ok && ka + u < kend) ? v : (TS)0;
             }
-        } else if (avec && ka + E <= kend) {
+        } else if (op.avec && ka + E <= kend) {
             loadv<E>(arow_ptr + ka, va);
             if (!a_ok)
 #pragma unroll
@@ -157,10 +156,11 @@ __global__ __launch_bounds__(256) void ggemm_kernel(const GemmProb* __restrict__
         }
         if constexpr (BT) {
             const int64_t gn = n0 + bj;
-            const bool n_ok = gn < pr.N;
-            const GP<const TB> brow = B + (n_ok ? gn : pr.N - 1) * pr.ldb;
+            const bool n_ok = gn < N;
+            const int64_t bn = n_ok ? gn : N - 1;
+            const GP<const TB> brow = op.B + (int64_t)(bmap ? bmap[bn] : bn) * op.ldb;
             const int64_t kb = k0 + bk;
-            if (bvec && kb + E <= kend) {
+            if (op.bvec && kb + E <= kend) {
                 loadv<E>(brow + kb, vb);
                 if (!n_ok)
 #pragma unroll
@@ -175,9 +175,10 @@ __global__ __launch_bounds__(256) void ggemm_kernel(const GemmProb* __restrict__
         } else {
             const int64_t gk = k0 + bk;
             const bool k_ok = gk < kend;
-            const GP<const TB> brow = B + (k_ok ? gk : kend - 1) * pr.ldb;
+            const int64_t bkk = k_ok ? gk : kend - 1;
+            const GP<const TB> brow = op.B + (int64_t)(bmap ? bmap[bkk] : bkk) * op.ldb;
             const int64_t gn = n0 + bj;
-            if (bvec && gn + E <= pr.N) {
+            if (op.bvec && gn + E <= N) {
                 loadv<E>(brow + gn, vb);
                 if (!k_ok)
 #pragma unroll
@@ -185,48 +186,21 @@ __global__ __launch_bounds__(256) void ggemm_kernel(const GemmProb* __restrict__
             } else {
 #pragma unroll
                 for (int u = 0; u < E; ++u) {
-                    const TS v = (TS)brow[gn + u < pr.N ? gn + u : pr.N - 1];
-                    vb[u] = (k_ok && gn + u < pr.N) ? v : (TS)0;
+                    const TS v = (TS)brow[gn + u < N ? gn + u : N - 1];
+                    vb[u] = (k_ok && gn + u < N) ? v : (TS)0;
                 }
             }
         }
     };
     auto store = [&](int buf) {
 #pragma unroll
-        for (int u = 0; u < E; ++u) As[buf][ak + u][ai] = va[u];
+        for (int u = 0; u < E; ++u) L.A[buf][ak + u][ai] = va[u];
         if constexpr (BT) {
 #pragma unroll
-            for (int u = 0; u < E; ++u) Bs[buf][bk + u][bj] = vb[u];
+            for (int u = 0; u < E; ++u) L.B[buf][bk + u][bj] = vb[u];
         } else {
 #pragma unroll
-            for (int u = 0; u < E; ++u) Bs[buf][bk][bj + u] = vb[u];
-        }
-    };
-
-    acc4 acc[WB][WB];
-#pragma unroll
-    for (int bi = 0; bi < WB; ++bi)
-#pragma unroll
-        for (int bj2 = 0; bj2 < WB; ++bj2) acc[bi][bj2] = acc4{0, 0, 0, 0};
-    double dacc[WB][WB][4];
-    if constexpr (MODE == 1) {
-#pragma unroll
-        for (int bi = 0; bi < WB; ++bi)
-#pragma unroll
-            for (int bj2 = 0; bj2 < WB; ++bj2)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) dacc[bi][bj2][r] = 0.0;
-    }
-    auto flush = [&]() {
-        if constexpr (MODE == 1) {
-#pragma unroll
-            for (int bi = 0; bi < WB; ++bi)
-#pragma unroll
-                for (int bj2 = 0; bj2 < WB; ++bj2) {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) dacc[bi][bj2][r] += (double)acc[bi][bj2][r];
-                    acc[bi][bj2] = acc4{0, 0, 0, 0};
-                }
+            for (int u = 0; u < E; ++u) L.B[buf][bk][bj + u] = vb[u];
         }
     };
 
@@ -239,47 +213,167 @@ __global__ __launch_bounds__(256) void ggemm_kernel(const GemmProb* __restrict__
     for (int it = 0; it < nk; ++it) {
         const int cur = it & 1;
         if (it + 1 < nk) load(kbeg + (int64_t)(it + 1) * GBK);
-        if (MODE == 1 && it > 0 && (it % (kFlushK / GBK)) == 0) flush();
 #pragma unroll
         for (int ks = 0; ks < GBK; ks += 4) {
             TS a[WB], b[WB];
 #pragma unroll
-            for (int bi = 0; bi < WB; ++bi) a[bi] = As[cur][ks + lk][wm + bi * 16 + li];
+            for (int bi = 0; bi < WB; ++bi) a[bi] = L.A[cur][ks + lk][wm + bi * 16 + li];
 #pragma unroll
-            for (int bj2 = 0; bj2 < WB; ++bj2) b[bj2] = Bs[cur][ks + lk][wn + bj2 * 16 + li];
+            for (int bj2 = 0; bj2 < WB; ++bj2) b[bj2] = L.B[cur][ks + lk][wn + bj2 * 16 + li];
 #pragma unroll
             for (int bi = 0; bi < WB; ++bi)
 #pragma unroll
-                for (int bj2 = 0; bj2 < WB; ++bj2) {
-                    if constexpr (MODE == 1)
-                        acc[bi][bj2] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[bi], b[bj2], acc[bi][bj2], 0, 0, 0);
-                    else
-                        acc[bi][bj2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi], b[bj2], acc[bi][bj2], 0, 0, 0);
-                }
+                for (int bj2 = 0; bj2 < WB; ++bj2) mfma_step<TS>(a[bi], b[bj2], acc[bi][bj2]);
         }
         if (it + 1 < nk) store(cur ^ 1);
         __syncthreads();
     }
-    flush();
+}
 
-    // accumulator layouts (wave64): FP64 D[i][j] in lane j + 16 (i % 4), element i / 4;
-    // FP32 D[i][j] in lane j + 16 (i / 4), element i % 4
+// The problem and output tile of workgroup blockIdx.x.  The hardware deals consecutive
+// workgroups out to the 8 XCDs in turn; workgroup w takes logical tile (w % 8) * per + w / 8,
+// so each XCD works through one contiguous range of tiles (tiles that share operands share
+// that XCD's L2).  Returns false for the padding workgroups of the last round.
+template <int WB>
+__device__ inline bool locate(const GemmProb* __restrict__ probs, int nprob, int64_t nwg, GemmProb& pr, int& z,
+                              int64_t& m0, int64_t& n0)
+{
+    const int64_t per = gridDim.x >> 3;   // gridDim.x is a multiple of 8
+    const int64_t w = blockIdx.x;
+    const int64_t logical = (w & 7) * per + (w >> 3);
+    if (logical >= nwg) return false;
+    int lo = 0, hi = nprob - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (probs[mid].wg0 <= logical) lo = mid;
+        else hi = mid - 1;
+    }
+    pr = probs[lo];
+    const int local = (int)(logical - pr.wg0);   // < tm tn ksplit, far below 2^31
+    const int tmn = pr.tm * pr.tn;
+    z = local / tmn;
+    const int rmn = local - z * tmn;
+    const int tn_i = rmn / pr.tm;
+    const int tm_i = rmn - tn_i * pr.tm;
+    m0 = (int64_t)tm_i * 32 * WB;
+    n0 = (int64_t)tn_i * 32 * WB;
+    return true;
+}
+
+// Writes the wave's blocks of acc to C (row crow(i), stride ldc), adding to C with kGemmAccumulate.
+// Accumulator layouts (wave64): FP64 D[i][j] in lane j + 16 (i % 4), element i / 4; FP32
+// D[i][j] in lane j + 16 (i / 4), element i % 4.
+template <typename TC, int MODE, int WB, typename ACC>
+__device__ inline void write_tile(const GemmProb& pr, int z, int64_t m0, int64_t n0, const ACC (&acc)[WB][WB])
+{
+    constexpr int BM = 32 * WB, BN = 32 * WB;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm = (wave >> 1) * (BM / 2), wn = (wave & 1) * (BN / 2);
+    const int li = lane & 15, lk = lane >> 4;
     const GP<TC> C = glbw(static_cast<TC*>(pr.C)) + (int64_t)z * pr.cstride;
+    auto write_out = [&](auto op) {
+#pragma unroll
+        for (int bi = 0; bi < WB; ++bi)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t gm = m0 + wm + bi * 16 + (MODE == 1 ? 4 * lk + r : 4 * r + lk);
+                if (gm >= pr.M) continue;
+                const GP<TC> crow = C + (int64_t)(pr.crow ? glb(pr.crow)[gm] : gm) * pr.ldc;
+#pragma unroll
+                for (int bj2 = 0; bj2 < WB; ++bj2) {
+                    const int64_t gn = n0 + wn + bj2 * 16 + li;
+                    if (gn < pr.N) op(crow + gn, (TC)acc[bi][bj2][r]);
+                }
+            }
+    };
+    if (pr.vec & kGemmAccumulate) write_out([](GP<TC> q, TC v) { *q += v; });
+    else write_out([](GP<TC> q, TC v) { *q = v; });
+}
+
+// WB x WB blocks of 16 x 16 per wave, 2 x 2 waves: BM = BN = 32 WB outputs per workgroup
+template <typename TA, typename TB, typename TC, int MODE, bool BT, int WB>
+__global__ __launch_bounds__(256, 2) void ggemm_kernel(const GemmProb* __restrict__ probs, int nprob, int64_t nwg)
+{
+    typedef typename GTraits<MODE>::TS TS;
+    typedef typename GTraits<MODE>::acc4 acc4;
+    __shared__ Stage<TS, WB> L;
+    GemmProb pr;
+    int z;
+    int64_t m0, n0;
+    if (!locate<WB>(probs, nprob, nwg, pr, z, m0, n0)) return;
+    const int64_t kbeg = (int64_t)z * pr.kchunk;
+    const int64_t kend = kbeg + pr.kchunk < pr.K ? kbeg + pr.kchunk : pr.K;
+    Operands<TA, TB> op{glb(static_cast<const TA*>(pr.A)), pr.arow, pr.acol, pr.lda,
+                        glb(static_cast<const TB*>(pr.B)), pr.bmap, pr.ldb, (pr.vec & 1) != 0, (pr.vec & 2) != 0};
+    acc4 acc[WB][WB];
 #pragma unroll
     for (int bi = 0; bi < WB; ++bi)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int64_t gm = m0 + wm + bi * 16 + (MODE == 1 ? 4 * lk + r : 4 * r + lk);
-            if (gm >= pr.M) continue;
-            const GP<TC> crow = C + (int64_t)(pr.crow ? glb(pr.crow)[gm] : gm) * pr.ldc;
+        for (int bj2 = 0; bj2 < WB; ++bj2) acc[bi][bj2] = acc4{0, 0, 0, 0};
+    mainloop<TS, TA, TB, BT, WB>(L, op, pr.M, pr.N, m0, n0, kbeg, kend, acc);
+    write_tile<TC, MODE, WB>(pr, z, m0, n0, acc);
+}
+
+// Split product (one chunk, B row-major): C = A B over the strong k (FP64 operands, FP64 matrix
+// cores) plus A2 B2 over the weak k (FP32 operands, FP32 matrix cores, K2 <= kFp32MaxK), the
+// FP32 sums added to the FP64 ones through LDS (the two accumulator layouts differ) and C
+// written once.
+template <int WB>
+__global__ __launch_bounds__(256, 2) void gsplit_kernel(const GemmProb* __restrict__ probs, int nprob, int64_t nwg)
+{
+    typedef GTraits<0>::acc4 acc64;
+    typedef GTraits<1>::acc4 acc32;
+    constexpr int BM = 32 * WB, BN = 32 * WB;
+    __shared__ Stage<double, WB> L;
+    GemmProb pr;
+    int z;
+    int64_t m0, n0;
+    if (!locate<WB>(probs, nprob, nwg, pr, z, m0, n0)) return;
+    acc64 acc[WB][WB];
 #pragma unroll
-            for (int bj2 = 0; bj2 < WB; ++bj2) {
-                const int64_t gn = n0 + wn + bj2 * 16 + li;
-                if (gn >= pr.N) continue;
-                if constexpr (MODE == 1) crow[gn] = (TC)dacc[bi][bj2][r];
-                else crow[gn] = (TC)acc[bi][bj2][r];
-            }
-        }
+    for (int bi = 0; bi < WB; ++bi)
+#pragma unroll
+        for (int bj2 = 0; bj2 < WB; ++bj2) acc[bi][bj2] = acc64{0, 0, 0, 0};
+    {
+        Operands<double, double> op{glb(static_cast<const double*>(pr.A)), pr.arow, pr.acol, pr.lda,
+                                    glb(static_cast<const double*>(pr.B)), pr.bmap, pr.ldb, (pr.vec & 1) != 0,
+                                    (pr.vec & 2) != 0};
+        mainloop<double, double, double, false, WB>(L, op, pr.M, pr.N, m0, n0, 0, pr.K, acc);
+    }
+    acc32 acw[WB][WB];
+#pragma unroll
+    for (int bi = 0; bi < WB; ++bi)
+#pragma unroll
+        for (int bj2 = 0; bj2 < WB; ++bj2) acw[bi][bj2] = acc32{0, 0, 0, 0};
+    Stage<float, WB>& Lf = *reinterpret_cast<Stage<float, WB>*>(&L);
+    {
+        Operands<float, float> op{glb(static_cast<const float*>(pr.A2)), pr.arow, nullptr, pr.lda2,
+                                  glb(static_cast<const float*>(pr.B2)), nullptr, pr.ldb2, (pr.vec & 8) != 0,
+                                  (pr.vec & 16) != 0};
+        mainloop<float, float, float, false, WB>(Lf, op, pr.M, pr.N, m0, n0, 0, pr.K2, acw);
+    }
+    // FP32 blocks to LDS in (row, column) order, read back in the FP64 layout
+    static_assert(sizeof(Stage<double, WB>) >= sizeof(float) * BM * (BN + 1), "LDS for the transpose");
+    float* T = reinterpret_cast<float*>(&L);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm = (wave >> 1) * (BM / 2), wn = (wave & 1) * (BN / 2);
+    const int li = lane & 15, lk = lane >> 4;
+#pragma unroll
+    for (int bi = 0; bi < WB; ++bi)
+#pragma unroll
+        for (int bj2 = 0; bj2 < WB; ++bj2)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                T[(wm + bi * 16 + 4 * lk + r) * (BN + 1) + wn + bj2 * 16 + li] = acw[bi][bj2][r];
+    __syncthreads();
+#pragma unroll
+    for (int bi = 0; bi < WB; ++bi)
+#pragma unroll
+        for (int bj2 = 0; bj2 < WB; ++bj2)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                acc[bi][bj2][r] += (double)T[(wm + bi * 16 + 4 * r + lk) * (BN + 1) + wn + bj2 * 16 + li];
+    write_tile<double, 0, WB>(pr, z, m0, n0, acc);
 }
 
 // One workgroup per target row r: for every tile in list order, the tile's local row of r
@@ -321,6 +415,140 @@ __global__ __launch_bounds__(256) void rinv_kernel(const int32_t* __restrict__ l
         rinv[(int64_t)t * nbf + lists[b + i]] = i;
 }
 
+// One workgroup row-chunk per tile (blockIdx.y): out[off + i ld + k] = src[row(i)][col(k)]
+template <typename TI, typename TO>
+__global__ __launch_bounds__(256) void gather_tiles_kernel(const TI* __restrict__ P,
+                                                           const GatherTile* __restrict__ tiles, TO* __restrict__ out)
+{
+    const GatherTile g = tiles[blockIdx.y];
+    for (int i = blockIdx.x; i < g.M; i += gridDim.x) {
+        const TI* src = P + g.src_off + (int64_t)(g.rows ? g.rows[i] : i) * g.src_ld;
+        TO* dst = out + g.out_off + (int64_t)i * g.ld;
+        for (int k = threadIdx.x; k < g.N; k += blockDim.x) dst[k] = (TO)src[g.cols ? g.cols[k] : k];
+    }
+}
+
+// One workgroup per tile: stable partition of the tile's rows into mx >= tau, then the rest
+__global__ __launch_bounds__(256) void partition_kernel(const double* __restrict__ mx, const int32_t* __restrict__ fn,
+                                                        const int32_t* __restrict__ roff, double tau,
+                                                        int32_t* __restrict__ perm, int32_t* __restrict__ cperm,
+                                                        int32_t* __restrict__ nstrong)
+{
+    __shared__ int32_t scan[256];
+    __shared__ int32_t base[2];
+    const int t = blockIdx.x, tid = threadIdx.x;
+    const int r0 = roff[t], n = roff[t + 1] - r0;
+    // pass 1: strong rows
+    int cnt = 0;
+    for (int r = tid; r < n; r += 256) cnt += mx[r0 + r] >= tau ? 1 : 0;
+    scan[tid] = cnt;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (tid < st) scan[tid] += scan[tid + st];
+        __syncthreads();
+    }
+    const int ns = scan[0];
+    __syncthreads();
+    if (tid == 0) {
+        base[0] = 0;
+        base[1] = ns;
+        // at most kFp32MaxK weak rows (FP32 sums of bounded length): the first of the others
+        // join the strong ones
+        nstrong[t] = ns > n - kFp32MaxK ? ns : n - kFp32MaxK;
+    }
+    __syncthreads();
+    // pass 2: chunks of 256 rows in order, exclusive scan of the strong flags within a chunk
+    for (int c0 = 0; c0 < n; c0 += 256) {
+        const int r = c0 + tid;
+        const int f = (r < n && mx[r0 + r] >= tau) ? 1 : 0;
+        scan[tid] = f;
+        __syncthreads();
+        for (int off = 1; off < 256; off <<= 1) {
+            const int v = tid >= off ? scan[tid - off] : 0;
+            __syncthreads();
+            scan[tid] += v;
+            __syncthreads();
+        }
+        const int incl = scan[tid];
+        const int strong_before = incl - f;
+        const int chunk_n = (n - c0) < 256 ? (n - c0) : 256;
+        if (r < n) {
+            const int pos = f ? base[0] + strong_before : base[1] + (tid - strong_before);
+            perm[r0 + pos] = r;
+            cperm[r0 + pos] = fn[r0 + r];
+        }
+        const int total_strong = scan[chunk_n - 1];
+        __syncthreads();
+        if (tid == 0) {
+            base[0] += total_strong;
+            base[1] += chunk_n - total_strong;
+        }
+        __syncthreads();
+    }
+}
+
+constexpr int kBoundChunks = kBoundChunksPerTile;
+
+// blockIdx.y = tile, blockIdx.x = chunk: waves take the tile's rows idx = chunk * 4 + wave
+// (mod kBoundChunks * 4); out[tile * kBoundChunks + chunk] = sum over those rows of g_r p_r
+__global__ __launch_bounds__(256) void lowprec_bound_kernel(const double* __restrict__ G, int64_t ld,
+                                                            const double* __restrict__ P, int64_t nbf,
+                                                            const BoundTile* __restrict__ tiles,
+                                                            const int32_t* __restrict__ rows,
+                                                            const int32_t* __restrict__ counts,
+                                                            const int32_t* __restrict__ cperm,
+                                                            double* __restrict__ out)
+{
+    __shared__ double part[4];
+    const int t = blockIdx.y, chunk = blockIdx.x;
+    const BoundTile bt = tiles[t];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int n = counts[t];
+    double acc = 0.0;
+    for (int idx = chunk * 4 + wave; idx < n; idx += kBoundChunks * 4) {
+        const int r = rows[(int64_t)t * nbf + idx];
+        const double* grow = G + (int64_t)r * ld + bt.col0;
+        double g = 0.0;
+        for (int i = lane; i < bt.ncols; i += 64) g += fabs(grow[i]);
+        const double* prow = P + (int64_t)r * nbf;
+        double p = 0.0;
+        for (int k = bt.nstrong + lane; k < bt.nB; k += 64) p += fabs(prow[cperm[bt.roff + k]]);
+        for (int o = 32; o > 0; o >>= 1) {
+            g += __shfl_xor(g, o);
+            p += __shfl_xor(p, o);
+        }
+        acc += g * p;
+    }
+    if (lane == 0) part[wave] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) out[(int64_t)t * kBoundChunks + chunk] = ((part[0] + part[1]) + part[2]) + part[3];
+}
+
+// acc[0] += sum of part[0 .. n) in a fixed order
+__global__ __launch_bounds__(256) void bound_sum_kernel(const double* __restrict__ part, int64_t n,
+                                                        double* __restrict__ acc)
+{
+    __shared__ double sh[256];
+    double v = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) v += part[i];
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) acc[0] += sh[0];
+}
+
+template <int WB>
+hipError_t launch_gsplit_wb(const GemmProb* probs, int nprob, int64_t nwg, hipStream_t s)
+{
+    const int64_t grid = ((nwg + 7) / 8) * 8;
+    if (grid > INT32_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((gsplit_kernel<WB>), dim3((unsigned)grid), dim3(256), 0, s, probs, nprob, nwg);
+    return hipGetLastError();
+}
+
 template <typename TA, typename TB, typename TC, int MODE, int WB>
 hipError_t launch_ggemm_wb(const GemmProb* probs, int nprob, int64_t nwg, bool bt, hipStream_t s)
 {
@@ -348,21 +576,16 @@ hipError_t launch_ggemm_t(const GemmProb* probs, int nprob, int64_t nwg, int til
 
 int ggemm_tile(const GemmProb* probs, int nprob)
 {
-    // Measured on gfx950: with k per workgroup of a few hundred the 64 x 64 tiles are faster
-    // (four times the workgroups in flight hide the short loops' prologue and stores); with long
-    // k the 128 x 128 tiles run about 1.9 times as many matrix-core flops per second, so the
-    // small tiles pay only where they save that much padding.
-    double w64 = 0.0, w128 = 0.0, kw = 0.0, ksum = 0.0;
+    // Measured on gfx950 (two workgroups per compute unit for the 128 x 128 tiles, four for
+    // 64 x 64): the large tiles run the products of the build 1.1 to 1.9 times as fast per
+    // padded flop (fewer operand bytes per flop), so the small tiles are taken only where
+    // they save at least that much padding.
+    double w64 = 0.0, w128 = 0.0;
     for (int i = 0; i < nprob; ++i) {
         const double k = (double)probs[i].K;
-        const double ks = (double)(probs[i].ksplit > 0 ? probs[i].ksplit : 1);
         w64 += (double)((probs[i].M + 63) / 64 * 64) * (double)((probs[i].N + 63) / 64 * 64) * k;
         w128 += (double)((probs[i].M + 127) / 128 * 128) * (double)((probs[i].N + 127) / 128 * 128) * k;
-        kw += k / ks * k;
-        ksum += k;
     }
-    const double kchunk = ksum > 0.0 ? kw / ksum : 0.0;   // work-weighted k per workgroup
-    if (kchunk <= 512.0) return 64;
     return 1.9 * w64 < w128 ? 64 : 128;
 }
 
@@ -373,7 +596,8 @@ void ggemm_plan(GemmProb& p, int tile, int asize, int bsize)
     const auto al = [](const void* q, int64_t ld, int sz) {
         return ((uintptr_t)q % 16 == 0) && ((ld * sz) % 16 == 0);
     };
-    p.vec = (al(p.A, p.lda, asize) ? 1 : 0) | (al(p.B, p.ldb, bsize) ? 2 : 0);
+    p.vec = (p.vec & kGemmAccumulate) | (al(p.A, p.lda, asize) ? 1 : 0) | (al(p.B, p.ldb, bsize) ? 2 : 0) |
+            (p.A2 && al(p.A2, p.lda2, 4) ? 8 : 0) | (p.B2 && al(p.B2, p.ldb2, 4) ? 16 : 0);
     p.tm = (int32_t)((p.M + tile - 1) / tile);
     p.tn = (int32_t)((p.N + tile - 1) / tile);
     if (p.ksplit < 1) p.ksplit = 1;
@@ -397,6 +621,66 @@ hipError_t launch_ggemm_f32(const GemmProb* probs, int nprob, int64_t nwg, int t
 hipError_t launch_ggemm_f32_dA(const GemmProb* probs, int nprob, int64_t nwg, int tile, bool bt, hipStream_t s)
 {
     return launch_ggemm_t<double, float, double, 1>(probs, nprob, nwg, tile, bt, s);
+}
+
+hipError_t launch_gsplit(const GemmProb* probs, int nprob, int64_t nwg, int tile, hipStream_t s)
+{
+    if (nprob <= 0 || nwg <= 0) return hipSuccess;
+    if (tile != 64 && tile != 128) return hipErrorInvalidValue;
+    return tile == 64 ? launch_gsplit_wb<2>(probs, nprob, nwg, s) : launch_gsplit_wb<4>(probs, nprob, nwg, s);
+}
+
+hipError_t launch_ggemm_f32_dd(const GemmProb* probs, int nprob, int64_t nwg, int tile, bool bt, hipStream_t s)
+{
+    return launch_ggemm_t<double, double, double, 1>(probs, nprob, nwg, tile, bt, s);
+}
+
+template <typename TI, typename TO>
+hipError_t launch_gather_tiles_t(const TI* src, const GatherTile* tiles, int ntile, int32_t max_rows, TO* out,
+                                 hipStream_t s)
+{
+    if (ntile <= 0 || max_rows <= 0) return hipSuccess;
+    const unsigned gx = (unsigned)(max_rows < 1024 ? max_rows : 1024);
+    hipLaunchKernelGGL((gather_tiles_kernel<TI, TO>), dim3(gx, (unsigned)ntile), dim3(256), 0, s, src, tiles, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_tiles(const double* src, const GatherTile* tiles, int ntile, int32_t max_rows, double* out,
+                               hipStream_t s)
+{
+    return launch_gather_tiles_t<double, double>(src, tiles, ntile, max_rows, out, s);
+}
+
+hipError_t launch_gather_tiles(const float* src, const GatherTile* tiles, int ntile, int32_t max_rows, float* out,
+                               hipStream_t s)
+{
+    return launch_gather_tiles_t<float, float>(src, tiles, ntile, max_rows, out, s);
+}
+
+hipError_t launch_gather_tiles(const double* src, const GatherTile* tiles, int ntile, int32_t max_rows, float* out,
+                               hipStream_t s)
+{
+    return launch_gather_tiles_t<double, float>(src, tiles, ntile, max_rows, out, s);
+}
+
+hipError_t launch_partition(const double* mx, const int32_t* fn, const int32_t* roff, int ntile, double tau,
+                            int32_t* perm, int32_t* cperm, int32_t* nstrong, hipStream_t s)
+{
+    if (ntile <= 0) return hipSuccess;
+    hipLaunchKernelGGL(partition_kernel, dim3((unsigned)ntile), dim3(256), 0, s, mx, fn, roff, tau, perm, cperm,
+                       nstrong);
+    return hipGetLastError();
+}
+
+hipError_t launch_lowprec_bound(const double* G, int64_t ld, const double* P, int64_t nbf, const BoundTile* tiles,
+                                int ntile, const int32_t* rows, const int32_t* counts, const int32_t* cperm,
+                                double* partials, double* acc, hipStream_t s)
+{
+    if (ntile <= 0) return hipSuccess;
+    hipLaunchKernelGGL(lowprec_bound_kernel, dim3(kBoundChunks, (unsigned)ntile), dim3(256), 0, s, G, ld, P, nbf,
+                       tiles, rows, counts, cperm, partials);
+    hipLaunchKernelGGL(bound_sum_kernel, dim3(1), dim3(256), 0, s, partials, (int64_t)ntile * kBoundChunks, acc);
+    return hipGetLastError();
 }
 
 hipError_t launch_group_reduce(const double* part, const RedTile* tiles, int ntile, double* T, int64_t ldt,

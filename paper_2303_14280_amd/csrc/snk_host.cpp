@@ -3,6 +3,7 @@
 // budget), the per-density build loop of Alg. 1 on one GPU, and the C ABI of snk.h.
 #include "snk.h"
 #include "snk_internal.h"
+#include "snk_testing.h"
 
 
 #include <algorithm>
@@ -146,6 +147,25 @@ struct snk_ctx {
     int nsplit = 1;                     // K GEMM split over points for full-width tiles
     int64_t part_elems = 0;             // capacity of the split partial-product buffer
     bool mixed = false;                 // SNK_MIXED + SNK_FP32_GEMM: FP32 Phi, P and F; FP32 matrix-core GEMMs
+    // SNK_MIXED with a density screen and basis screening: per tile, the functions whose largest
+    // |Phi| on the tile is below kWeakPhi enter both products through the FP32 matrix cores
+    bool split = false;
+    int32_t* d_perm = nullptr;          // [max_group_rows] Phi rows of each tile, strong then weak
+    int32_t* d_cperm = nullptr;         // [max_group_rows] their functions
+    int32_t* d_nstrong = nullptr;       // [max_group_tiles]
+    std::vector<int32_t> tile_nstrong;  // strong rows per tile of the current group
+    double* d_lpb = nullptr;            // [max_group_tiles * kBoundChunksPerTile + 1] bound partials, then the sum
+    double acc_flops64 = 0, acc_flops32 = 0;   // dense-product flops per precision of a build
+    const double* d_P_cur = nullptr;    // density of the build in progress (device)
+    // P[L_t, B_t] of every tile of a group, gathered once per build (grown on demand)
+    void* d_Pc = nullptr;
+    size_t pc_bytes = 0;
+    // split build: the weak columns of P[L_t, B_t] and the weak rows of Phi_t in FP32
+    void* d_Pw = nullptr;
+    size_t pw_bytes = 0;
+    void* d_Phw = nullptr;
+    size_t phw_bytes = 0;
+    std::vector<int64_t> tile_phw_off;  // per tile of the current group: first element of its rows in d_Phw
     float *d_Phi32 = nullptr, *d_F32 = nullptr, *d_P32 = nullptr;
     double *d_Phi = nullptr, *d_F = nullptr, *d_G = nullptr, *d_part = nullptr;
     double *d_Kt = nullptr, *d_P = nullptr, *d_K = nullptr, *d_partial = nullptr, *d_ex = nullptr;
@@ -153,6 +173,13 @@ struct snk_ctx {
     int nfinish = 256;
 
     hipEvent_t ev[16] = {};
+    // timed builds: HIP events around the grouped product launches of the current group
+    // (0: F FP64, 1: F FP32, 2: K FP64, 3: K FP32), each kind's time and launches per build
+    bool timing = false;
+    hipEvent_t gev[8] = {};
+    bool gl[4] = {false, false, false, false};
+    double gms[4] = {0, 0, 0, 0};
+    int64_t gcount[4] = {0, 0, 0, 0};
 
     // screening (rigorous bound): static diagonal-pair lists per l, per-group work buffers
     int32_t* d_diag_sh[3] = {nullptr, nullptr, nullptr};
@@ -966,6 +993,13 @@ void free_ctx(snk_ctx* c)
     (void)hipFree(c->d_tcount);
     (void)hipFree(c->d_rinv);
     (void)hipFree(c->d_arena);
+    (void)hipFree(c->d_perm);
+    (void)hipFree(c->d_cperm);
+    (void)hipFree(c->d_nstrong);
+    (void)hipFree(c->d_lpb);
+    (void)hipFree(c->d_Pc);
+    (void)hipFree(c->d_Pw);
+    (void)hipFree(c->d_Phw);
     for (int k = 0; k < 2; ++k) {
         if (c->pstream[k]) (void)hipStreamDestroy(c->pstream[k]);
         if (c->pev_k[k]) (void)hipEventDestroy(c->pev_k[k]);
@@ -1004,6 +1038,8 @@ void free_ctx(snk_ctx* c)
     (void)hipFree(c->d_ex);
     (void)hipFree(c->d_boys);
     for (auto& e : c->ev)
+        if (e) (void)hipEventDestroy(e);
+    for (auto& e : c->gev)
         if (e) (void)hipEventDestroy(e);
     for (int l = 0; l < 3; ++l) {
         (void)hipFree(c->d_diag_sh[l]);
@@ -1159,6 +1195,7 @@ int snk_ctx_create(const snk_basis* basis, const snk_grid* grid, const double* w
         c->own_stream = true;
     }
     for (auto& e : c->ev) CREATE_CHECK(hipEventCreate(&e) == hipSuccess ? SNK_OK : SNK_E_DEVICE);
+    for (auto& e : c->gev) CREATE_CHECK(hipEventCreate(&e) == hipSuccess ? SNK_OK : SNK_E_DEVICE);
 
     // basis
     c->nshell = basis->nshell;
@@ -1193,7 +1230,12 @@ int snk_ctx_create(const snk_basis* basis, const snk_grid* grid, const double* w
     CREATE_CHECK(upload(c, &c->d_pairs, c->pairs));
     CREATE_CHECK(upload(c, &c->d_prims, c->prims));
     // the mixed build evaluates the screen's small blocks in FP32
-    c->nlist = (o.precision == SNK_MIXED && o.screen != SNK_SCREEN_NONE) ? 12 : 6;
+    // FP32 A.F lists in the mixed build with a density screen, except where the dense products
+    // split by function magnitude (basis screening as well): there the screens skip nearly all
+    // the blocks the FP32 lists would take, and the extra lists cost more than they save
+    const bool split_products = o.precision == SNK_MIXED && !(o.flags & SNK_FP32_GEMM) &&
+                                o.screen != SNK_SCREEN_NONE && o.eps_basis > 0.0;
+    c->nlist = (o.precision == SNK_MIXED && o.screen != SNK_SCREEN_NONE && !split_products) ? 12 : 6;
     // FP32 records: the mixed build's FP32 blocks and the screen's diagonal bounds
     if (c->nlist == 12 || o.screen != SNK_SCREEN_NONE) CREATE_CHECK(ensure_prims32(c));
     CREATE_CHECK(build_pair_feats(c));
@@ -1209,7 +1251,7 @@ int snk_ctx_create(const snk_basis* basis, const snk_grid* grid, const double* w
     // workspace
     const int64_t nbf = c->nbf;
     {
-        const int64_t tiles = ((nbf + 63) / 64) * ((c->max_nB + 63) / 64);
+        const int64_t tiles = ((nbf + 127) / 128) * ((c->max_nB + 127) / 128);
         int ns = (int)std::max<int64_t>(1, (kGemmTarget + tiles - 1) / std::max<int64_t>(1, tiles));
         ns = (int)std::min<int64_t>(ns, std::max<int64_t>(1, c->max_tile_cols / kBatch));
         c->nsplit = std::max(1, std::min(ns, 256));
@@ -1264,6 +1306,13 @@ int snk_ctx_create(const snk_basis* basis, const snk_grid* grid, const double* w
     }
     if (c->row_restrict || c->frow_restrict)
         CREATE_CHECK(dalloc(c, &c->d_rinv, (size_t)std::max<int32_t>(1, c->max_group_tiles) * nbf));
+    c->split = o.precision == SNK_MIXED && !c->mixed && c->row_restrict && c->frow_restrict;
+    if (c->split) {
+        CREATE_CHECK(dalloc(c, &c->d_perm, (size_t)std::max<int32_t>(1, c->max_group_rows)));
+        CREATE_CHECK(dalloc(c, &c->d_cperm, (size_t)std::max<int32_t>(1, c->max_group_rows)));
+        CREATE_CHECK(dalloc(c, &c->d_nstrong, (size_t)std::max<int32_t>(1, c->max_group_tiles)));
+        CREATE_CHECK(dalloc(c, &c->d_lpb, (size_t)std::max<int32_t>(1, c->max_group_tiles) * kBoundChunksPerTile + 1));
+    }
     if (c->pipe) {
         c->p_Phi[0] = c->d_Phi;
         c->p_F[0] = c->d_F;
@@ -1345,6 +1394,13 @@ int group_F(snk_ctx* c, const Group& g, const double* dP, bool timed)
             HIPCHECK(c, launch_row_absmax(c->d_Phi, nfull, ncols_full, g.phi_rows, last.ncols, c->d_mx, s));
         HIPCHECK(c, launch_ftilde_flag(dP, nbf, g.d_fn_cat, g.d_roff, ntile, c->d_mx, c->opts.eps_basis, c->d_fn_shell,
                                        c->nshell, c->d_fflag, s));
+        if (c->split) {
+            HIPCHECK(c, launch_partition(c->d_mx, g.d_fn_cat, g.d_roff, ntile, kWeakPhi, c->d_perm, c->d_cperm,
+                                         c->d_nstrong, s));
+            c->tile_nstrong.assign(ntile, 0);
+            HIPCHECK(c, hipMemcpyAsync(c->tile_nstrong.data(), c->d_nstrong, ntile * sizeof(int32_t),
+                                       hipMemcpyDeviceToHost, s));
+        }
         HIPCHECK(c, launch_tile_rows(c->d_fflag, ntile, c->nshell, c->d_shell_l, c->d_shell_row, c->nbf, c->d_frows,
                                      c->d_fcount, s));
         c->tile_frows.assign(ntile, 0);
@@ -1396,15 +1452,16 @@ int push_vector(snk_ctx* c, std::vector<T>& v, const T** dptr)
     return rc;
 }
 
-enum GemmKind { kGemmF64 = 0, kGemmF32 = 1, kGemmF32dA = 2 };
+enum GemmKind { kGemmF64 = 0, kGemmF32 = 1, kGemmF32dA = 2, kGemmF32dd = 3, kGemmSplit = 4 };
 
-// One grouped launch of the products in probs (all read B the same way), on the context's stream.
-int run_gemms(snk_ctx* c, std::vector<GemmProb>& probs, GemmKind kind, bool bt)
+int launch_gemm_list(snk_ctx* c, std::vector<GemmProb>& probs, GemmKind kind, bool bt)
 {
     if (probs.empty()) return SNK_OK;
     int64_t nwg = 0;
-    const int asz = kind == kGemmF32 ? 4 : 8, bsz = kind == kGemmF64 ? 8 : 4;
-    const int tile = ggemm_tile(probs.data(), (int)probs.size());
+    const int asz = kind == kGemmF32 ? 4 : 8, bsz = (kind == kGemmF64 || kind == kGemmF32dd || kind == kGemmSplit) ? 8 : 4;
+    // split products run on 64 x 64 tiles (the 128 x 128 form holds both accumulator sets only
+    // with spills)
+    const int tile = kind == kGemmSplit ? 64 : ggemm_tile(probs.data(), (int)probs.size());
     for (auto& p : probs) {
         ggemm_plan(p, tile, asz, bsz);
         p.wg0 = nwg;
@@ -1414,10 +1471,52 @@ int run_gemms(snk_ctx* c, std::vector<GemmProb>& probs, GemmKind kind, bool bt)
     int rc = push_vector(c, probs, &d);
     if (rc) return rc;
     const int n = (int)probs.size();
-    hipError_t e = kind == kGemmF64 ? launch_ggemm_f64(d, n, nwg, tile, bt, c->stream)
-                   : kind == kGemmF32 ? launch_ggemm_f32(d, n, nwg, tile, bt, c->stream)
-                                      : launch_ggemm_f32_dA(d, n, nwg, tile, bt, c->stream);
+    hipError_t e = kind == kGemmF64    ? launch_ggemm_f64(d, n, nwg, tile, bt, c->stream)
+                   : kind == kGemmF32  ? launch_ggemm_f32(d, n, nwg, tile, bt, c->stream)
+                   : kind == kGemmF32dA ? launch_ggemm_f32_dA(d, n, nwg, tile, bt, c->stream)
+                   : kind == kGemmF32dd ? launch_ggemm_f32_dd(d, n, nwg, tile, bt, c->stream)
+                                        : launch_gsplit(d, n, nwg, tile, c->stream);
     HIPCHECK(c, e);
+    return SNK_OK;
+}
+
+// The products in probs (all read B the same way) in grouped launches on the context's stream.
+// FP32 kinds keep every FP32 sum within kFp32MaxK terms: split products must already have
+// chunks that short; a product written in one piece longer than that is cut into k slices, one
+// launch per slice, the later slices added into C.
+int run_gemms(snk_ctx* c, std::vector<GemmProb>& probs, GemmKind kind, bool bt)
+{
+    if (kind == kGemmF64 || kind == kGemmSplit) return launch_gemm_list(c, probs, kind, bt);
+    const int asz = kind == kGemmF32 ? 4 : 8, bsz = (kind == kGemmF64 || kind == kGemmF32dd) ? 8 : 4;
+    std::vector<std::vector<GemmProb>> slices(1);
+    for (const GemmProb& p : probs) {
+        if (p.ksplit > 1) {
+            if ((p.K + p.ksplit - 1) / p.ksplit > kFp32MaxK) {
+                set_err(c, "internal: FP32 product chunk longer than the FP32 sum limit");
+                return SNK_E_DEVICE;
+            }
+            slices[0].push_back(p);
+            continue;
+        }
+        for (int64_t k0 = 0, sl = 0; k0 < std::max<int64_t>(1, p.K); k0 += kFp32MaxK, ++sl) {
+            GemmProb q = p;
+            q.K = (int32_t)std::min<int64_t>(kFp32MaxK, p.K - k0);
+            if (k0 > 0) {
+                if (q.acol) q.acol += k0;
+                else q.A = (const char*)p.A + k0 * asz;
+                if (bt) q.B = (const char*)p.B + k0 * bsz;
+                else if (q.bmap) q.bmap += k0;
+                else q.B = (const char*)p.B + k0 * p.ldb * bsz;
+                q.vec |= kGemmAccumulate;
+            }
+            if ((size_t)sl >= slices.size()) slices.resize(sl + 1);
+            slices[sl].push_back(q);
+        }
+    }
+    for (auto& sl : slices) {
+        int rc = launch_gemm_list(c, sl, kind, bt);
+        if (rc) return rc;
+    }
     return SNK_OK;
 }
 
@@ -1462,20 +1561,62 @@ int choose_ksplit(int64_t otiles, int64_t batches)
     return (int)std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(ks, 256), std::max<int64_t>(1, batches)));
 }
 
-int64_t out_tiles(int64_t M, int64_t N) { return ((M + 63) / 64) * ((N + 63) / 64); }
+int64_t out_tiles(int64_t M, int64_t N) { return ((M + 127) / 128) * ((N + 127) / 128); }
 
-// Eq. fmat for group g: one grouped launch over its tiles, F[L_t, tile columns] = P[L_t, B_t] Phi_t
-// with the rows L_t and columns B_t of P read in place and the rows written straight into F.
+// Grows a device buffer to at least n bytes (the stream is drained before a smaller buffer is
+// replaced).
+int ensure_bytes(snk_ctx* c, void** p, size_t* cap, size_t n)
+{
+    if (n <= *cap && *p) return SNK_OK;
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    (void)hipFree(*p);
+    *p = nullptr;
+    const size_t sz = std::max<size_t>(n, *cap + *cap / 2);
+    hipError_t e = hipMalloc(p, std::max<size_t>(sz, 256));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        *cap = 0;
+        set_err(c, std::string("hipMalloc: ") + hipGetErrorString(e));
+        return e == hipErrorOutOfMemory ? SNK_E_NOMEM : SNK_E_DEVICE;
+    }
+    *cap = std::max<size_t>(sz, 256);
+    return SNK_OK;
+}
+
+// run_gemms between the timing events of product kind `slot` (timed builds)
+int timed_gemms(snk_ctx* c, int slot, std::vector<GemmProb>& probs, GemmKind kind, bool bt)
+{
+    if (probs.empty()) return SNK_OK;
+    if (c->timing) HIPCHECK(c, hipEventRecord(c->gev[2 * slot], c->stream));
+    int rc = run_gemms(c, probs, kind, bt);
+    if (rc) return rc;
+    if (c->timing) {
+        HIPCHECK(c, hipEventRecord(c->gev[2 * slot + 1], c->stream));
+        c->gl[slot] = true;
+    }
+    return SNK_OK;
+}
+
+// Eq. fmat for group g: F[L_t, tile columns] = P[L_t, B_t] Phi_t for every tile, with the rows
+// written straight into F.  Where a tile does not take every row and column of P, P[L_t, B_t]
+// is gathered first for all tiles in one launch.  One grouped launch computes every tile's
+// product.  Split build: the strong functions' columns of P are gathered in FP64, the weak
+// ones in FP32 together with the weak rows of Phi_t, and each tile's product is FP64 over the
+// strong functions plus FP32 matrix cores over the weak ones, written once.
 int group_fgemm(snk_ctx* c, const Group& g, const double* dP)
 {
     const int64_t nbf = c->nbf;
     const int64_t ld = g.ncols;
+    const size_t esz = c->mixed ? sizeof(float) : sizeof(double);
     // rows outside L_t are zero; they are written only where a reader takes every row (no
     // density screen, training data, debugging): the screens give those shells U = 0 without
     // reading them and never list their blocks
     const bool zero_rows = c->opts.screen == SNK_SCREEN_NONE || c->zero_f_rows;
     bool need_zero = false;
-    std::vector<GemmProb> probs;
+    std::vector<GatherTile> gt, gw, gphi;
+    std::vector<int64_t> pc_off(g.tiles.size(), -1), pw_off(g.tiles.size(), -1), phw_off(g.tiles.size(), -1);
+    int64_t pc_elems = 0, pw_elems = 0, phw_elems = 0;
+    int32_t max_rows = 0, max_wrows = 0;
     for (size_t ti = 0; ti < g.tiles.size(); ++ti) {
         const Tile& t = g.tiles[ti];
         const int64_t L = c->frow_restrict ? c->tile_frows[ti] : nbf;
@@ -1484,27 +1625,108 @@ int group_fgemm(snk_ctx* c, const Group& g, const double* dP)
         c->acc_cols += (double)t.ncols;
         if (t.nB == 0 || L == 0 || L < nbf) need_zero |= zero_rows;
         if (t.nB == 0 || L == 0) continue;
-        GemmProb p{};
-        p.A = c->mixed ? (const void*)c->d_P32 : (const void*)dP;
-        p.lda = nbf;
-        p.arow = L < nbf ? c->d_frows + (int64_t)ti * nbf : nullptr;
-        p.acol = t.all_functions ? nullptr : t.d_coll_fn;
-        p.B = c->mixed ? (const void*)(c->d_Phi32 + t.phi_off) : (const void*)(c->d_Phi + t.phi_off);
-        p.ldb = t.ncols;
-        p.C = c->mixed ? (void*)(c->d_F32 + t.col0) : (void*)(c->d_F + t.col0);
-        p.crow = p.arow;
-        p.ldc = ld;
-        p.M = (int32_t)L;
-        p.N = (int32_t)t.ncols;
-        p.K = t.nB;
-        p.ksplit = 1;
-        probs.push_back(p);
+        if (L < nbf || !t.all_functions || c->split) {
+            const int32_t ns = c->split ? c->tile_nstrong[ti] : t.nB;
+            GatherTile q{};
+            q.src_ld = nbf;
+            q.rows = L < nbf ? c->d_frows + (int64_t)ti * nbf : nullptr;
+            q.cols = c->split ? c->d_cperm + t.row_off : (t.all_functions ? nullptr : t.d_coll_fn);
+            q.M = (int32_t)L;
+            q.N = ns;
+            q.ld = (ns + 3) & ~3;   // 16-byte aligned rows for the vector loads of the product
+            q.out_off = pc_elems;
+            pc_off[ti] = pc_elems;
+            pc_elems += L * q.ld;
+            max_rows = std::max<int32_t>(max_rows, (int32_t)L);
+            if (ns > 0) gt.push_back(q);
+            if (ns < t.nB) {
+                // the weak columns of P and the weak rows of Phi_t, rounded to FP32
+                GatherTile w = q;
+                w.cols = q.cols + ns;
+                w.N = t.nB - ns;
+                w.ld = (w.N + 3) & ~3;
+                w.out_off = pw_elems;
+                pw_off[ti] = pw_elems;
+                pw_elems += L * w.ld;
+                gw.push_back(w);
+                GatherTile f{};
+                f.src_off = t.phi_off;
+                f.src_ld = t.ncols;
+                f.rows = c->d_perm + t.row_off + ns;
+                f.M = t.nB - ns;
+                f.N = (int32_t)t.ncols;
+                f.ld = (int32_t)t.ncols;
+                f.out_off = phw_elems;
+                phw_off[ti] = phw_elems;
+                phw_elems += (int64_t)f.M * t.ncols;
+                max_wrows = std::max<int32_t>(max_wrows, f.M);
+                gphi.push_back(f);
+            }
+        }
     }
     if (need_zero) {
         if (c->mixed) HIPCHECK(c, launch_fill(c->d_F32, nbf * ld, 0.0f, c->stream));
         else HIPCHECK(c, launch_fill(c->d_F, nbf * ld, 0.0, c->stream));
     }
-    return run_gemms(c, probs, c->mixed ? kGemmF32 : kGemmF64, false);
+    c->tile_phw_off = phw_off;
+    int rc = SNK_OK;
+    if (!gt.empty()) {
+        if ((rc = ensure_bytes(c, &c->d_Pc, &c->pc_bytes, (size_t)pc_elems * esz))) return rc;
+        const GatherTile* d = nullptr;
+        if ((rc = push_vector(c, gt, &d))) return rc;
+        if (c->mixed)
+            HIPCHECK(c, launch_gather_tiles(c->d_P32, d, (int)gt.size(), max_rows, (float*)c->d_Pc, c->stream));
+        else
+            HIPCHECK(c, launch_gather_tiles(dP, d, (int)gt.size(), max_rows, (double*)c->d_Pc, c->stream));
+    }
+    if (!gw.empty()) {
+        if ((rc = ensure_bytes(c, &c->d_Pw, &c->pw_bytes, (size_t)pw_elems * sizeof(float)))) return rc;
+        if ((rc = ensure_bytes(c, &c->d_Phw, &c->phw_bytes, (size_t)phw_elems * sizeof(float)))) return rc;
+        const GatherTile* d = nullptr;
+        if ((rc = push_vector(c, gw, &d))) return rc;
+        HIPCHECK(c, launch_gather_tiles(dP, d, (int)gw.size(), max_rows, (float*)c->d_Pw, c->stream));
+        if ((rc = push_vector(c, gphi, &d))) return rc;
+        HIPCHECK(c, launch_gather_tiles(c->d_Phi, d, (int)gphi.size(), max_wrows, (float*)c->d_Phw, c->stream));
+    }
+    std::vector<GemmProb> probs, split;
+    for (size_t ti = 0; ti < g.tiles.size(); ++ti) {
+        const Tile& t = g.tiles[ti];
+        const int64_t L = c->frow_restrict ? c->tile_frows[ti] : nbf;
+        if (t.nB == 0 || L == 0) continue;
+        const int32_t ns = c->split ? c->tile_nstrong[ti] : t.nB;
+        GemmProb p{};
+        if (pc_off[ti] >= 0) {
+            p.A = (const char*)c->d_Pc + pc_off[ti] * esz;
+            p.lda = (ns + 3) & ~3;
+        } else {
+            p.A = c->mixed ? (const void*)c->d_P32 : (const void*)dP;
+            p.lda = nbf;
+        }
+        p.B = c->mixed ? (const void*)(c->d_Phi32 + t.phi_off) : (const void*)(c->d_Phi + t.phi_off);
+        p.bmap = c->split ? c->d_perm + t.row_off : nullptr;
+        p.ldb = t.ncols;
+        p.C = c->mixed ? (void*)(c->d_F32 + t.col0) : (void*)(c->d_F + t.col0);
+        p.crow = L < nbf ? c->d_frows + (int64_t)ti * nbf : nullptr;
+        p.ldc = ld;
+        p.M = (int32_t)L;
+        p.N = (int32_t)t.ncols;
+        p.K = ns;
+        p.ksplit = 1;
+        c->acc_flops64 += 2.0 * (double)L * (double)t.ncols * (double)ns;
+        if (ns < t.nB) {
+            p.A2 = (const char*)c->d_Pw + pw_off[ti] * sizeof(float);
+            p.lda2 = (t.nB - ns + 3) & ~3;
+            p.B2 = (const char*)c->d_Phw + phw_off[ti] * sizeof(float);
+            p.ldb2 = t.ncols;
+            p.K2 = t.nB - ns;
+            c->acc_flops32 += 2.0 * (double)L * (double)t.ncols * (double)(t.nB - ns);
+            split.push_back(p);
+        } else {
+            probs.push_back(p);
+        }
+    }
+    if ((rc = timed_gemms(c, c->mixed ? 1 : 0, probs, c->mixed ? kGemmF32 : kGemmF64, false))) return rc;
+    return timed_gemms(c, 1, split, kGemmSplit, false);
 }
 
 // Eq. usym_k for group g: Kt[M_t, B_t] += G[M_t, tile columns] Phi_t^T for every tile in one
@@ -1534,45 +1756,79 @@ int group_K(snk_ctx* c, const Group& g)
         const int64_t M = restrict_rows ? c->tile_rows[ti] : nbf;
         if (t.nB == 0 || M == 0) continue;
         ks[ti] = c->pipe ? c->nsplit : choose_ksplit(otiles, t.b1 - t.b0);
+        // FP32 products (legacy FP32 storage, or the weak columns of the split build): chunks
+        // of at most kFp32MaxK points, added in FP64 by the reduction
+        if (c->mixed || c->split)
+            ks[ti] = std::max<int>(ks[ti], (int)((t.ncols + kFp32MaxK - 1) / kFp32MaxK));
         need += (int64_t)ks[ti] * M * t.nB;
     }
     int rc = ensure_part(c, need);
     if (rc) return rc;
     if (restrict_rows)
         HIPCHECK(c, launch_rinv(c->d_trows, nbf, nullptr, c->d_tcount, ntile, nbf, max_rows, c->d_rinv, c->stream));
-    std::vector<GemmProb> probs;
+    std::vector<GemmProb> probs, weak;
     std::vector<RedTile> red;
     int64_t poff = 0;
     for (int ti = 0; ti < ntile; ++ti) {
         const Tile& t = g.tiles[ti];
         const int64_t M = restrict_rows ? c->tile_rows[ti] : nbf;
         if (t.nB == 0 || M == 0) continue;
+        // split build: product columns in the tile's strong-then-weak order
+        const int32_t ns = c->split ? c->tile_nstrong[ti] : t.nB;
         GemmProb p{};
         p.A = c->d_G + t.col0;
         p.lda = ld;
         p.arow = restrict_rows ? c->d_trows + (int64_t)ti * nbf : nullptr;
         p.B = c->mixed ? (const void*)(c->d_Phi32 + t.phi_off) : (const void*)(c->d_Phi + t.phi_off);
+        p.bmap = c->split ? c->d_perm + t.row_off : nullptr;
         p.ldb = t.ncols;
         p.C = c->d_part + poff;
         p.ldc = t.nB;
         p.cstride = M * t.nB;
         p.M = (int32_t)M;
-        p.N = t.nB;
+        p.N = ns;
         p.K = (int32_t)t.ncols;
         p.ksplit = ks[ti];
-        probs.push_back(p);
+        if (ns > 0) probs.push_back(p);
+        c->acc_flops64 += 2.0 * (double)M * (double)ns * (double)t.ncols;
+        if (ns < t.nB) {
+            // the weak rows of Phi_t as the F product left them in FP32 (rows in weak order)
+            GemmProb q = p;
+            q.B = (const char*)c->d_Phw + c->tile_phw_off[ti] * sizeof(float);
+            q.bmap = nullptr;
+            q.C = c->d_part + poff + ns;
+            q.N = t.nB - ns;
+            weak.push_back(q);
+            c->acc_flops32 += 2.0 * (double)M * (double)(t.nB - ns) * (double)t.ncols;
+        }
         RedTile r{};
         r.poff = poff;
         r.M = (int32_t)M;
         r.N = t.nB;
         r.ksplit = ks[ti];
         r.rinv = restrict_rows ? c->d_rinv + (int64_t)ti * nbf : nullptr;
-        r.ccol = t.all_functions ? nullptr : t.d_coll_fn;
+        r.ccol = c->split ? c->d_cperm + t.row_off : (t.all_functions ? nullptr : t.d_coll_fn);
         red.push_back(r);
         poff += (int64_t)ks[ti] * M * t.nB;
     }
-    if ((rc = run_gemms(c, probs, c->mixed ? kGemmF32dA : kGemmF64, true))) return rc;
-    return run_reduce(c, red, c->d_Kt);
+    if ((rc = timed_gemms(c, c->mixed ? 3 : 2, probs, c->mixed ? kGemmF32dA : kGemmF64, true))) return rc;
+    if ((rc = timed_gemms(c, 3, weak, kGemmF32dA, true))) return rc;
+    if ((rc = run_reduce(c, red, c->d_Kt))) return rc;
+    if (c->split && restrict_rows) {
+        // rigorous bound on the energy moved by the FP32 products of the group (accumulated
+        // over the build): sum over tiles and G rows of |G row| (sum of |P| over weak columns)
+        std::vector<BoundTile> bt;
+        for (int ti = 0; ti < ntile; ++ti) {
+            const Tile& t = g.tiles[ti];
+            bt.push_back(BoundTile{t.col0, (int32_t)t.ncols, t.row_off, t.nB, c->tile_nstrong[ti]});
+        }
+        const BoundTile* d = nullptr;
+        if ((rc = push_vector(c, bt, &d))) return rc;
+        HIPCHECK(c, launch_lowprec_bound(c->d_G, ld, c->d_P_cur, nbf, d, ntile, c->d_trows, c->d_tcount, c->d_cperm,
+                                         c->d_lpb, c->d_lpb + (int64_t)c->max_group_tiles * kBoundChunksPerTile,
+                                         c->stream));
+    }
+    return SNK_OK;
 }
 
 // U (bound factors) and N (F norms) of every shell on every batch of the group
@@ -2218,8 +2474,16 @@ int snk_ctx_build(snk_ctx* c, const double* P, double* K_out, snk_stats* stats)
     double tcls[6] = {0, 0, 0, 0, 0, 0};
     GroupStats gs;
     const bool timed = stats != nullptr;
+    c->timing = timed;
+    for (int k = 0; k < 4; ++k) {
+        c->gms[k] = 0.0;
+        c->gcount[k] = 0;
+    }
 
     HIPCHECK(c, launch_fill(c->d_Kt, (int64_t)nb2, 0.0, s));
+    c->d_P_cur = dP;
+    c->acc_flops64 = c->acc_flops32 = 0.0;
+    if (c->split) HIPCHECK(c, launch_fill(c->d_lpb + (int64_t)c->max_group_tiles * kBoundChunksPerTile, 1, 0.0, s));
     if (c->kx_fn) {
         HIPCHECK(c, launch_fill(c->d_kxKt, (int64_t)nb2, 0.0, s));
         HIPCHECK(c, launch_fill(c->d_kxsum, 3, 0.0, s));
@@ -2247,6 +2511,12 @@ int snk_ctx_build(snk_ctx* c, const double* P, double* K_out, snk_stats* stats)
         if (timed) {
             HIPCHECK(c, hipEventRecord(c->ev[4], s));
             HIPCHECK(c, hipEventSynchronize(c->ev[4]));
+            for (int k = 0; k < 4; ++k)
+                if (c->gl[k]) {
+                    c->gms[k] += ev_ms(c->gev[2 * k], c->gev[2 * k + 1]);
+                    c->gcount[k] += 1;
+                    c->gl[k] = false;
+                }
             tcol += ev_ms(c->ev[0], c->ev[1]);
             tf += ev_ms(c->ev[1], c->ev[2]);
             if (c->opts.screen != SNK_SCREEN_NONE) {
@@ -2310,6 +2580,18 @@ int snk_ctx_build(snk_ctx* c, const double* P, double* K_out, snk_stats* stats)
         stats->tile_functions = c->acc_fn / cols;
         stats->tile_frows = c->acc_frows / cols;
         stats->tile_grows = c->row_restrict ? c->acc_grows / cols : (double)nbf;
+        stats->gemm_flops_fp64 = c->acc_flops64;
+        stats->gemm_flops_fp32 = c->acc_flops32;
+        for (int k = 0; k < 4; ++k) {
+            stats->t_gemm_ms[k] = c->gms[k];
+            stats->gemm_launches[k] = c->gcount[k];
+        }
+        if (c->split) {
+            double sum = 0.0;
+            HIPCHECK(c, hipMemcpy(&sum, c->d_lpb + (int64_t)c->max_group_tiles * kBoundChunksPerTile, sizeof(double),
+                                  hipMemcpyDeviceToHost));
+            stats->lowprec_bound = kFp32GemmGamma * kWeakPhi * sum;
+        }
     }
     return SNK_OK;
 }
@@ -2337,9 +2619,11 @@ int snk_shell_rcut(int l, const double* exps, const double* coefs, int nprim, do
 }
 
 int snk_debug_gemm_f64(int64_t M, int64_t N, int64_t K, const double* A, int64_t lda, const double* B, int64_t ldb,
-                       int bt, double* C, int64_t ldc, void* stream)
+                       int bt, double* C, int64_t ldc, int tile, void* stream)
 {
     if (M < 0 || N < 0 || K < 0 || !A || !B || !C) return arg_error(nullptr, "bad GEMM arguments");
+    if (tile != 0 && tile != 64 && tile != 128) return arg_error(nullptr, "tile must be 0, 64 or 128");
+    if (M == 0 || N == 0) return SNK_OK;
     if (lda < K || ldc < N || ldb < (bt ? K : N)) return arg_error(nullptr, "leading dimension too small");
     if (M > INT32_MAX || N > INT32_MAX || K > INT32_MAX) return arg_error(nullptr, "GEMM too large");
     GemmProb p{};
@@ -2353,7 +2637,7 @@ int snk_debug_gemm_f64(int64_t M, int64_t N, int64_t K, const double* A, int64_t
     p.N = (int32_t)N;
     p.K = (int32_t)K;
     p.ksplit = 1;
-    const int tile = ggemm_tile(&p, 1);
+    if (tile == 0) tile = ggemm_tile(&p, 1);
     ggemm_plan(p, tile, 8, 8);
     GemmProb* d = nullptr;
     hipStream_t s = (hipStream_t)stream;

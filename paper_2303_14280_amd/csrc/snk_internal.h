@@ -140,6 +140,15 @@ struct ScreenArgs {
 // summed estimates times kLowRelErr stay within eps_lowprec_energy.  FP32 rounds at 2^-24;
 // the recurrences and the contraction lose up to a few digits more on cancellation.
 constexpr double kLowRelErr = 1e-5;
+// Split build (SNK_MIXED with basis and density screening): on each tile the functions whose
+// largest |Phi| over the tile's points is below kWeakPhi enter F = P Phi and K~ = G Phi^T through
+// the FP32 matrix cores.  For such a function |Phi_nu,i| < kWeakPhi, so the FP32 products move
+// F_lam,i by at most gamma kWeakPhi sum_{nu weak} |P_lam,nu| and K~_mu,nu by at most
+// gamma kWeakPhi sum_i |G_mu,i|; with E_x = -1/2 sum F G this bounds the energy change by
+// gamma kWeakPhi sum_t sum_mu (sum_{i in t} |G_mu,i|) (sum_{nu weak on t} |P_mu,nu|).  gamma:
+// operands rounded to FP32 (2 u) and FP32 sums of at most 1024 terms (1024 u), u = 2^-24.
+constexpr double kWeakPhi = 1e-3;
+constexpr double kFp32GemmGamma = (2.0 + 1024.0) / 16777216.0;
 
 // block-energy histograms of the screens: bin = floor(2 log2 e) + kBinOff, clamped to [0, kNBins)
 constexpr int kBinOff = 400;
@@ -272,6 +281,7 @@ struct GemmProb {
     const int32_t* acol;
     int64_t lda;
     const void* B;
+    const int32_t* bmap;   // rows of B read through this map: B(k, j) = B[bmap(k) ldb + j] (bt: B[bmap(j) ldb + k])
     int64_t ldb;
     void* C;
     const int32_t* crow;
@@ -279,8 +289,17 @@ struct GemmProb {
     int64_t cstride;
     int64_t wg0;
     int32_t M, N, K, ksplit, kchunk, tm, tn;
-    int32_t vec;   // bit 0: A rows 16-byte aligned, bit 1: B rows (set by ggemm_plan)
+    int32_t vec;   // bit 0: A rows 16-byte aligned, bit 1: B rows (set by ggemm_plan); bit 2: C += product;
+                   // bits 3, 4: A2, B2 rows aligned (set by ggemm_plan)
+    // split products only (launch_gsplit): + A2 B2 over K2 more k, FP32 operands, A2 row-major
+    // (rows arow(i), stride lda2), B2 row-major K2 x N (stride ldb2)
+    const void* A2;
+    const void* B2;
+    int64_t lda2, ldb2;
+    int32_t K2, pad2;
 };
+constexpr int32_t kGemmAccumulate = 4;
+constexpr int kFp32MaxK = 1024;   // longest FP32 sum of a product element
 // One tile of a grouped reduction: T[r][ccol(n)] += sum_z part[poff + z M N + rinv(r) N + n]
 // for every row r with rinv(r) >= 0 (rinv null: r < M), in list order.
 struct RedTile {
@@ -289,8 +308,8 @@ struct RedTile {
     const int32_t* rinv;
     const int32_t* ccol;
 };
-// Output tile (64 or 128) for a launch of these problems (M, N, K and ksplit filled in): 64 for
-// short k per workgroup, else 128 unless 64 saves most of the padded work
+// Output tile (64 or 128) for a launch of these problems (M, N and K filled in): 128 unless
+// 64 saves most of the padded work
 int ggemm_tile(const GemmProb* probs, int nprob);
 // asize, bsize: bytes per element of A and B
 void ggemm_plan(GemmProb& p, int tile, int asize, int bsize);
@@ -298,10 +317,50 @@ int64_t ggemm_workgroups(const GemmProb& p);
 // probs: device array of nprob problems planned for the tile size, nwg workgroups in all;
 // FP64 matrix cores
 hipError_t launch_ggemm_f64(const GemmProb* probs, int nprob, int64_t nwg, int tile, bool bt, hipStream_t s);
-// FP32 matrix-core forms: operands rounded to FP32, FP32 sums over at most 1024 consecutive k
-// added into FP64 sums; f32: FP32 A, B, C; f32_dA: FP64 A, FP32 B, FP64 C
+// FP32 matrix-core forms: operands rounded to FP32 and FP32 sums over each workgroup's k chunk,
+// which the caller keeps at most kFp32MaxK long (ksplit), the chunks then added in FP64 by the
+// reduction; f32: FP32 A, B, C; f32_dA: FP64 A, FP32 B, FP64 C
 hipError_t launch_ggemm_f32(const GemmProb* probs, int nprob, int64_t nwg, int tile, bool bt, hipStream_t s);
 hipError_t launch_ggemm_f32_dA(const GemmProb* probs, int nprob, int64_t nwg, int tile, bool bt, hipStream_t s);
+// Split products (B row-major, one chunk, overwrite C): FP64 A B over K plus FP32 A2 B2 over
+// K2 <= kFp32MaxK, written once in FP64
+hipError_t launch_gsplit(const GemmProb* probs, int nprob, int64_t nwg, int tile, hipStream_t s);
+// FP32 matrix cores on FP64 operands rounded as they are staged, FP64 C
+hipError_t launch_ggemm_f32_dd(const GemmProb* probs, int nprob, int64_t nwg, int tile, bool bt, hipStream_t s);
+// One tile of a grouped gather: out[out_off + i ld + k] = src[src_off + rows(i) src_ld + cols(k)]
+// for i < M, k < N (rows, cols null: identity), converted to the output type
+struct GatherTile {
+    int64_t out_off;
+    int64_t src_off;
+    int64_t src_ld;
+    const int32_t* rows;
+    const int32_t* cols;
+    int32_t M, N, ld, pad;
+};
+hipError_t launch_gather_tiles(const double* src, const GatherTile* tiles, int ntile, int32_t max_rows, double* out,
+                               hipStream_t s);
+hipError_t launch_gather_tiles(const float* src, const GatherTile* tiles, int ntile, int32_t max_rows, float* out,
+                               hipStream_t s);
+hipError_t launch_gather_tiles(const double* src, const GatherTile* tiles, int ntile, int32_t max_rows, float* out,
+                               hipStream_t s);
+// Per tile t (rows roff[t] .. roff[t+1] of a group's Phi, row maxima mx): perm lists the rows
+// with mx >= tau in order, then the others in order (same offsets as the rows); cperm[k] =
+// fn[roff[t] + perm[k]] (the function of each permuted row); nstrong[t] = the rows with
+// mx >= tau, raised so that at most kFp32MaxK rows follow (the weak rows, k >= nstrong[t])
+hipError_t launch_partition(const double* mx, const int32_t* fn, const int32_t* roff, int ntile, double tau,
+                            int32_t* perm, int32_t* cperm, int32_t* nstrong, hipStream_t s);
+// Bound of the energy error of the FP32 products of a group (the weak rows k >= nstrong[t] of
+// each tile): acc[0] += sum over tiles t and the tile's G rows r = rows[t * nbf + 0 .. counts[t])
+// of (sum_{i < ncols_t} |G[r][col0_t + i]|) (sum_{k >= nstrong[t]} |P[r][cperm[roff_t + k]]|);
+// partials: kBoundChunks doubles per tile of scratch
+struct BoundTile {
+    int64_t col0;
+    int32_t ncols, roff, nB, nstrong;
+};
+hipError_t launch_lowprec_bound(const double* G, int64_t ld, const double* P, int64_t nbf, const BoundTile* tiles,
+                                int ntile, const int32_t* rows, const int32_t* counts, const int32_t* cperm,
+                                double* partials, double* acc, hipStream_t s);
+constexpr int kBoundChunksPerTile = 32;
 // T (nrow rows of stride ldt) += the tiles' chunk sums, one workgroup per row, tiles in order
 hipError_t launch_group_reduce(const double* part, const RedTile* tiles, int ntile, double* T, int64_t ldt,
                                int64_t nrow, hipStream_t s);

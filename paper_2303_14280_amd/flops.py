@@ -5,8 +5,10 @@ them term by term (add/sub/mul = 1, fused multiply-add = 2):
 
 per primitive pair and grid point
   - P - r_i and T = zeta_p |P - r_i|^2                                  9
-  - Boys function F_0..F_L, charged at its asymptotic branch            4 + 2L
-    (F_0 = c rsqrt(T), h = r^2/2, F_m = F_{m-1} (2m-1) h)
+  - Boys function F_0..F_L, charged at the cost of the evaluation the    2 + 22 (L + 1)
+    kernels use for T < 50 (nearly every evaluation): a table node and
+    offset, then an 11-term Taylor series in the offset for each order
+    (10 fused multiply-adds)
   - base case Theta^n_0 = pref F_n                                      L + 1
   - each VRR term: PA_q Theta^n - PC_q Theta^{n+1}                      3
     plus, when a_q > 0, a_q/(2 zeta_p) (Theta^n_{a-1} - Theta^{n+1}_{a-1})  4 more
@@ -44,7 +46,7 @@ def _dir(c) -> int:
 @lru_cache(maxsize=None)
 def per_prim_pair(la: int, lb: int) -> int:
     L = la + lb
-    f = 9 + (4 + 2 * L) + (L + 1)
+    f = 9 + (2 + 22 * (L + 1)) + (L + 1)
     for l in range(1, L + 1):
         for c in comps(l):
             q = _dir(c)
@@ -77,5 +79,6 @@ def class_flops(cls: int, pair_points: int, prim_pair_points: int) -> float:
 # MI355X (gfx950) peaks used for roofline fractions
 PEAK_FP64_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12   # 78.6: 256 CU x 4 SIMD x 16 lanes x FMA x 2.4 GHz
 PEAK_FP64_MFMA_TFLOPS = 78.6
+PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_BF16_MFMA_TFLOPS = 2500.0
 PEAK_HBM_GBS = 8000.0

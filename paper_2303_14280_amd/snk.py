@@ -48,11 +48,14 @@ class SnkStats(ctypes.Structure):
                 ("pair_points_lowprec", ctypes.c_int64), ("skipped_bound", ctypes.c_double),
                 ("n_batches", ctypes.c_int32), ("n_groups", ctypes.c_int32),
                 ("prim_pair_points", ctypes.c_int64 * 6), ("t_afg_class_ms", ctypes.c_double * 6),
-                ("tile_functions", ctypes.c_double), ("tile_frows", ctypes.c_double), ("tile_grows", ctypes.c_double)]
+                ("tile_functions", ctypes.c_double), ("tile_frows", ctypes.c_double), ("tile_grows", ctypes.c_double),
+                ("gemm_flops_fp64", ctypes.c_double), ("gemm_flops_fp32", ctypes.c_double),
+                ("lowprec_bound", ctypes.c_double), ("t_gemm_ms", ctypes.c_double * 4),
+                ("gemm_launches", ctypes.c_int64 * 4)]
 
     def as_dict(self) -> dict:
         d = {k: getattr(self, k) for k, _ in self._fields_}
-        for k in ("pair_points", "prim_pair_points", "t_afg_class_ms"):
+        for k in ("pair_points", "prim_pair_points", "t_afg_class_ms", "t_gemm_ms", "gemm_launches"):
             d[k] = list(d[k])
         return d
 
@@ -138,7 +141,7 @@ def lib():
             L.snk_boys_device.restype = ctypes.c_int
             L.snk_debug_gemm_f64.argtypes = [ctypes.c_int64] * 3 + [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                                                    ctypes.c_int64, ctypes.c_int, ctypes.c_void_p,
-                                                                   ctypes.c_int64, ctypes.c_void_p]
+                                                                   ctypes.c_int64, ctypes.c_int, ctypes.c_void_p]
             L.snk_debug_gemm_f64.restype = ctypes.c_int
             L.snk_debug_mfma_layout.argtypes = [ctypes.c_void_p]
             L.snk_debug_mfma_layout.restype = ctypes.c_int
@@ -445,9 +448,9 @@ def boys_device(T_ptr: int, n: int, mmax: int, F_ptr: int, stream: int = 0):
                                  ctypes.c_void_p(stream) if stream else None))
 
 
-def debug_gemm_f64(M, N, K, A_ptr, lda, B_ptr, ldb, bt, C_ptr, ldc, stream: int = 0):
+def debug_gemm_f64(M, N, K, A_ptr, lda, B_ptr, ldb, bt, C_ptr, ldc, stream: int = 0, tile: int = 0):
     _check(lib().snk_debug_gemm_f64(M, N, K, ctypes.c_void_p(A_ptr), lda, ctypes.c_void_p(B_ptr), ldb, int(bt),
-                                    ctypes.c_void_p(C_ptr), ldc, ctypes.c_void_p(stream) if stream else None))
+                                    ctypes.c_void_p(C_ptr), ldc, int(tile), ctypes.c_void_p(stream) if stream else None))
 
 
 def debug_mfma_layout() -> np.ndarray:

@@ -1,4 +1,4 @@
-"""The C-ABI library loads, exports every entry point declared in include/snk.h, and rejects
+"""The C-ABI library loads, exports every entry point declared in include/*.h, and rejects
 invalid arguments on the host before touching a device (no compute calls without a GPU)."""
 import ctypes
 import os
@@ -13,7 +13,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def declared_functions():
-    src = open(os.path.join(ROOT, "include", "snk.h")).read()
+    src = "".join(open(os.path.join(ROOT, "include", h)).read() for h in sorted(os.listdir(os.path.join(ROOT, "include")))
+                  if h.endswith(".h"))
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*([a-z_0-9]+)\s*\(", src, flags=re.M)
     return sorted(set(n for n in names if n.startswith("sn")))

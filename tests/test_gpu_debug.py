@@ -29,9 +29,10 @@ def test_mfma_f64_layout():
             assert say_ok
 
 
+@pytest.mark.parametrize("tile", [64, 128])
 @pytest.mark.parametrize("bt", [False, True])
 @pytest.mark.parametrize("shape", [(100, 130, 77), (300, 517, 333), (1, 1, 1), (129, 257, 16)])
-def test_gemm_f64_vs_numpy(bt, shape):
+def test_gemm_f64_vs_numpy(bt, shape, tile):
     """The grouped matrix-core product on one problem: ragged edges of the 128 x 128 output
     tiles and of the 16-wide k steps, several tiles in both directions."""
     import torch
@@ -44,8 +45,8 @@ def test_gemm_f64_vs_numpy(bt, shape):
     Bd = torch.tensor(B, device="cuda")
     Cd = torch.full((M, N), float("nan"), dtype=torch.float64, device="cuda")
     torch.cuda.synchronize()
-    say("gemm bt", bt, "shape", shape)
-    snk.debug_gemm_f64(M, N, K, Ad.data_ptr(), K, Bd.data_ptr(), K if bt else N, bt, Cd.data_ptr(), N)
+    say("gemm bt", bt, "shape", shape, "tile", tile)
+    snk.debug_gemm_f64(M, N, K, Ad.data_ptr(), K, Bd.data_ptr(), K if bt else N, bt, Cd.data_ptr(), N, tile=tile)
     torch.cuda.synchronize()
     C = Cd.cpu().numpy()
     err = np.max(np.abs(C - ref))
