@@ -297,7 +297,15 @@ int snk_shell_rcut(int l, const double* exps, const double* coefs, int nprim, do
  *   given upstream gradient dy[n] (device), into grads (nparams + 1 floats, the last 0): the
  *   plain backward pass of the FP32 network.
  * snk_mlp_adam_step: one Adam update (beta 0.9 / 0.999, eps 1e-8) at step t >= 1.
-
+ *
+ * snk_mlp_loss_grad_noalloc: snk_mlp_loss_grad for callers that cannot allocate device memory
+ *   (code under HIP graph capture, tight serving loops, harnesses that forbid allocation).
+ *   Same kernels and result; the per-workgroup partial sums live in a fixed array that each
+ *   GPU holds from the first snk_mlp_create on it until the process ends (21.8 MB), so the
+ *   call allocates nothing.  At most 65536 samples per call (more: SNK_E_ARG, message in
+ *   snk_last_error(NULL)); the network's device must be the current device.  Every call on a
+ *   GPU shares that GPU's array: calls that overlap on one GPU (different streams, threads)
+ *   race and must be ordered by the caller.
  */
 int snk_mlp_nparams(void);
 int snk_mlp_create(int device, snk_mlp** out);
@@ -309,6 +317,8 @@ int snk_mlp_set_range(snk_mlp* mlp, const float* lo, const float* hi, float marg
 int snk_mlp_forward(const snk_mlp* mlp, const float* x, int64_t n, float* y, int bf16, void* stream);
 int snk_mlp_loss_grad(snk_mlp* mlp, const float* x, const float* target, int64_t n, float under, float* grads,
                       void* stream);
+int snk_mlp_loss_grad_noalloc(snk_mlp* mlp, const float* x, const float* target, int64_t n, float under,
+                              float* grads, void* stream);
 int snk_mlp_backward(snk_mlp* mlp, const float* x, const float* dy, int64_t n, float* grads, void* stream);
 int snk_mlp_adam_step(snk_mlp* mlp, const float* grads, float lr, int t, void* stream);
 

@@ -23,6 +23,7 @@ const MlpNorm& mlp_norm(const snk_mlp* m);
 const float* mlp_params(const snk_mlp* m);
 void mlp_range(const snk_mlp* m, float* lo, float* hi, float* margin, int* has_range);
 int mlp_device(const snk_mlp* m);
+void set_last_error(const char* msg);
 }  // namespace snk
 
 namespace {
@@ -2925,3 +2926,8 @@ int snk_boys_device(const double* T, int64_t n, int mmax, double* F_out, void* s
 }
 
 }  // extern "C"
+
+namespace snk {
+// error text of a context-free call (snk_last_error(NULL)), for entry points in other files
+void set_last_error(const char* msg) { g_last_error = msg ? msg : ""; }
+}  // namespace snk

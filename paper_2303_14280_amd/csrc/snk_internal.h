@@ -157,6 +157,8 @@ constexpr int kNBins = 512;
 // learned screener network 16 -> 64 -> 64 -> 1
 constexpr int kMlpIn = 16;
 constexpr int kMlpParams = 64 * 16 + 64 + 64 * 64 + 64 + 64 + 1;   // 5313
+// samples per call of snk_mlp_loss_grad_noalloc (its fixed scratch array)
+constexpr int64_t kMlpNoAllocMaxSamples = 65536;
 struct MlpNorm {
     float mean[16];
     float inv_std[16];

@@ -22,6 +22,7 @@ struct snk_mlp {
 };
 
 namespace snk {
+int mlp_scratch_init(int device);
 // read by the screening host code
 const MlpNorm& mlp_norm(const snk_mlp* m) { return m->norm; }
 const float* mlp_params(const snk_mlp* m) { return m->d_params; }
@@ -44,6 +45,8 @@ int snk_mlp_create(int device, snk_mlp** out)
     if (!out) return SNK_E_ARG;
     *out = nullptr;
     if (hipSetDevice(device) != hipSuccess) return SNK_E_DEVICE;
+    // the device address of the fixed scratch array of snk_mlp_loss_grad_noalloc, once per device
+    if (mlp_scratch_init(device) != SNK_OK) return SNK_E_DEVICE;
     snk_mlp* m = new (std::nothrow) snk_mlp();
     if (!m) return SNK_E_NOMEM;
     m->device = device;

@@ -180,6 +180,8 @@ def lib():
             L.snk_mlp_loss_grad.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                             ctypes.c_float, ctypes.c_void_p, ctypes.c_void_p]
             L.snk_mlp_loss_grad.restype = ctypes.c_int
+            L.snk_mlp_loss_grad_noalloc.argtypes = L.snk_mlp_loss_grad.argtypes
+            L.snk_mlp_loss_grad_noalloc.restype = ctypes.c_int
             L.snk_mlp_adam_step.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_float, ctypes.c_int,
                                             ctypes.c_void_p]
             L.snk_mlp_adam_step.restype = ctypes.c_int
@@ -511,6 +513,13 @@ class Mlp:
         _check(lib().snk_mlp_loss_grad(self._h, ctypes.c_void_p(x_ptr), ctypes.c_void_p(t_ptr), int(n),
                                        float(under), ctypes.c_void_p(g_ptr),
                                        ctypes.c_void_p(stream) if stream else None))
+
+    def loss_grad_noalloc(self, x_ptr: int, t_ptr: int, n: int, g_ptr: int, under: float = 10.0,
+                          stream: int = 0) -> None:
+        """loss_grad without any device allocation (at most 65536 samples per call)."""
+        _check(lib().snk_mlp_loss_grad_noalloc(self._h, ctypes.c_void_p(x_ptr), ctypes.c_void_p(t_ptr), int(n),
+                                               float(under), ctypes.c_void_p(g_ptr),
+                                               ctypes.c_void_p(stream) if stream else None))
 
     def backward(self, x_ptr: int, dy_ptr: int, n: int, g_ptr: int, stream: int = 0) -> None:
         _check(lib().snk_mlp_backward(self._h, ctypes.c_void_p(x_ptr), ctypes.c_void_p(dy_ptr), int(n),
