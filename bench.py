@@ -39,20 +39,18 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(system, pairs_per_point: float, target_s: float = 20.0):
+def cpu_baseline(system, pairs_per_point: float):
     """The CPU oracle (plain sn-K: every shell pair at every point, FP64) timed on a bounded
-    sample of the same workload (evenly spaced grid points), in the units of `value`: the
-    GPU's count of surviving shell pairs per point times the points evaluated, per second."""
+    sample of the same workload: one evenly spaced grid point per host thread (the oracle
+    parallelises over points, and one point of this system is tens of seconds of one core's
+    work), in the units of `value`: the GPU's count of surviving shell pairs per point times the
+    points evaluated, per second."""
     import numpy as np
     from oracle import oracle as O
     nthreads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
-    probe = system.subset_points(np.arange(0, system.npts, max(1, system.npts // 4)))
-    t = time.perf_counter()
-    O.snk(probe, nthreads=nthreads)
-    dt = max(time.perf_counter() - t, 1e-3)
-    n = int(min(64, max(probe.npts, probe.npts * target_s / dt)))
+    n = max(1, min(64, nthreads))
     stride = max(1, system.npts // n)
-    sample = system.subset_points(np.arange(0, system.npts, stride)[:n])
+    sample = system.subset_points(np.arange(stride // 2, system.npts, stride)[:n])
     t = time.perf_counter()
     O.snk(sample, nthreads=nthreads)
     dt = time.perf_counter() - t
@@ -98,13 +96,11 @@ def dominant_kernel(st):
         work = flops.class_flops(c, st["pair_points"][c], st["prim_pair_points"][c])
         cands.append((st["t_afg_class_ms"][c], "afg_kernel<%d,%d> (%s, A.F digestion)" % (flops.CLASS_L[c] + (CLASSES[c],)),
                       work, groups, "alu", flops.PEAK_FP64_VALU_TFLOPS))
-    gflops = {0: None, 1: None, 2: None, 3: None}
     for k in range(4):
         if st["t_gemm_ms"][k] <= 0:
             continue
         cands.append((st["t_gemm_ms"][k], "ggemm_kernel (%s)" % GEMM_KINDS[k], None, max(1, st["gemm_launches"][k]),
                       "mfma", flops.PEAK_FP32_MFMA_TFLOPS if k in (1, 3) else flops.PEAK_FP64_MFMA_TFLOPS))
-        gflops[k] = k
     t, name, work, launches, bound, peak = max(cands, key=lambda x: x[0])
     if work is None:
         # the library reports the flops of the two products per precision; split them by the
