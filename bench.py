@@ -142,7 +142,7 @@ def run_variant(name, s, P, stream, mlp, steps, warmup, ref=None, **kw):
          "skipped_pair_points_fraction": st["pair_points_skipped"] / max(1.0, ints),
          "fp32_afg_pair_points_fraction": st["pair_points_lowprec"] / max(1.0, ints),
          "fp32_gemm_flops_fraction": g32 / max(1.0, g64 + g32), "gemm_flops": g64 + g32,
-         "fp32_gemm_energy_bound": st["lowprec_bound"], "skipped_energy_estimate": st["skipped_bound"],
+         "fp32_gemm_energy_bound": st["lowprec_bound"], "skipped_rigorous_bound_sum": st["skipped_bound"],
          "shell_pair_points": ints, "effective_rate": ints / (ms * 1e-3),
          "tile_functions": st["tile_functions"], "tile_f_rows": st["tile_frows"], "tile_g_rows": st["tile_grows"]}
     if ref is not None:

@@ -73,14 +73,17 @@ typedef enum snk_screen {
     SNK_SCREEN_NONE = 0,    /* every shell pair at every batch */
     SNK_SCREEN_BOUND = 1,   /* rigorous block bound (Sec. II.E, sn-LinK-type pair selection) */
     SNK_SCREEN_LEARNED = 2, /* MLP estimate with the rigorous bound as fallback */
-    SNK_SCREEN_LINK = 3     /* the paper's pair selection (Eq. sp_set): keep (A,B) on batch j when
-                               Ft_A Ft_B At_AB >= eps or max(Ft_A, Ft_B) phit_j At_AB >= eps,
-                               eps = eps_skip_energy (the paper uses 1e-9); Ft_A = max over the
-                               batch of sqrt(w_i) |F_a,i| (a in A, from F itself), phit_j = max_i
-                               sqrt(w_i) sum_mu |Phi_mu,i|, At_AB = sum over primitive pairs of
-                               |prefactor| max(1, |AB|)^(l_A + l_B) (a global estimate of
-                               max |A_ab|).  Not an energy budget: stats->skipped_bound
-                               reports the rigorous bound on the skipped blocks' energy */
+    SNK_SCREEN_LINK = 3     /* the paper's pair selection (Sec. II.E, Eq. sp_set): keep (A,B) on batch
+                               j when Ft_A Ft_B At_AB >= eps or max(Ft_A, Ft_B) phit_j At_AB >= eps,
+                               eps = eps_skip_energy (the paper uses 1e-9).  Ft_A = max over the
+                               functions mu of A of Ft_mu = sum_{nu in B_t} |P_mu,nu| Phit_nu
+                               (Eq. exx_fmat_approx, mu over the whole basis, one grouped product
+                               over the tiles), Phit_nu = max over the batch of sqrt(w_i)
+                               |Phi_nu,i|; phit_j = max_i sqrt(w_i) sum_mu |Phi_mu,i|; At_AB = sum
+                               over primitive pairs of |prefactor| max(1, |AB|)^(l_A + l_B) (a
+                               global estimate of max |A_ab|).  Not an energy budget:
+                               stats->skipped_bound reports the rigorous bound on the skipped
+                               blocks' energy */
 } snk_screen;
 
 /* opts.flags */
@@ -252,9 +255,12 @@ int snk_vxc_build(snk_ctx* ctx, const double* P, int functional, double* V_out, 
  * FP64 contexts without basis screening (eps_basis = 0) and without SNK_OVERLAP_GROUPS the
  * two share each batch group's collocation Phi and F = P Phi (Eq. fmat; the paper's common
  * intermediates of the exchange and XC builds): the XC point kernel and V product run on the
- * group's Phi and F after its K product.  Other contexts run the two builds one after the
- * other.  Outputs, pointer modes, statistics (those of sn-K; the XC work is outside its phase
- * timings) and error codes as for the two calls; K_out and V_out must not overlap.
+ * group's Phi and F after its K product, with the XC matrix Z in the place of the exchange G
+ * (no batch-group memory beyond the sn-K build's; the nbf^2 XC accumulator and its split
+ * partial products sit outside opts.max_device_bytes, as K~ does).  Other contexts run the two
+ * builds one after the other.  Outputs, pointer modes and error codes as for the two calls; the
+ * statistics are those of sn-K, with the XC work of a shared build outside the phase timings
+ * but inside t_total_ms; K_out and V_out must not overlap.
  */
 int snk_ctx_build_kxc(snk_ctx* ctx, const double* P, double* K_out, int functional, double* V_out, double* exc_out,
                       double* nel_out, snk_stats* stats);

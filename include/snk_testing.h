@@ -46,6 +46,11 @@ int snk_boys_device(const double* T, int64_t n, int mmax, double* F_out, void* s
  *   that group and pair index p, the raw network output yraw[b * npair_index + p] and the
  *   block estimate log2 est[...] (NaN for blocks the bound already skipped), and the
  *   first kept estimate bin thr[b].  *nbatch_out = batches of the group.
+ * snk_ctx_debug_kept: runs the first batch group of a context with a density screen (P a
+ *   host pointer, host-pointer context) and returns the shell pairs the screen kept for the
+ *   A.F step, as int32 triples (batch, A, B) in `out` (A is the shell of larger angular
+ *   momentum, or of larger index for equal ones); *n_out = number of triples.  out = NULL
+ *   queries the count; cap = triples out holds (SNK_E_ARG when fewer than kept).
  * snk_debug_mfma_bf16: D = A B (16 x 16 row-major host D) through one bf16 matrix-core op,
  *   A and B rounded to bf16: with k32 = 0, A and B are 16 x 16 (16x16x16 op); with k32 != 0,
  *   A is 16 x 32 and B 32 x 16 (16x16x32 op).  Layout check.
@@ -59,6 +64,7 @@ int snk_ctx_debug_intermediates(snk_ctx* ctx, const double* P, double* Phi, doub
 int64_t snk_ctx_npair_index(const snk_ctx* ctx);
 int snk_ctx_debug_learned(snk_ctx* ctx, const double* P, float* yraw, float* est, int32_t* thr,
                           int64_t* nbatch_out);
+int snk_ctx_debug_kept(snk_ctx* ctx, const double* P, int32_t* out, int64_t cap, int64_t* n_out);
 int snk_debug_mfma_bf16(const float* A, const float* B, float* D, int k32);
 
 #ifdef __cplusplus

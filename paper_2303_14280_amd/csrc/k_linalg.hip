@@ -48,6 +48,12 @@ __global__ __launch_bounds__(256) void convert_kernel(const double* __restrict__
         out[i] = (float)in[i];
 }
 
+__global__ __launch_bounds__(256) void abs_kernel(const double* __restrict__ in, int64_t n, double* __restrict__ out)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = fabs(in[i]);
+}
+
 __device__ double block_sum(double v, double* sh)
 {
     sh[threadIdx.x] = v;
@@ -165,6 +171,15 @@ hipError_t launch_convert_f32(const double* in, int64_t n, float* out, hipStream
     int64_t blocks = (n + 255) / 256;
     if (blocks > 65536) blocks = 65536;
     hipLaunchKernelGGL(convert_kernel, dim3((unsigned)blocks), dim3(256), 0, s, in, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_abs(const double* in, int64_t n, double* out, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(abs_kernel, dim3((unsigned)blocks), dim3(256), 0, s, in, n, out);
     return hipGetLastError();
 }
 

@@ -35,87 +35,147 @@ constexpr double kBoundSafety = 1.01;
 
 // ---------------------------------------------------------------------------------------
 // U_A for the shells of one angular momentum L: one workgroup per batch, lane = point.
-// With a tile shell flag array, shells whose F rows the tile did not compute (flag 0, F = 0
-// there) get U = 0 and N = 0 without evaluating their integrals.
+// With per-tile entry lists only the shells whose F rows the tile computed are evaluated;
+// the caller has set U = 0 (and the features to their U = 0 values) for the others.
+// Each wave evaluates kRed shells before it reduces their sums over its 64 lanes together.
 // ---------------------------------------------------------------------------------------
+constexpr int kRed = 8;
+
+// Sums (MAX: maxima) over the 64 lanes of a wave of kRed per-lane values in 10 exchanges
+// instead of 6 per value: each exchange halves the values a lane carries.  On return lane l
+// holds the result for value l >> 3.
+template <bool MAX>
+__device__ __forceinline__ double wave_reduce8(const double (&v)[kRed], int lane)
+{
+    static_assert(kRed == 8, "three halving steps");
+    auto op = [](double x, double y) { return MAX ? fmax(x, y) : x + y; };
+    const bool h5 = lane & 32, h4 = lane & 16, h3 = lane & 8;
+    double w4[4], w2[2];
+    sfor<0, 4>([&](auto jc) {
+        constexpr int j = CV(jc);
+        w4[j] = op(h5 ? v[j + 4] : v[j], __shfl_xor(h5 ? v[j] : v[j + 4], 32));
+    });
+    sfor<0, 2>([&](auto jc) {
+        constexpr int j = CV(jc);
+        w2[j] = op(h4 ? w4[j + 2] : w4[j], __shfl_xor(h4 ? w4[j] : w4[j + 2], 16));
+    });
+    double w1 = op(h3 ? w2[1] : w2[0], __shfl_xor(h3 ? w2[0] : w2[1], 8));
+    w1 = op(w1, __shfl_xor(w1, 4));
+    w1 = op(w1, __shfl_xor(w1, 2));
+    return op(w1, __shfl_xor(w1, 1));
+}
+
+// The read-only arrays come as separate restrict-qualified arguments so that their uniform
+// loads (entry indices, primitive-pair records) go through the scalar unit.
 template <int L, typename TF>
-__global__ __launch_bounds__(256) void diag_bound_kernel(const double* __restrict__ px, const double* __restrict__ py,
-                                                         const double* __restrict__ pz, const double* __restrict__ pw,
-                                                         const TF* __restrict__ F, int64_t ld,
+__global__ __launch_bounds__(256) void diag_bound_kernel(DiagArgs a, const TF* __restrict__ F,
                                                          const PrimPair32* __restrict__ prims,
-                                                         const int32_t* __restrict__ dsh,   // [n] shell
-                                                         const int32_t* __restrict__ drow,  // [n] first row
-                                                         const int32_t* __restrict__ dpb,   // [n] prim_begin of (A,A)
-                                                         const int32_t* __restrict__ dnp,   // [n] nprim of (A,A)
-                                                         int32_t n, double* __restrict__ U,
-                                                         float2* __restrict__ lun, int32_t nshell,
-                                                         const double* __restrict__ gtab,
-                                                         const int32_t* __restrict__ tflag, int32_t tile_batches,
-                                                         double* __restrict__ fmax_out)
+                                                         const int32_t* __restrict__ dsh,
+                                                         const int32_t* __restrict__ drow,
+                                                         const int32_t* __restrict__ dpb,
+                                                         const int32_t* __restrict__ dnp,
+                                                         const int32_t* __restrict__ dlist,
+                                                         const int32_t* __restrict__ dcount)
 {
     constexpr int N = ncart(L);
     __shared__ float tab[kBoysRows * kBoysCols];
     __shared__ double part[kGroup][4];
     __shared__ double npart[kGroup][4];
     __shared__ double mpart[kGroup][4];
-    for (int i = threadIdx.x; i < kBoysRows * kBoysCols; i += blockDim.x) tab[i] = (float)gtab[i];
+    for (int i = threadIdx.x; i < kBoysRows * kBoysCols; i += blockDim.x) tab[i] = (float)a.tab[i];
     __syncthreads();
     const int batch = blockIdx.x;
     const int64_t col = (int64_t)batch * kBatch + threadIdx.x;
-    const float cx = (float)px[col], cy = (float)py[col], cz = (float)pz[col];
-    const double w = pw[col];
+    const float cx = (float)a.px[col], cy = (float)a.py[col], cz = (float)a.pz[col];
+    const double w = a.pw[col], sw = sqrt(w);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const float AB[3] = {0.0f, 0.0f, 0.0f};
-    const int32_t* fl = tflag ? tflag + (int64_t)(batch / tile_batches) * nshell : nullptr;
-    // shells in groups of kGroup: per-wave partial sums in LDS, one barrier pair per group
-    for (int s0 = 0; s0 < n; s0 += kGroup) {
-        const int s1 = min(n, s0 + kGroup);
-        for (int s = s0; s < s1; ++s) {
-            if (fl && !fl[dsh[s]]) {   // uniform over the workgroup
-                if (lane == 0) {
-                    part[s - s0][wave] = 0.0;
-                    npart[s - s0][wave] = 0.0;
-                    mpart[s - s0][wave] = 0.0;
+    const int tile = batch / a.tile_batches;
+    const int32_t* list = dlist ? dlist + (int64_t)tile * a.n : nullptr;
+    const int cnt = dlist ? dcount[tile] : a.n;
+    const bool want_n = a.lun != nullptr, want_m = a.fmax != nullptr;
+    // entries in groups of kGroup: per-wave partial sums in LDS, one barrier pair per group
+    for (int s0 = 0; s0 < cnt; s0 += kGroup) {
+        const int s1 = min(cnt, s0 + kGroup);
+        for (int g0 = s0; g0 < s1; g0 += kRed) {
+            double v[kRed], q[kRed], m[kRed];
+            sfor<0, kRed>([&](auto jc) {
+                constexpr int j = CV(jc);
+                v[j] = 0.0;
+                q[j] = 0.0;
+                m[j] = 0.0;
+                if (g0 + j < s1) {   // uniform over the workgroup
+                    const int e = list ? list[g0 + j] : g0 + j;
+                    float Acc[N];
+                    diag_block<L, float>(prims + dpb[e], dnp[e], cx, cy, cz, tab, Acc);
+                    const int row = drow[e];
+                    double t = 0.0, f2 = 0.0, fm = 0.0;
+                    sfor<0, N>([&](auto cc) {
+                        constexpr int c = CV(cc);
+                        const double f = cnorm(L, c) * (double)F[(int64_t)(row + c) * a.ld + col];
+                        // A_cc of the unit-normalised component (FP32; U is scaled up by kBoundSafety)
+                        t += fabs(f) * (double)sqrtf(fmaxf(Acc[c], 0.0f));
+                        f2 += f * f;
+                        fm = fmax(fm, fabs(f));
+                    });
+                    v[j] = w * t * t;
+                    q[j] = w * f2;
+                    m[j] = sw * fm;
                 }
-                continue;
-            }
-            const int row = drow[s];
-            float Ab[N][N];
-            pair_block<L, L, float>(prims + dpb[s], dnp[s], AB, cx, cy, cz, tab, Ab);
-            double t = 0.0, f2 = 0.0, fm = 0.0;
-            sfor<0, N>([&](auto cc) {
-                constexpr int c = CV(cc);
-                const double f = cnorm(L, c) * (double)F[(int64_t)(row + c) * ld + col];
-                // A_cc of the unit-normalised component (FP32; the result is scaled up by kBoundSafety)
-                t += fabs(f) * (double)sqrtf(fmaxf(Ab[c][c], 0.0f));
-                f2 += f * f;
-                fm = fmax(fm, fabs(f));
             });
-            double v = w * t * t, q = w * f2, m = sqrt(w) * fm;
-            for (int o = 32; o > 0; o >>= 1) {
-                v += __shfl_xor(v, o);
-                q += __shfl_xor(q, o);
-                m = fmax(m, __shfl_xor(m, o));
-            }
-            if (lane == 0) {
-                part[s - s0][wave] = v;
-                npart[s - s0][wave] = q;
-                mpart[s - s0][wave] = m;
+            const double vs = wave_reduce8<false>(v, lane);
+            const double qs = want_n ? wave_reduce8<false>(q, lane) : 0.0;
+            const double ms = want_m ? wave_reduce8<true>(m, lane) : 0.0;
+            const int j = lane >> 3;
+            if ((lane & 7) == 0 && g0 + j < s1) {
+                part[g0 - s0 + j][wave] = vs;
+                npart[g0 - s0 + j][wave] = qs;
+                mpart[g0 - s0 + j][wave] = ms;
             }
         }
         __syncthreads();
         if ((int)threadIdx.x < s1 - s0) {
             const int k = threadIdx.x;
-            const int64_t o = (int64_t)batch * nshell + dsh[s0 + k];
+            const int e = list ? list[s0 + k] : s0 + k;
+            const int64_t o = (int64_t)batch * a.nshell + dsh[e];
             const double u = kBoundSafety * sqrt(part[k][0] + part[k][1] + part[k][2] + part[k][3]);
-            U[o] = u;
-            if (lun)
-                lun[o] = make_float2(learn::lg10(u),
-                                     learn::lg10(sqrt(npart[k][0] + npart[k][1] + npart[k][2] + npart[k][3])));
-            if (fmax_out) fmax_out[o] = fmax(fmax(mpart[k][0], mpart[k][1]), fmax(mpart[k][2], mpart[k][3]));
+            a.U[o] = u;
+            if (want_n)
+                a.lun[o] = make_float2(learn::lg10(u),
+                                       learn::lg10(sqrt(npart[k][0] + npart[k][1] + npart[k][2] + npart[k][3])));
+            if (want_m) a.fmax[o] = fmax(fmax(mpart[k][0], mpart[k][1]), fmax(mpart[k][2], mpart[k][3]));
         }
         __syncthreads();
     }
+}
+
+// One workgroup per (tile, angular momentum): each thread takes a contiguous run of the
+// diagonal entries, counts those whose shell the tile flags, and after a workgroup scan
+// writes their indices in ascending order.
+__global__ __launch_bounds__(256) void diag_lists_kernel(DiagLists d, const int32_t* __restrict__ flag,
+                                                         int32_t nshell)
+{
+    __shared__ int32_t part[256];
+    const int t = blockIdx.x, l = blockIdx.y, tid = threadIdx.x;
+    const int n = d.n[l];
+    const int32_t* f = flag + (int64_t)t * nshell;
+    const int32_t* dsh = d.dsh[l];
+    const int per = (n + 255) / 256;
+    const int k0 = min(n, tid * per), k1 = min(n, k0 + per);
+    int cnt = 0;
+    for (int k = k0; k < k1; ++k) cnt += f[dsh[k]] != 0;
+    part[tid] = cnt;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+        const int v = tid >= o ? part[tid - o] : 0;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    int r = part[tid] - cnt;
+    int32_t* out = d.list[l] + (int64_t)t * n;
+    for (int k = k0; k < k1; ++k)
+        if (f[dsh[k]]) out[r++] = k;
+    if (tid == 255) d.count[l][t] = part[255];
 }
 
 // block-wide exclusive prefix count of a per-thread flag (256 threads), returns the total
@@ -161,7 +221,8 @@ struct BoundShared {
 };
 
 __device__ void bound_setup(const double* __restrict__ Ub, int nshell, const int32_t* __restrict__ shell_l,
-                            double eps, double eps_low, int32_t* bins, int32_t* act, BoundShared& sh)
+                            double eps, double eps_low, int32_t* bins, int32_t* act, BoundShared& sh,
+                            bool all_active = false)
 {
     const int tid = threadIdx.x;
     for (int k = tid; k < kNBins; k += blockDim.x) sh.hist[k] = 0;
@@ -232,7 +293,8 @@ __device__ void bound_setup(const double* __restrict__ Ub, int nshell, const int
         const int base = sh.aoff[l];
         for (int s0 = 0; s0 < nshell; s0 += blockDim.x) {
             const int s = s0 + tid;
-            const bool f = s < nshell && shell_l[s] == l && bins[s] != kNoBin && bins[s] + bmax >= S;
+            const bool f =
+                s < nshell && shell_l[s] == l && (all_active || (bins[s] != kNoBin && bins[s] + bmax >= S));
             int rank;
             const int tot = block_scan_flag(f, sh.wsum, &rank);
             if (f) act[base + sh.carry + rank] = s;
@@ -435,7 +497,8 @@ __global__ __launch_bounds__(256) void screen_kernel(ScreenArgs a)
     const int tid = threadIdx.x;
     const double* Ub = a.U + (int64_t)batch * a.nshell;
     const bool learned = a.est != nullptr;
-    bound_setup(Ub, a.nshell, a.shell_l, a.eps_batch, learned ? 0.0 : a.eps_low, bins, act, sh);
+    // the paper's selection decides every pair itself (Eq. sp_set), without the bound's bins
+    bound_setup(Ub, a.nshell, a.shell_l, a.eps_batch, learned ? 0.0 : a.eps_low, bins, act, sh, a.link != 0);
     const int S = sh.S, S2 = sh.S2;
     const int T = learned ? a.thr[batch] : 0;
     const int T2 = learned ? a.thr2[batch] : 0;
@@ -450,7 +513,7 @@ __global__ __launch_bounds__(256) void screen_kernel(ScreenArgs a)
         return fm[aa] * fm[b] * at >= a.link_eps || ::fmax(fm[aa], fm[b]) * phit * at >= a.link_eps;
     };
     auto keep = [&](int aa, int b) -> bool {
-        if (bins[aa] + bins[b] < S) return false;
+        if (!a.link && bins[aa] + bins[b] < S) return false;
         const int64_t p = pair_index(aa, b);
         if (a.pairs[p].nprim == 0) return false;
         if (a.link && !link_keep(aa, b, p)) return false;
@@ -663,22 +726,20 @@ __global__ __launch_bounds__(256) void screen_scan_kernel(const int32_t* __restr
 
 }  // namespace
 
-hipError_t launch_diag_bound(int l, const double* px, const double* py, const double* pz, const double* pw,
-                             const double* F, const float* F32, int64_t ld, const PrimPair32* prims, const int32_t* dsh,
-                             const int32_t* drow, const int32_t* dpb, const int32_t* dnp, int32_t n, double* U,
-                             float2* N, int32_t nshell, int32_t nbatch, const double* tab, const int32_t* tflag,
-                             int32_t tile_batches, double* fmax, hipStream_t s)
+hipError_t launch_diag_bound(int l, const DiagArgs& a, hipStream_t s)
 {
-    if (tflag && tile_batches < 1) return hipErrorInvalidValue;
-    if (nbatch <= 0 || n <= 0) return hipSuccess;
-    dim3 grid(nbatch), block(kBatch);
+    if (a.list && (a.tile_batches < 1 || !a.count)) return hipErrorInvalidValue;
+    if (a.nbatch <= 0 || a.n <= 0) return hipSuccess;
+    DiagArgs b = a;
+    if (!b.list) b.tile_batches = 1;   // unused, but keeps the tile index defined
+    dim3 grid(a.nbatch), block(kBatch);
 #define SNK_DB(L)                                                                                                  \
-    if (F32)                                                                                                       \
-        hipLaunchKernelGGL((diag_bound_kernel<L, float>), grid, block, 0, s, px, py, pz, pw, F32, ld, prims, dsh,  \
-                           drow, dpb, dnp, n, U, N, nshell, tab, tflag, tile_batches, fmax);                       \
+    if (a.F32)                                                                                                     \
+        hipLaunchKernelGGL((diag_bound_kernel<L, float>), grid, block, 0, s, b, a.F32, a.prims, a.dsh, a.drow,     \
+                           a.dpb, a.dnp, a.list, a.count);                                                         \
     else                                                                                                           \
-        hipLaunchKernelGGL((diag_bound_kernel<L, double>), grid, block, 0, s, px, py, pz, pw, F, ld, prims, dsh,   \
-                           drow, dpb, dnp, n, U, N, nshell, tab, tflag, tile_batches, fmax)
+        hipLaunchKernelGGL((diag_bound_kernel<L, double>), grid, block, 0, s, b, a.F, a.prims, a.dsh, a.drow,      \
+                           a.dpb, a.dnp, a.list, a.count)
     switch (l) {
         case 0: SNK_DB(0); break;
         case 1: SNK_DB(1); break;
@@ -686,6 +747,15 @@ hipError_t launch_diag_bound(int l, const double* px, const double* py, const do
         default: return hipErrorInvalidValue;
     }
 #undef SNK_DB
+    return hipGetLastError();
+}
+
+hipError_t launch_diag_lists(const DiagLists& d, const int32_t* flag, int32_t ntile, int32_t nshell, hipStream_t s)
+{
+    if (ntile <= 0) return hipSuccess;
+    for (int l = 0; l < 3; ++l)
+        if (!d.count[l] || (d.n[l] > 0 && (!d.list[l] || !d.dsh[l]))) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(diag_lists_kernel, dim3(ntile, 3), dim3(256), 0, s, d, flag, nshell);
     return hipGetLastError();
 }
 
@@ -765,6 +835,75 @@ __global__ __launch_bounds__(256) void phisum_kernel(const T* __restrict__ Phi, 
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
     __syncthreads();
     if (threadIdx.x == 0) phit[b] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+}
+
+// One workgroup per batch b of a group, one wave per row k of the batch's tile:
+// out[b][k] = max_i sqrt(w_i) |Phi_k,i| over the batch's points (the Phi-tilde of the sn-LinK
+// estimates; rows beyond the tile's nB up to ld are left untouched).
+template <typename T>
+__global__ __launch_bounds__(256) void phimax_kernel(const T* __restrict__ Phi, const int32_t* __restrict__ roff,
+                                                     int32_t ntile, int32_t tile_batches, int64_t ncols_last,
+                                                     const double* __restrict__ pw, double* __restrict__ out,
+                                                     int64_t ld)
+{
+    const int b = blockIdx.x;
+    const int t = b / tile_batches;
+    const int64_t tile_cols = (int64_t)tile_batches * kBatch;
+    const int64_t ncols = t == ntile - 1 ? ncols_last : tile_cols;
+    const T* base = Phi + (int64_t)roff[t] * tile_cols;   // every tile before t is full
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t c0 = (int64_t)(b - t * tile_batches) * kBatch;
+    double sw[4];
+    for (int u = 0; u < 4; ++u) sw[u] = sqrt(pw[(int64_t)b * kBatch + lane + 64 * u]);
+    const int nB = roff[t + 1] - roff[t];
+    for (int k = wave; k < nB; k += 4) {
+        const T* row = base + (int64_t)k * ncols + c0;
+        double v = 0.0;
+        for (int u = 0; u < 4; ++u) v = fmax(v, sw[u] * fabs((double)row[lane + 64 * u]));
+        for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+        if (lane == 0) out[(int64_t)b * ld + k] = v;
+    }
+}
+
+// One workgroup per batch: fs[b][A] = max over the functions mu of shell A of Ft[b][mu].
+__global__ __launch_bounds__(256) void shellmax_kernel(const double* __restrict__ Ft, int64_t ldf,
+                                                       const int32_t* __restrict__ shell_l,
+                                                       const int32_t* __restrict__ shell_row, int32_t nshell,
+                                                       double* __restrict__ fs)
+{
+    const int b = blockIdx.x;
+    const double* f = Ft + (int64_t)b * ldf;
+    for (int A = threadIdx.x; A < nshell; A += blockDim.x) {
+        const int r = shell_row[A], n = (shell_l[A] + 1) * (shell_l[A] + 2) / 2;
+        double m = 0.0;
+        for (int k = 0; k < n; ++k) m = fmax(m, f[r + k]);
+        fs[(int64_t)b * nshell + A] = m;
+    }
+}
+
+hipError_t launch_phimax(const double* Phi, const float* Phi32, const int32_t* roff, int32_t ntile,
+                         int32_t tile_batches, int64_t ncols_last, const double* pw, int32_t nbatch, double* out,
+                         int64_t ld, hipStream_t s)
+{
+    if (nbatch <= 0) return hipSuccess;
+    if ((!Phi && !Phi32) || !roff || !pw || !out || tile_batches < 1 || ntile < 1 ||
+        (int64_t)ntile * tile_batches < nbatch)
+        return hipErrorInvalidValue;
+    if (Phi32)
+        hipLaunchKernelGGL((phimax_kernel<float>), dim3(nbatch), dim3(kBatch), 0, s, Phi32, roff, ntile, tile_batches,
+                           ncols_last, pw, out, ld);
+    else
+        hipLaunchKernelGGL((phimax_kernel<double>), dim3(nbatch), dim3(kBatch), 0, s, Phi, roff, ntile, tile_batches,
+                           ncols_last, pw, out, ld);
+    return hipGetLastError();
+}
+
+hipError_t launch_shellmax(const double* Ft, int64_t ldf, const int32_t* shell_l, const int32_t* shell_row,
+                           int32_t nshell, int32_t nbatch, double* fs, hipStream_t s)
+{
+    if (nbatch <= 0 || nshell <= 0) return hipSuccess;
+    hipLaunchKernelGGL(shellmax_kernel, dim3(nbatch), dim3(256), 0, s, Ft, ldf, shell_l, shell_row, nshell, fs);
+    return hipGetLastError();
 }
 
 hipError_t launch_phisum(const double* Phi, const float* Phi32, const int32_t* roff, int32_t ntile,

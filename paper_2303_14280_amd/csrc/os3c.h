@@ -222,5 +222,60 @@ __device__ __forceinline__ void pair_block(const typename PrimOf<R>::type* __res
     });
 }
 
+// Eq. vrr for a same-centre primitive pair (R_p = R_A, so PA = 0 and its term drops)
+template <int L, typename R>
+__device__ __forceinline__ void vrr_same_centre(R (&th)[L + 1][L + 1][16], const R (&PC)[3], R oo2zp)
+{
+    sfor<1, L + 1>([&](auto lc) {
+        constexpr int l = CV(lc);
+        sfor<0, ncart(l)>([&](auto cc) {
+            constexpr int c = CV(cc);
+            constexpr int q = dir_of(l, c);
+            constexpr int c1 = lower(l, c, q);
+            constexpr int am = comp(l, c, q) - 1;
+            constexpr int c2 = am > 0 ? lower(l - 1, c1, q) : 0;
+            sfor<0, L - l + 1>([&](auto nc) {
+                constexpr int n = CV(nc);
+                R v = -PC[q] * th[n + 1][l - 1][c1];
+                if constexpr (am > 0) v += ((R)am * oo2zp) * (th[n][l - 2][c2] - th[n + 1][l - 2][c2]);
+                th[n][l][c] = v;
+            });
+        });
+    });
+}
+
+// Diagonal A_cc(C) of the contracted same-shell block (A, A) at the lane's point, from
+// same-centre primitive-pair records (P = R_A).  With R_AB = 0 Eq. hrr only moves exponents
+// from b onto a, so A_cc is the contracted Theta^0 of the level-2L component with exponents
+// 2c; the recursion keeps only the entries those components need.
+template <int L, typename R, int TC = kBoysCols>
+__device__ __forceinline__ void diag_block(const typename PrimOf<R>::type* __restrict__ pp0, int nprim, R cx, R cy,
+                                           R cz, const R* __restrict__ tab, R (&Acc)[ncart(L)])
+{
+    typedef typename PrimOf<R>::type PP;
+    constexpr int L2 = 2 * L;
+    sfor<0, ncart(L)>([&](auto cc) { Acc[CV(cc)] = (R)0; });
+    auto prim = [&](const PP& pp) {
+        const R PC[3] = {pp.Px - cx, pp.Py - cy, pp.Pz - cz};
+        const R T = pp.zp * (PC[0] * PC[0] + PC[1] * PC[1] + PC[2] * PC[2]);
+        R Fm[L2 + 1];
+        boys<L2, R, TC>(T, tab, Fm);
+        R th[L2 + 1][L2 + 1][16];
+        sfor<0, L2 + 1>([&](auto nc) { th[CV(nc)][0][0] = pp.pref * Fm[CV(nc)]; });
+        vrr_same_centre<L2, R>(th, PC, pp.oo2zp);
+        sfor<0, ncart(L)>([&](auto cc) {
+            constexpr int c = CV(cc);
+            Acc[c] += th[0][L2][cidx(L2, 2 * comp(L, c, 0), 2 * comp(L, c, 2))];
+        });
+    };
+    PP nxt{};
+    if (nprim > 0) nxt = pp0[0];
+    for (int k = 0; k < nprim; ++k) {
+        const PP pp = nxt;
+        if (k + 1 < nprim) nxt = pp0[k + 1];
+        prim(pp);
+    }
+}
+
 }  // namespace os3c
 }  // namespace snk

@@ -188,6 +188,9 @@ struct snk_ctx {
     int32_t* d_diag_pb[3] = {nullptr, nullptr, nullptr};
     int32_t* d_diag_np[3] = {nullptr, nullptr, nullptr};
     int32_t n_diag[3] = {0, 0, 0};
+    PrimPair32* d_dprims32 = nullptr;   // folded same-centre primitive pairs of the diagonal entries
+    int32_t* d_dlist[3] = {nullptr, nullptr, nullptr};   // [max_group_tiles][n_diag[l]]
+    int32_t* d_dcount = nullptr;        // [3][max_group_tiles]
     int32_t* d_shell_l = nullptr;
     int32_t* d_shell_row = nullptr;
     int32_t max_group_batches = 0;
@@ -203,7 +206,13 @@ struct snk_ctx {
     PrimPair32* d_prims32 = nullptr;
     float2* d_lun = nullptr;        // [max_group_batches][nshell] log10 U, log10 F norm
     // the paper's pair selection (SNK_SCREEN_LINK)
-    double* d_fmax = nullptr;       // [max_group_batches][nshell] max_i sqrt(w_i) |F_a,i|
+    double* d_fmax = nullptr;       // [max_group_batches][nshell] F-tilde of each shell per batch (sn-LinK)
+    double* d_Pabs = nullptr;       // [nbf][nbf] |P| of the current build (sn-LinK)
+    double* d_phimax = nullptr;     // [max_group_batches][link_ld] Phi-tilde per batch and tile row
+    double* d_FtT = nullptr;        // [max_group_batches][nbf] F-tilde per batch and function
+    int64_t link_ld = 0;
+    bool kept_capture = false;      // testing: record the screen's kept pairs of the next group
+    std::vector<int32_t> kept;      // (batch, A, B) triples
     double* d_phit = nullptr;       // [max_group_batches] max_i sqrt(w_i) sum_mu |Phi_mu,i|
     double* d_atil = nullptr;       // [npair_total] global estimate of max |A_ab|
 
@@ -240,7 +249,6 @@ struct snk_ctx {
     // sn-K and XC from one pass (snk_ctx_build_kxc): the XC point kernel and V product run on
     // each group's Phi and F right after its K product
     int kx_fn = 0;                      // functional while a combined build runs, else 0
-    double* d_kxG = nullptr;            // [nbf][max_cols] G = 2 Z of the group
     double* d_kxe = nullptr;            // [2][max_cols] w eps, w rho
     double* d_kxKt = nullptr;           // [nbf][nbf] unsymmetrised V
     double* d_kxred = nullptr;          // [512]
@@ -882,15 +890,29 @@ int setup_screening(snk_ctx* c)
         int rc = ensure_prims32(c);
         if (rc) return rc;
     }
+    // Diagonal entries: the same-shell pair (A, A) of every shell, with its primitive pairs
+    // folded by symmetry ((i, j) and (j, i) give the same integral: one record of twice the
+    // prefactor), centred exactly on R_A.
+    std::vector<PrimPair32> dp;
     for (int l = 0; l < 3; ++l) {
         std::vector<int32_t> sh, row, pb, np;
         for (int s = 0; s < c->nshell; ++s) {
             if (c->sl[s] != l) continue;
-            const PairHdr& h = c->pairs[pair_index(s, s)];
+            const double* RA = &c->scen[3 * s];
             sh.push_back(s);
             row.push_back(c->sfn[s]);
-            pb.push_back(h.prim_begin);
-            np.push_back(h.nprim);
+            pb.push_back((int32_t)dp.size());
+            for (int i = 0; i < c->snp[s]; ++i)
+                for (int j = i; j < c->snp[s]; ++j) {
+                    const double za = c->exps[c->spo[s] + i], zb = c->exps[c->spo[s] + j];
+                    const double zp = za + zb;
+                    const double pref = (i == j ? 1.0 : 2.0) * 2.0 * kPi / zp * c->coefs[c->spo[s] + i] *
+                                        c->coefs[c->spo[s] + j];
+                    if (std::fabs(pref) < 1e-30) continue;   // the pair table's cutoff at R_AB = 0
+                    dp.push_back(PrimPair32{(float)RA[0], (float)RA[1], (float)RA[2], (float)zp, (float)pref, 0.0f,
+                                            0.0f, 0.0f, (float)(0.5 / zp), 0.0f});
+                }
+            np.push_back((int32_t)dp.size() - pb.back());
         }
         c->n_diag[l] = (int32_t)sh.size();
         int rc;
@@ -898,6 +920,11 @@ int setup_screening(snk_ctx* c)
         if ((rc = upload(c, &c->d_diag_row[l], row))) return rc;
         if ((rc = upload(c, &c->d_diag_pb[l], pb))) return rc;
         if ((rc = upload(c, &c->d_diag_np[l], np))) return rc;
+    }
+    if (dp.empty()) dp.push_back(PrimPair32{});
+    {
+        int rc = upload(c, &c->d_dprims32, dp);
+        if (rc) return rc;
     }
     int rc;
     int32_t mb = 0;
@@ -913,6 +940,13 @@ int setup_screening(snk_ctx* c)
     }
     if (c->opts.screen == SNK_SCREEN_LINK) {
         if ((rc = dalloc(c, &c->d_fmax, (size_t)mb * c->nshell))) return rc;
+        int32_t maxB = 1;
+        for (const auto& g : c->groups)
+            for (const Tile& t : g.tiles) maxB = std::max(maxB, t.nB);
+        c->link_ld = (maxB + 3) & ~3;
+        if ((rc = dalloc(c, &c->d_Pabs, (size_t)c->nbf * c->nbf))) return rc;
+        if ((rc = dalloc(c, &c->d_phimax, (size_t)mb * c->link_ld))) return rc;
+        if ((rc = dalloc(c, &c->d_FtT, (size_t)mb * c->nbf))) return rc;
         if ((rc = dalloc(c, &c->d_phit, (size_t)mb))) return rc;
         // At_AB = sum over primitive pairs of |prefactor| max(1, |AB|)^(l_A + l_B)
         std::vector<double> at(c->npair_total, 0.0);
@@ -1032,7 +1066,7 @@ void free_ctx(snk_ctx* c)
     (void)hipFree(c->d_xsum);
     (void)hipFree(c->d_xtiles);
     (void)hipFree(c->d_xshells);
-    for (double* p : {c->d_kxG, c->d_kxe, c->d_kxKt, c->d_kxred, c->d_kxsum}) (void)hipFree(p);
+    for (double* p : {c->d_kxe, c->d_kxKt, c->d_kxred, c->d_kxsum}) (void)hipFree(p);
     (void)hipFree(c->d_kxtiles);
     (void)hipFree(c->d_kxshells);
     (void)hipFree(c->d_partial);
@@ -1047,12 +1081,18 @@ void free_ctx(snk_ctx* c)
         (void)hipFree(c->d_diag_row[l]);
         (void)hipFree(c->d_diag_pb[l]);
         (void)hipFree(c->d_diag_np[l]);
+        (void)hipFree(c->d_dlist[l]);
     }
+    (void)hipFree(c->d_dprims32);
+    (void)hipFree(c->d_dcount);
     (void)hipFree(c->d_shell_l);
     (void)hipFree(c->d_shell_row);
     (void)hipFree(c->d_U);
     (void)hipFree(c->d_lun);
     (void)hipFree(c->d_fmax);
+    (void)hipFree(c->d_Pabs);
+    (void)hipFree(c->d_phimax);
+    (void)hipFree(c->d_FtT);
     (void)hipFree(c->d_phit);
     (void)hipFree(c->d_atil);
     (void)hipFree(c->d_pfeat);
@@ -1836,13 +1876,139 @@ int group_K(snk_ctx* c, const Group& g)
 int group_bounds(snk_ctx* c, const Group& g)
 {
     const int64_t off = (int64_t)g.b0 * kBatch;
-    for (int l = 0; l < 3; ++l)
-        HIPCHECK(c, launch_diag_bound(l, c->d_px + off, c->d_py + off, c->d_pz + off, c->d_pw + off, c->d_F,
-                                      c->mixed ? c->d_F32 : nullptr, g.ncols,
-                                      c->d_prims32, c->d_diag_sh[l], c->d_diag_row[l], c->d_diag_pb[l],
-                                      c->d_diag_np[l], c->n_diag[l], c->d_U, c->d_lun, c->nshell, g.b1 - g.b0,
-                                      c->d_boys, c->frow_restrict ? c->d_fflag : nullptr, c->tile_batches,
-                                      c->d_fmax, c->stream));
+    const int nb = g.b1 - g.b0;
+    const int ntile = (int)g.tiles.size();
+    hipStream_t s = c->stream;
+    DiagArgs a{};
+    a.px = c->d_px + off;
+    a.py = c->d_py + off;
+    a.pz = c->d_pz + off;
+    a.pw = c->d_pw + off;
+    a.F = c->d_F;
+    a.F32 = c->mixed ? c->d_F32 : nullptr;
+    a.ld = g.ncols;
+    a.prims = c->d_dprims32;
+    a.U = c->d_U;
+    a.lun = c->d_lun;
+    a.fmax = nullptr;   // the sn-LinK F-tilde is formed from |P| and Phi-tilde instead
+    a.nshell = c->nshell;
+    a.nbatch = nb;
+    a.tab = c->d_boys;
+    a.tile_batches = c->tile_batches;
+    if (c->frow_restrict) {
+        // only the shells whose F rows a tile computed have F != 0 there: list them per tile,
+        // evaluate those, and give every other shell U = 0 (log features -40, as for U = 0)
+        if (!c->d_dcount) {
+            int rc;
+            for (int l = 0; l < 3; ++l)
+                if ((rc = dalloc(c, &c->d_dlist[l], (size_t)c->max_group_tiles * std::max(1, c->n_diag[l]))))
+                    return rc;
+            if ((rc = dalloc(c, &c->d_dcount, (size_t)3 * c->max_group_tiles))) return rc;
+        }
+        DiagLists d{};
+        for (int l = 0; l < 3; ++l) {
+            d.dsh[l] = c->d_diag_sh[l];
+            d.n[l] = c->n_diag[l];
+            d.list[l] = c->d_dlist[l];
+            d.count[l] = c->d_dcount + (int64_t)l * c->max_group_tiles;
+        }
+        HIPCHECK(c, launch_diag_lists(d, c->d_fflag, ntile, c->nshell, s));
+        HIPCHECK(c, launch_fill(c->d_U, (int64_t)nb * c->nshell, 0.0, s));
+        if (c->d_lun) HIPCHECK(c, launch_fill(reinterpret_cast<float*>(c->d_lun), (int64_t)2 * nb * c->nshell, -40.0f, s));
+    }
+    for (int l = 0; l < 3; ++l) {
+        a.dsh = c->d_diag_sh[l];
+        a.drow = c->d_diag_row[l];
+        a.dpb = c->d_diag_pb[l];
+        a.dnp = c->d_diag_np[l];
+        a.n = c->n_diag[l];
+        a.list = c->frow_restrict ? c->d_dlist[l] : nullptr;
+        a.count = c->frow_restrict ? c->d_dcount + (int64_t)l * c->max_group_tiles : nullptr;
+        HIPCHECK(c, launch_diag_bound(l, a, s));
+    }
+    return SNK_OK;
+}
+
+// Eq. exx_fmat_approx for every batch of group g: Phi-tilde per batch and tile row, then one
+// grouped product over the tiles, Ft[b][mu] = sum_{nu in B_t} Phi~[b][nu] |P|[nu][mu] with mu over
+// the whole basis, then F-tilde per shell (the largest over its functions) into d_fmax.
+// |P| (d_Pabs) is formed once per build.
+int link_ftilde(snk_ctx* c, const Group& g)
+{
+    hipStream_t s = c->stream;
+    const int64_t nbf = c->nbf;
+    const int nb = g.b1 - g.b0;
+    const int ntile = (int)g.tiles.size();
+    const int64_t off = (int64_t)g.b0 * kBatch;
+    HIPCHECK(c, launch_phimax(c->mixed ? nullptr : c->d_Phi, c->mixed ? c->d_Phi32 : nullptr, g.d_roff, ntile,
+                              c->tile_batches, g.tiles.back().ncols, c->d_pw + off, nb, c->d_phimax, c->link_ld, s));
+    std::vector<GemmProb> probs;
+    bool empty = false;
+    for (const Tile& t : g.tiles) {
+        if (t.nB == 0) {
+            empty = true;
+            continue;
+        }
+        GemmProb p{};
+        p.A = c->d_phimax + (int64_t)(t.b0 - g.b0) * c->link_ld;
+        p.lda = c->link_ld;
+        p.B = c->d_Pabs;
+        p.bmap = t.all_functions ? nullptr : t.d_coll_fn;
+        p.ldb = nbf;
+        p.C = c->d_FtT + (int64_t)(t.b0 - g.b0) * nbf;
+        p.ldc = nbf;
+        p.M = t.b1 - t.b0;
+        p.N = (int32_t)nbf;
+        p.K = t.nB;
+        p.ksplit = 1;
+        probs.push_back(p);
+    }
+    if (empty) HIPCHECK(c, launch_fill(c->d_FtT, (int64_t)nb * nbf, 0.0, s));   // tiles without functions
+    int rc = launch_gemm_list(c, probs, kGemmF64, false);
+    if (rc) return rc;
+    HIPCHECK(c, launch_shellmax(c->d_FtT, nbf, c->d_shell_l, c->d_shell_row, c->nshell, nb, c->d_fmax, s));
+    return SNK_OK;
+}
+
+// |P| for the sn-LinK estimates of this build
+int link_prepare(snk_ctx* c, const double* dP)
+{
+    if (c->opts.screen != SNK_SCREEN_LINK || !c->d_Pabs) return SNK_OK;
+    HIPCHECK(c, launch_abs(dP, c->nbf * c->nbf, c->d_Pabs, c->stream));
+    return SNK_OK;
+}
+
+// Testing: decodes the run and B-task records the screen wrote for group g into
+// (batch, A, B) triples of kept shell pairs (c->kept).
+int capture_kept(snk_ctx* c, const Group& g, const int64_t* total_runs, const std::vector<int64_t>& bt_base)
+{
+    const int nb = g.b1 - g.b0;
+    std::vector<int32_t> shell_of(c->nbf, -1);
+    for (int sh = 0; sh < c->nshell; ++sh) shell_of[c->sfn[sh]] = sh;
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    c->kept.clear();
+    for (int k = 0; k < c->nlist; ++k) {
+        const int TA = kListTile(k), RS = 2 + TA, BS = 2 + 2 * TA;
+        const int64_t nrun = total_runs[k], nbt = bt_base[(size_t)k * (nb + 1) + nb];
+        if (nrun == 0) continue;
+        std::vector<int32_t> runs((size_t)nrun * RS), bts((size_t)nbt * BS), bro(nb + 1);
+        HIPCHECK(c, hipMemcpy(runs.data(), c->d_pool_runs[k], runs.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+        HIPCHECK(c, hipMemcpy(bts.data(), c->d_pool_bt[k], bts.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+        HIPCHECK(c, hipMemcpy(bro.data(), c->d_bro[k], bro.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+        for (int j = 0; j < nb; ++j)
+            for (int32_t r = bro[j]; r < bro[j + 1]; ++r) {
+                const int32_t* rec = &runs[(size_t)r * RS];
+                for (int32_t q = rec[0]; q < rec[1]; ++q) {
+                    const int32_t* bt = &bts[(size_t)q * BS];
+                    for (int a = 0; a < TA; ++a)
+                        if (bt[1] & (1 << a)) {
+                            c->kept.push_back(g.b0 + j);
+                            c->kept.push_back(shell_of[rec[2 + a]]);
+                            c->kept.push_back(shell_of[bt[0]]);
+                        }
+                }
+            }
+    }
     return SNK_OK;
 }
 
@@ -1930,6 +2096,8 @@ int group_until_G(snk_ctx* c, const Group& g, const double* dP, bool timed, Grou
         if (link) {
             HIPCHECK(c, launch_phisum(c->mixed ? nullptr : c->d_Phi, c->mixed ? c->d_Phi32 : nullptr, g.d_roff, ntile,
                                       c->tile_batches, g.tiles.back().ncols, c->d_pw + off, nb, c->d_phit, s));
+            int rc = link_ftilde(c, g);
+            if (rc) return rc;
             sa.link = 1;
             sa.link_eps = c->opts.eps_skip_energy;
             sa.fmax = c->d_fmax;
@@ -1977,6 +2145,10 @@ int group_until_G(snk_ctx* c, const Group& g, const double* dP, bool timed, Grou
         }
         for (int j = 0; j < nb; ++j) gs->skipped += skipped[j];
         HIPCHECK(c, launch_screen(true, sa, s));
+        if (c->kept_capture) {
+            int rc = capture_kept(c, g, total_runs, bb);
+            if (rc) return rc;
+        }
         if (timed) HIPCHECK(c, hipEventRecord(c->ev[14], s));
     } else {
         for (int cl = 0; cl < 6; ++cl) {
@@ -2265,11 +2437,11 @@ int kx_workspace(snk_ctx* c)
     std::vector<int32_t> shells((size_t)c->nshell);
     std::iota(shells.begin(), shells.end(), 0);
     int rc = 0;
-    if ((rc = dalloc(c, &c->d_kxG, (size_t)(nbf * cols))) || (rc = dalloc(c, &c->d_kxe, (size_t)(2 * cols))) ||
+    if ((rc = dalloc(c, &c->d_kxe, (size_t)(2 * cols))) ||
         (rc = dalloc(c, &c->d_kxKt, (size_t)(nbf * nbf))) || (rc = dalloc(c, &c->d_kxred, 512)) ||
         (rc = upload(c, &c->d_kxtiles, tiles)) || (rc = upload(c, &c->d_kxshells, shells)) ||
         (rc = dalloc(c, &c->d_kxsum, 3))) {
-        for (double** p : {&c->d_kxG, &c->d_kxe, &c->d_kxKt, &c->d_kxred, &c->d_kxsum}) {
+        for (double** p : {&c->d_kxe, &c->d_kxKt, &c->d_kxred, &c->d_kxsum}) {
             (void)hipFree(*p);
             *p = nullptr;
         }
@@ -2315,7 +2487,8 @@ int xc_vproduct(snk_ctx* c, const double* G, const double* Phi, int64_t ncols, i
 
 // Combined build, group gi: the XC point kernel on the group's Phi and F (Eqs. den_grid,
 // exc_grid, zmat) and Kt_xc += G_xc Phi^T (Eq. vxc_num), on the context's stream after the
-// group's K product, before the next group reuses Phi and F.
+// group's K product, before the next group reuses Phi and F.  G_xc = 2 Z takes the place of
+// the exchange G, which the K product has consumed by then.
 int group_kx(snk_ctx* c, size_t gi)
 {
     hipStream_t s = c->stream;
@@ -2324,9 +2497,9 @@ int group_kx(snk_ctx* c, size_t gi)
     const double* Phi = c->d_Phi + g.tiles[0].phi_off;
     HIPCHECK(c, launch_xc_point(c->d_px + off, c->d_py + off, c->d_pz + off, c->d_pw + off, ncols, c->d_shells,
                                 c->d_exps, c->d_coefs, c->d_kxtiles + gi, c->d_kxshells, (int32_t)(ncols / kBatch),
-                                c->d_F, c->kx_fn, c->d_kxG, c->d_kxe, s));
+                                c->d_F, c->kx_fn, c->d_G, c->d_kxe, s));
     HIPCHECK(c, launch_xc_sum(c->d_kxe, ncols, c->d_kxred, c->d_kxsum, true, s));
-    return xc_vproduct(c, c->d_kxG, Phi, ncols, std::min<int>(c->kx_nsplit, (int)(ncols / kBatch)), c->d_kxKt);
+    return xc_vproduct(c, c->d_G, Phi, ncols, std::min<int>(c->kx_nsplit, (int)(ncols / kBatch)), c->d_kxKt);
 }
 
 }  // namespace
@@ -2490,6 +2663,10 @@ int snk_ctx_build(snk_ctx* c, const double* P, double* K_out, snk_stats* stats)
         HIPCHECK(c, launch_fill(c->d_kxsum, 3, 0.0, s));
     }
     if (c->mixed) HIPCHECK(c, launch_convert_f32(dP, (int64_t)nb2, c->d_P32, s));
+    {
+        int rc = link_prepare(c, dP);
+        if (rc) return rc;
+    }
     if (c->mlp)
         HIPCHECK(c, launch_pair_pnorm(dP, nbf, c->d_ne_list, c->d_pa, c->d_pb, c->d_shell_l, c->d_shell_row,
                                       (int64_t)c->ne_list.size(), c->d_lp, s));
@@ -2600,6 +2777,7 @@ int snk_ctx_build(snk_ctx* c, const double* P, double* K_out, snk_stats* stats)
 int sn_k_build(const snk_basis* basis, const snk_grid* grid, const double* weights, const double* P, double* K_out,
                const snk_opts* opts)
 {
+    if (!P || !K_out) return arg_error(nullptr, "P or K_out is NULL");
     snk_ctx* c = nullptr;
     int rc = snk_ctx_create(basis, grid, weights, opts, &c);
     if (rc) return rc;
@@ -2697,7 +2875,9 @@ int snk_ctx_debug_intermediates(snk_ctx* c, const double* P, double* Phi, double
     HIPCHECK(c, hipSetDevice(c->device));
     HIPCHECK(c, hipMemcpyAsync(c->d_P, P, (size_t)nbf * nbf * sizeof(double), hipMemcpyHostToDevice, c->stream));
     GroupStats gs;
-    int rc = group_until_G(c, g, c->d_P, false, &gs);
+    int rc = link_prepare(c, c->d_P);
+    if (rc) return rc;
+    rc = group_until_G(c, g, c->d_P, false, &gs);
     if (rc) return rc;
     const size_t n = (size_t)nbf * g.ncols * sizeof(double);
     std::vector<double> phig(Phi ? (size_t)g.phi_elems : 0);
@@ -2785,6 +2965,7 @@ int snk_ctx_block_data(snk_ctx* c, const double* P, float* features, double* blo
     HIPCHECK(c, launch_pair_pnorm(dP, nbf, c->d_ne_list, c->d_pa, c->d_pb, c->d_shell_l, c->d_shell_row,
                                   (int64_t)c->ne_list.size(), c->d_lp, s));
     if (c->mixed) HIPCHECK(c, launch_convert_f32(dP, nbf * nbf, c->d_P32, s));
+    if ((rc = link_prepare(c, dP))) return rc;
     for (const Group& g : c->groups) {
         if ((rc = group_F(c, g, dP, false))) return rc;
         if ((rc = group_bounds(c, g))) return rc;
@@ -2860,6 +3041,7 @@ int snk_ctx_debug_learned(snk_ctx* c, const double* P, float* yraw, float* est, 
     HIPCHECK(c, launch_pair_pnorm(c->d_P, nbf, c->d_ne_list, c->d_pa, c->d_pb, c->d_shell_l, c->d_shell_row,
                                   (int64_t)c->ne_list.size(), c->d_lp, s));
     if (c->mixed) HIPCHECK(c, launch_convert_f32(c->d_P, nbf * nbf, c->d_P32, s));
+    if ((rc = link_prepare(c, c->d_P))) return rc;
     GroupStats gs;
     rc = group_until_G(c, g, c->d_P, false, &gs, d_y);
     if (!rc) {
@@ -2877,6 +3059,40 @@ int snk_ctx_debug_learned(snk_ctx* c, const double* P, float* yraw, float* est, 
     (void)hipFree(d_y);
     if (!rc && nbatch_out) *nbatch_out = nb;
     return rc;
+}
+
+int snk_ctx_debug_kept(snk_ctx* c, const double* P, int32_t* out, int64_t cap, int64_t* n_out)
+{
+    if (!c || !P || !n_out) return arg_error(c, "NULL argument");
+    if (c->opts.screen == SNK_SCREEN_NONE) return arg_error(c, "context has no density screen");
+    if (c->opts.flags & SNK_DEVICE_PTRS) return arg_error(c, "host-pointer contexts only");
+    *n_out = 0;
+    if (c->groups.empty()) return SNK_OK;
+    const int64_t nbf = c->nbf;
+    HIPCHECK(c, hipSetDevice(c->device));
+    int rc = setup_screening(c);
+    if (rc) return rc;
+    hipStream_t s = c->stream;
+    HIPCHECK(c, hipMemcpyAsync(c->d_P, P, (size_t)nbf * nbf * sizeof(double), hipMemcpyHostToDevice, s));
+    if (c->mixed) HIPCHECK(c, launch_convert_f32(c->d_P, nbf * nbf, c->d_P32, s));
+    if (c->mlp)
+        HIPCHECK(c, launch_pair_pnorm(c->d_P, nbf, c->d_ne_list, c->d_pa, c->d_pb, c->d_shell_l, c->d_shell_row,
+                                      (int64_t)c->ne_list.size(), c->d_lp, s));
+    if ((rc = link_prepare(c, c->d_P))) return rc;
+    c->d_P_cur = c->d_P;
+    GroupStats gs;
+    c->kept_capture = true;
+    rc = group_until_G(c, c->groups[0], c->d_P, false, &gs);
+    c->kept_capture = false;
+    if (rc) return rc;
+    HIPCHECK(c, hipStreamSynchronize(s));
+    const int64_t n = (int64_t)c->kept.size() / 3;
+    *n_out = n;
+    if (out) {
+        if (cap < n) return arg_error(c, "output holds fewer triples than the screen kept");
+        std::copy(c->kept.begin(), c->kept.end(), out);
+    }
+    return SNK_OK;
 }
 
 int64_t snk_ctx_npair_index(const snk_ctx* c) { return c ? c->npair_total : 0; }

@@ -227,14 +227,50 @@ hipError_t launch_mlp_grad(const float* params, const MlpNorm& nrm, const float*
 // out[k] = log10(in[k]) for in[k] > 1e-40, else -40
 hipError_t launch_log10(const double* in, int64_t n, float* out, hipStream_t s);
 hipError_t launch_mlp_adam(float* params, float* m, float* v, const float* g, float lr, int t, hipStream_t s);
-hipError_t launch_diag_bound(int l, const double* px, const double* py, const double* pz, const double* pw,
-                             const double* F, const float* F32, int64_t ld, const PrimPair32* prims, const int32_t* dsh,
-                             const int32_t* drow, const int32_t* dpb, const int32_t* dnp, int32_t n, double* U,
-                             float2* lun, int32_t nshell, int32_t nbatch, const double* tab, const int32_t* tflag,
-                             int32_t tile_batches, double* fmax, hipStream_t s);
+// U_A (and its log features) of the shells of one angular momentum for the batches of one
+// group: one workgroup per batch, lane = point.
+struct DiagArgs {
+    const double *px, *py, *pz, *pw;   // the group's points
+    const double* F;                   // F of the group (ld columns), or
+    const float* F32;                  // its FP32 copy
+    int64_t ld;
+    const PrimPair32* prims;           // folded same-centre primitive pairs of the diagonal entries
+    const int32_t* dsh;                // [n] shell of each diagonal entry
+    const int32_t* drow;               // [n] its first basis function
+    const int32_t* dpb;                // [n] first primitive-pair record
+    const int32_t* dnp;                // [n] number of records
+    int32_t n;
+    const int32_t* list;               // [ntile][n] per tile, the entries whose shell the tile flags, or nullptr: all
+    const int32_t* count;              // [ntile] list lengths
+    int32_t tile_batches;
+    double* U;                         // [nbatch][nshell]
+    float2* lun;                       // [nbatch][nshell] (log10 U, log10 |F_A|), or nullptr
+    double* fmax;                      // [nbatch][nshell] max_i sqrt(w_i) |F_A,i|, or nullptr
+    int32_t nshell;
+    int32_t nbatch;
+    const double* tab;                 // Boys table
+};
+hipError_t launch_diag_bound(int l, const DiagArgs& a, hipStream_t s);
+// Per tile and angular momentum l: list[l][t][..] = the diagonal entries k (ascending) with
+// flag[t][dsh[l][k]] != 0, count[l][t] their number.
+struct DiagLists {
+    const int32_t* dsh[3];
+    int32_t n[3];
+    int32_t* list[3];    // [ntile][n[l]]
+    int32_t* count[3];   // [ntile]
+};
+hipError_t launch_diag_lists(const DiagLists& d, const int32_t* flag, int32_t ntile, int32_t nshell, hipStream_t s);
 // phit[b] = max over the points of batch b of sqrt(w_i) sum_mu |Phi_mu,i| for the batches of one
 // group: batch b lies in tile t = b / tile_batches, whose Phi_t has rows roff[t]..roff[t+1]-1
 // (tiles before the last have tile_batches * 256 columns, the last ncols_last)
+// out[b][k] = max over the points i of batch b of sqrt(w_i) |Phi_k,i| for the rows k of the
+// batch's tile (tiles and Phi layout as for launch_phisum), row stride ld
+hipError_t launch_phimax(const double* Phi, const float* Phi32, const int32_t* roff, int32_t ntile,
+                         int32_t tile_batches, int64_t ncols_last, const double* pw, int32_t nbatch, double* out,
+                         int64_t ld, hipStream_t s);
+// fs[b][A] = max over the functions mu of shell A of Ft[b][mu] (row stride ldf)
+hipError_t launch_shellmax(const double* Ft, int64_t ldf, const int32_t* shell_l, const int32_t* shell_row,
+                           int32_t nshell, int32_t nbatch, double* fs, hipStream_t s);
 hipError_t launch_phisum(const double* Phi, const float* Phi32, const int32_t* roff, int32_t ntile,
                          int32_t tile_batches, int64_t ncols_last, const double* pw, int32_t nbatch, double* phit,
                          hipStream_t s);
@@ -372,6 +408,8 @@ hipError_t launch_rinv(const int32_t* lists, int64_t stride, const int32_t* roff
                        int64_t nbf, int64_t max_count, int32_t* rinv, hipStream_t s);
 hipError_t launch_convert_f32(const double* in, int64_t n, float* out, hipStream_t s);
 hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t s);
+// out[k] = |in[k]|
+hipError_t launch_abs(const double* in, int64_t n, double* out, hipStream_t s);
 hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t s);
 hipError_t launch_fill(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 // p[r * ld + c] = v for r < rows, c < cols

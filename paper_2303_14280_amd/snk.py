@@ -157,6 +157,8 @@ def lib():
             L.snk_ctx_npair_index.restype = ctypes.c_int64
             L.snk_ctx_debug_learned.argtypes = [ctypes.c_void_p] * 5 + [ctypes.POINTER(ctypes.c_int64)]
             L.snk_ctx_debug_learned.restype = ctypes.c_int
+            L.snk_ctx_debug_kept.argtypes = [ctypes.c_void_p] * 3 + [ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
+            L.snk_ctx_debug_kept.restype = ctypes.c_int
             L.snk_debug_mfma_bf16.argtypes = [ctypes.c_void_p] * 3 + [ctypes.c_int]
             L.snk_debug_mfma_bf16.restype = ctypes.c_int
             _F = ctypes.POINTER(ctypes.c_float)
@@ -431,6 +433,16 @@ class Context:
                                            ctypes.byref(n)), self.handle)
         k = n.value
         return y[:k * npi].reshape(k, npi), e[:k * npi].reshape(k, npi), t[:k]
+
+    def debug_kept(self, P: np.ndarray) -> np.ndarray:
+        """(batch, A, B) of every shell pair the density screen keeps in the first batch group."""
+        P = np.ascontiguousarray(P, np.float64)
+        n = ctypes.c_int64(0)
+        _check(lib().snk_ctx_debug_kept(self.handle, P.ctypes.data, None, 0, ctypes.byref(n)), self.handle)
+        out = np.zeros((max(1, n.value), 3), np.int32)
+        _check(lib().snk_ctx_debug_kept(self.handle, P.ctypes.data, out.ctypes.data, n.value, ctypes.byref(n)),
+               self.handle)
+        return out[:n.value]
 
     def close(self):
         if getattr(self, "handle", None):

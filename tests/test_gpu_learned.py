@@ -148,6 +148,60 @@ def test_block_data_matches_oracle_integrals():
     assert np.max(np.abs(t2.cpu().numpy().reshape(nb, nk) - ref)) <= 1e-5
 
 
+def test_bound_features_with_basis_screen():
+    """With eps_basis > 0 the diagonal bounds are evaluated only for the shells whose F rows a
+    tile computed.  Two copies of a small molecule 40 bohr apart with a molecule-local density:
+    the tiles of one copy compute no F rows of the other.  For every batch of the first group,
+    U_A and |F_A| (features 12-14) from the F the device used and the oracle's diagonal
+    integrals; shells without F rows on the tile have U = 0 and log features -40."""
+    xyz = [[0.0, 0.0, 0.0], [1.3, 0.4, -0.2], [-0.5, 1.1, 0.7]]
+    xyz = xyz + [[x + 40.0, y, z] for x, y, z in xyz]
+    shells = [
+        [(0, [2.1, 0.6], [0.5, 0.6]), (1, [1.4, 0.45], [0.7, 0.4]), (2, [0.9], [1.0])],
+        [(0, [1.7, 0.5], [0.4, 0.7]), (1, [0.8], [1.0])],
+        [(0, [1.1], [1.0]), (2, [1.3, 0.5], [0.5, 0.5]), (1, [30.0, 3.0, 0.3], [0.3, 0.5, 0.4])],
+    ]
+    s = synth.make_custom([8, 1, 1, 8, 1, 1], xyz, shells + shells, grid=(24, 38), n_occ=6)
+    offs = s.shell_offsets()
+    half = int(offs[sum(len(x) for x in shells)])
+    P = s.P.copy()
+    P[:half, half:] = 0.0
+    P[half:, :half] = 0.0
+    s = s.with_density(P)
+    ctx = snk.Context(s, screen=snk.SNK_SCREEN_BOUND, eps_basis=1e-6)
+    shells_k, feat, _ = _block_data(s, ctx)
+    _, F, _ = ctx.debug_intermediates(s.P)
+    order = ctx.point_order()
+    nb0 = F.shape[1] // 256
+    U = np.zeros((nb0, s.nshell))
+    N = np.zeros((nb0, s.nshell))
+    for b in range(nb0):
+        pts = order[b * 256:(b + 1) * 256]
+        for q, i in enumerate(pts):
+            if i < 0:
+                continue
+            d = np.sqrt(np.maximum(np.diag(O.a3c(s, s.grid_xyz[i])), 0.0))
+            f = F[:, b * 256 + q]
+            for sh in range(s.nshell):
+                sl = slice(offs[sh], offs[sh + 1])
+                U[b, sh] += s.grid_w[i] * np.sum(np.abs(f[sl]) * d[sl]) ** 2
+                N[b, sh] += s.grid_w[i] * np.sum((cnorm(s.shell_l[sh]) * f[sl]) ** 2)
+    U, N = 1.01 * np.sqrt(U), np.sqrt(N)
+    say("first group: %d batches, %d tiles, %d of %d (batch, shell) entries without F rows" %
+        (nb0, sum(1 for t in ctx.tiles() if t[0] == 0), int(np.sum(U == 0)), U.size))
+    assert np.any(U == 0) and np.any(U > 0)
+
+    def lg(v):
+        return np.where(v > 1e-40, np.log10(np.maximum(v, 1e-300)), -40.0)
+
+    for b in range(nb0):
+        for k, (A, B) in enumerate(shells_k):
+            cab = 0.5 if A == B else 1.0
+            ref = np.array([lg(N[b, A]), lg(N[b, B]), max(lg(cab * U[b, A] * U[b, B]), -40.0)])
+            got = feat[b, k, 12:15]
+            assert np.all(np.abs(got - ref) <= 2e-4 + 2e-5 * np.abs(ref)), (b, A, B, got, ref)
+
+
 def _random_network(seed, mean, std):
     m = snk.Mlp(0)
     p = mlp_ref.init_params(seed)

@@ -175,14 +175,17 @@ def test_xc_ignores_sn_k_modes_and_leaves_k_unchanged():
 
 
 @pytest.mark.parametrize("kw", [dict(), dict(screen=snk.SNK_SCREEN_LINK, eps_skip_energy=1e-9),
-                                dict(eps_basis=1e-9)])
+                                dict(eps_basis=1e-9), dict(max_device_bytes=40 * 290 * 256 * 24)])
 def test_combined_build_matches_separate_calls(kw):
     """snk_ctx_build_kxc (Phi and F shared between sn-K and XC where the context allows it) gives
     the K of snk_ctx_build bitwise and the V^xc of snk_vxc_build to rounding order; V^xc
-    also against the XC oracle."""
+    also against the XC oracle.  The last case splits the grid into several batch groups, whose
+    XC contributions accumulate across groups."""
     s = synth.make_system(2)
     s = s.subset_points(np.arange(1, s.npts, 9))
     ctx = snk.Context(s, **kw)
+    if "max_device_bytes" in kw:
+        assert ctx.ngroups > 1
     K0, st0 = ctx.build(s.P)
     V0, e0, n0 = ctx.vxc(s.P, snk.SNK_XC_PBE)
     K1, V1, e1, n1, st1 = ctx.build_kxc(s.P, snk.SNK_XC_PBE)
