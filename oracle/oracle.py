@@ -56,6 +56,10 @@ def lib():
             L.orc_snk.restype = ctypes.c_int
             L.orc_snk_rows.argtypes = basis + [ctypes.c_long, _D, _D, _D, _I, ctypes.c_int, _D, ctypes.c_int]
             L.orc_snk_rows.restype = ctypes.c_int
+            L.orc_eri_j.argtypes = basis + [_D, _D, ctypes.c_int]
+            L.orc_eri_j.restype = ctypes.c_int
+            L.orc_df_tensors.argtypes = basis + [ctypes.c_int, ctypes.c_int, _D, _D, ctypes.c_int]
+            L.orc_df_tensors.restype = ctypes.c_int
             L.orc_eri_shells.argtypes = basis + [ctypes.c_int] * 4 + [_D]
             L.orc_eri_shells.restype = None
             L.orc_eri_k.argtypes = basis + [_D, _D, ctypes.c_int]
@@ -169,6 +173,16 @@ def eri_k(s, P=None, nthreads: int = 0) -> np.ndarray:
     K = np.zeros((b.nbf, b.nbf))
     lib().orc_eri_k(*b.args(), _dp(P), _dp(K), int(nthreads))
     return K
+
+
+def eri_j(s, P=None, nthreads: int = 0) -> np.ndarray:
+    """Coulomb matrix J_{mu nu} = sum (mu nu | lam kap) P_{lam kap} from all four-centre integrals."""
+    b = _Basis(s)
+    P = np.ascontiguousarray(s.P if P is None else P, np.float64)
+    J = np.zeros((b.nbf, b.nbf))
+    if lib().orc_eri_j(*b.args(), _dp(P), _dp(J), int(nthreads)) != 0:
+        raise MemoryError("oracle J failed")
+    return J
 
 
 def exchange_energy(P: np.ndarray, K: np.ndarray) -> float:

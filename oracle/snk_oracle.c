@@ -721,3 +721,131 @@ int orc_eri_k(int nshell, const double* center, const int* l, const int* nprim, 
     free(off);
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* density-fitting tensors (Sec. II.B, Eqs. V_df, P_df, J_df)               */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Three- and two-centre Coulomb integrals of the density-fitting approximation over one
+ * combined shell list: shells [0, norb) are the orbital basis, shells [norb, norb + naux)
+ * the auxiliary basis, and shell norb + naux must be an s function of exponent 0 and
+ * coefficient 1 (the constant function 1), so that by the definitions
+ *   (mu nu | K) = (mu nu | K 1)   and   (K | L) = (K 1 | L 1)
+ * both come from the four-centre routine above.  Outputs (row-major, overwritten):
+ *   T[(mu * nbf + nu) * nauxf + K] = (mu nu | K)     nbf x nbf x nauxf
+ *   V[K * nauxf + L]                = (K | L)          nauxf x nauxf
+ * Returns 0 on success, -1 if the last shell is not the constant function.
+ */
+int orc_df_tensors(int nshell, const double* center, const int* l, const int* nprim, const int* prim_off,
+                   const double* exps, const double* coefs, int norb, int naux, double* T, double* V,
+                   int nthreads)
+{
+    const int one = norb + naux;
+    if (one != nshell - 1 || l[one] != 0 || nprim[one] != 1 || exps[prim_off[one]] != 0.0 ||
+        coefs[prim_off[one]] != 1.0)
+        return -1;
+    int* off = (int*)malloc(sizeof(int) * (size_t)(nshell + 1));
+    shell_offsets(nshell, l, off);
+    const int nbf = off[norb], nauxf = off[norb + naux] - off[norb];
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+    /* the auxiliary functions paired with the constant */
+    shell_pair* kp = (shell_pair*)malloc(sizeof(shell_pair) * (size_t)(naux > 0 ? naux : 1));
+    for (int k = 0; k < naux; ++k)
+        make_shell_pair(&kp[k], norb + k, one, center, l, nprim, prim_off, exps, coefs);
+    const int npair = norb * (norb + 1) / 2;
+#pragma omp parallel
+    {
+        double* blk = (double*)malloc(sizeof(double) * 1296);
+#pragma omp for schedule(dynamic, 1)
+        for (int p = 0; p < npair; ++p) {
+            int a = 0;
+            while ((a + 1) * (a + 2) / 2 <= p) ++a;
+            const int b = p - a * (a + 1) / 2;
+            shell_pair ab;
+            make_shell_pair(&ab, a, b, center, l, nprim, prim_off, exps, coefs);
+            const int na = ncart(l[a]), nb = ncart(l[b]);
+            for (int k = 0; k < naux; ++k) {
+                const int nk = ncart(l[norb + k]), k0 = off[norb + k] - nbf;
+                eri_block(&ab, &kp[k], blk);
+                for (int ia = 0; ia < na; ++ia)
+                    for (int ib = 0; ib < nb; ++ib)
+                        for (int ik = 0; ik < nk; ++ik) {
+                            const double v = blk[(ia * nb + ib) * nk + ik];
+                            T[((size_t)(off[a] + ia) * nbf + off[b] + ib) * nauxf + k0 + ik] = v;
+                            T[((size_t)(off[b] + ib) * nbf + off[a] + ia) * nauxf + k0 + ik] = v;
+                        }
+            }
+            free(ab.pp);
+        }
+#pragma omp for schedule(dynamic, 1)
+        for (int k = 0; k < naux; ++k) {
+            const int nk = ncart(l[norb + k]), k0 = off[norb + k] - nbf;
+            for (int m = 0; m < naux; ++m) {
+                const int nm = ncart(l[norb + m]), m0 = off[norb + m] - nbf;
+                eri_block(&kp[k], &kp[m], blk);
+                for (int ik = 0; ik < nk; ++ik)
+                    for (int im = 0; im < nm; ++im) V[(size_t)(k0 + ik) * nauxf + m0 + im] = blk[ik * nm + im];
+            }
+        }
+        free(blk);
+    }
+    for (int k = 0; k < naux; ++k) free(kp[k].pp);
+    free(kp);
+    free(off);
+    return 0;
+}
+
+/* J_{mu nu} = sum_{lam kap} (mu nu | lam kap) P_{lam kap}, all quartets, no screening. */
+int orc_eri_j(int nshell, const double* center, const int* l, const int* nprim, const int* prim_off,
+              const double* exps, const double* coefs, const double* P, double* J, int nthreads)
+{
+    const int nbf = orc_nbf(nshell, l);
+    int* off = (int*)malloc(sizeof(int) * (size_t)(nshell + 1));
+    shell_offsets(nshell, l, off);
+    shell_pair* sps = (shell_pair*)malloc(sizeof(shell_pair) * (size_t)nshell * nshell);
+    for (int a = 0; a < nshell; ++a)
+        for (int b = 0; b < nshell; ++b)
+            make_shell_pair(&sps[a * nshell + b], a, b, center, l, nprim, prim_off, exps, coefs);
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+    /* each (a, b) shell block of J is owned by one iteration */
+#pragma omp parallel
+    {
+        double* blk = (double*)malloc(sizeof(double) * 1296);
+#pragma omp for schedule(dynamic, 1) collapse(2)
+        for (int a = 0; a < nshell; ++a) {
+            for (int b = 0; b < nshell; ++b) {
+                const int na = ncart(l[a]), nb = ncart(l[b]);
+                double acc[36];
+                for (int k = 0; k < 36; ++k) acc[k] = 0.0;
+                for (int c = 0; c < nshell; ++c) {
+                    for (int d = 0; d < nshell; ++d) {
+                        const int nc = ncart(l[c]), nd = ncart(l[d]);
+                        eri_block(&sps[a * nshell + b], &sps[c * nshell + d], blk);
+                        for (int ia = 0; ia < na; ++ia)
+                            for (int ib = 0; ib < nb; ++ib)
+                                for (int ic = 0; ic < nc; ++ic)
+                                    for (int id = 0; id < nd; ++id)
+                                        acc[ia * nb + ib] += blk[((ia * nb + ib) * nc + ic) * nd + id] *
+                                                             P[(size_t)(off[c] + ic) * nbf + off[d] + id];
+                    }
+                }
+                for (int ia = 0; ia < na; ++ia)
+                    for (int ib = 0; ib < nb; ++ib) J[(size_t)(off[a] + ia) * nbf + off[b] + ib] = acc[ia * nb + ib];
+            }
+        }
+        free(blk);
+    }
+    for (int k = 0; k < nshell * nshell; ++k) free(sps[k].pp);
+    free(sps);
+    free(off);
+    return 0;
+}

@@ -531,3 +531,52 @@ def random_symmetric(n: int, seed: int) -> np.ndarray:
     rng = np.random.default_rng([9000 + seed])
     X = rng.normal(size=(n, n))
     return 0.5 * (X + X.T)
+
+
+# ----------------------------------------------------------------------------------------------
+# auxiliary (density-fitting) basis
+# ----------------------------------------------------------------------------------------------
+
+# one-primitive auxiliary shells per element: even-tempered exponents (l, first, ratio, count)
+# spanning the products of the orbital exponents (0.1 .. 5000), jittered per seed
+_AUX_SETS = {
+    Z_O: [(0, 0.2, 3.0, 10), (1, 0.3, 3.5, 5), (2, 0.4, 4.0, 3)],
+    Z_H: [(0, 0.2, 3.5, 8), (1, 0.3, 4.0, 3)],
+}
+
+
+@dataclasses.dataclass
+class AuxBasis:
+    """Auxiliary (density-fitting) basis in the same SoA layout as the orbital basis."""
+    shell_center: np.ndarray
+    shell_l: np.ndarray
+    shell_nprim: np.ndarray
+    shell_prim_off: np.ndarray
+    shell_atom: np.ndarray
+    exps: np.ndarray
+    coefs: np.ndarray
+
+    @property
+    def nshell(self) -> int:
+        return int(self.shell_l.shape[0])
+
+    @property
+    def nfunc(self) -> int:
+        return int(sum(ncart(int(l)) for l in self.shell_l))
+
+
+def make_aux_basis(s: "System", seed: int = 0) -> AuxBasis:
+    """A seeded even-tempered auxiliary basis on the atoms of `s`: one-primitive s, p, d shells
+    per element (O: 10s5p3d, H: 8s3p), exponents first * ratio^k, each scaled by a factor drawn
+    log-uniformly from [0.85, 1.15] per element and seed, normalised like the orbital shells."""
+    rng = np.random.default_rng([7000 + seed])
+    per_element = {}
+    for Z in (Z_O, Z_H):
+        shells = []
+        for (l, first, ratio, count) in _AUX_SETS[Z]:
+            for k in range(count):
+                e = np.array([first * ratio ** k * math.exp(rng.uniform(math.log(0.85), math.log(1.15)))])
+                shells.append((l, e, _normalised_coefs(l, e, np.ones(1))))
+        per_element[Z] = shells
+    cen, ls, npr, off, sat, ex, co = assemble_basis(s.atom_Z, s.atom_xyz, per_element)
+    return AuxBasis(cen, ls, npr, off, sat, ex, co)
