@@ -99,17 +99,15 @@ def dominant_kernel(st):
     for k in range(4):
         if st["t_gemm_ms"][k] <= 0:
             continue
-        cands.append((st["t_gemm_ms"][k], "ggemm_kernel (%s)" % GEMM_KINDS[k], None, max(1, st["gemm_launches"][k]),
-                      "mfma", flops.PEAK_FP32_MFMA_TFLOPS if k in (1, 3) else flops.PEAK_FP64_MFMA_TFLOPS))
+        f64, f32 = st["gemm_kind_flops"][k]
+        # a product with parts on both kinds of matrix cores is priced at its combined peak: the
+        # flops over the time the two parts take at their own peaks
+        ideal_s = f64 / (flops.PEAK_FP64_MFMA_TFLOPS * 1e12) + f32 / (flops.PEAK_FP32_MFMA_TFLOPS * 1e12)
+        peak = (f64 + f32) / ideal_s / 1e12 if ideal_s > 0 else flops.PEAK_FP64_MFMA_TFLOPS
+        cands.append((st["t_gemm_ms"][k], "%s (%s)" % ("gsplit_kernel" if f64 > 0 and f32 > 0 else "ggemm_kernel",
+                                                       GEMM_KINDS[k]),
+                      f64 + f32, max(1, st["gemm_launches"][k]), "mfma", peak))
     t, name, work, launches, bound, peak = max(cands, key=lambda x: x[0])
-    if work is None:
-        # the library reports the flops of the two products per precision; split them by the
-        # kinds' shares of the same precision's time
-        kidx = [k for k in range(4) if name.endswith(GEMM_KINDS[k] + ")")][0]
-        same = (0, 2) if kidx in (0, 2) else (1, 3)
-        tot = st["gemm_flops_fp64"] if kidx in (0, 2) else st["gemm_flops_fp32"]
-        tsum = sum(st["t_gemm_ms"][k] for k in same)
-        work = tot * (st["t_gemm_ms"][kidx] / tsum if tsum > 0 else 1.0)
     launch_ms = t / launches
     achieved = work / launches / (launch_ms * 1e-3) / 1e12
     return {"bound": bound, "kernel": name, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
@@ -234,6 +232,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the config 3 and config 2 comparisons")
     ap.add_argument("--eps", type=float, default=5e-6,
                     help="estimate budget (Eh) of the learned screen's skipped blocks and of the FP32 blocks")
+    ap.add_argument("--profile", action="store_true",
+                    help="only time the headline build (config 5, mixed + learned), for profiler runs; no JSON")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -262,6 +262,16 @@ def main():
     stream = torch.cuda.Stream(device=dev)          # default priority
     torch.cuda.set_stream(stream)
 
+    if args.profile:
+        from paper_2303_14280_amd import synth
+        s = synth.make_system(5)
+        P = torch.tensor(s.P, dtype=torch.float64, device="cuda")
+        mlp = snk.load_screener(device=0)
+        r, _, _ = run_variant("config 5 mixed+learned", s, P, stream, mlp, args.steps, args.warmup,
+                              eps_basis=EPS_BASIS, screen=snk.SNK_SCREEN_LEARNED, precision=snk.SNK_MIXED,
+                              eps_skip_energy=args.eps, eps_lowprec_energy=args.eps)
+        log("profile run: %.1f ms/step, phases %s" % (r["ms_per_step"], r["phases_ms"]))
+        return
     h = headline(args, stream)
     s = h["system"]
     m = h["mixed+learned"]

@@ -145,6 +145,9 @@ typedef struct snk_stats {
     double t_gemm_ms[4];         /* GPU time (HIP events) of the grouped dense-product launches: F on
                                     the FP64 / FP32 matrix cores, K~ on the FP64 / FP32 matrix cores */
     int64_t gemm_launches[4];    /* ... and the number of such timed launch sequences (one per group) */
+    double gemm_kind_flops[4][2];/* flops of each of those four kinds on the FP64 [0] and FP32 [1] matrix
+                                    cores (the fused split product of SNK_MIXED counts as "F on FP32"
+                                    and has both parts) */
 } snk_stats;
 
 typedef struct snk_mlp snk_mlp;

@@ -18,7 +18,7 @@ OUT = os.path.join(PKG, "libsnk.so")
 BUILD_DIR = os.path.join(PKG, "_build")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
-SOURCES = ["snk_host.cpp", "snk_mlp.cpp", "k_afg.hip", "k_collocate.hip", "k_ggemm.hip", "k_linalg.hip", "k_screen.hip", "k_mlp.hip", "k_mlp_noalloc.hip", "k_learn.hip", "k_xc.hip"]
+SOURCES = ["snk_host.cpp", "snk_mlp.cpp", "snk_dfj.cpp", "k_dfj.hip", "k_afg.hip", "k_collocate.hip", "k_ggemm.hip", "k_linalg.hip", "k_screen.hip", "k_mlp.hip", "k_mlp_noalloc.hip", "k_learn.hip", "k_xc.hip"]
 
 ARCH = os.environ.get("SNK_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -25,7 +25,13 @@
 namespace snk {
 namespace {
 
+// k extent of one staged operand step
 constexpr int GBK = 16, GPAD = 4;
+template <typename TS>
+constexpr int gbk()
+{
+    return GBK;
+}
 
 template <int MODE>
 struct GTraits;
@@ -85,11 +91,11 @@ struct Operands {
     bool avec, bvec;
 };
 
-// Double-buffered LDS staging of BM x GBK (A, k-major) and GBK x BN (B) operand tiles.
+// Double-buffered LDS staging of BM x BK (A, k-major) and BK x BN (B) operand tiles.
 template <typename TS, int WB>
 struct Stage {
-    TS A[2][GBK][32 * WB + GPAD];
-    TS B[2][GBK][32 * WB + GPAD];
+    TS A[2][gbk<TS>()][32 * WB + GPAD];
+    TS B[2][gbk<TS>()][32 * WB + GPAD];
 };
 
 template <typename TS>
@@ -110,9 +116,10 @@ __device__ inline void mainloop(Stage<TS, WB>& L, const Operands<TA, TB>& op, in
                                 typename GTraits<sizeof(TS) == 4 ? 1 : 0>::acc4 (&acc)[WB][WB])
 {
     constexpr int BM = 32 * WB, BN = 32 * WB;
-    constexpr int E = BM * GBK / 256;   // operand elements each thread stages per k step
-    constexpr int TPR = GBK / E;        // threads per k-contiguous run of 16
-    const int nk = kend > kbeg ? (int)((kend - kbeg + GBK - 1) / GBK) : 0;
+    constexpr int BK = gbk<TS>();
+    constexpr int E = BM * BK / 256;    // operand elements each thread stages per k step
+    constexpr int TPR = BK / E;         // threads per k-contiguous run of BK
+    const int nk = kend > kbeg ? (int)((kend - kbeg + BK - 1) / BK) : 0;
     const GP<const int32_t> acol = glb(op.acol);
     const GP<const int32_t> bmap = glb(op.bmap);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -212,9 +219,9 @@ __device__ inline void mainloop(Stage<TS, WB>& L, const Operands<TA, TB>& op, in
     __syncthreads();
     for (int it = 0; it < nk; ++it) {
         const int cur = it & 1;
-        if (it + 1 < nk) load(kbeg + (int64_t)(it + 1) * GBK);
+        if (it + 1 < nk) load(kbeg + (int64_t)(it + 1) * BK);
 #pragma unroll
-        for (int ks = 0; ks < GBK; ks += 4) {
+        for (int ks = 0; ks < BK; ks += 4) {
             TS a[WB], b[WB];
 #pragma unroll
             for (int bi = 0; bi < WB; ++bi) a[bi] = L.A[cur][ks + lk][wm + bi * 16 + li];
@@ -315,9 +322,10 @@ __global__ __launch_bounds__(256, 2) void ggemm_kernel(const GemmProb* __restric
 }
 
 // Split product (one chunk, B row-major): C = A B over the strong k (FP64 operands, FP64 matrix
-// cores) plus A2 B2 over the weak k (FP32 operands, FP32 matrix cores, K2 <= kFp32MaxK), the
-// FP32 sums added to the FP64 ones through LDS (the two accumulator layouts differ) and C
-// written once.
+// cores) plus A2 B2 over the weak k (FP32 operands, FP32 matrix cores, K2 <= kFp32MaxK), C
+// written once.  The weak sums come first: their FP32 accumulators go through LDS into the
+// FP64 layout (the two accumulator layouts differ) as the starting values of the FP64 sums, so
+// only one accumulator set is live at a time and the 128 x 128 tile fits in registers.
 template <int WB>
 __global__ __launch_bounds__(256, 2) void gsplit_kernel(const GemmProb* __restrict__ probs, int nprob, int64_t nwg)
 {
@@ -329,50 +337,47 @@ __global__ __launch_bounds__(256, 2) void gsplit_kernel(const GemmProb* __restri
     int z;
     int64_t m0, n0;
     if (!locate<WB>(probs, nprob, nwg, pr, z, m0, n0)) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm = (wave >> 1) * (BM / 2), wn = (wave & 1) * (BN / 2);
+    const int li = lane & 15, lk = lane >> 4;
+    static_assert(sizeof(Stage<double, WB>) >= sizeof(float) * BM * (BN + 1), "LDS for the transpose");
+    float* T = reinterpret_cast<float*>(&L);
+    {
+        acc32 acw[WB][WB];
+#pragma unroll
+        for (int bi = 0; bi < WB; ++bi)
+#pragma unroll
+            for (int bj2 = 0; bj2 < WB; ++bj2) acw[bi][bj2] = acc32{0, 0, 0, 0};
+        Stage<float, WB>& Lf = *reinterpret_cast<Stage<float, WB>*>(&L);
+        Operands<float, float> op{glb(static_cast<const float*>(pr.A2)), pr.arow, nullptr, pr.lda2,
+                                  glb(static_cast<const float*>(pr.B2)), nullptr, pr.ldb2, (pr.vec & 8) != 0,
+                                  (pr.vec & 16) != 0};
+        mainloop<float, float, float, false, WB>(Lf, op, pr.M, pr.N, m0, n0, 0, pr.K2, acw);
+        // FP32 blocks to LDS in (row, column) order (the main loop ends with a barrier)
+#pragma unroll
+        for (int bi = 0; bi < WB; ++bi)
+#pragma unroll
+            for (int bj2 = 0; bj2 < WB; ++bj2)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    T[(wm + bi * 16 + 4 * lk + r) * (BN + 1) + wn + bj2 * 16 + li] = acw[bi][bj2][r];
+    }
+    __syncthreads();
     acc64 acc[WB][WB];
 #pragma unroll
     for (int bi = 0; bi < WB; ++bi)
 #pragma unroll
-        for (int bj2 = 0; bj2 < WB; ++bj2) acc[bi][bj2] = acc64{0, 0, 0, 0};
+        for (int bj2 = 0; bj2 < WB; ++bj2)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                acc[bi][bj2][r] = (double)T[(wm + bi * 16 + 4 * r + lk) * (BN + 1) + wn + bj2 * 16 + li];
+    __syncthreads();   // the FP64 main loop restages operands in the same LDS
     {
         Operands<double, double> op{glb(static_cast<const double*>(pr.A)), pr.arow, pr.acol, pr.lda,
                                     glb(static_cast<const double*>(pr.B)), pr.bmap, pr.ldb, (pr.vec & 1) != 0,
                                     (pr.vec & 2) != 0};
         mainloop<double, double, double, false, WB>(L, op, pr.M, pr.N, m0, n0, 0, pr.K, acc);
     }
-    acc32 acw[WB][WB];
-#pragma unroll
-    for (int bi = 0; bi < WB; ++bi)
-#pragma unroll
-        for (int bj2 = 0; bj2 < WB; ++bj2) acw[bi][bj2] = acc32{0, 0, 0, 0};
-    Stage<float, WB>& Lf = *reinterpret_cast<Stage<float, WB>*>(&L);
-    {
-        Operands<float, float> op{glb(static_cast<const float*>(pr.A2)), pr.arow, nullptr, pr.lda2,
-                                  glb(static_cast<const float*>(pr.B2)), nullptr, pr.ldb2, (pr.vec & 8) != 0,
-                                  (pr.vec & 16) != 0};
-        mainloop<float, float, float, false, WB>(Lf, op, pr.M, pr.N, m0, n0, 0, pr.K2, acw);
-    }
-    // FP32 blocks to LDS in (row, column) order, read back in the FP64 layout
-    static_assert(sizeof(Stage<double, WB>) >= sizeof(float) * BM * (BN + 1), "LDS for the transpose");
-    float* T = reinterpret_cast<float*>(&L);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int wm = (wave >> 1) * (BM / 2), wn = (wave & 1) * (BN / 2);
-    const int li = lane & 15, lk = lane >> 4;
-#pragma unroll
-    for (int bi = 0; bi < WB; ++bi)
-#pragma unroll
-        for (int bj2 = 0; bj2 < WB; ++bj2)
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-                T[(wm + bi * 16 + 4 * lk + r) * (BN + 1) + wn + bj2 * 16 + li] = acw[bi][bj2][r];
-    __syncthreads();
-#pragma unroll
-    for (int bi = 0; bi < WB; ++bi)
-#pragma unroll
-        for (int bj2 = 0; bj2 < WB; ++bj2)
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-                acc[bi][bj2][r] += (double)T[(wm + bi * 16 + 4 * r + lk) * (BN + 1) + wn + bj2 * 16 + li];
     write_tile<double, 0, WB>(pr, z, m0, n0, acc);
 }
 

@@ -62,8 +62,8 @@ __device__ __forceinline__ void sfor(Fn&& f)
 template <typename R>
 constexpr int boys_terms() { return std::is_same<R, double>::value ? kBoysTerms : 7; }
 
-// TC: columns per row of the table in memory (the full kBoysCols, or a prefix of at least
-// L + boys_terms<R>() columns)
+// TC: columns per row of the table in memory (kBoysCols for the tables of the 3c-CP kernels,
+// more for higher orders, or a prefix of at least L + boys_terms<R>() columns)
 template <int L, typename R, int TC = kBoysCols>
 __device__ __forceinline__ void boys(R T, const R* __restrict__ tab, R (&F)[L + 1])
 {
@@ -71,7 +71,7 @@ __device__ __forceinline__ void boys(R T, const R* __restrict__ tab, R (&F)[L + 
     if (T < (R)kBoysTmax) {
         const int k = (int)(T * (R)(1.0 / kBoysStep) + (R)0.5);
         const R d = (R)k * (R)kBoysStep - T;
-        static_assert(TC >= L + NT && TC <= kBoysCols, "Boys table too narrow");
+        static_assert(TC >= L + NT, "Boys table too narrow");
         const R* row = tab + k * TC;
         R pw[NT];
         pw[0] = (R)1;

@@ -157,6 +157,7 @@ struct snk_ctx {
     std::vector<int32_t> tile_nstrong;  // strong rows per tile of the current group
     double* d_lpb = nullptr;            // [max_group_tiles * kBoundChunksPerTile + 1] bound partials, then the sum
     double acc_flops64 = 0, acc_flops32 = 0;   // dense-product flops per precision of a build
+    double slot_flops[4][2] = {};              // ... per timed launch kind (F64/F32 parts)
     const double* d_P_cur = nullptr;    // density of the build in progress (device)
     // P[L_t, B_t] of every tile of a group, gathered once per build (grown on demand)
     void* d_Pc = nullptr;
@@ -316,24 +317,7 @@ void gauss_legendre(int n, std::vector<long double>& x, std::vector<long double>
     }
 }
 
-std::vector<double> make_boys_table()
-{
-    std::vector<long double> gx, gw;
-    gauss_legendre(160, gx, gw);
-    std::vector<double> tab((size_t)kBoysRows * kBoysCols);
-    for (int k = 0; k < kBoysRows; ++k) {
-        const long double T = (long double)k * kBoysStep;
-        for (int m = 0; m < kBoysCols; ++m) {
-            long double s = 0.0L;
-            for (size_t q = 0; q < gx.size(); ++q) {
-                const long double y = 0.5L * (gx[q] + 1.0L);
-                s += gw[q] * powl(y, 2 * m) * expl(-T * y * y);
-            }
-            tab[(size_t)k * kBoysCols + m] = (double)(0.5L * s);
-        }
-    }
-    return tab;
-}
+std::vector<double> make_boys_table() { return snk::boys_table_cols(kBoysCols); }
 
 const std::vector<double>& boys_table()
 {
@@ -1500,9 +1484,15 @@ int launch_gemm_list(snk_ctx* c, std::vector<GemmProb>& probs, GemmKind kind, bo
     if (probs.empty()) return SNK_OK;
     int64_t nwg = 0;
     const int asz = kind == kGemmF32 ? 4 : 8, bsz = (kind == kGemmF64 || kind == kGemmF32dd || kind == kGemmSplit) ? 8 : 4;
-    // split products run on 64 x 64 tiles (the 128 x 128 form holds both accumulator sets only
-    // with spills)
-    const int tile = kind == kGemmSplit ? 64 : ggemm_tile(probs.data(), (int)probs.size());
+    int tile;
+    if (kind == kGemmSplit) {
+        // split products: the tile for the whole sum over both precisions
+        std::vector<GemmProb> full(probs);
+        for (auto& p : full) p.K += p.K2;
+        tile = ggemm_tile(full.data(), (int)full.size());
+    } else {
+        tile = ggemm_tile(probs.data(), (int)probs.size());
+    }
     for (auto& p : probs) {
         ggemm_plan(p, tile, asz, bsz);
         p.wg0 = nwg;
@@ -1753,16 +1743,22 @@ int group_fgemm(snk_ctx* c, const Group& g, const double* dP)
         p.N = (int32_t)t.ncols;
         p.K = ns;
         p.ksplit = 1;
-        c->acc_flops64 += 2.0 * (double)L * (double)t.ncols * (double)ns;
+        const double f_strong = 2.0 * (double)L * (double)t.ncols * (double)ns;
         if (ns < t.nB) {
             p.A2 = (const char*)c->d_Pw + pw_off[ti] * sizeof(float);
             p.lda2 = (t.nB - ns + 3) & ~3;
             p.B2 = (const char*)c->d_Phw + phw_off[ti] * sizeof(float);
             p.ldb2 = t.ncols;
             p.K2 = t.nB - ns;
-            c->acc_flops32 += 2.0 * (double)L * (double)t.ncols * (double)(t.nB - ns);
+            const double f_weak = 2.0 * (double)L * (double)t.ncols * (double)(t.nB - ns);
+            c->acc_flops64 += f_strong;
+            c->acc_flops32 += f_weak;
+            c->slot_flops[1][0] += f_strong;
+            c->slot_flops[1][1] += f_weak;
             split.push_back(p);
         } else {
+            (c->mixed ? c->acc_flops32 : c->acc_flops64) += f_strong;
+            c->slot_flops[c->mixed ? 1 : 0][c->mixed ? 1 : 0] += f_strong;
             probs.push_back(p);
         }
     }
@@ -1831,7 +1827,8 @@ int group_K(snk_ctx* c, const Group& g)
         p.K = (int32_t)t.ncols;
         p.ksplit = ks[ti];
         if (ns > 0) probs.push_back(p);
-        c->acc_flops64 += 2.0 * (double)M * (double)ns * (double)t.ncols;
+        (c->mixed ? c->acc_flops32 : c->acc_flops64) += 2.0 * (double)M * (double)ns * (double)t.ncols;
+        c->slot_flops[c->mixed ? 3 : 2][c->mixed ? 1 : 0] += 2.0 * (double)M * (double)ns * (double)t.ncols;
         if (ns < t.nB) {
             // the weak rows of Phi_t as the F product left them in FP32 (rows in weak order)
             GemmProb q = p;
@@ -1841,6 +1838,7 @@ int group_K(snk_ctx* c, const Group& g)
             q.N = t.nB - ns;
             weak.push_back(q);
             c->acc_flops32 += 2.0 * (double)M * (double)(t.nB - ns) * (double)t.ncols;
+            c->slot_flops[3][1] += 2.0 * (double)M * (double)(t.nB - ns) * (double)t.ncols;
         }
         RedTile r{};
         r.poff = poff;
@@ -2657,6 +2655,7 @@ int snk_ctx_build(snk_ctx* c, const double* P, double* K_out, snk_stats* stats)
     HIPCHECK(c, launch_fill(c->d_Kt, (int64_t)nb2, 0.0, s));
     c->d_P_cur = dP;
     c->acc_flops64 = c->acc_flops32 = 0.0;
+    for (auto& f : c->slot_flops) f[0] = f[1] = 0.0;
     if (c->split) HIPCHECK(c, launch_fill(c->d_lpb + (int64_t)c->max_group_tiles * kBoundChunksPerTile, 1, 0.0, s));
     if (c->kx_fn) {
         HIPCHECK(c, launch_fill(c->d_kxKt, (int64_t)nb2, 0.0, s));
@@ -2763,6 +2762,8 @@ int snk_ctx_build(snk_ctx* c, const double* P, double* K_out, snk_stats* stats)
         for (int k = 0; k < 4; ++k) {
             stats->t_gemm_ms[k] = c->gms[k];
             stats->gemm_launches[k] = c->gcount[k];
+            stats->gemm_kind_flops[k][0] = c->slot_flops[k][0];
+            stats->gemm_kind_flops[k][1] = c->slot_flops[k][1];
         }
         if (c->split) {
             double sum = 0.0;
@@ -3146,4 +3147,25 @@ int snk_boys_device(const double* T, int64_t n, int mmax, double* F_out, void* s
 namespace snk {
 // error text of a context-free call (snk_last_error(NULL)), for entry points in other files
 void set_last_error(const char* msg) { g_last_error = msg ? msg : ""; }
+
+// F_m(T_k), T_k = k kBoysStep (k < kBoysRows), m < cols, by Gauss-Legendre quadrature of the
+// defining integral (Eq. boys) in long double; row-major
+std::vector<double> boys_table_cols(int cols)
+{
+    std::vector<long double> gx, gw;
+    gauss_legendre(160, gx, gw);
+    std::vector<double> tab((size_t)kBoysRows * cols);
+    for (int k = 0; k < kBoysRows; ++k) {
+        const long double T = (long double)k * kBoysStep;
+        for (int m = 0; m < cols; ++m) {
+            long double s = 0.0L;
+            for (size_t q = 0; q < gx.size(); ++q) {
+                const long double y = 0.5L * (gx[q] + 1.0L);
+                s += gw[q] * powl(y, 2 * m) * expl(-T * y * y);
+            }
+            tab[(size_t)k * cols + m] = (double)(0.5L * s);
+        }
+    }
+    return tab;
+}
 }  // namespace snk

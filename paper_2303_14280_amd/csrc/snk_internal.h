@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 #include <cstdint>
+#include <vector>
 
 namespace snk {
 
@@ -407,6 +408,51 @@ hipError_t launch_group_reduce(const double* part, const RedTile* tiles, int nti
 hipError_t launch_rinv(const int32_t* lists, int64_t stride, const int32_t* roff, const int32_t* counts, int ntile,
                        int64_t nbf, int64_t max_count, int32_t* rinv, hipStream_t s);
 hipError_t launch_convert_f32(const double* in, int64_t n, float* out, hipStream_t s);
+// Density-fitted Coulomb matrix (Sec. II.B): records and launchers of the J-engine kernels.
+constexpr int kDfjBoysCols = 6 + kBoysTerms;   // F_m up to m = 2 + 2 + 2 with the Taylor terms
+constexpr int kDfjHerm = 35;                   // Hermite components up to l_a + l_b = 4
+constexpr int kDfjAuxHerm = 10;                // ... up to l_c = 2
+constexpr int kDfjCart = 36;                   // Cartesian pair components up to (d, d)
+// one orbital primitive pair (shells oriented l_A >= l_B)
+struct DfjPrim {
+    double Px, Py, Pz;     // product centre
+    double za, zb;         // exponents
+    double ABx, ABy, ABz;  // R_A - R_B
+    double cc;             // c_a c_b, doubled for A != B (both orders of the pair in the density sum)
+    double cc1;            // c_a c_b
+    int32_t fa, fb;        // first basis functions of A and B
+};
+// one orbital shell pair: its primitive pairs are records pbeg .. pbeg + np - 1
+struct DfjShellPair {
+    int32_t fa, fb, la, lb, pbeg, np;
+};
+// one auxiliary shell (one primitive)
+struct DfjAux {
+    double x, y, z, z_exp, coef;
+    int32_t l, f0;
+};
+hipError_t launch_dfj_hdens(int cls, const DfjPrim* pp, int32_t n, const double* P, int64_t nbf, double* Dh,
+                            hipStream_t s);
+hipError_t launch_dfj_vaux(int LP, int LC, const DfjPrim* pp, const double* Dh, int32_t pbeg, int32_t pend,
+                           int32_t chunk, int32_t slot0, const DfjAux* aux, int32_t abeg, int32_t aend, int32_t nslot,
+                           const double* tab, double* part, hipStream_t s);
+hipError_t launch_dfj_vfinish(const DfjAux* aux, int32_t naux, const double* part, int32_t nslot, double* v,
+                              hipStream_t s);
+hipError_t launch_dfj_auxdens(const DfjAux* aux, int32_t naux, const double* d, double* Dc, hipStream_t s);
+hipError_t launch_dfj_jpair(int cls, const DfjPrim* pp, int32_t n, const DfjAux* aux, const double* Dc,
+                            const int32_t* lbeg, const double* tab, double* Jpp, hipStream_t s);
+hipError_t launch_dfj_jcollect(const DfjShellPair* sp, int32_t nsp, const double* Jpp, double* J, int64_t nbf,
+                               hipStream_t s);
+hipError_t launch_dfj_metric(const DfjAux* aux, int32_t naux, const double* tab, double* V, int64_t n, hipStream_t s);
+// in place: the lower triangle of A becomes L (A = L L^T); U = L^T; status set to 1 when A is
+// not positive definite
+hipError_t launch_dfj_cholesky(double* A, int64_t n, double* U, int32_t* status, hipStream_t s);
+hipError_t launch_dfj_solve(const double* L, const double* U, int64_t n, const double* v, double* y, double* d,
+                            hipStream_t s);
+hipError_t launch_dfj_dot(const double* a, const double* b, int64_t n, double* out, hipStream_t s);
+
+// Boys table F_m(T_k), k < kBoysRows, m < cols (host, long-double quadrature)
+std::vector<double> boys_table_cols(int cols);
 hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t s);
 // out[k] = |in[k]|
 hipError_t launch_abs(const double* in, int64_t n, double* out, hipStream_t s);

@@ -51,12 +51,13 @@ class SnkStats(ctypes.Structure):
                 ("tile_functions", ctypes.c_double), ("tile_frows", ctypes.c_double), ("tile_grows", ctypes.c_double),
                 ("gemm_flops_fp64", ctypes.c_double), ("gemm_flops_fp32", ctypes.c_double),
                 ("lowprec_bound", ctypes.c_double), ("t_gemm_ms", ctypes.c_double * 4),
-                ("gemm_launches", ctypes.c_int64 * 4)]
+                ("gemm_launches", ctypes.c_int64 * 4), ("gemm_kind_flops", (ctypes.c_double * 2) * 4)]
 
     def as_dict(self) -> dict:
         d = {k: getattr(self, k) for k, _ in self._fields_}
         for k in ("pair_points", "prim_pair_points", "t_afg_class_ms", "t_gemm_ms", "gemm_launches"):
             d[k] = list(d[k])
+        d["gemm_kind_flops"] = [list(r) for r in self.gemm_kind_flops]
         return d
 
 
@@ -157,6 +158,17 @@ def lib():
             L.snk_ctx_npair_index.restype = ctypes.c_int64
             L.snk_ctx_debug_learned.argtypes = [ctypes.c_void_p] * 5 + [ctypes.POINTER(ctypes.c_int64)]
             L.snk_ctx_debug_learned.restype = ctypes.c_int
+            L.snk_dfj_create.argtypes = [ctypes.POINTER(SnkBasis), ctypes.POINTER(SnkBasis), ctypes.c_int,
+                                         ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]
+            L.snk_dfj_create.restype = ctypes.c_int
+            L.snk_dfj_build.argtypes = [ctypes.c_void_p] * 6 + [ctypes.c_uint32]
+            L.snk_dfj_build.restype = ctypes.c_int
+            L.snk_dfj_naux.argtypes = [ctypes.c_void_p]
+            L.snk_dfj_naux.restype = ctypes.c_int64
+            L.snk_dfj_last_error.argtypes = [ctypes.c_void_p]
+            L.snk_dfj_last_error.restype = ctypes.c_char_p
+            L.snk_dfj_destroy.argtypes = [ctypes.c_void_p]
+            L.snk_dfj_destroy.restype = None
             L.snk_ctx_debug_kept.argtypes = [ctypes.c_void_p] * 3 + [ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
             L.snk_ctx_debug_kept.restype = ctypes.c_int
             L.snk_debug_mfma_bf16.argtypes = [ctypes.c_void_p] * 3 + [ctypes.c_int]
@@ -232,6 +244,76 @@ class _Marshal:
                               self.exps.ctypes.data_as(_D), self.coefs.ctypes.data_as(_D))
         self.grid = SnkGrid(int(self.w.shape[0]), self.xyz.ctypes.data_as(_D),
                             self.atom.ctypes.data_as(_I32) if self.atom is not None else None)
+
+
+class _BasisOnly:
+    """Contiguous copies of one basis (orbital or auxiliary shell arrays) for a call."""
+
+    def __init__(self, b):
+        self.center = np.ascontiguousarray(b.shell_center, np.float64).reshape(-1)
+        self.l = np.ascontiguousarray(b.shell_l, np.int32)
+        self.nprim = np.ascontiguousarray(b.shell_nprim, np.int32)
+        self.prim_off = np.ascontiguousarray(b.shell_prim_off, np.int32)
+        self.exps = np.ascontiguousarray(b.exps, np.float64)
+        self.coefs = np.ascontiguousarray(b.coefs, np.float64)
+        self.basis = SnkBasis(int(self.l.shape[0]), self.center.ctypes.data_as(_D), self.l.ctypes.data_as(_I32),
+                              self.nprim.ctypes.data_as(_I32), self.prim_off.ctypes.data_as(_I32),
+                              self.exps.ctypes.data_as(_D), self.coefs.ctypes.data_as(_D))
+
+
+class DfJ:
+    """Density-fitted Coulomb matrix context (snk_dfj_*): orbital basis of `system`, auxiliary
+    basis `aux` (shell arrays as the orbital basis, one primitive per shell)."""
+
+    def __init__(self, system, aux, device: int = 0, stream: int = 0):
+        self.handle = None
+        b, a = _BasisOnly(system), _BasisOnly(aux)
+        h = ctypes.c_void_p()
+        rc = lib().snk_dfj_create(ctypes.byref(b.basis), ctypes.byref(a.basis), int(device),
+                                  ctypes.c_void_p(stream) if stream else None, ctypes.byref(h))
+        if rc != SNK_OK:
+            raise SnkError(rc, last_error(None))
+        self.handle = h
+        self.nbf = int(sum((int(x) + 1) * (int(x) + 2) // 2 for x in b.l))
+
+    @property
+    def naux(self) -> int:
+        return int(lib().snk_dfj_naux(self.handle))
+
+    def _check(self, rc):
+        if rc != SNK_OK:
+            raise SnkError(rc, lib().snk_dfj_last_error(self.handle).decode())
+
+    def build(self, P):
+        """(J, v, d, E_J) for a host density matrix."""
+        P = np.ascontiguousarray(P, np.float64)
+        J = np.zeros((self.nbf, self.nbf))
+        v = np.zeros(self.naux)
+        d = np.zeros(self.naux)
+        ej = ctypes.c_double(0.0)
+        self._check(lib().snk_dfj_build(self.handle, P.ctypes.data, J.ctypes.data, v.ctypes.data, d.ctypes.data,
+                                        ctypes.byref(ej), 0))
+        return J, v, d, ej.value
+
+    def build_device(self, P_ptr: int, J_ptr: int, v_ptr: int = 0, d_ptr: int = 0, energy: bool = False):
+        """Device-pointer build on the context's stream; returns E_J when energy is set."""
+        ej = ctypes.c_double(0.0)
+        self._check(lib().snk_dfj_build(self.handle, ctypes.c_void_p(P_ptr), ctypes.c_void_p(J_ptr),
+                                        ctypes.c_void_p(v_ptr) if v_ptr else None,
+                                        ctypes.c_void_p(d_ptr) if d_ptr else None,
+                                        ctypes.byref(ej) if energy else None, SNK_DEVICE_PTRS))
+        return ej.value if energy else None
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().snk_dfj_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def shell_rcut(l: int, exps, coefs, eps: float) -> float:

@@ -90,3 +90,18 @@ def test_null_pointers_rejected():
     assert L.snk_boys_device(None, 10, 7, None, None) == snk.SNK_E_ARG
     assert L.snk_vxc_build(None, None, snk.SNK_XC_LDA, None, None, None) == snk.SNK_E_ARG
     assert L.snk_ctx_build_kxc(None, None, None, snk.SNK_XC_LDA, None, None, None, None) == snk.SNK_E_ARG
+
+
+def test_dfj_validation_on_host():
+    """snk_dfj_create rejects invalid orbital or auxiliary shells before touching a device."""
+    import types
+    s = tiny()
+    aux = types.SimpleNamespace(shell_center=np.zeros((1, 3)), shell_l=np.zeros(1, np.int32),
+                                shell_nprim=np.array([2], np.int32), shell_prim_off=np.zeros(1, np.int32),
+                                exps=np.array([1.0, 0.5]), coefs=np.array([1.0, 1.0]))
+    _expect(snk.SNK_E_ARG, lambda: snk.DfJ(s, aux))
+    aux.shell_nprim[0] = 1
+    aux.exps[0] = -1.0
+    _expect(snk.SNK_E_ARG, lambda: snk.DfJ(s, aux))
+    L = snk.lib()
+    assert L.snk_dfj_naux(None) == 0
