@@ -204,6 +204,38 @@ def config3(args, stream):
     return res
 
 
+def dfj_config2(args, stream):
+    """The density-fitted Coulomb matrix (Sec. II.B) of config 2 with the seeded auxiliary basis:
+    set-up (metric and its Cholesky factor) once, then timed builds J[P]."""
+    import torch
+    from paper_2303_14280_amd import snk, synth
+    s = synth.make_system(2)
+    aux = synth.make_aux_basis(s)
+    t = time.perf_counter()
+    ctx = snk.DfJ(s, aux, stream=stream.cuda_stream)
+    t_create = time.perf_counter() - t
+    P = torch.tensor(s.P, dtype=torch.float64, device="cuda")
+    J = torch.empty_like(P)
+    for _ in range(args.warmup):
+        ctx.build_device(P.data_ptr(), J.data_ptr())
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        ctx.build_device(P.data_ptr(), J.data_ptr())
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = max(e0.elapsed_time(e1) / args.steps, 1000.0 * (time.perf_counter() - t0) / args.steps)
+    ej = ctx.build_device(P.data_ptr(), J.data_ptr(), energy=True)
+    ctx.close()
+    log("DF-J config 2: %d functions, %d auxiliary functions: %.2f ms/build (set-up %.2f s), E_J %.10f" %
+        (s.nbf, aux.nfunc, ms, t_create, ej))
+    return {"workload": "config2 density-fitted Coulomb matrix: %d functions, %d auxiliary functions "
+                        "(seeded even-tempered s/p/d set), FP64, no screening" % (s.nbf, aux.nfunc),
+            "ms_per_step": ms, "create_s": t_create, "e_j": ej}
+
+
 def config2(args, stream):
     """30-atom cluster: the plain FP64 build (the oracle-parity workload) and mixed + learned."""
     import torch
@@ -232,8 +264,10 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the config 3 and config 2 comparisons")
     ap.add_argument("--eps", type=float, default=5e-6,
                     help="estimate budget (Eh) of the learned screen's skipped blocks and of the FP32 blocks")
-    ap.add_argument("--profile", action="store_true",
-                    help="only time the headline build (config 5, mixed + learned), for profiler runs; no JSON")
+    ap.add_argument("--profile", choices=("config5", "config2", "dfj2"), default=None,
+                    help="only time one build for profiler runs (no JSON): config5 = the headline build "
+                         "(mixed + learned), config2 = the plain FP64 build of config 2, dfj2 = the "
+                         "density-fitted Coulomb build of config 2")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -264,12 +298,20 @@ def main():
 
     if args.profile:
         from paper_2303_14280_amd import synth
-        s = synth.make_system(5)
+        if args.profile == "dfj2":
+            r = dfj_config2(args, stream)
+            log("profile run: %.2f ms/step" % r["ms_per_step"])
+            return
+        cfg = 5 if args.profile == "config5" else 2
+        s = synth.make_system(cfg)
         P = torch.tensor(s.P, dtype=torch.float64, device="cuda")
         mlp = snk.load_screener(device=0)
-        r, _, _ = run_variant("config 5 mixed+learned", s, P, stream, mlp, args.steps, args.warmup,
-                              eps_basis=EPS_BASIS, screen=snk.SNK_SCREEN_LEARNED, precision=snk.SNK_MIXED,
-                              eps_skip_energy=args.eps, eps_lowprec_energy=args.eps)
+        if cfg == 5:
+            r, _, _ = run_variant("config 5 mixed+learned", s, P, stream, mlp, args.steps, args.warmup,
+                                  eps_basis=EPS_BASIS, screen=snk.SNK_SCREEN_LEARNED, precision=snk.SNK_MIXED,
+                                  eps_skip_energy=args.eps, eps_lowprec_energy=args.eps)
+        else:
+            r, _, _ = run_variant("config 2 fp64", s, P, stream, mlp, args.steps, args.warmup)
         log("profile run: %.1f ms/step, phases %s" % (r["ms_per_step"], r["phases_ms"]))
         return
     h = headline(args, stream)
@@ -313,6 +355,7 @@ def main():
     if not args.no_extras:
         out["config3"] = config3(args, stream)
         out["config2"] = config2(args, stream)
+        out["dfj_config2"] = dfj_config2(args, stream)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(s, ints / s.npts)

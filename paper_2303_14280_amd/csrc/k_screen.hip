@@ -404,16 +404,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void s
                 d.aa = act[sh.aoff[la] + ai];
                 d.b = act[sh.aoff[lb] + bi];
                 d.p = pair_index(d.aa, d.b);
-                const int32_t pos = a.ne_pos[d.p];
-                ok = pos >= 0;
-                k = ok ? pos : 0;
+                // the bound's test first (LDS only): the pair's records are gathered only for
+                // the candidates it leaves
+                ok = bins[d.aa] != kNoBin && bins[d.b] != kNoBin && bins[d.aa] + bins[d.b] >= S;
+                if (ok) {
+                    const int32_t pos = a.ne_pos[d.p];
+                    ok = pos >= 0;
+                    k = ok ? pos : 0;
+                }
             }
         }
         d.valid = ok && bins[d.aa] != kNoBin && bins[d.b] != kNoBin && bins[d.aa] + bins[d.b] >= S;
-        d.pf = a.ne_feat[k];
-        d.lp = a.ne_lp[k];
-        d.ua = Lb[d.aa];
-        d.ub = Lb[d.b];
+        if (d.valid) {
+            d.pf = a.ne_feat[k];
+            d.lp = a.ne_lp[k];
+            d.ua = Lb[d.aa];
+            d.ub = Lb[d.b];
+        } else {
+            d.pf = PairFeat{};
+            d.lp = 0.0f;
+            d.ua = d.ub = make_float2(0.0f, 0.0f);
+        }
     };
 
     Cand cur, nxt;

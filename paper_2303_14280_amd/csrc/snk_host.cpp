@@ -1383,6 +1383,8 @@ struct GroupStats {
 };
 
 int group_fgemm(snk_ctx* c, const Group& g, const double* dP);
+template <typename T>
+int push_vector(snk_ctx* c, std::vector<T>& v, const T** dptr);
 
 // Steps of one batch group up to G: Eq. collocation, Eq. fmat, the screen (when enabled),
 // Eqs. 3c_grid + gmat.
@@ -1392,17 +1394,33 @@ int group_F(snk_ctx* c, const Group& g, const double* dP, bool timed)
     hipStream_t s = c->stream;
     const int64_t nbf = c->nbf;
     if (timed) HIPCHECK(c, hipEventRecord(c->ev[0], s));
-    // Eq. collocation for every tile: Phi_t (nB x ncols_t, row stride ncols_t)
-    for (const Tile& t : g.tiles) {
-        const int64_t off = (int64_t)t.b0 * kBatch;
-        if (c->mixed)
-            HIPCHECK(c, launch_collocate(c->d_px + off, c->d_py + off, c->d_pz + off, t.ncols, c->d_shells, c->d_exps,
-                                         c->d_coefs, t.d_coll_shells, t.d_coll_rows, (int32_t)t.coll_shells.size(),
-                                         c->d_Phi32 + t.phi_off, t.ncols, s));
-        else
-            HIPCHECK(c, launch_collocate(c->d_px + off, c->d_py + off, c->d_pz + off, t.ncols, c->d_shells, c->d_exps,
-                                         c->d_coefs, t.d_coll_shells, t.d_coll_rows, (int32_t)t.coll_shells.size(),
-                                         c->d_Phi + t.phi_off, t.ncols, s));
+    // Eq. collocation for every tile in one launch: Phi_t (nB x ncols_t, row stride ncols_t)
+    {
+        std::vector<CollTile> ct;
+        for (const Tile& t : g.tiles) {
+            if (t.coll_shells.empty()) continue;
+            CollTile r{};
+            r.col0 = t.col0;
+            r.ncols = t.ncols;
+            r.phi_off = t.phi_off;
+            r.shells = t.d_coll_shells;
+            r.rows = t.d_coll_rows;
+            r.nsh = (int32_t)t.coll_shells.size();
+            ct.push_back(r);
+        }
+        const int64_t nwg = collocate_tiles_plan(ct.data(), (int32_t)ct.size());
+        if (!ct.empty()) {
+            const CollTile* d = nullptr;
+            int rc = push_vector(c, ct, &d);
+            if (rc) return rc;
+            const int64_t off = (int64_t)g.b0 * kBatch;
+            if (c->mixed)
+                HIPCHECK(c, launch_collocate_tiles(c->d_px + off, c->d_py + off, c->d_pz + off, c->d_shells, c->d_exps,
+                                                   c->d_coefs, d, (int32_t)ct.size(), nwg, c->d_Phi32, s));
+            else
+                HIPCHECK(c, launch_collocate_tiles(c->d_px + off, c->d_py + off, c->d_pz + off, c->d_shells, c->d_exps,
+                                                   c->d_coefs, d, (int32_t)ct.size(), nwg, c->d_Phi, s));
+        }
     }
     if (timed) HIPCHECK(c, hipEventRecord(c->ev[1], s));
     const int ntile = (int)g.tiles.size();

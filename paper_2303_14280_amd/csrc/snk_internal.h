@@ -300,6 +300,23 @@ hipError_t launch_mfma_bf16_k32_probe(const float* A, const float* B, float* D, 
 hipError_t launch_screen_scan(const int32_t* counts, int32_t nbatch, int32_t nlist, int64_t* run_base,
                               int64_t* bt_base, hipStream_t s);
 hipError_t launch_afg(int la, int lb, const AfgArgs& a, hipStream_t s);
+// One tile of a grouped collocation launch (Eq. collocation): columns col0 .. col0 + ncols - 1
+// of the group's points, shells[k] written to rows rows[k].. of Phi_t (nB x ncols at phi_off)
+struct CollTile {
+    int64_t col0, ncols, phi_off;
+    const int32_t* shells;
+    const int32_t* rows;
+    int32_t nsh, ncb;     // shells; column blocks (set by collocate_tiles_plan)
+    int64_t wg0;          // first workgroup (set by collocate_tiles_plan)
+};
+// fills ncb and wg0 of every tile in order; returns the workgroups of the launch
+int64_t collocate_tiles_plan(CollTile* tiles, int32_t ntile);
+hipError_t launch_collocate_tiles(const double* px, const double* py, const double* pz, const ShellDev* shells,
+                                  const double* exps, const double* coefs, const CollTile* tiles, int32_t ntile,
+                                  int64_t nwg, double* Phi, hipStream_t s);
+hipError_t launch_collocate_tiles(const double* px, const double* py, const double* pz, const ShellDev* shells,
+                                  const double* exps, const double* coefs, const CollTile* tiles, int32_t ntile,
+                                  int64_t nwg, float* Phi, hipStream_t s);
 hipError_t launch_collocate(const double* px, const double* py, const double* pz, int64_t ncols,
                             const ShellDev* shells, const double* exps, const double* coefs,
                             const int32_t* shell_list, const int32_t* shell_row, int32_t nsh,
