@@ -268,6 +268,9 @@ def main():
                     help="only time one build for profiler runs (no JSON): config5 = the headline build "
                          "(mixed + learned), config2 = the plain FP64 build of config 2, dfj2 = the "
                          "density-fitted Coulomb build of config 2")
+    ap.add_argument("--delocalised", type=int, default=0, metavar="CONFIG",
+                    help="only compare plain FP64 with FP64 + learned and mixed + learned on config 4 or 5 "
+                         "with a delocalised density (one JSON line of its own)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -296,6 +299,25 @@ def main():
     stream = torch.cuda.Stream(device=dev)          # default priority
     torch.cuda.set_stream(stream)
 
+    if args.delocalised:
+        from paper_2303_14280_amd import synth
+        if args.delocalised not in (4, 5):
+            raise SystemExit("--delocalised takes 4 or 5")
+        s = synth.make_system(args.delocalised, density="delocalised")
+        P = torch.tensor(s.P, dtype=torch.float64, device="cuda")
+        mlp = snk.load_screener(device=0)
+        r0, K0, _ = run_variant("config %d delocalised fp64" % args.delocalised, s, P, stream, mlp, 0, 0,
+                                eps_basis=EPS_BASIS)
+        ref = (K0, r0["ms_per_step"], r0["ex"])
+        rl, _, _ = run_variant("config %d delocalised fp64+learned" % args.delocalised, s, P, stream, mlp, 2, 1,
+                               ref=ref, eps_basis=EPS_BASIS, screen=snk.SNK_SCREEN_LEARNED, eps_skip_energy=args.eps)
+        rm, _, _ = run_variant("config %d delocalised mixed+learned" % args.delocalised, s, P, stream, mlp, 2, 1,
+                               ref=ref, eps_basis=EPS_BASIS, screen=snk.SNK_SCREEN_LEARNED, precision=snk.SNK_MIXED,
+                               eps_skip_energy=args.eps, eps_lowprec_energy=args.eps)
+        print(json.dumps({"workload": "config%d with a delocalised density: %d functions, %d grid points"
+                                      % (args.delocalised, s.nbf, s.npts),
+                          "fp64": r0, "fp64+learned": rl, "mixed+learned": rm}), flush=True)
+        return
     if args.profile:
         from paper_2303_14280_amd import synth
         if args.profile == "dfj2":
