@@ -26,20 +26,11 @@ namespace snk {
 namespace {
 
 // k extent of one staged operand step
-constexpr int GBK = 16;
+constexpr int GBK = 16, GPAD = 4;
 template <typename TS>
 constexpr int gbk()
 {
     return GBK;
-}
-// Row padding of the staged tiles (elements).  A wave reads 16 consecutive elements of each
-// of four k rows; the LDS serves 4-byte elements 32 lanes (two rows) per pass, so FP32 rows
-// start 16 banks apart (no two lanes of a pass on one bank); FP64 reads go 16 lanes (one
-// row) per pass and need only the 4-element pad that keeps 16-byte alignment.
-template <typename TS>
-constexpr int gpad()
-{
-    return sizeof(TS) == 4 ? 16 : 4;
 }
 
 template <int MODE>
@@ -103,8 +94,8 @@ struct Operands {
 // Double-buffered LDS staging of BM x BK (A, k-major) and BK x BN (B) operand tiles.
 template <typename TS, int WB>
 struct Stage {
-    TS A[2][gbk<TS>()][32 * WB + gpad<TS>()];
-    TS B[2][gbk<TS>()][32 * WB + gpad<TS>()];
+    TS A[2][gbk<TS>()][32 * WB + GPAD];
+    TS B[2][gbk<TS>()][32 * WB + GPAD];
 };
 
 template <typename TS>
@@ -350,7 +341,6 @@ __global__ __launch_bounds__(256, 2) void gsplit_kernel(const GemmProb* __restri
     const int wm = (wave >> 1) * (BM / 2), wn = (wave & 1) * (BN / 2);
     const int li = lane & 15, lk = lane >> 4;
     static_assert(sizeof(Stage<double, WB>) >= sizeof(float) * BM * (BN + 1), "LDS for the transpose");
-    static_assert(sizeof(Stage<double, WB>) >= sizeof(Stage<float, WB>), "FP32 staging inside the FP64 stage");
     float* T = reinterpret_cast<float*>(&L);
     {
         acc32 acw[WB][WB];

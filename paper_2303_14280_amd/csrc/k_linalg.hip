@@ -122,11 +122,9 @@ __global__ __launch_bounds__(256) void row_absmax_kernel(const T* __restrict__ P
     if (lane == 0) mx[r] = m;
 }
 
-// One lane per (function lam, tile t): Ft = sum_k |P[lam][fn[k]]| mx[k] over the tile's
+// One wave per (function lam, tile t): Ft = sum_k |P[lam][fn[k]]| mx[k] over the tile's
 // functions (rows roff[t] .. roff[t+1]-1 of fn and mx) bounds |F_lam,i| on every point of the
-// tile (Eq. fmat with |Phi_nu,i| <= mx); flag[t][shell_of[lam]] = 1 when Ft >= eps.  Each lane
-// walks its own row of P along the tile's functions (runs of consecutive columns, so the
-// lane's cache lines are reused), the function list and mx are read uniformly.
+// tile (Eq. fmat with |Phi_nu,i| <= mx); flag[t][shell_of[lam]] = 1 when Ft >= eps.
 __global__ __launch_bounds__(256) void ftilde_flag_kernel(const double* __restrict__ P, int64_t nbf,
                                                           const int32_t* __restrict__ fn,
                                                           const int32_t* __restrict__ roff,
@@ -134,14 +132,16 @@ __global__ __launch_bounds__(256) void ftilde_flag_kernel(const double* __restri
                                                           const int32_t* __restrict__ shell_of, int32_t nshell,
                                                           int32_t* __restrict__ flag)
 {
-    const int64_t lam = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t lam = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int t = blockIdx.y;
+    const int lane = threadIdx.x & 63;
     if (lam >= nbf) return;
     const double* row = P + lam * nbf;
     const int k0 = roff[t], k1 = roff[t + 1];
     double v = 0.0;
-    for (int k = k0; k < k1; ++k) v = fma(fabs(row[fn[k]]), mx[k], v);
-    if (v >= eps) flag[(int64_t)t * nshell + shell_of[lam]] = 1;
+    for (int k = k0 + lane; k < k1; k += 64) v = fma(fabs(row[fn[k]]), mx[k], v);
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if (lane == 0 && v >= eps) flag[(int64_t)t * nshell + shell_of[lam]] = 1;
 }
 
 // One wave: A[i][k] = (k == 0) + i (k == 1), B[k][j] = 100 j (k == 0) + (k == 1), so that
@@ -274,8 +274,8 @@ hipError_t launch_ftilde_flag(const double* P, int64_t nbf, const int32_t* fn, c
 {
     if (nbf <= 0 || ntile <= 0) return hipSuccess;
     if (!P || !fn || !roff || !mx || !shell_of || !flag) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(ftilde_flag_kernel, dim3((unsigned)((nbf + 255) / 256), (unsigned)ntile), dim3(256), 0, s, P,
-                       nbf, fn, roff, mx, eps, shell_of, nshell, flag);
+    hipLaunchKernelGGL(ftilde_flag_kernel, dim3((unsigned)((nbf + 3) / 4), (unsigned)ntile), dim3(256), 0, s, P, nbf,
+                       fn, roff, mx, eps, shell_of, nshell, flag);
     return hipGetLastError();
 }
 
