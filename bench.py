@@ -83,6 +83,12 @@ def phases(st):
             "afg": st["t_afg_ms"], "kgemm": st["t_kgemm_ms"], "finish": st["t_finish_ms"]}
 
 
+# HBM bytes per launch of a dominant kernel from the copy-calibrated FETCH_SIZE + WRITE_SIZE
+# counter runs of the same build (profiles/gsplit_config5_mixed_learned.md); valid only for the
+# kernel code those runs measured, so the entry goes when that kernel changes
+PROFILED_TRAFFIC = {"gsplit_kernel (F product, FP32 matrix cores)": 2.949e9}
+
+
 def dominant_kernel(st):
     """The kernel family with the most GPU time in a statistics build (per-class A.F kernels and
     the four grouped product kinds, all timed by the library with HIP events on its stream),
@@ -111,8 +117,8 @@ def dominant_kernel(st):
     launch_ms = t / launches
     achieved = work / launches / (launch_ms * 1e-3) / 1e12
     return {"bound": bound, "kernel": name, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-            "frac": achieved / peak, "traffic": None, "launch_ms": launch_ms, "algorithmic_flops": work / launches,
-            "launches_per_build": launches}
+            "frac": achieved / peak, "traffic": PROFILED_TRAFFIC.get(name), "launch_ms": launch_ms,
+            "algorithmic_flops": work / launches, "launches_per_build": launches}
 
 
 def make_ctx(s, stream, mlp, **kw):
@@ -264,10 +270,10 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the config 3 and config 2 comparisons")
     ap.add_argument("--eps", type=float, default=5e-6,
                     help="estimate budget (Eh) of the learned screen's skipped blocks and of the FP32 blocks")
-    ap.add_argument("--profile", choices=("config5", "config2", "dfj2"), default=None,
+    ap.add_argument("--profile", choices=("config5", "config2", "dfj2", "xc2"), default=None,
                     help="only time one build for profiler runs (no JSON): config5 = the headline build "
                          "(mixed + learned), config2 = the plain FP64 build of config 2, dfj2 = the "
-                         "density-fitted Coulomb build of config 2")
+                         "density-fitted Coulomb build of config 2, xc2 = the PBE potential of config 2")
     ap.add_argument("--delocalised", type=int, default=0, metavar="CONFIG",
                     help="only compare plain FP64 with FP64 + learned and mixed + learned on config 4 or 5 "
                          "with a delocalised density (one JSON line of its own)")
@@ -323,6 +329,23 @@ def main():
         if args.profile == "dfj2":
             r = dfj_config2(args, stream)
             log("profile run: %.2f ms/step" % r["ms_per_step"])
+            return
+        if args.profile == "xc2":
+            s = synth.make_system(2)
+            P = torch.tensor(s.P, dtype=torch.float64, device="cuda")
+            ctx = make_ctx(s, stream, None)
+            V = torch.empty_like(P)
+            for _ in range(args.warmup):
+                ctx.vxc_device(P.data_ptr(), V.data_ptr(), snk.SNK_XC_PBE)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                ctx.vxc_device(P.data_ptr(), V.data_ptr(), snk.SNK_XC_PBE)
+            torch.cuda.synchronize()
+            ms = 1000.0 * (time.perf_counter() - t0) / args.steps
+            exc, nel = ctx.vxc_device(P.data_ptr(), V.data_ptr(), snk.SNK_XC_PBE, scalars=True)
+            ctx.close()
+            log("profile run: %.2f ms/step (PBE potential of config 2: E_xc %.10f, N_el %.6f)" % (ms, exc, nel))
             return
         cfg = 5 if args.profile == "config5" else 2
         s = synth.make_system(cfg)

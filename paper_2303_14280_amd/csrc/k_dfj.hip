@@ -584,36 +584,70 @@ __global__ __launch_bounds__(256) void transpose_lower_kernel(const double* __re
     U[i * n + j] = j >= i ? L[j * n + i] : 0.0;
 }
 
-// Eq. P_df: d = V^-1 v = L^-T L^-1 v with one workgroup: forward substitution over the rows of
-// L, then back substitution over the rows of U = L^T; each step's dot product split over the
-// workgroup and reduced in a fixed order.
-__global__ __launch_bounds__(256) void chol_solve_kernel(const double* __restrict__ L, const double* __restrict__ U,
+// Eq. P_df: d = V^-1 v = L^-T L^-1 v with one workgroup, in blocks of 64 unknowns: the
+// sixteen waves form the block rows' dot products with the unknowns already solved (lanes along the
+// row, a fixed-order wave sum), then one wave solves the block's triangle from LDS, lane r
+// holding unknown r.  Forward substitution runs over the rows of L, back substitution over
+// the rows of U = L^T.
+constexpr int kSolveB = 64;
+
+constexpr int kSolveThreads = 1024;   // sixteen waves keep the row loads of a block in flight
+
+__global__ __launch_bounds__(kSolveThreads) void chol_solve_kernel(const double* __restrict__ L, const double* __restrict__ U,
                                                          int64_t n, const double* __restrict__ v,
                                                          double* __restrict__ y, double* __restrict__ d)
 {
-    __shared__ double red[4];
+    __shared__ double blk[kSolveB][kSolveB + 1];
+    __shared__ double part[kSolveB];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    auto block_sum = [&](double s) {
-        for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    // forward: L y = v
+    for (int64_t b0 = 0; b0 < n; b0 += kSolveB) {
+        const int nb = (int)min<int64_t>(kSolveB, n - b0);
+        for (int r = wave; r < nb; r += kSolveThreads / 64) {
+            const double* row = L + (b0 + r) * n;
+            double s = 0.0;
+#pragma unroll 4
+            for (int64_t k = lane; k < b0; k += 64) s += row[k] * y[k];
+            for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+            if (lane == 0) part[r] = s;
+        }
+        for (int e = tid; e < nb * nb; e += blockDim.x) blk[e / nb][e % nb] = L[(b0 + e / nb) * n + b0 + e % nb];
         __syncthreads();
-        if (lane == 0) red[wave] = s;
-        __syncthreads();
-        return (red[0] + red[1]) + (red[2] + red[3]);
-    };
-    for (int64_t j = 0; j < n; ++j) {
-        const double* row = L + j * n;
-        double s = 0.0;
-        for (int64_t k = tid; k < j; k += blockDim.x) s += row[k] * y[k];
-        s = block_sum(s);
-        if (tid == 0) y[j] = (v[j] - s) / row[j];
+        if (wave == 0) {
+            double x = lane < nb ? v[b0 + lane] - part[lane] : 0.0;
+            for (int j = 0; j < nb; ++j) {
+                const double yj = __shfl(x, j) / blk[j][j];
+                if (lane == j) x = yj;
+                else if (lane > j && lane < nb) x -= blk[lane][j] * yj;
+            }
+            if (lane < nb) y[b0 + lane] = x;
+        }
         __syncthreads();
     }
-    for (int64_t j = n - 1; j >= 0; --j) {
-        const double* row = U + j * n;
-        double s = 0.0;
-        for (int64_t k = j + 1 + tid; k < n; k += blockDim.x) s += row[k] * d[k];
-        s = block_sum(s);
-        if (tid == 0) d[j] = (y[j] - s) / row[j];
+    // back: L^T d = y, over the rows of U
+    const int64_t nblk = (n + kSolveB - 1) / kSolveB;
+    for (int64_t bi = nblk - 1; bi >= 0; --bi) {
+        const int64_t b0 = bi * kSolveB, b1 = min<int64_t>(n, b0 + kSolveB);
+        const int nb = (int)(b1 - b0);
+        for (int r = wave; r < nb; r += kSolveThreads / 64) {
+            const double* row = U + (b0 + r) * n;
+            double s = 0.0;
+#pragma unroll 4
+            for (int64_t k = b1 + lane; k < n; k += 64) s += row[k] * d[k];
+            for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+            if (lane == 0) part[r] = s;
+        }
+        for (int e = tid; e < nb * nb; e += blockDim.x) blk[e / nb][e % nb] = U[(b0 + e / nb) * n + b0 + e % nb];
+        __syncthreads();
+        if (wave == 0) {
+            double x = lane < nb ? y[b0 + lane] - part[lane] : 0.0;
+            for (int j = nb - 1; j >= 0; --j) {
+                const double dj = __shfl(x, j) / blk[j][j];
+                if (lane == j) x = dj;
+                else if (lane < j) x -= blk[lane][j] * dj;
+            }
+            if (lane < nb) d[b0 + lane] = x;
+        }
         __syncthreads();
     }
 }
@@ -737,7 +771,7 @@ hipError_t launch_dfj_solve(const double* L, const double* U, int64_t n, const d
                             hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(chol_solve_kernel, dim3(1), dim3(256), 0, s, L, U, n, v, y, d);
+    hipLaunchKernelGGL(chol_solve_kernel, dim3(1), dim3(kSolveThreads), 0, s, L, U, n, v, y, d);
     return hipGetLastError();
 }
 

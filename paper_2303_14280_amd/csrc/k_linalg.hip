@@ -103,6 +103,23 @@ __global__ __launch_bounds__(256) void fill_rows_kernel(double* __restrict__ p, 
     }
 }
 
+// Every tile of a group in one launch: workgroup (t, y) sets the rows rows[t * stride + m]
+// (m = y, y + gridDim.y, .. < count[t]) of p to v over the tile's columns cols[2t] ..
+// cols[2t] + cols[2t + 1] - 1.
+__global__ __launch_bounds__(256) void fill_rows_tiles_kernel(double* __restrict__ p, int64_t ld,
+                                                              const int32_t* __restrict__ rows, int64_t stride,
+                                                              const int32_t* __restrict__ count,
+                                                              const int64_t* __restrict__ cols, double v)
+{
+    const int t = blockIdx.x;
+    const int64_t c0 = cols[2 * t], nc = cols[2 * t + 1];
+    const int32_t* r = rows + (int64_t)t * stride;
+    for (int64_t m = blockIdx.y; m < count[t]; m += gridDim.y) {
+        double* dst = p + (int64_t)r[m] * ld + c0;
+        for (int64_t c = threadIdx.x; c < nc; c += blockDim.x) dst[c] = v;
+    }
+}
+
 // One wave per row of a group's Phi buffer (the tiles' Phi_t one after the other: nfull rows
 // of ncols_full columns, then the rows of the last tile with ncols_last columns):
 // mx[r] = max_c |Phi_r,c|
@@ -242,6 +259,16 @@ hipError_t launch_fill_rows(double* p, int64_t ld, const int32_t* rows, int64_t 
     if (M <= 0 || ncols <= 0) return hipSuccess;
     if (!p || !rows) return hipErrorInvalidValue;
     hipLaunchKernelGGL(fill_rows_kernel, rows_grid(M, ncols), dim3(256), 0, s, p, ld, rows, M, ncols, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_rows_tiles(double* p, int64_t ld, const int32_t* rows, int64_t stride, const int32_t* count,
+                                  const int64_t* cols, int32_t ntile, int32_t max_rows, double v, hipStream_t s)
+{
+    if (ntile <= 0 || max_rows <= 0) return hipSuccess;
+    if (!p || !rows || !count || !cols) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(fill_rows_tiles_kernel, dim3((unsigned)ntile, (unsigned)std::min(max_rows, 1024)), dim3(256), 0,
+                       s, p, ld, rows, stride, count, cols, v);
     return hipGetLastError();
 }
 

@@ -2175,10 +2175,20 @@ int group_until_G(snk_ctx* c, const Group& g, const double* dP, bool timed, Grou
     }
 
     if (screen && c->row_restrict && !c->zero_f_rows && c->tile_rows.size() == g.tiles.size()) {
-        // the A.F kernels update only the rows M_t of each tile's kept blocks
-        for (size_t ti = 0; ti < g.tiles.size(); ++ti)
-            HIPCHECK(c, launch_fill_rows(c->d_G + g.tiles[ti].col0, ld, c->d_trows + (int64_t)ti * nbf,
-                                         c->tile_rows[ti], g.tiles[ti].ncols, 0.0, s));
+        // the A.F kernels update only the rows M_t of each tile's kept blocks: clear those, for
+        // every tile in one launch
+        std::vector<int64_t> cols(2 * g.tiles.size());
+        int32_t max_rows = 0;
+        for (size_t ti = 0; ti < g.tiles.size(); ++ti) {
+            cols[2 * ti] = g.tiles[ti].col0;
+            cols[2 * ti + 1] = g.tiles[ti].ncols;
+            max_rows = std::max(max_rows, c->tile_rows[ti]);
+        }
+        const int64_t* d = nullptr;
+        int rc = push_vector(c, cols, &d);
+        if (rc) return rc;
+        HIPCHECK(c, launch_fill_rows_tiles(c->d_G, ld, c->d_trows, nbf, c->d_tcount, d, (int32_t)g.tiles.size(),
+                                           max_rows, 0.0, s));
     } else {
         HIPCHECK(c, launch_fill(c->d_G, nbf * g.ncols, 0.0, s));
     }

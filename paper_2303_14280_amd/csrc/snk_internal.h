@@ -503,6 +503,10 @@ hipError_t launch_xc_point(const double* px, const double* py, const double* pz,
                            double* epart, hipStream_t s);
 hipError_t launch_xc_sum(const double* epart, int64_t n, double* partial, double* out, bool accumulate, hipStream_t s);
 hipError_t launch_boys_eval(const double* T, int64_t n, int mmax, double* F, const double* tab, hipStream_t s);
+// every tile t < ntile of a group in one launch: rows rows[t * stride + m], m < count[t] (device),
+// of p over columns cols[2t] .. cols[2t] + cols[2t + 1] - 1 set to v; max_rows >= every count
+hipError_t launch_fill_rows_tiles(double* p, int64_t ld, const int32_t* rows, int64_t stride, const int32_t* count,
+                                  const int64_t* cols, int32_t ntile, int32_t max_rows, double v, hipStream_t s);
 // p[rows[m] * ld + c] = v for m < M, c < ncols
 hipError_t launch_fill_rows(double* p, int64_t ld, const int32_t* rows, int64_t M, int64_t ncols, double v,
                             hipStream_t s);

@@ -229,3 +229,27 @@ def test_two_stream_groups_match_sequential():
     assert np.array_equal(K1, K2)
     check(K2, st["ex"], g["K"], float(g["ex"][0]), "config2 two-stream")
     assert np.max(np.abs(K2 - K0)) <= 1e-12 * np.max(np.abs(K0))
+
+
+def test_validate_flag_through_one_shot_build():
+    """SNK_VALIDATE through sn_k_build: an asymmetric density is rejected with SNK_E_ASYM (and
+    accepted without the flag); an asymmetry within 1e-12 of max|P| passes; a non-finite element
+    is rejected either way."""
+    s = synth.make_system(1)
+    asym = s.P.copy()
+    asym[0, 1] += 1e-6
+    with pytest.raises(snk.SnkError) as e:
+        snk.sn_k_build(s, P=asym, flags=snk.SNK_VALIDATE)
+    assert e.value.status == snk.SNK_E_ASYM
+    K, st = snk.sn_k_build(s, P=asym)
+    assert np.all(np.isfinite(K))
+    near = s.P.copy()
+    near[0, 1] += 1e-14 * float(np.max(np.abs(s.P)))
+    K2, _ = snk.sn_k_build(s, P=near, flags=snk.SNK_VALIDATE)
+    assert np.array_equal(K2, K2.T)
+    bad = s.P.copy()
+    bad[2, 3] = np.nan
+    for flags in (0, snk.SNK_VALIDATE):
+        with pytest.raises(snk.SnkError) as e:
+            snk.sn_k_build(s, P=bad, flags=flags)
+        assert e.value.status == snk.SNK_E_ARG

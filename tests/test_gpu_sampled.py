@@ -62,3 +62,39 @@ def test_sampled_block_matches_oracle(cfg, stride):
     assert np.array_equal(K0, K0.T) and np.array_equal(K1, K1.T)
     assert d0 <= 1e-11 * scale
     assert d1 <= 1e-9 * scale
+
+
+@pytest.mark.parametrize("cfg", [3, 4, 5])
+def test_contiguous_full_batches_match_oracle(cfg):
+    """Full-occupancy batches at real shape: 768 consecutive grid points of one atom's inner
+    shells and 768 of another atom's outer shells (three whole 256-point batches each, as the
+    per-atom batching forms them), every basis function, against the oracle's K[S][S] on the
+    same points, with and without basis screening."""
+    s = synth.make_system(cfg)
+    rng = np.random.default_rng([cfg, 79])
+    a, b = (int(x) for x in rng.choice(len(s.atom_Z), size=2, replace=False))
+    pa = np.nonzero(s.grid_atom == a)[0][:768]
+    pb = np.nonzero(s.grid_atom == b)[0][-768:]
+    sub = s.subset_points(np.concatenate([pa, pb]))
+    offs = s.shell_offsets()
+    near = [k for k in range(s.nshell) if int(s.shell_atom[k]) in (a, b)]
+    rows = sorted(int(offs[k] + rng.integers(offs[k + 1] - offs[k])) for k in rng.choice(near, size=6, replace=False))
+    rows += [int(x) for x in rng.choice(s.nbf, size=3, replace=False) if int(x) not in rows]
+    rows = np.sort(np.array(rows))
+    ctx = snk.Context(sub)
+    order = ctx.point_order()
+    full = int(np.sum([np.all(order[j * 256:(j + 1) * 256] >= 0) for j in range(ctx.nbatches)]))
+    say("config %d: atoms %d, %d; %d points in %d batches (%d full); rows %s" %
+        (cfg, a, b, sub.npts, ctx.nbatches, full, rows.tolist()))
+    assert full == 6
+    Kref = O.k_block(sub, rows)
+    scale = float(np.max(np.abs(Kref)))
+    K0, _ = ctx.build(sub.P)
+    d0 = float(np.max(np.abs(K0[np.ix_(rows, rows)] - Kref)))
+    K1, st1 = snk.sn_k_build(sub, eps_basis=1e-9)
+    d1 = float(np.max(np.abs(K1[np.ix_(rows, rows)] - Kref)))
+    say("config %d: max|K[S][S]| %.3e; eps_basis 0: rel %.1e; eps_basis 1e-9: rel %.1e (tile F rows %.0f of %d)" %
+        (cfg, scale, d0 / scale, d1 / scale, st1["tile_frows"], sub.nbf))
+    assert np.array_equal(K0, K0.T)
+    assert d0 <= 1e-11 * scale
+    assert d1 <= 1e-9 * scale
