@@ -270,10 +270,11 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the config 3 and config 2 comparisons")
     ap.add_argument("--eps", type=float, default=5e-6,
                     help="estimate budget (Eh) of the learned screen's skipped blocks and of the FP32 blocks")
-    ap.add_argument("--profile", choices=("config5", "config2", "dfj2", "xc2"), default=None,
+    ap.add_argument("--profile", choices=("config5", "config2", "dfj2", "xc2", "deloc4"), default=None,
                     help="only time one build for profiler runs (no JSON): config5 = the headline build "
                          "(mixed + learned), config2 = the plain FP64 build of config 2, dfj2 = the "
-                         "density-fitted Coulomb build of config 2, xc2 = the PBE potential of config 2")
+                         "density-fitted Coulomb build of config 2, xc2 = the PBE potential of config 2, "
+                         "deloc4 = FP64 + learned on config 4 with a delocalised density")
     ap.add_argument("--delocalised", type=int, default=0, metavar="CONFIG",
                     help="only compare plain FP64 with FP64 + learned and mixed + learned on config 4 or 5 "
                          "with a delocalised density (one JSON line of its own)")
@@ -346,6 +347,14 @@ def main():
             exc, nel = ctx.vxc_device(P.data_ptr(), V.data_ptr(), snk.SNK_XC_PBE, scalars=True)
             ctx.close()
             log("profile run: %.2f ms/step (PBE potential of config 2: E_xc %.10f, N_el %.6f)" % (ms, exc, nel))
+            return
+        if args.profile == "deloc4":
+            s = synth.make_system(4, density="delocalised")
+            P = torch.tensor(s.P, dtype=torch.float64, device="cuda")
+            r, _, _ = run_variant("config 4 delocalised fp64+learned", s, P, stream, snk.load_screener(device=0),
+                                  args.steps, args.warmup, eps_basis=EPS_BASIS, screen=snk.SNK_SCREEN_LEARNED,
+                                  eps_skip_energy=args.eps)
+            log("profile run: %.1f ms/step, phases %s" % (r["ms_per_step"], r["phases_ms"]))
             return
         cfg = 5 if args.profile == "config5" else 2
         s = synth.make_system(cfg)

@@ -139,9 +139,11 @@ __global__ __launch_bounds__(256) void row_absmax_kernel(const T* __restrict__ P
     if (lane == 0) mx[r] = m;
 }
 
-// One wave per (function lam, tile t): Ft = sum_k |P[lam][fn[k]]| mx[k] over the tile's
+// One lane per (function lam, tile t): Ft = sum_k |P[lam][fn[k]]| mx[k] over the tile's
 // functions (rows roff[t] .. roff[t+1]-1 of fn and mx) bounds |F_lam,i| on every point of the
-// tile (Eq. fmat with |Phi_nu,i| <= mx); flag[t][shell_of[lam]] = 1 when Ft >= eps.
+// tile (Eq. fmat with |Phi_nu,i| <= mx); flag[t][shell_of[lam]] = 1 when Ft >= eps.  P is
+// symmetric, so |P[lam][fn[k]]| is read as |P[fn[k]][lam]|: for each k the lanes of a wave read
+// 64 consecutive elements of one row (the tile's function index and maximum are uniform).
 __global__ __launch_bounds__(256) void ftilde_flag_kernel(const double* __restrict__ P, int64_t nbf,
                                                           const int32_t* __restrict__ fn,
                                                           const int32_t* __restrict__ roff,
@@ -149,16 +151,21 @@ __global__ __launch_bounds__(256) void ftilde_flag_kernel(const double* __restri
                                                           const int32_t* __restrict__ shell_of, int32_t nshell,
                                                           int32_t* __restrict__ flag)
 {
-    const int64_t lam = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t lam = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int t = blockIdx.y;
-    const int lane = threadIdx.x & 63;
     if (lam >= nbf) return;
-    const double* row = P + lam * nbf;
+    const double* col = P + lam;
     const int k0 = roff[t], k1 = roff[t + 1];
-    double v = 0.0;
-    for (int k = k0 + lane; k < k1; k += 64) v = fma(fabs(row[fn[k]]), mx[k], v);
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    if (lane == 0 && v >= eps) flag[(int64_t)t * nshell + shell_of[lam]] = 1;
+    double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
+    int k = k0;
+    for (; k + 3 < k1; k += 4) {
+        v0 = fma(fabs(col[(int64_t)fn[k] * nbf]), mx[k], v0);
+        v1 = fma(fabs(col[(int64_t)fn[k + 1] * nbf]), mx[k + 1], v1);
+        v2 = fma(fabs(col[(int64_t)fn[k + 2] * nbf]), mx[k + 2], v2);
+        v3 = fma(fabs(col[(int64_t)fn[k + 3] * nbf]), mx[k + 3], v3);
+    }
+    for (; k < k1; ++k) v0 = fma(fabs(col[(int64_t)fn[k] * nbf]), mx[k], v0);
+    if ((v0 + v1) + (v2 + v3) >= eps) flag[(int64_t)t * nshell + shell_of[lam]] = 1;
 }
 
 // One wave: A[i][k] = (k == 0) + i (k == 1), B[k][j] = 100 j (k == 0) + (k == 1), so that
@@ -301,7 +308,7 @@ hipError_t launch_ftilde_flag(const double* P, int64_t nbf, const int32_t* fn, c
 {
     if (nbf <= 0 || ntile <= 0) return hipSuccess;
     if (!P || !fn || !roff || !mx || !shell_of || !flag) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(ftilde_flag_kernel, dim3((unsigned)((nbf + 3) / 4), (unsigned)ntile), dim3(256), 0, s, P, nbf,
+    hipLaunchKernelGGL(ftilde_flag_kernel, dim3((unsigned)((nbf + 255) / 256), (unsigned)ntile), dim3(256), 0, s, P, nbf,
                        fn, roff, mx, eps, shell_of, nshell, flag);
     return hipGetLastError();
 }

@@ -351,7 +351,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void s
     struct Cand {
         bool valid;
         int aa, b;
-        int64_t p;
+        int64_t p, k;
         PairFeat pf;
         float lp;
         float2 ua, ub;
@@ -415,6 +415,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void s
             }
         }
         d.valid = ok && bins[d.aa] != kNoBin && bins[d.b] != kNoBin && bins[d.aa] + bins[d.b] >= S;
+        d.k = k;
         if (d.valid) {
             d.pf = a.ne_feat[k];
             d.lp = a.ne_lp[k];
@@ -454,7 +455,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void s
             // log2 of the bound c_AB U_A U_B (an over-estimate where a factor was clamped)
             const float lbeta = (learn::log_cab(cur.pf) + cur.ua.x + cur.ub.x) * log2_10;
             const float lest = sample_oob ? lbeta : fminf(lbeta, fmaf(y, log2_10, mlog2));
-            const int64_t o = (int64_t)batch * a.npair_total + cur.p;
+            const int64_t o = (int64_t)batch * a.nne + cur.k;
             a.est[o] = lest;
             if (a.yraw) a.yraw[o] = y;
             atomicAdd(&lhist[est_bin(lest)], 1);
@@ -513,7 +514,7 @@ __global__ __launch_bounds__(256) void screen_kernel(ScreenArgs a)
     const int S = sh.S, S2 = sh.S2;
     const int T = learned ? a.thr[batch] : 0;
     const int T2 = learned ? a.thr2[batch] : 0;
-    const float* estb = learned ? a.est + (int64_t)batch * a.npair_total : nullptr;
+    const float* estb = learned ? a.est + (int64_t)batch * a.nne : nullptr;
     // block (aa, b) of the batch is evaluated in list category cat (0: FP64 or all, 1: FP32)
     int cat = 0;
     const double* fm = a.link ? a.fmax + (int64_t)batch * a.nshell : nullptr;
@@ -526,11 +527,12 @@ __global__ __launch_bounds__(256) void screen_kernel(ScreenArgs a)
     auto keep = [&](int aa, int b) -> bool {
         if (!a.link && bins[aa] + bins[b] < S) return false;
         const int64_t p = pair_index(aa, b);
-        if (a.pairs[p].nprim == 0) return false;
+        const int32_t pos = a.ne_pos[p];   // a 4-byte table instead of the pair record
+        if (pos < 0) return false;
         if (a.link && !link_keep(aa, b, p)) return false;
         bool high = true;
         if (learned) {
-            const int eb = est_bin(estb[p]);
+            const int eb = est_bin(estb[pos]);
             if (eb < T) return false;
             high = eb >= T2;
         } else {
@@ -568,7 +570,7 @@ __global__ __launch_bounds__(256) void screen_kernel(ScreenArgs a)
                     if (!keep(aa, b)) {
                         if (!WRITE && a.link && cat == 0) {
                             const int64_t p = pair_index(aa, b);
-                            if (a.pairs[p].nprim > 0 && !link_keep(aa, b, p))
+                            if (a.ne_pos[p] >= 0 && !link_keep(aa, b, p))
                                 lskip += (aa == b ? 0.5 : 1.0) * Ub[aa] * Ub[b];
                         }
                         continue;

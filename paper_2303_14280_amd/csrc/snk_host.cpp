@@ -225,7 +225,7 @@ struct snk_ctx {
     int32_t* d_pb = nullptr;
     BatchGeo* d_geo = nullptr;      // [nbatch]
     float* d_lp = nullptr;          // [npair_total]
-    float* d_est = nullptr;         // [max_group_batches][npair_total]
+    float* d_est = nullptr;         // [max_group_batches][nne]: by position among the pairs with kept primitive pairs
     int32_t* d_thr = nullptr;       // [max_group_batches]
     std::vector<int32_t> ne_list;   // pair indices with kept primitive pairs, class order
     int32_t ne_class_off[7] = {0, 0, 0, 0, 0, 0, 0};
@@ -701,7 +701,7 @@ int build_groups(snk_ctx* c)
     // mixed build stores Phi and F in FP32 and uses less), so that the groups, and with them
     // the basis-screened sets B_g, are the same for both
     int64_t per_batch = (int64_t)c->nbf * kBatch * 24;
-    if (c->opts.screen == SNK_SCREEN_LEARNED) per_batch += c->npair_total * (int64_t)sizeof(float);
+    if (c->opts.screen == SNK_SCREEN_LEARNED) per_batch += (int64_t)c->ne_list.size() * (int64_t)sizeof(float);
     int64_t budget = c->opts.max_device_bytes;
     if (budget <= 0) {
         size_t fr = 0, tot = 0;
@@ -918,7 +918,7 @@ int setup_screening(snk_ctx* c)
     if ((rc = dalloc(c, &c->d_lun, (size_t)mb * c->nshell))) return rc;
     if ((rc = dalloc(c, &c->d_lp, c->ne_list.size()))) return rc;
     if (c->opts.screen == SNK_SCREEN_LEARNED) {
-        if ((rc = dalloc(c, &c->d_est, (size_t)mb * c->npair_total))) return rc;
+        if ((rc = dalloc(c, &c->d_est, std::max<size_t>(1, (size_t)mb * c->ne_list.size())))) return rc;
         if ((rc = dalloc(c, &c->d_thr, (size_t)mb))) return rc;
         if ((rc = dalloc(c, &c->d_thr2, (size_t)mb))) return rc;
     }
@@ -2080,7 +2080,6 @@ int group_until_G(snk_ctx* c, const Group& g, const double* dP, bool timed, Grou
             ea.norm = mlp_norm(c->mlp);
             int hr = 0;
             mlp_range(c->mlp, ea.lo, ea.hi, &ea.margin, &hr);
-            ea.npair_total = c->npair_total;
             ea.est = c->d_est;
             ea.yraw = yraw;
             ea.thr = c->d_thr;
@@ -2102,7 +2101,8 @@ int group_until_G(snk_ctx* c, const Group& g, const double* dP, bool timed, Grou
         sa.est = c->mlp ? c->d_est : nullptr;
         sa.thr = c->mlp ? c->d_thr : nullptr;
         sa.thr2 = c->mlp ? c->d_thr2 : nullptr;
-        sa.npair_total = c->npair_total;
+        sa.ne_pos = c->d_ne_pos;
+        sa.nne = (int64_t)c->ne_list.size();
         sa.counts = c->d_counts;
         sa.npairs = c->d_npairs;
         sa.skipped = c->d_skipped;
@@ -3056,7 +3056,10 @@ int snk_ctx_debug_learned(snk_ctx* c, const double* P, float* yraw, float* est, 
     const Group& g = c->groups[0];
     const int64_t nbf = c->nbf;
     const int nb = g.b1 - g.b0;
-    const size_t n = (size_t)nb * c->npair_total;
+    // the library keeps estimates by position among the pairs with kept primitive pairs; the
+    // outputs are indexed by pair index
+    const size_t nne = c->ne_list.size();
+    const size_t n = std::max<size_t>(1, (size_t)nb * nne);
     HIPCHECK(c, hipSetDevice(c->device));
     hipStream_t s = c->stream;
     HIPCHECK(c, hipMemcpyAsync(c->d_P, P, (size_t)nbf * nbf * sizeof(double), hipMemcpyHostToDevice, s));
@@ -3074,14 +3077,24 @@ int snk_ctx_debug_learned(snk_ctx* c, const double* P, float* yraw, float* est, 
     GroupStats gs;
     rc = group_until_G(c, g, c->d_P, false, &gs, d_y);
     if (!rc) {
-        hipError_t e = hipSuccess;
-        if (yraw) e = hipMemcpyAsync(yraw, d_y, n * sizeof(float), hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess && est) e = hipMemcpyAsync(est, c->d_est, n * sizeof(float), hipMemcpyDeviceToHost, s);
+        std::vector<float> hy(n), he(n);
+        hipError_t e = hipMemcpyAsync(hy.data(), d_y, n * sizeof(float), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(he.data(), c->d_est, n * sizeof(float), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess && thr) e = hipMemcpyAsync(thr, c->d_thr, nb * sizeof(int32_t), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) {
             set_err(c, std::string("debug copy: ") + hipGetErrorString(e));
             rc = SNK_E_DEVICE;
+        } else {
+            const size_t np = (size_t)c->npair_total;
+            for (size_t b = 0; b < (size_t)nb; ++b) {
+                if (yraw) std::fill(yraw + b * np, yraw + (b + 1) * np, std::nanf(""));
+                if (est) std::fill(est + b * np, est + (b + 1) * np, std::nanf(""));
+                for (size_t k = 0; k < nne; ++k) {
+                    if (yraw) yraw[b * np + c->ne_list[k]] = hy[b * nne + k];
+                    if (est) est[b * np + c->ne_list[k]] = he[b * nne + k];
+                }
+            }
         }
     }
     (void)hipStreamSynchronize(s);

@@ -123,10 +123,12 @@ struct ScreenArgs {
     int32_t* btasks[12];
     double* btask_ab[12];
     int32_t* batch_run_off[12]; // [nbatch+1]
-    const float* est;           // learned screen: [nbatch][npair_total] log2 block estimate, or nullptr
+    const float* est;           // learned screen: [nbatch][nne] log2 block estimate, or nullptr
     const int32_t* thr;         // learned screen: [nbatch] first kept estimate bin
     const int32_t* thr2;        // learned screen: [nbatch] first FP64 estimate bin (bins thr..thr2-1 are FP32)
-    int64_t npair_total;
+    const int32_t* ne_pos;      // [npair_total] position of a pair among the pairs with kept primitive
+                                // pairs (the index of est), -1 for a pair without any
+    int64_t nne;                // pairs with kept primitive pairs
     int32_t* shell_flag;        // [tiles][nshell]: set to 1 for both shells of every kept block (or nullptr)
     int32_t tile_batches;       // batches per tile (tile of batch b: b / tile_batches)
     // pair selection of Eq. sp_set (link != 0): thresholds and the estimates it takes
@@ -188,7 +190,8 @@ struct BatchGeo {
 // Learned estimate pass of one batch group: per batch, every candidate block (pairs the
 // rigorous bound does not already skip) gets est = min(bound, 10^(y + margin)) from the
 // network (the bound alone when a feature lies outside the training range), stored as
-// log2(est) in est[batch][pair index]; the batch's skip threshold bin goes to thr[batch].
+// log2(est) in est[batch][k] (k: the pair's position in the list of pairs with kept primitive
+// pairs); the batch's skip threshold bin goes to thr[batch].
 struct EstArgs {
     const double* U;            // [nbatch][nshell] bound factors
     const float2* lun;          // [nbatch][nshell] log10 U and log10 of the F norm (clamped at -40)
@@ -207,9 +210,8 @@ struct EstArgs {
     MlpNorm norm;
     float lo[16], hi[16];       // training range of the raw features
     float margin;               // log10 units added to every prediction
-    int64_t npair_total;        // pair index space nshell (nshell + 1) / 2
-    float* est;                 // [nbatch][npair_total] log2 of the block estimate
-    float* yraw;                // optional [nbatch][npair_total] raw network output
+    float* est;                 // [nbatch][nne] log2 of the block estimate
+    float* yraw;                // optional [nbatch][nne] raw network output
     int32_t* thr;               // [nbatch] first kept bin of the learned estimate
     double eps_low;             // estimate budget of the reduced-precision blocks of one batch (0: none)
     int32_t* thr2;              // [nbatch] first FP64 bin (bins thr .. thr2-1 go to FP32)
