@@ -214,19 +214,28 @@ struct BoundShared {
     int32_t hist[kNBins];
     double cnt_s[2 * kNBins];
     int32_t aoff[4];
-    int32_t S, S2, bmax;
+    int32_t S, S2, bmin, bmax;
     double acc;
     int wsum[4];
+    long long wsum64[4];
     int carry;
 };
+
+// Shells per l packed into one 64-bit counter (21 bits per angular momentum)
+constexpr int kLBits = 21;
 
 __device__ void bound_setup(const double* __restrict__ Ub, int nshell, const int32_t* __restrict__ shell_l,
                             double eps, double eps_low, int32_t* bins, int32_t* act, BoundShared& sh,
                             bool all_active = false)
 {
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     for (int k = tid; k < kNBins; k += blockDim.x) sh.hist[k] = 0;
+    if (tid == 0) {
+        sh.bmin = kNBins;
+        sh.bmax = -1;
+    }
     __syncthreads();
+    int lo = kNBins, hi = -1;
     for (int s = tid; s < nshell; s += blockDim.x) {
         const double u = Ub[s];
         int b = kNoBin;
@@ -234,77 +243,101 @@ __device__ void bound_setup(const double* __restrict__ Ub, int nshell, const int
             b = (int)floor(2.0 * log2(u)) + kBinOff;
             b = b < 0 ? 0 : (b >= kNBins ? kNBins - 1 : b);   // clamped: still an upper bin
             atomicAdd(&sh.hist[b], 1);
+            lo = min(lo, b);
+            hi = max(hi, b);
         }
         bins[s] = b;
     }
+    if (hi >= 0) {
+        atomicMin(&sh.bmin, lo);
+        atomicMax(&sh.bmax, hi);
+    }
     __syncthreads();
-    // unordered pairs per bin sum s = k + l (index space), weighted by the pair bound
-    for (int s = tid; s < 2 * kNBins; s += blockDim.x) {
+    // the histogram is empty outside [bmin, bmax]: only bin sums 2 bmin .. 2 bmax can be non-zero
+    const int bmin = sh.bmin, bmax = sh.bmax;
+    // unordered pairs per bin sum s = k + l (index space), weighted by the pair bound (integer
+    // counts, exact in any order)
+    for (int s = 2 * bmin + tid; s <= 2 * bmax; s += blockDim.x) {
         double c = 0.0;
-        const int k0 = s - (kNBins - 1) > 0 ? s - (kNBins - 1) : 0;
-        const int k1 = s < kNBins - 1 ? s : kNBins - 1;
+        const int k0 = max(bmin, s - bmax), k1 = min(bmax, s - bmin);
         for (int k = k0; k <= k1; ++k) c += (double)sh.hist[k] * (double)sh.hist[s - k];
         if ((s & 1) == 0) c += (double)sh.hist[s >> 1];
         sh.cnt_s[s] = 0.5 * c;
     }
     __syncthreads();
     if (tid == 0) {
-        // largest S with sum_{s < S} count(s) * 2^{(s - 2 kBinOff + 2)/2} <= eps
+        // largest S with sum_{s < S} count(s) * 2^{(s - 2 kBinOff + 2)/2} <= eps (bin sums with
+        // no pairs extend S; past 2 bmax every sum is empty)
         double acc = 0.0;
-        int S = 0;
-        for (int s = 0; s < 2 * kNBins; ++s) {
-            if (sh.cnt_s[s] == 0.0) {
-                S = s + 1;
-                continue;
+        int S = 1 << 30, S2 = 1 << 30;   // every U is zero: nothing to evaluate
+        if (bmax >= 0) {
+            S = 2 * kNBins;
+            for (int s = 2 * bmin; s <= 2 * bmax; ++s) {
+                const double cs = sh.cnt_s[s];
+                if (cs == 0.0) continue;
+                const double add = cs * exp2(0.5 * (double)(s - 2 * kBinOff + 2));
+                if (acc + add > eps) {
+                    S = s;
+                    break;
+                }
+                acc += add;
             }
-            const double add = sh.cnt_s[s] * exp2(0.5 * (double)(s - 2 * kBinOff + 2));
-            if (acc + add > eps) break;
-            acc += add;
-            S = s + 1;
-        }
-        int bmax = -1;
-        for (int k = kNBins - 1; k >= 0; --k)
-            if (sh.hist[k]) {
-                bmax = k;
-                break;
+            // bound pairs S .. S2-1 may go to FP32 within eps_low
+            S2 = 2 * kNBins;
+            double low = 0.0;
+            for (int s = S; s <= 2 * bmax; ++s) {
+                const double add = sh.cnt_s[s] * exp2(0.5 * (double)(s - 2 * kBinOff + 2));
+                if (low + add > eps_low) {
+                    S2 = s;
+                    break;
+                }
+                low += add;
             }
-        // bound pairs S .. S2-1 may go to FP32 within eps_low
-        int S2 = S;
-        double low = 0.0;
-        for (int s = S; s < 2 * kNBins; ++s) {
-            const double add = sh.cnt_s[s] * exp2(0.5 * (double)(s - 2 * kBinOff + 2));
-            if (low + add > eps_low) break;
-            low += add;
-            S2 = s + 1;
         }
-        if (bmax < 0) S = S2 = 1 << 30;            // every U is zero: nothing to evaluate
         sh.S = S;
         sh.S2 = S2;
         sh.acc = acc;
-        sh.bmax = bmax;
         sh.aoff[0] = 0;
     }
     __syncthreads();
+    // Shells that can pair above S, by l in ascending shell order: each thread takes a
+    // contiguous run of shells, counts its shells per l, and places them after an exclusive
+    // scan of the packed counts over the workgroup.
     const int S = sh.S;
-    const int bmax = sh.bmax;
-    for (int l = 0; l <= 2; ++l) {
-        if (tid == 0) sh.carry = 0;
-        __syncthreads();
-        const int base = sh.aoff[l];
-        for (int s0 = 0; s0 < nshell; s0 += blockDim.x) {
-            const int s = s0 + tid;
-            const bool f =
-                s < nshell && shell_l[s] == l && (all_active || (bins[s] != kNoBin && bins[s] + bmax >= S));
-            int rank;
-            const int tot = block_scan_flag(f, sh.wsum, &rank);
-            if (f) act[base + sh.carry + rank] = s;
-            __syncthreads();
-            if (tid == 0) sh.carry += tot;
-            __syncthreads();
-        }
-        if (tid == 0) sh.aoff[l + 1] = base + sh.carry;
-        __syncthreads();
+    const int per = (nshell + (int)blockDim.x - 1) / (int)blockDim.x;
+    const int s0 = min(nshell, tid * per), s1 = min(nshell, s0 + per);
+    auto active = [&](int s) { return all_active || (bins[s] != kNoBin && bins[s] + bmax >= S); };
+    long long mine = 0;
+    for (int s = s0; s < s1; ++s)
+        if (active(s)) mine += 1ll << (kLBits * shell_l[s]);
+    long long incl = mine;
+    for (int o = 1; o < 64; o <<= 1) {
+        const long long v = __shfl_up(incl, o);
+        if (lane >= o) incl += v;
     }
+    if (lane == 63) sh.wsum64[wave] = incl;
+    __syncthreads();
+    long long before = incl - mine;
+    for (int w = 0; w < wave; ++w) before += sh.wsum64[w];
+    const long long total = sh.wsum64[0] + sh.wsum64[1] + sh.wsum64[2] + sh.wsum64[3];
+    constexpr long long kMask = (1ll << kLBits) - 1;
+    const int n0 = (int)(total & kMask), n1 = (int)((total >> kLBits) & kMask);
+    const int n2 = (int)((total >> (2 * kLBits)) & kMask);
+    int p0 = (int)(before & kMask), p1 = n0 + (int)((before >> kLBits) & kMask);
+    int p2 = n0 + n1 + (int)((before >> (2 * kLBits)) & kMask);
+    for (int s = s0; s < s1; ++s)
+        if (active(s)) {
+            const int l = shell_l[s];
+            if (l == 0) act[p0++] = s;
+            else if (l == 1) act[p1++] = s;
+            else act[p2++] = s;
+        }
+    if (tid == 0) {
+        sh.aoff[1] = n0;
+        sh.aoff[2] = n0 + n1;
+        sh.aoff[3] = n0 + n1 + n2;
+    }
+    __syncthreads();
 }
 
 __device__ __forceinline__ int est_bin(float lest)
@@ -332,7 +365,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void s
     const int r = lane & 15, g = lane >> 4;
     const double* Ub = a.U + (int64_t)batch * a.nshell;
     const float2* Lb = a.lun + (int64_t)batch * a.nshell;
+    __shared__ int32_t lmin, lmax;
     for (int k = tid; k < kNBins; k += blockDim.x) lhist[k] = 0;
+    if (tid == 0) {
+        lmin = kNBins;
+        lmax = -1;
+    }
+    int elo = kNBins, ehi = -1;   // this thread's range of estimate bins
     bound_setup(Ub, a.nshell, a.shell_l, a.eps_batch, 0.0, bins, act, sh);
     const int S = sh.S;
     const BatchGeo bg = a.geo[batch];
@@ -348,16 +387,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void s
     // active, or the combinations of the shells the bound leaves active (same-l classes over
     // the triangle ai >= bi; the active lists ascend in shell index) when few are.  Pairs
     // the bound already skips on this batch are dropped either way.
-    struct Cand {
-        bool valid;
-        int aa, b;
-        int64_t p, k;
-        PairFeat pf;
-        float lp;
-        float2 ua, ub;
-    };
+    //
+    // In rounds of kQueue candidates: the whole workgroup applies the bound's test (one
+    // candidate per thread) and queues the survivors' positions k in the list of pairs with
+    // kept primitive pairs; then the waves run the network on the queue, 16 entries at a time.
+    // Every survivor's estimate lands at its own k and the histogram counts are sums of
+    // integers, so the queue's order does not change the result.
     __shared__ int64_t coff[7];
     __shared__ int use_list;
+    __shared__ int qn;
+    constexpr int kQueue = 2 * kNBins * (int)(sizeof(double) / sizeof(int32_t));
+    int32_t* queue = reinterpret_cast<int32_t*>(sh.cnt_s);   // free once the bound is set up
     if (tid == 0) {
         int64_t acc = 0;
         for (int c = 0; c < 6; ++c) {
@@ -372,119 +412,142 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void s
     __syncthreads();
     const bool list = use_list != 0;
     const int64_t total = list ? a.nne : coff[6];
-    auto fetch = [&](int64_t i, Cand& d) {
-        int64_t k = 0;
-        bool ok = i < total;
+    // the bound's test of candidate i: its position k, or -1
+    auto survivor = [&](int64_t i) -> int32_t {
+        int aa, b;
+        int32_t k;
         if (list) {
-            k = ok ? i : 0;
-            const int2 ab = a.ne_ab[k];
-            d.aa = ab.x;
-            d.b = ab.y;
-            d.p = a.ne_p[k];
+            const int2 ab = a.ne_ab[i];
+            aa = ab.x;
+            b = ab.y;
+            k = (int32_t)i;
         } else {
-            d.aa = 0;
-            d.b = 0;
-            d.p = 0;
-            if (ok) {
-                int c = 0;
-                while (c < 5 && i >= coff[c + 1]) ++c;
-                const int la = kClassLA_dev(c), lb = kClassLB_dev(c);
-                const int64_t j = i - coff[c];
-                int ai, bi;
-                if (la == lb) {
-                    ai = (int)((sqrtf(8.0f * (float)j + 1.0f) - 1.0f) * 0.5f);
-                    while ((int64_t)ai * (ai + 1) / 2 > j) --ai;
-                    while ((int64_t)(ai + 1) * (ai + 2) / 2 <= j) ++ai;
-                    bi = (int)(j - (int64_t)ai * (ai + 1) / 2);
-                } else {
-                    const int nB = sh.aoff[lb + 1] - sh.aoff[lb];
-                    ai = (int)(j / nB);
-                    bi = (int)(j - (int64_t)ai * nB);
-                }
-                d.aa = act[sh.aoff[la] + ai];
-                d.b = act[sh.aoff[lb] + bi];
-                d.p = pair_index(d.aa, d.b);
-                // the bound's test first (LDS only): the pair's records are gathered only for
-                // the candidates it leaves
-                ok = bins[d.aa] != kNoBin && bins[d.b] != kNoBin && bins[d.aa] + bins[d.b] >= S;
-                if (ok) {
-                    const int32_t pos = a.ne_pos[d.p];
-                    ok = pos >= 0;
-                    k = ok ? pos : 0;
-                }
+            int c = 0;
+            while (c < 5 && i >= coff[c + 1]) ++c;
+            const int la = kClassLA_dev(c), lb = kClassLB_dev(c);
+            const int64_t j = i - coff[c];
+            int ai, bi;
+            if (la == lb) {
+                ai = (int)((sqrtf(8.0f * (float)j + 1.0f) - 1.0f) * 0.5f);
+                while ((int64_t)ai * (ai + 1) / 2 > j) --ai;
+                while ((int64_t)(ai + 1) * (ai + 2) / 2 <= j) ++ai;
+                bi = (int)(j - (int64_t)ai * (ai + 1) / 2);
+            } else {
+                const int nB = sh.aoff[lb + 1] - sh.aoff[lb];
+                ai = (int)(j / nB);
+                bi = (int)(j - (int64_t)ai * nB);
             }
+            aa = act[sh.aoff[la] + ai];
+            b = act[sh.aoff[lb] + bi];
+            k = -1;
         }
-        d.valid = ok && bins[d.aa] != kNoBin && bins[d.b] != kNoBin && bins[d.aa] + bins[d.b] >= S;
-        d.k = k;
+        if (bins[aa] == kNoBin || bins[b] == kNoBin || bins[aa] + bins[b] < S) return -1;
+        return list ? k : a.ne_pos[pair_index(aa, b)];
+    };
+    struct Cand {
+        bool valid;
+        int32_t k;
+        PairFeat pf;
+        float lp;
+        float2 ua, ub;
+    };
+    auto fetch = [&](int idx, int n, Cand& d) {
+        d.valid = idx < n;
         if (d.valid) {
-            d.pf = a.ne_feat[k];
-            d.lp = a.ne_lp[k];
-            d.ua = Lb[d.aa];
-            d.ub = Lb[d.b];
+            d.k = queue[idx];
+            const int2 ab = a.ne_ab[d.k];
+            d.pf = a.ne_feat[d.k];
+            d.lp = a.ne_lp[d.k];
+            d.ua = Lb[ab.x];
+            d.ub = Lb[ab.y];
         } else {
+            d.k = 0;
             d.pf = PairFeat{};
             d.lp = 0.0f;
             d.ua = d.ub = make_float2(0.0f, 0.0f);
         }
     };
 
-    Cand cur, nxt;
-    int64_t q = wave;
-    fetch(q * 16 + r, nxt);
-    for (; q * 16 < total; q += 4) {
-        cur = nxt;
-        fetch((q + 4) * 16 + r, nxt);
-        if (__ballot(cur.valid) == 0ull) continue;
-        float f[16];
-        learn::block_features(cur.pf, cur.lp, bg, cur.ua.x, cur.ub.x, cur.ua.y, cur.ub.y, f);
-        float x[4];
-        bool oob = false;
-        for (int e = 0; e < 4; ++e) {
-            // this lane supplies features 4g .. 4g+3 (constant-index selects, no scratch)
-            float v = f[e];
-            v = g == 1 ? f[4 + e] : v;
-            v = g == 2 ? f[8 + e] : v;
-            v = g == 3 ? f[12 + e] : v;
-            x[e] = v;
-            oob |= !(v >= msh.lo[4 * g + e] && v <= msh.hi[4 * g + e]);
+    for (int64_t base = 0; base < total; base += kQueue) {
+        if (tid == 0) qn = 0;
+        __syncthreads();
+        const int64_t end = base + kQueue < total ? base + kQueue : total;
+        for (int64_t i = base + tid; i < end; i += blockDim.x) {
+            const int32_t k = survivor(i);
+            if (k >= 0) queue[atomicAdd(&qn, 1)] = k;
         }
-        const unsigned long long mo = __ballot(oob);
-        const bool sample_oob = ((mo >> r) & 0x0001000100010001ull) != 0ull;
-        const float y = learn::mlp_eval16(R, msh, x);
-        if (g == 0 && cur.valid) {
-            // log2 of the bound c_AB U_A U_B (an over-estimate where a factor was clamped)
-            const float lbeta = (learn::log_cab(cur.pf) + cur.ua.x + cur.ub.x) * log2_10;
-            const float lest = sample_oob ? lbeta : fminf(lbeta, fmaf(y, log2_10, mlog2));
-            const int64_t o = (int64_t)batch * a.nne + cur.k;
-            a.est[o] = lest;
-            if (a.yraw) a.yraw[o] = y;
-            atomicAdd(&lhist[est_bin(lest)], 1);
+        __syncthreads();
+        const int n = qn;
+        Cand cur, nxt;
+        int q = wave * 16;
+        fetch(q + r, n, nxt);
+        for (; q < n; q += 64) {
+            cur = nxt;
+            fetch(q + 64 + r, n, nxt);
+            float f[16];
+            learn::block_features(cur.pf, cur.lp, bg, cur.ua.x, cur.ub.x, cur.ua.y, cur.ub.y, f);
+            float x[4];
+            bool oob = false;
+            for (int e = 0; e < 4; ++e) {
+                // this lane supplies features 4g .. 4g+3 (constant-index selects, no scratch)
+                float v = f[e];
+                v = g == 1 ? f[4 + e] : v;
+                v = g == 2 ? f[8 + e] : v;
+                v = g == 3 ? f[12 + e] : v;
+                x[e] = v;
+                oob |= !(v >= msh.lo[4 * g + e] && v <= msh.hi[4 * g + e]);
+            }
+            const unsigned long long mo = __ballot(oob);
+            const bool sample_oob = ((mo >> r) & 0x0001000100010001ull) != 0ull;
+            const float y = learn::mlp_eval16(R, msh, x);
+            if (g == 0 && cur.valid) {
+                // log2 of the bound c_AB U_A U_B (an over-estimate where a factor was clamped)
+                const float lbeta = (learn::log_cab(cur.pf) + cur.ua.x + cur.ub.x) * log2_10;
+                const float lest = sample_oob ? lbeta : fminf(lbeta, fmaf(y, log2_10, mlog2));
+                const int64_t o = (int64_t)batch * a.nne + cur.k;
+                a.est[o] = lest;
+                if (a.yraw) a.yraw[o] = y;
+                const int eb = est_bin(lest);
+                if (eb >= 0) {
+                    atomicAdd(&lhist[eb], 1);
+                    elo = min(elo, eb);
+                    ehi = max(ehi, eb);
+                }
+            }
         }
+        __syncthreads();   // the queue is refilled
+    }
+    if (ehi >= 0) {
+        atomicMin(&lmin, elo);
+        atomicMax(&lmax, ehi);
     }
     __syncthreads();
     if (tid == 0) {
         // largest T with sum_{k < T} count(k) 2^{(k + 1 - kBinOff)/2} <= budget left by the bound
+        // (empty bins extend T; the histogram is empty outside [lmin, lmax])
         const double rem = a.eps_batch - sh.acc;
         double acc = 0.0;
-        int T = 0;
-        for (int k = 0; k < kNBins; ++k) {
-            if (lhist[k] == 0) {
-                T = k + 1;
-                continue;
+        int T = kNBins, T2 = kNBins;
+        if (lmax >= 0) {
+            for (int k = lmin; k <= lmax; ++k) {
+                if (lhist[k] == 0) continue;
+                const double add = (double)lhist[k] * exp2(0.5 * (double)(k + 1 - kBinOff));
+                if (acc + add > rem) {
+                    T = k;
+                    break;
+                }
+                acc += add;
             }
-            const double add = (double)lhist[k] * exp2(0.5 * (double)(k + 1 - kBinOff));
-            if (acc + add > rem) break;
-            acc += add;
-            T = k + 1;
-        }
-        // then the FP32 set: bins T .. T2-1 whose estimates sum to at most eps_low
-        int T2 = T;
-        double low = 0.0;
-        for (int k = T; k < kNBins; ++k) {
-            const double add = (double)lhist[k] * exp2(0.5 * (double)(k + 1 - kBinOff));
-            if (low + add > a.eps_low) break;
-            low += add;
-            T2 = k + 1;
+            // then the FP32 set: bins T .. T2-1 whose estimates sum to at most eps_low
+            double low = 0.0;
+            for (int k = T; k <= lmax; ++k) {
+                const double add = (double)lhist[k] * exp2(0.5 * (double)(k + 1 - kBinOff));
+                if (low + add > a.eps_low) {
+                    T2 = k;
+                    break;
+                }
+                low += add;
+            }
         }
         a.thr[batch] = T;
         a.thr2[batch] = T2;
@@ -591,41 +654,63 @@ __global__ __launch_bounds__(256) void screen_kernel(ScreenArgs a)
         }
         __syncthreads();
         if (!WRITE) {
-            // reduce npair (and the link-skipped bound) over the block
+            // reduce npair, the link-skipped bound and the run and B-task counts over the block
+            // (integer counts; the bound sums in a fixed order)
+            int nrun = 0, nbt = 0;
+            for (int t = tid; t < nt; t += blockDim.x) {
+                const int n = tilecnt[t];
+                nbt += n;
+                nrun += n > 0;
+            }
             double v = (double)npair, ls = lskip;
             for (int o = 32; o > 0; o >>= 1) {
                 v += __shfl_xor(v, o);
                 ls += __shfl_xor(ls, o);
+                nrun += __shfl_xor(nrun, o);
+                nbt += __shfl_xor(nbt, o);
             }
             __shared__ double red[4], lred[4];
+            __shared__ int rred[4], bred[4];
             if ((tid & 63) == 0) {
                 red[tid >> 6] = v;
                 lred[tid >> 6] = ls;
+                rred[tid >> 6] = nrun;
+                bred[tid >> 6] = nbt;
             }
             __syncthreads();
-            if (a.link && tid == 0) sh.acc += lred[0] + lred[1] + lred[2] + lred[3];
-            int nrun = 0, nbt = 0;
             if (tid == 0) {
-                for (int t = 0; t < nt; ++t) {
-                    nbt += tilecnt[t];
-                    nrun += tilecnt[t] > 0;
-                }
-                a.counts[((int64_t)batch * a.nlist + c) * 2] = nrun;
-                a.counts[((int64_t)batch * a.nlist + c) * 2 + 1] = nbt;
+                if (a.link) sh.acc += lred[0] + lred[1] + lred[2] + lred[3];
+                a.counts[((int64_t)batch * a.nlist + c) * 2] = rred[0] + rred[1] + rred[2] + rred[3];
+                a.counts[((int64_t)batch * a.nlist + c) * 2 + 1] = bred[0] + bred[1] + bred[2] + bred[3];
                 a.npairs[(int64_t)batch * a.nlist + c] = (int64_t)(red[0] + red[1] + red[2] + red[3]);
             }
             __syncthreads();
             continue;
         }
-        // WRITE: exclusive scan of tile counts -> run records
-        if (tid == 0) {
+        // WRITE: run records from an exclusive scan of the tile counts, 256 tiles at a time
+        // (runs and B tasks counted together in one 64-bit value: runs << 32 | B tasks)
+        {
             const int64_t rb = a.run_base[(int64_t)c * (a.nbatch + 1) + batch];
             const int64_t bb = a.bt_base[(int64_t)c * (a.nbatch + 1) + batch];
-            int64_t bt = bb, r = rb;
             const int RS = 2 + TA;
-            for (int t = 0; t < nt; ++t) {
-                const int n = tilecnt[t];
+            const int lane = tid & 63, wave = tid >> 6;
+            long long carry = 0;
+            for (int t0 = 0; t0 < nt; t0 += blockDim.x) {
+                const int t = t0 + tid;
+                const int n = t < nt ? tilecnt[t] : 0;
+                const long long mine = n > 0 ? (1ll << 32) + n : 0ll;
+                long long incl = mine;
+                for (int o = 1; o < 64; o <<= 1) {
+                    const long long x = __shfl_up(incl, o);
+                    if (lane >= o) incl += x;
+                }
+                if (lane == 63) sh.wsum64[wave] = incl;
+                __syncthreads();
+                long long before = carry + incl - mine;
+                for (int w = 0; w < wave; ++w) before += sh.wsum64[w];
+                const long long tot = sh.wsum64[0] + sh.wsum64[1] + sh.wsum64[2] + sh.wsum64[3];
                 if (n > 0) {
+                    const int64_t r = rb + (before >> 32), bt = bb + (before & 0xffffffffll);
                     int32_t* rec = a.runs[c] + r * RS;
                     rec[0] = (int32_t)bt;
                     rec[1] = (int32_t)(bt + n);
@@ -633,14 +718,17 @@ __global__ __launch_bounds__(256) void screen_kernel(ScreenArgs a)
                         const int ai = t * TA + k;
                         rec[2 + k] = ai < nA ? a.shell_row[actA[ai]] : -1;
                     }
-                    ++r;
                 }
-                bt += n;
+                carry += tot;
+                __syncthreads();   // wsum64 is reused
             }
-            a.batch_run_off[c][batch] = (int32_t)rb;
-            if (batch == a.nbatch - 1) a.batch_run_off[c][a.nbatch] = (int32_t)r;
+            if (tid == 0) {
+                a.batch_run_off[c][batch] = (int32_t)rb;
+                if (batch == a.nbatch - 1) a.batch_run_off[c][a.nbatch] = (int32_t)(rb + (carry >> 32));
+            }
+            if (tid == 0) sh.carry = 0;
+            __syncthreads();
         }
-        __syncthreads();
         // pass 2: B-task records in (tile, B) order
         const int64_t bb = a.bt_base[(int64_t)c * (a.nbatch + 1) + batch];
         const int BS = 2 + 2 * TA;
