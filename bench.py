@@ -86,7 +86,7 @@ def phases(st):
 # HBM bytes per launch of a dominant kernel from the copy-calibrated FETCH_SIZE + WRITE_SIZE
 # counter runs of the same build (profiles/gsplit_config5_mixed_learned.md); valid only for the
 # kernel code those runs measured, so the entry goes when that kernel changes
-PROFILED_TRAFFIC = {"gsplit_kernel (F product, FP32 matrix cores)": 2.949e9}
+PROFILED_TRAFFIC = {}
 
 
 def dominant_kernel(st):

@@ -91,11 +91,25 @@ struct Operands {
     bool avec, bvec;
 };
 
+// Row-major B is staged with one free slot after every 8 columns (column j at j + j / 8): a
+// lane stages a run of 8 columns, so without the gaps the 16 lanes of a k row would start
+// their runs on only two (FP64) or four (FP32) of the 32 LDS banks.  The row length then puts
+// consecutive k rows 8 (FP64) or 16 (FP32) banks apart for the matrix-core operand reads.
+__host__ __device__ constexpr int skew(int j) { return j + (j >> 3); }
+template <typename TS>
+constexpr int bcols(int bn)
+{
+    int c = skew(bn);
+    const int target = sizeof(TS) == 8 ? 8 : 16;
+    while ((c * (int)sizeof(TS) / 4) % 32 != target) ++c;
+    return c;
+}
+
 // Double-buffered LDS staging of BM x BK (A, k-major) and BK x BN (B) operand tiles.
 template <typename TS, int WB>
 struct Stage {
     TS A[2][gbk<TS>()][32 * WB + GPAD];
-    TS B[2][gbk<TS>()][32 * WB + GPAD];
+    TS B[2][gbk<TS>()][bcols<TS>(32 * WB)];
 };
 
 template <typename TS>
@@ -207,7 +221,7 @@ __device__ inline void mainloop(Stage<TS, WB>& L, const Operands<TA, TB>& op, in
             for (int u = 0; u < E; ++u) L.B[buf][bk + u][bj] = vb[u];
         } else {
 #pragma unroll
-            for (int u = 0; u < E; ++u) L.B[buf][bk][bj + u] = vb[u];
+            for (int u = 0; u < E; ++u) L.B[buf][bk][skew(bj + u)] = vb[u];
         }
     };
 
@@ -226,7 +240,10 @@ __device__ inline void mainloop(Stage<TS, WB>& L, const Operands<TA, TB>& op, in
 #pragma unroll
             for (int bi = 0; bi < WB; ++bi) a[bi] = L.A[cur][ks + lk][wm + bi * 16 + li];
 #pragma unroll
-            for (int bj2 = 0; bj2 < WB; ++bj2) b[bj2] = L.B[cur][ks + lk][wn + bj2 * 16 + li];
+            for (int bj2 = 0; bj2 < WB; ++bj2) {
+                const int j = wn + bj2 * 16 + li;
+                b[bj2] = L.B[cur][ks + lk][BT ? j : skew(j)];
+            }
 #pragma unroll
             for (int bi = 0; bi < WB; ++bi)
 #pragma unroll
