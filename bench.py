@@ -86,7 +86,7 @@ def phases(st):
 # HBM bytes per launch of a dominant kernel from the copy-calibrated FETCH_SIZE + WRITE_SIZE
 # counter runs of the same build (profiles/gsplit_config5_mixed_learned.md); valid only for the
 # kernel code those runs measured, so the entry goes when that kernel changes
-PROFILED_TRAFFIC = {}
+PROFILED_TRAFFIC = {"gsplit_kernel (F product, FP32 matrix cores)": 4.512e9}
 
 
 def dominant_kernel(st):
@@ -121,8 +121,15 @@ def dominant_kernel(st):
             "algorithmic_flops": work / launches, "launches_per_build": launches}
 
 
+# Device memory the library may use for batch groups: a fixed figure (about 0.45 of an idle
+# MI355X's free memory, the library's own default) rather than a share of what is free at the
+# time, so that every run, profiled or not, splits a workload into the same groups.
+DEVICE_BUDGET = 120 << 30
+
+
 def make_ctx(s, stream, mlp, **kw):
     from paper_2303_14280_amd import snk
+    kw.setdefault("max_device_bytes", DEVICE_BUDGET)
     return snk.Context(s, flags=snk.SNK_DEVICE_PTRS, stream=stream.cuda_stream, device=0, screener=mlp, **kw)
 
 

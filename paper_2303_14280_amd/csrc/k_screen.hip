@@ -587,8 +587,15 @@ __global__ __launch_bounds__(256) void screen_kernel(ScreenArgs a)
         const double at = a.atil[p];
         return fm[aa] * fm[b] * at >= a.link_eps || ::fmax(fm[aa], fm[b]) * phit * at >= a.link_eps;
     };
+    // The learned estimate never exceeds the bound c_AB U_A U_B it was given (U clamped below at
+    // 1e-40 there), whose bin lies below fb(A) + fb(B) - kBinOff + 2 with fb = max(bin, the bin of
+    // 1e-40); so with T > 0 a pair whose bins sum to at most T + kBinOff - 3 cannot reach bin T,
+    // and is dropped without reading its estimate.
+    constexpr int kLunFloorBin = kBinOff - 266;   // floor(2 log2 1e-40) + kBinOff
+    const int tcut = T + kBinOff - 3;
     auto keep = [&](int aa, int b) -> bool {
         if (!a.link && bins[aa] + bins[b] < S) return false;
+        if (learned && T > 0 && max(bins[aa], kLunFloorBin) + max(bins[b], kLunFloorBin) <= tcut) return false;
         const int64_t p = pair_index(aa, b);
         const int32_t pos = a.ne_pos[p];   // a 4-byte table instead of the pair record
         if (pos < 0) return false;
