@@ -29,7 +29,8 @@ int snk_boys_device(const double* T, int64_t n, int mmax, double* F_out, void* s
  * snk_debug_gemm_f64: C = A op(B) with the library's grouped FP64 matrix-core product (one
  *   problem) on device pointers: A is M x K row-major (lda), B is K x N row-major (ldb) or,
  *   with bt != 0, N x K row-major; C is M x N row-major (ldc).  tile: output tile of the
- *   kernel, 64 or 128, or 0 for the library's own choice.  Synchronous on `stream`.
+ *   kernel, 64 (64 x 64), 128 (128 x 128) or 192 (64 rows x 128 columns), or 0 for the
+ *   library's own choice.  Synchronous on `stream`.
  * snk_debug_mfma_layout: writes 256 doubles to host memory `out`: element 4*lane + r of
  *   one v_mfma_f64_16x16x4f64 whose inputs encode D[i][j] = 100 j + i (layout check).
  * snk_ctx_point_order: col_to_point[c] (host, nbatches*256 entries) = input index of the

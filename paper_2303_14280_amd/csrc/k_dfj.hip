@@ -574,82 +574,75 @@ __global__ __launch_bounds__(256) void chol_update_kernel(double* __restrict__ A
     }
 }
 
-// U = L^T (row-major), zero below the diagonal
-__global__ __launch_bounds__(256) void transpose_lower_kernel(const double* __restrict__ L, int64_t n,
-                                                              double* __restrict__ U)
-{
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n * n) return;
-    const int64_t i = e / n, j = e % n;
-    U[i * n + j] = j >= i ? L[j * n + i] : 0.0;
-}
-
-// Eq. P_df: d = V^-1 v = L^-T L^-1 v with one workgroup, in blocks of 64 unknowns: the
-// sixteen waves form the block rows' dot products with the unknowns already solved (lanes along the
-// row, a fixed-order wave sum), then one wave solves the block's triangle from LDS, lane r
-// holding unknown r.  Forward substitution runs over the rows of L, back substitution over
-// the rows of U = L^T.
+// Eq. P_df at set-up: L^-1 column by column.  Workgroup j solves L x = e_j by forward
+// substitution in blocks of 64 unknowns (the sixteen waves form the block rows' dot products
+// with the unknowns already solved, lanes along the row with a fixed-order wave sum; one wave
+// solves the block's triangle from LDS, lane r holding unknown r) and writes x as row j of
+// W = L^-T (W[j][i] = (L^-1)_ij, zero for i < j).
 constexpr int kSolveB = 64;
 
 constexpr int kSolveThreads = 1024;   // sixteen waves keep the row loads of a block in flight
 
-__global__ __launch_bounds__(kSolveThreads) void chol_solve_kernel(const double* __restrict__ L, const double* __restrict__ U,
-                                                         int64_t n, const double* __restrict__ v,
-                                                         double* __restrict__ y, double* __restrict__ d)
+__global__ __launch_bounds__(kSolveThreads) void tri_inverse_kernel(const double* __restrict__ L, int64_t n,
+                                                                    double* __restrict__ W)
 {
     __shared__ double blk[kSolveB][kSolveB + 1];
     __shared__ double part[kSolveB];
+    const int64_t j = blockIdx.x;
+    double* x = W + j * n;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    // forward: L y = v
-    for (int64_t b0 = 0; b0 < n; b0 += kSolveB) {
+    const int64_t jb = (j / kSolveB) * kSolveB;   // the block holding unknown j
+    for (int64_t i = tid; i < jb; i += blockDim.x) x[i] = 0.0;
+    for (int64_t b0 = jb; b0 < n; b0 += kSolveB) {
         const int nb = (int)min<int64_t>(kSolveB, n - b0);
         for (int r = wave; r < nb; r += kSolveThreads / 64) {
             const double* row = L + (b0 + r) * n;
             double s = 0.0;
 #pragma unroll 4
-            for (int64_t k = lane; k < b0; k += 64) s += row[k] * y[k];
+            for (int64_t k = jb + lane; k < b0; k += 64) s += row[k] * x[k];
             for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
             if (lane == 0) part[r] = s;
         }
         for (int e = tid; e < nb * nb; e += blockDim.x) blk[e / nb][e % nb] = L[(b0 + e / nb) * n + b0 + e % nb];
         __syncthreads();
         if (wave == 0) {
-            double x = lane < nb ? v[b0 + lane] - part[lane] : 0.0;
-            for (int j = 0; j < nb; ++j) {
-                const double yj = __shfl(x, j) / blk[j][j];
-                if (lane == j) x = yj;
-                else if (lane > j && lane < nb) x -= blk[lane][j] * yj;
+            double xv = lane < nb ? (b0 + lane == j ? 1.0 : 0.0) - part[lane] : 0.0;
+            for (int c = 0; c < nb; ++c) {
+                const double xc = __shfl(xv, c) / blk[c][c];
+                if (lane == c) xv = xc;
+                else if (lane > c && lane < nb) xv -= blk[lane][c] * xc;
             }
-            if (lane < nb) y[b0 + lane] = x;
+            if (lane < nb) x[b0 + lane] = xv;
         }
         __syncthreads();
     }
-    // back: L^T d = y, over the rows of U
-    const int64_t nblk = (n + kSolveB - 1) / kSolveB;
-    for (int64_t bi = nblk - 1; bi >= 0; --bi) {
-        const int64_t b0 = bi * kSolveB, b1 = min<int64_t>(n, b0 + kSolveB);
-        const int nb = (int)(b1 - b0);
-        for (int r = wave; r < nb; r += kSolveThreads / 64) {
-            const double* row = U + (b0 + r) * n;
-            double s = 0.0;
+}
+
+// out = in^T (n x n)
+__global__ __launch_bounds__(256) void transpose_kernel(const double* __restrict__ in, int64_t n,
+                                                        double* __restrict__ out)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * n) return;
+    const int64_t i = e / n, j = e - i * n;
+    out[e] = in[j * n + i];
+}
+
+// Eq. P_df per build: y_i = sum_k M_ik x_k over k <= i (lower) or k >= i (upper); one wave per
+// row, lanes along the row, fixed-order sums.
+__global__ __launch_bounds__(256) void trmv_kernel(const double* __restrict__ M, int64_t n,
+                                                   const double* __restrict__ x, double* __restrict__ y, int lower)
+{
+    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (i >= n) return;
+    const double* row = M + i * n;
+    const int64_t k0 = lower ? 0 : i, k1 = lower ? i + 1 : n;
+    double s = 0.0;
 #pragma unroll 4
-            for (int64_t k = b1 + lane; k < n; k += 64) s += row[k] * d[k];
-            for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-            if (lane == 0) part[r] = s;
-        }
-        for (int e = tid; e < nb * nb; e += blockDim.x) blk[e / nb][e % nb] = U[(b0 + e / nb) * n + b0 + e % nb];
-        __syncthreads();
-        if (wave == 0) {
-            double x = lane < nb ? y[b0 + lane] - part[lane] : 0.0;
-            for (int j = nb - 1; j >= 0; --j) {
-                const double dj = __shfl(x, j) / blk[j][j];
-                if (lane == j) x = dj;
-                else if (lane < j) x -= blk[lane][j] * dj;
-            }
-            if (lane < nb) d[b0 + lane] = x;
-        }
-        __syncthreads();
-    }
+    for (int64_t k = k0 + lane; k < k1; k += 64) s += row[k] * x[k];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if (lane == 0) y[i] = s;
 }
 
 __global__ __launch_bounds__(256) void dot_kernel(const double* __restrict__ a, const double* __restrict__ b,
@@ -752,7 +745,7 @@ hipError_t launch_dfj_metric(const DfjAux* aux, int32_t naux, const double* tab,
     return hipGetLastError();
 }
 
-hipError_t launch_dfj_cholesky(double* A, int64_t n, double* U, int32_t* status, hipStream_t s)
+hipError_t launch_dfj_cholesky(double* A, int64_t n, int32_t* status, hipStream_t s)
 {
     for (int64_t j0 = 0; j0 < n; j0 += kCholB) {
         hipLaunchKernelGGL(chol_diag_kernel, dim3(1), dim3(256), 0, s, A, n, j0, status);
@@ -763,15 +756,24 @@ hipError_t launch_dfj_cholesky(double* A, int64_t n, double* U, int32_t* status,
             hipLaunchKernelGGL(chol_update_kernel, dim3((unsigned)(nbk * (nbk + 1) / 2)), dim3(256), 0, s, A, n, j0);
         }
     }
-    hipLaunchKernelGGL(transpose_lower_kernel, dim3((unsigned)((n * n + 255) / 256)), dim3(256), 0, s, A, n, U);
     return hipGetLastError();
 }
 
-hipError_t launch_dfj_solve(const double* L, const double* U, int64_t n, const double* v, double* y, double* d,
+hipError_t launch_dfj_invert(double* L, int64_t n, double* W, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(tri_inverse_kernel, dim3((unsigned)n), dim3(kSolveThreads), 0, s, L, n, W);
+    hipLaunchKernelGGL(transpose_kernel, dim3((unsigned)((n * n + 255) / 256)), dim3(256), 0, s, W, n, L);
+    return hipGetLastError();
+}
+
+hipError_t launch_dfj_solve(const double* Linv, const double* W, int64_t n, const double* v, double* y, double* d,
                             hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(chol_solve_kernel, dim3(1), dim3(kSolveThreads), 0, s, L, U, n, v, y, d);
+    const dim3 grid((unsigned)((n + 3) / 4));
+    hipLaunchKernelGGL(trmv_kernel, grid, dim3(256), 0, s, Linv, n, v, y, 1);
+    hipLaunchKernelGGL(trmv_kernel, grid, dim3(256), 0, s, W, n, y, d, 0);
     return hipGetLastError();
 }
 

@@ -10,7 +10,7 @@
 // transposed (B(k, j) = B[j ldb + k]).  Chunks partition k; each writes its own slice of C.
 //
 // Tiles: BM x BN outputs per workgroup of 256 threads (four wave64 in a 2 x 2 layout, each
-// wave WB x WB blocks of 16 x 16; 128 x 128 or 64 x 64, chosen per launch by the padded work
+// wave WM x WN blocks of 16 x 16; 128 x 128, 64 x 128 or 64 x 64, chosen per launch by the padded work
 // of its problems), k in steps of 16 staged through double-buffered LDS with the next step's
 // global loads in flight during the current step's matrix-core work.  FP64 mode:
 // v_mfma_f64_16x16x4f64, FP64 operands and sums.  FP32 mode: operands rounded to FP32 as they
@@ -106,10 +106,10 @@ constexpr int bcols(int bn)
 }
 
 // Double-buffered LDS staging of BM x BK (A, k-major) and BK x BN (B) operand tiles.
-template <typename TS, int WB>
+template <typename TS, int WM, int WN>
 struct Stage {
-    TS A[2][gbk<TS>()][32 * WB + GPAD];
-    TS B[2][gbk<TS>()][bcols<TS>(32 * WB)];
+    TS A[2][gbk<TS>()][32 * WM + GPAD];
+    TS B[2][gbk<TS>()][bcols<TS>(32 * WN)];
 };
 
 template <typename TS>
@@ -121,18 +121,20 @@ __device__ inline void mfma_step(TS a, TS b, typename GTraits<sizeof(TS) == 4 ? 
 
 // The k loop of one workgroup over [kbeg, kend) for outputs [m0, m0 + BM) x [n0, n0 + BN)
 // (rows < M, columns < N): operands staged to TS (FP64 or FP32) in LDS, matrix-core products
-// accumulated into acc (the wave's WB x WB blocks).  Every load address is clamped into the
+// accumulated into acc (the wave's WM x WN blocks).  Every load address is clamped into the
 // operand (k to kend - 1, columns to N - 1) and out-of-range elements are staged as zeros;
 // runs that lie inside and start on 16-byte aligned rows are read as vectors.
-template <typename TS, typename TA, typename TB, bool BT, int WB>
-__device__ inline void mainloop(Stage<TS, WB>& L, const Operands<TA, TB>& op, int64_t M, int64_t N, int64_t m0,
+template <typename TS, typename TA, typename TB, bool BT, int WM, int WN>
+__device__ inline void mainloop(Stage<TS, WM, WN>& L, const Operands<TA, TB>& op, int64_t M, int64_t N, int64_t m0,
                                 int64_t n0, int64_t kbeg, int64_t kend,
-                                typename GTraits<sizeof(TS) == 4 ? 1 : 0>::acc4 (&acc)[WB][WB])
+                                typename GTraits<sizeof(TS) == 4 ? 1 : 0>::acc4 (&acc)[WM][WN])
 {
-    constexpr int BM = 32 * WB, BN = 32 * WB;
+    constexpr int BM = 32 * WM, BN = 32 * WN;
     constexpr int BK = gbk<TS>();
-    constexpr int E = BM * BK / 256;    // operand elements each thread stages per k step
-    constexpr int TPR = BK / E;         // threads per k-contiguous run of BK
+    constexpr int E = BM * BK / 256;    // A elements each thread stages per k step
+    constexpr int TPR = BK / E;         // threads per k-contiguous run of BK of A
+    constexpr int EB = BN * BK / 256;   // B elements each thread stages per k step
+    constexpr int TPRB = BK / EB;
     const int nk = kend > kbeg ? (int)((kend - kbeg + BK - 1) / BK) : 0;
     const GP<const int32_t> acol = glb(op.acol);
     const GP<const int32_t> bmap = glb(op.bmap);
@@ -146,11 +148,11 @@ __device__ inline void mainloop(Stage<TS, WB>& L, const Operands<TA, TB>& op, in
     const bool a_ok = gma < M;
     const int64_t arow_i = a_ok ? gma : M - 1;
     const GP<const TA> arow_ptr = op.A + (int64_t)(op.arow ? glb(op.arow)[arow_i] : arow_i) * op.lda;
-    // B: row-major -> k = tid / (BN / E), columns (tid % (BN / E)) * E; transposed -> column
-    // tid / TPR, k run (tid % TPR) * E
-    const int bk = BT ? (tid % TPR) * E : tid / (BN / E);
-    const int bj = BT ? tid / TPR : (tid % (BN / E)) * E;
-    TS va[E], vb[E];
+    // B: row-major -> k = tid / (BN / EB), columns (tid % (BN / EB)) * EB; transposed -> column
+    // tid / TPRB, k run (tid % TPRB) * EB
+    const int bk = BT ? (tid % TPRB) * EB : tid / (BN / EB);
+    const int bj = BT ? tid / TPRB : (tid % (BN / EB)) * EB;
+    TS va[E], vb[EB];
 
     auto load = [&](int64_t k0) {
         const int64_t ka = k0 + ak;
@@ -181,14 +183,14 @@ __device__ inline void mainloop(Stage<TS, WB>& L, const Operands<TA, TB>& op, in
             const int64_t bn = n_ok ? gn : N - 1;
             const GP<const TB> brow = op.B + (int64_t)(bmap ? bmap[bn] : bn) * op.ldb;
             const int64_t kb = k0 + bk;
-            if (op.bvec && kb + E <= kend) {
-                loadv<E>(brow + kb, vb);
+            if (op.bvec && kb + EB <= kend) {
+                loadv<EB>(brow + kb, vb);
                 if (!n_ok)
 #pragma unroll
-                    for (int u = 0; u < E; ++u) vb[u] = (TS)0;
+                    for (int u = 0; u < EB; ++u) vb[u] = (TS)0;
             } else {
 #pragma unroll
-                for (int u = 0; u < E; ++u) {
+                for (int u = 0; u < EB; ++u) {
                     const TS v = (TS)brow[kb + u < kend ? kb + u : kend - 1];
                     vb[u] = (n_ok && kb + u < kend) ? v : (TS)0;
                 }
@@ -199,14 +201,14 @@ __device__ inline void mainloop(Stage<TS, WB>& L, const Operands<TA, TB>& op, in
             const int64_t bkk = k_ok ? gk : kend - 1;
             const GP<const TB> brow = op.B + (int64_t)(bmap ? bmap[bkk] : bkk) * op.ldb;
             const int64_t gn = n0 + bj;
-            if (op.bvec && gn + E <= N) {
-                loadv<E>(brow + gn, vb);
+            if (op.bvec && gn + EB <= N) {
+                loadv<EB>(brow + gn, vb);
                 if (!k_ok)
 #pragma unroll
-                    for (int u = 0; u < E; ++u) vb[u] = (TS)0;
+                    for (int u = 0; u < EB; ++u) vb[u] = (TS)0;
             } else {
 #pragma unroll
-                for (int u = 0; u < E; ++u) {
+                for (int u = 0; u < EB; ++u) {
                     const TS v = (TS)brow[gn + u < N ? gn + u : N - 1];
                     vb[u] = (k_ok && gn + u < N) ? v : (TS)0;
                 }
@@ -218,17 +220,21 @@ __device__ inline void mainloop(Stage<TS, WB>& L, const Operands<TA, TB>& op, in
         for (int u = 0; u < E; ++u) L.A[buf][ak + u][ai] = va[u];
         if constexpr (BT) {
 #pragma unroll
-            for (int u = 0; u < E; ++u) L.B[buf][bk + u][bj] = vb[u];
+            for (int u = 0; u < EB; ++u) L.B[buf][bk + u][bj] = vb[u];
         } else {
 #pragma unroll
-            for (int u = 0; u < E; ++u) L.B[buf][bk][skew(bj + u)] = vb[u];
+            for (int u = 0; u < EB; ++u) L.B[buf][bk][skew(bj + u)] = vb[u];
         }
     };
 
-    if (nk > 0) load(kbeg);
-    else
+    if (nk > 0) {
+        load(kbeg);
+    } else {
 #pragma unroll
-        for (int u = 0; u < E; ++u) va[u] = vb[u] = (TS)0;
+        for (int u = 0; u < E; ++u) va[u] = (TS)0;
+#pragma unroll
+        for (int u = 0; u < EB; ++u) vb[u] = (TS)0;
+    }
     store(0);
     __syncthreads();
     for (int it = 0; it < nk; ++it) {
@@ -236,18 +242,18 @@ __device__ inline void mainloop(Stage<TS, WB>& L, const Operands<TA, TB>& op, in
         if (it + 1 < nk) load(kbeg + (int64_t)(it + 1) * BK);
 #pragma unroll
         for (int ks = 0; ks < BK; ks += 4) {
-            TS a[WB], b[WB];
+            TS a[WM], b[WN];
 #pragma unroll
-            for (int bi = 0; bi < WB; ++bi) a[bi] = L.A[cur][ks + lk][wm + bi * 16 + li];
+            for (int bi = 0; bi < WM; ++bi) a[bi] = L.A[cur][ks + lk][wm + bi * 16 + li];
 #pragma unroll
-            for (int bj2 = 0; bj2 < WB; ++bj2) {
+            for (int bj2 = 0; bj2 < WN; ++bj2) {
                 const int j = wn + bj2 * 16 + li;
                 b[bj2] = L.B[cur][ks + lk][BT ? j : skew(j)];
             }
 #pragma unroll
-            for (int bi = 0; bi < WB; ++bi)
+            for (int bi = 0; bi < WM; ++bi)
 #pragma unroll
-                for (int bj2 = 0; bj2 < WB; ++bj2) mfma_step<TS>(a[bi], b[bj2], acc[bi][bj2]);
+                for (int bj2 = 0; bj2 < WN; ++bj2) mfma_step<TS>(a[bi], b[bj2], acc[bi][bj2]);
         }
         if (it + 1 < nk) store(cur ^ 1);
         __syncthreads();
@@ -258,7 +264,7 @@ __device__ inline void mainloop(Stage<TS, WB>& L, const Operands<TA, TB>& op, in
 // workgroups out to the 8 XCDs in turn; workgroup w takes logical tile (w % 8) * per + w / 8,
 // so each XCD works through one contiguous range of tiles (tiles that share operands share
 // that XCD's L2).  Returns false for the padding workgroups of the last round.
-template <int WB>
+template <int WM, int WN>
 __device__ inline bool locate(const GemmProb* __restrict__ probs, int nprob, int64_t nwg, GemmProb& pr, int& z,
                               int64_t& m0, int64_t& n0)
 {
@@ -279,32 +285,32 @@ __device__ inline bool locate(const GemmProb* __restrict__ probs, int nprob, int
     const int rmn = local - z * tmn;
     const int tn_i = rmn / pr.tm;
     const int tm_i = rmn - tn_i * pr.tm;
-    m0 = (int64_t)tm_i * 32 * WB;
-    n0 = (int64_t)tn_i * 32 * WB;
+    m0 = (int64_t)tm_i * 32 * WM;
+    n0 = (int64_t)tn_i * 32 * WN;
     return true;
 }
 
 // Writes the wave's blocks of acc to C (row crow(i), stride ldc), adding to C with kGemmAccumulate.
 // Accumulator layouts (wave64): FP64 D[i][j] in lane j + 16 (i % 4), element i / 4; FP32
 // D[i][j] in lane j + 16 (i / 4), element i % 4.
-template <typename TC, int MODE, int WB, typename ACC>
-__device__ inline void write_tile(const GemmProb& pr, int z, int64_t m0, int64_t n0, const ACC (&acc)[WB][WB])
+template <typename TC, int MODE, int WM, int WN, typename ACC>
+__device__ inline void write_tile(const GemmProb& pr, int z, int64_t m0, int64_t n0, const ACC (&acc)[WM][WN])
 {
-    constexpr int BM = 32 * WB, BN = 32 * WB;
+    constexpr int BM = 32 * WM, BN = 32 * WN;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = (wave >> 1) * (BM / 2), wn = (wave & 1) * (BN / 2);
     const int li = lane & 15, lk = lane >> 4;
     const GP<TC> C = glbw(static_cast<TC*>(pr.C)) + (int64_t)z * pr.cstride;
     auto write_out = [&](auto op) {
 #pragma unroll
-        for (int bi = 0; bi < WB; ++bi)
+        for (int bi = 0; bi < WM; ++bi)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int64_t gm = m0 + wm + bi * 16 + (MODE == 1 ? 4 * lk + r : 4 * r + lk);
                 if (gm >= pr.M) continue;
                 const GP<TC> crow = C + (int64_t)(pr.crow ? glb(pr.crow)[gm] : gm) * pr.ldc;
 #pragma unroll
-                for (int bj2 = 0; bj2 < WB; ++bj2) {
+                for (int bj2 = 0; bj2 < WN; ++bj2) {
                     const int64_t gn = n0 + wn + bj2 * 16 + li;
                     if (gn < pr.N) op(crow + gn, (TC)acc[bi][bj2][r]);
                 }
@@ -314,28 +320,28 @@ __device__ inline void write_tile(const GemmProb& pr, int z, int64_t m0, int64_t
     else write_out([](GP<TC> q, TC v) { *q = v; });
 }
 
-// WB x WB blocks of 16 x 16 per wave, 2 x 2 waves: BM = BN = 32 WB outputs per workgroup
-template <typename TA, typename TB, typename TC, int MODE, bool BT, int WB>
+// WM x WN blocks of 16 x 16 per wave, 2 x 2 waves: BM = 32 WM by BN = 32 WN outputs per workgroup
+template <typename TA, typename TB, typename TC, int MODE, bool BT, int WM, int WN>
 __global__ __launch_bounds__(256, 2) void ggemm_kernel(const GemmProb* __restrict__ probs, int nprob, int64_t nwg)
 {
     typedef typename GTraits<MODE>::TS TS;
     typedef typename GTraits<MODE>::acc4 acc4;
-    __shared__ Stage<TS, WB> L;
+    __shared__ Stage<TS, WM, WN> L;
     GemmProb pr;
     int z;
     int64_t m0, n0;
-    if (!locate<WB>(probs, nprob, nwg, pr, z, m0, n0)) return;
+    if (!locate<WM, WN>(probs, nprob, nwg, pr, z, m0, n0)) return;
     const int64_t kbeg = (int64_t)z * pr.kchunk;
     const int64_t kend = kbeg + pr.kchunk < pr.K ? kbeg + pr.kchunk : pr.K;
     Operands<TA, TB> op{glb(static_cast<const TA*>(pr.A)), pr.arow, pr.acol, pr.lda,
                         glb(static_cast<const TB*>(pr.B)), pr.bmap, pr.ldb, (pr.vec & 1) != 0, (pr.vec & 2) != 0};
-    acc4 acc[WB][WB];
+    acc4 acc[WM][WN];
 #pragma unroll
-    for (int bi = 0; bi < WB; ++bi)
+    for (int bi = 0; bi < WM; ++bi)
 #pragma unroll
-        for (int bj2 = 0; bj2 < WB; ++bj2) acc[bi][bj2] = acc4{0, 0, 0, 0};
-    mainloop<TS, TA, TB, BT, WB>(L, op, pr.M, pr.N, m0, n0, kbeg, kend, acc);
-    write_tile<TC, MODE, WB>(pr, z, m0, n0, acc);
+        for (int bj2 = 0; bj2 < WN; ++bj2) acc[bi][bj2] = acc4{0, 0, 0, 0};
+    mainloop<TS, TA, TB, BT, WM, WN>(L, op, pr.M, pr.N, m0, n0, kbeg, kend, acc);
+    write_tile<TC, MODE, WM, WN>(pr, z, m0, n0, acc);
 }
 
 // Split product (one chunk, B row-major): C = A B over the strong k (FP64 operands, FP64 matrix
@@ -343,48 +349,48 @@ __global__ __launch_bounds__(256, 2) void ggemm_kernel(const GemmProb* __restric
 // written once.  The weak sums come first: their FP32 accumulators go through LDS into the
 // FP64 layout (the two accumulator layouts differ) as the starting values of the FP64 sums, so
 // only one accumulator set is live at a time and the 128 x 128 tile fits in registers.
-template <int WB>
+template <int WM, int WN>
 __global__ __launch_bounds__(256, 2) void gsplit_kernel(const GemmProb* __restrict__ probs, int nprob, int64_t nwg)
 {
     typedef GTraits<0>::acc4 acc64;
     typedef GTraits<1>::acc4 acc32;
-    constexpr int BM = 32 * WB, BN = 32 * WB;
-    __shared__ Stage<double, WB> L;
+    constexpr int BM = 32 * WM, BN = 32 * WN;
+    __shared__ Stage<double, WM, WN> L;
     GemmProb pr;
     int z;
     int64_t m0, n0;
-    if (!locate<WB>(probs, nprob, nwg, pr, z, m0, n0)) return;
+    if (!locate<WM, WN>(probs, nprob, nwg, pr, z, m0, n0)) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = (wave >> 1) * (BM / 2), wn = (wave & 1) * (BN / 2);
     const int li = lane & 15, lk = lane >> 4;
-    static_assert(sizeof(Stage<double, WB>) >= sizeof(float) * BM * (BN + 1), "LDS for the transpose");
+    static_assert(sizeof(Stage<double, WM, WN>) >= sizeof(float) * BM * (BN + 1), "LDS for the transpose");
     float* T = reinterpret_cast<float*>(&L);
     {
-        acc32 acw[WB][WB];
+        acc32 acw[WM][WN];
 #pragma unroll
-        for (int bi = 0; bi < WB; ++bi)
+        for (int bi = 0; bi < WM; ++bi)
 #pragma unroll
-            for (int bj2 = 0; bj2 < WB; ++bj2) acw[bi][bj2] = acc32{0, 0, 0, 0};
-        Stage<float, WB>& Lf = *reinterpret_cast<Stage<float, WB>*>(&L);
+            for (int bj2 = 0; bj2 < WN; ++bj2) acw[bi][bj2] = acc32{0, 0, 0, 0};
+        Stage<float, WM, WN>& Lf = *reinterpret_cast<Stage<float, WM, WN>*>(&L);
         Operands<float, float> op{glb(static_cast<const float*>(pr.A2)), pr.arow, nullptr, pr.lda2,
                                   glb(static_cast<const float*>(pr.B2)), nullptr, pr.ldb2, (pr.vec & 8) != 0,
                                   (pr.vec & 16) != 0};
-        mainloop<float, float, float, false, WB>(Lf, op, pr.M, pr.N, m0, n0, 0, pr.K2, acw);
+        mainloop<float, float, float, false, WM, WN>(Lf, op, pr.M, pr.N, m0, n0, 0, pr.K2, acw);
         // FP32 blocks to LDS in (row, column) order (the main loop ends with a barrier)
 #pragma unroll
-        for (int bi = 0; bi < WB; ++bi)
+        for (int bi = 0; bi < WM; ++bi)
 #pragma unroll
-            for (int bj2 = 0; bj2 < WB; ++bj2)
+            for (int bj2 = 0; bj2 < WN; ++bj2)
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
                     T[(wm + bi * 16 + 4 * lk + r) * (BN + 1) + wn + bj2 * 16 + li] = acw[bi][bj2][r];
     }
     __syncthreads();
-    acc64 acc[WB][WB];
+    acc64 acc[WM][WN];
 #pragma unroll
-    for (int bi = 0; bi < WB; ++bi)
+    for (int bi = 0; bi < WM; ++bi)
 #pragma unroll
-        for (int bj2 = 0; bj2 < WB; ++bj2)
+        for (int bj2 = 0; bj2 < WN; ++bj2)
 #pragma unroll
             for (int r = 0; r < 4; ++r)
                 acc[bi][bj2][r] = (double)T[(wm + bi * 16 + 4 * r + lk) * (BN + 1) + wn + bj2 * 16 + li];
@@ -393,9 +399,9 @@ __global__ __launch_bounds__(256, 2) void gsplit_kernel(const GemmProb* __restri
         Operands<double, double> op{glb(static_cast<const double*>(pr.A)), pr.arow, pr.acol, pr.lda,
                                     glb(static_cast<const double*>(pr.B)), pr.bmap, pr.ldb, (pr.vec & 1) != 0,
                                     (pr.vec & 2) != 0};
-        mainloop<double, double, double, false, WB>(L, op, pr.M, pr.N, m0, n0, 0, pr.K, acc);
+        mainloop<double, double, double, false, WM, WN>(L, op, pr.M, pr.N, m0, n0, 0, pr.K, acc);
     }
-    write_tile<double, 0, WB>(pr, z, m0, n0, acc);
+    write_tile<double, 0, WM, WN>(pr, z, m0, n0, acc);
 }
 
 // One workgroup per target row r: for every tile in list order, the tile's local row of r
@@ -562,26 +568,26 @@ __global__ __launch_bounds__(256) void bound_sum_kernel(const double* __restrict
     if (threadIdx.x == 0) acc[0] += sh[0];
 }
 
-template <int WB>
+template <int WM, int WN>
 hipError_t launch_gsplit_wb(const GemmProb* probs, int nprob, int64_t nwg, hipStream_t s)
 {
     const int64_t grid = ((nwg + 7) / 8) * 8;
     if (grid > INT32_MAX) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((gsplit_kernel<WB>), dim3((unsigned)grid), dim3(256), 0, s, probs, nprob, nwg);
+    hipLaunchKernelGGL((gsplit_kernel<WM, WN>), dim3((unsigned)grid), dim3(256), 0, s, probs, nprob, nwg);
     return hipGetLastError();
 }
 
-template <typename TA, typename TB, typename TC, int MODE, int WB>
+template <typename TA, typename TB, typename TC, int MODE, int WM, int WN>
 hipError_t launch_ggemm_wb(const GemmProb* probs, int nprob, int64_t nwg, bool bt, hipStream_t s)
 {
     const int64_t grid = ((nwg + 7) / 8) * 8;
     if (grid > INT32_MAX) return hipErrorInvalidValue;
     if (bt)
-        hipLaunchKernelGGL((ggemm_kernel<TA, TB, TC, MODE, true, WB>), dim3((unsigned)grid), dim3(256), 0, s, probs,
-                           nprob, nwg);
+        hipLaunchKernelGGL((ggemm_kernel<TA, TB, TC, MODE, true, WM, WN>), dim3((unsigned)grid), dim3(256), 0, s,
+                           probs, nprob, nwg);
     else
-        hipLaunchKernelGGL((ggemm_kernel<TA, TB, TC, MODE, false, WB>), dim3((unsigned)grid), dim3(256), 0, s, probs,
-                           nprob, nwg);
+        hipLaunchKernelGGL((ggemm_kernel<TA, TB, TC, MODE, false, WM, WN>), dim3((unsigned)grid), dim3(256), 0, s,
+                           probs, nprob, nwg);
     return hipGetLastError();
 }
 
@@ -589,9 +595,12 @@ template <typename TA, typename TB, typename TC, int MODE>
 hipError_t launch_ggemm_t(const GemmProb* probs, int nprob, int64_t nwg, int tile, bool bt, hipStream_t s)
 {
     if (nprob <= 0 || nwg <= 0) return hipSuccess;
-    if (tile != 64 && tile != 128) return hipErrorInvalidValue;
-    return tile == 64 ? launch_ggemm_wb<TA, TB, TC, MODE, 2>(probs, nprob, nwg, bt, s)
-                      : launch_ggemm_wb<TA, TB, TC, MODE, 4>(probs, nprob, nwg, bt, s);
+    switch (tile) {
+        case kTile64: return launch_ggemm_wb<TA, TB, TC, MODE, 2, 2>(probs, nprob, nwg, bt, s);
+        case kTile64x128: return launch_ggemm_wb<TA, TB, TC, MODE, 2, 4>(probs, nprob, nwg, bt, s);
+        case kTile128: return launch_ggemm_wb<TA, TB, TC, MODE, 4, 4>(probs, nprob, nwg, bt, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace
@@ -600,15 +609,20 @@ int ggemm_tile(const GemmProb* probs, int nprob)
 {
     // Measured on gfx950 (two workgroups per compute unit for the 128 x 128 tiles, four for
     // 64 x 64): the large tiles run the products of the build 1.1 to 1.9 times as fast per
-    // padded flop (fewer operand bytes per flop), so the small tiles are taken only where
-    // they save at least that much padding.
-    double w64 = 0.0, w128 = 0.0;
+    // padded flop (fewer operand bytes per flop), so smaller tiles are taken only where they
+    // save at least that much padding; 64 x 128 sits between the two (charged 1.25).
+    double w64 = 0.0, w64x128 = 0.0, w128 = 0.0;
     for (int i = 0; i < nprob; ++i) {
         const double k = (double)probs[i].K;
-        w64 += (double)((probs[i].M + 63) / 64 * 64) * (double)((probs[i].N + 63) / 64 * 64) * k;
-        w128 += (double)((probs[i].M + 127) / 128 * 128) * (double)((probs[i].N + 127) / 128 * 128) * k;
+        const double m64 = (double)((probs[i].M + 63) / 64 * 64), m128 = (double)((probs[i].M + 127) / 128 * 128);
+        const double n64 = (double)((probs[i].N + 63) / 64 * 64), n128 = (double)((probs[i].N + 127) / 128 * 128);
+        w64 += m64 * n64 * k;
+        w64x128 += m64 * n128 * k;
+        w128 += m128 * n128 * k;
     }
-    return 1.9 * w64 < w128 ? 64 : 128;
+    const double c64 = 1.9 * w64, c64x128 = 1.25 * w64x128;
+    if (c64 < w128 && c64 < c64x128) return kTile64;
+    return c64x128 < w128 ? kTile64x128 : kTile128;
 }
 
 void ggemm_plan(GemmProb& p, int tile, int asize, int bsize)
@@ -620,8 +634,9 @@ void ggemm_plan(GemmProb& p, int tile, int asize, int bsize)
     };
     p.vec = (p.vec & kGemmAccumulate) | (al(p.A, p.lda, asize) ? 1 : 0) | (al(p.B, p.ldb, bsize) ? 2 : 0) |
             (p.A2 && al(p.A2, p.lda2, 4) ? 8 : 0) | (p.B2 && al(p.B2, p.ldb2, 4) ? 16 : 0);
-    p.tm = (int32_t)((p.M + tile - 1) / tile);
-    p.tn = (int32_t)((p.N + tile - 1) / tile);
+    const int rows = tile_rows(tile), cols = tile_cols(tile);
+    p.tm = (int32_t)((p.M + rows - 1) / rows);
+    p.tn = (int32_t)((p.N + cols - 1) / cols);
     if (p.ksplit < 1) p.ksplit = 1;
     int64_t kc = (p.K + p.ksplit - 1) / p.ksplit;
     kc = ((kc + GBK - 1) / GBK) * GBK;
@@ -648,8 +663,12 @@ hipError_t launch_ggemm_f32_dA(const GemmProb* probs, int nprob, int64_t nwg, in
 hipError_t launch_gsplit(const GemmProb* probs, int nprob, int64_t nwg, int tile, hipStream_t s)
 {
     if (nprob <= 0 || nwg <= 0) return hipSuccess;
-    if (tile != 64 && tile != 128) return hipErrorInvalidValue;
-    return tile == 64 ? launch_gsplit_wb<2>(probs, nprob, nwg, s) : launch_gsplit_wb<4>(probs, nprob, nwg, s);
+    switch (tile) {
+        case kTile64: return launch_gsplit_wb<2, 2>(probs, nprob, nwg, s);
+        case kTile64x128: return launch_gsplit_wb<2, 4>(probs, nprob, nwg, s);
+        case kTile128: return launch_gsplit_wb<4, 4>(probs, nprob, nwg, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_ggemm_f32_dd(const GemmProb* probs, int nprob, int64_t nwg, int tile, bool bt, hipStream_t s)

@@ -35,8 +35,8 @@ struct snk_dfj {
     double* d_Jpp = nullptr;               // [npp][kDfjCart]
     double* d_part = nullptr;              // [naux][nslot][kDfjAuxHerm]
     double* d_Dc = nullptr;                // [naux][kDfjAuxHerm]
-    double* d_L = nullptr;                 // [nauxf][nauxf] Cholesky factor (lower)
-    double* d_U = nullptr;                 // its transpose
+    double* d_L = nullptr;                 // [nauxf][nauxf] L^-1 of the Cholesky factor L (lower)
+    double* d_U = nullptr;                 // its transpose L^-T
     double* d_v = nullptr;
     double* d_y = nullptr;
     double* d_d = nullptr;
@@ -229,11 +229,15 @@ int setup(snk_dfj* c, const snk_basis* b, const snk_basis* a)
     // the metric and its factor (Eq. P_df's V, once per auxiliary basis)
     DFJ_HIP(c, hipMemsetAsync(c->d_status, 0, sizeof(int32_t), c->stream));
     DFJ_HIP(c, launch_dfj_metric(c->d_aux, c->naux, c->d_tab, c->d_L, c->nauxf, c->stream));
-    DFJ_HIP(c, launch_dfj_cholesky(c->d_L, c->nauxf, c->d_U, c->d_status, c->stream));
+    DFJ_HIP(c, launch_dfj_cholesky(c->d_L, c->nauxf, c->d_status, c->stream));
     int32_t status = 0;
     DFJ_HIP(c, hipMemcpyAsync(&status, c->d_status, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
     DFJ_HIP(c, hipStreamSynchronize(c->stream));
     if (status) return dfj_err(c, "auxiliary metric not positive definite (linearly dependent functions)", SNK_E_ARG);
+    // V^-1 = L^-T L^-1: the inverse factor once, so that a build's solve is two triangular
+    // products
+    DFJ_HIP(c, launch_dfj_invert(c->d_L, c->nauxf, c->d_U, c->stream));
+    DFJ_HIP(c, hipStreamSynchronize(c->stream));
     return SNK_OK;
 }
 

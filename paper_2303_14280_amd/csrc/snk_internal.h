@@ -366,8 +366,14 @@ struct RedTile {
     const int32_t* rinv;
     const int32_t* ccol;
 };
-// Output tile (64 or 128) for a launch of these problems (M, N and K filled in): 128 unless
-// 64 saves most of the padded work
+// Output tiles of the grouped products (rows x columns per workgroup)
+constexpr int kTile64 = 64;         // 64 x 64
+constexpr int kTile128 = 128;       // 128 x 128
+constexpr int kTile64x128 = 192;    // 64 x 128
+inline int tile_rows(int tile) { return tile == kTile128 ? 128 : 64; }
+inline int tile_cols(int tile) { return tile == kTile64 ? 64 : 128; }
+// Output tile for a launch of these problems (M, N and K filled in): 128 x 128 unless a
+// smaller tile saves most of the padded work
 int ggemm_tile(const GemmProb* probs, int nprob);
 // asize, bsize: bytes per element of A and B
 void ggemm_plan(GemmProb& p, int tile, int asize, int bsize);
@@ -463,10 +469,13 @@ hipError_t launch_dfj_jpair(int cls, const DfjPrim* pp, int32_t n, const DfjAux*
 hipError_t launch_dfj_jcollect(const DfjShellPair* sp, int32_t nsp, const double* Jpp, double* J, int64_t nbf,
                                hipStream_t s);
 hipError_t launch_dfj_metric(const DfjAux* aux, int32_t naux, const double* tab, double* V, int64_t n, hipStream_t s);
-// in place: the lower triangle of A becomes L (A = L L^T); U = L^T; status set to 1 when A is
-// not positive definite
-hipError_t launch_dfj_cholesky(double* A, int64_t n, double* U, int32_t* status, hipStream_t s);
-hipError_t launch_dfj_solve(const double* L, const double* U, int64_t n, const double* v, double* y, double* d,
+// in place: the lower triangle of A becomes L (A = L L^T); status set to 1 when A is not
+// positive definite
+hipError_t launch_dfj_cholesky(double* A, int64_t n, int32_t* status, hipStream_t s);
+// in place: L becomes L^-1 (lower), W = L^-T (upper); n workgroups, set-up only
+hipError_t launch_dfj_invert(double* L, int64_t n, double* W, hipStream_t s);
+// d = W (Linv v) with Linv = L^-1, W = L^-T: two triangular products (y holds Linv v)
+hipError_t launch_dfj_solve(const double* Linv, const double* W, int64_t n, const double* v, double* y, double* d,
                             hipStream_t s);
 hipError_t launch_dfj_dot(const double* a, const double* b, int64_t n, double* out, hipStream_t s);
 
