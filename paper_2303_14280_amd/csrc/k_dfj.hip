@@ -335,13 +335,20 @@ __device__ __forceinline__ void jp_accumulate(double zp, const double (&P)[3], c
     });
 }
 
+// Eq. J_df in the Hermite basis: one lane per orbital primitive pair p, J_p~ = sum over the
+// auxiliary shells c of workgroup row blockIdx.y (shells [y chunk, (y + 1) chunk)) of
+// sum_c~ (p~|c~) D_c~, the shells staged through LDS in blocks of kAuxBlock.  Splitting the
+// auxiliary shells over workgroup rows fills the device when the orbital pairs are few; the
+// rows' sums go to Jh[y][p][p~] and jpair_finish_kernel adds them in row order.
 template <int LA, int LB>
 __global__ __launch_bounds__(256) void jpair_kernel(const DfjPrim* __restrict__ pp, int32_t n,
                                                     const DfjAux* __restrict__ aux, const double* __restrict__ Dc,
                                                     const int32_t* __restrict__ lbeg,   // [4] aux ranges by l
-                                                    const double* __restrict__ gtab, double* __restrict__ Jpp)
+                                                    const double* __restrict__ gtab, int32_t chunk,
+                                                    double* __restrict__ Jh)
 {
     constexpr int LP = LA + LB;
+    constexpr int NH = nherm(LP);
     __shared__ double tab[kBoysRows * kDfjBoysCols];
     __shared__ DfjAux sa[kAuxBlock];
     __shared__ double sd[kAuxBlock][kDfjAuxHerm];
@@ -351,10 +358,10 @@ __global__ __launch_bounds__(256) void jpair_kernel(const DfjPrim* __restrict__ 
     const DfjPrim q = pp[live ? k : 0];
     const double P[3] = {q.Px, q.Py, q.Pz};
     const double zp = q.za + q.zb;
-    double J[nherm(LP)];
-    sfor<0, nherm(LP)>([&](auto ic) { J[CV(ic)] = 0.0; });
-    const int a_end = lbeg[3];
-    for (int b0 = 0; b0 < a_end; b0 += kAuxBlock) {
+    double J[NH];
+    sfor<0, NH>([&](auto ic) { J[CV(ic)] = 0.0; });
+    const int a_beg = blockIdx.y * chunk, a_end = min(lbeg[3], a_beg + chunk);
+    for (int b0 = a_beg; b0 < a_end; b0 += kAuxBlock) {
         const int nb = min(kAuxBlock, a_end - b0);
         __syncthreads();
         for (int i = threadIdx.x; i < nb; i += blockDim.x) sa[i] = aux[b0 + i];
@@ -370,6 +377,28 @@ __global__ __launch_bounds__(256) void jpair_kernel(const DfjPrim* __restrict__ 
             jp_accumulate<LP, 2>(zp, P, sa[i - b0], sd[i - b0], tab, J);
     }
     if (!live) return;
+    double* out = Jh + ((int64_t)blockIdx.y * n + k) * NH;
+    sfor<0, NH>([&](auto ic) { out[CV(ic)] = J[CV(ic)]; });
+}
+
+// One lane per orbital primitive pair: J_p~ summed over the nchunk rows of jpair_kernel in
+// order, then taken back to the Cartesian pair (Eq. Dp in reverse) and scaled.
+template <int LA, int LB>
+__global__ __launch_bounds__(256) void jpair_finish_kernel(const DfjPrim* __restrict__ pp, int32_t n,
+                                                           const double* __restrict__ Jh, int32_t nchunk,
+                                                           double* __restrict__ Jpp)
+{
+    constexpr int LP = LA + LB;
+    constexpr int NH = nherm(LP);
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const DfjPrim q = pp[k];
+    double J[NH];
+    sfor<0, NH>([&](auto ic) { J[CV(ic)] = Jh[(int64_t)k * NH + CV(ic)]; });
+    for (int c = 1; c < nchunk; ++c) {
+        const double* in = Jh + ((int64_t)c * n + k) * NH;
+        sfor<0, NH>([&](auto ic) { J[CV(ic)] += in[CV(ic)]; });
+    }
     double Ex[LA + 1][LB + 1][LP + 1], Ey[LA + 1][LB + 1][LP + 1], Ez[LA + 1][LB + 1][LP + 1];
     md_e<LA, LB>(q.za, q.zb, q.ABx, Ex);
     md_e<LA, LB>(q.za, q.zb, q.ABy, Ey);
@@ -712,20 +741,35 @@ hipError_t launch_dfj_auxdens(const DfjAux* aux, int32_t naux, const double* d, 
     return hipGetLastError();
 }
 
-hipError_t launch_dfj_jpair(int cls, const DfjPrim* pp, int32_t n, const DfjAux* aux, const double* Dc,
-                            const int32_t* lbeg, const double* tab, double* Jpp, hipStream_t s)
+int dfj_jpair_chunks(int32_t n, int32_t naux)
+{
+    // about 2048 workgroups per class, each row of them at least kAuxBlock / 4 shells
+    const int64_t wg = std::max<int64_t>(1, (n + 255) / 256);
+    const int64_t want = std::max<int64_t>(1, 2048 / wg);
+    const int64_t most = std::max<int64_t>(1, naux / (kAuxBlock / 4));
+    return (int)std::min<int64_t>(want, most);
+}
+
+hipError_t launch_dfj_jpair(int cls, const DfjPrim* pp, int32_t n, const DfjAux* aux, int32_t naux, const double* Dc,
+                            const int32_t* lbeg, const double* tab, double* Jh, double* Jpp, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    const dim3 g((n + 255) / 256), b(256);
+    const int nchunk = dfj_jpair_chunks(n, naux);
+    const int chunk = (naux + nchunk - 1) / nchunk;
+    const dim3 g((n + 255) / 256, nchunk), gf((n + 255) / 256), b(256);
+#define SNK_JP(LA, LB)                                                                                          \
+    hipLaunchKernelGGL((jpair_kernel<LA, LB>), g, b, 0, s, pp, n, aux, Dc, lbeg, tab, chunk, Jh);                \
+    hipLaunchKernelGGL((jpair_finish_kernel<LA, LB>), gf, b, 0, s, pp, n, Jh, nchunk, Jpp)
     switch (cls) {
-        case 0: hipLaunchKernelGGL((jpair_kernel<0, 0>), g, b, 0, s, pp, n, aux, Dc, lbeg, tab, Jpp); break;
-        case 1: hipLaunchKernelGGL((jpair_kernel<1, 0>), g, b, 0, s, pp, n, aux, Dc, lbeg, tab, Jpp); break;
-        case 2: hipLaunchKernelGGL((jpair_kernel<1, 1>), g, b, 0, s, pp, n, aux, Dc, lbeg, tab, Jpp); break;
-        case 3: hipLaunchKernelGGL((jpair_kernel<2, 0>), g, b, 0, s, pp, n, aux, Dc, lbeg, tab, Jpp); break;
-        case 4: hipLaunchKernelGGL((jpair_kernel<2, 1>), g, b, 0, s, pp, n, aux, Dc, lbeg, tab, Jpp); break;
-        case 5: hipLaunchKernelGGL((jpair_kernel<2, 2>), g, b, 0, s, pp, n, aux, Dc, lbeg, tab, Jpp); break;
+        case 0: SNK_JP(0, 0); break;
+        case 1: SNK_JP(1, 0); break;
+        case 2: SNK_JP(1, 1); break;
+        case 3: SNK_JP(2, 0); break;
+        case 4: SNK_JP(2, 1); break;
+        case 5: SNK_JP(2, 2); break;
         default: return hipErrorInvalidValue;
     }
+#undef SNK_JP
     return hipGetLastError();
 }
 

@@ -607,10 +607,10 @@ hipError_t launch_ggemm_t(const GemmProb* probs, int nprob, int64_t nwg, int til
 
 int ggemm_tile(const GemmProb* probs, int nprob)
 {
-    // Measured on gfx950 (two workgroups per compute unit for the 128 x 128 tiles, four for
-    // 64 x 64): the large tiles run the products of the build 1.1 to 1.9 times as fast per
-    // padded flop (fewer operand bytes per flop), so smaller tiles are taken only where they
-    // save at least that much padding; 64 x 128 sits between the two (charged 1.25).
+    // Measured on gfx950 with the build's product shapes (FP64, two workgroups per compute
+    // unit): per padded flop 64 x 128 tiles run at about 0.9 and 64 x 64 tiles at about 0.75 of
+    // the rate of 128 x 128 tiles (more operand bytes per flop), so a smaller tile is taken only
+    // where it saves more padding than that.
     double w64 = 0.0, w64x128 = 0.0, w128 = 0.0;
     for (int i = 0; i < nprob; ++i) {
         const double k = (double)probs[i].K;
@@ -620,7 +620,7 @@ int ggemm_tile(const GemmProb* probs, int nprob)
         w64x128 += m64 * n128 * k;
         w128 += m128 * n128 * k;
     }
-    const double c64 = 1.9 * w64, c64x128 = 1.25 * w64x128;
+    const double c64 = 1.35 * w64, c64x128 = 1.1 * w64x128;
     if (c64 < w128 && c64 < c64x128) return kTile64;
     return c64x128 < w128 ? kTile64x128 : kTile128;
 }

@@ -33,6 +33,7 @@ struct snk_dfj {
     double* d_tab = nullptr;
     double* d_Dh = nullptr;                // [npp][kDfjHerm]
     double* d_Jpp = nullptr;               // [npp][kDfjCart]
+    double* d_jh = nullptr;                // Hermite J partial sums of one class's launch, per auxiliary chunk
     double* d_part = nullptr;              // [naux][nslot][kDfjAuxHerm]
     double* d_Dc = nullptr;                // [naux][kDfjAuxHerm]
     double* d_L = nullptr;                 // [nauxf][nauxf] L^-1 of the Cholesky factor L (lower)
@@ -116,7 +117,7 @@ void free_dfj(snk_dfj* c)
 {
     if (!c) return;
     for (void* p : {(void*)c->d_pp, (void*)c->d_sp, (void*)c->d_aux, (void*)c->d_lbeg, (void*)c->d_tab,
-                    (void*)c->d_Dh, (void*)c->d_Jpp, (void*)c->d_part, (void*)c->d_Dc, (void*)c->d_L, (void*)c->d_U,
+                    (void*)c->d_Dh, (void*)c->d_Jpp, (void*)c->d_jh, (void*)c->d_part, (void*)c->d_Dc, (void*)c->d_L, (void*)c->d_U,
                     (void*)c->d_v, (void*)c->d_y, (void*)c->d_d, (void*)c->d_P, (void*)c->d_J, (void*)c->d_ej,
                     (void*)c->d_status})
         (void)hipFree(p);
@@ -212,6 +213,15 @@ int setup(snk_dfj* c, const snk_basis* b, const snk_basis* a)
     c->lp_slot[5] = c->nslot;
 
     int rc;
+    // the J digestion's workspace: the largest class launch
+    size_t jh = 1;
+    for (int cls = 0; cls < 6; ++cls) {
+        const int32_t n = c->cls_beg[cls + 1] - c->cls_beg[cls];
+        const int lp = kClassLP[cls];
+        if (n > 0)
+            jh = std::max(jh, (size_t)dfj_jpair_chunks(n, c->naux) * n * ((lp + 1) * (lp + 2) * (lp + 3) / 6));
+    }
+    if ((rc = dfj_alloc(c, &c->d_jh, jh))) return rc;
     const std::vector<double> tab = boys_table_cols(kDfjBoysCols);
     const std::vector<int32_t> lb(c->lbeg, c->lbeg + 4);
     if ((rc = dfj_upload(c, &c->d_pp, allpp)) || (rc = dfj_upload(c, &c->d_sp, allsp)) ||
@@ -313,7 +323,8 @@ int snk_dfj_build(snk_dfj* c, const double* P, double* J_out, double* v_out, dou
     DFJ_HIP(c, launch_dfj_auxdens(c->d_aux, c->naux, dd, c->d_Dc, s));
     for (int cls = 0; cls < 6; ++cls)
         DFJ_HIP(c, launch_dfj_jpair(cls, c->d_pp + c->cls_beg[cls], c->cls_beg[cls + 1] - c->cls_beg[cls], c->d_aux,
-                                    c->d_Dc, c->d_lbeg, c->d_tab, c->d_Jpp + (int64_t)c->cls_beg[cls] * kDfjCart, s));
+                                    c->naux, c->d_Dc, c->d_lbeg, c->d_tab, c->d_jh,
+                                    c->d_Jpp + (int64_t)c->cls_beg[cls] * kDfjCart, s));
     DFJ_HIP(c, launch_dfj_jcollect(c->d_sp, c->nsp, c->d_Jpp, dJ, nbf, s));
     if (ej_out) DFJ_HIP(c, launch_dfj_dot(dP, dJ, nb2, c->d_ej, s));
     if (!dev) {

@@ -464,8 +464,12 @@ hipError_t launch_dfj_vaux(int LP, int LC, const DfjPrim* pp, const double* Dh, 
 hipError_t launch_dfj_vfinish(const DfjAux* aux, int32_t naux, const double* part, int32_t nslot, double* v,
                               hipStream_t s);
 hipError_t launch_dfj_auxdens(const DfjAux* aux, int32_t naux, const double* d, double* Dc, hipStream_t s);
-hipError_t launch_dfj_jpair(int cls, const DfjPrim* pp, int32_t n, const DfjAux* aux, const double* Dc,
-                            const int32_t* lbeg, const double* tab, double* Jpp, hipStream_t s);
+// workgroup rows over the auxiliary shells of a J digestion launch of n primitive pairs
+int dfj_jpair_chunks(int32_t n, int32_t naux);
+// Eq. J_df per primitive pair of one class; Jh: workspace of dfj_jpair_chunks(n, naux) * n *
+// nherm(l_A + l_B) doubles
+hipError_t launch_dfj_jpair(int cls, const DfjPrim* pp, int32_t n, const DfjAux* aux, int32_t naux, const double* Dc,
+                            const int32_t* lbeg, const double* tab, double* Jh, double* Jpp, hipStream_t s);
 hipError_t launch_dfj_jcollect(const DfjShellPair* sp, int32_t nsp, const double* Jpp, double* J, int64_t nbf,
                                hipStream_t s);
 hipError_t launch_dfj_metric(const DfjAux* aux, int32_t naux, const double* tab, double* V, int64_t n, hipStream_t s);
