@@ -84,9 +84,11 @@ def phases(st):
 
 
 # HBM bytes per launch of a dominant kernel from the copy-calibrated FETCH_SIZE + WRITE_SIZE
-# counter runs of the same build (profiles/gsplit_config5_mixed_learned.md); valid only for the
-# kernel code those runs measured, so the entry goes when that kernel changes
-PROFILED_TRAFFIC = {"gsplit_kernel (F product, FP32 matrix cores)": 4.512e9}
+# counter runs of the same build (profiles/gsplit_config5_mixed_learned.md,
+# profiles/afg_config2_fp64.md); valid only for the kernel code and batch groups those runs
+# measured, so an entry goes when its kernel changes
+PROFILED_TRAFFIC = {"gsplit_kernel (F product, FP32 matrix cores)": 4.512e9,   # config 5, mixed + learned
+                    "afg_kernel<1,0> (ps, A.F digestion)": 2.821e10}           # config 2, plain FP64
 
 
 def dominant_kernel(st):

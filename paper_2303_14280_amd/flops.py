@@ -76,6 +76,40 @@ def class_flops(cls: int, pair_points: int, prim_pair_points: int) -> float:
     return float(prim_pair_points) * per_prim_pair(la, lb) + float(pair_points) * per_shell_pair(la, lb)
 
 
+def nherm(l: int) -> int:
+    """Hermite components t + u + v <= l."""
+    return (l + 1) * (l + 2) * (l + 3) // 6
+
+
+@lru_cache(maxsize=None)
+def dfj_pair_aux(lp: int, lc: int) -> int:
+    """Flops of one (orbital primitive pair of total angular momentum lp, auxiliary shell lc)
+    term of the Coulomb build's digestion (Sec. II.B, Eqs. pc, md1, cabP-jengine):
+      - P - C, alpha = zeta_p zeta_c / (zeta_p + zeta_c), T = alpha |P - C|^2        12
+      - Boys function F_0..F_N, N = lp + lc, as above                            2 + 22 (N + 1)
+      - (-2 alpha)^n, n <= N                                                     N
+      - Eq. md1: R^(n)_tuv for t + u + v <= N - n; the first of each level one
+        multiply, the others a multiply plus, with a lower index > 1, one fused
+        multiply-add                                                             1, 1 or 3
+      - prefactor 2 pi^(5/2) / (zeta_p zeta_c sqrt(zeta_p + zeta_c))             4
+      - digestion sum_c~ (p~|c~) D_c~ per p~ and its update with the prefactor    2 nherm(lc) + 2
+    The same count serves the v pass (Eq. V_df), which digests the pair's Hermite density
+    against the same integrals."""
+    n_all = lp + lc
+    f = 12 + 2 + 22 * (n_all + 1) + n_all + 4
+    for n in range(n_all + 1):
+        top = n_all - n
+        for t in range(top + 1):
+            for u in range(top + 1 - t):
+                for v in range(top + 1 - t - u):
+                    if t + u + v == 0:
+                        f += 1
+                    else:
+                        k = t if t > 0 else (u if u > 0 else v)
+                        f += 3 if k > 1 else 1
+    return f + nherm(lp) * (2 * nherm(lc) + 2)
+
+
 # MI355X (gfx950) peaks used for roofline fractions
 PEAK_FP64_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12   # 78.6: 256 CU x 4 SIMD x 16 lanes x FMA x 2.4 GHz
 PEAK_FP64_MFMA_TFLOPS = 78.6
