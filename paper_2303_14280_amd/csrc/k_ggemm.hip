@@ -605,8 +605,11 @@ hipError_t launch_ggemm_t(const GemmProb* probs, int nprob, int64_t nwg, int til
 
 }  // namespace
 
+int g_force_tile = 0;
+
 int ggemm_tile(const GemmProb* probs, int nprob)
 {
+    if (g_force_tile) return g_force_tile;
     // Measured on gfx950 with the build's product shapes (FP64, two workgroups per compute
     // unit): per padded flop 64 x 128 tiles run at about 0.9 and 64 x 64 tiles at about 0.75 of
     // the rate of 128 x 128 tiles (more operand bytes per flop), so a smaller tile is taken only

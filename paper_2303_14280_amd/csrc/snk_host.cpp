@@ -2862,6 +2862,14 @@ int snk_debug_gemm_f64(int64_t M, int64_t N, int64_t K, const double* A, int64_t
     return SNK_OK;
 }
 
+int snk_debug_force_tile(int tile)
+{
+    if (tile != 0 && tile != kTile64 && tile != kTile128 && tile != kTile64x128)
+        return arg_error(nullptr, "tile must be 0, 64, 128 or 192");
+    g_force_tile = tile;
+    return SNK_OK;
+}
+
 int snk_debug_mfma_layout(double* out)
 {
     if (!out) return arg_error(nullptr, "NULL output");

@@ -373,8 +373,9 @@ constexpr int kTile64x128 = 192;    // 64 x 128
 inline int tile_rows(int tile) { return tile == kTile128 ? 128 : 64; }
 inline int tile_cols(int tile) { return tile == kTile64 ? 64 : 128; }
 // Output tile for a launch of these problems (M, N and K filled in): 128 x 128 unless a
-// smaller tile saves most of the padded work
+// smaller tile saves most of the padded work; g_force_tile (a test hook, 0 = off) overrides it
 int ggemm_tile(const GemmProb* probs, int nprob);
+extern int g_force_tile;
 // asize, bsize: bytes per element of A and B
 void ggemm_plan(GemmProb& p, int tile, int asize, int bsize);
 int64_t ggemm_workgroups(const GemmProb& p);

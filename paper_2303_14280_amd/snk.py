@@ -144,6 +144,8 @@ def lib():
                                                                    ctypes.c_int64, ctypes.c_int, ctypes.c_void_p,
                                                                    ctypes.c_int64, ctypes.c_int, ctypes.c_void_p]
             L.snk_debug_gemm_f64.restype = ctypes.c_int
+            L.snk_debug_force_tile.argtypes = [ctypes.c_int]
+            L.snk_debug_force_tile.restype = ctypes.c_int
             L.snk_debug_mfma_layout.argtypes = [ctypes.c_void_p]
             L.snk_debug_mfma_layout.restype = ctypes.c_int
             L.snk_ctx_point_order.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
@@ -547,6 +549,10 @@ def boys_device(T_ptr: int, n: int, mmax: int, F_ptr: int, stream: int = 0):
 def debug_gemm_f64(M, N, K, A_ptr, lda, B_ptr, ldb, bt, C_ptr, ldc, stream: int = 0, tile: int = 0):
     _check(lib().snk_debug_gemm_f64(M, N, K, ctypes.c_void_p(A_ptr), lda, ctypes.c_void_p(B_ptr), ldb, int(bt),
                                     ctypes.c_void_p(C_ptr), ldc, int(tile), ctypes.c_void_p(stream) if stream else None))
+
+
+def debug_force_tile(tile: int = 0):
+    _check(lib().snk_debug_force_tile(int(tile)))
 
 
 def debug_mfma_layout() -> np.ndarray:

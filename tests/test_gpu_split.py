@@ -61,3 +61,28 @@ def test_split_with_learned_screen_within_budget():
     say("config 3/4 mixed+learned vs plain FP64: |dE_x| %.3e, FP32 product share %.3f, bound %.3e" %
         (dE, st1["gemm_flops_fp32"] / (st1["gemm_flops_fp32"] + st1["gemm_flops_fp64"]), st1["lowprec_bound"]))
     assert dE <= 1e-6
+
+
+def test_output_tiles_give_identical_products():
+    """Every output tile of the grouped products (64 x 64, 128 x 128, 64 x 128) sums each
+    element over k in the same order, so a mixed split build (FP64 and FP32 matrix-core
+    products, F and K) is bitwise the same whichever tile every launch is forced to."""
+    s = synth.make_system(3)
+    s = s.subset_points(np.arange(0, s.npts, 16))
+    kw = dict(eps_basis=1e-9, screen=snk.SNK_SCREEN_BOUND, eps_skip_energy=1e-6, precision=snk.SNK_MIXED)
+    ctx = snk.Context(s, **kw)
+    out = {}
+    try:
+        for tile in (0, 64, 128, 192):
+            snk.debug_force_tile(tile)
+            out[tile] = ctx.build(s.P)
+    finally:
+        snk.debug_force_tile(0)
+    K0, st0 = out[0]
+    say("forced tiles: E_x %.12f, FP32 product share %.3f" %
+        (st0["ex"], st0["gemm_flops_fp32"] / (st0["gemm_flops_fp32"] + st0["gemm_flops_fp64"])))
+    assert st0["gemm_flops_fp32"] > 0
+    for tile in (64, 128, 192):
+        assert np.array_equal(out[tile][0], K0), tile
+    with pytest.raises(snk.SnkError):
+        snk.debug_force_tile(96)
