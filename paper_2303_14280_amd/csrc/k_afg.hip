@@ -40,7 +40,7 @@ __global__ __launch_bounds__(256) void afg_kernel(const double* __restrict__ px,
                                                   const typename PrimOf<R>::type* __restrict__ prims,
                                                   const int32_t* __restrict__ runs,
                                                   const int32_t* __restrict__ btasks,
-                                                  const double* __restrict__ btask_ab,
+                                                  const double* __restrict__ rowc,
                                                   const int32_t* __restrict__ batch_run_off, int32_t nrun,
                                                   const double* __restrict__ gtab)
 {
@@ -76,10 +76,15 @@ __global__ __launch_bounds__(256) void afg_kernel(const double* __restrict__ px,
         const int32_t* run = runs + (int64_t)r * RS;
         const int b0 = run[0], b1 = run[1];
         int arow[TA];
+        double RA[TA][3];   // centres of the tile's A shells (wave-uniform)
         R Fa[NP][TA][NA], Ga[NP][TA][NA];
         sfor<0, TA>([&](auto kc) {
             constexpr int k = CV(kc);
             arow[k] = run[2 + k];
+            const double* ca = rowc + 3 * (int64_t)(arow[k] >= 0 ? arow[k] : 0);
+            RA[k][0] = ca[0];
+            RA[k][1] = ca[1];
+            RA[k][2] = ca[2];
             sfor<0, NP>([&](auto pc) {
                 constexpr int p = CV(pc);
                 sfor<0, NA>([&](auto ic) {
@@ -121,12 +126,13 @@ __global__ __launch_bounds__(256) void afg_kernel(const double* __restrict__ px,
             });
             if (bt + 1 < b1) fetch(bt + 1);
             const int mask = cur[1];
+            const double* cb = rowc + 3 * (int64_t)brow;
+            const double RB[3] = {cb[0], cb[1], cb[2]};
             bool transposed = false;
             sfor<0, TA>([&](auto kc) {
                 constexpr int k = CV(kc);
                 if (mask & (1 << k)) {
-                    const double* ab = btask_ab + ((int64_t)bt * TA + k) * 3;
-                    const R AB[3] = {(R)ab[0], (R)ab[1], (R)ab[2]};
+                    const R AB[3] = {(R)(RA[k][0] - RB[0]), (R)(RA[k][1] - RB[1]), (R)(RA[k][2] - RB[2])};
                     R Ab[NP][NA][NB];
                     pair_block_n<LA, LB, R, NP, TC>(prims + cur[2 + 2 * k], cur[3 + 2 * k], AB, cx, cy, cz, tab, Ab);
                     const bool offdiag = arow[k] != brow;   // A != B: the transposed block feeds G_B
@@ -198,7 +204,7 @@ hipError_t launch_afg(int la, int lb, const AfgArgs& a, hipStream_t s)
     const bool two = la == 1 && lb == 0 && a.batch_run_off == nullptr;
 #define SNK_AFG_NP(LA, LB, TA, NP, TF, R, FP, PR)                                                                  \
     hipLaunchKernelGGL((afg_kernel<LA, LB, TA, NP, TF, R>), grid, dim3(kBatch / NP), 0, s, a.px, a.py, a.pz, a.pw, \
-                       FP, a.G, a.ld, PR, a.runs, a.btasks, a.btask_ab, a.batch_run_off, a.nrun, a.boys_tab)
+                       FP, a.G, a.ld, PR, a.runs, a.btasks, a.rowc, a.batch_run_off, a.nrun, a.boys_tab)
 #define SNK_AFG_T(LA, LB, TA, TF, R, FP, PR)                                                                       \
     do {                                                                                                          \
         if (two)                                                                                                  \

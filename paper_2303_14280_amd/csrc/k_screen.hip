@@ -760,26 +760,18 @@ __global__ __launch_bounds__(256) void screen_kernel(ScreenArgs a)
             if (mask) {
                 const int64_t slot = bb + sh.carry + rank;
                 int32_t* rec = a.btasks[c] + slot * BS;
-                double* ab = a.btask_ab[c] + slot * 3 * TA;
                 rec[0] = a.shell_row[b];
                 rec[1] = mask;
                 for (int k = 0; k < TA; ++k) {
                     const int ai = t * TA + k;
                     int pb = 0, np = 0;
-                    double x = 0.0, y = 0.0, z = 0.0;
                     if (mask & (1 << k)) {
-                        const PairHdr h = a.pairs[pair_index(actA[ai], b)];
+                        const PairHdr& h = a.pairs[pair_index(actA[ai], b)];
                         pb = h.prim_begin;
                         np = h.nprim;
-                        x = h.ABx;
-                        y = h.ABy;
-                        z = h.ABz;
                     }
                     rec[2 + 2 * k] = pb;
                     rec[3 + 2 * k] = np;
-                    ab[3 * k] = x;
-                    ab[3 * k + 1] = y;
-                    ab[3 * k + 2] = z;
                 }
             }
             __syncthreads();

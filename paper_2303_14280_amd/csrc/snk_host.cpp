@@ -90,7 +90,6 @@ struct snk_ctx {
     PrimPair* d_prims = nullptr;
     int32_t* d_runs[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     int32_t* d_btasks[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-    double* d_btask_ab[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     int32_t nrun[6] = {0, 0, 0, 0, 0, 0};
     int64_t ntask[6] = {0, 0, 0, 0, 0, 0};        // shell pairs of a class evaluated at every batch
     int64_t task_prims[6] = {0, 0, 0, 0, 0, 0};   // surviving primitive pairs summed over those pairs
@@ -194,6 +193,7 @@ struct snk_ctx {
     int32_t* d_dcount = nullptr;        // [3][max_group_tiles]
     int32_t* d_shell_l = nullptr;
     int32_t* d_shell_row = nullptr;
+    double* d_rowc = nullptr;           // [nbf][3] centre of the shell of each basis function
     int32_t max_group_batches = 0;
     double* d_U = nullptr;
     int32_t* d_counts = nullptr;
@@ -235,7 +235,6 @@ struct snk_ctx {
     PairFeat* d_ne_feat = nullptr;
     int32_t* d_pool_runs[12] = {};
     int32_t* d_pool_bt[12] = {};
-    double* d_pool_ab[12] = {};
     int64_t cap_runs[12] = {};
     int64_t cap_bt[12] = {};
 
@@ -808,7 +807,6 @@ int build_runs(snk_ctx* c)
             if (c->sl[sh] == LB) SB.push_back(sh);
         }
         std::vector<int32_t> runs, bt;
-        std::vector<double> bab;
         int64_t ntask = 0, nprim = 0;
         for (size_t t0 = 0; t0 < SA.size(); t0 += TA) {
             std::vector<int32_t> rec(RS, -1);
@@ -817,7 +815,6 @@ int build_runs(snk_ctx* c)
                 if (t0 + k < SA.size()) rec[2 + k] = c->sfn[SA[t0 + k]];
             for (int b : SB) {
                 std::vector<int32_t> brec(BS, 0);
-                std::vector<double> ab(3 * TA, 0.0);
                 brec[0] = c->sfn[b];
                 int mask = 0;
                 for (int k = 0; k < TA && t0 + k < SA.size(); ++k) {
@@ -829,16 +826,12 @@ int build_runs(snk_ctx* c)
                     mask |= 1 << k;
                     brec[2 + 2 * k] = h.prim_begin;
                     brec[3 + 2 * k] = h.nprim;
-                    ab[3 * k] = h.ABx;
-                    ab[3 * k + 1] = h.ABy;
-                    ab[3 * k + 2] = h.ABz;
                     ntask += 1;
                     nprim += h.nprim;
                 }
                 if (!mask) continue;
                 brec[1] = mask;
                 bt.insert(bt.end(), brec.begin(), brec.end());
-                bab.insert(bab.end(), ab.begin(), ab.end());
             }
             rec[1] = (int32_t)(bt.size() / BS);
             if (rec[1] > rec[0]) runs.insert(runs.end(), rec.begin(), rec.end());
@@ -849,7 +842,6 @@ int build_runs(snk_ctx* c)
         int rc = upload(c, &c->d_runs[cl], runs);
         if (rc) return rc;
         if ((rc = upload(c, &c->d_btasks[cl], bt))) return rc;
-        if ((rc = upload(c, &c->d_btask_ab[cl], bab))) return rc;
     }
     return SNK_OK;
 }
@@ -968,11 +960,9 @@ int ensure_pools(snk_ctx* c, int k, int64_t nrun, int64_t nbt)
     }
     if (nbt > c->cap_bt[k]) {
         (void)hipFree(c->d_pool_bt[k]);
-        (void)hipFree(c->d_pool_ab[k]);
         const int64_t cap = std::max<int64_t>(nbt + nbt / 4, 4096);
         int rc = dalloc(c, &c->d_pool_bt[k], (size_t)cap * (2 + 2 * TA));
         if (rc) return rc;
-        if ((rc = dalloc(c, &c->d_pool_ab[k], (size_t)cap * 3 * TA))) return rc;
         c->cap_bt[k] = cap;
     }
     return SNK_OK;
@@ -989,7 +979,6 @@ void free_ctx(snk_ctx* c)
     for (int k = 0; k < 6; ++k) {
         (void)hipFree(c->d_runs[k]);
         (void)hipFree(c->d_btasks[k]);
-        (void)hipFree(c->d_btask_ab[k]);
     }
     (void)hipFree(c->d_px);
     (void)hipFree(c->d_py);
@@ -1071,6 +1060,7 @@ void free_ctx(snk_ctx* c)
     (void)hipFree(c->d_dcount);
     (void)hipFree(c->d_shell_l);
     (void)hipFree(c->d_shell_row);
+    (void)hipFree(c->d_rowc);
     (void)hipFree(c->d_U);
     (void)hipFree(c->d_lun);
     (void)hipFree(c->d_fmax);
@@ -1101,7 +1091,6 @@ void free_ctx(snk_ctx* c)
         (void)hipFree(c->d_bro[k]);
         (void)hipFree(c->d_pool_runs[k]);
         (void)hipFree(c->d_pool_bt[k]);
-        (void)hipFree(c->d_pool_ab[k]);
     }
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
@@ -1272,6 +1261,14 @@ int snk_ctx_create(const snk_basis* basis, const snk_grid* grid, const double* w
     // angular momentum and first function of every shell (screens and tile row lists)
     CREATE_CHECK(upload(c, &c->d_shell_l, c->sl));
     CREATE_CHECK(upload(c, &c->d_shell_row, c->sfn));
+    {
+        // the A.F kernels form R_A - R_B from these (the pair table's own difference)
+        std::vector<double> rowc(3 * (size_t)c->nbf, 0.0);
+        for (int sh = 0; sh < c->nshell; ++sh)
+            for (int k = 0; k < ncart(c->sl[sh]); ++k)
+                for (int d = 0; d < 3; ++d) rowc[3 * (size_t)(c->sfn[sh] + k) + d] = c->scen[3 * sh + d];
+        CREATE_CHECK(upload(c, &c->d_rowc, rowc));
+    }
 
     // workspace
     const int64_t nbf = c->nbf;
@@ -2149,7 +2146,6 @@ int group_until_G(snk_ctx* c, const Group& g, const double* dP, bool timed, Grou
             if (rc) return rc;
             sa.runs[k] = c->d_pool_runs[k];
             sa.btasks[k] = c->d_pool_bt[k];
-            sa.btask_ab[k] = c->d_pool_ab[k];
             sa.batch_run_off[k] = c->d_bro[k];
             const double avg_prims = c->ntask[cl] ? (double)c->task_prims[cl] / (double)c->ntask[cl] : 0.0;
             for (int j = 0; j < nb; ++j) {
@@ -2204,6 +2200,7 @@ int group_until_G(snk_ctx* c, const Group& g, const double* dP, bool timed, Grou
     a.pairs = c->d_pairs;
     a.prims = c->d_prims;
     a.prims32 = c->d_prims32;
+    a.rowc = c->d_rowc;
     a.nbatch = nb;
     a.boys_tab = c->d_boys;
     for (int cl = 0; cl < 6; ++cl) {
@@ -2214,13 +2211,11 @@ int group_until_G(snk_ctx* c, const Group& g, const double* dP, bool timed, Grou
             if (screen) {
                 a.runs = c->d_pool_runs[k];
                 a.btasks = c->d_pool_bt[k];
-                a.btask_ab = c->d_pool_ab[k];
                 a.batch_run_off = c->d_bro[k];
                 a.nrun = 0;
             } else {
                 a.runs = c->d_runs[cl];
                 a.btasks = c->d_btasks[cl];
-                a.btask_ab = c->d_btask_ab[cl];
                 a.batch_run_off = nullptr;
                 a.nrun = c->nrun[cl];
             }

@@ -54,12 +54,13 @@ struct ShellDev {
 // A.F work of one (l_A, l_B) class is organised in runs.  A run fixes a tile of up
 // to kTileA[class] A shells whose F rows and G accumulators stay in registers; it
 // lists B tasks, each a B shell with the pairs (a_k, B) of the tile to evaluate.
-// Runs and B tasks are int32 records, with the pair geometry beside them:
+// Runs and B tasks are int32 records:
 //   run:   [b_begin, b_end, arow_0 .. arow_{TA-1}]                 (arow = -1: empty slot)
 //   btask: [brow, mask, prim_begin_0, nprim_0, .., prim_begin_{TA-1}, nprim_{TA-1}]
 //          (bit k of mask: pair (a_k, B) present; its primitive pairs are
 //           prims[prim_begin_k .. prim_begin_k + nprim_k))
-//   btask_ab: [btask][k][3] doubles, R_A - R_B of pair k
+// The pair geometry R_A - R_B comes from the shell centres by basis-function row (rowc), the
+// same difference the pair table holds.
 constexpr int kMaxTile = 8;
 constexpr int kTileA[6] = {4, 2, 2, 1, 1, 1};   // ss, ps, pp, ds, dp, dd
 // A tiles of the FP32 lists (list 6 + class): FP32 registers are half as wide, so twice the
@@ -96,7 +97,7 @@ struct AfgArgs {
     bool lowp;                      // evaluate in FP32 (reduced-precision blocks)
     const int32_t* runs;            // run records of one class
     const int32_t* btasks;          // B-task records of that class
-    const double* btask_ab;         // R_A - R_B per B task and tile slot
+    const double* rowc;             // [rows][3] centre of the shell of each basis function
     const int32_t* batch_run_off;   // [nbatch+1] per-batch run ranges, or nullptr: all runs for all batches
     int32_t nrun;
     int32_t nbatch;
@@ -121,7 +122,6 @@ struct ScreenArgs {
     const int64_t* bt_base;     // [nlist][nbatch+1]
     int32_t* runs[12];
     int32_t* btasks[12];
-    double* btask_ab[12];
     int32_t* batch_run_off[12]; // [nbatch+1]
     const float* est;           // learned screen: [nbatch][nne] log2 block estimate, or nullptr
     const int32_t* thr;         // learned screen: [nbatch] first kept estimate bin
