@@ -29,10 +29,10 @@ int snk_boys_device(const double* T, int64_t n, int mmax, double* F_out, void* s
  * snk_debug_gemm_f64: C = A op(B) with the library's grouped FP64 matrix-core product (one
  *   problem) on device pointers: A is M x K row-major (lda), B is K x N row-major (ldb) or,
  *   with bt != 0, N x K row-major; C is M x N row-major (ldc).  tile: output tile of the
- *   kernel, 64 (64 x 64), 128 (128 x 128) or 192 (64 rows x 128 columns), or 0 for the
- *   library's own choice.  Synchronous on `stream`.
+ *   kernel, 64 (64 x 64), 128 (128 x 128), 192 (64 rows x 128 columns) or 384 (128 rows x
+ *   256 columns), or 0 for the library's own choice.  Synchronous on `stream`.
  * snk_debug_force_tile: every grouped product launched afterwards in the process uses this
- *   output tile (64, 128 or 192 as for snk_debug_gemm_f64), or the library's own choice again
+ *   output tile (64, 128, 192 or 384 as for snk_debug_gemm_f64), or the library's own choice again
  *   for 0; process-wide, not thread-safe.  SNK_E_ARG for any other value.
  * snk_debug_mfma_layout: writes 256 doubles to host memory `out`: element 4*lane + r of
  *   one v_mfma_f64_16x16x4f64 whose inputs encode D[i][j] = 100 j + i (layout check).

@@ -105,11 +105,18 @@ constexpr int bcols(int bn)
     return c;
 }
 
+// Workgroup shape: 2 x GN waves (128 GN threads), each wave WM x WN blocks of 16 x 16, so
+// BM = 32 WM rows and BN = 16 WN GN columns of output.
+template <int GN>
+constexpr int nthreads() { return 128 * GN; }
+template <int WN, int GN>
+constexpr int tile_n() { return 16 * WN * GN; }
+
 // Double-buffered LDS staging of BM x BK (A, k-major) and BK x BN (B) operand tiles.
-template <typename TS, int WM, int WN>
+template <typename TS, int WM, int WN, int GN>
 struct Stage {
     TS A[2][gbk<TS>()][32 * WM + GPAD];
-    TS B[2][gbk<TS>()][bcols<TS>(32 * WN)];
+    TS B[2][gbk<TS>()][bcols<TS>(tile_n<WN, GN>())];
 };
 
 template <typename TS>
@@ -124,22 +131,24 @@ __device__ inline void mfma_step(TS a, TS b, typename GTraits<sizeof(TS) == 4 ? 
 // accumulated into acc (the wave's WM x WN blocks).  Every load address is clamped into the
 // operand (k to kend - 1, columns to N - 1) and out-of-range elements are staged as zeros;
 // runs that lie inside and start on 16-byte aligned rows are read as vectors.
-template <typename TS, typename TA, typename TB, bool BT, int WM, int WN>
-__device__ inline void mainloop(Stage<TS, WM, WN>& L, const Operands<TA, TB>& op, int64_t M, int64_t N, int64_t m0,
-                                int64_t n0, int64_t kbeg, int64_t kend,
+template <typename TS, typename TA, typename TB, bool BT, int WM, int WN, int GN>
+__device__ inline void mainloop(Stage<TS, WM, WN, GN>& L, const Operands<TA, TB>& op, int64_t M, int64_t N,
+                                int64_t m0, int64_t n0, int64_t kbeg, int64_t kend,
                                 typename GTraits<sizeof(TS) == 4 ? 1 : 0>::acc4 (&acc)[WM][WN])
 {
-    constexpr int BM = 32 * WM, BN = 32 * WN;
+    constexpr int NT = nthreads<GN>();
+    constexpr int BM = 32 * WM, BN = tile_n<WN, GN>();
     constexpr int BK = gbk<TS>();
-    constexpr int E = BM * BK / 256;    // A elements each thread stages per k step
+    constexpr int E = BM * BK / NT;     // A elements each thread stages per k step
     constexpr int TPR = BK / E;         // threads per k-contiguous run of BK of A
-    constexpr int EB = BN * BK / 256;   // B elements each thread stages per k step
+    constexpr int EB = BN * BK / NT;    // B elements each thread stages per k step
     constexpr int TPRB = BK / EB;
+    static_assert(BM * BK == NT * E && BN * BK == NT * EB, "whole runs per thread");
     const int nk = kend > kbeg ? (int)((kend - kbeg + BK - 1) / BK) : 0;
     const GP<const int32_t> acol = glb(op.acol);
     const GP<const int32_t> bmap = glb(op.bmap);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = (wave >> 1) * (BM / 2), wn = (wave & 1) * (BN / 2);
+    const int wm = (wave / GN) * (BM / 2), wn = (wave % GN) * (BN / GN);
     const int li = lane & 15, lk = lane >> 4;
 
     // A row tid / TPR, k run (tid % TPR) * E; rows past M read row M - 1 and stage zeros
@@ -264,7 +273,7 @@ __device__ inline void mainloop(Stage<TS, WM, WN>& L, const Operands<TA, TB>& op
 // workgroups out to the 8 XCDs in turn; workgroup w takes logical tile (w % 8) * per + w / 8,
 // so each XCD works through one contiguous range of tiles (tiles that share operands share
 // that XCD's L2).  Returns false for the padding workgroups of the last round.
-template <int WM, int WN>
+template <int WM, int WN, int GN>
 __device__ inline bool locate(const GemmProb* __restrict__ probs, int nprob, int64_t nwg, GemmProb& pr, int& z,
                               int64_t& m0, int64_t& n0)
 {
@@ -286,19 +295,19 @@ __device__ inline bool locate(const GemmProb* __restrict__ probs, int nprob, int
     const int tn_i = rmn / pr.tm;
     const int tm_i = rmn - tn_i * pr.tm;
     m0 = (int64_t)tm_i * 32 * WM;
-    n0 = (int64_t)tn_i * 32 * WN;
+    n0 = (int64_t)tn_i * tile_n<WN, GN>();
     return true;
 }
 
 // Writes the wave's blocks of acc to C (row crow(i), stride ldc), adding to C with kGemmAccumulate.
 // Accumulator layouts (wave64): FP64 D[i][j] in lane j + 16 (i % 4), element i / 4; FP32
 // D[i][j] in lane j + 16 (i / 4), element i % 4.
-template <typename TC, int MODE, int WM, int WN, typename ACC>
+template <typename TC, int MODE, int WM, int WN, int GN, typename ACC>
 __device__ inline void write_tile(const GemmProb& pr, int z, int64_t m0, int64_t n0, const ACC (&acc)[WM][WN])
 {
-    constexpr int BM = 32 * WM, BN = 32 * WN;
+    constexpr int BM = 32 * WM, BN = tile_n<WN, GN>();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int wm = (wave >> 1) * (BM / 2), wn = (wave & 1) * (BN / 2);
+    const int wm = (wave / GN) * (BM / 2), wn = (wave % GN) * (BN / GN);
     const int li = lane & 15, lk = lane >> 4;
     const GP<TC> C = glbw(static_cast<TC*>(pr.C)) + (int64_t)z * pr.cstride;
     auto write_out = [&](auto op) {
@@ -320,17 +329,19 @@ __device__ inline void write_tile(const GemmProb& pr, int z, int64_t m0, int64_t
     else write_out([](GP<TC> q, TC v) { *q = v; });
 }
 
-// WM x WN blocks of 16 x 16 per wave, 2 x 2 waves: BM = 32 WM by BN = 32 WN outputs per workgroup
-template <typename TA, typename TB, typename TC, int MODE, bool BT, int WM, int WN>
-__global__ __launch_bounds__(256, 2) void ggemm_kernel(const GemmProb* __restrict__ probs, int nprob, int64_t nwg)
+// WM x WN blocks of 16 x 16 per wave, 2 x GN waves: BM = 32 WM by BN = 16 WN GN outputs per
+// workgroup (two workgroups of 256 threads or one of 512 per compute unit)
+template <typename TA, typename TB, typename TC, int MODE, bool BT, int WM, int WN, int GN>
+__global__ __launch_bounds__(nthreads<GN>(), 512 / nthreads<GN>()) void ggemm_kernel(const GemmProb* __restrict__ probs,
+                                                                                      int nprob, int64_t nwg)
 {
     typedef typename GTraits<MODE>::TS TS;
     typedef typename GTraits<MODE>::acc4 acc4;
-    __shared__ Stage<TS, WM, WN> L;
+    __shared__ Stage<TS, WM, WN, GN> L;
     GemmProb pr;
     int z;
     int64_t m0, n0;
-    if (!locate<WM, WN>(probs, nprob, nwg, pr, z, m0, n0)) return;
+    if (!locate<WM, WN, GN>(probs, nprob, nwg, pr, z, m0, n0)) return;
     const int64_t kbeg = (int64_t)z * pr.kchunk;
     const int64_t kend = kbeg + pr.kchunk < pr.K ? kbeg + pr.kchunk : pr.K;
     Operands<TA, TB> op{glb(static_cast<const TA*>(pr.A)), pr.arow, pr.acol, pr.lda,
@@ -340,8 +351,8 @@ __global__ __launch_bounds__(256, 2) void ggemm_kernel(const GemmProb* __restric
     for (int bi = 0; bi < WM; ++bi)
 #pragma unroll
         for (int bj2 = 0; bj2 < WN; ++bj2) acc[bi][bj2] = acc4{0, 0, 0, 0};
-    mainloop<TS, TA, TB, BT, WM, WN>(L, op, pr.M, pr.N, m0, n0, kbeg, kend, acc);
-    write_tile<TC, MODE, WM, WN>(pr, z, m0, n0, acc);
+    mainloop<TS, TA, TB, BT, WM, WN, GN>(L, op, pr.M, pr.N, m0, n0, kbeg, kend, acc);
+    write_tile<TC, MODE, WM, WN, GN>(pr, z, m0, n0, acc);
 }
 
 // Split product (one chunk, B row-major): C = A B over the strong k (FP64 operands, FP64 matrix
@@ -349,59 +360,73 @@ __global__ __launch_bounds__(256, 2) void ggemm_kernel(const GemmProb* __restric
 // written once.  The weak sums come first: their FP32 accumulators go through LDS into the
 // FP64 layout (the two accumulator layouts differ) as the starting values of the FP64 sums, so
 // only one accumulator set is live at a time and the 128 x 128 tile fits in registers.
-template <int WM, int WN>
-__global__ __launch_bounds__(256, 2) void gsplit_kernel(const GemmProb* __restrict__ probs, int nprob, int64_t nwg)
+template <int WM, int WN, int GN>
+__global__ __launch_bounds__(nthreads<GN>(), 512 / nthreads<GN>()) void gsplit_kernel(const GemmProb* __restrict__ probs,
+                                                                                       int nprob, int64_t nwg)
 {
     typedef GTraits<0>::acc4 acc64;
     typedef GTraits<1>::acc4 acc32;
-    constexpr int BM = 32 * WM, BN = 32 * WN;
-    __shared__ Stage<double, WM, WN> L;
+    constexpr int BM = 32 * WM, BN = tile_n<WN, GN>();
+    __shared__ Stage<double, WM, WN, GN> L;
     GemmProb pr;
     int z;
     int64_t m0, n0;
-    if (!locate<WM, WN>(probs, nprob, nwg, pr, z, m0, n0)) return;
+    if (!locate<WM, WN, GN>(probs, nprob, nwg, pr, z, m0, n0)) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int wm = (wave >> 1) * (BM / 2), wn = (wave & 1) * (BN / 2);
+    const int wm = (wave / GN) * (BM / 2), wn = (wave % GN) * (BN / GN);
     const int li = lane & 15, lk = lane >> 4;
-    static_assert(sizeof(Stage<double, WM, WN>) >= sizeof(float) * BM * (BN + 1), "LDS for the transpose");
+    // the transpose goes through the staging LDS in NH column parts when it cannot hold the
+    // whole tile at once
+    constexpr int NH = sizeof(Stage<double, WM, WN, GN>) >= sizeof(float) * BM * (BN + 1) ? 1 : 2;
+    constexpr int HC = BN / NH;
+    static_assert(sizeof(Stage<double, WM, WN, GN>) >= sizeof(float) * BM * (HC + 1), "LDS for the transpose");
+    static_assert(BN / GN <= HC && HC % (BN / GN) == 0, "each wave's columns within one part");
     float* T = reinterpret_cast<float*>(&L);
-    {
-        acc32 acw[WM][WN];
-#pragma unroll
-        for (int bi = 0; bi < WM; ++bi)
-#pragma unroll
-            for (int bj2 = 0; bj2 < WN; ++bj2) acw[bi][bj2] = acc32{0, 0, 0, 0};
-        Stage<float, WM, WN>& Lf = *reinterpret_cast<Stage<float, WM, WN>*>(&L);
-        Operands<float, float> op{glb(static_cast<const float*>(pr.A2)), pr.arow, nullptr, pr.lda2,
-                                  glb(static_cast<const float*>(pr.B2)), nullptr, pr.ldb2, (pr.vec & 8) != 0,
-                                  (pr.vec & 16) != 0};
-        mainloop<float, float, float, false, WM, WN>(Lf, op, pr.M, pr.N, m0, n0, 0, pr.K2, acw);
-        // FP32 blocks to LDS in (row, column) order (the main loop ends with a barrier)
-#pragma unroll
-        for (int bi = 0; bi < WM; ++bi)
-#pragma unroll
-            for (int bj2 = 0; bj2 < WN; ++bj2)
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    T[(wm + bi * 16 + 4 * lk + r) * (BN + 1) + wn + bj2 * 16 + li] = acw[bi][bj2][r];
-    }
-    __syncthreads();
-    acc64 acc[WM][WN];
+    acc32 acw[WM][WN];
 #pragma unroll
     for (int bi = 0; bi < WM; ++bi)
 #pragma unroll
-        for (int bj2 = 0; bj2 < WN; ++bj2)
+        for (int bj2 = 0; bj2 < WN; ++bj2) acw[bi][bj2] = acc32{0, 0, 0, 0};
+    {
+        Stage<float, WM, WN, GN>& Lf = *reinterpret_cast<Stage<float, WM, WN, GN>*>(&L);
+        Operands<float, float> op{glb(static_cast<const float*>(pr.A2)), pr.arow, nullptr, pr.lda2,
+                                  glb(static_cast<const float*>(pr.B2)), nullptr, pr.ldb2, (pr.vec & 8) != 0,
+                                  (pr.vec & 16) != 0};
+        mainloop<float, float, float, false, WM, WN, GN>(Lf, op, pr.M, pr.N, m0, n0, 0, pr.K2, acw);
+    }
+    // FP32 blocks to LDS in (row, column) order and back in the FP64 accumulator layout (the
+    // main loop ends with a barrier)
+    acc64 acc[WM][WN];
+    const int part = wn / HC, wc = wn - part * HC;
+    for (int h = 0; h < NH; ++h) {
+        if (part == h) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-                acc[bi][bj2][r] = (double)T[(wm + bi * 16 + 4 * r + lk) * (BN + 1) + wn + bj2 * 16 + li];
-    __syncthreads();   // the FP64 main loop restages operands in the same LDS
+            for (int bi = 0; bi < WM; ++bi)
+#pragma unroll
+                for (int bj2 = 0; bj2 < WN; ++bj2)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        T[(wm + bi * 16 + 4 * lk + r) * (HC + 1) + wc + bj2 * 16 + li] = acw[bi][bj2][r];
+        }
+        __syncthreads();
+        if (part == h) {
+#pragma unroll
+            for (int bi = 0; bi < WM; ++bi)
+#pragma unroll
+                for (int bj2 = 0; bj2 < WN; ++bj2)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        acc[bi][bj2][r] = (double)T[(wm + bi * 16 + 4 * r + lk) * (HC + 1) + wc + bj2 * 16 + li];
+        }
+        __syncthreads();   // the next part, then the FP64 main loop, restage the same LDS
+    }
     {
         Operands<double, double> op{glb(static_cast<const double*>(pr.A)), pr.arow, pr.acol, pr.lda,
                                     glb(static_cast<const double*>(pr.B)), pr.bmap, pr.ldb, (pr.vec & 1) != 0,
                                     (pr.vec & 2) != 0};
-        mainloop<double, double, double, false, WM, WN>(L, op, pr.M, pr.N, m0, n0, 0, pr.K, acc);
+        mainloop<double, double, double, false, WM, WN, GN>(L, op, pr.M, pr.N, m0, n0, 0, pr.K, acc);
     }
-    write_tile<double, 0, WM, WN>(pr, z, m0, n0, acc);
+    write_tile<double, 0, WM, WN, GN>(pr, z, m0, n0, acc);
 }
 
 // One workgroup per target row r: for every tile in list order, the tile's local row of r
@@ -568,26 +593,27 @@ __global__ __launch_bounds__(256) void bound_sum_kernel(const double* __restrict
     if (threadIdx.x == 0) acc[0] += sh[0];
 }
 
-template <int WM, int WN>
+template <int WM, int WN, int GN>
 hipError_t launch_gsplit_wb(const GemmProb* probs, int nprob, int64_t nwg, hipStream_t s)
 {
     const int64_t grid = ((nwg + 7) / 8) * 8;
     if (grid > INT32_MAX) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((gsplit_kernel<WM, WN>), dim3((unsigned)grid), dim3(256), 0, s, probs, nprob, nwg);
+    hipLaunchKernelGGL((gsplit_kernel<WM, WN, GN>), dim3((unsigned)grid), dim3(nthreads<GN>()), 0, s, probs, nprob,
+                       nwg);
     return hipGetLastError();
 }
 
-template <typename TA, typename TB, typename TC, int MODE, int WM, int WN>
+template <typename TA, typename TB, typename TC, int MODE, int WM, int WN, int GN>
 hipError_t launch_ggemm_wb(const GemmProb* probs, int nprob, int64_t nwg, bool bt, hipStream_t s)
 {
     const int64_t grid = ((nwg + 7) / 8) * 8;
     if (grid > INT32_MAX) return hipErrorInvalidValue;
     if (bt)
-        hipLaunchKernelGGL((ggemm_kernel<TA, TB, TC, MODE, true, WM, WN>), dim3((unsigned)grid), dim3(256), 0, s,
-                           probs, nprob, nwg);
+        hipLaunchKernelGGL((ggemm_kernel<TA, TB, TC, MODE, true, WM, WN, GN>), dim3((unsigned)grid),
+                           dim3(nthreads<GN>()), 0, s, probs, nprob, nwg);
     else
-        hipLaunchKernelGGL((ggemm_kernel<TA, TB, TC, MODE, false, WM, WN>), dim3((unsigned)grid), dim3(256), 0, s,
-                           probs, nprob, nwg);
+        hipLaunchKernelGGL((ggemm_kernel<TA, TB, TC, MODE, false, WM, WN, GN>), dim3((unsigned)grid),
+                           dim3(nthreads<GN>()), 0, s, probs, nprob, nwg);
     return hipGetLastError();
 }
 
@@ -596,9 +622,10 @@ hipError_t launch_ggemm_t(const GemmProb* probs, int nprob, int64_t nwg, int til
 {
     if (nprob <= 0 || nwg <= 0) return hipSuccess;
     switch (tile) {
-        case kTile64: return launch_ggemm_wb<TA, TB, TC, MODE, 2, 2>(probs, nprob, nwg, bt, s);
-        case kTile64x128: return launch_ggemm_wb<TA, TB, TC, MODE, 2, 4>(probs, nprob, nwg, bt, s);
-        case kTile128: return launch_ggemm_wb<TA, TB, TC, MODE, 4, 4>(probs, nprob, nwg, bt, s);
+        case kTile64: return launch_ggemm_wb<TA, TB, TC, MODE, 2, 2, 2>(probs, nprob, nwg, bt, s);
+        case kTile64x128: return launch_ggemm_wb<TA, TB, TC, MODE, 2, 4, 2>(probs, nprob, nwg, bt, s);
+        case kTile128: return launch_ggemm_wb<TA, TB, TC, MODE, 4, 4, 2>(probs, nprob, nwg, bt, s);
+        case kTile128x256: return launch_ggemm_wb<TA, TB, TC, MODE, 4, 4, 4>(probs, nprob, nwg, bt, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -607,6 +634,12 @@ hipError_t launch_ggemm_t(const GemmProb* probs, int nprob, int64_t nwg, int til
 
 int g_force_tile = 0;
 
+// Relative cost per padded flop of the 128 x 256 tiles (workgroups of 512 threads, one per
+// compute unit): 1.01 to 1.03 of 128 x 128 on gfx950 (the split F product of the 1000-atom
+// build 8.26 against 8.18 ms per launch), although they stage a third fewer operand bytes per
+// flop; taken only where they save padding.
+constexpr double kWideRate = 1.03;
+
 int ggemm_tile(const GemmProb* probs, int nprob)
 {
     if (g_force_tile) return g_force_tile;
@@ -614,18 +647,23 @@ int ggemm_tile(const GemmProb* probs, int nprob)
     // unit): per padded flop 64 x 128 tiles run at about 0.9 and 64 x 64 tiles at about 0.75 of
     // the rate of 128 x 128 tiles (more operand bytes per flop), so a smaller tile is taken only
     // where it saves more padding than that.
-    double w64 = 0.0, w64x128 = 0.0, w128 = 0.0;
+    double w64 = 0.0, w64x128 = 0.0, w128 = 0.0, w128x256 = 0.0;
     for (int i = 0; i < nprob; ++i) {
         const double k = (double)probs[i].K;
         const double m64 = (double)((probs[i].M + 63) / 64 * 64), m128 = (double)((probs[i].M + 127) / 128 * 128);
         const double n64 = (double)((probs[i].N + 63) / 64 * 64), n128 = (double)((probs[i].N + 127) / 128 * 128);
+        const double n256 = (double)((probs[i].N + 255) / 256 * 256);
         w64 += m64 * n64 * k;
         w64x128 += m64 * n128 * k;
         w128 += m128 * n128 * k;
+        w128x256 += m128 * n256 * k;
     }
-    const double c64 = 1.35 * w64, c64x128 = 1.1 * w64x128;
-    if (c64 < w128 && c64 < c64x128) return kTile64;
-    return c64x128 < w128 ? kTile64x128 : kTile128;
+    const double c[4] = {1.35 * w64, 1.1 * w64x128, w128, kWideRate * w128x256};
+    const int tiles[4] = {kTile64, kTile64x128, kTile128, kTile128x256};
+    int best = 2;
+    for (int t = 0; t < 4; ++t)
+        if (c[t] < c[best]) best = t;
+    return tiles[best];
 }
 
 void ggemm_plan(GemmProb& p, int tile, int asize, int bsize)
@@ -667,9 +705,10 @@ hipError_t launch_gsplit(const GemmProb* probs, int nprob, int64_t nwg, int tile
 {
     if (nprob <= 0 || nwg <= 0) return hipSuccess;
     switch (tile) {
-        case kTile64: return launch_gsplit_wb<2, 2>(probs, nprob, nwg, s);
-        case kTile64x128: return launch_gsplit_wb<2, 4>(probs, nprob, nwg, s);
-        case kTile128: return launch_gsplit_wb<4, 4>(probs, nprob, nwg, s);
+        case kTile64: return launch_gsplit_wb<2, 2, 2>(probs, nprob, nwg, s);
+        case kTile64x128: return launch_gsplit_wb<2, 4, 2>(probs, nprob, nwg, s);
+        case kTile128: return launch_gsplit_wb<4, 4, 2>(probs, nprob, nwg, s);
+        case kTile128x256: return launch_gsplit_wb<4, 4, 4>(probs, nprob, nwg, s);
         default: return hipErrorInvalidValue;
     }
 }

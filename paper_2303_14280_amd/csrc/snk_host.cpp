@@ -2825,8 +2825,8 @@ int snk_debug_gemm_f64(int64_t M, int64_t N, int64_t K, const double* A, int64_t
                        int bt, double* C, int64_t ldc, int tile, void* stream)
 {
     if (M < 0 || N < 0 || K < 0 || !A || !B || !C) return arg_error(nullptr, "bad GEMM arguments");
-    if (tile != 0 && tile != kTile64 && tile != kTile128 && tile != kTile64x128)
-        return arg_error(nullptr, "tile must be 0, 64, 128 or 192");
+    if (tile != 0 && tile != kTile64 && tile != kTile128 && tile != kTile64x128 && tile != kTile128x256)
+        return arg_error(nullptr, "tile must be 0, 64, 128, 192 or 384");
     if (M == 0 || N == 0) return SNK_OK;
     if (lda < K || ldc < N || ldb < (bt ? K : N)) return arg_error(nullptr, "leading dimension too small");
     if (M > INT32_MAX || N > INT32_MAX || K > INT32_MAX) return arg_error(nullptr, "GEMM too large");
@@ -2859,8 +2859,8 @@ int snk_debug_gemm_f64(int64_t M, int64_t N, int64_t K, const double* A, int64_t
 
 int snk_debug_force_tile(int tile)
 {
-    if (tile != 0 && tile != kTile64 && tile != kTile128 && tile != kTile64x128)
-        return arg_error(nullptr, "tile must be 0, 64, 128 or 192");
+    if (tile != 0 && tile != kTile64 && tile != kTile128 && tile != kTile64x128 && tile != kTile128x256)
+        return arg_error(nullptr, "tile must be 0, 64, 128, 192 or 384");
     g_force_tile = tile;
     return SNK_OK;
 }

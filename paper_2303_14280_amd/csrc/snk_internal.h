@@ -370,8 +370,9 @@ struct RedTile {
 constexpr int kTile64 = 64;         // 64 x 64
 constexpr int kTile128 = 128;       // 128 x 128
 constexpr int kTile64x128 = 192;    // 64 x 128
-inline int tile_rows(int tile) { return tile == kTile128 ? 128 : 64; }
-inline int tile_cols(int tile) { return tile == kTile64 ? 64 : 128; }
+constexpr int kTile128x256 = 384;   // 128 x 256 (workgroups of 512 threads)
+inline int tile_rows(int tile) { return tile == kTile128 || tile == kTile128x256 ? 128 : 64; }
+inline int tile_cols(int tile) { return tile == kTile64 ? 64 : (tile == kTile128x256 ? 256 : 128); }
 // Output tile for a launch of these problems (M, N and K filled in): 128 x 128 unless a
 // smaller tile saves most of the padded work; g_force_tile (a test hook, 0 = off) overrides it
 int ggemm_tile(const GemmProb* probs, int nprob);

@@ -29,12 +29,12 @@ def test_mfma_f64_layout():
             assert say_ok
 
 
-@pytest.mark.parametrize("tile", [64, 128, 192])
+@pytest.mark.parametrize("tile", [64, 128, 192, 384])
 @pytest.mark.parametrize("bt", [False, True])
 @pytest.mark.parametrize("shape", [(100, 130, 77), (300, 517, 333), (1, 1, 1), (129, 257, 16)])
 def test_gemm_f64_vs_numpy(bt, shape, tile):
     """The grouped matrix-core product on one problem: ragged edges of the output tiles (64 x 64,
-    128 x 128, 64 x 128) and of the 16-wide k steps, several tiles in both directions."""
+    128 x 128, 64 x 128, 128 x 256) and of the 16-wide k steps, several tiles in both directions."""
     import torch
     rng = np.random.default_rng(1)
     M, N, K = shape

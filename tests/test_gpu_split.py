@@ -64,7 +64,7 @@ def test_split_with_learned_screen_within_budget():
 
 
 def test_output_tiles_give_identical_products():
-    """Every output tile of the grouped products (64 x 64, 128 x 128, 64 x 128) sums each
+    """Every output tile of the grouped products (64 x 64, 128 x 128, 64 x 128, 128 x 256) sums each
     element over k in the same order, so a mixed split build (FP64 and FP32 matrix-core
     products, F and K) is bitwise the same whichever tile every launch is forced to."""
     s = synth.make_system(3)
@@ -73,7 +73,7 @@ def test_output_tiles_give_identical_products():
     ctx = snk.Context(s, **kw)
     out = {}
     try:
-        for tile in (0, 64, 128, 192):
+        for tile in (0, 64, 128, 192, 384):
             snk.debug_force_tile(tile)
             out[tile] = ctx.build(s.P)
     finally:
@@ -82,7 +82,7 @@ def test_output_tiles_give_identical_products():
     say("forced tiles: E_x %.12f, FP32 product share %.3f" %
         (st0["ex"], st0["gemm_flops_fp32"] / (st0["gemm_flops_fp32"] + st0["gemm_flops_fp64"])))
     assert st0["gemm_flops_fp32"] > 0
-    for tile in (64, 128, 192):
+    for tile in (64, 128, 192, 384):
         assert np.array_equal(out[tile][0], K0), tile
     with pytest.raises(snk.SnkError):
         snk.debug_force_tile(96)
