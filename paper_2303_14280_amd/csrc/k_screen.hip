@@ -212,7 +212,10 @@ __device__ __forceinline__ int64_t pair_index(int s, int t)
 // ---------------------------------------------------------------------------------------
 struct BoundShared {
     int32_t hist[kNBins];
-    double cnt_s[2 * kNBins];
+    union {
+        double cnt_s[2 * kNBins];      // bound set-up: pair counts per bin sum
+        int32_t queue[4 * kNBins];     // learned estimate, afterwards: candidate queue
+    };
     int32_t aoff[4];
     int32_t S, S2, bmin, bmax;
     double acc;
@@ -396,8 +399,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void s
     __shared__ int64_t coff[7];
     __shared__ int use_list;
     __shared__ int qn;
-    constexpr int kQueue = 2 * kNBins * (int)(sizeof(double) / sizeof(int32_t));
-    int32_t* queue = reinterpret_cast<int32_t*>(sh.cnt_s);   // free once the bound is set up
+    constexpr int kQueue = 4 * kNBins;
+    int32_t* queue = sh.queue;   // the bin-sum counts' space, free once the bound is set up
     if (tid == 0) {
         int64_t acc = 0;
         for (int c = 0; c < 6; ++c) {
