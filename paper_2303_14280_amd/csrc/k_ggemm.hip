@@ -11,8 +11,9 @@
 //
 // Tiles: BM x BN outputs per workgroup of 256 threads (four wave64 in a 2 x 2 layout, each
 // wave WM x WN blocks of 16 x 16; 128 x 128, 64 x 128 or 64 x 64, chosen per launch by the padded work
-// of its problems), k in steps of 16 staged through double-buffered LDS with the next step's
-// global loads in flight during the current step's matrix-core work.  FP64 mode:
+// of its problems), k in steps of 16 (32 for the FP32 part of a split product: the same
+// matrix-core time per step as its FP64 part) staged through double-buffered LDS with the next
+// step's global loads in flight during the current step's matrix-core work.  FP64 mode:
 // v_mfma_f64_16x16x4f64, FP64 operands and sums.  FP32 mode: operands rounded to FP32 as they
 // are staged, v_mfma_f32_16x16x4f32 with FP32 sums over the workgroup's k chunk; the host keeps
 // those chunks at most kFp32MaxK long and adds chunks in FP64 (split products) or FP64
@@ -25,13 +26,11 @@
 namespace snk {
 namespace {
 
-// k extent of one staged operand step
+// k extent of one staged operand step (chunks of a split k are multiples of it).  The FP32 part
+// of a split product stages 2 GBK: an FP32 16 x 16 x 4 product takes half the cycles of the FP64
+// one, so its steps then take as long as the FP64 part's and the barrier and load latency per
+// step weigh the same; the plain FP32 products keep GBK.
 constexpr int GBK = 16, GPAD = 4;
-template <typename TS>
-constexpr int gbk()
-{
-    return GBK;
-}
 
 template <int MODE>
 struct GTraits;
@@ -113,10 +112,10 @@ template <int WN, int GN>
 constexpr int tile_n() { return 16 * WN * GN; }
 
 // Double-buffered LDS staging of BM x BK (A, k-major) and BK x BN (B) operand tiles.
-template <typename TS, int WM, int WN, int GN>
+template <typename TS, int WM, int WN, int GN, int BK = GBK>
 struct Stage {
-    TS A[2][gbk<TS>()][32 * WM + GPAD];
-    TS B[2][gbk<TS>()][bcols<TS>(tile_n<WN, GN>())];
+    TS A[2][BK][32 * WM + GPAD];
+    TS B[2][BK][bcols<TS>(tile_n<WN, GN>())];
 };
 
 template <typename TS>
@@ -130,15 +129,17 @@ __device__ inline void mfma_step(TS a, TS b, typename GTraits<sizeof(TS) == 4 ? 
 // (rows < M, columns < N): operands staged to TS (FP64 or FP32) in LDS, matrix-core products
 // accumulated into acc (the wave's WM x WN blocks).  Every load address is clamped into the
 // operand (k to kend - 1, columns to N - 1) and out-of-range elements are staged as zeros;
-// runs that lie inside and start on 16-byte aligned rows are read as vectors.
-template <typename TS, typename TA, typename TB, bool BT, int WM, int WN, int GN>
-__device__ inline void mainloop(Stage<TS, WM, WN, GN>& L, const Operands<TA, TB>& op, int64_t M, int64_t N,
+// runs that lie inside and start on 16-byte aligned rows are read as vectors.  With TAIL a
+// partial last step stops after its last 4-wide k group (the staged zeros past it add nothing):
+// the split product's short k ranges gain 3% from it, while the other products' long chunks
+// lose up to 14% to the branch in their step loop on gfx950, so only the split product sets it.
+template <typename TS, typename TA, typename TB, bool BT, int WM, int WN, int GN, int BK, bool TAIL = false>
+__device__ inline void mainloop(Stage<TS, WM, WN, GN, BK>& L, const Operands<TA, TB>& op, int64_t M, int64_t N,
                                 int64_t m0, int64_t n0, int64_t kbeg, int64_t kend,
                                 typename GTraits<sizeof(TS) == 4 ? 1 : 0>::acc4 (&acc)[WM][WN])
 {
     constexpr int NT = nthreads<GN>();
     constexpr int BM = 32 * WM, BN = tile_n<WN, GN>();
-    constexpr int BK = gbk<TS>();
     constexpr int E = BM * BK / NT;     // A elements each thread stages per k step
     constexpr int TPR = BK / E;         // threads per k-contiguous run of BK of A
     constexpr int EB = BN * BK / NT;    // B elements each thread stages per k step
@@ -248,9 +249,15 @@ __device__ inline void mainloop(Stage<TS, WM, WN, GN>& L, const Operands<TA, TB>
     __syncthreads();
     for (int it = 0; it < nk; ++it) {
         const int cur = it & 1;
+        // k left in this step, the same in every lane
+        const int64_t kleft = kend - kbeg - (int64_t)it * BK;
+        const int krem = __builtin_amdgcn_readfirstlane(kleft < BK ? (int)kleft : BK);
         if (it + 1 < nk) load(kbeg + (int64_t)(it + 1) * BK);
 #pragma unroll
         for (int ks = 0; ks < BK; ks += 4) {
+            if constexpr (TAIL) {
+                if (ks >= krem) break;
+            }
             TS a[WM], b[WN];
 #pragma unroll
             for (int bi = 0; bi < WM; ++bi) a[bi] = L.A[cur][ks + lk][wm + bi * 16 + li];
@@ -355,6 +362,13 @@ __global__ __launch_bounds__(nthreads<GN>(), 512 / nthreads<GN>()) void ggemm_ke
     write_tile<TC, MODE, WM, WN, GN>(pr, z, m0, n0, acc);
 }
 
+// LDS of the split product: the FP32 stage (32-deep k steps) and the FP64 stage in turn
+template <int WM, int WN, int GN>
+union SplitStage {
+    Stage<double, WM, WN, GN> d;
+    Stage<float, WM, WN, GN, 2 * GBK> f;
+};
+
 // Split product (one chunk, B row-major): C = A B over the strong k (FP64 operands, FP64 matrix
 // cores) plus A2 B2 over the weak k (FP32 operands, FP32 matrix cores, K2 <= kFp32MaxK), C
 // written once.  The weak sums come first: their FP32 accumulators go through LDS into the
@@ -367,7 +381,7 @@ __global__ __launch_bounds__(nthreads<GN>(), 512 / nthreads<GN>()) void gsplit_k
     typedef GTraits<0>::acc4 acc64;
     typedef GTraits<1>::acc4 acc32;
     constexpr int BM = 32 * WM, BN = tile_n<WN, GN>();
-    __shared__ Stage<double, WM, WN, GN> L;
+    __shared__ SplitStage<WM, WN, GN> L;
     GemmProb pr;
     int z;
     int64_t m0, n0;
@@ -377,9 +391,9 @@ __global__ __launch_bounds__(nthreads<GN>(), 512 / nthreads<GN>()) void gsplit_k
     const int li = lane & 15, lk = lane >> 4;
     // the transpose goes through the staging LDS in NH column parts when it cannot hold the
     // whole tile at once
-    constexpr int NH = sizeof(Stage<double, WM, WN, GN>) >= sizeof(float) * BM * (BN + 1) ? 1 : 2;
+    constexpr int NH = sizeof(SplitStage<WM, WN, GN>) >= sizeof(float) * BM * (BN + 1) ? 1 : 2;
     constexpr int HC = BN / NH;
-    static_assert(sizeof(Stage<double, WM, WN, GN>) >= sizeof(float) * BM * (HC + 1), "LDS for the transpose");
+    static_assert(sizeof(SplitStage<WM, WN, GN>) >= sizeof(float) * BM * (HC + 1), "LDS for the transpose");
     static_assert(BN / GN <= HC && HC % (BN / GN) == 0, "each wave's columns within one part");
     float* T = reinterpret_cast<float*>(&L);
     acc32 acw[WM][WN];
@@ -388,11 +402,10 @@ __global__ __launch_bounds__(nthreads<GN>(), 512 / nthreads<GN>()) void gsplit_k
 #pragma unroll
         for (int bj2 = 0; bj2 < WN; ++bj2) acw[bi][bj2] = acc32{0, 0, 0, 0};
     {
-        Stage<float, WM, WN, GN>& Lf = *reinterpret_cast<Stage<float, WM, WN, GN>*>(&L);
         Operands<float, float> op{glb(static_cast<const float*>(pr.A2)), pr.arow, nullptr, pr.lda2,
                                   glb(static_cast<const float*>(pr.B2)), nullptr, pr.ldb2, (pr.vec & 8) != 0,
                                   (pr.vec & 16) != 0};
-        mainloop<float, float, float, false, WM, WN, GN>(Lf, op, pr.M, pr.N, m0, n0, 0, pr.K2, acw);
+        mainloop<float, float, float, false, WM, WN, GN, 2 * GBK, true>(L.f, op, pr.M, pr.N, m0, n0, 0, pr.K2, acw);
     }
     // FP32 blocks to LDS in (row, column) order and back in the FP64 accumulator layout (the
     // main loop ends with a barrier)
@@ -424,7 +437,7 @@ __global__ __launch_bounds__(nthreads<GN>(), 512 / nthreads<GN>()) void gsplit_k
         Operands<double, double> op{glb(static_cast<const double*>(pr.A)), pr.arow, pr.acol, pr.lda,
                                     glb(static_cast<const double*>(pr.B)), pr.bmap, pr.ldb, (pr.vec & 1) != 0,
                                     (pr.vec & 2) != 0};
-        mainloop<double, double, double, false, WM, WN, GN>(L, op, pr.M, pr.N, m0, n0, 0, pr.K, acc);
+        mainloop<double, double, double, false, WM, WN, GN, GBK, true>(L.d, op, pr.M, pr.N, m0, n0, 0, pr.K, acc);
     }
     write_tile<double, 0, WM, WN, GN>(pr, z, m0, n0, acc);
 }
