@@ -444,25 +444,47 @@ __global__ __launch_bounds__(nthreads<GN>(), 512 / nthreads<GN>()) void gsplit_k
 
 // One workgroup per target row r: for every tile in list order, the tile's local row of r
 // (if any) summed over its chunks in chunk order and added into the row's columns.  Within a
-// tile the target columns are distinct; the barrier orders tiles that share columns.
+// tile the target columns are distinct; the barrier orders tiles that share columns.  The tiles
+// holding r are found 256 at a time, one lane per tile, and compacted in list order through LDS,
+// so the ordered walk visits only those (a row sits in a few of a group's tiles when the basis
+// is screened) instead of waiting on two dependent loads per tile.
 __global__ __launch_bounds__(256) void group_reduce_kernel(const double* __restrict__ part,
                                                            const RedTile* __restrict__ tiles, int ntile,
                                                            double* __restrict__ T, int64_t ldt, int64_t nrow)
 {
+    __shared__ int2 hit[256];
+    __shared__ int wcount[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int64_t r = blockIdx.x; r < nrow; r += gridDim.x) {
         double* trow = T + r * ldt;
-        for (int t = 0; t < ntile; ++t) {
-            const RedTile tl = tiles[t];
-            const int i = tl.rinv ? tl.rinv[r] : (r < tl.M ? (int)r : -1);
-            if (i < 0) continue;   // uniform over the workgroup
-            const int64_t mn = (int64_t)tl.M * tl.N;
-            const double* p = part + tl.poff + (int64_t)i * tl.N;
-            for (int n = threadIdx.x; n < tl.N; n += blockDim.x) {
-                double s = 0.0;
-                for (int zz = 0; zz < tl.ksplit; ++zz) s += p[zz * mn + n];
-                trow[tl.ccol ? tl.ccol[n] : n] += s;
+        for (int t0 = 0; t0 < ntile; t0 += 256) {
+            const int t = t0 + (int)threadIdx.x;
+            int i = -1;
+            if (t < ntile) {
+                const int32_t* rinv = tiles[t].rinv;
+                i = rinv ? rinv[r] : (r < tiles[t].M ? (int)r : -1);
             }
+            const uint64_t m = __ballot(i >= 0);
+            if (lane == 0) wcount[wave] = __popcll(m);
             __syncthreads();
+            int base = 0;
+            for (int w = 0; w < wave; ++w) base += wcount[w];
+            const int nh = wcount[0] + wcount[1] + wcount[2] + wcount[3];
+            if (i >= 0) hit[base + __popcll(m & ((1ull << lane) - 1))] = make_int2(t, i);
+            __syncthreads();
+            for (int h = 0; h < nh; ++h) {
+                const int2 e = hit[h];
+                const RedTile tl = tiles[e.x];
+                const int64_t mn = (int64_t)tl.M * tl.N;
+                const double* p = part + tl.poff + (int64_t)e.y * tl.N;
+                for (int n = threadIdx.x; n < tl.N; n += blockDim.x) {
+                    double s = 0.0;
+                    for (int zz = 0; zz < tl.ksplit; ++zz) s += p[zz * mn + n];
+                    trow[tl.ccol ? tl.ccol[n] : n] += s;
+                }
+                __syncthreads();
+            }
+            __syncthreads();   // hit and wcount are rewritten by the next 256 tiles
         }
     }
 }
