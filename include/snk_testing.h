@@ -34,6 +34,11 @@ int snk_boys_device(const double* T, int64_t n, int mmax, double* F_out, void* s
  * snk_debug_force_tile: every grouped product launched afterwards in the process uses this
  *   output tile (64, 128, 192 or 384 as for snk_debug_gemm_f64), or the library's own choice again
  *   for 0; process-wide, not thread-safe.  SNK_E_ARG for any other value.
+ * snk_debug_frow_prefilter: with 0, every build afterwards in the process tests every function
+ *   in the F-row restriction of basis screening instead of only those its block bound (the
+ *   largest |P| over the basis functions of two centres) leaves; 1 (the default) restores the
+ *   prefilter.  Both give the same rows, so the same K bit for bit; process-wide, not
+ *   thread-safe.  SNK_E_ARG for any other value.
  * snk_debug_mfma_layout: writes 256 doubles to host memory `out`: element 4*lane + r of
  *   one v_mfma_f64_16x16x4f64 whose inputs encode D[i][j] = 100 j + i (layout check).
  * snk_ctx_point_order: col_to_point[c] (host, nbatches*256 entries) = input index of the
@@ -62,6 +67,7 @@ int snk_boys_device(const double* T, int64_t n, int mmax, double* F_out, void* s
 int snk_debug_gemm_f64(int64_t M, int64_t N, int64_t K, const double* A, int64_t lda, const double* B,
                        int64_t ldb, int bt, double* C, int64_t ldc, int tile, void* stream);
 int snk_debug_force_tile(int tile);
+int snk_debug_frow_prefilter(int on);
 int snk_debug_mfma_layout(double* out);
 int snk_ctx_point_order(const snk_ctx* ctx, int64_t* col_to_point);
 int snk_ctx_debug_intermediates(snk_ctx* ctx, const double* P, double* Phi, double* F, double* G,

@@ -143,17 +143,22 @@ __global__ __launch_bounds__(256) void row_absmax_kernel(const T* __restrict__ P
 // functions (rows roff[t] .. roff[t+1]-1 of fn and mx) bounds |F_lam,i| on every point of the
 // tile (Eq. fmat with |Phi_nu,i| <= mx); flag[t][shell_of[lam]] = 1 when Ft >= eps.  P is
 // symmetric, so |P[lam][fn[k]]| is read as |P[fn[k]][lam]|: for each k the lanes of a wave read
-// 64 consecutive elements of one row (the tile's function index and maximum are uniform).
+// consecutive elements of one row (the tile's function index and maximum are uniform).  With a
+// candidate list (cand, ncand) lane i of tile t takes lam = cand[t][i], i < ncand[t]: the
+// functions not listed are those whose Ft is known to stay below eps.
 __global__ __launch_bounds__(256) void ftilde_flag_kernel(const double* __restrict__ P, int64_t nbf,
                                                           const int32_t* __restrict__ fn,
                                                           const int32_t* __restrict__ roff,
                                                           const double* __restrict__ mx, double eps,
                                                           const int32_t* __restrict__ shell_of, int32_t nshell,
+                                                          const int32_t* __restrict__ cand, int64_t cand_stride,
+                                                          const int32_t* __restrict__ ncand,
                                                           int32_t* __restrict__ flag)
 {
-    const int64_t lam = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int t = blockIdx.y;
-    if (lam >= nbf) return;
+    if (idx >= (cand ? (int64_t)ncand[t] : nbf)) return;
+    const int64_t lam = cand ? (int64_t)cand[(int64_t)t * cand_stride + idx] : idx;
     const double* col = P + lam;
     const int k0 = roff[t], k1 = roff[t + 1];
     double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
@@ -166,6 +171,100 @@ __global__ __launch_bounds__(256) void ftilde_flag_kernel(const double* __restri
     }
     for (; k < k1; ++k) v0 = fma(fabs(col[(int64_t)fn[k] * nbf]), mx[k], v0);
     if ((v0 + v1) + (v2 + v3) >= eps) flag[(int64_t)t * nshell + shell_of[lam]] = 1;
+}
+
+// pmax[a][b] = max |P[lam][nu]| over the functions lam of block a and nu of block b (blocks:
+// consecutive functions, blk_fn0[a] .. blk_fn0[a+1]-1); one workgroup per block a, a lane per b.
+__global__ __launch_bounds__(256) void pblock_max_kernel(const double* __restrict__ P, int64_t nbf,
+                                                         const int32_t* __restrict__ blk_fn0, int32_t nblk,
+                                                         double* __restrict__ pmax)
+{
+    const int a = blockIdx.x;
+    const int l0 = blk_fn0[a], l1 = blk_fn0[a + 1];
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
+        const int n0 = blk_fn0[b], n1 = blk_fn0[b + 1];
+        double m = 0.0;
+        for (int l = l0; l < l1; ++l) {
+            const double* row = P + (int64_t)l * nbf;
+            for (int n = n0; n < n1; ++n) m = fmax(m, fabs(row[n]));
+        }
+        pmax[(int64_t)a * nblk + b] = m;
+    }
+}
+
+// Candidates of the F-row test of tile t (kCandSlices workgroups per tile, each taking every
+// kCandSlices-th 256 blocks a): with s_b = sum of mx[k] over the tile's functions fn[k] in block
+// b, every function lam of block a has
+//     Ft_lam = sum_k |P[lam][fn[k]]| mx[k] <= U_a = sum_b pmax[a][b] s_b,
+// so only the blocks with U_a (1 + 1e-10) >= eps (the margin covers the rounding of both sums)
+// list their functions in cand[t], counted in ncand[t] (zero on entry; the list is in no
+// particular order and the test of each listed function is exact).  The tile's (block, s_b)
+// pairs are gathered in LDS 256 functions at a time; a tile with more than kCandBlocks of them
+// lists every function.
+constexpr int kCandBlocks = 1024, kCandSlices = 4;
+__global__ __launch_bounds__(256) void ftilde_cand_kernel(const int32_t* __restrict__ fn,
+                                                          const int32_t* __restrict__ roff,
+                                                          const double* __restrict__ mx,
+                                                          const int32_t* __restrict__ fn_blk,
+                                                          const int32_t* __restrict__ blk_fn0, int32_t nblk,
+                                                          const double* __restrict__ pmax, double eps, int64_t nbf,
+                                                          int32_t* __restrict__ cand, int64_t cand_stride,
+                                                          int32_t* __restrict__ ncand)
+{
+    __shared__ int32_t tb[kCandBlocks];
+    __shared__ double ts[kCandBlocks];
+    __shared__ int32_t cb[256];
+    __shared__ double cm[256];
+    __shared__ int32_t nb;
+    const int t = blockIdx.x;
+    const int k0 = roff[t], k1 = roff[t + 1];
+    int32_t* out = cand + (int64_t)t * cand_stride;
+    if (threadIdx.x == 0) nb = 0;
+    __syncthreads();
+    for (int c0 = k0; c0 < k1; c0 += 256) {
+        const int k = c0 + (int)threadIdx.x;
+        if (k < k1) {
+            cb[threadIdx.x] = fn_blk[fn[k]];
+            cm[threadIdx.x] = mx[k];
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int n = nb;
+            const int m = min(256, k1 - c0);
+            for (int j = 0; j < m && n <= kCandBlocks; ++j) {
+                if (n > 0 && tb[n - 1] == cb[j]) {
+                    ts[n - 1] += cm[j];
+                } else if (n < kCandBlocks) {
+                    tb[n] = cb[j];
+                    ts[n] = cm[j];
+                    ++n;
+                } else {
+                    n = kCandBlocks + 1;   // overflow: every function is a candidate
+                }
+            }
+            nb = n;
+        }
+        __syncthreads();
+    }
+    const int n = nb;
+    if (n > kCandBlocks) {
+        if (blockIdx.y == 0) {
+            for (int64_t l = threadIdx.x; l < nbf; l += blockDim.x) out[l] = (int32_t)l;
+            if (threadIdx.x == 0) ncand[t] = (int32_t)nbf;
+        }
+        return;
+    }
+    for (int a = blockIdx.y * blockDim.x + threadIdx.x; a < nblk; a += blockDim.x * gridDim.y) {
+        const double* row = pmax + (int64_t)a * nblk;
+        double u = 0.0;
+#pragma unroll 8
+        for (int j = 0; j < n; ++j) u = fma(row[tb[j]], ts[j], u);
+        if (u * (1.0 + 1e-10) >= eps) {
+            const int l0 = blk_fn0[a], l1 = blk_fn0[a + 1];
+            const int pos = atomicAdd(&ncand[t], l1 - l0);
+            for (int l = l0; l < l1; ++l) out[pos + (l - l0)] = l;
+        }
+    }
 }
 
 // One wave: A[i][k] = (k == 0) + i (k == 1), B[k][j] = 100 j (k == 0) + (k == 1), so that
@@ -304,12 +403,37 @@ hipError_t launch_row_absmax(const float* Phi, int64_t nfull, int64_t ncols_full
 
 hipError_t launch_ftilde_flag(const double* P, int64_t nbf, const int32_t* fn, const int32_t* roff, int32_t ntile,
                               const double* mx, double eps, const int32_t* shell_of, int32_t nshell, int32_t* flag,
-                              hipStream_t s)
+                              hipStream_t s, const int32_t* cand, int64_t cand_stride, const int32_t* ncand)
 {
     if (nbf <= 0 || ntile <= 0) return hipSuccess;
-    if (!P || !fn || !roff || !mx || !shell_of || !flag) return hipErrorInvalidValue;
+    if (!P || !fn || !roff || !mx || !shell_of || !flag || (cand && (!ncand || cand_stride < nbf)))
+        return hipErrorInvalidValue;
     hipLaunchKernelGGL(ftilde_flag_kernel, dim3((unsigned)((nbf + 255) / 256), (unsigned)ntile), dim3(256), 0, s, P, nbf,
-                       fn, roff, mx, eps, shell_of, nshell, flag);
+                       fn, roff, mx, eps, shell_of, nshell, cand, cand_stride, ncand, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_pblock_max(const double* P, int64_t nbf, const int32_t* blk_fn0, int32_t nblk, double* pmax,
+                             hipStream_t s)
+{
+    if (nblk <= 0) return hipSuccess;
+    if (!P || !blk_fn0 || !pmax) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(pblock_max_kernel, dim3((unsigned)nblk), dim3(256), 0, s, P, nbf, blk_fn0, nblk, pmax);
+    return hipGetLastError();
+}
+
+hipError_t launch_ftilde_cand(const int32_t* fn, const int32_t* roff, const double* mx, int32_t ntile,
+                              const int32_t* fn_blk, const int32_t* blk_fn0, int32_t nblk, const double* pmax,
+                              double eps, int64_t nbf, int32_t* cand, int64_t cand_stride, int32_t* ncand,
+                              hipStream_t s)
+{
+    if (ntile <= 0) return hipSuccess;
+    if (!fn || !roff || !mx || !fn_blk || !blk_fn0 || !pmax || !cand || !ncand || cand_stride < nbf)
+        return hipErrorInvalidValue;
+    hipError_t e = launch_fill(ncand, (int64_t)ntile, 0, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(ftilde_cand_kernel, dim3((unsigned)ntile, kCandSlices), dim3(256), 0, s, fn, roff, mx, fn_blk,
+                       blk_fn0, nblk, pmax, eps, nbf, cand, cand_stride, ncand);
     return hipGetLastError();
 }
 

@@ -127,6 +127,13 @@ struct snk_ctx {
     int32_t max_group_rows = 0;
     int32_t* d_fn_shell = nullptr;      // [nbf] shell of each function
     std::vector<int32_t> tile_frows;    // F rows per tile of the current group
+    // block prefilter of the F-row test: blocks = the functions of one centre (consecutive)
+    int32_t nblk = 0;
+    int32_t* d_blk_fn0 = nullptr;       // [nblk + 1] first function of each block
+    int32_t* d_fn_blk = nullptr;        // [nbf] block of each function
+    double* d_pmax = nullptr;           // [nblk][nblk] max |P| per block pair of the current build
+    int32_t* d_cand = nullptr;          // [max_group_tiles][nbf] candidate functions per tile
+    int32_t* d_ncand = nullptr;         // [max_group_tiles]
     // Grouped products: problem and reduction records of the launches, staged through a host
     // mirror that is never rewritten before the stream has passed every copy out of it
     char* d_arena = nullptr;
@@ -1024,6 +1031,11 @@ void free_ctx(snk_ctx* c)
     (void)hipFree(c->d_fcount);
     (void)hipFree(c->d_mx);
     (void)hipFree(c->d_fn_shell);
+    (void)hipFree(c->d_blk_fn0);
+    (void)hipFree(c->d_fn_blk);
+    (void)hipFree(c->d_pmax);
+    (void)hipFree(c->d_cand);
+    (void)hipFree(c->d_ncand);
     (void)hipFree(c->d_Phi);
     (void)hipFree(c->d_F);
     (void)hipFree(c->d_G);
@@ -1325,6 +1337,29 @@ int snk_ctx_create(const snk_basis* basis, const snk_grid* grid, const double* w
         for (int sh = 0; sh < c->nshell; ++sh)
             for (int k = 0; k < ncart(c->sl[sh]); ++k) fs[c->sfn[sh] + k] = sh;
         CREATE_CHECK(upload(c, &c->d_fn_shell, fs));
+        // Centre blocks for the prefilter of the F-row test: runs of consecutive shells on one
+        // centre, whose functions are consecutive.  Left out (every function tested) when the
+        // functions do not follow the shell order or the block-pair table would pass 256 MiB.
+        std::vector<int32_t> fn0, fblk(nbf);
+        bool ok = true;
+        for (int sh = 0, f = 0; sh < c->nshell && ok; ++sh) {
+            ok = c->sfn[sh] == f;
+            if (sh == 0 || c->scen[3 * sh] != c->scen[3 * sh - 3] || c->scen[3 * sh + 1] != c->scen[3 * sh - 2] ||
+                c->scen[3 * sh + 2] != c->scen[3 * sh - 1])
+                fn0.push_back(f);
+            for (int k = 0; k < ncart(c->sl[sh]); ++k) fblk[f + k] = (int32_t)fn0.size() - 1;
+            f += ncart(c->sl[sh]);
+        }
+        fn0.push_back((int32_t)nbf);
+        const int64_t nblk = (int64_t)fn0.size() - 1;
+        if (ok && nblk > 0 && nblk * nblk * (int64_t)sizeof(double) <= ((int64_t)256 << 20)) {
+            c->nblk = (int32_t)nblk;
+            CREATE_CHECK(upload(c, &c->d_blk_fn0, fn0));
+            CREATE_CHECK(upload(c, &c->d_fn_blk, fblk));
+            CREATE_CHECK(dalloc(c, &c->d_pmax, (size_t)(nblk * nblk)));
+            CREATE_CHECK(dalloc(c, &c->d_cand, (size_t)c->max_group_tiles * nbf));
+            CREATE_CHECK(dalloc(c, &c->d_ncand, (size_t)std::max<int32_t>(1, c->max_group_tiles)));
+        }
     }
     if (c->row_restrict || c->frow_restrict)
         CREATE_CHECK(dalloc(c, &c->d_rinv, (size_t)std::max<int32_t>(1, c->max_group_tiles) * nbf));
@@ -1386,6 +1421,9 @@ int push_vector(snk_ctx* c, std::vector<T>& v, const T** dptr);
 // Steps of one batch group up to G: Eq. collocation, Eq. fmat, the screen (when enabled),
 // Eqs. 3c_grid + gmat.
 // Eq. collocation and Eq. fmat for one batch group: Phi_g, then F_g = P[:, B_g] Phi_g.
+// test hook: 0 runs the F-row test on every function (no block prefilter)
+int g_frow_prefilter = 1;
+
 int group_F(snk_ctx* c, const Group& g, const double* dP, bool timed)
 {
     hipStream_t s = c->stream;
@@ -1432,8 +1470,19 @@ int group_F(snk_ctx* c, const Group& g, const double* dP, bool timed)
             HIPCHECK(c, launch_row_absmax(c->d_Phi32, nfull, ncols_full, g.phi_rows, last.ncols, c->d_mx, s));
         else
             HIPCHECK(c, launch_row_absmax(c->d_Phi, nfull, ncols_full, g.phi_rows, last.ncols, c->d_mx, s));
-        HIPCHECK(c, launch_ftilde_flag(dP, nbf, g.d_fn_cat, g.d_roff, ntile, c->d_mx, c->opts.eps_basis, c->d_fn_shell,
-                                       c->nshell, c->d_fflag, s));
+        if (c->d_pmax && g_frow_prefilter) {
+            // the block maxima of |P| once per build (every caller runs the groups from the
+            // first), then per tile the functions the block bound cannot rule out
+            if (&g == &c->groups.front())
+                HIPCHECK(c, launch_pblock_max(dP, nbf, c->d_blk_fn0, c->nblk, c->d_pmax, s));
+            HIPCHECK(c, launch_ftilde_cand(g.d_fn_cat, g.d_roff, c->d_mx, ntile, c->d_fn_blk, c->d_blk_fn0, c->nblk,
+                                           c->d_pmax, c->opts.eps_basis, nbf, c->d_cand, nbf, c->d_ncand, s));
+            HIPCHECK(c, launch_ftilde_flag(dP, nbf, g.d_fn_cat, g.d_roff, ntile, c->d_mx, c->opts.eps_basis,
+                                           c->d_fn_shell, c->nshell, c->d_fflag, s, c->d_cand, nbf, c->d_ncand));
+        } else {
+            HIPCHECK(c, launch_ftilde_flag(dP, nbf, g.d_fn_cat, g.d_roff, ntile, c->d_mx, c->opts.eps_basis,
+                                           c->d_fn_shell, c->nshell, c->d_fflag, s));
+        }
         if (c->split) {
             HIPCHECK(c, launch_partition(c->d_mx, g.d_fn_cat, g.d_roff, ntile, kWeakPhi, c->d_perm, c->d_cperm,
                                          c->d_nstrong, s));
@@ -2854,6 +2903,13 @@ int snk_debug_gemm_f64(int64_t M, int64_t N, int64_t K, const double* A, int64_t
         g_last_error = hipGetErrorString(e);
         return SNK_E_DEVICE;
     }
+    return SNK_OK;
+}
+
+int snk_debug_frow_prefilter(int on)
+{
+    if (on != 0 && on != 1) return arg_error(nullptr, "on must be 0 or 1");
+    g_frow_prefilter = on;
     return SNK_OK;
 }
 

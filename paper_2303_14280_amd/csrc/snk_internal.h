@@ -537,6 +537,17 @@ hipError_t launch_row_absmax(const float* Phi, int64_t nfull, int64_t ncols_full
 // (a bound on |F_lam| over tile t), for every function lam and tile t < ntile
 hipError_t launch_ftilde_flag(const double* P, int64_t nbf, const int32_t* fn, const int32_t* roff, int32_t ntile,
                               const double* mx, double eps, const int32_t* shell_of, int32_t nshell, int32_t* flag,
+                              hipStream_t s, const int32_t* cand = nullptr, int64_t cand_stride = 0,
+                              const int32_t* ncand = nullptr);
+// pmax[a][b] = max |P| over the block of rows a and columns b (blocks of consecutive functions
+// blk_fn0[a] .. blk_fn0[a+1]-1; the basis functions of one centre)
+hipError_t launch_pblock_max(const double* P, int64_t nbf, const int32_t* blk_fn0, int32_t nblk, double* pmax,
+                             hipStream_t s);
+// per tile, the functions whose F-row bound can reach eps by the block bound (cand[t][0 ..
+// ncand[t]-1], cand_stride >= nbf)
+hipError_t launch_ftilde_cand(const int32_t* fn, const int32_t* roff, const double* mx, int32_t ntile,
+                              const int32_t* fn_blk, const int32_t* blk_fn0, int32_t nblk, const double* pmax,
+                              double eps, int64_t nbf, int32_t* cand, int64_t cand_stride, int32_t* ncand,
                               hipStream_t s);
 
 }  // namespace snk

@@ -146,6 +146,8 @@ def lib():
             L.snk_debug_gemm_f64.restype = ctypes.c_int
             L.snk_debug_force_tile.argtypes = [ctypes.c_int]
             L.snk_debug_force_tile.restype = ctypes.c_int
+            L.snk_debug_frow_prefilter.argtypes = [ctypes.c_int]
+            L.snk_debug_frow_prefilter.restype = ctypes.c_int
             L.snk_debug_mfma_layout.argtypes = [ctypes.c_void_p]
             L.snk_debug_mfma_layout.restype = ctypes.c_int
             L.snk_ctx_point_order.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
@@ -553,6 +555,10 @@ def debug_gemm_f64(M, N, K, A_ptr, lda, B_ptr, ldb, bt, C_ptr, ldc, stream: int 
 
 def debug_force_tile(tile: int = 0):
     _check(lib().snk_debug_force_tile(int(tile)))
+
+
+def debug_frow_prefilter(on: bool = True):
+    _check(lib().snk_debug_frow_prefilter(int(on)))
 
 
 def debug_mfma_layout() -> np.ndarray:

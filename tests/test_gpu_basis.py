@@ -176,3 +176,32 @@ def test_f_rows_bound(screen):
          np.max(np.abs(F[kept] - ref[kept]))))
     assert np.max(np.abs(F - ref)) <= eps
     assert np.max(np.abs(F[kept] - ref[kept])) <= 1e-12 * max(1.0, np.max(np.abs(ref)))
+
+
+@pytest.mark.parametrize("cfg,stride,precision", [(5, 64, snk.SNK_MIXED), (5, 64, snk.SNK_FP64), (3, 16, snk.SNK_MIXED)])
+def test_f_row_prefilter_is_exact(cfg, stride, precision):
+    """The block prefilter of the F-row restriction (a function of centre a is tested only when
+    sum_b max|P_ab| sum_{nu in B_t on b} max|phi_nu| reaches eps_basis, an upper bound of its
+    own test sum) rules out only functions whose exact test fails, so the kept rows, K and E_x
+    are bit for bit those of testing every function: the 1000-atom cluster with its
+    molecule-local density (most blocks ruled out) and the 150-atom one with a delocalised
+    density, FP64 and mixed builds, on subsets of their points."""
+    s = synth.make_system(cfg)
+    s = s.subset_points(np.arange(0, s.npts, stride))
+    kw = dict(eps_basis=1e-9, screen=snk.SNK_SCREEN_BOUND, eps_skip_energy=1e-6, precision=precision)
+    ctx = snk.Context(s, **kw)
+    try:
+        snk.debug_frow_prefilter(False)
+        K0, st0 = ctx.build(s.P)
+        snk.debug_frow_prefilter(True)
+        K1, st1 = ctx.build(s.P)
+    finally:
+        snk.debug_frow_prefilter(True)
+    say("config %d / %d, precision %d: mean F rows per tile %.1f (every function tested) and %.1f "
+        "(prefiltered), E_x %.12f" % (cfg, stride, precision, st0["tile_frows"], st1["tile_frows"], st1["ex"]))
+    assert st0["tile_frows"] == st1["tile_frows"]
+    assert st0["gemm_flops_fp64"] == st1["gemm_flops_fp64"] and st0["gemm_flops_fp32"] == st1["gemm_flops_fp32"]
+    assert st0["ex"] == st1["ex"]
+    assert np.array_equal(K0, K1)
+    with pytest.raises(snk.SnkError):
+        snk.debug_frow_prefilter(2)
