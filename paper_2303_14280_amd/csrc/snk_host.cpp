@@ -1874,8 +1874,11 @@ int group_K(snk_ctx* c, const Group& g)
         const Tile& t = g.tiles[ti];
         const int64_t M = restrict_rows ? c->tile_rows[ti] : nbf;
         if (t.nB == 0 || M == 0) continue;
-        // split build: product columns in the tile's strong-then-weak order
-        const int32_t ns = c->split ? c->tile_nstrong[ti] : t.nB;
+        // split build: product columns in the tile's strong-then-weak order; the FP64 product
+        // takes the strong columns rounded up to whole 64-column blocks (its output tiles would
+        // pad them anyway), so the first weak columns leave the FP32 product
+        const int32_t ns0 = c->split ? c->tile_nstrong[ti] : t.nB;
+        const int32_t ns = c->split ? std::min<int32_t>(t.nB, (ns0 + 63) / 64 * 64) : t.nB;
         GemmProb p{};
         p.A = c->d_G + t.col0;
         p.lda = ld;
@@ -1896,7 +1899,7 @@ int group_K(snk_ctx* c, const Group& g)
         if (ns < t.nB) {
             // the weak rows of Phi_t as the F product left them in FP32 (rows in weak order)
             GemmProb q = p;
-            q.B = (const char*)c->d_Phw + c->tile_phw_off[ti] * sizeof(float);
+            q.B = (const char*)c->d_Phw + (c->tile_phw_off[ti] + (int64_t)(ns - ns0) * t.ncols) * sizeof(float);
             q.bmap = nullptr;
             q.C = c->d_part + poff + ns;
             q.N = t.nB - ns;
