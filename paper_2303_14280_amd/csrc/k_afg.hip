@@ -7,9 +7,10 @@
 //   G_{a,i} += w_i sum_b A_ab(r_i) F_{b,i},   G_{b,i} += w_i sum_a A_ab(r_i) F_{a,i}  (A != B).
 // The integral block is never written to memory.
 //
-// Work mapping (gfx950): one workgroup = one 256-point batch = four wave64; a
-// lane owns one grid point, so every G update is lane-private (no atomics and a
-// fixed summation order).  All lanes of a wave walk the same work list, so pair
+// Work mapping (gfx950): one workgroup = one 256-point batch = four wave64 (screened
+// launches: only the batches with runs, those with the most B tasks first, so that the
+// heaviest workgroups do not form the launch's tail); a lane owns one grid point, so every
+// G update is lane-private (no atomics and a fixed summation order).  All lanes of a wave walk the same work list, so pair
 // and primitive data are wave-uniform and come through scalar loads (restrict
 // kernel arguments); F/G rows move as 512-byte coalesced vectors.  A run keeps
 // the F rows and G accumulators of a tile of A shells in registers while it
@@ -42,6 +43,7 @@ __global__ __launch_bounds__(256) void afg_kernel(const double* __restrict__ px,
                                                   const int32_t* __restrict__ btasks,
                                                   const double* __restrict__ rowc,
                                                   const int32_t* __restrict__ batch_run_off, int32_t nrun,
+                                                  const int32_t* __restrict__ batch_order,
                                                   const double* __restrict__ gtab)
 {
     constexpr int NA = ncart(LA), NB = ncart(LB);
@@ -54,7 +56,7 @@ __global__ __launch_bounds__(256) void afg_kernel(const double* __restrict__ px,
     for (int i = threadIdx.x; i < kBoysRows * TC; i += blockDim.x) tab[i] = (R)gtab[(i / TC) * kBoysCols + i % TC];
     __syncthreads();
 
-    const int batch = blockIdx.x;
+    const int batch = batch_order ? batch_order[blockIdx.x] : (int)blockIdx.x;
     int64_t col[NP];
     R cx[NP], cy[NP], cz[NP];
     double w[NP];
@@ -204,7 +206,8 @@ hipError_t launch_afg(int la, int lb, const AfgArgs& a, hipStream_t s)
     const bool two = la == 1 && lb == 0 && a.batch_run_off == nullptr;
 #define SNK_AFG_NP(LA, LB, TA, NP, TF, R, FP, PR)                                                                  \
     hipLaunchKernelGGL((afg_kernel<LA, LB, TA, NP, TF, R>), grid, dim3(kBatch / NP), 0, s, a.px, a.py, a.pz, a.pw, \
-                       FP, a.G, a.ld, PR, a.runs, a.btasks, a.rowc, a.batch_run_off, a.nrun, a.boys_tab)
+                       FP, a.G, a.ld, PR, a.runs, a.btasks, a.rowc, a.batch_run_off, a.nrun, a.batch_order,    \
+                       a.boys_tab)
 #define SNK_AFG_T(LA, LB, TA, TF, R, FP, PR)                                                                       \
     do {                                                                                                          \
         if (two)                                                                                                  \

@@ -1418,12 +1418,12 @@ int group_fgemm(snk_ctx* c, const Group& g, const double* dP);
 template <typename T>
 int push_vector(snk_ctx* c, std::vector<T>& v, const T** dptr);
 
-// Steps of one batch group up to G: Eq. collocation, Eq. fmat, the screen (when enabled),
-// Eqs. 3c_grid + gmat.
-// Eq. collocation and Eq. fmat for one batch group: Phi_g, then F_g = P[:, B_g] Phi_g.
 // test hook: 0 runs the F-row test on every function (no block prefilter)
 int g_frow_prefilter = 1;
 
+// Steps of one batch group up to G: Eq. collocation, Eq. fmat, the screen (when enabled),
+// Eqs. 3c_grid + gmat.
+// Eq. collocation and Eq. fmat for one batch group: Phi_g, then F_g = P[:, B_g] Phi_g.
 int group_F(snk_ctx* c, const Group& g, const double* dP, bool timed)
 {
     hipStream_t s = c->stream;
@@ -2098,6 +2098,14 @@ int group_until_G(snk_ctx* c, const Group& g, const double* dP, bool timed, Grou
     }
     for (int cl = 0; cl < 6; ++cl) gs->cand += c->ntask[cl] * gpts;
     int64_t total_runs[12] = {};
+    // screened lists: per list the batches with runs, in decreasing powers of two of their B
+    // tasks (batches write disjoint columns of G, so the order only schedules the heavy
+    // workgroups ahead of the launch's tail; a bucket pass keeps the host's share, which the
+    // device waits for, linear), one upload for all lists
+    std::vector<int32_t> order;
+    int64_t order_off[12] = {};
+    int32_t order_cnt[12] = {};
+    const int32_t* d_order = nullptr;
     if (screen) {
         if (timed) HIPCHECK(c, hipEventRecord(c->ev[7], s));
         {
@@ -2208,6 +2216,32 @@ int group_until_G(snk_ctx* c, const Group& g, const double* dP, bool timed, Grou
             }
         }
         for (int j = 0; j < nb; ++j) gs->skipped += skipped[j];
+        std::vector<uint8_t> key(nb);
+        for (int k = 0; k < NL; ++k) {
+            const int64_t* rk = &rb[(size_t)k * (nb + 1)];
+            const int64_t* bk = &bb[(size_t)k * (nb + 1)];
+            int32_t cnt[65] = {};   // batches per bucket: 64 = no runs, else 63 - floor(log2(B tasks + 1))
+            for (int j = 0; j < nb; ++j) {
+                const uint64_t n = (uint64_t)(bk[j + 1] - bk[j]) + 1;
+                key[j] = rk[j + 1] > rk[j] ? (uint8_t)__builtin_clzll(n) : (uint8_t)64;
+                ++cnt[key[j]];
+            }
+            const size_t first = order.size();
+            order_off[k] = (int64_t)first;
+            order_cnt[k] = nb - cnt[64];
+            order.resize(first + order_cnt[k]);
+            int32_t pos[64];
+            for (int q = 0, p = 0; q < 64; ++q) {
+                pos[q] = p;
+                p += cnt[q];
+            }
+            for (int j = 0; j < nb; ++j)
+                if (key[j] < 64) order[first + pos[key[j]]++] = j;
+        }
+        if (!order.empty()) {
+            int rc = push_vector(c, order, &d_order);
+            if (rc) return rc;
+        }
         HIPCHECK(c, launch_screen(true, sa, s));
         if (c->kept_capture) {
             int rc = capture_kept(c, g, total_runs, bb);
@@ -2265,11 +2299,15 @@ int group_until_G(snk_ctx* c, const Group& g, const double* dP, bool timed, Grou
                 a.btasks = c->d_pool_bt[k];
                 a.batch_run_off = c->d_bro[k];
                 a.nrun = 0;
+                a.batch_order = d_order + order_off[k];
+                a.nbatch = order_cnt[k];
             } else {
                 a.runs = c->d_runs[cl];
                 a.btasks = c->d_btasks[cl];
                 a.batch_run_off = nullptr;
                 a.nrun = c->nrun[cl];
+                a.batch_order = nullptr;
+                a.nbatch = nb;
             }
             a.lowp = k >= 6;
             HIPCHECK(c, launch_afg(kClassLA[cl], kClassLB[cl], a, s));

@@ -100,7 +100,8 @@ struct AfgArgs {
     const double* rowc;             // [rows][3] centre of the shell of each basis function
     const int32_t* batch_run_off;   // [nbatch+1] per-batch run ranges, or nullptr: all runs for all batches
     int32_t nrun;
-    int32_t nbatch;
+    int32_t nbatch;                 // workgroups: batches of the group, or entries of batch_order
+    const int32_t* batch_order;     // [nbatch] batch of each workgroup, or nullptr: workgroup w, batch w
     const double* boys_tab;
 };
 
