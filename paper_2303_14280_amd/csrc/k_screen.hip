@@ -571,7 +571,7 @@ __global__ __launch_bounds__(256) void screen_kernel(ScreenArgs a)
     int32_t* tilecnt = dyn + 2 * a.nshell;
     __shared__ BoundShared sh;
 
-    const int batch = blockIdx.x;
+    const int batch = a.batch_order ? a.batch_order[blockIdx.x] : (int)blockIdx.x;
     const int tid = threadIdx.x;
     const double* Ub = a.U + (int64_t)batch * a.nshell;
     const bool learned = a.est != nullptr;

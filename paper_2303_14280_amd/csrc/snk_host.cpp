@@ -2238,10 +2238,30 @@ int group_until_G(snk_ctx* c, const Group& g, const double* dP, bool timed, Grou
             for (int j = 0; j < nb; ++j)
                 if (key[j] < 64) order[first + pos[key[j]]++] = j;
         }
-        if (!order.empty()) {
+        // the write pass of the lists: every batch (each writes its own records and offsets),
+        // in decreasing powers of two of its B tasks over all lists
+        const size_t wfirst = order.size();
+        {
+            int32_t cnt[64] = {};
+            for (int j = 0; j < nb; ++j) {
+                uint64_t n = 1;
+                for (int k = 0; k < NL; ++k) n += (uint64_t)(bb[(size_t)k * (nb + 1) + j + 1] - bb[(size_t)k * (nb + 1) + j]);
+                key[j] = (uint8_t)__builtin_clzll(n);
+                ++cnt[key[j]];
+            }
+            order.resize(wfirst + nb);
+            int32_t pos[64];
+            for (int q = 0, p = 0; q < 64; ++q) {
+                pos[q] = p;
+                p += cnt[q];
+            }
+            for (int j = 0; j < nb; ++j) order[wfirst + pos[key[j]]++] = j;
+        }
+        {
             int rc = push_vector(c, order, &d_order);
             if (rc) return rc;
         }
+        sa.batch_order = d_order + wfirst;
         HIPCHECK(c, launch_screen(true, sa, s));
         if (c->kept_capture) {
             int rc = capture_kept(c, g, total_runs, bb);

@@ -110,6 +110,7 @@ struct ScreenArgs {
     const double* U;            // [nbatch][nshell] block-bound factors
     int32_t nshell;
     int32_t nbatch;
+    const int32_t* batch_order; // [nbatch] batch of each workgroup (a permutation), or nullptr: workgroup w, batch w
     const int32_t* shell_l;     // [nshell]
     const int32_t* shell_row;   // [nshell] first row of the shell in F/G
     const PairHdr* pairs;       // unique pairs, index s(s+1)/2 + t for s >= t
