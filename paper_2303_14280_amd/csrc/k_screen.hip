@@ -84,7 +84,7 @@ __global__ __launch_bounds__(256) void diag_bound_kernel(DiagArgs a, const TF* _
     __shared__ double mpart[kGroup][4];
     for (int i = threadIdx.x; i < kBoysRows * kBoysCols; i += blockDim.x) tab[i] = (float)a.tab[i];
     __syncthreads();
-    const int batch = blockIdx.x;
+    const int batch = a.batch_order ? a.batch_order[blockIdx.x] : (int)blockIdx.x;
     const int64_t col = (int64_t)batch * kBatch + threadIdx.x;
     const float cx = (float)a.px[col], cy = (float)a.py[col], cz = (float)a.pz[col];
     const double w = a.pw[col], sw = sqrt(w);

@@ -1980,6 +1980,26 @@ int group_bounds(snk_ctx* c, const Group& g)
         HIPCHECK(c, launch_diag_lists(d, c->d_fflag, ntile, c->nshell, s));
         HIPCHECK(c, launch_fill(c->d_U, (int64_t)nb * c->nshell, 0.0, s));
         if (c->d_lun) HIPCHECK(c, launch_fill(reinterpret_cast<float*>(c->d_lun), (int64_t)2 * nb * c->nshell, -40.0f, s));
+        if ((int)c->tile_frows.size() == ntile && ntile > 1 && c->tile_batches > 0) {
+            // the batches of the tiles with the most F rows (a tile's listed shells) first, in
+            // decreasing powers of two: each batch writes only its own U, so the order only
+            // schedules the heavy workgroups ahead of the launches' tails
+            std::vector<int32_t> order(nb);
+            std::vector<uint8_t> key(nb);
+            int32_t cnt[32] = {}, pos[32];
+            for (int j = 0; j < nb; ++j) {
+                const int t = std::min(ntile - 1, j / c->tile_batches);
+                key[j] = (uint8_t)__builtin_clz((uint32_t)std::max(0, c->tile_frows[t]) + 1u);
+                ++cnt[key[j]];
+            }
+            for (int q = 0, p = 0; q < 32; ++q) {
+                pos[q] = p;
+                p += cnt[q];
+            }
+            for (int j = 0; j < nb; ++j) order[pos[key[j]]++] = j;
+            int rc = push_vector(c, order, &a.batch_order);
+            if (rc) return rc;
+        }
     }
     for (int l = 0; l < 3; ++l) {
         a.dsh = c->d_diag_sh[l];
@@ -2239,9 +2259,11 @@ int group_until_G(snk_ctx* c, const Group& g, const double* dP, bool timed, Grou
                 if (key[j] < 64) order[first + pos[key[j]]++] = j;
         }
         // the write pass of the lists: every batch (each writes its own records and offsets),
-        // in decreasing powers of two of its B tasks over all lists
-        const size_t wfirst = order.size();
+        // in decreasing powers of two of its B tasks over all lists.  (An uploaded record stays
+        // valid only until the next upload, which may restart the staging arena: each order is
+        // uploaded right before the launches that read it.)
         {
+            std::vector<int32_t> worder(nb);
             int32_t cnt[64] = {};
             for (int j = 0; j < nb; ++j) {
                 uint64_t n = 1;
@@ -2249,19 +2271,15 @@ int group_until_G(snk_ctx* c, const Group& g, const double* dP, bool timed, Grou
                 key[j] = (uint8_t)__builtin_clzll(n);
                 ++cnt[key[j]];
             }
-            order.resize(wfirst + nb);
             int32_t pos[64];
             for (int q = 0, p = 0; q < 64; ++q) {
                 pos[q] = p;
                 p += cnt[q];
             }
-            for (int j = 0; j < nb; ++j) order[wfirst + pos[key[j]]++] = j;
-        }
-        {
-            int rc = push_vector(c, order, &d_order);
+            for (int j = 0; j < nb; ++j) worder[pos[key[j]]++] = j;
+            int rc = push_vector(c, worder, &sa.batch_order);
             if (rc) return rc;
         }
-        sa.batch_order = d_order + wfirst;
         HIPCHECK(c, launch_screen(true, sa, s));
         if (c->kept_capture) {
             int rc = capture_kept(c, g, total_runs, bb);
@@ -2309,6 +2327,11 @@ int group_until_G(snk_ctx* c, const Group& g, const double* dP, bool timed, Grou
     a.rowc = c->d_rowc;
     a.nbatch = nb;
     a.boys_tab = c->d_boys;
+    if (!order.empty()) {
+        // the A.F launches' batch orders, uploaded after every other record of the group
+        int rc = push_vector(c, order, &d_order);
+        if (rc) return rc;
+    }
     for (int cl = 0; cl < 6; ++cl) {
         if (timed) HIPCHECK(c, hipEventRecord(c->ev[8 + cl], s));
         // the class's FP64 list, then (mixed build) its FP32 list

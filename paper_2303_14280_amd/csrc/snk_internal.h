@@ -236,6 +236,7 @@ hipError_t launch_mlp_adam(float* params, float* m, float* v, const float* g, fl
 // group: one workgroup per batch, lane = point.
 struct DiagArgs {
     const double *px, *py, *pz, *pw;   // the group's points
+    const int32_t* batch_order;        // [nbatch] batch of each workgroup (a permutation), or nullptr
     const double* F;                   // F of the group (ld columns), or
     const float* F32;                  // its FP32 copy
     int64_t ld;
