@@ -363,7 +363,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void s
     __shared__ BoundShared sh;
     __shared__ int32_t lhist[kNBins];
 
-    const int batch = blockIdx.x;
+    const int batch = a.batch_order ? a.batch_order[blockIdx.x] : (int)blockIdx.x;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r = lane & 15, g = lane >> 4;
     const double* Ub = a.U + (int64_t)batch * a.nshell;

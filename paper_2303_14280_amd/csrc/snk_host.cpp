@@ -127,6 +127,7 @@ struct snk_ctx {
     int32_t max_group_rows = 0;
     int32_t* d_fn_shell = nullptr;      // [nbf] shell of each function
     std::vector<int32_t> tile_frows;    // F rows per tile of the current group
+    std::vector<int32_t> bound_order;   // batches of the current group, heaviest tiles first (or empty)
     // block prefilter of the F-row test: blocks = the functions of one centre (consecutive)
     int32_t nblk = 0;
     int32_t* d_blk_fn0 = nullptr;       // [nblk + 1] first function of each block
@@ -1944,6 +1945,7 @@ int group_bounds(snk_ctx* c, const Group& g)
     const int nb = g.b1 - g.b0;
     const int ntile = (int)g.tiles.size();
     hipStream_t s = c->stream;
+    c->bound_order.clear();
     DiagArgs a{};
     a.px = c->d_px + off;
     a.py = c->d_py + off;
@@ -1999,6 +2001,7 @@ int group_bounds(snk_ctx* c, const Group& g)
             for (int j = 0; j < nb; ++j) order[pos[key[j]]++] = j;
             int rc = push_vector(c, order, &a.batch_order);
             if (rc) return rc;
+            c->bound_order = std::move(order);   // also the order of the estimate and count passes
         }
     }
     for (int l = 0; l < 3; ++l) {
@@ -2163,6 +2166,10 @@ int group_until_G(snk_ctx* c, const Group& g, const double* dP, bool timed, Grou
             ea.eps_low = eps_low;
             ea.thr2 = c->d_thr2;
             ea.skipped = c->d_skipped;
+            if ((int)c->bound_order.size() == nb) {
+                int rc = push_vector(c, c->bound_order, &ea.batch_order);   // read by this launch only
+                if (rc) return rc;
+            }
             HIPCHECK(c, launch_screen_est(ea, s));
         }
         ScreenArgs sa{};
@@ -2201,6 +2208,10 @@ int group_until_G(snk_ctx* c, const Group& g, const double* dP, bool timed, Grou
             HIPCHECK(c, launch_fill(c->d_shell_flag, (int64_t)ntile * c->nshell, 0, s));
             sa.shell_flag = c->d_shell_flag;
             sa.tile_batches = c->tile_batches;
+        }
+        if ((int)c->bound_order.size() == nb) {
+            int rc = push_vector(c, c->bound_order, &sa.batch_order);   // the count pass only
+            if (rc) return rc;
         }
         HIPCHECK(c, launch_screen(false, sa, s));
         const int NL = c->nlist;

@@ -199,6 +199,7 @@ struct EstArgs {
     const float2* lun;          // [nbatch][nshell] log10 U and log10 of the F norm (clamped at -40)
     int32_t nshell;
     int32_t nbatch;
+    const int32_t* batch_order; // [nbatch] batch of each workgroup (a permutation), or nullptr
     const int32_t* shell_l;
     int64_t nne;                // pairs with kept primitive pairs, in class order:
     const int32_t* ne_p;        //   [nne] pair index
